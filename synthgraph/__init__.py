@@ -1,0 +1,172 @@
+"""Seeded synthetic graphs in CSR form (input data for the library, its tests and
+its benchmark).
+
+This module generates inputs only; it holds none of the Katz method's arithmetic.
+Large generators (Erdos-Renyi, R-MAT, Barabasi-Albert) run in ``gen.cpp`` through
+ctypes; the small fixed shapes used by the tests (complete graph, cycle, star,
+path, random small graphs) are written here in numpy.
+
+Every graph is returned as ``(row_ptr, col)``: ``row_ptr`` int64 of length n + 1,
+``col`` int32 of length nnz.  Undirected graphs store both arcs of every edge;
+rows are sorted, duplicate-free and loop-free.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsynthgraph.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile ``gen.cpp`` into ``libsynthgraph.so`` (g++ with OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["g++", "-O3", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
+               os.path.join(_HERE, "gen.cpp"), "-o", _LIB_PATH + ".tmp"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is not built; run synthgraph.build() first")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i64, i32, u64, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+    lib.sg_er.restype = vp
+    lib.sg_er.argtypes = [i64, i64, u64]
+    lib.sg_rmat.restype = vp
+    lib.sg_rmat.argtypes = [i32, i32, f64, f64, f64, u64, i32]
+    lib.sg_ba.restype = vp
+    lib.sg_ba.argtypes = [i64, i32, u64]
+    lib.sg_n.restype = i64
+    lib.sg_n.argtypes = [vp]
+    lib.sg_nnz.restype = i64
+    lib.sg_nnz.argtypes = [vp]
+    lib.sg_export.restype = None
+    lib.sg_export.argtypes = [vp, vp, vp]
+    lib.sg_free.restype = None
+    lib.sg_free.argtypes = [vp]
+    lib.sg_draw.restype = None
+    lib.sg_draw.argtypes = [u64, u64, u64, i64, vp]
+    _lib = lib
+    return lib
+
+
+def _take(handle):
+    lib = _load()
+    if not handle:
+        raise ValueError("graph generator rejected its arguments or ran out of memory")
+    try:
+        n = lib.sg_n(handle)
+        nnz = lib.sg_nnz(handle)
+        row_ptr = np.empty(n + 1, dtype=np.int64)
+        col = np.empty(max(nnz, 1), dtype=np.int32)
+        lib.sg_export(handle, row_ptr.ctypes.data, col.ctypes.data)
+    finally:
+        lib.sg_free(handle)
+    return row_ptr, col[:nnz]
+
+
+def erdos_renyi(n: int, m_edges: int, seed: int):
+    """G(n, M): ``m_edges`` distinct undirected edges, uniform, no self-loops."""
+    return _take(_load().sg_er(n, m_edges, seed))
+
+
+def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
+         c: float = 0.19, seed: int = 1, relabel: bool = True):
+    """R-MAT with 2^scale vertices and edge_factor * 2^scale edge draws,
+    symmetrised, deduplicated, self-loops dropped, vertices relabelled by a
+    seeded random permutation.  d = 1 - a - b - c."""
+    return _take(_load().sg_rmat(scale, edge_factor, a, b, c, seed, int(relabel)))
+
+
+def barabasi_albert(n: int, m: int, seed: int):
+    """Preferential attachment: (m+1)-clique seed, then m distinct targets per vertex."""
+    return _take(_load().sg_ba(n, m, seed))
+
+
+def raw_draws(seed: int, stream: int, first: int, count: int) -> np.ndarray:
+    """The counter-based generator's 64-bit outputs, for pinning it in tests."""
+    out = np.empty(count, dtype=np.uint64)
+    _load().sg_draw(seed, stream, first, count, out.ctypes.data)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Small fixed shapes (numpy), for tests.
+# ---------------------------------------------------------------------------
+
+def from_edges(n: int, src, dst, undirected: bool = True):
+    """Canonical CSR from an arc list.  Undirected adds the reverse arcs.
+    Self-loops and duplicates are removed; rows are sorted."""
+    src = np.asarray(src, dtype=np.int64).ravel()
+    dst = np.asarray(dst, dtype=np.int64).ravel()
+    if undirected:
+        src, dst = np.concatenate([src, dst]), np.concatenate([dst, src])
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    key = np.unique(src * n + dst)
+    src, dst = key // n, key % n
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row_ptr, src + 1, 1)
+    row_ptr = np.cumsum(row_ptr)
+    return row_ptr, dst.astype(np.int32)
+
+
+def complete_graph(n: int):
+    i, j = np.triu_indices(n, 1)
+    return from_edges(n, i, j)
+
+
+def cycle_graph(n: int):
+    i = np.arange(n)
+    return from_edges(n, i, (i + 1) % n)
+
+
+def star_graph(leaves: int):
+    """Vertex 0 is the centre, vertices 1..leaves the leaves."""
+    return from_edges(leaves + 1, np.zeros(leaves, dtype=np.int64), np.arange(1, leaves + 1))
+
+
+def path_graph(n: int, undirected: bool = True):
+    i = np.arange(n - 1)
+    return from_edges(n, i, i + 1, undirected=undirected)
+
+
+def random_graph(n: int, p: float, seed: int, undirected: bool = True):
+    """Each pair (undirected) or ordered pair (directed) present with probability p."""
+    rng = np.random.default_rng(seed)
+    if undirected:
+        i, j = np.triu_indices(n, 1)
+        keep = rng.random(i.size) < p
+        return from_edges(n, i[keep], j[keep], undirected=True)
+    i, j = np.nonzero(rng.random((n, n)) < p)
+    return from_edges(n, i, j, undirected=False)
+
+
+def random_dag(n: int, p: float, seed: int):
+    """Directed acyclic: arcs only from lower to higher id."""
+    rng = np.random.default_rng(seed)
+    i, j = np.triu_indices(n, 1)
+    keep = rng.random(i.size) < p
+    return from_edges(n, i[keep], j[keep], undirected=False)
+
+
+def with_isolated(row_ptr, col, extra: int):
+    """Append ``extra`` isolated vertices."""
+    tail = np.full(extra, row_ptr[-1], dtype=np.int64)
+    return np.concatenate([row_ptr, tail]), col.copy()
+
+
+def max_degree(row_ptr) -> int:
+    row_ptr = np.asarray(row_ptr)
+    return int(np.max(np.diff(row_ptr))) if row_ptr.size > 1 else 0
