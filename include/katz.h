@@ -1,0 +1,217 @@
+/*
+ * katz.h -- C ABI of the MI355X (gfx950) certified top-k Katz ranking library.
+ *
+ * Method: van der Grinten, Bergamini, Green, Bader, Meyerhenke, "Scalable Katz
+ * Ranking Computation in Large Static and Dynamic Graphs", ESA 2018.
+ *
+ *   Katz centrality     c(v) = sum_{i>=1} alpha^i omega_i(v), omega_i(v) the number
+ *                       of walks of length i that start at v (Section 1, Eq. (katz)).
+ *   Walk recurrence     omega_i(v) = sum_{v->x} omega_{i-1}(x), omega_0 = 1
+ *                       (Section 3.2, Eq. (basic_recurrence)): one sparse
+ *                       matrix-vector product per iteration.
+ *   Bounds after r      l_r = c_r (+ alpha^{r+1} omega_r on undirected graphs),
+ *   iterations          u_r = c_r + alpha^{r+1} omega_r gamma,
+ *                       gamma = deg_max / (1 - alpha deg_max), alpha < 1/deg_max
+ *                       (Section 3.1, Theorem 1; monotone in r by Lemma 2).
+ *   Top-k criterion     stop once the k nodes with the largest lower bounds are
+ *                       eps-separated, l(w) > u(v) - eps, from each other and from
+ *                       every other node (Section 3.1, Eq. (epsilon_sep);
+ *                       Algorithm 1 with its converged() test).
+ *   Dynamic update      edge insertions I and deletions D, I n E = {}, D c E;
+ *                       recompute the walk counts of the affected nodes level by
+ *                       level, reactivate, resume (Section 4, Algorithm 2).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers marked "host or device" may point to host memory or to device
+ *     memory of the current HIP device; the library detects which with
+ *     hipPointerGetAttributes.  Host inputs are copied to the device; host
+ *     outputs are written by a device-to-host copy that has completed when the
+ *     call returns.
+ *   - `stream` is a hipStream_t (NULL = the default stream) of the current
+ *     device.  Every call is blocking: when it returns, all its device work on
+ *     `stream` has finished and every output is written.  Convergence is data
+ *     dependent, so the host reads a device flag while iterating.
+ *   - The caller owns every input and output buffer; the library never frees
+ *     them and keeps no pointer to them after returning (katz_state copies the
+ *     graph).  The library allocates its own workspace on the current device.
+ *   - Return value: 0 = KATZ_OK; > 0 = a warning, the outputs are written;
+ *     < 0 = an error, no output is written and a state passed in is unchanged.
+ *     Argument errors are detected before any device work is enqueued.
+ *   - Node ids are int32 (0 <= id < n <= 2^31 - 1); arc counts are int64.
+ *   - Distinct states may be used from different host threads at once; a single
+ *     state is not re-entrant.
+ */
+#ifndef KATZ_H_
+#define KATZ_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define KATZ_OK                  0
+#define KATZ_W_ITER_LIMIT        1  /* max_iter reached before certification          */
+#define KATZ_W_PRECISION_LIMIT   2  /* FP32 form: bound widths stopped shrinking below */
+                                    /* the rounding margin; not certified             */
+#define KATZ_W_EXACT_TIES        3  /* walks died out (bounds exact) and a pair is a   */
+                                    /* true tie that eps = 0 cannot separate          */
+#define KATZ_E_INVALID_ARG      -1  /* null pointer, k < 1, k > n, eps < 0 or NaN, r < 1 */
+#define KATZ_E_ALPHA            -2  /* alpha <= 0, NaN, or alpha * deg_max >= 1        */
+#define KATZ_E_CSR              -3  /* malformed CSR (see katz_params.validate)        */
+#define KATZ_E_UPDATE           -4  /* update batch violates I n E = {}, D c E, ...    */
+#define KATZ_E_DEGREE_CAP       -5  /* insertion would exceed the state's degree cap   */
+#define KATZ_E_OOM              -6  /* device allocation failed                        */
+#define KATZ_E_HIP              -7  /* a HIP runtime call failed                       */
+#define KATZ_E_UNSUPPORTED      -8  /* valid request outside what this build supports  */
+
+/* ---- precision forms ------------------------------------------------------ */
+#define KATZ_FP64         0  /* walk vector, sums and bounds in FP64 (the plain method)  */
+#define KATZ_FP32_MARGIN  1  /* walk vector and row sums in FP32; c, bounds and the     */
+                             /* rounding-error margin that widens both bounds in FP64    */
+
+/* ---- stopping criteria (Section 3.1) -------------------------------------- */
+#define KATZ_TOPK         0  /* the only criterion implemented; others -> E_UNSUPPORTED */
+
+/* ---- CSR validation levels -------------------------------------------------- */
+#define KATZ_VALIDATE_NONE    0  /* trust the caller                                   */
+#define KATZ_VALIDATE_BASIC   1  /* row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz,  */
+                                 /* 0 <= col < n (default)                             */
+#define KATZ_VALIDATE_STRICT  2  /* BASIC + rows strictly increasing (no duplicates),   */
+                                 /* no self-loops, and symmetry when undirected = 1     */
+
+/* A graph in compressed sparse row form.  Row v lists the out-neighbours of v:
+ * arcs v -> col[j] for row_ptr[v] <= j < row_ptr[v+1].  An undirected graph
+ * stores both arcs of each edge (Section 2.1) and sets undirected = 1, which
+ * enables the improved lower bound of Section 3.1.  row_ptr and col: host or
+ * device, read only. */
+typedef struct katz_csr {
+  int64_t n;              /* number of nodes, 1 <= n <= 2^31 - 1                    */
+  int64_t nnz;            /* number of arcs = row_ptr[n]                            */
+  const void* row_ptr;    /* n + 1 offsets: int32 if row_ptr_64 = 0, else int64     */
+  const int32_t* col;     /* nnz target ids                                         */
+  int32_t row_ptr_64;     /* 0: row_ptr is int32 (needs nnz < 2^31); 1: int64       */
+  int32_t undirected;     /* 1: symmetric adjacency                                 */
+} katz_csr;
+
+/* Problem parameters (Section 3: alpha, k, eps and the stopping criterion). */
+typedef struct katz_params {
+  double alpha;           /* attenuation, 0 < alpha < 1/deg_max (Theorem 1);        */
+                          /* 0.0 selects 1/(1 + deg_max) (Section 3.1)              */
+  double epsilon;         /* separation tolerance eps >= 0 (absolute); 0 = strict   */
+  int32_t k;              /* 1 <= k <= min(n, 4096)                                 */
+  int32_t max_iter;       /* iteration cap; 0 selects 1000                          */
+  int32_t precision;      /* KATZ_FP64 or KATZ_FP32_MARGIN                          */
+  int32_t criterion;      /* KATZ_TOPK                                              */
+  int32_t validate;       /* KATZ_VALIDATE_*; applies to the input CSR              */
+  int32_t reserved;       /* must be 0                                              */
+  int64_t degree_cap;     /* states only: the largest deg_max that edge insertions  */
+                          /* may create; 0 = the initial deg_max.  alpha must obey  */
+                          /* alpha * degree_cap < 1.                                */
+} katz_params;
+
+/* Output of a ranking call.  topk_ids, lower, upper: caller-owned arrays of k
+ * elements, host or device, written in ranking order (lower bound descending,
+ * ties by ascending id).  The scalar fields are written by the library. */
+typedef struct katz_result {
+  int32_t* topk_ids;       /* [k] node ids                                          */
+  double* lower;           /* [k] l_r of each ranked node (FP32 form: widened)      */
+  double* upper;           /* [k] u_r of each ranked node (FP32 form: widened)      */
+  double rest_upper_max;   /* max u_r over the nodes outside the top-k; -inf if k=n */
+  double alpha_used;       /* the alpha the run used                                */
+  double eta;              /* FP32 form: relative error bound of the walk vector at */
+                           /* the last iteration; 0 for FP64                        */
+  int64_t active_final;    /* |M| when the run stopped (k once certified)           */
+  int32_t iterations;      /* r                                                     */
+  int32_t status;          /* same value as the return code                         */
+} katz_result;
+
+/* Library-owned, device-resident state for dynamic updates: a copy of the graph
+ * (CSR with per-row slack), the walk-vector history x_0..x_r, c_r and the active
+ * set M (Section 4: Algorithm 2 resumes from Algorithm 1's state). */
+typedef struct katz_state katz_state;
+
+/*
+ * katz_rank_static -- Algorithm 1 (Section 3.2) with the top-k criterion.
+ *
+ * Ranks `count` independent graphs: g[i] with parameters p[i] into out[i].
+ * count = 1 is the plain call; count > 1 runs all graphs together (one walk
+ * sparse matrix-vector product per iteration over every graph that is still
+ * iterating, per-graph selection and separation test), each with its own alpha,
+ * k and eps.
+ *
+ * states: NULL, or an array of `count` pointers that receives one new
+ *         katz_state per graph for later katz_rank_update calls (FP64 only;
+ *         free each with katz_state_free).
+ * Errors: E_INVALID_ARG, E_ALPHA, E_CSR, E_UNSUPPORTED (criterion other than
+ *         top-k, k > 4096, FP32 form with states), E_OOM, E_HIP.  With
+ *         count > 1 the first failing graph's error is returned and nothing is
+ *         written for any graph.
+ */
+int katz_rank_static(int32_t count, const katz_csr* g, const katz_params* p,
+                     katz_result* out, katz_state** states, void* stream);
+
+/*
+ * katz_rank_update -- Algorithm 2 (Section 4): apply one batch of undirected
+ * edge insertions (ins_u[i], ins_v[i]) and deletions (del_u[i], del_v[i]) to the
+ * state's graph, recompute the walk counts of every affected node for levels
+ * 1..r, patch c_r, recompute the bounds, reactivate nodes whose upper bound
+ * reaches min_{x in M} l(x) - eps, and iterate further until converged()
+ * holds.  Each pair denotes both arcs.  The batch is atomic: it is validated
+ * whole (ids in range, no self-loops, no pair twice, inserted edges absent,
+ * deleted edges present, no edge both inserted and deleted, degree cap) and
+ * rejected with E_UPDATE / E_DEGREE_CAP before the state changes.
+ * The id arrays: host or device; n_ins or n_del may be 0 (arrays then unused).
+ * The result has the state's k.  Errors: E_INVALID_ARG, E_UPDATE,
+ * E_DEGREE_CAP, E_OOM, E_HIP.
+ */
+int katz_rank_update(katz_state* st, const int32_t* ins_u, const int32_t* ins_v,
+                     int64_t n_ins, const int32_t* del_u, const int32_t* del_v,
+                     int64_t n_del, katz_result* out, void* stream);
+
+/*
+ * katz_bounds -- exactly r iterations of Algorithm 1 without a convergence test,
+ * then l_r and u_r of every node (Section 3.1, Theorem 1).  This is the score
+ * surface used for parity checks.  lower, upper: caller-owned arrays of n
+ * doubles, host or device, indexed by node id.  p->k, p->epsilon and
+ * p->max_iter are ignored.  Errors: E_INVALID_ARG (r < 1), E_ALPHA, E_CSR,
+ * E_OOM, E_HIP.
+ */
+int katz_bounds(const katz_csr* g, const katz_params* p, int32_t r,
+                double* lower, double* upper, void* stream);
+
+/* Frees a state from katz_rank_static (NULL is ignored). */
+void katz_state_free(katz_state* st);
+
+/* A static, human-readable description of a status code. */
+const char* katz_strerror(int code);
+
+/* ---- device timing (instrumentation for benchmarks and profiles) ----------
+ * While enabled, every ranking call records hipEvent pairs on its own stream
+ * around each of its phases and adds the elapsed device times to process-wide
+ * counters when the call has finished.  walk_step covers the walk
+ * sparse matrix-vector product of iterations r >= 2 (one kernel launch per
+ * iteration); walk_first covers iteration 1 (x_0 = 1 needs no gather, plus the
+ * column-range check); select covers the selection and converged() kernels of
+ * every iteration.  Recording adds a little host work per launch. */
+typedef struct katz_timing {
+  double walk_step_ms;       int64_t walk_step_launches;
+  double walk_first_ms;      int64_t walk_first_launches;
+  double select_ms;          int64_t select_iterations;
+  double prep_ms;            /* staging, binning, d_max read-back              */
+  double result_ms;          /* output kernels                                 */
+  double call_ms;            /* first to last event of each call, summed       */
+  int64_t calls;
+} katz_timing;
+
+/* on = 1: reset the counters and start recording; on = 0: stop. */
+void katz_timing_enable(int on);
+/* Copies the counters; E_INVALID_ARG if out is NULL. */
+int katz_timing_read(katz_timing* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KATZ_H_ */

@@ -1,0 +1,191 @@
+// Internal declarations shared by the kernels and the host runtime.
+//
+// Layout of a ranking run on the device
+//   * Rows are binned by length (degree-binned scheduling).  Each bin holds
+//     RowDesc records {offset, row, length} in ascending row order.  A bin has a
+//     fixed number of lanes per row, so the summation order of every row, and
+//     therefore its floating-point result, depends only on the row's length.
+//   * Rows longer than kBlockRowMax are cut into segments of kSeg arcs; one
+//     workgroup sums a segment; the workgroup that finishes a row's last
+//     segment combines the row's partials in segment order.
+//   * The first walk step (x_0 = 1) sums no vector: row v's sum is its length.
+//   * The walk vector is double-buffered; c (FP64) is updated in place; the
+//     FP32 form adds the per-node margin accumulator e (FP32, rounded up).
+//   * The active set M is a compacted list of node ids, double-buffered.  The
+//     top-k threshold is found by an MSB-first radix select on the IEEE bit
+//     pattern of the lower bound (non-negative, so the bit order is the value
+//     order), 12 bits per digit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "katz.h"
+
+namespace katz {
+
+constexpr int kWG = 256;                 // threads per workgroup (4 waves of 64)
+constexpr int kWave = 64;
+constexpr int kPerLane = 16;             // max row elements summed serially per lane
+constexpr int kSeg = kWG * kPerLane;     // arcs per huge-row segment (4096)
+constexpr int kWaveRowMax = kWave * kPerLane;   // 1024
+constexpr int kBlockRowMax = kSeg;              // 4096
+constexpr int kDigitBits = 12;
+constexpr int kDigits = 1 << kDigitBits;        // histogram bins per radix digit
+constexpr int kSelectLevels = 6;                // digits of a 63-bit key: 12*5 + 3
+constexpr int kMaxK = 4096;                     // LDS sort capacity of the check
+constexpr int kFinishThreads = 1024;
+constexpr int kSmallCand = 16384;               // finish directly below this many
+
+enum BinId : int {
+  BIN_HUGE = 0,   // len > 4096: segmented, multi-workgroup
+  BIN_B256,       // 1025..4096: one workgroup per row
+  BIN_W64,        // 33..1024: one wave per row
+  BIN_G32,        // 17..32: 32 lanes per row
+  BIN_G16,        // 9..16
+  BIN_G8,         // 5..8
+  BIN_G4,         // 1..4
+  BIN_EMPTY,      // 0
+  NUM_BINS
+};
+
+struct RowDesc {
+  int64_t off;
+  int32_t row;
+  int32_t len;
+};
+
+struct SegDesc {
+  int64_t off;
+  int32_t len;
+  int32_t part;   // index of this segment's partial sum
+  int32_t hrow;   // index of the owning row in the huge-row table
+  int32_t pad;
+};
+
+struct HugeRow {
+  int32_t row;
+  int32_t len;
+  int32_t nseg;
+  int32_t part0;  // partials part0 .. part0 + nseg - 1, in segment order
+};
+
+// Device-resident scalars of one run.
+struct RunScalars {
+  int err;            // CSR validation failure
+  int done;           // the run has stopped (every later kernel returns at once)
+  int status;         // KATZ_OK or a warning
+  int iterations;     // r of the last completed iteration
+  int m;              // |M|: length of the current active list
+  int top_count;      // top-k nodes appended by the apply kernel
+  int kept_count;     // non-top nodes kept active
+  int progress;       // FP32 form: some active interval can still shrink
+  int cand_count[2];  // candidates compacted at select levels 0 and 1
+  int need;           // rank still to find inside the current bucket
+  int level;          // select digits resolved so far
+  int cut_ext;        // ties with key == theta_key are top iff ext id <= cut_ext
+  int fail;           // adjacent-pair test failed
+  int dmax;           // prep: maximum row length
+  int pad;
+  unsigned long long prefix;     // resolved high bits of the k-th key
+  unsigned long long theta_key;  // bit pattern of l(M[k])
+  double theta;                  // l(M[k])
+  long long bin_count[NUM_BINS];
+  long long bin_base[NUM_BINS];
+  long long seg_total;
+};
+
+// Bound evaluation parameters of one iteration.
+struct BoundArgs {
+  const double* c;
+  const void* x;          // double* (FP64) or float* (FP32)
+  const float* e;         // FP32 form margin accumulator
+  const double* sigma;    // FP32 form: per-iteration scale sigma_r (device)
+  const double* sigma_sum;
+  int r;
+  int fp32;
+  int undirected;
+  int pad;
+  double alpha;
+  double beta;            // FP64: fl(alpha * gamma); FP32: upward-rounded beta
+  double eps;
+  // FP32 widening factors (see bound_eval):
+  double f_lo_c, f_hi_c, f_lo_s, f_hi_s, f_e, tau_coef, kappa;
+};
+
+struct IterArgs {
+  const RowDesc* desc;
+  const int32_t* col;
+  const SegDesc* segs;
+  const HugeRow* huge;
+  long long first_block[NUM_BINS + 1];  // fused-launch block ranges per bin
+  long long bin_base[NUM_BINS];
+  long long bin_count[NUM_BINS];
+  const void* x_in;
+  void* x_out;
+  double* c;
+  float* e;
+  void* partial;
+  int* seg_done;                 // [n_huge] segments finished this iteration
+  unsigned* xmax32;              // [max_iter + 1] float bits of max x~_r
+  unsigned long long* xmax64;    // [max_iter + 1] double bits of max s_r
+  double* sigma;                 // [max_iter + 1]
+  double* sigma_sum;             // [max_iter + 1]
+  RunScalars* sc;
+  int n;
+  int r;
+  int validate_cols;
+  int write_empty;
+  int clog2_dmax;
+  int pad;
+  double alpha;
+  double etap;                   // eta'_r
+};
+
+struct SelArgs {
+  BoundArgs b;
+  const int32_t* act_in;
+  int32_t* act_out;
+  unsigned long long* keys;
+  unsigned long long* cand_key[2];
+  int32_t* cand_v[2];
+  unsigned* hist;                // [2][kDigits]
+  const int32_t* ext_of;         // internal -> external id (nullptr: identity)
+  const int32_t* int_of;         // external -> internal id (nullptr: identity)
+  int32_t* top_sorted;           // [k] internal ids in ranking order
+  double* top_lo;
+  double* top_up;
+  const unsigned* xmax32;
+  const unsigned long long* xmax64;
+  RunScalars* sc;
+  int identity_in;               // r == 1: the active list is 0..n-1
+  int k;
+  int n;
+  int max_iter;
+};
+
+// ---- launchers (katz_kernels.hip) ----------------------------------------
+hipError_t launch_prep_count(const void* row_ptr, int row_ptr_64, int64_t n, int64_t nnz,
+                             long long* blk, int nblocks, RunScalars* sc, hipStream_t s);
+hipError_t launch_prep_scan(long long* blk, int nblocks, RunScalars* sc, hipStream_t s);
+hipError_t launch_prep_scatter(const void* row_ptr, int row_ptr_64, int64_t n,
+                               const long long* blk, int nblocks, RowDesc* desc,
+                               SegDesc* segs, HugeRow* huge, RunScalars* sc, hipStream_t s);
+hipError_t launch_validate_strict(const RowDesc* desc, long long n, const int32_t* col, int undirected,
+                                  long long* row_off, int* row_len, RunScalars* sc, hipStream_t s);
+hipError_t launch_walk_first(const IterArgs& a, int fp32, long long n, long long nnz, int validate,
+                             hipStream_t s);
+hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, hipStream_t s);
+hipError_t launch_select_iteration(const SelArgs& a, int grid, hipStream_t s);
+hipError_t launch_write_result(const SelArgs& a, uint8_t* mark, int32_t* out_ids, double* out_lo,
+                               double* out_up, unsigned long long* rest_bits, int grid, hipStream_t s);
+hipError_t launch_all_bounds(const BoundArgs& b, int64_t n, const int32_t* ext_of,
+                             double* lower, double* upper, hipStream_t s);
+hipError_t launch_init_run(RunScalars* sc, int64_t n, double* sigma, double* sigma_sum,
+                           unsigned* xmax32, unsigned long long* xmax64, int max_iter,
+                           unsigned* hist, hipStream_t s);
+
+int bin_of_host(int64_t len);
+
+}  // namespace katz

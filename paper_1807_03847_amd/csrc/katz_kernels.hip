@@ -1,0 +1,1024 @@
+// Device kernels of the certified top-k Katz ranking (gfx950, wave64).
+//
+// One iteration r of Algorithm 1 (Section 3.2) is
+//   walk_first (r = 1) / walk_step (r >= 2)
+//                                 walk step of Eq. (basic_recurrence) for every
+//                                 row, fused with the update of c_r (and of the
+//                                 FP32 margin accumulator),
+//   sel_hist / sel_scan / sel_compact (levels 0, 1), sel_finish
+//                                 radix select of the k-th largest lower bound
+//                                 over the active set M,
+//   sel_apply                     deactivation u - eps < l(M[k]) and compaction
+//                                 of M (converged() of Algorithm 1),
+//   sel_check                     LDS sort of the top-k and the adjacent-pair
+//                                 eps-separation test; sets the stop flag.
+// Every kernel returns immediately once the run has stopped, so the host may
+// enqueue iterations ahead of reading the flag.
+#include <algorithm>
+#include <climits>
+#include <cstdint>
+
+#include "katz_internal.h"
+
+namespace katz {
+
+__host__ __device__ constexpr int bin_of_len(long long len) {
+  return len <= 0 ? BIN_EMPTY
+       : len <= 4 ? BIN_G4
+       : len <= 8 ? BIN_G8
+       : len <= 16 ? BIN_G16
+       : len <= 32 ? BIN_G32
+       : len <= kWaveRowMax ? BIN_W64
+       : len <= kBlockRowMax ? BIN_B256
+       : BIN_HUGE;
+}
+
+int bin_of_host(int64_t len) { return bin_of_len(len); }
+
+namespace {
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+  return (1ull << lane_id()) - 1ull;
+}
+
+// Wave-aggregated append: one atomic per wave.  Every lane of the wave must call it.
+__device__ __forceinline__ int wave_append(int* counter, bool pred) {
+  const unsigned long long mask = __ballot(pred);
+  if (mask == 0ull) return -1;
+  const int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, __popcll(mask));
+  base = __shfl(base, leader);
+  return base + __popcll(mask & lanemask_lt());
+}
+
+template <bool F32> struct Prec;
+template <> struct Prec<false> { using T = double; };
+template <> struct Prec<true> { using T = float; };
+
+template <bool F32>
+__device__ __forceinline__ typename Prec<F32>::T ldx(const void* x, int32_t j) {
+  return reinterpret_cast<const typename Prec<F32>::T*>(x)[j];
+}
+
+// ---------------------------------------------------------------------------
+// Bound evaluation (Section 3.1, Theorem 1).
+//   FP64 form:  l = c + alpha s (undirected) or c;  u = c + beta s.
+//   FP32 form:  s = sigma_r x~, with every rounding of the walk vector bounded
+//               by the per-node accumulator e and the global factors; the
+//               interval [lo, up] contains the exact l_r and u_r.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void bound_eval(const BoundArgs& b, int v, double& lo, double& up) {
+  const double cv = b.c[v];
+  if (!b.fp32) {
+    const double s = reinterpret_cast<const double*>(b.x)[v];
+    lo = b.undirected ? cv + b.alpha * s : cv;
+    up = cv + b.beta * s;
+  } else {
+    const double s = b.sigma[b.r] * (double)reinterpret_cast<const float*>(b.x)[v];
+    const double down = (double)b.e[v] * b.f_e + b.tau_coef * b.sigma_sum[b.r];
+    const double l = cv * b.f_lo_c + s * b.f_lo_s - down;
+    lo = l > 0.0 ? l : 0.0;
+    up = cv * b.f_hi_c + down + s * b.f_hi_s;
+  }
+}
+
+// FP32 form: true while the part of the interval that further iterations
+// shrink still exceeds 1/16 of the part they cannot shrink (rounding margin).
+__device__ __forceinline__ bool can_progress(const BoundArgs& b, int v) {
+  if (!b.fp32) return true;
+  const double cv = b.c[v];
+  const double s = b.sigma[b.r] * (double)reinterpret_cast<const float*>(b.x)[v];
+  const double down = (double)b.e[v] * b.f_e + b.tau_coef * b.sigma_sum[b.r];
+  const double intrinsic = s * (b.f_hi_s - b.f_lo_s);
+  const double margin = 2.0 * down + 2.0 * b.kappa * cv;
+  return intrinsic * 16.0 > margin;
+}
+
+__device__ __forceinline__ unsigned long long key_of(double lo) {
+  return (unsigned long long)__double_as_longlong(lo);
+}
+
+// ---------------------------------------------------------------------------
+// Prep: per-block bin counts, maximum degree, CSR checks.
+// blk layout: [NUM_BINS + 1][nblocks]; column NUM_BINS counts huge segments.
+// ---------------------------------------------------------------------------
+template <class OffT>
+__global__ void __launch_bounds__(kWG) prep_count(const OffT* row_ptr, long long n, long long nnz,
+                                                  long long* blk, int nblocks, RunScalars* sc) {
+  __shared__ int cnt[NUM_BINS + 1];
+  if (threadIdx.x <= NUM_BINS) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const long long v = (long long)blockIdx.x * kWG + threadIdx.x;
+  int dmax = 0;
+  bool bad = false;
+  if (v < n) {
+    const long long o0 = (long long)row_ptr[v];
+    const long long o1 = (long long)row_ptr[v + 1];
+    const long long len = o1 - o0;
+    if (len < 0 || len > INT_MAX || o0 < 0 || o1 > nnz) {
+      bad = true;
+    } else {
+      const int b = bin_of_len(len);
+      atomicAdd(&cnt[b], 1);
+      if (b == BIN_HUGE) atomicAdd(&cnt[NUM_BINS], (int)((len + kSeg - 1) / kSeg));
+      dmax = (int)len;
+    }
+  }
+  if (v == 0) {
+    if ((long long)row_ptr[0] != 0 || (long long)row_ptr[n] != nnz) bad = true;
+  }
+  for (int o = 32; o >= 1; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o));
+  if (lane_id() == 0 && dmax > 0) atomicMax(&sc->dmax, dmax);
+  if (bad) atomicOr(&sc->err, 1);
+  __syncthreads();
+  if (threadIdx.x <= NUM_BINS) blk[(long long)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Exclusive scan of a long long array of length len with one 1024-thread block.
+__device__ void block_exclusive_scan_ll(long long* a, long long len, long long* total_out) {
+  __shared__ long long wsum[kFinishThreads / kWave];
+  __shared__ long long carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int lane = lane_id();
+  const int w = t / kWave;
+  for (long long base = 0; base < len; base += kFinishThreads) {
+    const long long i = base + t;
+    long long x = i < len ? a[i] : 0;
+    long long inc = x;
+    for (int o = 1; o < kWave; o <<= 1) {
+      long long y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+      long long ws = lane < kFinishThreads / kWave ? wsum[lane] : 0;
+      long long wi = ws;
+      for (int o = 1; o < kWave; o <<= 1) {
+        long long y = __shfl_up(wi, o);
+        if (lane >= o) wi += y;
+      }
+      if (lane < kFinishThreads / kWave) wsum[lane] = wi - ws;   // exclusive wave offsets
+    }
+    __syncthreads();
+    const long long c0 = carry;
+    if (i < len) a[i] = c0 + wsum[w] + inc - x;
+    __syncthreads();
+    if (t == kFinishThreads - 1) carry = c0 + wsum[w] + inc;
+    __syncthreads();
+  }
+  if (t == 0 && total_out) *total_out = carry;
+}
+
+__global__ void __launch_bounds__(kFinishThreads) prep_scan(long long* blk, int nblocks, RunScalars* sc) {
+  if (sc->err) return;
+  // Bins are scanned together (bin-major) so each bin is one contiguous range.
+  __shared__ long long firsts[NUM_BINS];
+  if (threadIdx.x < NUM_BINS) firsts[threadIdx.x] = 0;
+  long long total = 0;
+  // Record per-bin totals before the scan overwrites the counts.
+  for (int b = 0; b < NUM_BINS; ++b) {
+    __syncthreads();
+    long long part = 0;
+    for (long long i = threadIdx.x; i < nblocks; i += kFinishThreads) part += blk[(long long)b * nblocks + i];
+    for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o);
+    if (lane_id() == 0) atomicAdd((unsigned long long*)&firsts[b], (unsigned long long)part);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long acc = 0;
+    for (int b = 0; b < NUM_BINS; ++b) {
+      sc->bin_count[b] = firsts[b];
+      sc->bin_base[b] = acc;
+      acc += firsts[b];
+    }
+  }
+  __syncthreads();
+  block_exclusive_scan_ll(blk, (long long)NUM_BINS * nblocks, &total);
+  __syncthreads();
+  block_exclusive_scan_ll(blk + (long long)NUM_BINS * nblocks, nblocks, &total);
+  if (threadIdx.x == 0) sc->seg_total = total;
+}
+
+template <class OffT>
+__global__ void __launch_bounds__(kWG) prep_scatter(const OffT* row_ptr, long long n, const long long* blk,
+                                                    int nblocks, RowDesc* desc, SegDesc* segs,
+                                                    HugeRow* huge, RunScalars* sc) {
+  if (sc->err) return;
+  __shared__ int wcnt[NUM_BINS][kWG / kWave];
+  __shared__ int wseg[kWG / kWave];
+  const long long v = (long long)blockIdx.x * kWG + threadIdx.x;
+  const int lane = lane_id();
+  const int w = threadIdx.x / kWave;
+  long long off = 0;
+  int len = 0;
+  int bin = -1;
+  int nseg = 0;
+  if (v < n) {
+    off = (long long)row_ptr[v];
+    len = (int)((long long)row_ptr[v + 1] - off);
+    bin = bin_of_len(len);
+    if (bin == BIN_HUGE) nseg = (len + kSeg - 1) / kSeg;
+  }
+  int rank_in_wave = 0;
+  for (int b = 0; b < NUM_BINS; ++b) {
+    const unsigned long long mask = __ballot(bin == b);
+    if (bin == b) rank_in_wave = __popcll(mask & lanemask_lt());
+    if (lane == 0) wcnt[b][w] = __popcll(mask);
+  }
+  // Segment offsets of huge rows inside the wave (inclusive scan of nseg).
+  int sinc = nseg;
+  for (int o = 1; o < kWave; o <<= 1) {
+    int y = __shfl_up(sinc, o);
+    if (lane >= o) sinc += y;
+  }
+  if (lane == kWave - 1) wseg[w] = sinc;
+  __syncthreads();
+  if (v < n) {
+    int before = 0;
+    for (int ww = 0; ww < w; ++ww) before += wcnt[bin][ww];
+    const long long pos = blk[(long long)bin * nblocks + blockIdx.x] + before + rank_in_wave;
+    desc[pos] = RowDesc{off, (int32_t)v, len};
+    if (bin == BIN_HUGE) {
+      int sbefore = 0;
+      for (int ww = 0; ww < w; ++ww) sbefore += wseg[ww];
+      const long long part0 = blk[(long long)NUM_BINS * nblocks + blockIdx.x] + sbefore + sinc - nseg;
+      huge[pos - sc->bin_base[BIN_HUGE]] = HugeRow{(int32_t)v, len, nseg, (int32_t)part0};
+      for (int s = 0; s < nseg; ++s) {
+        const int slen = min(kSeg, len - s * kSeg);
+        segs[part0 + s] = SegDesc{off + (long long)s * kSeg, slen, (int32_t)(part0 + s),
+                                  (int32_t)(pos - sc->bin_base[BIN_HUGE]), 0};
+      }
+    }
+  }
+}
+
+// Strict CSR checks: rows strictly increasing (no duplicates), no self-loops.
+__global__ void __launch_bounds__(kWG) validate_strict(const RowDesc* desc, long long count,
+                                                       const int32_t* col, long long n, RunScalars* sc) {
+  const long long wv = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave;
+  const int lane = lane_id();
+  if (wv >= count) return;
+  const RowDesc d = desc[wv];
+  bool bad = false;
+  for (int j = lane; j < d.len; j += kWave) {
+    const int32_t u = col[d.off + j];
+    if (u < 0 || u >= n || u == d.row) bad = true;
+    if (j > 0 && col[d.off + j - 1] >= u) bad = true;
+  }
+  if (bad) atomicOr(&sc->err, 1);
+}
+
+// Symmetry: arc v->u must have u->v.  Rows are looked up through the row
+// pointer of the descriptor table (desc is in bin order, so use an index).
+__global__ void __launch_bounds__(kWG) validate_symmetry(const long long* row_off, const int* row_len,
+                                                         const int32_t* col, long long n, RunScalars* sc) {
+  const long long v = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (v >= n) return;
+  bool bad = false;
+  const long long o = row_off[v];
+  const int len = row_len[v];
+  for (int j = 0; j < len && !bad; ++j) {
+    const int32_t u = col[o + j];
+    if (u < 0 || u >= n) { bad = true; break; }
+    long long lo = row_off[u], hi = row_off[u] + row_len[u];
+    while (lo < hi) {
+      const long long mid = (lo + hi) >> 1;
+      if (col[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    if (lo >= row_off[u] + row_len[u] || col[lo] != v) bad = true;
+  }
+  if (bad) atomicOr(&sc->err, 1);
+}
+
+__global__ void __launch_bounds__(kWG) desc_to_rows(const RowDesc* desc, long long count,
+                                                    long long* row_off, int* row_len) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i >= count) return;
+  const RowDesc d = desc[i];
+  row_off[d.row] = d.off;
+  row_len[d.row] = d.len;
+}
+
+// ---------------------------------------------------------------------------
+// Walk step (Eq. (basic_recurrence)) with the fused bound epilogue.
+// ---------------------------------------------------------------------------
+template <bool F32>
+struct Epi {
+  double sigma_r;
+  int e_r;
+};
+
+// Per-iteration scale of the FP32 form: x~_r = T * 2^-e_r with 2^e_r above
+// deg_max * max(x~_{r-1}), so max x~_r < 1; sigma_r = alpha sigma_{r-1} 2^e_r.
+template <bool F32>
+__device__ __forceinline__ Epi<F32> compute_epi(const IterArgs& a) {
+  Epi<F32> ep{1.0, 0};
+  if constexpr (F32) {
+    const float M = (a.r == 1) ? 1.0f : __uint_as_float(a.xmax32[a.r - 1]);
+    int ex = 0;
+    if (M > 0.0f) {
+      (void)frexpf(M, &ex);
+      ex += a.clog2_dmax;
+    }
+    ep.e_r = ex;
+    ep.sigma_r = ldexp(a.alpha * a.sigma[a.r - 1], ex);
+  }
+  return ep;
+}
+
+template <bool F32>
+__device__ __forceinline__ void epilogue(const IterArgs& a, const Epi<F32>& ep, int row,
+                                         typename Prec<F32>::T t, double& vmax) {
+  if constexpr (!F32) {
+    const double s = a.alpha * t;
+    reinterpret_cast<double*>(a.x_out)[row] = s;
+    a.c[row] = (a.r == 1) ? s : a.c[row] + s;
+    vmax = fmax(vmax, s);
+  } else {
+    const float xs = ldexpf(t, -ep.e_r);
+    reinterpret_cast<float*>(a.x_out)[row] = xs;
+    const double s = ep.sigma_r * (double)xs;
+    const double e_prev = (a.r == 1) ? 0.0 : (double)a.e[row];
+    a.c[row] = (a.r == 1) ? s : a.c[row] + s;
+    a.e[row] = __double2float_ru((e_prev + a.etap * s) * (1.0 + 0x1p-50));
+    vmax = fmax(vmax, (double)xs);
+  }
+}
+
+// Strided row sum over G lanes: lane l adds elements l, l+G, l+2G, ... in
+// order (four independent loads in flight), then an xor butterfly.
+template <bool F32, int G>
+__device__ __forceinline__ typename Prec<F32>::T strided_sum(const IterArgs& a, const int32_t* cp, int len,
+                                                             int lane) {
+  using T = typename Prec<F32>::T;
+  T sum = 0;
+  int j = lane;
+  for (; j + 3 * G < len; j += 4 * G) {
+    const int32_t c0 = cp[j], c1 = cp[j + G], c2 = cp[j + 2 * G], c3 = cp[j + 3 * G];
+    const T v0 = ldx<F32>(a.x_in, c0), v1 = ldx<F32>(a.x_in, c1);
+    const T v2 = ldx<F32>(a.x_in, c2), v3 = ldx<F32>(a.x_in, c3);
+    sum += v0;
+    sum += v1;
+    sum += v2;
+    sum += v3;
+  }
+  for (; j < len; j += G) sum += ldx<F32>(a.x_in, cp[j]);
+  return sum;
+}
+
+template <bool F32, int G>
+__device__ __forceinline__ void rows_group(const IterArgs& a, const Epi<F32>& ep, long long lb, int bin,
+                                           double& vmax) {
+  using T = typename Prec<F32>::T;
+  constexpr int RPB = kWG / G;
+  const int lane = threadIdx.x & (G - 1);
+  const long long i = lb * RPB + threadIdx.x / G;
+  const bool valid = i < a.bin_count[bin];
+  RowDesc d{0, 0, 0};
+  if (valid) d = a.desc[a.bin_base[bin] + i];
+  T sum = strided_sum<F32, G>(a, a.col + d.off, d.len, lane);
+#pragma unroll
+  for (int o = G / 2; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, G);
+  if (valid && lane == 0) epilogue<F32>(a, ep, d.row, sum, vmax);
+}
+
+// Whole-workgroup sum of one row or segment: 256 strided lanes, wave
+// butterflies, then the four wave sums as (w0 + w1) + (w2 + w3).
+template <bool F32>
+__device__ __forceinline__ typename Prec<F32>::T block_sum(const IterArgs& a, const int32_t* cp, int len) {
+  using T = typename Prec<F32>::T;
+  __shared__ T part[kWG / kWave];
+  T sum = strided_sum<F32, kWG>(a, cp, len, threadIdx.x);
+  for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
+  if (lane_id() == 0) part[threadIdx.x / kWave] = sum;
+  __syncthreads();
+  const T tot = (part[0] + part[1]) + (part[2] + part[3]);
+  __syncthreads();
+  return tot;
+}
+
+// First walk step: x_0 = 1, so the sum over row v is its length, exactly.
+template <bool F32>
+__global__ void __launch_bounds__(kWG) walk_first(IterArgs a) {
+  if (a.sc->err || a.sc->done) return;
+  const Epi<F32> ep = compute_epi<F32>(a);
+  if constexpr (F32) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.sigma[1] = ep.sigma_r;
+      a.sigma_sum[1] = ep.sigma_r;
+    }
+  }
+  double vmax = 0.0;
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i < a.n) {
+    const RowDesc d = a.desc[i];
+    epilogue<F32>(a, ep, d.row, (typename Prec<F32>::T)d.len, vmax);
+  }
+  for (int o = 32; o >= 1; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
+  if (lane_id() == 0 && vmax > 0.0) {
+    if constexpr (F32) atomicMax(&a.xmax32[1], __float_as_uint((float)vmax));
+    else atomicMax(&a.xmax64[1], (unsigned long long)__double_as_longlong(vmax));
+  }
+}
+
+// 0 <= col < n for every arc (basic validation, before the first gather).
+__global__ void __launch_bounds__(kWG) check_col_range(const int32_t* col, long long nnz, long long n,
+                                                       RunScalars* sc) {
+  bool bad = false;
+  for (long long j = (long long)blockIdx.x * kWG + threadIdx.x; j < nnz; j += (long long)gridDim.x * kWG)
+    if ((unsigned)col[j] >= (unsigned long long)n) bad = true;
+  if (__ballot(bad) && lane_id() == 0) atomicOr(&sc->err, 1);
+}
+
+// Walk step r >= 2: every bin in one launch, heavy bins first.
+template <bool F32>
+__global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
+  if (a.sc->err || a.sc->done) return;
+  using T = typename Prec<F32>::T;
+  const Epi<F32> ep = compute_epi<F32>(a);
+  if constexpr (F32) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.sigma[a.r] = ep.sigma_r;
+      a.sigma_sum[a.r] = a.sigma_sum[a.r - 1] + ep.sigma_r;
+    }
+  }
+  double vmax = 0.0;
+  const long long b = blockIdx.x;
+  int bin = 0;
+  while (bin < NUM_BINS && b >= a.first_block[bin + 1]) ++bin;
+  const long long lb = b - a.first_block[bin];
+  switch (bin) {
+    case BIN_HUGE: {
+      __shared__ int s_last;
+      const SegDesc sd = a.segs[lb];
+      const T tot = block_sum<F32>(a, a.col + sd.off, sd.len);
+      T* part = reinterpret_cast<T*>(a.partial);
+      if (threadIdx.x == 0) {
+        part[sd.part] = tot;
+        __threadfence();
+        const HugeRow h = a.huge[sd.hrow];
+        s_last = atomicAdd(&a.seg_done[sd.hrow], 1) == h.nseg - 1;
+      }
+      __syncthreads();
+      if (s_last && threadIdx.x < kWave) {
+        // This workgroup finished the row's last segment: combine all partials
+        // in segment order (lane l takes l, l+64, ...; then a butterfly).
+        __threadfence();
+        const HugeRow h = a.huge[sd.hrow];
+        const int lane = threadIdx.x;
+        T sum = 0;
+        for (int s2 = lane; s2 < h.nseg; s2 += kWave) sum += part[h.part0 + s2];
+        for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
+        if (lane == 0) {
+          epilogue<F32>(a, ep, h.row, sum, vmax);
+          a.seg_done[sd.hrow] = 0;
+        }
+      }
+      break;
+    }
+    case BIN_B256: {
+      const RowDesc d = a.desc[a.bin_base[BIN_B256] + lb];
+      const T tot = block_sum<F32>(a, a.col + d.off, d.len);
+      if (threadIdx.x == 0) epilogue<F32>(a, ep, d.row, tot, vmax);
+      break;
+    }
+    case BIN_W64: rows_group<F32, 64>(a, ep, lb, BIN_W64, vmax); break;
+    case BIN_G32: rows_group<F32, 32>(a, ep, lb, BIN_G32, vmax); break;
+    case BIN_G16: rows_group<F32, 16>(a, ep, lb, BIN_G16, vmax); break;
+    case BIN_G8: rows_group<F32, 8>(a, ep, lb, BIN_G8, vmax); break;
+    case BIN_G4: rows_group<F32, 4>(a, ep, lb, BIN_G4, vmax); break;
+    case BIN_EMPTY: {
+      // Only at r = 2: the buffer of x_2 was never written for empty rows.
+      const long long i = lb * kWG + threadIdx.x;
+      if (i < a.bin_count[BIN_EMPTY]) {
+        const int row = a.desc[a.bin_base[BIN_EMPTY] + i].row;
+        reinterpret_cast<T*>(a.x_out)[row] = (T)0;
+      }
+      break;
+    }
+    default: break;
+  }
+  for (int o = 32; o >= 1; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
+  if (lane_id() == 0 && vmax > 0.0) {
+    if constexpr (F32) atomicMax(&a.xmax32[a.r], __float_as_uint((float)vmax));
+    else atomicMax(&a.xmax64[a.r], (unsigned long long)__double_as_longlong(vmax));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Top-k selection and converged() (Algorithm 1).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool stopped(const RunScalars* sc) { return sc->err || sc->done; }
+
+__device__ __forceinline__ int ext_id(const SelArgs& a, int v) { return a.ext_of ? a.ext_of[v] : v; }
+__device__ __forceinline__ int int_id(const SelArgs& a, int e) { return a.int_of ? a.int_of[e] : e; }
+
+// Level-0 keys and histogram of bits [62:51] over the active list.
+__global__ void __launch_bounds__(kWG) sel_hist0(SelArgs a) {
+  if (stopped(a.sc)) return;
+  __shared__ unsigned h[kDigits];
+  for (int d = threadIdx.x; d < kDigits; d += kWG) h[d] = 0;
+  __syncthreads();
+  const int m = a.sc->m;
+  for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < m; i += (long long)gridDim.x * kWG) {
+    const int v = a.identity_in ? (int)i : a.act_in[i];
+    double lo, up;
+    bound_eval(a.b, v, lo, up);
+    const unsigned long long key = key_of(lo);
+    a.keys[i] = key;
+    atomicAdd(&h[(key >> 51) & (kDigits - 1)], 1u);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < kDigits; d += kWG)
+    if (h[d]) atomicAdd(&a.hist[d], h[d]);
+}
+
+// Level-1 histogram of bits [50:39] over the level-0 candidates.
+__global__ void __launch_bounds__(kWG) sel_hist1(SelArgs a) {
+  if (stopped(a.sc)) return;
+  const int cnt = a.sc->cand_count[0];
+  if (cnt <= kSmallCand) return;
+  __shared__ unsigned h[kDigits];
+  for (int d = threadIdx.x; d < kDigits; d += kWG) h[d] = 0;
+  __syncthreads();
+  for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < cnt; i += (long long)gridDim.x * kWG)
+    atomicAdd(&h[(a.cand_key[0][i] >> 39) & (kDigits - 1)], 1u);
+  __syncthreads();
+  for (int d = threadIdx.x; d < kDigits; d += kWG)
+    if (h[d]) atomicAdd(&a.hist[kDigits + d], h[d]);
+}
+
+// Inside one 1024-thread block: the bucket of hist[0..nb) (nb <= 4096) that holds
+// rank `need` (1-based), counting from the largest bucket (desc) or the
+// smallest.  Thread t owns positions 4t..4t+3 of that order.
+struct Bucket {
+  int b;
+  int need;   // rank inside the bucket
+  int count;  // items in the bucket
+};
+
+__device__ Bucket find_bucket(const unsigned* h, int nb, int need, bool desc) {
+  __shared__ long long wsum[kFinishThreads / kWave];
+  __shared__ Bucket res;
+  const int t = threadIdx.x;
+  const int lane = lane_id();
+  const int w = t / kWave;
+  unsigned loc[4];
+  long long tot = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int pos = 4 * t + j;
+    const int bin = desc ? nb - 1 - pos : pos;
+    loc[j] = (pos < nb) ? h[bin] : 0u;
+    tot += loc[j];
+  }
+  long long inc = tot;
+  for (int o = 1; o < kWave; o <<= 1) {
+    long long y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == kWave - 1) wsum[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    long long ws = lane < kFinishThreads / kWave ? wsum[lane] : 0;
+    long long wi = ws;
+    for (int o = 1; o < kWave; o <<= 1) {
+      long long y = __shfl_up(wi, o);
+      if (lane >= o) wi += y;
+    }
+    if (lane < kFinishThreads / kWave) wsum[lane] = wi - ws;
+  }
+  __syncthreads();
+  long long cum = wsum[w] + inc - tot;   // items before this thread's positions
+  if (cum < need && need <= cum + tot) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (need <= cum + (long long)loc[j]) {
+        const int pos = 4 * t + j;
+        res.b = desc ? nb - 1 - pos : pos;
+        res.need = (int)(need - cum);
+        res.count = (int)loc[j];
+        break;
+      }
+      cum += loc[j];
+    }
+  }
+  __syncthreads();
+  const Bucket r = res;
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(kFinishThreads) sel_scan(SelArgs a, int level) {
+  if (stopped(a.sc)) return;
+  if (level == 1 && a.sc->cand_count[0] <= kSmallCand) return;
+  unsigned* hist = a.hist + level * kDigits;
+  const int need = (level == 0) ? a.k : a.sc->need;
+  const Bucket bk = find_bucket(hist, kDigits, need, true);
+  for (int d = threadIdx.x; d < kDigits; d += kFinishThreads) hist[d] = 0u;
+  if (threadIdx.x == 0) {
+    a.sc->need = bk.need;
+    a.sc->prefix = (level == 0) ? (unsigned long long)bk.b : ((a.sc->prefix << kDigitBits) | (unsigned)bk.b);
+    a.sc->level = level + 1;
+  }
+}
+
+__global__ void __launch_bounds__(kWG) sel_compact(SelArgs a, int level) {
+  if (stopped(a.sc)) return;
+  const int c0 = a.sc->cand_count[0];
+  if (level == 1 && c0 <= kSmallCand) return;
+  const unsigned long long pre = a.sc->prefix;
+  const int shift = level == 0 ? 51 : 39;
+  const int cnt = level == 0 ? a.sc->m : c0;
+  const long long stride = (long long)gridDim.x * kWG;
+  for (long long base = (long long)blockIdx.x * kWG; base < cnt; base += stride) {
+    const long long i = base + threadIdx.x;
+    const bool valid = i < cnt;
+    unsigned long long key = 0;
+    int v = 0;
+    if (valid) {
+      if (level == 0) {
+        key = a.keys[i];
+        v = a.identity_in ? (int)i : a.act_in[i];
+      } else {
+        key = a.cand_key[0][i];
+        v = a.cand_v[0][i];
+      }
+    }
+    const bool pred = valid && (key >> shift) == pre;
+    const int pos = wave_append(&a.sc->cand_count[level], pred);
+    if (pred) {
+      a.cand_key[level][pos] = key;
+      a.cand_v[level][pos] = v;
+    }
+  }
+}
+
+// Resolves the remaining digits of the k-th key and the id cut inside its ties.
+__global__ void __launch_bounds__(kFinishThreads) sel_finish(SelArgs a) {
+  if (stopped(a.sc)) return;
+  __shared__ unsigned h[kDigits];
+  __shared__ unsigned long long s_prefix;
+  __shared__ int s_need, s_count;
+  const bool from1 = a.sc->cand_count[0] > kSmallCand;
+  const unsigned long long* ck = a.cand_key[from1 ? 1 : 0];
+  const int32_t* cv = a.cand_v[from1 ? 1 : 0];
+  const int cnt = a.sc->cand_count[from1 ? 1 : 0];
+  if (threadIdx.x == 0) {
+    s_prefix = a.sc->prefix;
+    s_need = a.sc->need;
+    s_count = cnt;
+  }
+  __syncthreads();
+  for (int level = from1 ? 2 : 1; level < kSelectLevels; ++level) {
+    const int shift = level < 5 ? 51 - kDigitBits * level : 0;
+    const int width = level < 5 ? kDigitBits : 3;
+    const int hishift = shift + width;
+    for (int d = threadIdx.x; d < kDigits; d += kFinishThreads) h[d] = 0u;
+    __syncthreads();
+    const unsigned long long pre = s_prefix;
+    for (int i = threadIdx.x; i < cnt; i += kFinishThreads) {
+      const unsigned long long key = ck[i];
+      if ((key >> hishift) == pre) atomicAdd(&h[(key >> shift) & ((1u << width) - 1u)], 1u);
+    }
+    __syncthreads();
+    const Bucket bk = find_bucket(h, 1 << width, s_need, true);
+    if (threadIdx.x == 0) {
+      s_prefix = (pre << width) | (unsigned)bk.b;
+      s_need = bk.need;
+      s_count = bk.count;
+    }
+    __syncthreads();
+  }
+  const unsigned long long theta_key = s_prefix;
+  const int need = s_need;        // how many of the tied keys belong to the top-k
+  const int ties = s_count;       // how many active nodes carry exactly theta_key
+  int cut = INT_MAX;
+  if (need < ties) {
+    // The need-th smallest external id among the ties: 31-bit ids, digits
+    // [30:20], [19:9], [8:0], ascending.
+    __shared__ int s_idpre, s_idneed;
+    if (threadIdx.x == 0) {
+      s_idpre = 0;
+      s_idneed = need;
+    }
+    __syncthreads();
+    const int widths[3] = {11, 11, 9};
+    int shift = 31;
+    for (int L = 0; L < 3; ++L) {
+      const int width = widths[L];
+      const int hishift = shift;
+      shift -= width;
+      for (int d = threadIdx.x; d < kDigits; d += kFinishThreads) h[d] = 0u;
+      __syncthreads();
+      const int pre = s_idpre;
+      for (int i = threadIdx.x; i < cnt; i += kFinishThreads) {
+        if (ck[i] != theta_key) continue;
+        const int e = ext_id(a, cv[i]);
+        if ((hishift >= 31 ? 0 : (e >> hishift)) == pre) atomicAdd(&h[(e >> shift) & ((1 << width) - 1)], 1u);
+      }
+      __syncthreads();
+      const Bucket bk = find_bucket(h, 1 << width, s_idneed, false);
+      if (threadIdx.x == 0) {
+        s_idpre = (pre << width) | bk.b;
+        s_idneed = bk.need;
+      }
+      __syncthreads();
+    }
+    cut = s_idpre;
+  }
+  if (threadIdx.x == 0) {
+    a.sc->theta_key = theta_key;
+    a.sc->theta = __longlong_as_double((long long)theta_key);
+    a.sc->cut_ext = cut;
+  }
+}
+
+// converged(), first half: nodes past position k leave M when u - eps < l(M[k]).
+__global__ void __launch_bounds__(kWG) sel_apply(SelArgs a) {
+  if (stopped(a.sc)) return;
+  const int m = a.sc->m;
+  const unsigned long long tk = a.sc->theta_key;
+  const double theta = a.sc->theta;
+  const int cut = a.sc->cut_ext;
+  const double eps = a.b.eps;
+  const long long stride = (long long)gridDim.x * kWG;
+  bool prog = false;
+  for (long long base = (long long)blockIdx.x * kWG; base < m; base += stride) {
+    const long long i = base + threadIdx.x;
+    const bool valid = i < m;
+    bool top = false, keep = false;
+    int v = 0;
+    if (valid) {
+      v = a.identity_in ? (int)i : a.act_in[i];
+      const unsigned long long key = a.keys[i];
+      top = key > tk || (key == tk && ext_id(a, v) <= cut);
+      if (!top) {
+        double lo, up;
+        bound_eval(a.b, v, lo, up);
+        keep = !(up - eps < theta);
+      }
+      if ((top || keep) && can_progress(a.b, v)) prog = true;
+    }
+    const int pt = wave_append(&a.sc->top_count, top);
+    if (top && pt < a.k) a.act_out[pt] = v;
+    const int pk = wave_append(&a.sc->kept_count, keep);
+    if (keep && (long long)a.k + pk < a.n) a.act_out[a.k + pk] = v;
+  }
+  if (__ballot(prog) && lane_id() == 0) atomicOr(&a.sc->progress, 1);
+}
+
+// converged(), second half: sort the top-k by (l desc, id asc) in LDS and test
+// every adjacent pair for eps-separation; decide whether the run stops.
+__global__ void __launch_bounds__(kFinishThreads) sel_check(SelArgs a) {
+  if (stopped(a.sc)) return;
+  if (a.sc->top_count != a.k) {
+    // The selection must produce exactly k top nodes; anything else is an
+    // internal inconsistency and stops the run before ids are dereferenced.
+    if (threadIdx.x == 0) a.sc->err = 2;
+    return;
+  }
+  __shared__ unsigned long long skey[kMaxK];
+  __shared__ int sext[kMaxK];
+  __shared__ int s_fail;
+  const int k = a.k;
+  int P = 1;
+  while (P < k) P <<= 1;
+  if (threadIdx.x == 0) s_fail = 0;
+  for (int i = threadIdx.x; i < P; i += kFinishThreads) {
+    if (i < k) {
+      const int v = a.act_out[i];
+      double lo, up;
+      bound_eval(a.b, v, lo, up);
+      skey[i] = key_of(lo);
+      sext[i] = ext_id(a, v);
+    } else {
+      skey[i] = 0ull;
+      sext[i] = INT_MAX;
+    }
+  }
+  __syncthreads();
+  // Bitonic sort, "before" = larger key, then smaller id.
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < P / 2; t += kFinishThreads) {
+        const int i = 2 * t - (t & (stride - 1));
+        const int j = i + stride;
+        const bool up = ((i & size) == 0);
+        const unsigned long long ki = skey[i], kj = skey[j];
+        const int ei = sext[i], ej = sext[j];
+        const bool j_before_i = kj > ki || (kj == ki && ej < ei);
+        if (j_before_i == up) {
+          skey[i] = kj;
+          skey[j] = ki;
+          sext[i] = ej;
+          sext[j] = ei;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const double eps = a.b.eps;
+  for (int i = threadIdx.x; i < k; i += kFinishThreads) {
+    const int v = int_id(a, sext[i]);
+    double lo, up;
+    bound_eval(a.b, v, lo, up);
+    a.top_sorted[i] = v;
+    a.top_lo[i] = lo;
+    a.top_up[i] = up;
+    if (i > 0 && up - eps >= __longlong_as_double((long long)skey[i - 1])) s_fail = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    RunScalars* sc = a.sc;
+    const int kept = sc->kept_count;
+    const bool certified = kept == 0 && !s_fail;
+    const bool walk_zero = a.b.fp32 ? (a.xmax32[a.b.r] == 0u) : (a.xmax64[a.b.r] == 0ull);
+    int status = -1;
+    if (certified) status = KATZ_OK;
+    else if (walk_zero) status = KATZ_W_EXACT_TIES;
+    else if (a.b.fp32 && !sc->progress) status = KATZ_W_PRECISION_LIMIT;
+    else if (a.b.r >= a.max_iter) status = KATZ_W_ITER_LIMIT;
+    sc->iterations = a.b.r;
+    sc->m = k + kept;
+    sc->top_count = 0;
+    sc->kept_count = 0;
+    sc->cand_count[0] = 0;
+    sc->cand_count[1] = 0;
+    sc->progress = 0;
+    if (status >= 0) {
+      sc->status = status;
+      sc->done = 1;
+    }
+  }
+}
+
+// Final outputs: external ids and bounds of the ranked nodes, and the largest
+// upper bound outside the top-k.
+__global__ void __launch_bounds__(kWG) write_top(SelArgs a, uint8_t* mark, int32_t* ids, double* lo,
+                                                 double* up) {
+  const int i = blockIdx.x * kWG + threadIdx.x;
+  if (i >= a.k) return;
+  const int v = a.top_sorted[i];
+  mark[v] = 1;
+  ids[i] = ext_id(a, v);
+  lo[i] = a.top_lo[i];
+  up[i] = a.top_up[i];
+}
+
+__global__ void __launch_bounds__(kWG) rest_max(SelArgs a, const uint8_t* mark, unsigned long long* out) {
+  double best = 0.0;
+  bool any = false;
+  for (long long v = (long long)blockIdx.x * kWG + threadIdx.x; v < a.n; v += (long long)gridDim.x * kWG) {
+    if (mark[v]) continue;
+    double lo, up;
+    bound_eval(a.b, (int)v, lo, up);
+    best = any ? fmax(best, up) : up;
+    any = true;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double y = __shfl_xor(best, o);
+    best = fmax(best, y);
+  }
+  if (lane_id() == 0) atomicMax(out, (unsigned long long)__double_as_longlong(best));
+}
+
+__global__ void __launch_bounds__(kWG) all_bounds(BoundArgs b, long long n, const int32_t* ext_of,
+                                                  double* lower, double* upper) {
+  const long long v = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (v >= n) return;
+  double lo, up;
+  bound_eval(b, (int)v, lo, up);
+  const int e = ext_of ? ext_of[v] : (int)v;
+  lower[e] = lo;
+  upper[e] = up;
+}
+
+__global__ void init_run(RunScalars* sc, long long n, double* sigma, double* sigma_sum, unsigned* xmax32,
+                         unsigned long long* xmax64, int max_iter, unsigned* hist) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  if (t == 0) {
+    RunScalars z{};
+    z.m = (int)n;
+    z.status = KATZ_OK;
+    *sc = z;
+    sigma[0] = 1.0;
+    sigma_sum[0] = 0.0;
+  }
+  for (long long i = t; i <= max_iter; i += stride) {
+    xmax32[i] = 0u;
+    xmax64[i] = 0ull;
+    if (i > 0) {
+      sigma[i] = 0.0;
+      sigma_sum[i] = 0.0;
+    }
+  }
+  for (long long i = t; i < 2 * kDigits; i += stride) hist[i] = 0u;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_prep_count(const void* row_ptr, int row_ptr_64, int64_t n, int64_t nnz, long long* blk,
+                             int nblocks, RunScalars* sc, hipStream_t s) {
+  if (row_ptr_64)
+    hipLaunchKernelGGL(prep_count<int64_t>, dim3(nblocks), dim3(kWG), 0, s, (const int64_t*)row_ptr,
+                       (long long)n, (long long)nnz, blk, nblocks, sc);
+  else
+    hipLaunchKernelGGL(prep_count<int32_t>, dim3(nblocks), dim3(kWG), 0, s, (const int32_t*)row_ptr,
+                       (long long)n, (long long)nnz, blk, nblocks, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_scan(long long* blk, int nblocks, RunScalars* sc, hipStream_t s) {
+  hipLaunchKernelGGL(prep_scan, dim3(1), dim3(kFinishThreads), 0, s, blk, nblocks, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_scatter(const void* row_ptr, int row_ptr_64, int64_t n, const long long* blk,
+                               int nblocks, RowDesc* desc, SegDesc* segs, HugeRow* huge, RunScalars* sc,
+                               hipStream_t s) {
+  if (row_ptr_64)
+    hipLaunchKernelGGL(prep_scatter<int64_t>, dim3(nblocks), dim3(kWG), 0, s, (const int64_t*)row_ptr,
+                       (long long)n, blk, nblocks, desc, segs, huge, sc);
+  else
+    hipLaunchKernelGGL(prep_scatter<int32_t>, dim3(nblocks), dim3(kWG), 0, s, (const int32_t*)row_ptr,
+                       (long long)n, blk, nblocks, desc, segs, huge, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate_strict(const RowDesc* desc, long long n, const int32_t* col, int undirected,
+                                  long long* row_off, int* row_len, RunScalars* sc, hipStream_t s) {
+  const long long blocks = (n * kWave + kWG - 1) / kWG;
+  hipLaunchKernelGGL(validate_strict, dim3((unsigned)blocks), dim3(kWG), 0, s, desc, n, col, n, sc);
+  if (undirected) {
+    const long long nb = (n + kWG - 1) / kWG;
+    hipLaunchKernelGGL(desc_to_rows, dim3((unsigned)nb), dim3(kWG), 0, s, desc, n, row_off, row_len);
+    hipLaunchKernelGGL(validate_symmetry, dim3((unsigned)nb), dim3(kWG), 0, s, row_off, row_len, col, n, sc);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_first(const IterArgs& a, int fp32, long long n, long long nnz, int validate,
+                             hipStream_t s) {
+  if (validate && nnz > 0) {
+    const long long nb = std::min<long long>((nnz + kWG - 1) / kWG, 4096);
+    hipLaunchKernelGGL(check_col_range, dim3((unsigned)nb), dim3(kWG), 0, s, a.col, nnz, n, a.sc);
+  }
+  const unsigned grid = (unsigned)((n + kWG - 1) / kWG);
+  if (fp32) hipLaunchKernelGGL(walk_first<true>, dim3(grid), dim3(kWG), 0, s, a);
+  else hipLaunchKernelGGL(walk_first<false>, dim3(grid), dim3(kWG), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, hipStream_t s) {
+  const unsigned grid = (unsigned)(total_blocks > 0 ? total_blocks : 1);
+  if (fp32) hipLaunchKernelGGL(walk_step<true>, dim3(grid), dim3(kWG), 0, s, a);
+  else hipLaunchKernelGGL(walk_step<false>, dim3(grid), dim3(kWG), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_iteration(const SelArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(sel_hist0, dim3(grid), dim3(kWG), 0, s, a);
+  hipLaunchKernelGGL(sel_scan, dim3(1), dim3(kFinishThreads), 0, s, a, 0);
+  hipLaunchKernelGGL(sel_compact, dim3(grid), dim3(kWG), 0, s, a, 0);
+  hipLaunchKernelGGL(sel_hist1, dim3(grid), dim3(kWG), 0, s, a);
+  hipLaunchKernelGGL(sel_scan, dim3(1), dim3(kFinishThreads), 0, s, a, 1);
+  hipLaunchKernelGGL(sel_compact, dim3(grid), dim3(kWG), 0, s, a, 1);
+  hipLaunchKernelGGL(sel_finish, dim3(1), dim3(kFinishThreads), 0, s, a);
+  hipLaunchKernelGGL(sel_apply, dim3(grid), dim3(kWG), 0, s, a);
+  hipLaunchKernelGGL(sel_check, dim3(1), dim3(kFinishThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_write_result(const SelArgs& a, uint8_t* mark, int32_t* out_ids, double* out_lo,
+                               double* out_up, unsigned long long* rest_bits, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(write_top, dim3((a.k + kWG - 1) / kWG), dim3(kWG), 0, s, a, mark, out_ids, out_lo, out_up);
+  hipLaunchKernelGGL(rest_max, dim3(grid), dim3(kWG), 0, s, a, (const uint8_t*)mark, rest_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_all_bounds(const BoundArgs& b, int64_t n, const int32_t* ext_of, double* lower,
+                             double* upper, hipStream_t s) {
+  const unsigned nb = (unsigned)((n + kWG - 1) / kWG);
+  hipLaunchKernelGGL(all_bounds, dim3(nb), dim3(kWG), 0, s, b, (long long)n, ext_of, lower, upper);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_run(RunScalars* sc, int64_t n, double* sigma, double* sigma_sum, unsigned* xmax32,
+                           unsigned long long* xmax64, int max_iter, unsigned* hist, hipStream_t s) {
+  hipLaunchKernelGGL(init_run, dim3(16), dim3(kWG), 0, s, sc, (long long)n, sigma, sigma_sum, xmax32, xmax64,
+                     max_iter, hist);
+  return hipGetLastError();
+}
+
+}  // namespace katz

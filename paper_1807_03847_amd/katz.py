@@ -1,0 +1,220 @@
+"""Thin Python binding of ``libkatz.so`` (the C ABI in ``include/katz.h``).
+
+Argument marshalling only: every step of the ranking runs in the HIP library.
+Torch tensors provide device memory and streams.  Importing this module fails
+loudly when the compiled library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkatz.so")
+
+OK = 0
+W_ITER_LIMIT = 1
+W_PRECISION_LIMIT = 2
+W_EXACT_TIES = 3
+E_INVALID_ARG = -1
+E_ALPHA = -2
+E_CSR = -3
+E_UPDATE = -4
+E_DEGREE_CAP = -5
+E_OOM = -6
+E_HIP = -7
+E_UNSUPPORTED = -8
+
+FP64 = 0
+FP32_MARGIN = 1
+TOPK = 0
+VALIDATE_NONE, VALIDATE_BASIC, VALIDATE_STRICT = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32_MARGIN}
+
+
+class KatzCSR(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("row_ptr_64", ctypes.c_int32), ("undirected", ctypes.c_int32)]
+
+
+class KatzParams(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("epsilon", ctypes.c_double), ("k", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32), ("criterion", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("reserved", ctypes.c_int32), ("degree_cap", ctypes.c_int64)]
+
+
+class KatzResult(ctypes.Structure):
+    _fields_ = [("topk_ids", ctypes.c_void_p), ("lower", ctypes.c_void_p), ("upper", ctypes.c_void_p),
+                ("rest_upper_max", ctypes.c_double), ("alpha_used", ctypes.c_double),
+                ("eta", ctypes.c_double), ("active_final", ctypes.c_int64),
+                ("iterations", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+class KatzTiming(ctypes.Structure):
+    _fields_ = [("walk_step_ms", ctypes.c_double), ("walk_step_launches", ctypes.c_int64),
+                ("walk_first_ms", ctypes.c_double), ("walk_first_launches", ctypes.c_int64),
+                ("select_ms", ctypes.c_double), ("select_iterations", ctypes.c_int64),
+                ("prep_ms", ctypes.c_double), ("result_ms", ctypes.c_double),
+                ("call_ms", ctypes.c_double), ("calls", ctypes.c_int64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1807_03847_amd._build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.katz_rank_static.restype = ctypes.c_int
+    lib.katz_rank_static.argtypes = [i32, ctypes.POINTER(KatzCSR), ctypes.POINTER(KatzParams),
+                                     ctypes.POINTER(KatzResult), ctypes.POINTER(vp), vp]
+    lib.katz_rank_update.restype = ctypes.c_int
+    lib.katz_rank_update.argtypes = [vp, vp, vp, i64, vp, vp, i64, ctypes.POINTER(KatzResult), vp]
+    lib.katz_bounds.restype = ctypes.c_int
+    lib.katz_bounds.argtypes = [ctypes.POINTER(KatzCSR), ctypes.POINTER(KatzParams), i32, vp, vp, vp]
+    lib.katz_state_free.restype = None
+    lib.katz_state_free.argtypes = [vp]
+    lib.katz_strerror.restype = ctypes.c_char_p
+    lib.katz_strerror.argtypes = [ctypes.c_int]
+    lib.katz_timing_enable.restype = None
+    lib.katz_timing_enable.argtypes = [ctypes.c_int]
+    lib.katz_timing_read.restype = ctypes.c_int
+    lib.katz_timing_read.argtypes = [ctypes.POINTER(KatzTiming)]
+    return lib
+
+
+lib = _load()
+
+
+class KatzError(RuntimeError):
+    def __init__(self, code: int):
+        self.code = code
+        super().__init__(f"katz error {code}: {strerror(code)}")
+
+
+def strerror(code: int) -> str:
+    return lib.katz_strerror(code).decode()
+
+
+@dataclass
+class RankResult:
+    topk: torch.Tensor          # int32 [k] node ids in ranking order
+    lower: torch.Tensor         # float64 [k]
+    upper: torch.Tensor         # float64 [k]
+    iterations: int
+    status: int
+    rest_upper_max: float
+    alpha: float
+    eta: float
+    active_final: int
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream_handle(stream, device):
+    if device.type != "cuda":
+        return ctypes.c_void_p(0)
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_csr(row_ptr: torch.Tensor, col: torch.Tensor, undirected: bool = True) -> KatzCSR:
+    if row_ptr.dtype not in (torch.int32, torch.int64) or col.dtype != torch.int32:
+        raise TypeError("row_ptr must be int32/int64 and col int32")
+    if not (row_ptr.is_contiguous() and col.is_contiguous()):
+        raise ValueError("row_ptr and col must be contiguous")
+    n = row_ptr.numel() - 1
+    return KatzCSR(n=n, nnz=col.numel(), row_ptr=row_ptr.data_ptr(), col=col.data_ptr() if col.numel() else 0,
+                   row_ptr_64=int(row_ptr.dtype == torch.int64), undirected=int(bool(undirected)))
+
+
+def make_params(k=1, alpha=0.0, eps=0.0, precision="fp64", max_iter=0, validate=VALIDATE_BASIC,
+                degree_cap=0) -> KatzParams:
+    return KatzParams(alpha=float(alpha), epsilon=float(eps), k=int(k), max_iter=int(max_iter),
+                      precision=PRECISIONS[precision] if isinstance(precision, str) else int(precision),
+                      criterion=TOPK, validate=int(validate), reserved=0, degree_cap=int(degree_cap))
+
+
+def _alloc_outputs(k, device):
+    return (torch.empty(k, dtype=torch.int32, device=device),
+            torch.empty(k, dtype=torch.float64, device=device),
+            torch.empty(k, dtype=torch.float64, device=device))
+
+
+def _to_result(res: KatzResult, ids, lo, up) -> RankResult:
+    return RankResult(topk=ids, lower=lo, upper=up, iterations=res.iterations, status=res.status,
+                      rest_upper_max=res.rest_upper_max, alpha=res.alpha_used, eta=res.eta,
+                      active_final=res.active_final)
+
+
+def rank_static(row_ptr, col, k, *, alpha=0.0, eps=0.0, precision="fp64", undirected=True, max_iter=0,
+                validate=VALIDATE_BASIC, stream=None, out=None) -> RankResult:
+    """katz_rank_static for one graph (Algorithm 1, top-k criterion).
+
+    ``out`` may pass preallocated (ids, lower, upper) tensors of length k."""
+    device = row_ptr.device
+    g = make_csr(row_ptr, col, undirected)
+    p = make_params(k, alpha, eps, precision, max_iter, validate)
+    ids, lo, up = out if out is not None else _alloc_outputs(k, device)
+    res = KatzResult(topk_ids=ids.data_ptr(), lower=lo.data_ptr(), upper=up.data_ptr())
+    rc = lib.katz_rank_static(1, ctypes.byref(g), ctypes.byref(p), ctypes.byref(res), None,
+                              _stream_handle(stream, device))
+    if rc < 0:
+        raise KatzError(rc)
+    return _to_result(res, ids, lo, up)
+
+
+def rank_static_batch(graphs, params, *, stream=None):
+    """katz_rank_static with count = len(graphs).
+
+    graphs: list of (row_ptr, col, undirected); params: list of dicts with the
+    keyword arguments of ``make_params``."""
+    count = len(graphs)
+    device = graphs[0][0].device
+    G = (KatzCSR * count)(*[make_csr(rp, c, u) for rp, c, u in graphs])
+    P = (KatzParams * count)(*[make_params(**pp) for pp in params])
+    outs = [_alloc_outputs(pp["k"], device) for pp in params]
+    R = (KatzResult * count)(*[KatzResult(topk_ids=i.data_ptr(), lower=l.data_ptr(), upper=u.data_ptr())
+                               for i, l, u in outs])
+    rc = lib.katz_rank_static(count, G, P, R, None, _stream_handle(stream, device))
+    if rc < 0:
+        raise KatzError(rc)
+    return [_to_result(R[i], *outs[i]) for i in range(count)]
+
+
+def bounds(row_ptr, col, r, *, alpha=0.0, precision="fp64", undirected=True, validate=VALIDATE_BASIC,
+           stream=None):
+    """katz_bounds: (lower, upper) of every node after exactly r iterations."""
+    device = row_ptr.device
+    g = make_csr(row_ptr, col, undirected)
+    p = make_params(1, alpha, 0.0, precision, 0, validate)
+    n = row_ptr.numel() - 1
+    lo = torch.empty(n, dtype=torch.float64, device=device)
+    up = torch.empty(n, dtype=torch.float64, device=device)
+    rc = lib.katz_bounds(ctypes.byref(g), ctypes.byref(p), int(r), _ptr(lo), _ptr(up),
+                         _stream_handle(stream, device))
+    if rc < 0:
+        raise KatzError(rc)
+    return lo, up
+
+
+def timing_enable(on: bool = True) -> None:
+    """Reset the library's device-time counters and start (or stop) recording."""
+    lib.katz_timing_enable(int(bool(on)))
+
+
+def timing_read() -> dict:
+    t = KatzTiming()
+    lib.katz_timing_read(ctypes.byref(t))
+    return {name: getattr(t, name) for name, _ in KatzTiming._fields_}
+
+
+def default_alpha(dmax: int) -> float:
+    return 1.0 / (1.0 + dmax)
+
+
+NEG_INF = -math.inf

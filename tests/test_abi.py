@@ -1,0 +1,111 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/katz.h declares, the binding's structs match the header's layout, and
+argument errors come back before any device work."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "katz.h")
+
+
+def K():
+    import paper_1807_03847_amd.katz as katz
+    return katz
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(katz_\w+)\s*\(", text, re.M)))
+
+
+def test_header_functions_exported():
+    names = declared_functions()
+    assert {"katz_rank_static", "katz_rank_update", "katz_bounds", "katz_state_free",
+            "katz_strerror"} <= set(names)
+    lib = ctypes.CDLL(K().LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_struct_layout_matches_header():
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "katz.h"
+#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
+int main(void) {
+  printf("katz_csr %zu\nkatz_params %zu\nkatz_result %zu\n", sizeof(katz_csr), sizeof(katz_params), sizeof(katz_result));
+  F(katz_csr, col) F(katz_csr, row_ptr_64) F(katz_csr, undirected)
+  F(katz_params, k) F(katz_params, precision) F(katz_params, validate) F(katz_params, degree_cap)
+  F(katz_result, rest_upper_max) F(katz_result, active_final) F(katz_result, iterations) F(katz_result, status)
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(line.split(" ") for line in out if line)
+    katz = K()
+    assert int(got["katz_csr"]) == ctypes.sizeof(katz.KatzCSR)
+    assert int(got["katz_params"]) == ctypes.sizeof(katz.KatzParams)
+    assert int(got["katz_result"]) == ctypes.sizeof(katz.KatzResult)
+    for key, val in got.items():
+        if "." in key:
+            struct, field = key.split(".")
+            cls = {"katz_csr": katz.KatzCSR, "katz_params": katz.KatzParams, "katz_result": katz.KatzResult}[struct]
+            assert getattr(cls, field).offset == int(val), key
+
+
+def test_strerror_covers_codes():
+    katz = K()
+    for code in range(-8, 4):
+        assert "unknown" not in katz.strerror(code)
+    assert "unknown" in katz.strerror(99)
+
+
+def _call(g, p, res, count=1):
+    katz = K()
+    return katz.lib.katz_rank_static(count, ctypes.byref(g) if g is not None else None,
+                                     ctypes.byref(p) if p is not None else None,
+                                     ctypes.byref(res) if res is not None else None, None, None)
+
+
+def test_argument_errors_before_device_work():
+    katz = K()
+    buf = (ctypes.c_int64 * 4)(0, 1, 2, 2)
+    col = (ctypes.c_int32 * 2)(1, 0)
+    out_ids = (ctypes.c_int32 * 8)()
+    out_d = (ctypes.c_double * 8)()
+    out_u = (ctypes.c_double * 8)()
+    g = katz.KatzCSR(n=3, nnz=2, row_ptr=ctypes.addressof(buf), col=ctypes.addressof(col), row_ptr_64=1,
+                     undirected=1)
+    res = katz.KatzResult(topk_ids=ctypes.addressof(out_ids), lower=ctypes.addressof(out_d),
+                          upper=ctypes.addressof(out_u))
+    assert _call(g, katz.make_params(0), res) == katz.E_INVALID_ARG          # k < 1
+    assert _call(g, katz.make_params(4), res) == katz.E_INVALID_ARG          # k > n
+    assert _call(g, katz.make_params(1, alpha=float("nan")), res) == katz.E_ALPHA
+    assert _call(g, katz.make_params(1, alpha=-1.0), res) == katz.E_ALPHA
+    assert _call(g, katz.make_params(1, eps=-1.0), res) == katz.E_INVALID_ARG
+    assert _call(g, katz.make_params(1, precision=7), res) == katz.E_INVALID_ARG
+    p = katz.make_params(1)
+    p.criterion = 1
+    assert _call(g, p, res) == katz.E_UNSUPPORTED
+    p = katz.make_params(1)
+    p.reserved = 3
+    assert _call(g, p, res) == katz.E_INVALID_ARG
+    assert _call(None, katz.make_params(1), res) == katz.E_INVALID_ARG
+    assert _call(g, katz.make_params(1), res, count=0) == katz.E_INVALID_ARG
+    bad = katz.KatzCSR(n=0, nnz=0, row_ptr=ctypes.addressof(buf), col=0, row_ptr_64=1, undirected=1)
+    assert _call(bad, katz.make_params(1), res) == katz.E_INVALID_ARG
+    lo = (ctypes.c_double * 3)()
+    assert katz.lib.katz_bounds(ctypes.byref(g), ctypes.byref(katz.make_params(1)), 0, ctypes.addressof(lo),
+                                ctypes.addressof(lo), None) == katz.E_INVALID_ARG
+    assert katz.lib.katz_rank_update(None, None, None, 0, None, None, 0, None, None) == katz.E_INVALID_ARG
