@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -68,6 +70,15 @@ def main():
 
     import synthgraph as sg
     import paper_1807_03847_amd.katz as katz
+
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {args.copy_mib} MiB read + {args.copy_mib} MiB written", flush=True)
+        del src, dst
 
     t = time.perf_counter()
     rp, col = sg.rmat(SCALE, EDGE_FACTOR, 0.57, 0.19, 0.19, seed=SEED)

@@ -1,31 +1,74 @@
 // Host runtime of the C ABI declared in include/katz.h.
 //
-// A call validates its arguments on the host, stages host inputs to the
+// A ranking call validates its arguments on the host, stages host inputs to the
 // device, bins the rows (prep), then enqueues iterations of Algorithm 1
-// (walk step + selection + converged()) and reads the device stop flag.
-// Workspace comes from a per-device pool of grow-only arenas, so repeated calls
-// on graphs of similar size do not call hipMalloc.
+// (walk step + selection + converged()) and reads the device stop flag one
+// iteration behind.  Static calls take their workspace from a per-device pool
+// of grow-only arenas; a dynamic state (Algorithm 2) owns its memory: the graph
+// as a CSR with per-row slack, the walk history x_1..x_r, c_r and M.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <limits>
 #include <mutex>
+#include <numeric>
+#include <utility>
 #include <vector>
 
 #include "katz_internal.h"
 
 #define KATZ_EXPORT extern "C" __attribute__((visibility("default")))
 
-namespace katz {
+#define KATZ_HIP(call)                    \
+  do {                                    \
+    if ((call) != hipSuccess) {           \
+      (void)hipGetLastError();            \
+      return KATZ_E_HIP;                  \
+    }                                     \
+  } while (0)
 
+#define KATZ_TRY(expr)          \
+  do {                          \
+    const int rc_ = (expr);     \
+    if (rc_ < 0) return rc_;    \
+  } while (0)
+
+namespace katz {
 namespace {
 
 constexpr double kU64 = 0x1p-53;   // unit roundoff of FP64
 constexpr double kU32 = 0x1p-24;   // unit roundoff of FP32
 
 // ---------------------------------------------------------------------------
-// Workspace arenas.
+// Pinned host mirrors used to read the device flags.
+// ---------------------------------------------------------------------------
+struct HostSync {
+  RunScalars* sc = nullptr;        // final read-back
+  RunScalars* ring = nullptr;      // 2 slots: per-pass copies of the flags
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  unsigned long long* bits = nullptr;   // 8 words of scalar read-backs
+
+  int init() {
+    if (sc) return KATZ_OK;
+    if (hipHostMalloc((void**)&sc, sizeof(RunScalars)) != hipSuccess) return KATZ_E_OOM;
+    if (hipHostMalloc((void**)&ring, 2 * sizeof(RunScalars)) != hipSuccess) return KATZ_E_OOM;
+    if (hipHostMalloc((void**)&bits, 8 * sizeof(unsigned long long)) != hipSuccess) return KATZ_E_OOM;
+    for (hipEvent_t& e : ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return KATZ_E_HIP;
+    return KATZ_OK;
+  }
+  ~HostSync() {
+    if (sc) (void)hipHostFree(sc);
+    if (ring) (void)hipHostFree(ring);
+    if (bits) (void)hipHostFree(bits);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Workspace arenas for static calls.
 // ---------------------------------------------------------------------------
 struct Arena {
   int device = -1;
@@ -33,13 +76,10 @@ struct Arena {
   size_t cap = 0;
   size_t used = 0;
   bool measuring = false;
-  RunScalars* host_sc = nullptr;          // pinned
-  unsigned long long* host_bits = nullptr;  // pinned, 8 words
+  HostSync hs;
 
   ~Arena() {
     if (base) (void)hipFree(base);
-    if (host_sc) (void)hipHostFree(host_sc);
-    if (host_bits) (void)hipHostFree(host_bits);
   }
   template <class T>
   T* take(size_t count) {
@@ -49,10 +89,7 @@ struct Arena {
     return p;
   }
   int grow(size_t bytes) {
-    if (!host_sc) {
-      if (hipHostMalloc((void**)&host_sc, sizeof(RunScalars)) != hipSuccess) return KATZ_E_OOM;
-      if (hipHostMalloc((void**)&host_bits, 8 * sizeof(unsigned long long)) != hipSuccess) return KATZ_E_OOM;
-    }
+    KATZ_TRY(hs.init());
     if (bytes <= cap) return KATZ_OK;
     if (base) (void)hipFree(base);
     base = nullptr;
@@ -185,14 +222,6 @@ struct CallTimer {
   }
 };
 
-#define KATZ_HIP(call)                    \
-  do {                                    \
-    if ((call) != hipSuccess) {           \
-      (void)hipGetLastError();            \
-      return KATZ_E_HIP;                  \
-    }                                     \
-  } while (0)
-
 int clog2(long long d) {
   int e = 0;
   while ((1ll << e) < d) ++e;
@@ -216,6 +245,7 @@ int check_params(const katz_params* p, long long n, bool need_k) {
   if (!p) return KATZ_E_INVALID_ARG;
   if (p->precision != KATZ_FP64 && p->precision != KATZ_FP32_MARGIN) return KATZ_E_INVALID_ARG;
   if (p->validate < 0 || p->validate > 2 || p->reserved != 0 || p->max_iter < 0) return KATZ_E_INVALID_ARG;
+  if (p->degree_cap < 0) return KATZ_E_INVALID_ARG;
   if (std::isnan(p->alpha) || p->alpha < 0.0 || std::isinf(p->alpha)) return KATZ_E_ALPHA;
   if (need_k) {
     if (p->criterion != KATZ_TOPK) return KATZ_E_UNSUPPORTED;
@@ -227,29 +257,42 @@ int check_params(const katz_params* p, long long n, bool need_k) {
 }
 
 // ---------------------------------------------------------------------------
-// One prepared graph on the device.
+// Bins of one graph (or of one list of affected rows).
 // ---------------------------------------------------------------------------
-struct Prepared {
-  const void* row_ptr = nullptr;
-  const int32_t* col = nullptr;
+struct Bins {
   RowDesc* desc = nullptr;
   SegDesc* segs = nullptr;
   HugeRow* huge = nullptr;
-  long long* blk = nullptr;
-  long long* row_off = nullptr;
-  int* row_len = nullptr;
   int* seg_done = nullptr;
-  RunScalars* sc = nullptr;
+  long long* blk = nullptr;
   int nblocks = 0;
   long long seg_cap = 0, huge_cap = 0;
-  // read back after prep
+  long long count = 0;   // rows binned
   long long bin_count[NUM_BINS] = {};
   long long bin_base[NUM_BINS] = {};
   long long seg_total = 0;
   int dmax = 0;
+
+  void read_back(const RunScalars& h, long long rows) {
+    std::memcpy(bin_count, h.bin_count, sizeof(bin_count));
+    std::memcpy(bin_base, h.bin_base, sizeof(bin_base));
+    seg_total = h.seg_total;
+    dmax = h.dmax;
+    count = rows;
+  }
 };
 
-struct RunBuffers {
+// Capacities for binning up to `rows` rows that hold at most `arcs` arcs.
+void bins_caps(Bins& b, long long rows, long long arcs) {
+  b.nblocks = (int)std::max<long long>(1, (rows + kWG - 1) / kWG);
+  b.seg_cap = 2 * (arcs / kSeg) + 2;
+  b.huge_cap = arcs / (kBlockRowMax + 1) + 1;
+}
+
+// ---------------------------------------------------------------------------
+// Per-run buffers.
+// ---------------------------------------------------------------------------
+struct Work {
   void* x[2] = {nullptr, nullptr};
   double* c = nullptr;
   float* e = nullptr;
@@ -268,125 +311,39 @@ struct RunBuffers {
   double* top_up = nullptr;
   uint8_t* mark = nullptr;
   unsigned long long* rest_bits = nullptr;
-  int32_t* out_ids = nullptr;
-  double* out_lo = nullptr;
-  double* out_up = nullptr;
+  RunScalars* sc = nullptr;
 };
 
-// Lays out every buffer of one call in the arena (measure pass, then real pass).
-struct Plan {
-  const katz_csr* g;
-  int fp32;
-  int k;
-  int max_iter;
-  int validate;
-  bool rp_host, col_host, out_host, select;
-  size_t out_n;   // elements per output array (k for ranking, n for bounds)
+struct Scalars {
+  double alpha = 0, gamma = 0, beta = 0, beta_hi = 0;
+  double rho = 0;
+  std::vector<double> eta, etap;   // [max_iter + 1]
 };
 
-void layout(Arena& ar, const Plan& pl, Prepared& pr, RunBuffers& rb) {
-  const long long n = pl.g->n, nnz = pl.g->nnz;
-  ar.used = 0;
-  pr.nblocks = (int)((n + kWG - 1) / kWG);
-  pr.seg_cap = 2 * (nnz / kSeg) + 2;
-  pr.huge_cap = nnz / (kBlockRowMax + 1) + 1;
-  pr.sc = ar.take<RunScalars>(1);
-  pr.blk = ar.take<long long>((size_t)(NUM_BINS + 1) * pr.nblocks);
-  pr.desc = ar.take<RowDesc>(n);
-  pr.segs = ar.take<SegDesc>(pr.seg_cap);
-  pr.huge = ar.take<HugeRow>(pr.huge_cap);
-  pr.seg_done = ar.take<int>(pr.huge_cap);
-  if (pl.rp_host) pr.row_ptr = ar.take<char>((size_t)(n + 1) * (pl.g->row_ptr_64 ? 8 : 4));
-  if (pl.col_host) pr.col = ar.take<int32_t>(std::max<long long>(nnz, 1));
-  if (pl.validate == KATZ_VALIDATE_STRICT && pl.g->undirected) {
-    pr.row_off = ar.take<long long>(n);
-    pr.row_len = ar.take<int>(n);
-  }
-  const size_t xs = pl.fp32 ? 4 : 8;
-  rb.x[0] = ar.take<char>(n * xs);
-  rb.x[1] = ar.take<char>(n * xs);
-  rb.c = ar.take<double>(n);
-  if (pl.fp32) rb.e = ar.take<float>(n);
-  rb.partial = ar.take<char>(pr.seg_cap * xs);
-  rb.xmax32 = ar.take<unsigned>(pl.max_iter + 1);
-  rb.xmax64 = ar.take<unsigned long long>(pl.max_iter + 1);
-  rb.sigma = ar.take<double>(pl.max_iter + 1);
-  rb.sigma_sum = ar.take<double>(pl.max_iter + 1);
-  rb.hist = ar.take<unsigned>(2 * kDigits);
-  if (pl.select) {
-    rb.act[0] = ar.take<int32_t>(n);
-    rb.act[1] = ar.take<int32_t>(n);
-    rb.keys = ar.take<unsigned long long>(n);
-    rb.cand_key[0] = ar.take<unsigned long long>(n);
-    rb.cand_key[1] = ar.take<unsigned long long>(n);
-    rb.cand_v[0] = ar.take<int32_t>(n);
-    rb.cand_v[1] = ar.take<int32_t>(n);
-    rb.top_sorted = ar.take<int32_t>(pl.k);
-    rb.top_lo = ar.take<double>(pl.k);
-    rb.top_up = ar.take<double>(pl.k);
-    rb.mark = ar.take<uint8_t>(n);
-    rb.rest_bits = ar.take<unsigned long long>(1);
-  }
-  if (pl.out_host) {
-    rb.out_ids = ar.take<int32_t>(pl.out_n);
-    rb.out_lo = ar.take<double>(pl.out_n);
-    rb.out_up = ar.take<double>(pl.out_n);
-  }
+// gamma and beta exactly as the plain FP64 method evaluates them (Theorem 1);
+// beta_hi rounded upward for the FP32 form: 1 - alpha d with one rounding
+// (fma), each of the three operations at most one ulp, then 8 ulps of slack.
+void set_gamma(Scalars& S, int dmax) {
+  S.gamma = (double)dmax / (1.0 - S.alpha * (double)dmax);
+  S.beta = S.alpha * S.gamma;
+  const double den = std::fma(-S.alpha, (double)dmax, 1.0);
+  S.beta_hi = S.alpha * ((double)dmax / den) * (1.0 + 8.0 * kU64);
 }
 
-int plan_and_allocate(Arena& ar, const Plan& pl, Prepared& pr, RunBuffers& rb) {
-  ar.measuring = true;
-  layout(ar, pl, pr, rb);
-  ar.measuring = false;
-  const int rc = ar.grow(ar.used);
-  if (rc) return rc;
-  layout(ar, pl, pr, rb);
-  return KATZ_OK;
-}
-
-// Stages host inputs, bins the rows, reads back d_max and the bin sizes.
-int prepare(Arena& ar, const Plan& pl, Prepared& pr, int max_iter, RunBuffers& rb, hipStream_t s) {
-  const katz_csr* g = pl.g;
-  if (pl.rp_host) {
-    KATZ_HIP(hipMemcpyAsync((void*)pr.row_ptr, g->row_ptr, (size_t)(g->n + 1) * (g->row_ptr_64 ? 8 : 4),
-                            hipMemcpyHostToDevice, s));
-  } else {
-    pr.row_ptr = g->row_ptr;
-  }
-  if (pl.col_host) {
-    if (g->nnz > 0)
-      KATZ_HIP(hipMemcpyAsync((void*)pr.col, g->col, (size_t)g->nnz * 4, hipMemcpyHostToDevice, s));
-  } else {
-    pr.col = g->col;
-  }
-  KATZ_HIP(launch_init_run(pr.sc, g->n, rb.sigma, rb.sigma_sum, rb.xmax32, rb.xmax64, max_iter, rb.hist, s));
-  KATZ_HIP(hipMemsetAsync(pr.seg_done, 0, sizeof(int) * pr.huge_cap, s));
-  KATZ_HIP(launch_prep_count(pr.row_ptr, g->row_ptr_64, g->n, g->nnz, pr.blk, pr.nblocks, pr.sc, s));
-  KATZ_HIP(launch_prep_scan(pr.blk, pr.nblocks, pr.sc, s));
-  KATZ_HIP(launch_prep_scatter(pr.row_ptr, g->row_ptr_64, g->n, pr.blk, pr.nblocks, pr.desc, pr.segs, pr.huge,
-                               pr.sc, s));
-  KATZ_HIP(hipMemcpyAsync(ar.host_sc, pr.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
-  KATZ_HIP(hipStreamSynchronize(s));
-  if (ar.host_sc->err) return KATZ_E_CSR;
-  std::memcpy(pr.bin_count, ar.host_sc->bin_count, sizeof(pr.bin_count));
-  std::memcpy(pr.bin_base, ar.host_sc->bin_base, sizeof(pr.bin_base));
-  pr.seg_total = ar.host_sc->seg_total;
-  pr.dmax = ar.host_sc->dmax;
-  if (pl.validate == KATZ_VALIDATE_STRICT) {
-    KATZ_HIP(launch_validate_strict(pr.desc, g->n, pr.col, g->undirected, pr.row_off, pr.row_len, pr.sc, s));
-    KATZ_HIP(hipMemcpyAsync(ar.host_sc, pr.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
-    KATZ_HIP(hipStreamSynchronize(s));
-    if (ar.host_sc->err) return KATZ_E_CSR;
-  }
+int resolve_alpha(double alpha_in, int dmax, Scalars& S) {
+  const double alpha = alpha_in == 0.0 ? 1.0 / (1.0 + (double)dmax) : alpha_in;
+  if (!(alpha > 0.0) || !(alpha * (double)dmax < 1.0)) return KATZ_E_ALPHA;
+  S.alpha = alpha;
+  set_gamma(S, dmax);
   return KATZ_OK;
 }
 
 // Deepest rounding chain of any row sum under the bin schedule: serial adds per
 // lane, then the butterfly levels (and the segment combine for huge rows).
-int max_reduction_depth(const Prepared& pr) {
+int max_reduction_depth(const Bins& b) {
   int m = 0;
   auto upd = [&](int bin, int d) {
-    if (pr.bin_count[bin] > 0) m = std::max(m, d);
+    if (b.bin_count[bin] > 0) m = std::max(m, d);
   };
   upd(BIN_G4, 2);
   upd(BIN_G8, 3);
@@ -394,49 +351,194 @@ int max_reduction_depth(const Prepared& pr) {
   upd(BIN_G32, 5);
   upd(BIN_W64, (kPerLane - 1) + 6);
   upd(BIN_B256, (kPerLane - 1) + 8);
-  if (pr.bin_count[BIN_HUGE] > 0) {
-    const long long max_seg = (pr.dmax + kSeg - 1) / kSeg;
+  if (b.bin_count[BIN_HUGE] > 0) {
+    const long long max_seg = (b.dmax + kSeg - 1) / kSeg;
     const long long q = (max_seg + kWave - 1) / kWave;
-    m = std::max<long long>(m, (kPerLane - 1) + 8 + (q - 1) + 6);
+    m = (int)std::max<long long>(m, (kPerLane - 1) + 8 + (q - 1) + 6);
   }
   return m;
 }
 
-struct Scalars {
-  double alpha, gamma, beta, beta_hi;
-  double rho;
-  std::vector<double> eta, etap;   // [max_iter + 1]
-  double tau_coef0;
-};
-
 // FP32 form: eta_r bounds the relative error of every entry of x~_r; eta_1 = 0
 // because the first walk step sums exact ones; later steps multiply by (1 + rho),
 // rho = gamma_m = m u / (1 - m u) for the deepest reduction chain m.
-void fp32_tables(Scalars& S, const Prepared& pr, int max_iter) {
-  const int m = max_reduction_depth(pr);
+void fp32_tables(Scalars& S, const Bins& b, int max_iter) {
+  const int m = max_reduction_depth(b);
   S.rho = (m * kU32) / (1.0 - m * kU32) * (1.0 + 0x1p-40);
   S.eta.assign(max_iter + 1, 0.0);
   S.etap.assign(max_iter + 1, 0.0);
   const double up = 1.0 + 0x1p-50;
-  S.eta[1] = pr.dmax < (1 << 24) ? 0.0 : kU32;
+  S.eta[1] = b.dmax < (1 << 24) ? 0.0 : kU32;
   for (int r = 2; r <= max_iter; ++r) S.eta[r] = ((1.0 + S.eta[r - 1]) * (1.0 + S.rho) - 1.0) * up;
   for (int r = 1; r <= max_iter; ++r) S.etap[r] = S.eta[r] / (1.0 - S.eta[r]) * up;
 }
 
-BoundArgs bound_args(const Plan& pl, const Prepared& pr, const RunBuffers& rb, const Scalars& S, int r,
-                     double eps, int undirected) {
+}  // namespace
+}  // namespace katz
+
+namespace katz {
+// Device scratch of one update batch; grows to the largest batch seen.
+struct UpdateBufs {
+  int32_t* pairs = nullptr; size_t pairs_cap = 0;       // a[...] then b[...]
+  int32_t* rows = nullptr; size_t rows_cap = 0;
+  long long* ll = nullptr; size_t ll_cap = 0;           // ins_off | del_off | new_len | sbase | dest_off
+  int* ints = nullptr; size_t ints_cap = 0;             // ins_cnt | del_cnt | delta | dest_cap | caps
+  int32_t* dst = nullptr; size_t dst_cap = 0;           // ins_dst | del_dst
+  int32_t* scratch = nullptr; size_t scratch_cap = 0;
+};
+}  // namespace katz
+
+// ---------------------------------------------------------------------------
+// Dynamic state (opaque in the C ABI).
+// ---------------------------------------------------------------------------
+struct katz_state {
+  int device = 0;
+  long long n = 0, nnz = 0;
+  double alpha = 0, eps = 0;
+  int k = 1, max_iter = 1000;
+  long long degree_cap = 0;
+  int r = 0;       // iterations reached
+  int cur = 0;     // active-list buffer holding M
+  // Slack CSR.
+  long long* row_off = nullptr;
+  int* row_len = nullptr;
+  int* row_cap = nullptr;
+  int32_t* pool = nullptr;
+  long long pool_cap = 0, pool_used = 0;
+  katz::Bins bins;    // whole graph
+  katz::Bins lbins;   // one re-walk level
+  katz::Work w;
+  katz::Scalars S;
+  std::vector<double*> X;          // X[1..]: walk history (X[0] unused)
+  double** X_dev = nullptr;        // device copy of the pointer table
+  int X_dev_cap = 0;
+  // Re-walk scratch.
+  int* level_of = nullptr;
+  int32_t* clist = nullptr;
+  int* counter = nullptr;
+  int* dmax_dev = nullptr;
+  int* err_dev = nullptr;
+  unsigned long long* min_bits = nullptr;
+  uint8_t* tmark = nullptr;        // touched rows
+  katz::RunScalars* sc2 = nullptr;       // prep of one level
+  katz::UpdateBufs ub;
+  int X_dev_synced = 0;            // entries of X already copied to X_dev
+  katz::HostSync hs;
+  std::vector<void*> owned;
+
+  ~katz_state() {
+    for (void* p : owned) (void)hipFree(p);
+    for (double* p : X)
+      if (p) (void)hipFree(p);
+  }
+};
+
+namespace katz {
+namespace {
+
+template <class T>
+T* dalloc(katz_state* st, size_t count) {
+  T* p = nullptr;
+  if (hipMalloc((void**)&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  st->owned.push_back(p);
+  return p;
+}
+
+void dfree(katz_state* st, void* p) {
+  auto it = std::find(st->owned.begin(), st->owned.end(), p);
+  if (it != st->owned.end()) {
+    st->owned.erase(it);
+    (void)hipFree(p);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A run: the graph view, its bins, the buffers and the parameters.
+// ---------------------------------------------------------------------------
+struct Run {
+  long long n = 0, nnz = 0;
+  int undirected = 1;
+  int fp32 = 0;
+  int validate = 0;
+  const int32_t* col = nullptr;
+  Bins* bins = nullptr;
+  Work* w = nullptr;
+  katz_state* st = nullptr;   // history mode when set (FP64 only)
+  Scalars* S = nullptr;
+  double eps = 0;
+  int k = 1;
+  int max_iter = 1000;
+  int cur = 0;
+  bool first_select = true;
+  int grid = 1;
+};
+
+void* x_at(const Run& run, int r) { return run.st ? (void*)run.st->X[r] : run.w->x[r & 1]; }
+
+void fill_blocks(IterArgs& ia, const Bins& b, bool write_empty, long long& total) {
+  long long blocks[NUM_BINS] = {};
+  blocks[BIN_HUGE] = b.seg_total;
+  blocks[BIN_B256] = b.bin_count[BIN_B256];
+  blocks[BIN_W64] = (b.bin_count[BIN_W64] + 3) / 4;
+  blocks[BIN_G32] = (b.bin_count[BIN_G32] + 7) / 8;
+  blocks[BIN_G16] = (b.bin_count[BIN_G16] + 15) / 16;
+  blocks[BIN_G8] = (b.bin_count[BIN_G8] + 31) / 32;
+  blocks[BIN_G4] = (b.bin_count[BIN_G4] + 63) / 64;
+  blocks[BIN_EMPTY] = write_empty ? (b.bin_count[BIN_EMPTY] + kWG - 1) / kWG : 0;
+  ia.first_block[0] = 0;
+  for (int i = 0; i < NUM_BINS; ++i) ia.first_block[i + 1] = ia.first_block[i] + blocks[i];
+  total = ia.first_block[NUM_BINS];
+}
+
+IterArgs iter_args(const Run& run, const Bins& b, int r, bool rewalk, long long& total_blocks) {
+  IterArgs ia{};
+  ia.desc = b.desc;
+  ia.col = run.col;
+  ia.segs = b.segs;
+  ia.huge = b.huge;
+  ia.seg_done = b.seg_done;
+  for (int i = 0; i < NUM_BINS; ++i) {
+    ia.bin_base[i] = b.bin_base[i];
+    ia.bin_count[i] = b.bin_count[i];
+  }
+  fill_blocks(ia, b, rewalk || r == 2, total_blocks);
+  ia.x_in = r >= 2 ? x_at(run, r - 1) : nullptr;
+  ia.x_out = x_at(run, r);
+  ia.c = run.w->c;
+  ia.e = run.w->e;
+  ia.partial = run.w->partial;
+  ia.xmax32 = run.w->xmax32;
+  ia.xmax64 = run.w->xmax64;
+  ia.sigma = run.w->sigma;
+  ia.sigma_sum = run.w->sigma_sum;
+  ia.sc = run.w->sc;
+  ia.n = (int)run.n;
+  ia.r = r;
+  ia.count_first = (int)b.count;
+  ia.clog2_dmax = clog2(std::max(run.bins->dmax, 1));
+  ia.rewalk = rewalk ? 1 : 0;
+  ia.alpha = run.S->alpha;
+  ia.etap = run.fp32 ? run.S->etap[r] : 0.0;
+  return ia;
+}
+
+BoundArgs bound_args(const Run& run, int r) {
+  const Scalars& S = *run.S;
   BoundArgs b{};
-  b.c = rb.c;
-  b.x = rb.x[r & 1];
-  b.e = rb.e;
-  b.sigma = rb.sigma;
-  b.sigma_sum = rb.sigma_sum;
+  b.c = run.w->c;
+  b.x = x_at(run, r);
+  b.e = run.w->e;
+  b.sigma = run.w->sigma;
+  b.sigma_sum = run.w->sigma_sum;
   b.r = r;
-  b.fp32 = pl.fp32;
-  b.undirected = undirected;
+  b.fp32 = run.fp32;
+  b.undirected = run.undirected;
   b.alpha = S.alpha;
-  b.eps = eps;
-  if (!pl.fp32) {
+  b.eps = run.eps;
+  if (!run.fp32) {
     b.beta = S.beta;
   } else {
     // kappa covers the FP64 roundings of sigma_r (r products), of s~ (one),
@@ -448,87 +550,255 @@ BoundArgs bound_args(const Plan& pl, const Prepared& pr, const RunBuffers& rb, c
     b.f_lo_c = 1.0 - kap;
     b.f_hi_c = 1.0 + kap;
     b.f_e = 1.0 + kap;
-    b.f_lo_s = undirected ? S.alpha * (1.0 - ep) * (1.0 - kap) * (1.0 - 8.0 * kU64) : 0.0;
+    b.f_lo_s = run.undirected ? S.alpha * (1.0 - ep) * (1.0 - kap) * (1.0 - 8.0 * kU64) : 0.0;
     b.f_hi_s = S.beta_hi * (1.0 + ep) * (1.0 + kap) * (1.0 + 8.0 * kU64);
     // Underflow of x~ entries: at most (deg_max + 1) 2^-126 per entry and level
     // in units of sigma_i, carried through c (r levels) and the bounds (beta).
-    b.tau_coef = 4.0 * (r + S.beta_hi + 2.0) * (pr.dmax + 2.0) * 0x1p-126;
+    b.tau_coef = 4.0 * (r + S.beta_hi + 2.0) * (run.bins->dmax + 2.0) * 0x1p-126;
   }
   return b;
 }
 
-void fill_blocks(IterArgs& ia, const Prepared& pr, bool write_empty, long long& total) {
-  long long blocks[NUM_BINS] = {};
-  blocks[BIN_HUGE] = pr.seg_total;
-  blocks[BIN_B256] = pr.bin_count[BIN_B256];
-  blocks[BIN_W64] = (pr.bin_count[BIN_W64] + 3) / 4;
-  blocks[BIN_G32] = (pr.bin_count[BIN_G32] + 7) / 8;
-  blocks[BIN_G16] = (pr.bin_count[BIN_G16] + 15) / 16;
-  blocks[BIN_G8] = (pr.bin_count[BIN_G8] + 31) / 32;
-  blocks[BIN_G4] = (pr.bin_count[BIN_G4] + 63) / 64;
-  blocks[BIN_EMPTY] = write_empty ? (pr.bin_count[BIN_EMPTY] + kWG - 1) / kWG : 0;
-  ia.first_block[0] = 0;
-  for (int b = 0; b < NUM_BINS; ++b) ia.first_block[b + 1] = ia.first_block[b] + blocks[b];
-  total = ia.first_block[NUM_BINS];
+SelArgs sel_args(const Run& run, int r) {
+  SelArgs sa{};
+  sa.b = bound_args(run, r);
+  sa.act_in = run.w->act[run.cur];
+  sa.act_out = run.w->act[run.cur ^ 1];
+  sa.act_out_idx = run.cur ^ 1;
+  sa.keys = run.w->keys;
+  sa.cand_key[0] = run.w->cand_key[0];
+  sa.cand_key[1] = run.w->cand_key[1];
+  sa.cand_v[0] = run.w->cand_v[0];
+  sa.cand_v[1] = run.w->cand_v[1];
+  sa.hist = run.w->hist;
+  sa.top_sorted = run.w->top_sorted;
+  sa.top_lo = run.w->top_lo;
+  sa.top_up = run.w->top_up;
+  sa.xmax32 = run.w->xmax32;
+  sa.xmax64 = run.w->xmax64;
+  sa.sc = run.w->sc;
+  sa.identity_in = run.first_select ? 1 : 0;
+  sa.k = run.k;
+  sa.n = (int)run.n;
+  sa.max_iter = run.max_iter;
+  return sa;
 }
 
-IterArgs iter_args(const Plan& pl, const Prepared& pr, const RunBuffers& rb, const Scalars& S, int r,
-                   long long& total_blocks) {
-  IterArgs ia{};
-  ia.desc = pr.desc;
-  ia.col = pr.col;
-  ia.segs = pr.segs;
-  ia.huge = pr.huge;
-  for (int b = 0; b < NUM_BINS; ++b) {
-    ia.bin_base[b] = pr.bin_base[b];
-    ia.bin_count[b] = pr.bin_count[b];
-  }
-  fill_blocks(ia, pr, r == 2, total_blocks);
-  ia.x_in = rb.x[(r + 1) & 1];
-  ia.x_out = rb.x[r & 1];
-  ia.c = rb.c;
-  ia.e = rb.e;
-  ia.partial = rb.partial;
-  ia.seg_done = pr.seg_done;
-  ia.xmax32 = rb.xmax32;
-  ia.xmax64 = rb.xmax64;
-  ia.sigma = rb.sigma;
-  ia.sigma_sum = rb.sigma_sum;
-  ia.sc = pr.sc;
-  ia.n = (int)pl.g->n;
-  ia.r = r;
-  ia.validate_cols = (r == 1 && pl.validate >= KATZ_VALIDATE_BASIC) ? 1 : 0;
-  ia.write_empty = r == 2;
-  ia.clog2_dmax = clog2(std::max(pr.dmax, 1));
-  ia.alpha = S.alpha;
-  ia.etap = pl.fp32 ? S.etap[r] : 0.0;
-  return ia;
-}
+int ensure_levels(katz_state* st, int r);
 
-int resolve_alpha(const katz_params* p, int dmax, Scalars& S) {
-  const double alpha = p->alpha == 0.0 ? 1.0 / (1.0 + (double)dmax) : p->alpha;
-  if (!(alpha > 0.0) || !(alpha * (double)dmax < 1.0)) return KATZ_E_ALPHA;
-  S.alpha = alpha;
-  // gamma and beta exactly as the plain FP64 method evaluates them (Theorem 1).
-  S.gamma = (double)dmax / (1.0 - alpha * (double)dmax);
-  S.beta = alpha * S.gamma;
-  // Upward-rounded beta for the FP32 form: 1 - alpha d with one rounding (fma),
-  // each of the three operations at most one ulp, then 8 ulps of slack.
-  const double den = std::fma(-alpha, (double)dmax, 1.0);
-  S.beta_hi = alpha * ((double)dmax / den) * (1.0 + 8.0 * kU64);
+int enqueue_walk(Run& run, int r, hipStream_t s, CallTimer& T) {
+  long long tb = 0;
+  const IterArgs ia = iter_args(run, *run.bins, r, false, tb);
+  const int tw = T.start(r == 1 ? T_FIRST : T_STEP, s);
+  if (r == 1) KATZ_HIP(launch_walk_first(ia, run.fp32, run.n, run.nnz, run.validate >= KATZ_VALIDATE_BASIC, s));
+  else KATZ_HIP(launch_walk_step(ia, run.fp32, tb, s));
+  T.stop(tw, s);
   return KATZ_OK;
 }
 
-int sync_every_default() { return 1; }
+int enqueue_select(Run& run, int r, hipStream_t s, CallTimer& T) {
+  const SelArgs sa = sel_args(run, r);
+  const int ts = T.start(T_SELECT, s);
+  KATZ_HIP(launch_select_iteration(sa, run.grid, s));
+  T.stop(ts, s);
+  run.cur ^= 1;
+  run.first_select = false;
+  return KATZ_OK;
+}
+
+// Iterates until the device stop flag: walk step r_next, selection,
+// converged(); then r_next + 1, ...  With check_first, the first pass is only a
+// selection at r_next - 1 (after a dynamic update).  Pass p is enqueued before
+// the host waits for the flags of pass p - 1; passes enqueued after the stop
+// return at once on the device.  On return hs.sc holds the final flags.
+int iterate(Run& run, HostSync& hs, int r_next, bool check_first, hipStream_t s, CallTimer& T) {
+  bool stopped = false;
+  int pass = 0;
+  int r = r_next;
+  while (!stopped) {
+    if (pass == 0 && check_first) {
+      KATZ_TRY(enqueue_select(run, r - 1, s, T));
+    } else if (r <= run.max_iter) {
+      if (run.st) KATZ_TRY(ensure_levels(run.st, r));
+      KATZ_TRY(enqueue_walk(run, r, s, T));
+      KATZ_TRY(enqueue_select(run, r, s, T));
+      ++r;
+    } else {
+      break;
+    }
+    KATZ_HIP(hipMemcpyAsync(&hs.ring[pass & 1], run.w->sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipEventRecord(hs.ev[pass & 1], s));
+    if (pass >= 1) {
+      KATZ_HIP(hipEventSynchronize(hs.ev[(pass - 1) & 1]));
+      const RunScalars& prev = hs.ring[(pass - 1) & 1];
+      if (prev.err || prev.done) stopped = true;
+    }
+    ++pass;
+  }
+  KATZ_HIP(hipMemcpyAsync(hs.sc, run.w->sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+  KATZ_HIP(hipStreamSynchronize(s));
+  if (hs.sc->err) return hs.sc->err == 2 ? KATZ_E_HIP : KATZ_E_CSR;
+  return KATZ_OK;
+}
+
+// Writes ids and bounds of the ranked nodes and the scalar outputs.
+int write_result(Run& run, HostSync& hs, katz_result* out, int32_t* stage_ids, double* stage_lo,
+                 double* stage_up, hipStream_t s, CallTimer& T) {
+  const int rf = hs.sc->iterations;
+  const int status = hs.sc->status;
+  const long long m_final = hs.sc->m;
+  const bool ids_dev = is_device_ptr(out->topk_ids), lo_dev = is_device_ptr(out->lower),
+             up_dev = is_device_ptr(out->upper);
+  const bool direct = ids_dev && lo_dev && up_dev;
+  SelArgs fa{};
+  fa.b = bound_args(run, rf);
+  fa.top_sorted = run.w->top_sorted;
+  fa.top_lo = run.w->top_lo;
+  fa.top_up = run.w->top_up;
+  fa.k = run.k;
+  fa.n = (int)run.n;
+  int32_t* ids = direct ? out->topk_ids : stage_ids;
+  double* lo = direct ? out->lower : stage_lo;
+  double* up = direct ? out->upper : stage_up;
+  const int tr = T.start(T_RESULT, s);
+  KATZ_HIP(hipMemsetAsync(run.w->mark, 0, (size_t)run.n, s));
+  KATZ_HIP(hipMemsetAsync(run.w->rest_bits, 0, sizeof(unsigned long long), s));
+  KATZ_HIP(launch_write_result(fa, run.w->mark, ids, lo, up, run.w->rest_bits, run.grid, s));
+  T.stop(tr, s);
+  KATZ_HIP(hipMemcpyAsync(hs.bits, run.w->rest_bits, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  if (!direct) {
+    KATZ_HIP(hipMemcpyAsync(out->topk_ids, ids, sizeof(int32_t) * run.k, hipMemcpyDefault, s));
+    KATZ_HIP(hipMemcpyAsync(out->lower, lo, sizeof(double) * run.k, hipMemcpyDefault, s));
+    KATZ_HIP(hipMemcpyAsync(out->upper, up, sizeof(double) * run.k, hipMemcpyDefault, s));
+  }
+  KATZ_HIP(hipStreamSynchronize(s));
+  T.commit(s);
+  double rest;
+  std::memcpy(&rest, hs.bits, sizeof(double));
+  out->rest_upper_max = (run.k == run.n) ? -std::numeric_limits<double>::infinity() : rest;
+  out->alpha_used = run.S->alpha;
+  out->eta = run.fp32 ? run.S->eta[rf] : 0.0;
+  out->active_final = m_final;
+  out->iterations = rf;
+  out->status = status;
+  return status;
+}
 
 // ---------------------------------------------------------------------------
-// Static ranking of one graph.
+// Static calls: workspace layout in an arena (measure pass, then real pass).
 // ---------------------------------------------------------------------------
+struct Plan {
+  const katz_csr* g;
+  int fp32;
+  int k;
+  int max_iter;
+  int validate;
+  bool rp_host, col_host, out_host, select;
+  size_t out_n;   // elements per output array (k for ranking, n for bounds)
+};
+
+struct Staging {
+  const void* row_ptr = nullptr;
+  const int32_t* col = nullptr;
+  long long* row_off = nullptr;   // strict symmetry check
+  int* row_len = nullptr;
+  int32_t* out_ids = nullptr;
+  double* out_lo = nullptr;
+  double* out_up = nullptr;
+};
+
+void layout(Arena& ar, const Plan& pl, Bins& b, Work& w, Staging& stg) {
+  const long long n = pl.g->n, nnz = pl.g->nnz;
+  ar.used = 0;
+  bins_caps(b, n, nnz);
+  w.sc = ar.take<RunScalars>(1);
+  b.blk = ar.take<long long>((size_t)(NUM_BINS + 1) * b.nblocks);
+  b.desc = ar.take<RowDesc>(n);
+  b.segs = ar.take<SegDesc>(b.seg_cap);
+  b.huge = ar.take<HugeRow>(b.huge_cap);
+  b.seg_done = ar.take<int>(b.huge_cap);
+  if (pl.rp_host) stg.row_ptr = ar.take<char>((size_t)(n + 1) * (pl.g->row_ptr_64 ? 8 : 4));
+  if (pl.col_host) stg.col = ar.take<int32_t>(std::max<long long>(nnz, 1));
+  if (pl.validate == KATZ_VALIDATE_STRICT && pl.g->undirected) {
+    stg.row_off = ar.take<long long>(n);
+    stg.row_len = ar.take<int>(n);
+  }
+  const size_t xs = pl.fp32 ? 4 : 8;
+  w.x[0] = ar.take<char>(n * xs);
+  w.x[1] = ar.take<char>(n * xs);
+  w.c = ar.take<double>(n);
+  if (pl.fp32) w.e = ar.take<float>(n);
+  w.partial = ar.take<char>(b.seg_cap * xs);
+  w.xmax32 = ar.take<unsigned>(pl.max_iter + 1);
+  w.xmax64 = ar.take<unsigned long long>(pl.max_iter + 1);
+  w.sigma = ar.take<double>(pl.max_iter + 1);
+  w.sigma_sum = ar.take<double>(pl.max_iter + 1);
+  w.hist = ar.take<unsigned>(2 * kDigits);
+  if (pl.select) {
+    w.act[0] = ar.take<int32_t>(n);
+    w.act[1] = ar.take<int32_t>(n);
+    w.keys = ar.take<unsigned long long>(n);
+    w.cand_key[0] = ar.take<unsigned long long>(n);
+    w.cand_key[1] = ar.take<unsigned long long>(n);
+    w.cand_v[0] = ar.take<int32_t>(n);
+    w.cand_v[1] = ar.take<int32_t>(n);
+    w.top_sorted = ar.take<int32_t>(pl.k);
+    w.top_lo = ar.take<double>(pl.k);
+    w.top_up = ar.take<double>(pl.k);
+    w.mark = ar.take<uint8_t>(n);
+    w.rest_bits = ar.take<unsigned long long>(1);
+  }
+  if (pl.out_host) {
+    stg.out_ids = ar.take<int32_t>(pl.out_n);
+    stg.out_lo = ar.take<double>(pl.out_n);
+    stg.out_up = ar.take<double>(pl.out_n);
+  }
+}
+
+int plan_and_allocate(Arena& ar, const Plan& pl, Bins& b, Work& w, Staging& stg) {
+  ar.measuring = true;
+  layout(ar, pl, b, w, stg);
+  ar.measuring = false;
+  KATZ_TRY(ar.grow(ar.used));
+  layout(ar, pl, b, w, stg);
+  return KATZ_OK;
+}
+
+// Stages host inputs, bins the rows, reads back d_max and the bin sizes.
+int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStream_t s) {
+  const katz_csr* g = pl.g;
+  if (pl.rp_host)
+    KATZ_HIP(hipMemcpyAsync((void*)stg.row_ptr, g->row_ptr, (size_t)(g->n + 1) * (g->row_ptr_64 ? 8 : 4),
+                            hipMemcpyHostToDevice, s));
+  else
+    stg.row_ptr = g->row_ptr;
+  if (pl.col_host) {
+    if (g->nnz > 0)
+      KATZ_HIP(hipMemcpyAsync((void*)stg.col, g->col, (size_t)g->nnz * 4, hipMemcpyHostToDevice, s));
+  } else {
+    stg.col = g->col;
+  }
+  KATZ_HIP(launch_init_run(w.sc, g->n, w.sigma, w.sigma_sum, w.xmax32, w.xmax64, pl.max_iter, w.hist, s));
+  KATZ_HIP(hipMemsetAsync(b.seg_done, 0, sizeof(int) * b.huge_cap, s));
+  KATZ_HIP(launch_prep_count(stg.row_ptr, g->row_ptr_64, g->n, g->nnz, b.blk, b.nblocks, w.sc, s));
+  KATZ_HIP(launch_prep_scan(b.blk, b.nblocks, w.sc, s));
+  KATZ_HIP(launch_prep_scatter(stg.row_ptr, g->row_ptr_64, g->n, b.blk, b.nblocks, b.desc, b.segs, b.huge, w.sc, s));
+  KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+  KATZ_HIP(hipStreamSynchronize(s));
+  if (hs.sc->err) return KATZ_E_CSR;
+  b.read_back(*hs.sc, g->n);
+  if (pl.validate == KATZ_VALIDATE_STRICT) {
+    KATZ_HIP(launch_validate_strict(b.desc, g->n, stg.col, g->undirected, stg.row_off, stg.row_len, w.sc, s));
+    KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipStreamSynchronize(s));
+    if (hs.sc->err) return KATZ_E_CSR;
+  }
+  return KATZ_OK;
+}
+
 int rank_one(const katz_csr* g, const katz_params* p, katz_result* out, hipStream_t s) {
-  int rc = check_graph(g);
-  if (rc) return rc;
-  rc = check_params(p, g->n, true);
-  if (rc) return rc;
+  KATZ_TRY(check_graph(g));
+  KATZ_TRY(check_params(p, g->n, true));
   if (!out || !out->topk_ids || !out->lower || !out->upper) return KATZ_E_INVALID_ARG;
   int dev = 0;
   KATZ_HIP(hipGetDevice(&dev));
@@ -543,116 +813,47 @@ int rank_one(const katz_csr* g, const katz_params* p, katz_result* out, hipStrea
   pl.validate = p->validate;
   pl.rp_host = !is_device_ptr(g->row_ptr);
   pl.col_host = g->nnz > 0 && !is_device_ptr(g->col);
-  const bool ids_dev = is_device_ptr(out->topk_ids), lo_dev = is_device_ptr(out->lower),
-             up_dev = is_device_ptr(out->upper);
-  pl.out_host = !(ids_dev && lo_dev && up_dev);
+  pl.out_host = !(is_device_ptr(out->topk_ids) && is_device_ptr(out->lower) && is_device_ptr(out->upper));
   pl.select = true;
   pl.out_n = (size_t)p->k;
 
-  Prepared pr;
-  RunBuffers rb;
-  rc = plan_and_allocate(ar, pl, pr, rb);
-  if (rc) return rc;
+  Bins b;
+  Work w;
+  Staging stg;
+  KATZ_TRY(plan_and_allocate(ar, pl, b, w, stg));
   CallTimer T;
   T.call_begin(s);
   const int tp = T.start(T_PREP, s);
-  rc = prepare(ar, pl, pr, pl.max_iter, rb, s);
+  const int prc = prepare(ar.hs, pl, b, w, stg, s);
   T.stop(tp, s);
-  if (rc) return rc;
+  KATZ_TRY(prc);
 
-  Scalars S{};
-  rc = resolve_alpha(p, pr.dmax, S);
-  if (rc) return rc;
-  if (pl.fp32) fp32_tables(S, pr, pl.max_iter);
+  Scalars S;
+  KATZ_TRY(resolve_alpha(p->alpha, b.dmax, S));
+  if (pl.fp32) fp32_tables(S, b, pl.max_iter);
 
-  const long long n = g->n;
-  const int grid = (int)std::min<long long>((n + kWG - 1) / kWG, 2048);
-  const int sync_every = sync_every_default();
-  int r = 0;
-  for (r = 1; r <= pl.max_iter; ++r) {
-    long long total_blocks = 0;
-    const IterArgs ia = iter_args(pl, pr, rb, S, r, total_blocks);
-    const int tw = T.start(r == 1 ? T_FIRST : T_STEP, s);
-    if (r == 1) KATZ_HIP(launch_walk_first(ia, pl.fp32, n, g->nnz, pl.validate >= KATZ_VALIDATE_BASIC, s));
-    else KATZ_HIP(launch_walk_step(ia, pl.fp32, total_blocks, s));
-    T.stop(tw, s);
-    SelArgs sa{};
-    sa.b = bound_args(pl, pr, rb, S, r, p->epsilon, g->undirected);
-    sa.act_in = rb.act[(r + 1) & 1];
-    sa.act_out = rb.act[r & 1];
-    sa.keys = rb.keys;
-    sa.cand_key[0] = rb.cand_key[0];
-    sa.cand_key[1] = rb.cand_key[1];
-    sa.cand_v[0] = rb.cand_v[0];
-    sa.cand_v[1] = rb.cand_v[1];
-    sa.hist = rb.hist;
-    sa.top_sorted = rb.top_sorted;
-    sa.top_lo = rb.top_lo;
-    sa.top_up = rb.top_up;
-    sa.xmax32 = rb.xmax32;
-    sa.xmax64 = rb.xmax64;
-    sa.sc = pr.sc;
-    sa.identity_in = r == 1;
-    sa.k = p->k;
-    sa.n = (int)n;
-    sa.max_iter = pl.max_iter;
-    const int ts = T.start(T_SELECT, s);
-    KATZ_HIP(launch_select_iteration(sa, grid, s));
-    T.stop(ts, s);
-    if (r % sync_every == 0 || r == pl.max_iter) {
-      KATZ_HIP(hipMemcpyAsync(ar.host_sc, pr.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
-      KATZ_HIP(hipStreamSynchronize(s));
-      if (ar.host_sc->err) return KATZ_E_CSR;
-      if (ar.host_sc->done) break;
-    }
-  }
-  const int rf = ar.host_sc->iterations;
-  const int status = ar.host_sc->status;
-  const long long m_final = ar.host_sc->m;
-
-  SelArgs fa{};
-  fa.b = bound_args(pl, pr, rb, S, rf, p->epsilon, g->undirected);
-  fa.top_sorted = rb.top_sorted;
-  fa.top_lo = rb.top_lo;
-  fa.top_up = rb.top_up;
-  fa.k = p->k;
-  fa.n = (int)n;
-  int32_t* ids = pl.out_host ? rb.out_ids : out->topk_ids;
-  double* lo = pl.out_host ? rb.out_lo : out->lower;
-  double* up = pl.out_host ? rb.out_up : out->upper;
-  const int tr = T.start(T_RESULT, s);
-  KATZ_HIP(hipMemsetAsync(rb.mark, 0, (size_t)n, s));
-  KATZ_HIP(hipMemsetAsync(rb.rest_bits, 0, sizeof(unsigned long long), s));
-  KATZ_HIP(launch_write_result(fa, rb.mark, ids, lo, up, rb.rest_bits, grid, s));
-  T.stop(tr, s);
-  KATZ_HIP(hipMemcpyAsync(ar.host_bits, rb.rest_bits, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-  if (pl.out_host) {
-    KATZ_HIP(hipMemcpyAsync(out->topk_ids, ids, sizeof(int32_t) * p->k,
-                            ids_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
-    KATZ_HIP(hipMemcpyAsync(out->lower, lo, sizeof(double) * p->k,
-                            lo_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
-    KATZ_HIP(hipMemcpyAsync(out->upper, up, sizeof(double) * p->k,
-                            up_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
-  }
-  KATZ_HIP(hipStreamSynchronize(s));
-  T.commit(s);
-  double rest;
-  std::memcpy(&rest, ar.host_bits, sizeof(double));
-  out->rest_upper_max = (p->k == n) ? -std::numeric_limits<double>::infinity() : rest;
-  out->alpha_used = S.alpha;
-  out->eta = pl.fp32 ? S.eta[rf] : 0.0;
-  out->active_final = m_final;
-  out->iterations = rf;
-  out->status = status;
-  return status;
+  Run run;
+  run.n = g->n;
+  run.nnz = g->nnz;
+  run.undirected = g->undirected;
+  run.fp32 = pl.fp32;
+  run.validate = pl.validate;
+  run.col = stg.col;
+  run.bins = &b;
+  run.w = &w;
+  run.S = &S;
+  run.eps = p->epsilon;
+  run.k = p->k;
+  run.max_iter = pl.max_iter;
+  run.grid = (int)std::min<long long>((g->n + kWG - 1) / kWG, 2048);
+  KATZ_TRY(iterate(run, ar.hs, 1, false, s, T));
+  return write_result(run, ar.hs, out, stg.out_ids, stg.out_lo, stg.out_up, s, T);
 }
 
 int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lower, double* upper,
                hipStream_t s) {
-  int rc = check_graph(g);
-  if (rc) return rc;
-  rc = check_params(p, g->n, false);
-  if (rc) return rc;
+  KATZ_TRY(check_graph(g));
+  KATZ_TRY(check_params(p, g->n, false));
   if (r_target < 1 || !lower || !upper) return KATZ_E_INVALID_ARG;
   int dev = 0;
   KATZ_HIP(hipGetDevice(&dev));
@@ -670,37 +871,563 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   pl.out_host = !(lo_dev && up_dev);
   pl.select = false;
   pl.out_n = (size_t)g->n;
-  Prepared pr;
-  RunBuffers rb;
-  rc = plan_and_allocate(ar, pl, pr, rb);
-  if (rc) return rc;
-  rc = prepare(ar, pl, pr, pl.max_iter, rb, s);
-  if (rc) return rc;
-  Scalars S{};
-  rc = resolve_alpha(p, pr.dmax, S);
-  if (rc) return rc;
-  if (pl.fp32) fp32_tables(S, pr, pl.max_iter);
-  for (int r = 1; r <= r_target; ++r) {
-    long long total_blocks = 0;
-    const IterArgs ia = iter_args(pl, pr, rb, S, r, total_blocks);
-    if (r == 1) KATZ_HIP(launch_walk_first(ia, pl.fp32, g->n, g->nnz, pl.validate >= KATZ_VALIDATE_BASIC, s));
-    else KATZ_HIP(launch_walk_step(ia, pl.fp32, total_blocks, s));
-  }
-  KATZ_HIP(hipMemcpyAsync(ar.host_sc, pr.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+  Bins b;
+  Work w;
+  Staging stg;
+  KATZ_TRY(plan_and_allocate(ar, pl, b, w, stg));
+  KATZ_TRY(prepare(ar.hs, pl, b, w, stg, s));
+  Scalars S;
+  KATZ_TRY(resolve_alpha(p->alpha, b.dmax, S));
+  if (pl.fp32) fp32_tables(S, b, pl.max_iter);
+  Run run;
+  run.n = g->n;
+  run.nnz = g->nnz;
+  run.undirected = g->undirected;
+  run.fp32 = pl.fp32;
+  run.validate = pl.validate;
+  run.col = stg.col;
+  run.bins = &b;
+  run.w = &w;
+  run.S = &S;
+  CallTimer T;
+  for (int r = 1; r <= r_target; ++r) KATZ_TRY(enqueue_walk(run, r, s, T));
+  KATZ_HIP(hipMemcpyAsync(ar.hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
   KATZ_HIP(hipStreamSynchronize(s));
-  if (ar.host_sc->err) return KATZ_E_CSR;
-  const BoundArgs b = bound_args(pl, pr, rb, S, r_target, 0.0, g->undirected);
-  double* lo = pl.out_host ? rb.out_lo : lower;
-  double* up = pl.out_host ? rb.out_up : upper;
-  KATZ_HIP(launch_all_bounds(b, g->n, nullptr, lo, up, s));
+  if (ar.hs.sc->err) return KATZ_E_CSR;
+  const BoundArgs bd = bound_args(run, r_target);
+  double* lo = pl.out_host ? stg.out_lo : lower;
+  double* up = pl.out_host ? stg.out_up : upper;
+  KATZ_HIP(launch_all_bounds(bd, g->n, nullptr, lo, up, s));
   if (pl.out_host) {
-    KATZ_HIP(hipMemcpyAsync(lower, lo, sizeof(double) * g->n,
-                            lo_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
-    KATZ_HIP(hipMemcpyAsync(upper, up, sizeof(double) * g->n,
-                            up_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipMemcpyAsync(lower, lo, sizeof(double) * g->n, hipMemcpyDefault, s));
+    KATZ_HIP(hipMemcpyAsync(upper, up, sizeof(double) * g->n, hipMemcpyDefault, s));
   }
   KATZ_HIP(hipStreamSynchronize(s));
   return KATZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Dynamic state.
+// ---------------------------------------------------------------------------
+long long slack_cap_host(long long len) { return len + std::max(2ll, len >> 3); }
+
+// Walk history levels 1..r exist (zero-initialised, so rows that are empty from
+// the start read as 0 without ever being written).
+int ensure_levels(katz_state* st, int r) {
+  if ((int)st->X.size() <= r) {
+    const int want = std::max(r + 1, (int)st->X.size() + 8);
+    while ((int)st->X.size() < want) {
+      double* p = nullptr;
+      if (st->X.empty()) {
+        st->X.push_back(nullptr);   // level 0 is the implicit all-ones vector
+        continue;
+      }
+      if (hipMalloc((void**)&p, sizeof(double) * st->n) != hipSuccess) {
+        (void)hipGetLastError();
+        return KATZ_E_OOM;
+      }
+      if (hipMemset(p, 0, sizeof(double) * st->n) != hipSuccess) return KATZ_E_HIP;
+      st->X.push_back(p);
+    }
+  }
+  if (st->X_dev_synced == (int)st->X.size()) return KATZ_OK;
+  if (st->X_dev_cap < (int)st->X.size()) {
+    if (st->X_dev) dfree(st, st->X_dev);
+    st->X_dev_cap = (int)st->X.size() + 8;
+    st->X_dev = dalloc<double*>(st, st->X_dev_cap);
+    if (!st->X_dev) return KATZ_E_OOM;
+  }
+  KATZ_HIP(hipMemcpy(st->X_dev, st->X.data(), sizeof(double*) * st->X.size(), hipMemcpyHostToDevice));
+  st->X_dev_synced = (int)st->X.size();
+  return KATZ_OK;
+}
+
+// Bins sized for the pool capacity (an upper bound of the arc count).
+int alloc_bins(katz_state* st, Bins& b) {
+  if (b.desc) {
+    dfree(st, b.desc);
+    dfree(st, b.segs);
+    dfree(st, b.huge);
+    dfree(st, b.seg_done);
+    dfree(st, b.blk);
+  }
+  bins_caps(b, st->n, st->pool_cap);
+  b.desc = dalloc<RowDesc>(st, st->n);
+  b.segs = dalloc<SegDesc>(st, b.seg_cap);
+  b.huge = dalloc<HugeRow>(st, b.huge_cap);
+  b.seg_done = dalloc<int>(st, b.huge_cap);
+  b.blk = dalloc<long long>(st, (size_t)(NUM_BINS + 1) * b.nblocks);
+  if (!b.desc || !b.segs || !b.huge || !b.seg_done || !b.blk) return KATZ_E_OOM;
+  KATZ_HIP(hipMemset(b.seg_done, 0, sizeof(int) * b.huge_cap));
+  return KATZ_OK;
+}
+
+int alloc_partial(katz_state* st) {
+  if (st->w.partial) dfree(st, st->w.partial);
+  st->w.partial = dalloc<double>(st, st->bins.seg_cap);
+  return st->w.partial ? KATZ_OK : KATZ_E_OOM;
+}
+
+// Bins the rows `ids[0..count)` (or every row when ids is null) of the slack CSR.
+int bin_rows(katz_state* st, Bins& b, RunScalars* sc, const int32_t* ids, long long count, hipStream_t s) {
+  KATZ_HIP(launch_reset_flags(sc, s));
+  b.nblocks = (int)std::max<long long>(1, (count + kWG - 1) / kWG);
+  KATZ_HIP(launch_prep_rows(ids, count, st->row_off, st->row_len, b.blk, b.nblocks, b.desc, b.segs, b.huge, sc, s));
+  KATZ_HIP(hipMemcpyAsync(st->hs.sc, sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+  KATZ_HIP(hipStreamSynchronize(s));
+  if (st->hs.sc->err) return KATZ_E_HIP;
+  b.read_back(*st->hs.sc, count);
+  return KATZ_OK;
+}
+
+Run state_run(katz_state* st) {
+  Run run;
+  run.n = st->n;
+  run.nnz = st->nnz;
+  run.undirected = 1;
+  run.fp32 = 0;
+  run.validate = 0;
+  run.col = st->pool;
+  run.bins = &st->bins;
+  run.w = &st->w;
+  run.st = st;
+  run.S = &st->S;
+  run.eps = st->eps;
+  run.k = st->k;
+  run.max_iter = st->max_iter;
+  run.cur = st->cur;
+  run.first_select = false;
+  run.grid = (int)std::min<long long>((st->n + kWG - 1) / kWG, 2048);
+  return run;
+}
+
+// Creates a state from a caller CSR and runs Algorithm 1 on it in history mode.
+int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz_state** stp, hipStream_t s) {
+  KATZ_TRY(check_graph(g));
+  KATZ_TRY(check_params(p, g->n, true));
+  if (!out || !out->topk_ids || !out->lower || !out->upper) return KATZ_E_INVALID_ARG;
+  if (p->precision != KATZ_FP64 || !g->undirected) return KATZ_E_UNSUPPORTED;
+  int dev = 0;
+  KATZ_HIP(hipGetDevice(&dev));
+  katz_state* st = new katz_state;
+  struct Guard {
+    katz_state*& p;
+    bool keep = false;
+    ~Guard() {
+      if (!keep) delete p;
+    }
+  } guard{st};
+  st->device = dev;
+  st->n = g->n;
+  st->nnz = g->nnz;
+  st->eps = p->epsilon;
+  st->k = p->k;
+  st->max_iter = p->max_iter ? p->max_iter : 1000;
+  KATZ_TRY(st->hs.init());
+  const long long n = g->n;
+
+  // Stage a host CSR.
+  const void* rp = g->row_ptr;
+  const int32_t* col = g->col;
+  void* rp_tmp = nullptr;
+  int32_t* col_tmp = nullptr;
+  if (!is_device_ptr(g->row_ptr)) {
+    rp_tmp = dalloc<char>(st, (size_t)(n + 1) * (g->row_ptr_64 ? 8 : 4));
+    if (!rp_tmp) return KATZ_E_OOM;
+    KATZ_HIP(hipMemcpyAsync(rp_tmp, g->row_ptr, (size_t)(n + 1) * (g->row_ptr_64 ? 8 : 4), hipMemcpyHostToDevice,
+                            s));
+    rp = rp_tmp;
+  }
+  if (g->nnz > 0 && !is_device_ptr(g->col)) {
+    col_tmp = dalloc<int32_t>(st, g->nnz);
+    if (!col_tmp) return KATZ_E_OOM;
+    KATZ_HIP(hipMemcpyAsync(col_tmp, g->col, (size_t)g->nnz * 4, hipMemcpyHostToDevice, s));
+    col = col_tmp;
+  }
+
+  // Validate the input CSR (offsets, column range) before converting it.
+  st->w.sc = dalloc<RunScalars>(st, 1);
+  st->sc2 = dalloc<RunScalars>(st, 1);
+  if (!st->w.sc || !st->sc2) return KATZ_E_OOM;
+  {
+    Bins tmp;
+    bins_caps(tmp, n, g->nnz);
+    long long* blk = dalloc<long long>(st, (size_t)(NUM_BINS + 1) * tmp.nblocks);
+    if (!blk) return KATZ_E_OOM;
+    KATZ_HIP(launch_reset_flags(st->w.sc, s));
+    KATZ_HIP(launch_prep_count(rp, g->row_ptr_64, n, g->nnz, blk, tmp.nblocks, st->w.sc, s));
+    KATZ_HIP(launch_check_col_range(col, g->nnz, n, st->w.sc, s));
+    KATZ_HIP(hipMemcpyAsync(st->hs.sc, st->w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipStreamSynchronize(s));
+    dfree(st, blk);
+    if (st->hs.sc->err) return KATZ_E_CSR;
+  }
+
+  // Slack CSR: capacities, offsets, copy.
+  st->row_off = dalloc<long long>(st, n);
+  st->row_len = dalloc<int>(st, n);
+  st->row_cap = dalloc<int>(st, n);
+  long long* cap_ll = dalloc<long long>(st, n);
+  long long* sums = dalloc<long long>(st, scan_sums_capacity(n));
+  long long* total = dalloc<long long>(st, 1);
+  if (!st->row_off || !st->row_len || !st->row_cap || !cap_ll || !sums || !total) return KATZ_E_OOM;
+  KATZ_HIP(launch_slack_caps(rp, g->row_ptr_64, n, st->row_len, st->row_cap, cap_ll, s));
+  KATZ_HIP(launch_scan_ll(cap_ll, n, st->row_off, sums, total, s));
+  long long pool_need = 0;
+  KATZ_HIP(hipMemcpyAsync(&pool_need, total, sizeof(long long), hipMemcpyDeviceToHost, s));
+  KATZ_HIP(hipStreamSynchronize(s));
+  dfree(st, cap_ll);
+  dfree(st, sums);
+  dfree(st, total);
+  st->pool_used = pool_need;
+  st->pool_cap = pool_need + pool_need / 8 + 4096;
+  st->pool = dalloc<int32_t>(st, st->pool_cap);
+  if (!st->pool) return KATZ_E_OOM;
+  KATZ_HIP(launch_copy_rows_to_pool(rp, g->row_ptr_64, col, n, st->row_off, st->pool, s));
+  if (rp_tmp) dfree(st, rp_tmp);
+  if (col_tmp) dfree(st, col_tmp);
+
+  // Bins of the whole graph, strict checks (sorted rows, no loops, symmetry).
+  KATZ_TRY(alloc_bins(st, st->bins));
+  KATZ_TRY(alloc_bins(st, st->lbins));
+  KATZ_TRY(bin_rows(st, st->bins, st->w.sc, nullptr, n, s));
+  KATZ_HIP(launch_reset_flags(st->w.sc, s));
+  KATZ_HIP(launch_validate_strict(st->bins.desc, n, st->pool, 1, st->row_off, st->row_len, st->w.sc, s));
+  KATZ_HIP(hipMemcpyAsync(st->hs.sc, st->w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+  KATZ_HIP(hipStreamSynchronize(s));
+  if (st->hs.sc->err) return KATZ_E_CSR;
+  // validate_strict rewrote row_off/row_len from the descriptors: unchanged values.
+
+  const int dmax = st->bins.dmax;
+  KATZ_TRY(resolve_alpha(p->alpha, dmax, st->S));
+  st->alpha = st->S.alpha;
+  st->degree_cap = p->degree_cap ? p->degree_cap : dmax;
+  if (st->degree_cap < dmax) return KATZ_E_INVALID_ARG;
+  if (!(st->alpha * (double)st->degree_cap < 1.0)) return KATZ_E_ALPHA;
+
+  // Run buffers.
+  Work& w = st->w;
+  KATZ_TRY(alloc_partial(st));
+  w.c = dalloc<double>(st, n);
+  w.act[0] = dalloc<int32_t>(st, n);
+  w.act[1] = dalloc<int32_t>(st, n);
+  w.keys = dalloc<unsigned long long>(st, n);
+  w.cand_key[0] = dalloc<unsigned long long>(st, n);
+  w.cand_key[1] = dalloc<unsigned long long>(st, n);
+  w.cand_v[0] = dalloc<int32_t>(st, n);
+  w.cand_v[1] = dalloc<int32_t>(st, n);
+  w.hist = dalloc<unsigned>(st, 2 * kDigits);
+  w.xmax32 = dalloc<unsigned>(st, st->max_iter + 1);
+  w.xmax64 = dalloc<unsigned long long>(st, st->max_iter + 1);
+  w.sigma = dalloc<double>(st, st->max_iter + 1);
+  w.sigma_sum = dalloc<double>(st, st->max_iter + 1);
+  w.top_sorted = dalloc<int32_t>(st, st->k);
+  w.top_lo = dalloc<double>(st, st->k);
+  w.top_up = dalloc<double>(st, st->k);
+  w.mark = dalloc<uint8_t>(st, n);
+  w.rest_bits = dalloc<unsigned long long>(st, 1);
+  st->level_of = dalloc<int>(st, n);
+  st->clist = dalloc<int32_t>(st, n);
+  st->counter = dalloc<int>(st, 1);
+  st->dmax_dev = dalloc<int>(st, 1);
+  st->err_dev = dalloc<int>(st, 1);
+  st->min_bits = dalloc<unsigned long long>(st, 1);
+  st->tmark = dalloc<uint8_t>(st, n);
+  if (!w.c || !w.act[0] || !w.act[1] || !w.keys || !w.cand_key[0] || !w.cand_key[1] || !w.cand_v[0] ||
+      !w.cand_v[1] || !w.hist || !w.xmax32 || !w.xmax64 || !w.sigma || !w.sigma_sum || !w.top_sorted ||
+      !w.top_lo || !w.top_up || !w.mark || !w.rest_bits || !st->level_of || !st->clist || !st->counter ||
+      !st->dmax_dev || !st->err_dev || !st->min_bits || !st->tmark)
+    return KATZ_E_OOM;
+  KATZ_HIP(hipMemsetAsync(w.mark, 0, n, s));
+  KATZ_HIP(hipMemsetAsync(st->tmark, 0, n, s));
+  KATZ_HIP(hipMemsetAsync(st->level_of, 0, sizeof(int) * n, s));
+  KATZ_HIP(launch_init_run(w.sc, n, w.sigma, w.sigma_sum, w.xmax32, w.xmax64, st->max_iter, w.hist, s));
+
+  CallTimer T;
+  T.call_begin(s);
+  Run run = state_run(st);
+  run.first_select = true;
+  run.cur = 0;
+  KATZ_TRY(iterate(run, st->hs, 1, false, s, T));
+  st->r = st->hs.sc->iterations;
+  st->cur = st->hs.sc->cur;
+  const int status = write_result(run, st->hs, out, nullptr, nullptr, nullptr, s, T);
+  guard.keep = true;
+  *stp = st;
+  return status;
+}
+
+struct Arc {
+  int32_t src, dst;
+  bool operator<(const Arc& o) const { return src != o.src ? src < o.src : dst < o.dst; }
+};
+
+// Copies `count` ids from host or device memory into a host vector.
+int fetch_ids(const int32_t* p, long long count, std::vector<int32_t>& out) {
+  out.resize(count);
+  if (count == 0) return KATZ_OK;
+  KATZ_HIP(hipMemcpy(out.data(), p, sizeof(int32_t) * count, hipMemcpyDefault));
+  return KATZ_OK;
+}
+
+// A device buffer owned by the state that grows on demand.
+template <class T>
+int grow_buf(katz_state* st, T*& p, size_t& cap, size_t count) {
+  if (count <= cap && p) return KATZ_OK;
+  if (p) dfree(st, p);
+  cap = std::max<size_t>(count, 1024);
+  p = dalloc<T>(st, cap);
+  return p ? KATZ_OK : KATZ_E_OOM;
+}
+
+
+// Moves the pool to a larger allocation.
+int grow_pool(katz_state* st, long long need, hipStream_t s) {
+  if (st->pool_used + need <= st->pool_cap) return KATZ_OK;
+  const long long cap = std::max(st->pool_cap * 2, st->pool_used + need + 4096);
+  int32_t* np = dalloc<int32_t>(st, cap);
+  if (!np) return KATZ_E_OOM;
+  KATZ_HIP(hipMemcpyAsync(np, st->pool, sizeof(int32_t) * st->pool_used, hipMemcpyDeviceToDevice, s));
+  KATZ_HIP(hipStreamSynchronize(s));
+  dfree(st, st->pool);
+  st->pool = np;
+  st->pool_cap = cap;
+  KATZ_TRY(alloc_bins(st, st->bins));
+  KATZ_TRY(alloc_bins(st, st->lbins));
+  KATZ_TRY(alloc_partial(st));
+  return KATZ_OK;
+}
+
+int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, long long n_ins, const int32_t* del_u,
+                 const int32_t* del_v, long long n_del, katz_result* out, hipStream_t s) {
+  if (n_ins < 0 || n_del < 0) return KATZ_E_INVALID_ARG;
+  if ((n_ins > 0 && (!ins_u || !ins_v)) || (n_del > 0 && (!del_u || !del_v))) return KATZ_E_INVALID_ARG;
+  if (!out || !out->topk_ids || !out->lower || !out->upper) return KATZ_E_INVALID_ARG;
+  const long long n = st->n;
+
+  // ---- validate the batch on its own (ids, loops, repeats, I n D) ----
+  std::vector<int32_t> iu, iv, du, dv;
+  KATZ_TRY(fetch_ids(ins_u, n_ins, iu));
+  KATZ_TRY(fetch_ids(ins_v, n_ins, iv));
+  KATZ_TRY(fetch_ids(del_u, n_del, du));
+  KATZ_TRY(fetch_ids(del_v, n_del, dv));
+  std::vector<long long> ki, kd;
+  ki.reserve(n_ins);
+  kd.reserve(n_del);
+  for (long long j = 0; j < n_ins; ++j) {
+    if (iu[j] < 0 || iu[j] >= n || iv[j] < 0 || iv[j] >= n || iu[j] == iv[j]) return KATZ_E_UPDATE;
+    ki.push_back((long long)std::min(iu[j], iv[j]) * n + std::max(iu[j], iv[j]));
+  }
+  for (long long j = 0; j < n_del; ++j) {
+    if (du[j] < 0 || du[j] >= n || dv[j] < 0 || dv[j] >= n || du[j] == dv[j]) return KATZ_E_UPDATE;
+    kd.push_back((long long)std::min(du[j], dv[j]) * n + std::max(du[j], dv[j]));
+  }
+  std::sort(ki.begin(), ki.end());
+  std::sort(kd.begin(), kd.end());
+  if (std::adjacent_find(ki.begin(), ki.end()) != ki.end()) return KATZ_E_UPDATE;
+  if (std::adjacent_find(kd.begin(), kd.end()) != kd.end()) return KATZ_E_UPDATE;
+  {
+    std::vector<long long> both;
+    std::set_intersection(ki.begin(), ki.end(), kd.begin(), kd.end(), std::back_inserter(both));
+    if (!both.empty()) return KATZ_E_UPDATE;
+  }
+
+  UpdateBufs& ub = st->ub;
+
+  // ---- existence checks against the graph (device) ----
+  const long long np = n_ins + n_del;
+  if (np > 0) {
+    KATZ_TRY(grow_buf(st, ub.pairs, ub.pairs_cap, 2 * np));
+    std::vector<int32_t> pa(2 * np);
+    for (long long j = 0; j < n_ins; ++j) {
+      pa[j] = iu[j];
+      pa[np + j] = iv[j];
+    }
+    for (long long j = 0; j < n_del; ++j) {
+      pa[n_ins + j] = du[j];
+      pa[np + n_ins + j] = dv[j];
+    }
+    KATZ_HIP(hipMemcpyAsync(ub.pairs, pa.data(), sizeof(int32_t) * 2 * np, hipMemcpyHostToDevice, s));
+    KATZ_HIP(hipMemsetAsync(st->err_dev, 0, sizeof(int), s));
+    KATZ_HIP(launch_batch_exist(ub.pairs, ub.pairs + np, n_ins, np, st->row_off, st->row_len, st->pool, st->err_dev,
+                                s));
+    int err = 0;
+    KATZ_HIP(hipMemcpyAsync(&err, st->err_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipStreamSynchronize(s));
+    if (err) return KATZ_E_UPDATE;
+  }
+
+  // ---- arcs grouped by source row (both arcs of every pair) ----
+  std::vector<Arc> ia, da;
+  ia.reserve(2 * n_ins);
+  da.reserve(2 * n_del);
+  for (long long j = 0; j < n_ins; ++j) {
+    ia.push_back({iu[j], iv[j]});
+    ia.push_back({iv[j], iu[j]});
+  }
+  for (long long j = 0; j < n_del; ++j) {
+    da.push_back({du[j], dv[j]});
+    da.push_back({dv[j], du[j]});
+  }
+  std::sort(ia.begin(), ia.end());
+  std::sort(da.begin(), da.end());
+  std::vector<int32_t> trows;
+  for (const Arc& a : ia) trows.push_back(a.src);
+  for (const Arc& a : da) trows.push_back(a.src);
+  std::sort(trows.begin(), trows.end());
+  trows.erase(std::unique(trows.begin(), trows.end()), trows.end());
+  const long long t = (long long)trows.size();
+  std::vector<long long> ins_off(t), del_off(t);
+  std::vector<int> ins_cnt(t, 0), del_cnt(t, 0), delta(t);
+  std::vector<int32_t> ins_dst, del_dst;
+  {
+    size_t pi = 0, pd = 0;
+    for (long long i = 0; i < t; ++i) {
+      ins_off[i] = (long long)ins_dst.size();
+      while (pi < ia.size() && ia[pi].src == trows[i]) ins_dst.push_back(ia[pi++].dst);
+      ins_cnt[i] = (int)(ins_dst.size() - ins_off[i]);
+      del_off[i] = (long long)del_dst.size();
+      while (pd < da.size() && da[pd].src == trows[i]) del_dst.push_back(da[pd++].dst);
+      del_cnt[i] = (int)(del_dst.size() - del_off[i]);
+      delta[i] = ins_cnt[i] - del_cnt[i];
+    }
+  }
+
+  CallTimer T;
+  T.call_begin(s);
+  Run run = state_run(st);
+  int new_dmax = st->bins.dmax;
+  std::vector<long long> new_len(t);
+  if (t > 0) {
+    // ---- candidate degrees and the degree cap (Theorem 1 needs alpha d < 1) ----
+    KATZ_TRY(grow_buf(st, ub.rows, ub.rows_cap, t));
+    KATZ_TRY(grow_buf(st, ub.ll, ub.ll_cap, 5 * t));
+    KATZ_TRY(grow_buf(st, ub.ints, ub.ints_cap, 5 * t));
+    KATZ_TRY(grow_buf(st, ub.dst, ub.dst_cap, ins_dst.size() + del_dst.size()));
+    long long* d_ins_off = ub.ll;
+    long long* d_del_off = ub.ll + t;
+    long long* d_new_len = ub.ll + 2 * t;
+    long long* d_sbase = ub.ll + 3 * t;
+    long long* d_dest_off = ub.ll + 4 * t;
+    int* d_ins_cnt = ub.ints;
+    int* d_del_cnt = ub.ints + t;
+    int* d_delta = ub.ints + 2 * t;
+    int* d_dest_cap = ub.ints + 3 * t;
+    int* d_caps = ub.ints + 4 * t;
+    int32_t* d_ins_dst = ub.dst;
+    int32_t* d_del_dst = ub.dst + ins_dst.size();
+    KATZ_HIP(hipMemcpyAsync(ub.rows, trows.data(), sizeof(int32_t) * t, hipMemcpyHostToDevice, s));
+    KATZ_HIP(hipMemcpyAsync(d_ins_off, ins_off.data(), sizeof(long long) * t, hipMemcpyHostToDevice, s));
+    KATZ_HIP(hipMemcpyAsync(d_del_off, del_off.data(), sizeof(long long) * t, hipMemcpyHostToDevice, s));
+    KATZ_HIP(hipMemcpyAsync(d_ins_cnt, ins_cnt.data(), sizeof(int) * t, hipMemcpyHostToDevice, s));
+    KATZ_HIP(hipMemcpyAsync(d_del_cnt, del_cnt.data(), sizeof(int) * t, hipMemcpyHostToDevice, s));
+    KATZ_HIP(hipMemcpyAsync(d_delta, delta.data(), sizeof(int) * t, hipMemcpyHostToDevice, s));
+    if (!ins_dst.empty())
+      KATZ_HIP(hipMemcpyAsync(d_ins_dst, ins_dst.data(), sizeof(int32_t) * ins_dst.size(), hipMemcpyHostToDevice, s));
+    if (!del_dst.empty())
+      KATZ_HIP(hipMemcpyAsync(d_del_dst, del_dst.data(), sizeof(int32_t) * del_dst.size(), hipMemcpyHostToDevice, s));
+    KATZ_HIP(launch_touched_lengths(ub.rows, t, d_delta, st->row_len, d_new_len, st->tmark, s));
+    KATZ_HIP(hipMemsetAsync(st->dmax_dev, 0, sizeof(int), s));
+    KATZ_HIP(launch_max_len_after(st->row_len, st->tmark, n, d_new_len, t, st->dmax_dev, s));
+    KATZ_HIP(launch_unmark_rows(ub.rows, t, st->tmark, s));
+    KATZ_HIP(launch_gather_int(ub.rows, t, st->row_cap, d_caps, s));
+    std::vector<int> caps(t);
+    std::vector<long long> offs(t);
+    KATZ_HIP(launch_gather_ll(ub.rows, t, st->row_off, d_dest_off, s));
+    KATZ_HIP(hipMemcpyAsync(&new_dmax, st->dmax_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipMemcpyAsync(new_len.data(), d_new_len, sizeof(long long) * t, hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipMemcpyAsync(caps.data(), d_caps, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipMemcpyAsync(offs.data(), d_dest_off, sizeof(long long) * t, hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipStreamSynchronize(s));
+    if (!(st->alpha * (double)new_dmax < 1.0) || new_dmax > st->degree_cap) return KATZ_E_DEGREE_CAP;
+
+    // ---- apply: merge every touched row into scratch, then place it ----
+    std::vector<long long> sbase(t), dest_off(t);
+    std::vector<int> dest_cap(t);
+    long long scratch_total = 0, grow_need = 0;
+    for (long long i = 0; i < t; ++i) {
+      sbase[i] = scratch_total;
+      scratch_total += new_len[i];
+      if (new_len[i] > caps[i]) grow_need += slack_cap_host(new_len[i]);
+    }
+    KATZ_TRY(grow_pool(st, grow_need, s));
+    for (long long i = 0; i < t; ++i) {
+      if (new_len[i] <= caps[i]) {
+        dest_off[i] = offs[i];
+        dest_cap[i] = caps[i];
+      } else {
+        dest_cap[i] = (int)slack_cap_host(new_len[i]);
+        dest_off[i] = st->pool_used;
+        st->pool_used += dest_cap[i];
+      }
+    }
+    KATZ_TRY(grow_buf(st, ub.scratch, ub.scratch_cap, (size_t)scratch_total));
+    KATZ_HIP(hipMemcpyAsync(d_sbase, sbase.data(), sizeof(long long) * t, hipMemcpyHostToDevice, s));
+    KATZ_HIP(hipMemcpyAsync(d_dest_off, dest_off.data(), sizeof(long long) * t, hipMemcpyHostToDevice, s));
+    KATZ_HIP(hipMemcpyAsync(d_dest_cap, dest_cap.data(), sizeof(int) * t, hipMemcpyHostToDevice, s));
+    KATZ_HIP(launch_merge_rows(ub.rows, t, d_ins_off, d_ins_cnt, d_ins_dst, d_del_off, d_del_cnt, d_del_dst, d_sbase,
+                               st->row_off, st->row_len, st->pool, ub.scratch, s));
+    KATZ_HIP(launch_copy_back_rows(ub.rows, t, d_sbase, d_new_len, d_dest_off, d_dest_cap, ub.scratch, st->row_off,
+                                   st->row_len, st->row_cap, st->pool, s));
+    st->nnz += 2 * (n_ins - n_del);
+
+    // ---- bins of the new graph ----
+    run = state_run(st);
+    KATZ_TRY(bin_rows(st, st->bins, st->sc2, nullptr, n, s));
+    st->bins.dmax = new_dmax;
+
+    // ---- re-walk levels 1..r over the affected set (Algorithm 2) ----
+    const long long dense_at = std::max<long long>(1, n / 4);
+    KATZ_HIP(hipMemcpyAsync(st->clist, ub.rows, sizeof(int32_t) * t, hipMemcpyDeviceToDevice, s));
+    KATZ_HIP(launch_set_levels(ub.rows, t, st->level_of, 1, s));
+    long long csize = t, fbeg = 0;
+    bool dense = csize > dense_at;
+    for (int i = 1; i <= st->r; ++i) {
+      if (i >= 2 && !dense) {
+        // C_i = C_{i-1} u in-neighbours(F_{i-1}); F_{i-1} = C[fbeg .. csize).
+        KATZ_HIP(hipMemcpyAsync(st->counter, &csize, sizeof(int), hipMemcpyHostToDevice, s));
+        KATZ_HIP(launch_frontier_expand(st->clist + fbeg, csize - fbeg, st->row_off, st->row_len, st->pool,
+                                        st->level_of, i, st->clist, st->counter, s));
+        int c2 = 0;
+        KATZ_HIP(hipMemcpyAsync(&c2, st->counter, sizeof(int), hipMemcpyDeviceToHost, s));
+        KATZ_HIP(hipStreamSynchronize(s));
+        fbeg = csize;
+        csize = c2;
+        if (csize > dense_at) dense = true;
+      }
+      long long tb = 0;
+      if (dense) {
+        const IterArgs ia2 = iter_args(run, st->bins, i, true, tb);
+        if (i == 1) KATZ_HIP(launch_walk_first(ia2, 0, n, st->nnz, 0, s));
+        else KATZ_HIP(launch_walk_step(ia2, 0, tb, s));
+      } else {
+        KATZ_TRY(bin_rows(st, st->lbins, st->sc2, st->clist, csize, s));
+        const IterArgs ia2 = iter_args(run, st->lbins, i, true, tb);
+        if (i == 1) KATZ_HIP(launch_walk_first(ia2, 0, n, st->nnz, 0, s));
+        else KATZ_HIP(launch_walk_step(ia2, 0, tb, s));
+      }
+    }
+    // c_r(w) = sum_i x_i(w) for every recomputed w, in the static order.
+    KATZ_HIP(launch_c_from_history(dense ? nullptr : st->clist, dense ? n : csize, st->X_dev, st->r, st->w.c, s));
+    KATZ_HIP(launch_clear_levels(st->clist, csize, st->level_of, s));
+  }
+
+  // ---- gamma from the new deg_max; bounds, reactivation, resume ----
+  set_gamma(st->S, new_dmax);
+  KATZ_HIP(hipMemsetAsync(&st->w.xmax64[st->r], 0, sizeof(unsigned long long), s));
+  KATZ_HIP(launch_max_of_vector(st->X[st->r], n, &st->w.xmax64[st->r], s));
+  KATZ_HIP(launch_reset_flags(st->w.sc, s));
+  run = state_run(st);
+  const BoundArgs b = bound_args(run, st->r);
+  KATZ_HIP(hipMemsetAsync(st->min_bits, 0xff, sizeof(unsigned long long), s));
+  KATZ_HIP(launch_min_lower_active(b, st->w.act[st->cur], &st->w.sc->m, st->min_bits, st->w.mark, n, s));
+  KATZ_HIP(hipMemsetAsync(&st->w.sc->m, 0, sizeof(int), s));
+  KATZ_HIP(launch_reactivate_all(b, n, st->min_bits, st->w.mark, st->w.act[st->cur ^ 1], &st->w.sc->m, s));
+  run.cur = st->cur ^ 1;
+  KATZ_TRY(iterate(run, st->hs, st->r + 1, true, s, T));
+  st->r = st->hs.sc->iterations;
+  st->cur = st->hs.sc->cur;
+  return write_result(run, st->hs, out, nullptr, nullptr, nullptr, s, T);
 }
 
 }  // namespace
@@ -709,23 +1436,31 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
 // ---------------------------------------------------------------------------
 // C ABI.
 // ---------------------------------------------------------------------------
-struct katz_state {
-  int unused;
-};
-
 KATZ_EXPORT int katz_rank_static(int32_t count, const katz_csr* g, const katz_params* p, katz_result* out,
                                  katz_state** states, void* stream) {
   if (count < 1 || !g || !p || !out) return KATZ_E_INVALID_ARG;
-  if (states) return KATZ_E_UNSUPPORTED;
   for (int32_t i = 0; i < count; ++i) {
     int rc = katz::check_graph(&g[i]);
     if (!rc) rc = katz::check_params(&p[i], g[i].n, true);
     if (!rc && (!out[i].topk_ids || !out[i].lower || !out[i].upper)) rc = KATZ_E_INVALID_ARG;
+    if (!rc && states && (p[i].precision != KATZ_FP64 || !g[i].undirected)) rc = KATZ_E_UNSUPPORTED;
     if (rc) return rc;
   }
   int worst = KATZ_OK;
   for (int32_t i = 0; i < count; ++i) {
-    const int rc = katz::rank_one(&g[i], &p[i], &out[i], (hipStream_t)stream);
+    int rc;
+    if (states) {
+      states[i] = nullptr;
+      rc = katz::create_state(&g[i], &p[i], &out[i], &states[i], (hipStream_t)stream);
+      if (rc < 0) {
+        for (int32_t j = 0; j < i; ++j) {
+          delete states[j];
+          states[j] = nullptr;
+        }
+      }
+    } else {
+      rc = katz::rank_one(&g[i], &p[i], &out[i], (hipStream_t)stream);
+    }
     if (rc < 0) return rc;
     worst = std::max(worst, rc);
   }
@@ -735,9 +1470,8 @@ KATZ_EXPORT int katz_rank_static(int32_t count, const katz_csr* g, const katz_pa
 KATZ_EXPORT int katz_rank_update(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, int64_t n_ins,
                                  const int32_t* del_u, const int32_t* del_v, int64_t n_del, katz_result* out,
                                  void* stream) {
-  (void)ins_u; (void)ins_v; (void)n_ins; (void)del_u; (void)del_v; (void)n_del; (void)out; (void)stream;
   if (!st) return KATZ_E_INVALID_ARG;
-  return KATZ_E_UNSUPPORTED;
+  return katz::update_state(st, ins_u, ins_v, n_ins, del_u, del_v, n_del, out, (hipStream_t)stream);
 }
 
 KATZ_EXPORT int katz_bounds(const katz_csr* g, const katz_params* p, int32_t r, double* lower, double* upper,

@@ -1,0 +1,129 @@
+// Device helpers shared by the kernel sources (inline, header-only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "katz_internal.h"
+
+namespace katz {
+
+__host__ __device__ constexpr int bin_of_len(long long len) {
+  return len <= 0 ? BIN_EMPTY
+       : len <= 4 ? BIN_G4
+       : len <= 8 ? BIN_G8
+       : len <= 16 ? BIN_G16
+       : len <= 32 ? BIN_G32
+       : len <= kWaveRowMax ? BIN_W64
+       : len <= kBlockRowMax ? BIN_B256
+       : BIN_HUGE;
+}
+
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+  return (1ull << lane_id()) - 1ull;
+}
+
+// Wave-aggregated append: one atomic per wave.  Every lane of the wave must call it.
+__device__ __forceinline__ int wave_append(int* counter, bool pred) {
+  const unsigned long long mask = __ballot(pred);
+  if (mask == 0ull) return -1;
+  const int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, __popcll(mask));
+  base = __shfl(base, leader);
+  return base + __popcll(mask & lanemask_lt());
+}
+
+template <bool F32> struct Prec;
+template <> struct Prec<false> { using T = double; };
+template <> struct Prec<true> { using T = float; };
+
+template <bool F32>
+__device__ __forceinline__ typename Prec<F32>::T ldx(const void* x, int32_t j) {
+  return reinterpret_cast<const typename Prec<F32>::T*>(x)[j];
+}
+
+// ---------------------------------------------------------------------------
+// Bound evaluation (Section 3.1, Theorem 1).
+//   FP64 form:  l = c + alpha s (undirected) or c;  u = c + beta s.
+//   FP32 form:  s = sigma_r x~, with every rounding of the walk vector bounded
+//               by the per-node accumulator e and the global factors; the
+//               interval [lo, up] contains the exact l_r and u_r.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void bound_eval(const BoundArgs& b, int v, double& lo, double& up) {
+  const double cv = b.c[v];
+  if (!b.fp32) {
+    const double s = reinterpret_cast<const double*>(b.x)[v];
+    lo = b.undirected ? cv + b.alpha * s : cv;
+    up = cv + b.beta * s;
+  } else {
+    const double s = b.sigma[b.r] * (double)reinterpret_cast<const float*>(b.x)[v];
+    const double down = (double)b.e[v] * b.f_e + b.tau_coef * b.sigma_sum[b.r];
+    const double l = cv * b.f_lo_c + s * b.f_lo_s - down;
+    lo = l > 0.0 ? l : 0.0;
+    up = cv * b.f_hi_c + down + s * b.f_hi_s;
+  }
+}
+
+// FP32 form: true while the part of the interval that further iterations
+// shrink still exceeds 1/16 of the part they cannot shrink (rounding margin).
+__device__ __forceinline__ bool can_progress(const BoundArgs& b, int v) {
+  if (!b.fp32) return true;
+  const double cv = b.c[v];
+  const double s = b.sigma[b.r] * (double)reinterpret_cast<const float*>(b.x)[v];
+  const double down = (double)b.e[v] * b.f_e + b.tau_coef * b.sigma_sum[b.r];
+  const double intrinsic = s * (b.f_hi_s - b.f_lo_s);
+  const double margin = 2.0 * down + 2.0 * b.kappa * cv;
+  return intrinsic * 16.0 > margin;
+}
+
+__device__ __forceinline__ unsigned long long key_of(double lo) {
+  return (unsigned long long)__double_as_longlong(lo);
+}
+
+
+// Exclusive scan of a long long array of length len with one 1024-thread block.
+__device__ inline void block_exclusive_scan_ll(long long* a, long long len, long long* total_out) {
+  __shared__ long long wsum[kFinishThreads / kWave];
+  __shared__ long long carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int lane = lane_id();
+  const int w = t / kWave;
+  for (long long base = 0; base < len; base += kFinishThreads) {
+    const long long i = base + t;
+    long long x = i < len ? a[i] : 0;
+    long long inc = x;
+    for (int o = 1; o < kWave; o <<= 1) {
+      long long y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+      long long ws = lane < kFinishThreads / kWave ? wsum[lane] : 0;
+      long long wi = ws;
+      for (int o = 1; o < kWave; o <<= 1) {
+        long long y = __shfl_up(wi, o);
+        if (lane >= o) wi += y;
+      }
+      if (lane < kFinishThreads / kWave) wsum[lane] = wi - ws;   // exclusive wave offsets
+    }
+    __syncthreads();
+    const long long c0 = carry;
+    if (i < len) a[i] = c0 + wsum[w] + inc - x;
+    __syncthreads();
+    if (t == kFinishThreads - 1) carry = c0 + wsum[w] + inc;
+    __syncthreads();
+  }
+  if (t == 0 && total_out) *total_out = carry;
+}
+
+
+}  // namespace katz

@@ -1,0 +1,449 @@
+// Kernels of the dynamic update (Section 4, Algorithm 2).
+//
+// The state keeps the graph as a CSR with per-row slack: row v occupies
+// pool[row_off[v] .. row_off[v] + row_cap[v]) with its row_len[v] arcs sorted
+// at the front.  A batch of edge insertions I and deletions D is applied as a
+// sorted merge per touched row (in place when the new length fits the row's
+// capacity, otherwise into a fresh region at the pool's end).
+//
+// Walk counts are then recomputed level by level over the affected set
+// C_1 = touched rows, C_{i+1} = C_i u {w : w -> x, x in C_i} (the breadth-first
+// search over the reverse graph of Algorithm 2; undirected graphs are their own
+// reverse), with the same row kernels as the static walk step, so every
+// recomputed entry is bitwise the value a static run on the new graph computes.
+#include <algorithm>
+
+#include "katz_device.h"
+
+namespace katz {
+namespace {
+
+__device__ __forceinline__ long long slack_cap(long long len) { return len + max(2ll, len >> 3); }
+
+template <class OffT>
+__global__ void __launch_bounds__(kWG) slack_caps(const OffT* rp, long long n, int* row_len, int* row_cap,
+                                                  long long* cap_ll) {
+  const long long v = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (v >= n) return;
+  const long long len = (long long)rp[v + 1] - (long long)rp[v];
+  const long long cap = slack_cap(len);
+  row_len[v] = (int)len;
+  row_cap[v] = (int)cap;
+  cap_ll[v] = cap;
+}
+
+// Device-wide exclusive scan in three phases: per-chunk sums, a one-block scan
+// of the sums, per-chunk scans that start from their chunk offset.
+constexpr int kScanPer = 16;
+constexpr long long kScanChunk = (long long)kWG * kScanPer;
+
+__global__ void __launch_bounds__(kWG) scan_chunk_sums(const long long* in, long long count, long long* sums) {
+  const long long base = (long long)blockIdx.x * kScanChunk;
+  long long acc = 0;
+  for (int j = 0; j < kScanPer; ++j) {
+    const long long i = base + (long long)j * kWG + threadIdx.x;
+    if (i < count) acc += in[i];
+  }
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+  __shared__ long long ws[kWG / kWave];
+  if (lane_id() == 0) ws[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) sums[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ void __launch_bounds__(kFinishThreads) scan_sums(long long* sums, long long nb, long long* total) {
+  block_exclusive_scan_ll(sums, nb, total);
+}
+
+__global__ void __launch_bounds__(kWG) scan_chunk_apply(const long long* in, long long count, const long long* sums,
+                                                        long long* out) {
+  const long long base = (long long)blockIdx.x * kScanChunk;
+  // Thread t owns elements base + t*kScanPer .. + kScanPer - 1 (contiguous).
+  long long loc[kScanPer];
+  long long acc = 0;
+  for (int j = 0; j < kScanPer; ++j) {
+    const long long i = base + (long long)threadIdx.x * kScanPer + j;
+    loc[j] = i < count ? in[i] : 0;
+    acc += loc[j];
+  }
+  long long inc = acc;
+  const int lane = lane_id();
+  for (int o = 1; o < kWave; o <<= 1) {
+    const long long y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  __shared__ long long ws[kWG / kWave];
+  if (lane == kWave - 1) ws[threadIdx.x / kWave] = inc;
+  __syncthreads();
+  long long before = sums[blockIdx.x] + inc - acc;
+  for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) before += ws[w];
+  for (int j = 0; j < kScanPer; ++j) {
+    const long long i = base + (long long)threadIdx.x * kScanPer + j;
+    if (i < count) out[i] = before;
+    before += loc[j];
+  }
+}
+
+// One wave per row: copy the caller's CSR row into the slack pool.
+template <class OffT>
+__global__ void __launch_bounds__(kWG) copy_rows_to_pool(const OffT* rp, const int32_t* col, long long n,
+                                                         const long long* row_off, int32_t* pool) {
+  const long long v = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave;
+  if (v >= n) return;
+  const long long src = (long long)rp[v];
+  const long long len = (long long)rp[v + 1] - src;
+  const long long dst = row_off[v];
+  for (long long j = lane_id(); j < len; j += kWave) pool[dst + j] = col[src + j];
+}
+
+__device__ __forceinline__ long long lower_bound_i32(const int32_t* a, long long len, int32_t x) {
+  long long lo = 0, hi = len;
+  while (lo < hi) {
+    const long long mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Inserted arcs must be absent and deleted arcs present (Section 4: I n E = {},
+// D c E).  Pairs [0, n_ins) are insertions, [n_ins, n_ins + n_del) deletions.
+__global__ void __launch_bounds__(kWG) batch_exist(const int32_t* a, const int32_t* b, long long n_ins,
+                                                   long long total, const long long* row_off, const int* row_len,
+                                                   const int32_t* pool, int* err) {
+  const long long j = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (j >= total) return;
+  const int32_t u = a[j], v = b[j];
+  const int32_t* row = pool + row_off[u];
+  const long long len = row_len[u];
+  const long long p = lower_bound_i32(row, len, v);
+  const bool found = p < len && row[p] == v;
+  if ((j < n_ins) == found) atomicOr(err, 1);
+}
+
+// Candidate lengths of the touched rows; marks them.
+__global__ void __launch_bounds__(kWG) touched_lengths(const int32_t* rows, long long t, const int* delta,
+                                                       const int* row_len, long long* new_len, uint8_t* mark) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i >= t) return;
+  const int w = rows[i];
+  new_len[i] = (long long)row_len[w] + delta[i];
+  mark[w] = 1;
+}
+
+// Maximum row length after the batch: untouched rows as they are, touched rows
+// at their candidate length.
+__global__ void __launch_bounds__(kWG) max_len_after(const int* row_len, const uint8_t* mark, long long n,
+                                                     const long long* new_len, long long t, int* out) {
+  int m = 0;
+  for (long long v = (long long)blockIdx.x * kWG + threadIdx.x; v < n; v += (long long)gridDim.x * kWG)
+    if (!mark[v]) m = max(m, row_len[v]);
+  for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < t; i += (long long)gridDim.x * kWG)
+    m = max(m, (int)new_len[i]);
+  for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o));
+  if (lane_id() == 0) atomicMax(out, m);
+}
+
+__global__ void __launch_bounds__(kWG) unmark_rows(const int32_t* rows, long long t, uint8_t* mark) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i < t) mark[rows[i]] = 0;
+}
+
+// One workgroup per touched row w: new row = (old row \ del) u ins, sorted,
+// written to scratch[sbase[i] ..].  ins and del are sorted per row.
+__global__ void __launch_bounds__(kWG) merge_rows(const int32_t* rows, const long long* ins_off, const int* ins_cnt,
+                                                  const int32_t* ins_dst, const long long* del_off,
+                                                  const int* del_cnt, const int32_t* del_dst,
+                                                  const long long* sbase, const long long* row_off,
+                                                  const int* row_len, const int32_t* pool, int32_t* scratch) {
+  const long long i = blockIdx.x;
+  const int w = rows[i];
+  const int32_t* old = pool + row_off[w];
+  const long long len = row_len[w];
+  const int32_t* ins = ins_dst + ins_off[i];
+  const int32_t* del = del_dst + del_off[i];
+  const int ni = ins_cnt[i], nd = del_cnt[i];
+  int32_t* out = scratch + sbase[i];
+  for (long long j = threadIdx.x; j < len; j += kWG) {
+    const int32_t x = old[j];
+    const long long pd = lower_bound_i32(del, nd, x);
+    if (pd < nd && del[pd] == x) continue;
+    const long long pi = lower_bound_i32(ins, ni, x);
+    out[j - pd + pi] = x;
+  }
+  for (int j = threadIdx.x; j < ni; j += kWG) {
+    const int32_t x = ins[j];
+    const long long po = lower_bound_i32(old, len, x);
+    const long long pd = lower_bound_i32(del, nd, x);
+    out[j + po - pd] = x;
+  }
+}
+
+__global__ void __launch_bounds__(kWG) copy_back_rows(const int32_t* rows, const long long* sbase,
+                                                      const long long* new_len, const long long* dest_off,
+                                                      const int* dest_cap, const int32_t* scratch,
+                                                      long long* row_off, int* row_len, int* row_cap,
+                                                      int32_t* pool) {
+  const long long i = blockIdx.x;
+  const int w = rows[i];
+  const long long len = new_len[i];
+  const long long dst = dest_off[i];
+  for (long long j = threadIdx.x; j < len; j += kWG) pool[dst + j] = scratch[sbase[i] + j];
+  if (threadIdx.x == 0) {
+    row_off[w] = dst;
+    row_len[w] = (int)len;
+    row_cap[w] = dest_cap[i];
+  }
+}
+
+// Breadth-first expansion: every neighbour of a frontier row that is not yet in
+// C joins C at `level` and the next frontier.  One wave per frontier row.
+__global__ void __launch_bounds__(kWG) frontier_expand(const int32_t* frontier, long long f, const long long* row_off,
+                                                       const int* row_len, const int32_t* pool, int* level_of,
+                                                       int level, int32_t* next, int* next_count) {
+  const long long wv = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave;
+  const int lane = lane_id();
+  const bool valid_row = wv < f;
+  const int w = valid_row ? frontier[wv] : 0;
+  const long long off = valid_row ? row_off[w] : 0;
+  const int len = valid_row ? row_len[w] : 0;
+  // Every lane of a wave runs the same trip count (wave_append needs them all).
+  for (int base = 0; base < len; base += kWave) {
+    const int j = base + lane;
+    bool fresh = false;
+    int u = 0;
+    if (j < len) {
+      u = pool[off + j];
+      fresh = atomicCAS(&level_of[u], 0, level) == 0;
+    }
+    const int pos = wave_append(next_count, fresh);
+    if (fresh) next[pos] = u;
+  }
+}
+
+__global__ void __launch_bounds__(kWG) set_levels(const int32_t* rows, long long t, int* level_of, int level) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i < t) level_of[rows[i]] = level;
+}
+
+__global__ void __launch_bounds__(kWG) clear_levels(const int32_t* rows, long long t, int* level_of) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i < t) level_of[rows[i]] = 0;
+}
+
+// c(w) = x_1(w) + x_2(w) + ... + x_r(w), accumulated in the static order.
+__global__ void __launch_bounds__(kWG) c_from_history(const int32_t* rows, long long count, double* const* X,
+                                                      int r, double* c) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i >= count) return;
+  const int w = rows ? rows[i] : (int)i;
+  double acc = X[1][w];
+  for (int l = 2; l <= r; ++l) acc = acc + X[l][w];
+  c[w] = acc;
+}
+
+__global__ void __launch_bounds__(kWG) max_of_vector(const double* x, long long n, unsigned long long* out) {
+  double m = 0.0;
+  for (long long v = (long long)blockIdx.x * kWG + threadIdx.x; v < n; v += (long long)gridDim.x * kWG)
+    m = fmax(m, x[v]);
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if (lane_id() == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+// min over the active list of the lower bound (as non-negative IEEE bits).
+__global__ void __launch_bounds__(kWG) min_lower_active(BoundArgs b, const int32_t* act, const int* m_ptr,
+                                                        unsigned long long* out, uint8_t* mark) {
+  const int m = *m_ptr;
+  unsigned long long best = ~0ull;
+  for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < m; i += (long long)gridDim.x * kWG) {
+    const int v = act[i];
+    double lo, up;
+    bound_eval(b, v, lo, up);
+    best = min(best, key_of(lo));
+    mark[v] = 1;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned long long y = __shfl_xor(best, o);
+    best = min(best, y);
+  }
+  if (lane_id() == 0) atomicMin(out, best);
+}
+
+// Reactivation (Algorithm 2): M <- M u {w : u(w) >= min_{x in M} l(x) - eps}.
+__global__ void __launch_bounds__(kWG) reactivate(BoundArgs b, long long n, const unsigned long long* min_bits,
+                                                  uint8_t* mark, int32_t* out, int* count) {
+  const double thr = __longlong_as_double((long long)*min_bits) - b.eps;
+  const long long stride = (long long)gridDim.x * kWG;
+  for (long long base = (long long)blockIdx.x * kWG; base < n; base += stride) {
+    const long long v = base + threadIdx.x;
+    bool keep = false;
+    if (v < n) {
+      if (mark[v]) {
+        keep = true;
+        mark[v] = 0;
+      } else {
+        double lo, up;
+        bound_eval(b, (int)v, lo, up);
+        keep = up >= thr;
+      }
+    }
+    const int pos = wave_append(count, keep);
+    if (keep) out[pos] = (int)v;
+  }
+}
+
+__global__ void __launch_bounds__(kWG) gather_int(const int32_t* rows, long long t, const int* src, int* out) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i < t) out[i] = src[rows[i]];
+}
+
+__global__ void __launch_bounds__(kWG) gather_ll(const int32_t* rows, long long t, const long long* src,
+                                                 long long* out) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i < t) out[i] = src[rows[i]];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+static unsigned blocks_for(long long count, int per_block = kWG) {
+  return (unsigned)std::max<long long>(1, (count + per_block - 1) / per_block);
+}
+
+hipError_t launch_scan_ll(const long long* in, long long count, long long* out, long long* sums,
+                          long long* total, hipStream_t s) {
+  const long long nb = std::max<long long>(1, (count + kScanChunk - 1) / kScanChunk);
+  hipLaunchKernelGGL(scan_chunk_sums, dim3((unsigned)nb), dim3(kWG), 0, s, in, count, sums);
+  hipLaunchKernelGGL(scan_sums, dim3(1), dim3(kFinishThreads), 0, s, sums, nb, total);
+  hipLaunchKernelGGL(scan_chunk_apply, dim3((unsigned)nb), dim3(kWG), 0, s, in, count, (const long long*)sums, out);
+  return hipGetLastError();
+}
+
+long long scan_sums_capacity(long long count) { return std::max<long long>(1, (count + kScanChunk - 1) / kScanChunk); }
+
+hipError_t launch_slack_caps(const void* rp, int rp64, long long n, int* row_len, int* row_cap, long long* cap_ll,
+                             hipStream_t s) {
+  if (rp64)
+    hipLaunchKernelGGL(slack_caps<int64_t>, dim3(blocks_for(n)), dim3(kWG), 0, s, (const int64_t*)rp, n, row_len,
+                       row_cap, cap_ll);
+  else
+    hipLaunchKernelGGL(slack_caps<int32_t>, dim3(blocks_for(n)), dim3(kWG), 0, s, (const int32_t*)rp, n, row_len,
+                       row_cap, cap_ll);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_rows_to_pool(const void* rp, int rp64, const int32_t* col, long long n,
+                                    const long long* row_off, int32_t* pool, hipStream_t s) {
+  const unsigned nb = blocks_for(n * kWave);
+  if (rp64)
+    hipLaunchKernelGGL(copy_rows_to_pool<int64_t>, dim3(nb), dim3(kWG), 0, s, (const int64_t*)rp, col, n, row_off,
+                       pool);
+  else
+    hipLaunchKernelGGL(copy_rows_to_pool<int32_t>, dim3(nb), dim3(kWG), 0, s, (const int32_t*)rp, col, n, row_off,
+                       pool);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_exist(const int32_t* a, const int32_t* b, long long n_ins, long long total,
+                              const long long* row_off, const int* row_len, const int32_t* pool, int* err,
+                              hipStream_t s) {
+  if (total > 0)
+    hipLaunchKernelGGL(batch_exist, dim3(blocks_for(total)), dim3(kWG), 0, s, a, b, n_ins, total, row_off, row_len,
+                       pool, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_touched_lengths(const int32_t* rows, long long t, const int* delta, const int* row_len,
+                                  long long* new_len, uint8_t* mark, hipStream_t s) {
+  hipLaunchKernelGGL(touched_lengths, dim3(blocks_for(t)), dim3(kWG), 0, s, rows, t, delta, row_len, new_len, mark);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_len_after(const int* row_len, const uint8_t* mark, long long n, const long long* new_len,
+                                long long t, int* out, hipStream_t s) {
+  const unsigned nb = (unsigned)std::min<long long>(blocks_for(n), 2048);
+  hipLaunchKernelGGL(max_len_after, dim3(nb), dim3(kWG), 0, s, row_len, mark, n, new_len, t, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_unmark_rows(const int32_t* rows, long long t, uint8_t* mark, hipStream_t s) {
+  hipLaunchKernelGGL(unmark_rows, dim3(blocks_for(t)), dim3(kWG), 0, s, rows, t, mark);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_rows(const int32_t* rows, long long t, const long long* ins_off, const int* ins_cnt,
+                             const int32_t* ins_dst, const long long* del_off, const int* del_cnt,
+                             const int32_t* del_dst, const long long* sbase, const long long* row_off,
+                             const int* row_len, const int32_t* pool, int32_t* scratch, hipStream_t s) {
+  if (t > 0)
+    hipLaunchKernelGGL(merge_rows, dim3((unsigned)t), dim3(kWG), 0, s, rows, ins_off, ins_cnt, ins_dst, del_off,
+                       del_cnt, del_dst, sbase, row_off, row_len, pool, scratch);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_back_rows(const int32_t* rows, long long t, const long long* sbase, const long long* new_len,
+                                 const long long* dest_off, const int* dest_cap, const int32_t* scratch,
+                                 long long* row_off, int* row_len, int* row_cap, int32_t* pool, hipStream_t s) {
+  if (t > 0)
+    hipLaunchKernelGGL(copy_back_rows, dim3((unsigned)t), dim3(kWG), 0, s, rows, sbase, new_len, dest_off, dest_cap,
+                       scratch, row_off, row_len, row_cap, pool);
+  return hipGetLastError();
+}
+
+hipError_t launch_frontier_expand(const int32_t* frontier, long long f, const long long* row_off, const int* row_len,
+                                  const int32_t* pool, int* level_of, int level, int32_t* next, int* next_count,
+                                  hipStream_t s) {
+  if (f > 0)
+    hipLaunchKernelGGL(frontier_expand, dim3(blocks_for(f * kWave)), dim3(kWG), 0, s, frontier, f, row_off, row_len,
+                       pool, level_of, level, next, next_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_levels(const int32_t* rows, long long t, int* level_of, int level, hipStream_t s) {
+  if (t > 0) hipLaunchKernelGGL(set_levels, dim3(blocks_for(t)), dim3(kWG), 0, s, rows, t, level_of, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_levels(const int32_t* rows, long long t, int* level_of, hipStream_t s) {
+  if (t > 0) hipLaunchKernelGGL(clear_levels, dim3(blocks_for(t)), dim3(kWG), 0, s, rows, t, level_of);
+  return hipGetLastError();
+}
+
+hipError_t launch_c_from_history(const int32_t* rows, long long count, double* const* X, int r, double* c,
+                                 hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(c_from_history, dim3(blocks_for(count)), dim3(kWG), 0, s, rows, count, X, r, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_of_vector(const double* x, long long n, unsigned long long* out, hipStream_t s) {
+  const unsigned nb = (unsigned)std::min<long long>(blocks_for(n), 2048);
+  hipLaunchKernelGGL(max_of_vector, dim3(nb), dim3(kWG), 0, s, x, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_min_lower_active(const BoundArgs& b, const int32_t* act, const int* m_ptr,
+                                   unsigned long long* min_bits, uint8_t* mark, long long n, hipStream_t s) {
+  const unsigned nb = (unsigned)std::min<long long>(blocks_for(n), 2048);
+  hipLaunchKernelGGL(min_lower_active, dim3(nb), dim3(kWG), 0, s, b, act, m_ptr, min_bits, mark);
+  return hipGetLastError();
+}
+
+hipError_t launch_reactivate_all(const BoundArgs& b, long long n, const unsigned long long* min_bits,
+                                 uint8_t* mark, int32_t* out, int* count, hipStream_t s) {
+  const unsigned nb = (unsigned)std::min<long long>(blocks_for(n), 2048);
+  hipLaunchKernelGGL(reactivate, dim3(nb), dim3(kWG), 0, s, b, n, min_bits, mark, out, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_int(const int32_t* rows, long long t, const int* src, int* out, hipStream_t s) {
+  if (t > 0) hipLaunchKernelGGL(gather_int, dim3(blocks_for(t)), dim3(kWG), 0, s, rows, t, src, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_ll(const int32_t* rows, long long t, const long long* src, long long* out, hipStream_t s) {
+  if (t > 0) hipLaunchKernelGGL(gather_ll, dim3(blocks_for(t)), dim3(kWG), 0, s, rows, t, src, out);
+  return hipGetLastError();
+}
+
+}  // namespace katz

@@ -87,7 +87,7 @@ struct RunScalars {
   int cut_ext;        // ties with key == theta_key are top iff ext id <= cut_ext
   int fail;           // adjacent-pair test failed
   int dmax;           // prep: maximum row length
-  int pad;
+  int cur;            // active-list buffer written by the last completed check
   unsigned long long prefix;     // resolved high bits of the k-th key
   unsigned long long theta_key;  // bit pattern of l(M[k])
   double theta;                  // l(M[k])
@@ -135,10 +135,10 @@ struct IterArgs {
   RunScalars* sc;
   int n;
   int r;
-  int validate_cols;
+  int count_first;               // walk_first: number of descriptors to process
   int write_empty;
   int clog2_dmax;
-  int pad;
+  int rewalk;                    // dynamic re-walk: write x only (no c, no maxima)
   double alpha;
   double etap;                   // eta'_r
 };
@@ -159,10 +159,12 @@ struct SelArgs {
   const unsigned* xmax32;
   const unsigned long long* xmax64;
   RunScalars* sc;
-  int identity_in;               // r == 1: the active list is 0..n-1
+  int identity_in;               // first selection of a run: the active list is 0..n-1
   int k;
   int n;
   int max_iter;
+  int act_out_idx;               // which active-list buffer act_out is (recorded on completion)
+  int pad;
 };
 
 // ---- launchers (katz_kernels.hip) ----------------------------------------
@@ -177,6 +179,7 @@ hipError_t launch_validate_strict(const RowDesc* desc, long long n, const int32_
 hipError_t launch_walk_first(const IterArgs& a, int fp32, long long n, long long nnz, int validate,
                              hipStream_t s);
 hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, hipStream_t s);
+hipError_t launch_check_col_range(const int32_t* col, long long nnz, long long n, RunScalars* sc, hipStream_t s);
 hipError_t launch_select_iteration(const SelArgs& a, int grid, hipStream_t s);
 hipError_t launch_write_result(const SelArgs& a, uint8_t* mark, int32_t* out_ids, double* out_lo,
                                double* out_up, unsigned long long* rest_bits, int grid, hipStream_t s);
@@ -185,6 +188,50 @@ hipError_t launch_all_bounds(const BoundArgs& b, int64_t n, const int32_t* ext_o
 hipError_t launch_init_run(RunScalars* sc, int64_t n, double* sigma, double* sigma_sum,
                            unsigned* xmax32, unsigned long long* xmax64, int max_iter,
                            unsigned* hist, hipStream_t s);
+
+hipError_t launch_prep_rows(const int32_t* ids, long long count, const long long* off, const int* len,
+                            long long* blk, int nblocks, RowDesc* desc, SegDesc* segs, HugeRow* huge,
+                            RunScalars* sc, hipStream_t s);
+
+// ---- dynamic update (katz_dynamic.hip) ----------------------------------------
+hipError_t launch_scan_ll(const long long* in, long long count, long long* out, long long* sums,
+                          long long* total, hipStream_t s);
+long long scan_sums_capacity(long long count);
+hipError_t launch_slack_caps(const void* rp, int rp64, long long n, int* row_len, int* row_cap,
+                             long long* cap_ll, hipStream_t s);
+hipError_t launch_copy_rows_to_pool(const void* rp, int rp64, const int32_t* col, long long n,
+                                    const long long* row_off, int32_t* pool, hipStream_t s);
+hipError_t launch_batch_exist(const int32_t* a, const int32_t* b, long long n_ins, long long total,
+                              const long long* row_off, const int* row_len, const int32_t* pool, int* err,
+                              hipStream_t s);
+hipError_t launch_touched_lengths(const int32_t* rows, long long t, const int* delta, const int* row_len,
+                                  long long* new_len, uint8_t* mark, hipStream_t s);
+hipError_t launch_max_len_after(const int* row_len, const uint8_t* mark, long long n, const long long* new_len,
+                                long long t, int* out, hipStream_t s);
+hipError_t launch_unmark_rows(const int32_t* rows, long long t, uint8_t* mark, hipStream_t s);
+hipError_t launch_merge_rows(const int32_t* rows, long long t, const long long* ins_off, const int* ins_cnt,
+                             const int32_t* ins_dst, const long long* del_off, const int* del_cnt,
+                             const int32_t* del_dst, const long long* sbase, const long long* row_off,
+                             const int* row_len, const int32_t* pool, int32_t* scratch, hipStream_t s);
+hipError_t launch_copy_back_rows(const int32_t* rows, long long t, const long long* sbase, const long long* new_len,
+                                 const long long* dest_off, const int* dest_cap, const int32_t* scratch,
+                                 long long* row_off, int* row_len, int* row_cap, int32_t* pool, hipStream_t s);
+hipError_t launch_frontier_expand(const int32_t* frontier, long long f, const long long* row_off, const int* row_len,
+                                  const int32_t* pool, int* level_of, int level, int32_t* next, int* next_count,
+                                  hipStream_t s);
+hipError_t launch_set_levels(const int32_t* rows, long long t, int* level_of, int level, hipStream_t s);
+hipError_t launch_clear_levels(const int32_t* rows, long long t, int* level_of, hipStream_t s);
+hipError_t launch_c_from_history(const int32_t* rows, long long count, double* const* X, int r, double* c,
+                                 hipStream_t s);
+hipError_t launch_max_of_vector(const double* x, long long n, unsigned long long* out, hipStream_t s);
+
+hipError_t launch_reset_flags(RunScalars* sc, hipStream_t s);
+hipError_t launch_gather_int(const int32_t* rows, long long t, const int* src, int* out, hipStream_t s);
+hipError_t launch_gather_ll(const int32_t* rows, long long t, const long long* src, long long* out, hipStream_t s);
+hipError_t launch_min_lower_active(const BoundArgs& b, const int32_t* act, const int* m_ptr,
+                                   unsigned long long* min_bits, uint8_t* mark, long long n, hipStream_t s);
+hipError_t launch_reactivate_all(const BoundArgs& b, long long n, const unsigned long long* min_bits,
+                                 uint8_t* mark, int32_t* out, int* count, hipStream_t s);
 
 int bin_of_host(int64_t len);
 

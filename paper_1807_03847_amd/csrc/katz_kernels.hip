@@ -18,107 +18,76 @@
 #include <climits>
 #include <cstdint>
 
-#include "katz_internal.h"
+#include "katz_device.h"
 
 namespace katz {
-
-__host__ __device__ constexpr int bin_of_len(long long len) {
-  return len <= 0 ? BIN_EMPTY
-       : len <= 4 ? BIN_G4
-       : len <= 8 ? BIN_G8
-       : len <= 16 ? BIN_G16
-       : len <= 32 ? BIN_G32
-       : len <= kWaveRowMax ? BIN_W64
-       : len <= kBlockRowMax ? BIN_B256
-       : BIN_HUGE;
-}
 
 int bin_of_host(int64_t len) { return bin_of_len(len); }
 
 namespace {
 
-__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
-
-__device__ __forceinline__ unsigned long long lanemask_lt() {
-  return (1ull << lane_id()) - 1ull;
-}
-
-// Wave-aggregated append: one atomic per wave.  Every lane of the wave must call it.
-__device__ __forceinline__ int wave_append(int* counter, bool pred) {
-  const unsigned long long mask = __ballot(pred);
-  if (mask == 0ull) return -1;
-  const int leader = __ffsll((long long)mask) - 1;
-  int base = 0;
-  if (lane_id() == leader) base = atomicAdd(counter, __popcll(mask));
-  base = __shfl(base, leader);
-  return base + __popcll(mask & lanemask_lt());
-}
-
-template <bool F32> struct Prec;
-template <> struct Prec<false> { using T = double; };
-template <> struct Prec<true> { using T = float; };
-
-template <bool F32>
-__device__ __forceinline__ typename Prec<F32>::T ldx(const void* x, int32_t j) {
-  return reinterpret_cast<const typename Prec<F32>::T*>(x)[j];
-}
-
 // ---------------------------------------------------------------------------
-// Bound evaluation (Section 3.1, Theorem 1).
-//   FP64 form:  l = c + alpha s (undirected) or c;  u = c + beta s.
-//   FP32 form:  s = sigma_r x~, with every rounding of the walk vector bounded
-//               by the per-node accumulator e and the global factors; the
-//               interval [lo, up] contains the exact l_r and u_r.
+// Row sources for binning: a caller CSR, the slack CSR of a dynamic state, or
+// a list of row ids of the slack CSR (the affected rows of one re-walk level).
+// get(i) yields row id, offset and length of entry i; false marks a malformed
+// CSR row.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void bound_eval(const BoundArgs& b, int v, double& lo, double& up) {
-  const double cv = b.c[v];
-  if (!b.fp32) {
-    const double s = reinterpret_cast<const double*>(b.x)[v];
-    lo = b.undirected ? cv + b.alpha * s : cv;
-    up = cv + b.beta * s;
-  } else {
-    const double s = b.sigma[b.r] * (double)reinterpret_cast<const float*>(b.x)[v];
-    const double down = (double)b.e[v] * b.f_e + b.tau_coef * b.sigma_sum[b.r];
-    const double l = cv * b.f_lo_c + s * b.f_lo_s - down;
-    lo = l > 0.0 ? l : 0.0;
-    up = cv * b.f_hi_c + down + s * b.f_hi_s;
+template <class OffT>
+struct CsrRows {
+  const OffT* rp;
+  long long nnz;
+  static constexpr bool kCsr = true;
+  __device__ __forceinline__ bool get(long long i, int& row, long long& off, long long& len) const {
+    row = (int)i;
+    off = (long long)rp[i];
+    const long long end = (long long)rp[i + 1];
+    len = end - off;
+    return len >= 0 && len <= INT_MAX && off >= 0 && end <= nnz;
   }
-}
+};
 
-// FP32 form: true while the part of the interval that further iterations
-// shrink still exceeds 1/16 of the part they cannot shrink (rounding margin).
-__device__ __forceinline__ bool can_progress(const BoundArgs& b, int v) {
-  if (!b.fp32) return true;
-  const double cv = b.c[v];
-  const double s = b.sigma[b.r] * (double)reinterpret_cast<const float*>(b.x)[v];
-  const double down = (double)b.e[v] * b.f_e + b.tau_coef * b.sigma_sum[b.r];
-  const double intrinsic = s * (b.f_hi_s - b.f_lo_s);
-  const double margin = 2.0 * down + 2.0 * b.kappa * cv;
-  return intrinsic * 16.0 > margin;
-}
+struct SlackRows {
+  const long long* off;
+  const int* len;
+  static constexpr bool kCsr = false;
+  __device__ __forceinline__ bool get(long long i, int& row, long long& o, long long& l) const {
+    row = (int)i;
+    o = off[i];
+    l = len[i];
+    return true;
+  }
+};
 
-__device__ __forceinline__ unsigned long long key_of(double lo) {
-  return (unsigned long long)__double_as_longlong(lo);
-}
+struct ListRows {
+  const int32_t* ids;
+  const long long* off;
+  const int* len;
+  static constexpr bool kCsr = false;
+  __device__ __forceinline__ bool get(long long i, int& row, long long& o, long long& l) const {
+    row = ids[i];
+    o = off[row];
+    l = len[row];
+    return true;
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Prep: per-block bin counts, maximum degree, CSR checks.
 // blk layout: [NUM_BINS + 1][nblocks]; column NUM_BINS counts huge segments.
 // ---------------------------------------------------------------------------
-template <class OffT>
-__global__ void __launch_bounds__(kWG) prep_count(const OffT* row_ptr, long long n, long long nnz,
-                                                  long long* blk, int nblocks, RunScalars* sc) {
+template <class Rows>
+__global__ void __launch_bounds__(kWG) prep_count(Rows rows, long long count, long long* blk, int nblocks,
+                                                  RunScalars* sc) {
   __shared__ int cnt[NUM_BINS + 1];
   if (threadIdx.x <= NUM_BINS) cnt[threadIdx.x] = 0;
   __syncthreads();
-  const long long v = (long long)blockIdx.x * kWG + threadIdx.x;
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
   int dmax = 0;
   bool bad = false;
-  if (v < n) {
-    const long long o0 = (long long)row_ptr[v];
-    const long long o1 = (long long)row_ptr[v + 1];
-    const long long len = o1 - o0;
-    if (len < 0 || len > INT_MAX || o0 < 0 || o1 > nnz) {
+  if (i < count) {
+    int row;
+    long long off, len;
+    if (!rows.get(i, row, off, len)) {
       bad = true;
     } else {
       const int b = bin_of_len(len);
@@ -127,52 +96,14 @@ __global__ void __launch_bounds__(kWG) prep_count(const OffT* row_ptr, long long
       dmax = (int)len;
     }
   }
-  if (v == 0) {
-    if ((long long)row_ptr[0] != 0 || (long long)row_ptr[n] != nnz) bad = true;
+  if constexpr (Rows::kCsr) {
+    if (i == 0 && ((long long)rows.rp[0] != 0 || (long long)rows.rp[count] != rows.nnz)) bad = true;
   }
   for (int o = 32; o >= 1; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o));
   if (lane_id() == 0 && dmax > 0) atomicMax(&sc->dmax, dmax);
   if (bad) atomicOr(&sc->err, 1);
   __syncthreads();
   if (threadIdx.x <= NUM_BINS) blk[(long long)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
-}
-
-// Exclusive scan of a long long array of length len with one 1024-thread block.
-__device__ void block_exclusive_scan_ll(long long* a, long long len, long long* total_out) {
-  __shared__ long long wsum[kFinishThreads / kWave];
-  __shared__ long long carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  const int t = threadIdx.x;
-  const int lane = lane_id();
-  const int w = t / kWave;
-  for (long long base = 0; base < len; base += kFinishThreads) {
-    const long long i = base + t;
-    long long x = i < len ? a[i] : 0;
-    long long inc = x;
-    for (int o = 1; o < kWave; o <<= 1) {
-      long long y = __shfl_up(inc, o);
-      if (lane >= o) inc += y;
-    }
-    if (lane == kWave - 1) wsum[w] = inc;
-    __syncthreads();
-    if (w == 0) {
-      long long ws = lane < kFinishThreads / kWave ? wsum[lane] : 0;
-      long long wi = ws;
-      for (int o = 1; o < kWave; o <<= 1) {
-        long long y = __shfl_up(wi, o);
-        if (lane >= o) wi += y;
-      }
-      if (lane < kFinishThreads / kWave) wsum[lane] = wi - ws;   // exclusive wave offsets
-    }
-    __syncthreads();
-    const long long c0 = carry;
-    if (i < len) a[i] = c0 + wsum[w] + inc - x;
-    __syncthreads();
-    if (t == kFinishThreads - 1) carry = c0 + wsum[w] + inc;
-    __syncthreads();
-  }
-  if (t == 0 && total_out) *total_out = carry;
 }
 
 __global__ void __launch_bounds__(kFinishThreads) prep_scan(long long* blk, int nblocks, RunScalars* sc) {
@@ -205,25 +136,24 @@ __global__ void __launch_bounds__(kFinishThreads) prep_scan(long long* blk, int 
   if (threadIdx.x == 0) sc->seg_total = total;
 }
 
-template <class OffT>
-__global__ void __launch_bounds__(kWG) prep_scatter(const OffT* row_ptr, long long n, const long long* blk,
+template <class Rows>
+__global__ void __launch_bounds__(kWG) prep_scatter(Rows rows, long long count, const long long* blk,
                                                     int nblocks, RowDesc* desc, SegDesc* segs,
                                                     HugeRow* huge, RunScalars* sc) {
   if (sc->err) return;
   __shared__ int wcnt[NUM_BINS][kWG / kWave];
   __shared__ int wseg[kWG / kWave];
-  const long long v = (long long)blockIdx.x * kWG + threadIdx.x;
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
   const int lane = lane_id();
   const int w = threadIdx.x / kWave;
-  long long off = 0;
-  int len = 0;
+  long long off = 0, len = 0;
+  int row = 0;
   int bin = -1;
   int nseg = 0;
-  if (v < n) {
-    off = (long long)row_ptr[v];
-    len = (int)((long long)row_ptr[v + 1] - off);
+  if (i < count) {
+    rows.get(i, row, off, len);
     bin = bin_of_len(len);
-    if (bin == BIN_HUGE) nseg = (len + kSeg - 1) / kSeg;
+    if (bin == BIN_HUGE) nseg = (int)((len + kSeg - 1) / kSeg);
   }
   int rank_in_wave = 0;
   for (int b = 0; b < NUM_BINS; ++b) {
@@ -239,20 +169,20 @@ __global__ void __launch_bounds__(kWG) prep_scatter(const OffT* row_ptr, long lo
   }
   if (lane == kWave - 1) wseg[w] = sinc;
   __syncthreads();
-  if (v < n) {
+  if (i < count) {
     int before = 0;
     for (int ww = 0; ww < w; ++ww) before += wcnt[bin][ww];
     const long long pos = blk[(long long)bin * nblocks + blockIdx.x] + before + rank_in_wave;
-    desc[pos] = RowDesc{off, (int32_t)v, len};
+    desc[pos] = RowDesc{off, (int32_t)row, (int32_t)len};
     if (bin == BIN_HUGE) {
       int sbefore = 0;
       for (int ww = 0; ww < w; ++ww) sbefore += wseg[ww];
       const long long part0 = blk[(long long)NUM_BINS * nblocks + blockIdx.x] + sbefore + sinc - nseg;
-      huge[pos - sc->bin_base[BIN_HUGE]] = HugeRow{(int32_t)v, len, nseg, (int32_t)part0};
-      for (int s = 0; s < nseg; ++s) {
-        const int slen = min(kSeg, len - s * kSeg);
-        segs[part0 + s] = SegDesc{off + (long long)s * kSeg, slen, (int32_t)(part0 + s),
-                                  (int32_t)(pos - sc->bin_base[BIN_HUGE]), 0};
+      const long long hidx = pos - sc->bin_base[BIN_HUGE];
+      huge[hidx] = HugeRow{(int32_t)row, (int32_t)len, nseg, (int32_t)part0};
+      for (int sg = 0; sg < nseg; ++sg) {
+        const int slen = (int)min((long long)kSeg, len - (long long)sg * kSeg);
+        segs[part0 + sg] = SegDesc{off + (long long)sg * kSeg, slen, (int32_t)(part0 + sg), (int32_t)hidx, 0};
       }
     }
   }
@@ -338,6 +268,7 @@ __device__ __forceinline__ void epilogue(const IterArgs& a, const Epi<F32>& ep, 
   if constexpr (!F32) {
     const double s = a.alpha * t;
     reinterpret_cast<double*>(a.x_out)[row] = s;
+    if (a.rewalk) return;
     a.c[row] = (a.r == 1) ? s : a.c[row] + s;
     vmax = fmax(vmax, s);
   } else {
@@ -416,7 +347,7 @@ __global__ void __launch_bounds__(kWG) walk_first(IterArgs a) {
   }
   double vmax = 0.0;
   const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
-  if (i < a.n) {
+  if (i < a.count_first) {
     const RowDesc d = a.desc[i];
     epilogue<F32>(a, ep, d.row, (typename Prec<F32>::T)d.len, vmax);
   }
@@ -846,6 +777,7 @@ __global__ void __launch_bounds__(kFinishThreads) sel_check(SelArgs a) {
     else if (a.b.fp32 && !sc->progress) status = KATZ_W_PRECISION_LIMIT;
     else if (a.b.r >= a.max_iter) status = KATZ_W_ITER_LIMIT;
     sc->iterations = a.b.r;
+    sc->cur = a.act_out_idx;
     sc->m = k + kept;
     sc->top_count = 0;
     sc->kept_count = 0;
@@ -923,7 +855,24 @@ __global__ void init_run(RunScalars* sc, long long n, double* sigma, double* sig
   for (long long i = t; i < 2 * kDigits; i += stride) hist[i] = 0u;
 }
 
+__global__ void reset_flags(RunScalars* sc) {
+  sc->err = 0;
+  sc->done = 0;
+  sc->status = KATZ_OK;
+  sc->top_count = 0;
+  sc->kept_count = 0;
+  sc->progress = 0;
+  sc->cand_count[0] = 0;
+  sc->cand_count[1] = 0;
+  sc->dmax = 0;
+}
+
 }  // namespace
+
+hipError_t launch_reset_flags(RunScalars* sc, hipStream_t s) {
+  hipLaunchKernelGGL(reset_flags, dim3(1), dim3(1), 0, s, sc);
+  return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // Launchers.
@@ -931,11 +880,11 @@ __global__ void init_run(RunScalars* sc, long long n, double* sigma, double* sig
 hipError_t launch_prep_count(const void* row_ptr, int row_ptr_64, int64_t n, int64_t nnz, long long* blk,
                              int nblocks, RunScalars* sc, hipStream_t s) {
   if (row_ptr_64)
-    hipLaunchKernelGGL(prep_count<int64_t>, dim3(nblocks), dim3(kWG), 0, s, (const int64_t*)row_ptr,
-                       (long long)n, (long long)nnz, blk, nblocks, sc);
+    hipLaunchKernelGGL(prep_count<CsrRows<int64_t>>, dim3(nblocks), dim3(kWG), 0, s,
+                       CsrRows<int64_t>{(const int64_t*)row_ptr, (long long)nnz}, (long long)n, blk, nblocks, sc);
   else
-    hipLaunchKernelGGL(prep_count<int32_t>, dim3(nblocks), dim3(kWG), 0, s, (const int32_t*)row_ptr,
-                       (long long)n, (long long)nnz, blk, nblocks, sc);
+    hipLaunchKernelGGL(prep_count<CsrRows<int32_t>>, dim3(nblocks), dim3(kWG), 0, s,
+                       CsrRows<int32_t>{(const int32_t*)row_ptr, (long long)nnz}, (long long)n, blk, nblocks, sc);
   return hipGetLastError();
 }
 
@@ -948,11 +897,32 @@ hipError_t launch_prep_scatter(const void* row_ptr, int row_ptr_64, int64_t n, c
                                int nblocks, RowDesc* desc, SegDesc* segs, HugeRow* huge, RunScalars* sc,
                                hipStream_t s) {
   if (row_ptr_64)
-    hipLaunchKernelGGL(prep_scatter<int64_t>, dim3(nblocks), dim3(kWG), 0, s, (const int64_t*)row_ptr,
-                       (long long)n, blk, nblocks, desc, segs, huge, sc);
+    hipLaunchKernelGGL(prep_scatter<CsrRows<int64_t>>, dim3(nblocks), dim3(kWG), 0, s,
+                       CsrRows<int64_t>{(const int64_t*)row_ptr, 0}, (long long)n, blk, nblocks, desc, segs, huge,
+                       sc);
   else
-    hipLaunchKernelGGL(prep_scatter<int32_t>, dim3(nblocks), dim3(kWG), 0, s, (const int32_t*)row_ptr,
-                       (long long)n, blk, nblocks, desc, segs, huge, sc);
+    hipLaunchKernelGGL(prep_scatter<CsrRows<int32_t>>, dim3(nblocks), dim3(kWG), 0, s,
+                       CsrRows<int32_t>{(const int32_t*)row_ptr, 0}, (long long)n, blk, nblocks, desc, segs, huge,
+                       sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_rows(const int32_t* ids, long long count, const long long* off, const int* len,
+                            long long* blk, int nblocks, RowDesc* desc, SegDesc* segs, HugeRow* huge,
+                            RunScalars* sc, hipStream_t s) {
+  if (ids) {
+    const ListRows rows{ids, off, len};
+    hipLaunchKernelGGL(prep_count<ListRows>, dim3(nblocks), dim3(kWG), 0, s, rows, count, blk, nblocks, sc);
+    hipLaunchKernelGGL(prep_scan, dim3(1), dim3(kFinishThreads), 0, s, blk, nblocks, sc);
+    hipLaunchKernelGGL(prep_scatter<ListRows>, dim3(nblocks), dim3(kWG), 0, s, rows, count, (const long long*)blk,
+                       nblocks, desc, segs, huge, sc);
+  } else {
+    const SlackRows rows{off, len};
+    hipLaunchKernelGGL(prep_count<SlackRows>, dim3(nblocks), dim3(kWG), 0, s, rows, count, blk, nblocks, sc);
+    hipLaunchKernelGGL(prep_scan, dim3(1), dim3(kFinishThreads), 0, s, blk, nblocks, sc);
+    hipLaunchKernelGGL(prep_scatter<SlackRows>, dim3(nblocks), dim3(kWG), 0, s, rows, count, (const long long*)blk,
+                       nblocks, desc, segs, huge, sc);
+  }
   return hipGetLastError();
 }
 
@@ -974,9 +944,17 @@ hipError_t launch_walk_first(const IterArgs& a, int fp32, long long n, long long
     const long long nb = std::min<long long>((nnz + kWG - 1) / kWG, 4096);
     hipLaunchKernelGGL(check_col_range, dim3((unsigned)nb), dim3(kWG), 0, s, a.col, nnz, n, a.sc);
   }
-  const unsigned grid = (unsigned)((n + kWG - 1) / kWG);
+  const unsigned grid = (unsigned)std::max<long long>(1, (a.count_first + kWG - 1) / kWG);
   if (fp32) hipLaunchKernelGGL(walk_first<true>, dim3(grid), dim3(kWG), 0, s, a);
   else hipLaunchKernelGGL(walk_first<false>, dim3(grid), dim3(kWG), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_col_range(const int32_t* col, long long nnz, long long n, RunScalars* sc, hipStream_t s) {
+  if (nnz > 0) {
+    const long long nb = std::min<long long>((nnz + kWG - 1) / kWG, 4096);
+    hipLaunchKernelGGL(check_col_range, dim3((unsigned)nb), dim3(kWG), 0, s, col, nnz, n, sc);
+  }
   return hipGetLastError();
 }
 

@@ -202,6 +202,60 @@ def bounds(row_ptr, col, r, *, alpha=0.0, precision="fp64", undirected=True, val
     return lo, up
 
 
+class State:
+    """A dynamic ranking state (katz_state): the graph, the walk history, c_r and
+    M on the device.  ``update`` applies one batch of undirected edge insertions
+    and deletions (Algorithm 2) and returns the re-certified top-k."""
+
+    def __init__(self, handle, k, device):
+        self._h = handle
+        self.k = k
+        self.device = device
+
+    def update(self, ins=None, dels=None, *, stream=None, out=None) -> RankResult:
+        import numpy as np
+        ins = np.asarray(ins if ins is not None else np.zeros((0, 2)), dtype=np.int32).reshape(-1, 2)
+        dels = np.asarray(dels if dels is not None else np.zeros((0, 2)), dtype=np.int32).reshape(-1, 2)
+        iu, iv = np.ascontiguousarray(ins[:, 0]), np.ascontiguousarray(ins[:, 1])
+        du, dv = np.ascontiguousarray(dels[:, 0]), np.ascontiguousarray(dels[:, 1])
+        ids, lo, up = out if out is not None else _alloc_outputs(self.k, self.device)
+        res = KatzResult(topk_ids=ids.data_ptr(), lower=lo.data_ptr(), upper=up.data_ptr())
+        rc = lib.katz_rank_update(ctypes.c_void_p(self._h), iu.ctypes.data, iv.ctypes.data, len(iu),
+                                  du.ctypes.data, dv.ctypes.data, len(du), ctypes.byref(res),
+                                  _stream_handle(stream, self.device))
+        if rc < 0:
+            raise KatzError(rc)
+        return _to_result(res, ids, lo, up)
+
+    def free(self):
+        if self._h:
+            lib.katz_state_free(ctypes.c_void_p(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def create_state(row_ptr, col, k, *, alpha=0.0, eps=0.0, max_iter=0, degree_cap=0, validate=VALIDATE_BASIC,
+                 stream=None):
+    """katz_rank_static with a state: ranks the graph (Algorithm 1, FP64, kept
+    walk history) and returns (State, RankResult) for later updates."""
+    device = row_ptr.device
+    g = make_csr(row_ptr, col, True)
+    p = make_params(k, alpha, eps, "fp64", max_iter, validate, degree_cap)
+    ids, lo, up = _alloc_outputs(k, device)
+    res = KatzResult(topk_ids=ids.data_ptr(), lower=lo.data_ptr(), upper=up.data_ptr())
+    handle = ctypes.c_void_p(0)
+    rc = lib.katz_rank_static(1, ctypes.byref(g), ctypes.byref(p), ctypes.byref(res), ctypes.byref(handle),
+                              _stream_handle(stream, device))
+    if rc < 0:
+        raise KatzError(rc)
+    return State(handle.value, k, device), _to_result(res, ids, lo, up)
+
+
 def timing_enable(on: bool = True) -> None:
     """Reset the library's device-time counters and start (or stop) recording."""
     lib.katz_timing_enable(int(bool(on)))

@@ -1,0 +1,166 @@
+"""GPU parity of dynamic updates (katz_rank_update, Algorithm 2).
+
+Each update is checked three ways: against the oracle's delta-form Algorithm 2
+(parity contract), bitwise against katz_bounds on the updated graph at the same
+r (the re-walk computes exactly what a static run computes), and by the status.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthgraph as sg
+from tests.parity import assert_topk_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def K():
+    import paper_1807_03847_amd.katz as katz
+    return katz
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(rp, col):
+    return torch.from_numpy(np.asarray(rp, dtype=np.int64)).cuda(), torch.from_numpy(np.asarray(col, np.int32)).cuda()
+
+
+def random_batch(rng, rp, col, n, n_ins, n_del, hub_bias=0.0):
+    src = np.repeat(np.arange(n), np.diff(rp))
+    mask = src < col
+    und = np.stack([src[mask], col[mask]], 1)
+    existing = set(map(tuple, und.tolist()))
+    dels = und[rng.choice(len(und), size=min(n_del, len(und)), replace=False)] if n_del else np.zeros((0, 2), int)
+    ins = set()
+    deg = np.diff(rp)
+    hubs = np.argsort(-deg)[:8]
+    while len(ins) < n_ins:
+        a = int(rng.choice(hubs)) if rng.random() < hub_bias else int(rng.integers(0, n))
+        b = int(rng.integers(0, n))
+        a, b = min(a, b), max(a, b)
+        if a != b and (a, b) not in existing:
+            ins.add((a, b))
+    return np.array(sorted(ins), dtype=np.int64).reshape(-1, 2), np.asarray(dels, dtype=np.int64).reshape(-1, 2)
+
+
+def check_against_static(katz, dyn_res, rp_new, col_new, alpha):
+    """Bitwise: the dynamic l_r, u_r of the returned nodes equal katz_bounds on the
+    new graph at the same r."""
+    lo, up = katz.bounds(*dev(rp_new, col_new), dyn_res.iterations, alpha=alpha)
+    ids = dyn_res.topk.long()
+    assert torch.equal(lo[ids], dyn_res.lower)
+    assert torch.equal(up[ids], dyn_res.upper)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_dynamic_er_batches(seed):
+    katz = K()
+    rng = np.random.default_rng(seed)
+    rp, col = sg.erdos_renyi(3000, 15000, 40 + seed)
+    dmax = sg.max_degree(rp)
+    H = 30
+    alpha = 1.0 / (1 + dmax + H)
+    k, eps = 40, 1e-9
+    say("dyn er create", seed)
+    st, res0 = katz.create_state(*dev(rp, col), k, alpha=alpha, eps=eps, degree_cap=dmax + H)
+    dyn = oracle.DynamicOracle(rp, col, alpha, k=k, eps=eps, degree_cap=dmax + H)
+    assert_topk_parity(res0.topk.cpu().numpy(), res0.lower.cpu().numpy(), res0.upper.cpu().numpy(), dyn.result,
+                       gpu_status=res0.status)
+    for b, (ni, nd) in enumerate([(1, 0), (0, 1), (5, 3), (40, 20), (300, 100), (2000, 800)]):
+        ins, dels = random_batch(rng, dyn.row_ptr, dyn.col, 3000, ni, nd)
+        say("dyn er batch", seed, b, ni, nd)
+        res = st.update(ins, dels)
+        orc = dyn.update(ins, dels)
+        assert res.iterations == orc.iterations
+        assert_topk_parity(res.topk.cpu().numpy(), res.lower.cpu().numpy(), res.upper.cpu().numpy(), orc,
+                           gpu_status=res.status)
+        check_against_static(katz, res, dyn.row_ptr, dyn.col, alpha)
+    st.free()
+
+
+def test_dynamic_rmat_hubs_and_relocation():
+    """Skewed graph with segmented hub rows; insertions concentrated on hubs force
+    row relocation in the slack pool; a large batch takes the dense re-walk."""
+    katz = K()
+    rng = np.random.default_rng(7)
+    rp, col = sg.rmat(15, seed=3)
+    n = len(rp) - 1
+    dmax = sg.max_degree(rp)
+    H = 5000
+    alpha = 1.0 / (1 + dmax + H)
+    k, eps = 200, 1e-7
+    say("dyn rmat create")
+    st, res0 = katz.create_state(*dev(rp, col), k, alpha=alpha, eps=eps, degree_cap=dmax + H)
+    cur_rp, cur_col = rp, col
+    for b, (ni, nd, bias) in enumerate([(10, 5, 0.9), (800, 10, 0.8), (3000, 3000, 0.2), (1, 1, 0.0)]):
+        ins, dels = random_batch(rng, cur_rp, cur_col, n, ni, nd, hub_bias=bias)
+        say("dyn rmat batch", b, ni, nd)
+        res = st.update(ins, dels)
+        # New graph on the host.
+        src = np.repeat(np.arange(n), np.diff(cur_rp))
+        keys = set(zip(src.tolist(), cur_col.tolist()))
+        for a, c in dels:
+            keys.discard((a, c))
+            keys.discard((c, a))
+        for a, c in ins:
+            keys.add((a, c))
+            keys.add((c, a))
+        arr = np.array(sorted(keys), dtype=np.int64)
+        cur_rp, cur_col = sg.from_edges(n, arr[:, 0], arr[:, 1], undirected=False)
+        check_against_static(katz, res, cur_rp, cur_col, alpha)
+        orc = oracle.rank_static(cur_rp, cur_col, alpha, k, eps)
+        # The dynamic r never shrinks (it may exceed the static one); compare the
+        # certified rankings through the oracle's tie groups at its own r.
+        assert res.status == orc.status == oracle.OK
+        assert_topk_parity(res.topk.cpu().numpy(), res.lower.cpu().numpy(), res.upper.cpu().numpy(), orc,
+                           check_status=False)
+    st.free()
+
+
+def test_dynamic_rejections_leave_state_unchanged():
+    katz = K()
+    rp, col = sg.erdos_renyi(500, 2000, 9)
+    dmax = sg.max_degree(rp)
+    alpha = 1.0 / (2 + dmax)
+    say("dyn reject create")
+    st, _ = katz.create_state(*dev(rp, col), 10, alpha=alpha, eps=1e-9, degree_cap=dmax + 1)
+    src = np.repeat(np.arange(500), np.diff(rp))
+    e0 = (int(src[0]), int(col[0]))
+    absent = next((a, b) for a in range(500) for b in range(a + 1, 500)
+                  if b not in set(col[rp[a]:rp[a + 1]].tolist()))
+    bad = [([e0], []), ([], [absent]), ([(3, 3)], []), ([(0, 600)], []), ([absent, absent[::-1]], []),
+           ([absent], [absent])]
+    for ins, dels in bad:
+        with pytest.raises(katz.KatzError) as e:
+            st.update(np.array(ins).reshape(-1, 2), np.array(dels).reshape(-1, 2))
+        assert e.value.code == katz.E_UPDATE
+    hub = int(np.argmax(np.diff(rp)))
+    nbrs = set(col[rp[hub]:rp[hub + 1]].tolist())
+    extra = [(min(hub, v), max(hub, v)) for v in range(500) if v != hub and v not in nbrs][:2]
+    with pytest.raises(katz.KatzError) as e:
+        st.update(np.array(extra), None)
+    assert e.value.code == katz.E_DEGREE_CAP
+    # A valid batch still gives the static answer on the updated graph.
+    res = st.update(np.array([absent]), None)
+    dyn = oracle.DynamicOracle(rp, col, alpha, k=10, eps=1e-9, degree_cap=dmax + 1)
+    orc = dyn.update(np.array([absent]), None)
+    assert_topk_parity(res.topk.cpu().numpy(), res.lower.cpu().numpy(), res.upper.cpu().numpy(), orc,
+                       gpu_status=res.status)
+    st.free()
+
+
+def test_empty_batch_is_a_noop():
+    katz = K()
+    rp, col = sg.erdos_renyi(800, 3000, 2)
+    st, r0 = katz.create_state(*dev(rp, col), 15, eps=1e-9)
+    say("dyn empty batch")
+    r1 = st.update(None, None)
+    assert torch.equal(r0.topk, r1.topk) and torch.equal(r0.lower, r1.lower)
+    assert r1.iterations == r0.iterations
+    st.free()
