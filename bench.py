@@ -35,15 +35,15 @@ def algorithmic_bytes_per_walk_step(n, nnz, precision):
     return 4 * nnz + per_node * n
 
 
-def time_form(katz, torch, rp_t, col_t, precision, steps, warmup):
+def time_form(katz, torch, rp_t, col_t, precision, steps, warmup, flags=0):
     for _ in range(warmup):
-        res = katz.rank_static(rp_t, col_t, K, eps=EPS, precision=precision)
+        res = katz.rank_static(rp_t, col_t, K, eps=EPS, precision=precision, flags=flags)
     torch.cuda.synchronize()
     katz.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        res = katz.rank_static(rp_t, col_t, K, eps=EPS, precision=precision)
+        res = katz.rank_static(rp_t, col_t, K, eps=EPS, precision=precision, flags=flags)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     tm = katz.timing_read()
@@ -97,6 +97,11 @@ def main():
                                 gteps=res.iterations * nnz / sec / 1e9)
         print(f"[bench] {precision}: r={res.iterations} status={res.status} {sec * 1e3:.3f} ms/step "
               f"walk_step {walk_avg_ms * 1e3:.1f} us", flush=True)
+
+    # The same FP32 run without the internal renumbering, for context.
+    res_nr, sec_nr, tm_nr = time_form(katz, torch, rp_t, col_t, "fp32", max(1, args.steps // 2), 1,
+                                      flags=katz.FLAG_NO_REORDER)
+    print(f"[bench] fp32 caller order: {sec_nr * 1e3:.3f} ms/step", flush=True)
 
     f32, f64 = forms["fp32"], forms["fp64"]
     bytes_step = algorithmic_bytes_per_walk_step(n, nnz, "fp32")
@@ -153,6 +158,11 @@ def main():
         },
     }
 
+    out["fp32_caller_order"] = {
+        "ms_per_step": round(sec_nr * 1e3, 4),
+        "walk_step_avg_us": round(tm_nr["walk_step_ms"] / max(tm_nr["walk_step_launches"], 1) * 1e3, 2),
+        "same_result": bool(torch.equal(res_nr.topk, f32["res"].topk) and torch.equal(res_nr.lower, f32["res"].lower)),
+    }
     same = bool(torch.equal(f32["res"].topk, f64["res"].topk))
     out["fp32_fp64_same_topk"] = same
 

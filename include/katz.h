@@ -81,6 +81,14 @@ extern "C" {
 #define KATZ_VALIDATE_STRICT  2  /* BASIC + rows strictly increasing (no duplicates),   */
                                  /* no self-loops, and symmetry when undirected = 1     */
 
+/* ---- option flags (katz_params.flags) --------------------------------------- */
+#define KATZ_FLAG_NO_REORDER  1  /* keep the caller's node order on the device.  By     */
+                                 /* default static calls renumber nodes internally by   */
+                                 /* degree class (rows of similar length contiguous,    */
+                                 /* high-degree nodes first) so the walk vector's most  */
+                                 /* gathered entries share cache lines; results, ids    */
+                                 /* and tie order are the same either way.              */
+
 /* A graph in compressed sparse row form.  Row v lists the out-neighbours of v:
  * arcs v -> col[j] for row_ptr[v] <= j < row_ptr[v+1].  An undirected graph
  * stores both arcs of each edge (Section 2.1) and sets undirected = 1, which
@@ -105,7 +113,7 @@ typedef struct katz_params {
   int32_t precision;      /* KATZ_FP64 or KATZ_FP32_MARGIN                          */
   int32_t criterion;      /* KATZ_TOPK                                              */
   int32_t validate;       /* KATZ_VALIDATE_*; applies to the input CSR              */
-  int32_t reserved;       /* must be 0                                              */
+  int32_t flags;          /* KATZ_FLAG_* bits; 0 = defaults                         */
   int64_t degree_cap;     /* states only: the largest deg_max that edge insertions  */
                           /* may create; 0 = the initial deg_max.  alpha must obey  */
                           /* alpha * degree_cap < 1.                                */

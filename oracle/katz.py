@@ -321,8 +321,8 @@ class DynamicOracle:
 
     # -- Algorithm 2 ---------------------------------------------------------
     def update(self, ins_pairs, del_pairs):
-        ins = np.asarray(ins_pairs, dtype=np.int64).reshape(-1, 2)
-        dels = np.asarray(del_pairs, dtype=np.int64).reshape(-1, 2)
+        ins = np.asarray(ins_pairs if ins_pairs is not None else [], dtype=np.int64).reshape(-1, 2)
+        dels = np.asarray(del_pairs if del_pairs is not None else [], dtype=np.int64).reshape(-1, 2)
         arcs_I, arcs_D, keys_E, kdl, new_rp, new_col = self._validate_batch(ins, dels)
         n, alpha = self.n, self.alpha
 

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <climits>
 #include <limits>
 #include <mutex>
 #include <numeric>
@@ -244,7 +245,8 @@ int check_graph(const katz_csr* g) {
 int check_params(const katz_params* p, long long n, bool need_k) {
   if (!p) return KATZ_E_INVALID_ARG;
   if (p->precision != KATZ_FP64 && p->precision != KATZ_FP32_MARGIN) return KATZ_E_INVALID_ARG;
-  if (p->validate < 0 || p->validate > 2 || p->reserved != 0 || p->max_iter < 0) return KATZ_E_INVALID_ARG;
+  if (p->validate < 0 || p->validate > 2 || (p->flags & ~KATZ_FLAG_NO_REORDER) || p->max_iter < 0)
+    return KATZ_E_INVALID_ARG;
   if (p->degree_cap < 0) return KATZ_E_INVALID_ARG;
   if (std::isnan(p->alpha) || p->alpha < 0.0 || std::isinf(p->alpha)) return KATZ_E_ALPHA;
   if (need_k) {
@@ -297,6 +299,7 @@ struct Work {
   double* c = nullptr;
   float* e = nullptr;
   void* partial = nullptr;
+  void* blkmax = nullptr;          // per-workgroup maxima of one walk launch
   int32_t* act[2] = {nullptr, nullptr};
   unsigned long long* keys = nullptr;
   unsigned long long* cand_key[2] = {nullptr, nullptr};
@@ -467,6 +470,8 @@ struct Run {
   Bins* bins = nullptr;
   Work* w = nullptr;
   katz_state* st = nullptr;   // history mode when set (FP64 only)
+  const int32_t* ext_of = nullptr;   // internal -> caller id (nullptr: identity)
+  const int32_t* int_of = nullptr;
   Scalars* S = nullptr;
   double eps = 0;
   int k = 1;
@@ -510,6 +515,7 @@ IterArgs iter_args(const Run& run, const Bins& b, int r, bool rewalk, long long&
   ia.c = run.w->c;
   ia.e = run.w->e;
   ia.partial = run.w->partial;
+  ia.blkmax = run.w->blkmax;
   ia.xmax32 = run.w->xmax32;
   ia.xmax64 = run.w->xmax64;
   ia.sigma = run.w->sigma;
@@ -578,6 +584,8 @@ SelArgs sel_args(const Run& run, int r) {
   sa.xmax64 = run.w->xmax64;
   sa.sc = run.w->sc;
   sa.identity_in = run.first_select ? 1 : 0;
+  sa.ext_of = run.ext_of;
+  sa.int_of = run.int_of;
   sa.k = run.k;
   sa.n = (int)run.n;
   sa.max_iter = run.max_iter;
@@ -593,13 +601,42 @@ int enqueue_walk(Run& run, int r, hipStream_t s, CallTimer& T) {
   if (r == 1) KATZ_HIP(launch_walk_first(ia, run.fp32, run.n, run.nnz, run.validate >= KATZ_VALIDATE_BASIC, s));
   else KATZ_HIP(launch_walk_step(ia, run.fp32, tb, s));
   T.stop(tw, s);
+  const long long nb = r == 1 ? std::max<long long>(1, (run.bins->count + kWG - 1) / kWG) : std::max(tb, 1ll);
+  KATZ_HIP(launch_reduce_blkmax(run.w->blkmax, nb, run.fp32, run.w->xmax32, run.w->xmax64, r, run.w->sc, s));
   return KATZ_OK;
 }
 
-int enqueue_select(Run& run, int r, hipStream_t s, CallTimer& T) {
-  const SelArgs sa = sel_args(run, r);
+// small_m: the active set is known to hold at most kSmallActive nodes, so one
+// workgroup runs the whole of converged().
+int enqueue_select(Run& run, int r, hipStream_t s, CallTimer& T, bool small_m) {
   const int ts = T.start(T_SELECT, s);
-  KATZ_HIP(launch_select_iteration(sa, run.grid, s));
+  if (small_m) {
+    GraphSel gs{};
+    gs.b = bound_args(run, r);
+    gs.act[0] = run.w->act[0];
+    gs.act[1] = run.w->act[1];
+    gs.keys = run.w->keys;
+    gs.cand_key = run.w->cand_key[0];
+    gs.cand_v = run.w->cand_v[0];
+    gs.top_sorted = run.w->top_sorted;
+    gs.top_lo = run.w->top_lo;
+    gs.top_up = run.w->top_up;
+    gs.sc = run.w->sc;
+    gs.xmax32 = run.w->xmax32;
+    gs.xmax64 = run.w->xmax64;
+    gs.base = 0;
+    gs.n = (int)run.n;
+    gs.k = run.k;
+    gs.max_iter = run.max_iter;
+    gs.identity_in = run.first_select ? 1 : 0;
+    gs.cur = run.cur;
+    gs.ext_of = run.ext_of;
+    gs.int_of = run.int_of;
+    KATZ_HIP(launch_select_wg_one(gs, s));
+  } else {
+    const SelArgs sa = sel_args(run, r);
+    KATZ_HIP(launch_select_iteration(sa, run.grid, s));
+  }
   T.stop(ts, s);
   run.cur ^= 1;
   run.first_select = false;
@@ -615,13 +652,17 @@ int iterate(Run& run, HostSync& hs, int r_next, bool check_first, hipStream_t s,
   bool stopped = false;
   int pass = 0;
   int r = r_next;
+  // Upper bound of |M| from the latest flags read back; M never grows inside
+  // this loop, so a bound read one pass behind stays valid.
+  long long m_known = check_first ? LLONG_MAX : run.n;
   while (!stopped) {
+    const bool small_m = m_known <= kSmallActive;
     if (pass == 0 && check_first) {
-      KATZ_TRY(enqueue_select(run, r - 1, s, T));
+      KATZ_TRY(enqueue_select(run, r - 1, s, T, false));
     } else if (r <= run.max_iter) {
       if (run.st) KATZ_TRY(ensure_levels(run.st, r));
       KATZ_TRY(enqueue_walk(run, r, s, T));
-      KATZ_TRY(enqueue_select(run, r, s, T));
+      KATZ_TRY(enqueue_select(run, r, s, T, small_m));
       ++r;
     } else {
       break;
@@ -632,6 +673,7 @@ int iterate(Run& run, HostSync& hs, int r_next, bool check_first, hipStream_t s,
       KATZ_HIP(hipEventSynchronize(hs.ev[(pass - 1) & 1]));
       const RunScalars& prev = hs.ring[(pass - 1) & 1];
       if (prev.err || prev.done) stopped = true;
+      m_known = prev.m;
     }
     ++pass;
   }
@@ -655,6 +697,8 @@ int write_result(Run& run, HostSync& hs, katz_result* out, int32_t* stage_ids, d
   fa.top_sorted = run.w->top_sorted;
   fa.top_lo = run.w->top_lo;
   fa.top_up = run.w->top_up;
+  fa.ext_of = run.ext_of;
+  fa.int_of = run.int_of;
   fa.k = run.k;
   fa.n = (int)run.n;
   int32_t* ids = direct ? out->topk_ids : stage_ids;
@@ -694,12 +738,22 @@ struct Plan {
   int max_iter;
   int validate;
   bool rp_host, col_host, out_host, select;
+  bool reorder;   // renumber nodes by degree class (internal)
   size_t out_n;   // elements per output array (k for ranking, n for bounds)
 };
 
 struct Staging {
   const void* row_ptr = nullptr;
   const int32_t* col = nullptr;
+  // Internal renumbering (Plan::reorder).
+  int32_t* ncol = nullptr;
+  long long* noff = nullptr;
+  long long* len_ll = nullptr;
+  int* len32 = nullptr;
+  int32_t* ext_of = nullptr;
+  int32_t* int_of = nullptr;
+  long long* sums = nullptr;
+  long long* total = nullptr;
   long long* row_off = nullptr;   // strict symmetry check
   int* row_len = nullptr;
   int32_t* out_ids = nullptr;
@@ -712,7 +766,7 @@ void layout(Arena& ar, const Plan& pl, Bins& b, Work& w, Staging& stg) {
   ar.used = 0;
   bins_caps(b, n, nnz);
   w.sc = ar.take<RunScalars>(1);
-  b.blk = ar.take<long long>((size_t)(NUM_BINS + 1) * b.nblocks);
+  b.blk = ar.take<long long>((size_t)(NUM_BINS + 2) * b.nblocks);
   b.desc = ar.take<RowDesc>(n);
   b.segs = ar.take<SegDesc>(b.seg_cap);
   b.huge = ar.take<HugeRow>(b.huge_cap);
@@ -723,12 +777,23 @@ void layout(Arena& ar, const Plan& pl, Bins& b, Work& w, Staging& stg) {
     stg.row_off = ar.take<long long>(n);
     stg.row_len = ar.take<int>(n);
   }
+  if (pl.reorder) {
+    stg.ncol = ar.take<int32_t>(std::max<long long>(nnz, 1));
+    stg.noff = ar.take<long long>(n);
+    stg.len_ll = ar.take<long long>(n);
+    stg.len32 = ar.take<int>(n);
+    stg.ext_of = ar.take<int32_t>(n);
+    stg.int_of = ar.take<int32_t>(n);
+    stg.sums = ar.take<long long>(scan_sums_capacity(n));
+    stg.total = ar.take<long long>(1);
+  }
   const size_t xs = pl.fp32 ? 4 : 8;
   w.x[0] = ar.take<char>(n * xs);
   w.x[1] = ar.take<char>(n * xs);
   w.c = ar.take<double>(n);
   if (pl.fp32) w.e = ar.take<float>(n);
   w.partial = ar.take<char>(b.seg_cap * xs);
+  w.blkmax = ar.take<double>(n + b.seg_cap + 1);
   w.xmax32 = ar.take<unsigned>(pl.max_iter + 1);
   w.xmax64 = ar.take<unsigned long long>(pl.max_iter + 1);
   w.sigma = ar.take<double>(pl.max_iter + 1);
@@ -783,6 +848,7 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
   KATZ_HIP(launch_prep_count(stg.row_ptr, g->row_ptr_64, g->n, g->nnz, b.blk, b.nblocks, w.sc, s));
   KATZ_HIP(launch_prep_scan(b.blk, b.nblocks, w.sc, s));
   KATZ_HIP(launch_prep_scatter(stg.row_ptr, g->row_ptr_64, g->n, b.blk, b.nblocks, b.desc, b.segs, b.huge, w.sc, s));
+  if (pl.validate >= KATZ_VALIDATE_BASIC) KATZ_HIP(launch_check_col_range(stg.col, g->nnz, g->n, w.sc, s));
   KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
   KATZ_HIP(hipStreamSynchronize(s));
   if (hs.sc->err) return KATZ_E_CSR;
@@ -792,6 +858,19 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
     KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
     KATZ_HIP(hipStreamSynchronize(s));
     if (hs.sc->err) return KATZ_E_CSR;
+  }
+  if (pl.reorder) {
+    // Renumber by the binned order and rebuild the bins on the renumbered rows
+    // (now contiguous per bin).  Column ids were range-checked above.
+    KATZ_HIP(launch_relabel(b.desc, g->n, stg.col, stg.ext_of, stg.int_of, stg.len_ll, stg.len32, stg.noff,
+                            stg.sums, stg.total, stg.ncol, s));
+    KATZ_HIP(hipMemsetAsync(b.seg_done, 0, sizeof(int) * b.huge_cap, s));
+    KATZ_HIP(launch_prep_rows(nullptr, g->n, stg.noff, stg.len32, b.blk, b.nblocks, b.desc, b.segs, b.huge, w.sc,
+                              s));
+    KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipStreamSynchronize(s));
+    if (hs.sc->err) return KATZ_E_HIP;
+    b.read_back(*hs.sc, g->n);
   }
   return KATZ_OK;
 }
@@ -815,6 +894,7 @@ int rank_one(const katz_csr* g, const katz_params* p, katz_result* out, hipStrea
   pl.col_host = g->nnz > 0 && !is_device_ptr(g->col);
   pl.out_host = !(is_device_ptr(out->topk_ids) && is_device_ptr(out->lower) && is_device_ptr(out->upper));
   pl.select = true;
+  pl.reorder = !(p->flags & KATZ_FLAG_NO_REORDER);
   pl.out_n = (size_t)p->k;
 
   Bins b;
@@ -837,8 +917,10 @@ int rank_one(const katz_csr* g, const katz_params* p, katz_result* out, hipStrea
   run.nnz = g->nnz;
   run.undirected = g->undirected;
   run.fp32 = pl.fp32;
-  run.validate = pl.validate;
-  run.col = stg.col;
+  run.validate = KATZ_VALIDATE_NONE;   // columns were checked in prepare()
+  run.col = pl.reorder ? stg.ncol : stg.col;
+  run.ext_of = pl.reorder ? stg.ext_of : nullptr;
+  run.int_of = pl.reorder ? stg.int_of : nullptr;
   run.bins = &b;
   run.w = &w;
   run.S = &S;
@@ -870,6 +952,7 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   const bool lo_dev = is_device_ptr(lower), up_dev = is_device_ptr(upper);
   pl.out_host = !(lo_dev && up_dev);
   pl.select = false;
+  pl.reorder = !(p->flags & KATZ_FLAG_NO_REORDER);
   pl.out_n = (size_t)g->n;
   Bins b;
   Work w;
@@ -884,8 +967,10 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   run.nnz = g->nnz;
   run.undirected = g->undirected;
   run.fp32 = pl.fp32;
-  run.validate = pl.validate;
-  run.col = stg.col;
+  run.validate = KATZ_VALIDATE_NONE;   // columns were checked in prepare()
+  run.col = pl.reorder ? stg.ncol : stg.col;
+  run.ext_of = pl.reorder ? stg.ext_of : nullptr;
+  run.int_of = pl.reorder ? stg.int_of : nullptr;
   run.bins = &b;
   run.w = &w;
   run.S = &S;
@@ -897,7 +982,7 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   const BoundArgs bd = bound_args(run, r_target);
   double* lo = pl.out_host ? stg.out_lo : lower;
   double* up = pl.out_host ? stg.out_up : upper;
-  KATZ_HIP(launch_all_bounds(bd, g->n, nullptr, lo, up, s));
+  KATZ_HIP(launch_all_bounds(bd, g->n, run.ext_of, lo, up, s));
   if (pl.out_host) {
     KATZ_HIP(hipMemcpyAsync(lower, lo, sizeof(double) * g->n, hipMemcpyDefault, s));
     KATZ_HIP(hipMemcpyAsync(upper, up, sizeof(double) * g->n, hipMemcpyDefault, s));
@@ -956,7 +1041,7 @@ int alloc_bins(katz_state* st, Bins& b) {
   b.segs = dalloc<SegDesc>(st, b.seg_cap);
   b.huge = dalloc<HugeRow>(st, b.huge_cap);
   b.seg_done = dalloc<int>(st, b.huge_cap);
-  b.blk = dalloc<long long>(st, (size_t)(NUM_BINS + 1) * b.nblocks);
+  b.blk = dalloc<long long>(st, (size_t)(NUM_BINS + 2) * b.nblocks);
   if (!b.desc || !b.segs || !b.huge || !b.seg_done || !b.blk) return KATZ_E_OOM;
   KATZ_HIP(hipMemset(b.seg_done, 0, sizeof(int) * b.huge_cap));
   return KATZ_OK;
@@ -964,8 +1049,10 @@ int alloc_bins(katz_state* st, Bins& b) {
 
 int alloc_partial(katz_state* st) {
   if (st->w.partial) dfree(st, st->w.partial);
+  if (st->w.blkmax) dfree(st, st->w.blkmax);
   st->w.partial = dalloc<double>(st, st->bins.seg_cap);
-  return st->w.partial ? KATZ_OK : KATZ_E_OOM;
+  st->w.blkmax = dalloc<double>(st, st->n + st->bins.seg_cap + 1);
+  return st->w.partial && st->w.blkmax ? KATZ_OK : KATZ_E_OOM;
 }
 
 // Bins the rows `ids[0..count)` (or every row when ids is null) of the slack CSR.
@@ -1052,7 +1139,7 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
   {
     Bins tmp;
     bins_caps(tmp, n, g->nnz);
-    long long* blk = dalloc<long long>(st, (size_t)(NUM_BINS + 1) * tmp.nblocks);
+    long long* blk = dalloc<long long>(st, (size_t)(NUM_BINS + 2) * tmp.nblocks);
     if (!blk) return KATZ_E_OOM;
     KATZ_HIP(launch_reset_flags(st->w.sc, s));
     KATZ_HIP(launch_prep_count(rp, g->row_ptr_64, n, g->nnz, blk, tmp.nblocks, st->w.sc, s));
@@ -1377,6 +1464,9 @@ int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, lon
     st->bins.dmax = new_dmax;
 
     // ---- re-walk levels 1..r over the affected set (Algorithm 2) ----
+    // The walk kernels return at once while the run's stop flag is set; the
+    // previous run left it set.
+    KATZ_HIP(launch_reset_flags(st->w.sc, s));
     const long long dense_at = std::max<long long>(1, n / 4);
     KATZ_HIP(hipMemcpyAsync(st->clist, ub.rows, sizeof(int32_t) * t, hipMemcpyDeviceToDevice, s));
     KATZ_HIP(launch_set_levels(ub.rows, t, st->level_of, 1, s));

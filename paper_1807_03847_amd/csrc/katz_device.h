@@ -126,4 +126,103 @@ __device__ inline void block_exclusive_scan_ll(long long* a, long long len, long
 }
 
 
+// Inside one 1024-thread block: the bucket of hist[0..nb) (nb <= 4096) that holds
+// rank `need` (1-based), counting from the largest bucket (desc) or the
+// smallest.  Thread t owns positions 4t..4t+3 of that order.
+struct Bucket {
+  int b;
+  int need;   // rank inside the bucket
+  int count;  // items in the bucket
+};
+
+__device__ inline Bucket find_bucket(const unsigned* h, int nb, int need, bool desc) {
+  __shared__ long long wsum[kFinishThreads / kWave];
+  __shared__ Bucket res;
+  const int t = threadIdx.x;
+  const int lane = lane_id();
+  const int w = t / kWave;
+  unsigned loc[4];
+  long long tot = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int pos = 4 * t + j;
+    const int bin = desc ? nb - 1 - pos : pos;
+    loc[j] = (pos < nb) ? h[bin] : 0u;
+    tot += loc[j];
+  }
+  long long inc = tot;
+  for (int o = 1; o < kWave; o <<= 1) {
+    long long y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == kWave - 1) wsum[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    long long ws = lane < kFinishThreads / kWave ? wsum[lane] : 0;
+    long long wi = ws;
+    for (int o = 1; o < kWave; o <<= 1) {
+      long long y = __shfl_up(wi, o);
+      if (lane >= o) wi += y;
+    }
+    if (lane < kFinishThreads / kWave) wsum[lane] = wi - ws;
+  }
+  __syncthreads();
+  long long cum = wsum[w] + inc - tot;   // items before this thread's positions
+  if (cum < need && need <= cum + tot) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (need <= cum + (long long)loc[j]) {
+        const int pos = 4 * t + j;
+        res.b = desc ? nb - 1 - pos : pos;
+        res.need = (int)(need - cum);
+        res.count = (int)loc[j];
+        break;
+      }
+      cum += loc[j];
+    }
+  }
+  __syncthreads();
+  const Bucket r = res;
+  __syncthreads();
+  return r;
+}
+
+// Exclusive scan of one int per thread over a 256-thread workgroup; returns the
+// thread's prefix and writes the total to *total (all threads).
+__device__ inline int block_scan_256(int x, int* total) {
+  __shared__ int ws[kWG / kWave];
+  const int lane = lane_id();
+  const int w = threadIdx.x / kWave;
+  int inc = x;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == kWave - 1) ws[w] = inc;
+  __syncthreads();
+  int before = 0, all = 0;
+  for (int i = 0; i < kWG / kWave; ++i) {
+    if (i < w) before += ws[i];
+    all += ws[i];
+  }
+  __syncthreads();
+  *total = all;
+  return before + inc - x;
+}
+
+// Appends for a group of 256 x IPT items (IPT per thread): bit j of `mask` flags
+// the thread's j-th item.  One atomic per workgroup reserves the group's slots;
+// returns the thread's first slot (its flagged items take consecutive slots).
+// Every thread of the workgroup must call it.
+__device__ inline int block_reserve(int* counter, unsigned mask) {
+  __shared__ int s_base;
+  int total = 0;
+  const int ex = block_scan_256(__popc(mask), &total);
+  if (threadIdx.x == 0) s_base = total > 0 ? atomicAdd(counter, total) : 0;
+  __syncthreads();
+  const int base = s_base;
+  __syncthreads();
+  return base + ex;
+}
+
 }  // namespace katz

@@ -139,8 +139,11 @@ __global__ void __launch_bounds__(kWG) max_len_after(const int* row_len, const u
     if (!mark[v]) m = max(m, row_len[v]);
   for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < t; i += (long long)gridDim.x * kWG)
     m = max(m, (int)new_len[i]);
+  __shared__ int wm[kWG / kWave];
   for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o));
-  if (lane_id() == 0) atomicMax(out, m);
+  if (lane_id() == 0) wm[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(out, max(max(wm[0], wm[1]), max(wm[2], wm[3])));
 }
 
 __global__ void __launch_bounds__(kWG) unmark_rows(const int32_t* rows, long long t, uint8_t* mark) {
@@ -245,8 +248,12 @@ __global__ void __launch_bounds__(kWG) max_of_vector(const double* x, long long 
   double m = 0.0;
   for (long long v = (long long)blockIdx.x * kWG + threadIdx.x; v < n; v += (long long)gridDim.x * kWG)
     m = fmax(m, x[v]);
+  __shared__ double wm[kWG / kWave];
   for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-  if (lane_id() == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  if (lane_id() == 0) wm[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(out, (unsigned long long)__double_as_longlong(fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]))));
 }
 
 // min over the active list of the lower bound (as non-negative IEEE bits).
@@ -261,22 +268,29 @@ __global__ void __launch_bounds__(kWG) min_lower_active(BoundArgs b, const int32
     best = min(best, key_of(lo));
     mark[v] = 1;
   }
+  __shared__ unsigned long long wm[kWG / kWave];
   for (int o = 32; o >= 1; o >>= 1) {
     const unsigned long long y = __shfl_xor(best, o);
     best = min(best, y);
   }
-  if (lane_id() == 0) atomicMin(out, best);
+  if (lane_id() == 0) wm[threadIdx.x / kWave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMin(out, min(min(wm[0], wm[1]), min(wm[2], wm[3])));
 }
 
 // Reactivation (Algorithm 2): M <- M u {w : u(w) >= min_{x in M} l(x) - eps}.
 __global__ void __launch_bounds__(kWG) reactivate(BoundArgs b, long long n, const unsigned long long* min_bits,
                                                   uint8_t* mark, int32_t* out, int* count) {
   const double thr = __longlong_as_double((long long)*min_bits) - b.eps;
-  const long long stride = (long long)gridDim.x * kWG;
-  for (long long base = (long long)blockIdx.x * kWG; base < n; base += stride) {
-    const long long v = base + threadIdx.x;
-    bool keep = false;
-    if (v < n) {
+  constexpr int IPT = 8;
+  const long long group = (long long)kWG * IPT;
+  for (long long g0 = (long long)blockIdx.x * group; g0 < n; g0 += (long long)gridDim.x * group) {
+    unsigned mask = 0;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      const long long v = g0 + (long long)j * kWG + threadIdx.x;
+      if (v >= n) continue;
+      bool keep;
       if (mark[v]) {
         keep = true;
         mark[v] = 0;
@@ -285,9 +299,12 @@ __global__ void __launch_bounds__(kWG) reactivate(BoundArgs b, long long n, cons
         bound_eval(b, (int)v, lo, up);
         keep = up >= thr;
       }
+      if (keep) mask |= 1u << j;
     }
-    const int pos = wave_append(count, keep);
-    if (keep) out[pos] = (int)v;
+    int pos = block_reserve(count, mask);
+#pragma unroll
+    for (int j = 0; j < IPT; ++j)
+      if (mask >> j & 1u) out[pos++] = (int)(g0 + (long long)j * kWG + threadIdx.x);
   }
 }
 
@@ -362,7 +379,7 @@ hipError_t launch_touched_lengths(const int32_t* rows, long long t, const int* d
 
 hipError_t launch_max_len_after(const int* row_len, const uint8_t* mark, long long n, const long long* new_len,
                                 long long t, int* out, hipStream_t s) {
-  const unsigned nb = (unsigned)std::min<long long>(blocks_for(n), 2048);
+  const unsigned nb = (unsigned)std::min<long long>(blocks_for(n), 512);
   hipLaunchKernelGGL(max_len_after, dim3(nb), dim3(kWG), 0, s, row_len, mark, n, new_len, t, out);
   return hipGetLastError();
 }
@@ -417,14 +434,14 @@ hipError_t launch_c_from_history(const int32_t* rows, long long count, double* c
 }
 
 hipError_t launch_max_of_vector(const double* x, long long n, unsigned long long* out, hipStream_t s) {
-  const unsigned nb = (unsigned)std::min<long long>(blocks_for(n), 2048);
+  const unsigned nb = (unsigned)std::min<long long>(blocks_for(n), 512);
   hipLaunchKernelGGL(max_of_vector, dim3(nb), dim3(kWG), 0, s, x, n, out);
   return hipGetLastError();
 }
 
 hipError_t launch_min_lower_active(const BoundArgs& b, const int32_t* act, const int* m_ptr,
                                    unsigned long long* min_bits, uint8_t* mark, long long n, hipStream_t s) {
-  const unsigned nb = (unsigned)std::min<long long>(blocks_for(n), 2048);
+  const unsigned nb = (unsigned)std::min<long long>(blocks_for(n), 512);
   hipLaunchKernelGGL(min_lower_active, dim3(nb), dim3(kWG), 0, s, b, act, m_ptr, min_bits, mark);
   return hipGetLastError();
 }

@@ -127,6 +127,7 @@ struct IterArgs {
   double* c;
   float* e;
   void* partial;
+  void* blkmax;                  // per-workgroup maximum of the new walk entries
   int* seg_done;                 // [n_huge] segments finished this iteration
   unsigned* xmax32;              // [max_iter + 1] float bits of max x~_r
   unsigned long long* xmax64;    // [max_iter + 1] double bits of max s_r
@@ -167,6 +168,32 @@ struct SelArgs {
   int pad;
 };
 
+// One graph's view for the one-workgroup selection (select_wg): every array
+// points at the graph's own region; node ids are global (base .. base + n).
+struct GraphSel {
+  BoundArgs b;                   // with a device iteration counter, r and x are refreshed
+  const void* xbuf[2];           // walk vector buffers by parity of r (device-counter mode)
+  const double* etap;            // FP32 form: eta'_r table (device-counter mode)
+  const int32_t* act[2];         // active-list buffers of this graph
+  unsigned long long* keys;
+  unsigned long long* cand_key;
+  int32_t* cand_v;
+  int32_t* top_sorted;
+  double* top_lo;
+  double* top_up;
+  RunScalars* sc;
+  const unsigned* xmax32;        // indexed by r
+  const unsigned long long* xmax64;
+  const int32_t* ext_of;         // internal -> caller id (nullptr: identity); ties go by caller id
+  const int32_t* int_of;         // caller id -> internal id
+  int base;
+  int n;
+  int k;
+  int max_iter;
+  int identity_in;               // the active list is base .. base + n - 1
+  int cur;                       // host-driven mode: buffer holding M (act[cur])
+};
+
 // ---- launchers (katz_kernels.hip) ----------------------------------------
 hipError_t launch_prep_count(const void* row_ptr, int row_ptr_64, int64_t n, int64_t nnz,
                              long long* blk, int nblocks, RunScalars* sc, hipStream_t s);
@@ -179,6 +206,9 @@ hipError_t launch_validate_strict(const RowDesc* desc, long long n, const int32_
 hipError_t launch_walk_first(const IterArgs& a, int fp32, long long n, long long nnz, int validate,
                              hipStream_t s);
 hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, hipStream_t s);
+// Reduces the per-workgroup maxima of walk iteration r into xmax32[r] / xmax64[r].
+hipError_t launch_reduce_blkmax(const void* blkmax, long long nb, int fp32, unsigned* xmax32,
+                                unsigned long long* xmax64, int r, const RunScalars* sc, hipStream_t s);
 hipError_t launch_check_col_range(const int32_t* col, long long nnz, long long n, RunScalars* sc, hipStream_t s);
 hipError_t launch_select_iteration(const SelArgs& a, int grid, hipStream_t s);
 hipError_t launch_write_result(const SelArgs& a, uint8_t* mark, int32_t* out_ids, double* out_lo,
@@ -226,12 +256,19 @@ hipError_t launch_c_from_history(const int32_t* rows, long long count, double* c
 hipError_t launch_max_of_vector(const double* x, long long n, unsigned long long* out, hipStream_t s);
 
 hipError_t launch_reset_flags(RunScalars* sc, hipStream_t s);
+hipError_t launch_relabel(const RowDesc* desc, long long n, const int32_t* col, int32_t* ext_of, int32_t* int_of,
+                          long long* len_ll, int* len32, long long* noff, long long* sums, long long* total,
+                          int32_t* ncol, hipStream_t s);
 hipError_t launch_gather_int(const int32_t* rows, long long t, const int* src, int* out, hipStream_t s);
 hipError_t launch_gather_ll(const int32_t* rows, long long t, const long long* src, long long* out, hipStream_t s);
 hipError_t launch_min_lower_active(const BoundArgs& b, const int32_t* act, const int* m_ptr,
                                    unsigned long long* min_bits, uint8_t* mark, long long n, hipStream_t s);
 hipError_t launch_reactivate_all(const BoundArgs& b, long long n, const unsigned long long* min_bits,
                                  uint8_t* mark, int32_t* out, int* count, hipStream_t s);
+
+hipError_t launch_select_wg(const GraphSel* gsel, int count, const int* r_dev, hipStream_t s);
+hipError_t launch_select_wg_one(const GraphSel& one, hipStream_t s);
+constexpr int kSmallActive = 1 << 16;   // |M| at or below which one workgroup selects
 
 int bin_of_host(int64_t len);
 

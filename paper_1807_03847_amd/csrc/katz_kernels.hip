@@ -99,11 +99,15 @@ __global__ void __launch_bounds__(kWG) prep_count(Rows rows, long long count, lo
   if constexpr (Rows::kCsr) {
     if (i == 0 && ((long long)rows.rp[0] != 0 || (long long)rows.rp[count] != rows.nnz)) bad = true;
   }
+  __shared__ int wmax[kWG / kWave];
   for (int o = 32; o >= 1; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o));
-  if (lane_id() == 0 && dmax > 0) atomicMax(&sc->dmax, dmax);
+  if (lane_id() == 0) wmax[threadIdx.x / kWave] = dmax;
   if (bad) atomicOr(&sc->err, 1);
   __syncthreads();
   if (threadIdx.x <= NUM_BINS) blk[(long long)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+  // Column NUM_BINS + 1: the block's longest row (reduced by prep_scan).
+  if (threadIdx.x == 0)
+    blk[(long long)(NUM_BINS + 1) * nblocks + blockIdx.x] = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
 }
 
 __global__ void __launch_bounds__(kFinishThreads) prep_scan(long long* blk, int nblocks, RunScalars* sc) {
@@ -119,6 +123,14 @@ __global__ void __launch_bounds__(kFinishThreads) prep_scan(long long* blk, int 
     for (long long i = threadIdx.x; i < nblocks; i += kFinishThreads) part += blk[(long long)b * nblocks + i];
     for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o);
     if (lane_id() == 0) atomicAdd((unsigned long long*)&firsts[b], (unsigned long long)part);
+  }
+  // Longest row: maximum of the per-block column.
+  {
+    long long dm = 0;
+    for (long long i = threadIdx.x; i < nblocks; i += kFinishThreads)
+      dm = max(dm, blk[(long long)(NUM_BINS + 1) * nblocks + i]);
+    for (int o = 32; o >= 1; o >>= 1) dm = max(dm, __shfl_xor(dm, o));
+    if (lane_id() == 0) atomicMax(&sc->dmax, (int)dm);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -334,6 +346,21 @@ __device__ __forceinline__ typename Prec<F32>::T block_sum(const IterArgs& a, co
   return tot;
 }
 
+// Per-workgroup maximum of the new walk entries, stored without atomics (a
+// one-block kernel reduces the array afterwards).  All threads must call it.
+template <bool F32>
+__device__ __forceinline__ void store_block_max(const IterArgs& a, double vmax) {
+  __shared__ double wm[kWG / kWave];
+  for (int o = 32; o >= 1; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
+  if (lane_id() == 0) wm[threadIdx.x / kWave] = vmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
+    if constexpr (F32) reinterpret_cast<float*>(a.blkmax)[blockIdx.x] = (float)m;
+    else reinterpret_cast<double*>(a.blkmax)[blockIdx.x] = m;
+  }
+}
+
 // First walk step: x_0 = 1, so the sum over row v is its length, exactly.
 template <bool F32>
 __global__ void __launch_bounds__(kWG) walk_first(IterArgs a) {
@@ -351,11 +378,7 @@ __global__ void __launch_bounds__(kWG) walk_first(IterArgs a) {
     const RowDesc d = a.desc[i];
     epilogue<F32>(a, ep, d.row, (typename Prec<F32>::T)d.len, vmax);
   }
-  for (int o = 32; o >= 1; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
-  if (lane_id() == 0 && vmax > 0.0) {
-    if constexpr (F32) atomicMax(&a.xmax32[1], __float_as_uint((float)vmax));
-    else atomicMax(&a.xmax64[1], (unsigned long long)__double_as_longlong(vmax));
-  }
+  store_block_max<F32>(a, vmax);
 }
 
 // 0 <= col < n for every arc (basic validation, before the first gather).
@@ -435,10 +458,25 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
     }
     default: break;
   }
-  for (int o = 32; o >= 1; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
-  if (lane_id() == 0 && vmax > 0.0) {
-    if constexpr (F32) atomicMax(&a.xmax32[a.r], __float_as_uint((float)vmax));
-    else atomicMax(&a.xmax64[a.r], (unsigned long long)__double_as_longlong(vmax));
+  store_block_max<F32>(a, vmax);
+}
+
+__global__ void __launch_bounds__(kFinishThreads) reduce_blkmax(const void* blkmax, long long nb, int fp32,
+                                                                unsigned* xmax32, unsigned long long* xmax64,
+                                                                int r, const RunScalars* sc) {
+  if (sc->err || sc->done) return;
+  __shared__ double wm[kFinishThreads / kWave];
+  double m = 0.0;
+  for (long long i = threadIdx.x; i < nb; i += kFinishThreads)
+    m = fmax(m, fp32 ? (double)reinterpret_cast<const float*>(blkmax)[i] : reinterpret_cast<const double*>(blkmax)[i]);
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if (lane_id() == 0) wm[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kFinishThreads / kWave; ++i) m = fmax(m, wm[i]);
+    m = fmax(m, wm[0]);
+    if (fp32) xmax32[r] = __float_as_uint((float)m);
+    else xmax64[r] = (unsigned long long)__double_as_longlong(m);
   }
 }
 
@@ -485,67 +523,6 @@ __global__ void __launch_bounds__(kWG) sel_hist1(SelArgs a) {
     if (h[d]) atomicAdd(&a.hist[kDigits + d], h[d]);
 }
 
-// Inside one 1024-thread block: the bucket of hist[0..nb) (nb <= 4096) that holds
-// rank `need` (1-based), counting from the largest bucket (desc) or the
-// smallest.  Thread t owns positions 4t..4t+3 of that order.
-struct Bucket {
-  int b;
-  int need;   // rank inside the bucket
-  int count;  // items in the bucket
-};
-
-__device__ Bucket find_bucket(const unsigned* h, int nb, int need, bool desc) {
-  __shared__ long long wsum[kFinishThreads / kWave];
-  __shared__ Bucket res;
-  const int t = threadIdx.x;
-  const int lane = lane_id();
-  const int w = t / kWave;
-  unsigned loc[4];
-  long long tot = 0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int pos = 4 * t + j;
-    const int bin = desc ? nb - 1 - pos : pos;
-    loc[j] = (pos < nb) ? h[bin] : 0u;
-    tot += loc[j];
-  }
-  long long inc = tot;
-  for (int o = 1; o < kWave; o <<= 1) {
-    long long y = __shfl_up(inc, o);
-    if (lane >= o) inc += y;
-  }
-  if (lane == kWave - 1) wsum[w] = inc;
-  __syncthreads();
-  if (w == 0) {
-    long long ws = lane < kFinishThreads / kWave ? wsum[lane] : 0;
-    long long wi = ws;
-    for (int o = 1; o < kWave; o <<= 1) {
-      long long y = __shfl_up(wi, o);
-      if (lane >= o) wi += y;
-    }
-    if (lane < kFinishThreads / kWave) wsum[lane] = wi - ws;
-  }
-  __syncthreads();
-  long long cum = wsum[w] + inc - tot;   // items before this thread's positions
-  if (cum < need && need <= cum + tot) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (need <= cum + (long long)loc[j]) {
-        const int pos = 4 * t + j;
-        res.b = desc ? nb - 1 - pos : pos;
-        res.need = (int)(need - cum);
-        res.count = (int)loc[j];
-        break;
-      }
-      cum += loc[j];
-    }
-  }
-  __syncthreads();
-  const Bucket r = res;
-  __syncthreads();
-  return r;
-}
-
 __global__ void __launch_bounds__(kFinishThreads) sel_scan(SelArgs a, int level) {
   if (stopped(a.sc)) return;
   if (level == 1 && a.sc->cand_count[0] <= kSmallCand) return;
@@ -560,6 +537,9 @@ __global__ void __launch_bounds__(kFinishThreads) sel_scan(SelArgs a, int level)
   }
 }
 
+constexpr int kIPT = 8;                         // items per thread per append group
+constexpr long long kGroup = (long long)kWG * kIPT;
+
 __global__ void __launch_bounds__(kWG) sel_compact(SelArgs a, int level) {
   if (stopped(a.sc)) return;
   const int c0 = a.sc->cand_count[0];
@@ -567,26 +547,34 @@ __global__ void __launch_bounds__(kWG) sel_compact(SelArgs a, int level) {
   const unsigned long long pre = a.sc->prefix;
   const int shift = level == 0 ? 51 : 39;
   const int cnt = level == 0 ? a.sc->m : c0;
-  const long long stride = (long long)gridDim.x * kWG;
-  for (long long base = (long long)blockIdx.x * kWG; base < cnt; base += stride) {
-    const long long i = base + threadIdx.x;
-    const bool valid = i < cnt;
-    unsigned long long key = 0;
-    int v = 0;
-    if (valid) {
-      if (level == 0) {
-        key = a.keys[i];
-        v = a.identity_in ? (int)i : a.act_in[i];
-      } else {
-        key = a.cand_key[0][i];
-        v = a.cand_v[0][i];
+  for (long long g0 = (long long)blockIdx.x * kGroup; g0 < cnt; g0 += (long long)gridDim.x * kGroup) {
+    unsigned long long key[kIPT];
+    int v[kIPT];
+    unsigned mask = 0;
+#pragma unroll
+    for (int j = 0; j < kIPT; ++j) {
+      const long long i = g0 + (long long)j * kWG + threadIdx.x;
+      key[j] = 0;
+      v[j] = 0;
+      if (i < cnt) {
+        if (level == 0) {
+          key[j] = a.keys[i];
+          v[j] = a.identity_in ? (int)i : a.act_in[i];
+        } else {
+          key[j] = a.cand_key[0][i];
+          v[j] = a.cand_v[0][i];
+        }
+        if ((key[j] >> shift) == pre) mask |= 1u << j;
       }
     }
-    const bool pred = valid && (key >> shift) == pre;
-    const int pos = wave_append(&a.sc->cand_count[level], pred);
-    if (pred) {
-      a.cand_key[level][pos] = key;
-      a.cand_v[level][pos] = v;
+    int pos = block_reserve(&a.sc->cand_count[level], mask);
+#pragma unroll
+    for (int j = 0; j < kIPT; ++j) {
+      if (mask >> j & 1u) {
+        a.cand_key[level][pos] = key[j];
+        a.cand_v[level][pos] = v[j];
+        ++pos;
+      }
     }
   }
 }
@@ -674,35 +662,53 @@ __global__ void __launch_bounds__(kFinishThreads) sel_finish(SelArgs a) {
 // converged(), first half: nodes past position k leave M when u - eps < l(M[k]).
 __global__ void __launch_bounds__(kWG) sel_apply(SelArgs a) {
   if (stopped(a.sc)) return;
+  __shared__ int s_prog;
+  if (threadIdx.x == 0) s_prog = 0;
   const int m = a.sc->m;
   const unsigned long long tk = a.sc->theta_key;
   const double theta = a.sc->theta;
   const int cut = a.sc->cut_ext;
   const double eps = a.b.eps;
-  const long long stride = (long long)gridDim.x * kWG;
   bool prog = false;
-  for (long long base = (long long)blockIdx.x * kWG; base < m; base += stride) {
-    const long long i = base + threadIdx.x;
-    const bool valid = i < m;
-    bool top = false, keep = false;
-    int v = 0;
-    if (valid) {
-      v = a.identity_in ? (int)i : a.act_in[i];
-      const unsigned long long key = a.keys[i];
-      top = key > tk || (key == tk && ext_id(a, v) <= cut);
-      if (!top) {
-        double lo, up;
-        bound_eval(a.b, v, lo, up);
-        keep = !(up - eps < theta);
+  for (long long g0 = (long long)blockIdx.x * kGroup; g0 < m; g0 += (long long)gridDim.x * kGroup) {
+    int v[kIPT];
+    unsigned mt = 0, mk = 0;
+#pragma unroll
+    for (int j = 0; j < kIPT; ++j) {
+      const long long i = g0 + (long long)j * kWG + threadIdx.x;
+      v[j] = 0;
+      if (i < m) {
+        v[j] = a.identity_in ? (int)i : a.act_in[i];
+        const unsigned long long key = a.keys[i];
+        const bool top = key > tk || (key == tk && ext_id(a, v[j]) <= cut);
+        bool keep = false;
+        if (!top) {
+          double lo, up;
+          bound_eval(a.b, v[j], lo, up);
+          keep = !(up - eps < theta);
+        }
+        if (top) mt |= 1u << j;
+        if (keep) mk |= 1u << j;
+        if ((top || keep) && !prog && can_progress(a.b, v[j])) prog = true;
       }
-      if ((top || keep) && can_progress(a.b, v)) prog = true;
     }
-    const int pt = wave_append(&a.sc->top_count, top);
-    if (top && pt < a.k) a.act_out[pt] = v;
-    const int pk = wave_append(&a.sc->kept_count, keep);
-    if (keep && (long long)a.k + pk < a.n) a.act_out[a.k + pk] = v;
+    int pt = block_reserve(&a.sc->top_count, mt);
+    int pk = block_reserve(&a.sc->kept_count, mk);
+#pragma unroll
+    for (int j = 0; j < kIPT; ++j) {
+      if (mt >> j & 1u) {
+        if (pt < a.k) a.act_out[pt] = v[j];
+        ++pt;
+      }
+      if (mk >> j & 1u) {
+        if ((long long)a.k + pk < a.n) a.act_out[a.k + pk] = v[j];
+        ++pk;
+      }
+    }
   }
-  if (__ballot(prog) && lane_id() == 0) atomicOr(&a.sc->progress, 1);
+  if (prog) s_prog = 1;
+  __syncthreads();
+  if (threadIdx.x == 0 && s_prog) atomicOr(&a.sc->progress, 1);
 }
 
 // converged(), second half: sort the top-k by (l desc, id asc) in LDS and test
@@ -814,11 +820,17 @@ __global__ void __launch_bounds__(kWG) rest_max(SelArgs a, const uint8_t* mark, 
     best = any ? fmax(best, up) : up;
     any = true;
   }
+  __shared__ double wm[kWG / kWave];
   for (int o = 32; o >= 1; o >>= 1) {
     const double y = __shfl_xor(best, o);
     best = fmax(best, y);
   }
-  if (lane_id() == 0) atomicMax(out, (unsigned long long)__double_as_longlong(best));
+  if (lane_id() == 0) wm[threadIdx.x / kWave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
+    atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  }
 }
 
 __global__ void __launch_bounds__(kWG) all_bounds(BoundArgs b, long long n, const int32_t* ext_of,
@@ -855,6 +867,29 @@ __global__ void init_run(RunScalars* sc, long long n, double* sigma, double* sig
   for (long long i = t; i < 2 * kDigits; i += stride) hist[i] = 0u;
 }
 
+// Internal renumbering: new id i = position of the row in the binned order
+// (degree classes, longest first).  ext_of[i] is the caller's id of new node i.
+__global__ void __launch_bounds__(kWG) relabel_ids(const RowDesc* desc, long long n, int32_t* ext_of,
+                                                   int32_t* int_of, long long* len_ll, int* len32) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i >= n) return;
+  const RowDesc d = desc[i];
+  ext_of[i] = d.row;
+  int_of[d.row] = (int32_t)i;
+  len_ll[i] = d.len;
+  len32[i] = d.len;
+}
+
+// One wave per new row: its arcs in their original order, targets renamed.
+__global__ void __launch_bounds__(kWG) remap_rows(const RowDesc* desc, long long n, const int32_t* col,
+                                                  const int32_t* int_of, const long long* noff, int32_t* ncol) {
+  const long long i = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave;
+  if (i >= n) return;
+  const RowDesc d = desc[i];
+  const long long dst = noff[i];
+  for (long long j = lane_id(); j < d.len; j += kWave) ncol[dst + j] = int_of[col[d.off + j]];
+}
+
 __global__ void reset_flags(RunScalars* sc) {
   sc->err = 0;
   sc->done = 0;
@@ -868,6 +903,19 @@ __global__ void reset_flags(RunScalars* sc) {
 }
 
 }  // namespace
+
+hipError_t launch_relabel(const RowDesc* desc, long long n, const int32_t* col, int32_t* ext_of, int32_t* int_of,
+                          long long* len_ll, int* len32, long long* noff, long long* sums, long long* total,
+                          int32_t* ncol, hipStream_t s) {
+  const unsigned nb = (unsigned)std::max<long long>(1, (n + kWG - 1) / kWG);
+  hipLaunchKernelGGL(relabel_ids, dim3(nb), dim3(kWG), 0, s, desc, n, ext_of, int_of, len_ll, len32);
+  const hipError_t e = launch_scan_ll(len_ll, n, noff, sums, total, s);
+  if (e != hipSuccess) return e;
+  const unsigned nw = (unsigned)std::max<long long>(1, (n * kWave + kWG - 1) / kWG);
+  hipLaunchKernelGGL(remap_rows, dim3(nw), dim3(kWG), 0, s, desc, n, col, (const int32_t*)int_of,
+                     (const long long*)noff, ncol);
+  return hipGetLastError();
+}
 
 hipError_t launch_reset_flags(RunScalars* sc, hipStream_t s) {
   hipLaunchKernelGGL(reset_flags, dim3(1), dim3(1), 0, s, sc);
@@ -958,6 +1006,12 @@ hipError_t launch_check_col_range(const int32_t* col, long long nnz, long long n
   return hipGetLastError();
 }
 
+hipError_t launch_reduce_blkmax(const void* blkmax, long long nb, int fp32, unsigned* xmax32,
+                                unsigned long long* xmax64, int r, const RunScalars* sc, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_blkmax, dim3(1), dim3(kFinishThreads), 0, s, blkmax, nb, fp32, xmax32, xmax64, r, sc);
+  return hipGetLastError();
+}
+
 hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, hipStream_t s) {
   const unsigned grid = (unsigned)(total_blocks > 0 ? total_blocks : 1);
   if (fp32) hipLaunchKernelGGL(walk_step<true>, dim3(grid), dim3(kWG), 0, s, a);
@@ -981,7 +1035,7 @@ hipError_t launch_select_iteration(const SelArgs& a, int grid, hipStream_t s) {
 hipError_t launch_write_result(const SelArgs& a, uint8_t* mark, int32_t* out_ids, double* out_lo,
                                double* out_up, unsigned long long* rest_bits, int grid, hipStream_t s) {
   hipLaunchKernelGGL(write_top, dim3((a.k + kWG - 1) / kWG), dim3(kWG), 0, s, a, mark, out_ids, out_lo, out_up);
-  hipLaunchKernelGGL(rest_max, dim3(grid), dim3(kWG), 0, s, a, (const uint8_t*)mark, rest_bits);
+  hipLaunchKernelGGL(rest_max, dim3(std::min(grid, 512)), dim3(kWG), 0, s, a, (const uint8_t*)mark, rest_bits);
   return hipGetLastError();
 }
 

@@ -1,0 +1,274 @@
+// converged() of Algorithm 1 for one graph in one 1024-thread workgroup: the
+// radix select of the k-th largest lower bound over M, the deactivation pass
+// (u - eps < l(M[k])), the LDS sort of the top-k and the adjacent-pair
+// eps-separation test.  A launch handles one graph per workgroup: the batched
+// form runs every graph of a batch in one launch, and a single graph uses it
+// once its active set is small.
+#include <algorithm>
+
+#include "katz_device.h"
+
+namespace katz {
+namespace {
+
+// The bound factors of iteration r, recomputed on the device when r comes from
+// a device counter (same expressions as the host-side bound arguments).
+__device__ void refresh_bounds(BoundArgs& b, const GraphSel& gs, int r) {
+  b.r = r;
+  b.x = gs.xbuf[r & 1];
+  if (b.fp32) {
+    const double u64 = 0x1p-53;
+    const double kap = (2.0 * r + 32.0) * u64;
+    const double ep = gs.etap[r];
+    b.kappa = kap;
+    b.f_lo_c = 1.0 - kap;
+    b.f_hi_c = 1.0 + kap;
+    b.f_e = 1.0 + kap;
+    b.f_lo_s = b.undirected ? b.alpha * (1.0 - ep) * (1.0 - kap) * (1.0 - 8.0 * u64) : 0.0;
+    b.f_hi_s = b.beta * (1.0 + ep) * (1.0 + kap) * (1.0 + 8.0 * u64);
+  }
+}
+
+__device__ __forceinline__ int gs_ext(const GraphSel& gs, int v) { return gs.ext_of ? gs.ext_of[v] : v; }
+__device__ __forceinline__ int gs_int(const GraphSel& gs, int e) { return gs.int_of ? gs.int_of[e] : e; }
+
+struct SortArea {
+  unsigned long long key[kMaxK];
+  int ext[kMaxK];
+};
+
+__global__ void __launch_bounds__(kFinishThreads) select_wg(const GraphSel* gsel, GraphSel one, const int* r_dev) {
+  const GraphSel& gs = gsel ? gsel[blockIdx.x] : one;
+  RunScalars* sc = gs.sc;
+  if (sc->done || sc->err) return;
+  BoundArgs b = gs.b;
+  if (r_dev) refresh_bounds(b, gs, *r_dev);
+  const int cur = r_dev ? sc->cur : gs.cur;
+  const int32_t* act_in = gs.act[cur];
+  int32_t* act_out = const_cast<int32_t*>(gs.act[cur ^ 1]);
+  const bool identity = r_dev ? (b.r == 1) : gs.identity_in;
+  const int m = identity ? gs.n : sc->m;
+  const int k = gs.k;
+  const int t = threadIdx.x;
+
+  __shared__ union {
+    unsigned h[kDigits];
+    SortArea srt;
+  } sm;
+  __shared__ unsigned long long s_prefix;
+  __shared__ int s_need, s_count, s_cnt, s_top, s_kept, s_fail, s_prog, s_idpre, s_idneed;
+
+  // Keys of M and the histogram of their top digit (bits 62..51).
+  for (int d = t; d < kDigits; d += kFinishThreads) sm.h[d] = 0u;
+  if (t == 0) {
+    s_cnt = 0;
+    s_top = 0;
+    s_kept = 0;
+    s_fail = 0;
+    s_prog = 0;
+  }
+  __syncthreads();
+  for (int i = t; i < m; i += kFinishThreads) {
+    const int v = identity ? gs.base + i : act_in[i];
+    double lo, up;
+    bound_eval(b, v, lo, up);
+    const unsigned long long key = key_of(lo);
+    gs.keys[i] = key;
+    atomicAdd(&sm.h[(key >> 51) & (kDigits - 1)], 1u);
+  }
+  __syncthreads();
+  Bucket bk = find_bucket(sm.h, kDigits, k, true);
+  if (t == 0) {
+    s_prefix = (unsigned long long)bk.b;
+    s_need = bk.need;
+    s_count = bk.count;
+  }
+  __syncthreads();
+  // Candidates: the nodes whose top digit is the k-th key's.
+  {
+    const unsigned long long pre = s_prefix;
+    for (int base = 0; base < m; base += kFinishThreads) {
+      const int i = base + t;
+      const bool valid = i < m;
+      unsigned long long key = 0;
+      int v = 0;
+      if (valid) {
+        key = gs.keys[i];
+        v = identity ? gs.base + i : act_in[i];
+      }
+      const bool pred = valid && (key >> 51) == pre;
+      const int pos = wave_append(&s_cnt, pred);
+      if (pred) {
+        gs.cand_key[pos] = key;
+        gs.cand_v[pos] = v;
+      }
+    }
+  }
+  __syncthreads();
+  const int cnt = s_cnt;
+  // Remaining digits: 50..39, 38..27, 26..15, 14..3, 2..0.
+  for (int level = 1; level < kSelectLevels; ++level) {
+    const int shift = level < 5 ? 51 - kDigitBits * level : 0;
+    const int width = level < 5 ? kDigitBits : 3;
+    const int hishift = shift + width;
+    for (int d = t; d < kDigits; d += kFinishThreads) sm.h[d] = 0u;
+    __syncthreads();
+    const unsigned long long pre = s_prefix;
+    for (int i = t; i < cnt; i += kFinishThreads) {
+      const unsigned long long key = gs.cand_key[i];
+      if ((key >> hishift) == pre) atomicAdd(&sm.h[(key >> shift) & ((1u << width) - 1u)], 1u);
+    }
+    __syncthreads();
+    bk = find_bucket(sm.h, 1 << width, s_need, true);
+    if (t == 0) {
+      s_prefix = (pre << width) | (unsigned)bk.b;
+      s_need = bk.need;
+      s_count = bk.count;
+    }
+    __syncthreads();
+  }
+  const unsigned long long theta_key = s_prefix;
+  const double theta = __longlong_as_double((long long)theta_key);
+  const int need = s_need;
+  const int ties = s_count;
+  int cut = INT_MAX;
+  if (need < ties) {
+    // The need-th smallest id among the ties (ids are 31-bit: 11 + 11 + 9 bits).
+    if (t == 0) {
+      s_idpre = 0;
+      s_idneed = need;
+    }
+    __syncthreads();
+    const int widths[3] = {11, 11, 9};
+    int shift = 31;
+    for (int L = 0; L < 3; ++L) {
+      const int width = widths[L];
+      const int hishift = shift;
+      shift -= width;
+      for (int d = t; d < kDigits; d += kFinishThreads) sm.h[d] = 0u;
+      __syncthreads();
+      const int pre = s_idpre;
+      for (int i = t; i < cnt; i += kFinishThreads) {
+        if (gs.cand_key[i] != theta_key) continue;
+        const int e = gs_ext(gs, gs.cand_v[i]);
+        if ((hishift >= 31 ? 0 : (e >> hishift)) == pre) atomicAdd(&sm.h[(e >> shift) & ((1 << width) - 1)], 1u);
+      }
+      __syncthreads();
+      bk = find_bucket(sm.h, 1 << width, s_idneed, false);
+      if (t == 0) {
+        s_idpre = (pre << width) | bk.b;
+        s_idneed = bk.need;
+      }
+      __syncthreads();
+    }
+    cut = s_idpre;
+  }
+  // Deactivation: nodes past position k leave M when u - eps < l(M[k]).
+  {
+    bool prog = false;
+    for (int base = 0; base < m; base += kFinishThreads) {
+      const int i = base + t;
+      const bool valid = i < m;
+      bool top = false, keep = false;
+      int v = 0;
+      if (valid) {
+        v = identity ? gs.base + i : act_in[i];
+        const unsigned long long key = gs.keys[i];
+        top = key > theta_key || (key == theta_key && gs_ext(gs, v) <= cut);
+        if (!top) {
+          double lo, up;
+          bound_eval(b, v, lo, up);
+          keep = !(up - b.eps < theta);
+        }
+        if ((top || keep) && can_progress(b, v)) prog = true;
+      }
+      const int pt = wave_append(&s_top, top);
+      if (top && pt < k) act_out[pt] = v;
+      const int pk = wave_append(&s_kept, keep);
+      if (keep && k + pk < gs.n) act_out[k + pk] = v;
+    }
+    if (prog) s_prog = 1;
+  }
+  __syncthreads();
+  if (s_top != k) {
+    if (t == 0) sc->err = 2;
+    return;
+  }
+  // Sort the top-k by (lower desc, id asc) and test adjacent pairs.
+  int P = 1;
+  while (P < k) P <<= 1;
+  for (int i = t; i < P; i += kFinishThreads) {
+    if (i < k) {
+      const int v = act_out[i];
+      double lo, up;
+      bound_eval(b, v, lo, up);
+      sm.srt.key[i] = key_of(lo);
+      sm.srt.ext[i] = gs_ext(gs, v);
+    } else {
+      sm.srt.key[i] = 0ull;
+      sm.srt.ext[i] = INT_MAX;
+    }
+  }
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int q = t; q < P / 2; q += kFinishThreads) {
+        const int i = 2 * q - (q & (stride - 1));
+        const int j = i + stride;
+        const bool up = ((i & size) == 0);
+        const unsigned long long ki = sm.srt.key[i], kj = sm.srt.key[j];
+        const int ei = sm.srt.ext[i], ej = sm.srt.ext[j];
+        const bool j_before_i = kj > ki || (kj == ki && ej < ei);
+        if (j_before_i == up) {
+          sm.srt.key[i] = kj;
+          sm.srt.key[j] = ki;
+          sm.srt.ext[i] = ej;
+          sm.srt.ext[j] = ei;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = t; i < k; i += kFinishThreads) {
+    const int v = gs_int(gs, sm.srt.ext[i]);
+    double lo, up;
+    bound_eval(b, v, lo, up);
+    gs.top_sorted[i] = v;
+    gs.top_lo[i] = lo;
+    gs.top_up[i] = up;
+    if (i > 0 && up - b.eps >= __longlong_as_double((long long)sm.srt.key[i - 1])) s_fail = 1;
+  }
+  __syncthreads();
+  if (t == 0) {
+    const int kept = s_kept;
+    const bool certified = kept == 0 && !s_fail;
+    const bool walk_zero = b.fp32 ? (gs.xmax32[b.r] == 0u) : (gs.xmax64[b.r] == 0ull);
+    int status = -1;
+    if (certified) status = KATZ_OK;
+    else if (walk_zero) status = KATZ_W_EXACT_TIES;
+    else if (b.fp32 && !s_prog) status = KATZ_W_PRECISION_LIMIT;
+    else if (b.r >= gs.max_iter) status = KATZ_W_ITER_LIMIT;
+    sc->iterations = b.r;
+    sc->cur = cur ^ 1;
+    sc->m = k + kept;
+    if (status >= 0) {
+      sc->status = status;
+      sc->done = 1;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_select_wg(const GraphSel* gsel, int count, const int* r_dev, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(select_wg, dim3(count), dim3(kFinishThreads), 0, s, gsel, GraphSel{}, r_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_wg_one(const GraphSel& one, hipStream_t s) {
+  hipLaunchKernelGGL(select_wg, dim3(1), dim3(kFinishThreads), 0, s, (const GraphSel*)nullptr, one,
+                     (const int*)nullptr);
+  return hipGetLastError();
+}
+
+}  // namespace katz

@@ -44,7 +44,7 @@ class KatzCSR(ctypes.Structure):
 class KatzParams(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("epsilon", ctypes.c_double), ("k", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32), ("criterion", ctypes.c_int32),
-                ("validate", ctypes.c_int32), ("reserved", ctypes.c_int32), ("degree_cap", ctypes.c_int64)]
+                ("validate", ctypes.c_int32), ("flags", ctypes.c_int32), ("degree_cap", ctypes.c_int64)]
 
 
 class KatzResult(ctypes.Structure):
@@ -132,11 +132,14 @@ def make_csr(row_ptr: torch.Tensor, col: torch.Tensor, undirected: bool = True) 
                    row_ptr_64=int(row_ptr.dtype == torch.int64), undirected=int(bool(undirected)))
 
 
+FLAG_NO_REORDER = 1
+
+
 def make_params(k=1, alpha=0.0, eps=0.0, precision="fp64", max_iter=0, validate=VALIDATE_BASIC,
-                degree_cap=0) -> KatzParams:
+                degree_cap=0, flags=0) -> KatzParams:
     return KatzParams(alpha=float(alpha), epsilon=float(eps), k=int(k), max_iter=int(max_iter),
                       precision=PRECISIONS[precision] if isinstance(precision, str) else int(precision),
-                      criterion=TOPK, validate=int(validate), reserved=0, degree_cap=int(degree_cap))
+                      criterion=TOPK, validate=int(validate), flags=int(flags), degree_cap=int(degree_cap))
 
 
 def _alloc_outputs(k, device):
@@ -152,13 +155,13 @@ def _to_result(res: KatzResult, ids, lo, up) -> RankResult:
 
 
 def rank_static(row_ptr, col, k, *, alpha=0.0, eps=0.0, precision="fp64", undirected=True, max_iter=0,
-                validate=VALIDATE_BASIC, stream=None, out=None) -> RankResult:
+                validate=VALIDATE_BASIC, flags=0, stream=None, out=None) -> RankResult:
     """katz_rank_static for one graph (Algorithm 1, top-k criterion).
 
     ``out`` may pass preallocated (ids, lower, upper) tensors of length k."""
     device = row_ptr.device
     g = make_csr(row_ptr, col, undirected)
-    p = make_params(k, alpha, eps, precision, max_iter, validate)
+    p = make_params(k, alpha, eps, precision, max_iter, validate, 0, flags)
     ids, lo, up = out if out is not None else _alloc_outputs(k, device)
     res = KatzResult(topk_ids=ids.data_ptr(), lower=lo.data_ptr(), upper=up.data_ptr())
     rc = lib.katz_rank_static(1, ctypes.byref(g), ctypes.byref(p), ctypes.byref(res), None,
@@ -187,11 +190,11 @@ def rank_static_batch(graphs, params, *, stream=None):
 
 
 def bounds(row_ptr, col, r, *, alpha=0.0, precision="fp64", undirected=True, validate=VALIDATE_BASIC,
-           stream=None):
+           flags=0, stream=None):
     """katz_bounds: (lower, upper) of every node after exactly r iterations."""
     device = row_ptr.device
     g = make_csr(row_ptr, col, undirected)
-    p = make_params(1, alpha, 0.0, precision, 0, validate)
+    p = make_params(1, alpha, 0.0, precision, 0, validate, 0, flags)
     n = row_ptr.numel() - 1
     lo = torch.empty(n, dtype=torch.float64, device=device)
     up = torch.empty(n, dtype=torch.float64, device=device)

@@ -41,7 +41,7 @@ def test_struct_layout_matches_header():
 int main(void) {
   printf("katz_csr %zu\nkatz_params %zu\nkatz_result %zu\n", sizeof(katz_csr), sizeof(katz_params), sizeof(katz_result));
   F(katz_csr, col) F(katz_csr, row_ptr_64) F(katz_csr, undirected)
-  F(katz_params, k) F(katz_params, precision) F(katz_params, validate) F(katz_params, degree_cap)
+  F(katz_params, k) F(katz_params, precision) F(katz_params, validate) F(katz_params, flags) F(katz_params, degree_cap)
   F(katz_result, rest_upper_max) F(katz_result, active_final) F(katz_result, iterations) F(katz_result, status)
   return 0;
 }
@@ -99,7 +99,7 @@ def test_argument_errors_before_device_work():
     p.criterion = 1
     assert _call(g, p, res) == katz.E_UNSUPPORTED
     p = katz.make_params(1)
-    p.reserved = 3
+    p.flags = 1 << 7                                                     # unknown flag bit
     assert _call(g, p, res) == katz.E_INVALID_ARG
     assert _call(None, katz.make_params(1), res) == katz.E_INVALID_ARG
     assert _call(g, katz.make_params(1), res, count=0) == katz.E_INVALID_ARG

@@ -287,3 +287,20 @@ def test_rmat22_full_size_both_forms():
     lo, up = lo.cpu().numpy()[sample], up.cpu().numpy()[sample]
     assert np.all(lo <= olo[sample] * (1 + TAU)) and np.all(up >= oup[sample] * (1 - TAU))
     assert np.all(np.abs(lo - olo[sample]) <= 1e-6 * olo[sample] + 1e-24)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_internal_renumbering_is_invisible(precision):
+    """Renumbering nodes by degree class changes only the memory layout: ids,
+    bounds, r and status are bitwise those of a run in the caller's order."""
+    katz = K()
+    rp, col = sg.rmat(16, seed=11)
+    rp_t, col_t = dev(rp, col)
+    say("renumbering", precision)
+    a = katz.rank_static(rp_t, col_t, 500, eps=1e-6, precision=precision)
+    b = katz.rank_static(rp_t, col_t, 500, eps=1e-6, precision=precision, flags=katz.FLAG_NO_REORDER)
+    assert torch.equal(a.topk, b.topk) and torch.equal(a.lower, b.lower) and torch.equal(a.upper, b.upper)
+    assert (a.iterations, a.status, a.rest_upper_max) == (b.iterations, b.status, b.rest_upper_max)
+    la, ua = katz.bounds(rp_t, col_t, 5, precision=precision)
+    lb, ub = katz.bounds(rp_t, col_t, 5, precision=precision, flags=katz.FLAG_NO_REORDER)
+    assert torch.equal(la, lb) and torch.equal(ua, ub)
