@@ -267,6 +267,8 @@ struct Bins {
   HugeRow* huge = nullptr;
   int* seg_done = nullptr;
   long long* blk = nullptr;
+  long long* scan_sums = nullptr;    // scratch of the device-wide scans
+  long long* scan_totals = nullptr;  // [2]
   int nblocks = 0;
   long long seg_cap = 0, huge_cap = 0;
   long long count = 0;   // rows binned
@@ -767,6 +769,8 @@ void layout(Arena& ar, const Plan& pl, Bins& b, Work& w, Staging& stg) {
   bins_caps(b, n, nnz);
   w.sc = ar.take<RunScalars>(1);
   b.blk = ar.take<long long>((size_t)(NUM_BINS + 2) * b.nblocks);
+  b.scan_sums = ar.take<long long>(scan_sums_capacity((long long)NUM_BINS * b.nblocks));
+  b.scan_totals = ar.take<long long>(2);
   b.desc = ar.take<RowDesc>(n);
   b.segs = ar.take<SegDesc>(b.seg_cap);
   b.huge = ar.take<HugeRow>(b.huge_cap);
@@ -846,7 +850,7 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
   KATZ_HIP(launch_init_run(w.sc, g->n, w.sigma, w.sigma_sum, w.xmax32, w.xmax64, pl.max_iter, w.hist, s));
   KATZ_HIP(hipMemsetAsync(b.seg_done, 0, sizeof(int) * b.huge_cap, s));
   KATZ_HIP(launch_prep_count(stg.row_ptr, g->row_ptr_64, g->n, g->nnz, b.blk, b.nblocks, w.sc, s));
-  KATZ_HIP(launch_prep_scan(b.blk, b.nblocks, w.sc, s));
+  KATZ_HIP(launch_prep_scan(b.blk, b.nblocks, b.scan_sums, b.scan_totals, w.sc, s));
   KATZ_HIP(launch_prep_scatter(stg.row_ptr, g->row_ptr_64, g->n, b.blk, b.nblocks, b.desc, b.segs, b.huge, w.sc, s));
   if (pl.validate >= KATZ_VALIDATE_BASIC) KATZ_HIP(launch_check_col_range(stg.col, g->nnz, g->n, w.sc, s));
   KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
@@ -865,8 +869,8 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
     KATZ_HIP(launch_relabel(b.desc, g->n, stg.col, stg.ext_of, stg.int_of, stg.len_ll, stg.len32, stg.noff,
                             stg.sums, stg.total, stg.ncol, s));
     KATZ_HIP(hipMemsetAsync(b.seg_done, 0, sizeof(int) * b.huge_cap, s));
-    KATZ_HIP(launch_prep_rows(nullptr, g->n, stg.noff, stg.len32, b.blk, b.nblocks, b.desc, b.segs, b.huge, w.sc,
-                              s));
+    KATZ_HIP(launch_prep_rows(nullptr, g->n, stg.noff, stg.len32, b.blk, b.nblocks, b.scan_sums, b.scan_totals,
+                              b.desc, b.segs, b.huge, w.sc, s));
     KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
     KATZ_HIP(hipStreamSynchronize(s));
     if (hs.sc->err) return KATZ_E_HIP;
@@ -992,6 +996,366 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
 }
 
 // ---------------------------------------------------------------------------
+// Batched form: many graphs in one sequence of launches (katz_batch.hip).
+// ---------------------------------------------------------------------------
+constexpr int kItersPerGraph = 4;   // iterations captured in one hipGraph
+
+int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* out, hipStream_t s) {
+  const int fp32 = p[0].precision == KATZ_FP32_MARGIN;
+  long long total_n = 0, total_nnz = 0, max_nnz = 0, sum_k = 0;
+  int max_iter = 1;
+  for (int i = 0; i < count; ++i) {
+    if ((p[i].precision == KATZ_FP32_MARGIN) != (fp32 != 0)) return KATZ_E_UNSUPPORTED;
+    total_n += g[i].n;
+    total_nnz += g[i].nnz;
+    max_nnz = std::max<long long>(max_nnz, g[i].nnz);
+    sum_k += p[i].k;
+    max_iter = std::max(max_iter, p[i].max_iter ? p[i].max_iter : 1000);
+  }
+  if (total_n > INT32_MAX) return KATZ_E_UNSUPPORTED;
+  const int stride = max_iter + 1;
+  int dev = 0;
+  KATZ_HIP(hipGetDevice(&dev));
+  ArenaLease lease(dev);
+  Arena& ar = *lease.a;
+
+  // ---- layout ----
+  std::vector<bool> rp_host(count), col_host(count);
+  bool out_host = false;
+  for (int i = 0; i < count; ++i) {
+    rp_host[i] = !is_device_ptr(g[i].row_ptr);
+    col_host[i] = g[i].nnz > 0 && !is_device_ptr(g[i].col);
+    out_host = out_host || !(is_device_ptr(out[i].topk_ids) && is_device_ptr(out[i].lower) &&
+                             is_device_ptr(out[i].upper));
+  }
+  Bins b;
+  Work w;
+  RunScalars* gsc = nullptr;
+  long long* gbase = nullptr;
+  const void** grp = nullptr;
+  int* grp64 = nullptr;
+  long long* gnnz = nullptr;
+  const int32_t** gcol = nullptr;
+  double* galpha = nullptr;
+  int* gclog2 = nullptr;
+  int* gdmax = nullptr;
+  double *gsigma = nullptr, *gsigsum = nullptr, *etap = nullptr, *rest = nullptr;
+  int* gexp = nullptr;
+  unsigned* gxmax32 = nullptr;
+  unsigned long long* gxmax64 = nullptr;
+  int* gid_of = nullptr;
+  GraphSel* gsel = nullptr;
+  int* r_dev = nullptr;
+  int* ndone = nullptr;
+  int32_t** o_ids = nullptr;
+  double** o_lo = nullptr;
+  double** o_up = nullptr;
+  std::vector<void*> stage_rp(count, nullptr), stage_col(count, nullptr);
+  int32_t* st_ids = nullptr;
+  double *st_lo = nullptr, *st_up = nullptr;
+  auto lay = [&]() {
+    ar.used = 0;
+    bins_caps(b, total_n, total_nnz + count);
+    w.sc = ar.take<RunScalars>(1);
+    gsc = ar.take<RunScalars>(count);
+    gbase = ar.take<long long>(count + 1);
+    grp = ar.take<const void*>(count);
+    grp64 = ar.take<int>(count);
+    gnnz = ar.take<long long>(count);
+    gcol = ar.take<const int32_t*>(count);
+    galpha = ar.take<double>(count);
+    gclog2 = ar.take<int>(count);
+    gdmax = ar.take<int>(count);
+    gsigma = ar.take<double>((size_t)count * stride);
+    gsigsum = ar.take<double>((size_t)count * stride);
+    gexp = ar.take<int>((size_t)count * stride);
+    gxmax32 = ar.take<unsigned>((size_t)count * stride);
+    gxmax64 = ar.take<unsigned long long>((size_t)count * stride);
+    etap = ar.take<double>(stride);
+    rest = ar.take<double>(count);
+    gid_of = ar.take<int>(total_n);
+    gsel = ar.take<GraphSel>(count);
+    r_dev = ar.take<int>(1);
+    ndone = ar.take<int>(1);
+    o_ids = ar.take<int32_t*>(count);
+    o_lo = ar.take<double*>(count);
+    o_up = ar.take<double*>(count);
+    b.blk = ar.take<long long>((size_t)(NUM_BINS + 2) * b.nblocks);
+    b.scan_sums = ar.take<long long>(scan_sums_capacity((long long)NUM_BINS * b.nblocks));
+    b.scan_totals = ar.take<long long>(2);
+    b.desc = ar.take<RowDesc>(total_n);
+    b.segs = ar.take<SegDesc>(b.seg_cap);
+    b.huge = ar.take<HugeRow>(b.huge_cap);
+    b.seg_done = ar.take<int>(b.huge_cap);
+    const size_t xs = fp32 ? 4 : 8;
+    w.x[0] = ar.take<char>(total_n * xs);
+    w.x[1] = ar.take<char>(total_n * xs);
+    w.c = ar.take<double>(total_n);
+    if (fp32) w.e = ar.take<float>(total_n);
+    w.partial = ar.take<char>(b.seg_cap * xs);
+    w.act[0] = ar.take<int32_t>(total_n);
+    w.act[1] = ar.take<int32_t>(total_n);
+    w.keys = ar.take<unsigned long long>(total_n);
+    w.cand_key[0] = ar.take<unsigned long long>(total_n);
+    w.cand_v[0] = ar.take<int32_t>(total_n);
+    w.top_sorted = ar.take<int32_t>(sum_k);
+    w.top_lo = ar.take<double>(sum_k);
+    w.top_up = ar.take<double>(sum_k);
+    w.mark = ar.take<uint8_t>(total_n);
+    for (int i = 0; i < count; ++i) {
+      if (rp_host[i]) stage_rp[i] = ar.take<char>((size_t)(g[i].n + 1) * (g[i].row_ptr_64 ? 8 : 4));
+      if (col_host[i]) stage_col[i] = ar.take<int32_t>(g[i].nnz);
+    }
+    if (out_host) {
+      st_ids = ar.take<int32_t>(sum_k);
+      st_lo = ar.take<double>(sum_k);
+      st_up = ar.take<double>(sum_k);
+    }
+  };
+  ar.measuring = true;
+  lay();
+  ar.measuring = false;
+  KATZ_TRY(ar.grow(ar.used));
+  lay();
+
+  CallTimer T;
+  T.call_begin(s);
+  const int tp = T.start(T_PREP, s);
+  // ---- per-graph tables ----
+  std::vector<long long> h_base(count + 1, 0), h_nnz(count);
+  std::vector<const void*> h_rp(count);
+  std::vector<const int32_t*> h_col(count);
+  std::vector<int> h_rp64(count);
+  for (int i = 0; i < count; ++i) {
+    h_base[i + 1] = h_base[i] + g[i].n;
+    h_nnz[i] = g[i].nnz;
+    h_rp64[i] = g[i].row_ptr_64;
+    h_rp[i] = rp_host[i] ? stage_rp[i] : g[i].row_ptr;
+    h_col[i] = col_host[i] ? (const int32_t*)stage_col[i] : g[i].col;
+    if (rp_host[i])
+      KATZ_HIP(hipMemcpyAsync(stage_rp[i], g[i].row_ptr, (size_t)(g[i].n + 1) * (g[i].row_ptr_64 ? 8 : 4),
+                              hipMemcpyHostToDevice, s));
+    if (col_host[i])
+      KATZ_HIP(hipMemcpyAsync(stage_col[i], g[i].col, (size_t)g[i].nnz * 4, hipMemcpyHostToDevice, s));
+  }
+  KATZ_HIP(hipMemcpyAsync(gbase, h_base.data(), sizeof(long long) * (count + 1), hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(gnnz, h_nnz.data(), sizeof(long long) * count, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(grp, h_rp.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(grp64, h_rp64.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(gcol, h_col.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
+  KATZ_HIP(launch_reset_flags(w.sc, s));
+  KATZ_HIP(hipMemsetAsync(b.seg_done, 0, sizeof(int) * b.huge_cap, s));
+  KATZ_HIP(hipMemsetAsync(gdmax, 0, sizeof(int) * count, s));
+  int validate = 0;
+  for (int i = 0; i < count; ++i) validate = std::max(validate, p[i].validate);
+  KATZ_HIP(launch_batch_prep(gbase, grp, grp64, gnnz, gcol, count, total_n, max_nnz, gid_of, b.blk, b.nblocks,
+                             b.scan_sums, b.scan_totals, b.desc, b.segs, b.huge, w.sc, validate, s));
+  KATZ_HIP(launch_batch_dmax(b.desc, total_n, gid_of, gdmax, s));
+  std::vector<int> h_dmax(count);
+  KATZ_HIP(hipMemcpyAsync(h_dmax.data(), gdmax, sizeof(int) * count, hipMemcpyDeviceToHost, s));
+  KATZ_HIP(hipMemcpyAsync(ar.hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+  KATZ_HIP(hipStreamSynchronize(s));
+  if (ar.hs.sc->err) return KATZ_E_CSR;
+  b.read_back(*ar.hs.sc, total_n);
+
+  // ---- per-graph scalars, selection views, initial state ----
+  std::vector<Scalars> S(count);
+  for (int i = 0; i < count; ++i) KATZ_TRY(resolve_alpha(p[i].alpha, h_dmax[i], S[i]));
+  Scalars G;   // FP32 eta tables for the deepest reduction of the whole batch
+  if (fp32) fp32_tables(G, b, max_iter);
+  std::vector<double> h_alpha(count), h_sigma((size_t)count * stride, 0.0), h_sigsum((size_t)count * stride, 0.0);
+  std::vector<int> h_clog2(count), h_exp((size_t)count * stride, 0);
+  std::vector<RunScalars> h_sc(count);
+  std::vector<GraphSel> h_sel(count);
+  std::vector<int32_t*> h_oids(count);
+  std::vector<double*> h_olo(count), h_oup(count);
+  long long koff = 0;
+  for (int i = 0; i < count; ++i) {
+    h_alpha[i] = S[i].alpha;
+    h_clog2[i] = clog2(std::max(h_dmax[i], 1));
+    h_sigma[(size_t)i * stride] = 1.0;
+    if (fp32) {
+      // x_0 = 1, so the first scale exponent is 1 + ceil(log2 d_max).
+      const int e1 = 1 + h_clog2[i];
+      h_exp[(size_t)i * stride + 1] = e1;
+      h_sigma[(size_t)i * stride + 1] = std::ldexp(S[i].alpha, e1);
+      h_sigsum[(size_t)i * stride + 1] = h_sigma[(size_t)i * stride + 1];
+    }
+    RunScalars z{};
+    z.m = (int)g[i].n;
+    h_sc[i] = z;
+    GraphSel& gs = h_sel[i];
+    gs = GraphSel{};
+    BoundArgs& bd = gs.b;
+    bd.c = w.c;
+    bd.e = w.e;
+    bd.sigma = gsigma + (size_t)i * stride;
+    bd.sigma_sum = gsigsum + (size_t)i * stride;
+    bd.fp32 = fp32;
+    bd.undirected = g[i].undirected;
+    bd.alpha = S[i].alpha;
+    bd.beta = fp32 ? S[i].beta_hi : S[i].beta;
+    bd.eps = p[i].epsilon;
+    // Underflow slack with r at its largest (it grows with r).
+    bd.tau_coef = 4.0 * (stride + S[i].beta_hi + 2.0) * (h_dmax[i] + 2.0) * 0x1p-126;
+    gs.xbuf[0] = w.x[0];
+    gs.xbuf[1] = w.x[1];
+    gs.etap = etap;
+    gs.act[0] = w.act[0] + h_base[i];
+    gs.act[1] = w.act[1] + h_base[i];
+    gs.keys = w.keys + h_base[i];
+    gs.cand_key = w.cand_key[0] + h_base[i];
+    gs.cand_v = w.cand_v[0] + h_base[i];
+    gs.top_sorted = w.top_sorted + koff;
+    gs.top_lo = w.top_lo + koff;
+    gs.top_up = w.top_up + koff;
+    gs.sc = gsc + i;
+    gs.xmax32 = gxmax32 + (size_t)i * stride;
+    gs.xmax64 = gxmax64 + (size_t)i * stride;
+    gs.base = (int)h_base[i];
+    gs.n = (int)g[i].n;
+    gs.k = p[i].k;
+    gs.max_iter = p[i].max_iter ? p[i].max_iter : 1000;
+    h_oids[i] = out_host ? st_ids + koff : out[i].topk_ids;
+    h_olo[i] = out_host ? st_lo + koff : out[i].lower;
+    h_oup[i] = out_host ? st_up + koff : out[i].upper;
+    koff += p[i].k;
+  }
+  std::vector<double> h_etap(stride, 0.0);
+  if (fp32)
+    for (int r = 0; r <= max_iter; ++r) h_etap[r] = G.etap[r];
+  KATZ_HIP(hipMemcpyAsync(galpha, h_alpha.data(), sizeof(double) * count, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(gclog2, h_clog2.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(gsigma, h_sigma.data(), sizeof(double) * h_sigma.size(), hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(gsigsum, h_sigsum.data(), sizeof(double) * h_sigsum.size(), hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(gexp, h_exp.data(), sizeof(int) * h_exp.size(), hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(etap, h_etap.data(), sizeof(double) * stride, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(gsc, h_sc.data(), sizeof(RunScalars) * count, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(gsel, h_sel.data(), sizeof(GraphSel) * count, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(o_ids, h_oids.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(o_lo, h_olo.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(o_up, h_oup.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemsetAsync(gxmax32, 0, sizeof(unsigned) * (size_t)count * stride, s));
+  KATZ_HIP(hipMemsetAsync(gxmax64, 0, sizeof(unsigned long long) * (size_t)count * stride, s));
+  KATZ_HIP(launch_fill_ones(w.x[0], total_n, fp32, s));
+  const int one = 1;
+  KATZ_HIP(hipMemcpyAsync(r_dev, &one, sizeof(int), hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemsetAsync(ndone, 0, sizeof(int), s));
+  T.stop(tp, s);
+
+  // ---- the iteration, captured once and replayed ----
+  BatchWalk bw{};
+  bw.desc = b.desc;
+  bw.segs = b.segs;
+  bw.huge = b.huge;
+  bw.seg_done = b.seg_done;
+  {
+    IterArgs tmp{};
+    long long tb = 0;
+    fill_blocks(tmp, b, true, tb);
+    for (int i = 0; i <= NUM_BINS; ++i) bw.first_block[i] = tmp.first_block[i];
+  }
+  for (int i = 0; i < NUM_BINS; ++i) {
+    bw.bin_base[i] = b.bin_base[i];
+    bw.bin_count[i] = b.bin_count[i];
+  }
+  bw.gid_of = gid_of;
+  bw.gcol = gcol;
+  bw.gbase = gbase;
+  bw.galpha = galpha;
+  bw.gsc = gsc;
+  bw.gsigma = gsigma;
+  bw.gexp = gexp;
+  bw.gxmax32 = gxmax32;
+  bw.gxmax64 = gxmax64;
+  bw.xbuf[0] = w.x[0];
+  bw.xbuf[1] = w.x[1];
+  bw.c = w.c;
+  bw.e = w.e;
+  bw.partial = w.partial;
+  bw.etap = etap;
+  bw.r_dev = r_dev;
+  bw.stride = stride;
+  bw.fp32 = fp32;
+  const long long total_blocks = bw.first_block[NUM_BINS];
+
+  hipStream_t cs = nullptr;
+  KATZ_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  struct StreamGuard {
+    hipStream_t s;
+    hipGraph_t gr = nullptr;
+    hipGraphExec_t ex = nullptr;
+    ~StreamGuard() {
+      if (ex) (void)hipGraphExecDestroy(ex);
+      if (gr) (void)hipGraphDestroy(gr);
+      (void)hipStreamDestroy(s);
+    }
+  } guard{cs};
+  KATZ_HIP(hipStreamSynchronize(s));
+  KATZ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  for (int it = 0; it < kItersPerGraph; ++it) {
+    KATZ_HIP(launch_walk_batch(bw, total_blocks, cs));
+    KATZ_HIP(launch_select_wg(gsel, count, r_dev, cs));
+    KATZ_HIP(launch_batch_advance(r_dev, count, gsc, gxmax32, gsigma, gsigsum, gexp, galpha, gclog2, stride, fp32,
+                                  ndone, cs));
+  }
+  KATZ_HIP(hipStreamEndCapture(cs, &guard.gr));
+  KATZ_HIP(hipGraphInstantiate(&guard.ex, guard.gr, nullptr, nullptr, 0));
+  const int ts = T.start(T_STEP, cs);
+  const int max_replays = (max_iter + kItersPerGraph - 1) / kItersPerGraph + 1;
+  int replay = 0;
+  bool finished = false;
+  int* h_done = reinterpret_cast<int*>(ar.hs.bits);
+  while (!finished && replay < max_replays) {
+    KATZ_HIP(hipGraphLaunch(guard.ex, cs));
+    KATZ_HIP(hipMemcpyAsync(&h_done[replay & 1], ndone, sizeof(int), hipMemcpyDeviceToHost, cs));
+    KATZ_HIP(hipEventRecord(ar.hs.ev[replay & 1], cs));
+    if (replay >= 1) {
+      KATZ_HIP(hipEventSynchronize(ar.hs.ev[(replay - 1) & 1]));
+      if (h_done[(replay - 1) & 1] >= count) finished = true;
+    }
+    ++replay;
+  }
+  T.stop(ts, cs);
+  KATZ_HIP(hipStreamSynchronize(cs));
+
+  // ---- outputs ----
+  std::vector<RunScalars> fin(count);
+  KATZ_HIP(hipMemcpyAsync(fin.data(), gsc, sizeof(RunScalars) * count, hipMemcpyDeviceToHost, cs));
+  KATZ_HIP(hipStreamSynchronize(cs));
+  for (int i = 0; i < count; ++i)
+    if (fin[i].err) return fin[i].err == 2 ? KATZ_E_HIP : KATZ_E_CSR;
+  const int tr = T.start(T_RESULT, cs);
+  KATZ_HIP(hipMemsetAsync(w.mark, 0, (size_t)total_n, cs));
+  KATZ_HIP(launch_batch_write(gsel, count, o_ids, o_lo, o_up, w.mark, rest, cs));
+  T.stop(tr, cs);
+  std::vector<double> h_rest(count);
+  KATZ_HIP(hipMemcpyAsync(h_rest.data(), rest, sizeof(double) * count, hipMemcpyDeviceToHost, cs));
+  if (out_host) {
+    koff = 0;
+    for (int i = 0; i < count; ++i) {
+      KATZ_HIP(hipMemcpyAsync(out[i].topk_ids, st_ids + koff, sizeof(int32_t) * p[i].k, hipMemcpyDefault, cs));
+      KATZ_HIP(hipMemcpyAsync(out[i].lower, st_lo + koff, sizeof(double) * p[i].k, hipMemcpyDefault, cs));
+      KATZ_HIP(hipMemcpyAsync(out[i].upper, st_up + koff, sizeof(double) * p[i].k, hipMemcpyDefault, cs));
+      koff += p[i].k;
+    }
+  }
+  KATZ_HIP(hipStreamSynchronize(cs));
+  T.commit(cs);
+  int worst = KATZ_OK;
+  for (int i = 0; i < count; ++i) {
+    out[i].iterations = fin[i].iterations;
+    out[i].status = fin[i].done ? fin[i].status : KATZ_W_ITER_LIMIT;
+    out[i].active_final = fin[i].m;
+    out[i].alpha_used = S[i].alpha;
+    out[i].eta = fp32 ? G.eta[std::max(1, fin[i].iterations)] : 0.0;
+    out[i].rest_upper_max = (p[i].k == g[i].n) ? -std::numeric_limits<double>::infinity() : h_rest[i];
+    worst = std::max(worst, out[i].status);
+  }
+  return worst;
+}
+
+// ---------------------------------------------------------------------------
 // Dynamic state.
 // ---------------------------------------------------------------------------
 long long slack_cap_host(long long len) { return len + std::max(2ll, len >> 3); }
@@ -1035,6 +1399,8 @@ int alloc_bins(katz_state* st, Bins& b) {
     dfree(st, b.huge);
     dfree(st, b.seg_done);
     dfree(st, b.blk);
+    dfree(st, b.scan_sums);
+    dfree(st, b.scan_totals);
   }
   bins_caps(b, st->n, st->pool_cap);
   b.desc = dalloc<RowDesc>(st, st->n);
@@ -1042,7 +1408,9 @@ int alloc_bins(katz_state* st, Bins& b) {
   b.huge = dalloc<HugeRow>(st, b.huge_cap);
   b.seg_done = dalloc<int>(st, b.huge_cap);
   b.blk = dalloc<long long>(st, (size_t)(NUM_BINS + 2) * b.nblocks);
-  if (!b.desc || !b.segs || !b.huge || !b.seg_done || !b.blk) return KATZ_E_OOM;
+  b.scan_sums = dalloc<long long>(st, scan_sums_capacity((long long)NUM_BINS * b.nblocks));
+  b.scan_totals = dalloc<long long>(st, 2);
+  if (!b.desc || !b.segs || !b.huge || !b.seg_done || !b.blk || !b.scan_sums || !b.scan_totals) return KATZ_E_OOM;
   KATZ_HIP(hipMemset(b.seg_done, 0, sizeof(int) * b.huge_cap));
   return KATZ_OK;
 }
@@ -1059,7 +1427,8 @@ int alloc_partial(katz_state* st) {
 int bin_rows(katz_state* st, Bins& b, RunScalars* sc, const int32_t* ids, long long count, hipStream_t s) {
   KATZ_HIP(launch_reset_flags(sc, s));
   b.nblocks = (int)std::max<long long>(1, (count + kWG - 1) / kWG);
-  KATZ_HIP(launch_prep_rows(ids, count, st->row_off, st->row_len, b.blk, b.nblocks, b.desc, b.segs, b.huge, sc, s));
+  KATZ_HIP(launch_prep_rows(ids, count, st->row_off, st->row_len, b.blk, b.nblocks, b.scan_sums, b.scan_totals,
+                            b.desc, b.segs, b.huge, sc, s));
   KATZ_HIP(hipMemcpyAsync(st->hs.sc, sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
   KATZ_HIP(hipStreamSynchronize(s));
   if (st->hs.sc->err) return KATZ_E_HIP;
@@ -1536,6 +1905,7 @@ KATZ_EXPORT int katz_rank_static(int32_t count, const katz_csr* g, const katz_pa
     if (!rc && states && (p[i].precision != KATZ_FP64 || !g[i].undirected)) rc = KATZ_E_UNSUPPORTED;
     if (rc) return rc;
   }
+  if (count > 1 && !states) return katz::rank_batch(count, g, p, out, (hipStream_t)stream);
   int worst = KATZ_OK;
   for (int32_t i = 0; i < count; ++i) {
     int rc;

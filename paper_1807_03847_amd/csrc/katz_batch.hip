@@ -1,0 +1,447 @@
+// Batched form: Algorithm 1 over many independent graphs at once, each with its
+// own alpha, k and eps.
+//
+// The graphs are not copied: their rows are binned together under global row
+// ids (graph g owns ids gbase[g] .. gbase[g+1] - 1), and every row carries the
+// graph id that locates its column array, its node base and its alpha.  One
+// iteration is three launches whose arguments never change, so a block of
+// iterations can be captured into a hipGraph and replayed:
+//   walk_batch     walk step of every row whose graph is still iterating,
+//   select_wg      one workgroup per graph (converged() of Algorithm 1),
+//   batch_advance  FP32 scales of the next iteration; r += 1.
+// The iteration number r lives in device memory.  The walk vector's r = 0
+// buffer holds ones, so the first iteration is an ordinary walk step.
+#include <algorithm>
+
+#include "katz_device.h"
+
+namespace katz {
+namespace {
+
+struct BatchRows {
+  const int* gid_of;
+  const long long* gbase;
+  const void* const* grp;
+  const int* grp64;
+  const long long* gnnz;
+  static constexpr bool kCsr = false;
+  __device__ __forceinline__ bool get(long long i, int& row, long long& off, long long& len) const {
+    const int g = gid_of[i];
+    const long long v = i - gbase[g];
+    row = (int)i;
+    long long o0, o1;
+    if (grp64[g]) {
+      o0 = reinterpret_cast<const long long*>(grp[g])[v];
+      o1 = reinterpret_cast<const long long*>(grp[g])[v + 1];
+    } else {
+      o0 = reinterpret_cast<const int*>(grp[g])[v];
+      o1 = reinterpret_cast<const int*>(grp[g])[v + 1];
+    }
+    off = o0;
+    len = o1 - o0;
+    return len >= 0 && len <= INT_MAX && o0 >= 0 && o1 <= gnnz[g];
+  }
+};
+
+__global__ void __launch_bounds__(kWG) fill_gid(const long long* gbase, int count, long long total, int* gid_of) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i >= total) return;
+  int lo = 0, hi = count;   // largest g with gbase[g] <= i
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (gbase[mid] <= i) lo = mid; else hi = mid;
+  }
+  gid_of[i] = lo;
+}
+
+// Per graph: row_ptr[0] = 0 and row_ptr[n] = nnz.
+__global__ void batch_csr_ends(const void* const* grp, const int* grp64, const long long* gbase,
+                               const long long* gnnz, int count, RunScalars* sc) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= count) return;
+  const long long n = gbase[g + 1] - gbase[g];
+  long long a, b;
+  if (grp64[g]) {
+    a = reinterpret_cast<const long long*>(grp[g])[0];
+    b = reinterpret_cast<const long long*>(grp[g])[n];
+  } else {
+    a = reinterpret_cast<const int*>(grp[g])[0];
+    b = reinterpret_cast<const int*>(grp[g])[n];
+  }
+  if (a != 0 || b != gnnz[g]) atomicOr(&sc->err, 1);
+}
+
+// Column range per graph: blockIdx.y is the graph.
+__global__ void __launch_bounds__(kWG) batch_col_range(const int32_t* const* gcol, const long long* gnnz,
+                                                       const long long* gbase, RunScalars* sc) {
+  const int g = blockIdx.y;
+  const long long nnz = gnnz[g];
+  const long long n = gbase[g + 1] - gbase[g];
+  const int32_t* col = gcol[g];
+  bool bad = false;
+  for (long long j = (long long)blockIdx.x * kWG + threadIdx.x; j < nnz; j += (long long)gridDim.x * kWG)
+    if ((unsigned)col[j] >= (unsigned long long)n) bad = true;
+  if (__ballot(bad) && lane_id() == 0) atomicOr(&sc->err, 1);
+}
+
+// Longest row of every graph (a wave whose rows share one graph adds one atomic).
+__global__ void __launch_bounds__(kWG) batch_dmax(const RowDesc* desc, long long count, const int* gid_of,
+                                                  int* gdmax) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  int g = -1, len = 0;
+  if (i < count) {
+    const RowDesc d = desc[i];
+    g = gid_of[d.row];
+    len = d.len;
+  }
+  const int g0 = __shfl(g, 0);
+  const bool uniform = __all(g == g0 || g < 0);
+  if (uniform) {
+    int m = len;
+    for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o));
+    if (lane_id() == 0 && g0 >= 0 && m > 0) atomicMax(&gdmax[g0], m);
+  } else if (g >= 0 && len > 0) {
+    atomicMax(&gdmax[g], len);
+  }
+}
+
+template <bool F32>
+__device__ __forceinline__ bool graph_live(const BatchWalk& a, int g) {
+  const RunScalars& s = a.gsc[g];
+  return !s.done && !s.err;
+}
+
+template <bool F32>
+__device__ __forceinline__ typename Prec<F32>::T batch_strided_sum(const typename Prec<F32>::T* x,
+                                                                   const int32_t* cp, int len, int lane, int G) {
+  using T = typename Prec<F32>::T;
+  T sum = 0;
+  constexpr int B = 8;
+  for (int j0 = lane; j0 < len; j0 += B * G) {
+    int32_t c[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int j = j0 + u * G;
+      c[u] = j < len ? cp[j] : -1;
+    }
+    T v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) v[u] = c[u] >= 0 ? x[c[u]] : (T)0;
+#pragma unroll
+    for (int u = 0; u < B; ++u) sum += v[u];
+  }
+  return sum;
+}
+
+// Row epilogue of the batched walk (same arithmetic as the single-graph one,
+// with the graph's alpha and FP32 scale).
+template <bool F32>
+__device__ __forceinline__ void batch_epilogue(const BatchWalk& a, int r, int g, int row, typename Prec<F32>::T t,
+                                               double& vmax) {
+  const int in = (r + 1) & 1, out = r & 1;
+  (void)in;
+  if constexpr (!F32) {
+    const double s = a.galpha[g] * t;
+    reinterpret_cast<double*>(a.xbuf[out])[row] = s;
+    a.c[row] = (r == 1) ? s : a.c[row] + s;
+    vmax = fmax(vmax, s);
+  } else {
+    const int ex = a.gexp[(long long)g * a.stride + r];
+    const double sigma = a.gsigma[(long long)g * a.stride + r];
+    const float xs = ldexpf(t, -ex);
+    reinterpret_cast<float*>(a.xbuf[out])[row] = xs;
+    const double s = sigma * (double)xs;
+    const double e_prev = (r == 1) ? 0.0 : (double)a.e[row];
+    a.c[row] = (r == 1) ? s : a.c[row] + s;
+    a.e[row] = __double2float_ru((e_prev + a.etap[r] * s) * (1.0 + 0x1p-50));
+    vmax = fmax(vmax, (double)xs);
+  }
+}
+
+// Per-graph maxima: one atomic per wave when the wave's rows share a graph.
+template <bool F32>
+__device__ __forceinline__ void batch_store_max(const BatchWalk& a, int r, int g, double vmax) {
+  const int g0 = __shfl(g, 0);
+  const bool uniform = __all(g == g0 || g < 0);
+  if (uniform) {
+    for (int o = 32; o >= 1; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
+    if (lane_id() == 0 && g0 >= 0 && vmax > 0.0) {
+      if constexpr (F32) atomicMax(&a.gxmax32[(long long)g0 * a.stride + r], __float_as_uint((float)vmax));
+      else atomicMax(&a.gxmax64[(long long)g0 * a.stride + r], (unsigned long long)__double_as_longlong(vmax));
+    }
+  } else if (g >= 0 && vmax > 0.0) {
+    if constexpr (F32) atomicMax(&a.gxmax32[(long long)g * a.stride + r], __float_as_uint((float)vmax));
+    else atomicMax(&a.gxmax64[(long long)g * a.stride + r], (unsigned long long)__double_as_longlong(vmax));
+  }
+}
+
+template <bool F32, int G>
+__device__ __forceinline__ void batch_rows_group(const BatchWalk& a, int r, long long lb, int bin, int& g_out,
+                                                 double& vmax) {
+  using T = typename Prec<F32>::T;
+  constexpr int RPB = kWG / G;
+  const int lane = threadIdx.x & (G - 1);
+  const long long i = lb * RPB + threadIdx.x / G;
+  bool valid = i < a.bin_count[bin];
+  RowDesc d{0, 0, 0};
+  int g = -1;
+  if (valid) {
+    d = a.desc[a.bin_base[bin] + i];
+    g = a.gid_of[d.row];
+    valid = graph_live<F32>(a, g);
+  }
+  T sum = 0;
+  if (valid) {
+    const T* x = reinterpret_cast<const T*>(a.xbuf[(r + 1) & 1]) + a.gbase[g];
+    sum = batch_strided_sum<F32>(x, a.gcol[g] + d.off, d.len, lane, G);
+  }
+#pragma unroll
+  for (int o = G / 2; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, G);
+  if (valid && lane == 0) {
+    batch_epilogue<F32>(a, r, g, d.row, sum, vmax);
+    g_out = g;
+  }
+}
+
+template <bool F32>
+__device__ __forceinline__ typename Prec<F32>::T batch_block_sum(const typename Prec<F32>::T* x, const int32_t* cp,
+                                                                 int len) {
+  using T = typename Prec<F32>::T;
+  __shared__ T part[kWG / kWave];
+  T sum = batch_strided_sum<F32>(x, cp, len, threadIdx.x, kWG);
+  for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
+  if (lane_id() == 0) part[threadIdx.x / kWave] = sum;
+  __syncthreads();
+  const T tot = (part[0] + part[1]) + (part[2] + part[3]);
+  __syncthreads();
+  return tot;
+}
+
+template <bool F32>
+__global__ void __launch_bounds__(kWG) walk_batch(BatchWalk a) {
+  using T = typename Prec<F32>::T;
+  const int r = *a.r_dev;
+  if (r >= a.stride) return;
+  double vmax = 0.0;
+  int g_mine = -1;
+  const long long b = blockIdx.x;
+  int bin = 0;
+  while (bin < NUM_BINS && b >= a.first_block[bin + 1]) ++bin;
+  const long long lb = b - a.first_block[bin];
+  const T* xin = reinterpret_cast<const T*>(a.xbuf[(r + 1) & 1]);
+  switch (bin) {
+    case BIN_HUGE: {
+      __shared__ int s_last;
+      const SegDesc sd = a.segs[lb];
+      const HugeRow h = a.huge[sd.hrow];
+      const int g = a.gid_of[h.row];
+      if (!graph_live<F32>(a, g)) break;          // uniform over the workgroup
+      const T tot = batch_block_sum<F32>(xin + a.gbase[g], a.gcol[g] + sd.off, sd.len);
+      T* part = reinterpret_cast<T*>(a.partial);
+      if (threadIdx.x == 0) {
+        part[sd.part] = tot;
+        __threadfence();
+        s_last = atomicAdd(&a.seg_done[sd.hrow], 1) == h.nseg - 1;
+      }
+      __syncthreads();
+      if (s_last && threadIdx.x < kWave) {
+        __threadfence();
+        const int lane = threadIdx.x;
+        T sum = 0;
+        for (int s2 = lane; s2 < h.nseg; s2 += kWave) sum += part[h.part0 + s2];
+        for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
+        if (lane == 0) {
+          batch_epilogue<F32>(a, r, g, h.row, sum, vmax);
+          g_mine = g;
+          a.seg_done[sd.hrow] = 0;
+        }
+      }
+      break;
+    }
+    case BIN_B256: {
+      const RowDesc d = a.desc[a.bin_base[BIN_B256] + lb];
+      const int g = a.gid_of[d.row];
+      if (!graph_live<F32>(a, g)) break;
+      const T tot = batch_block_sum<F32>(xin + a.gbase[g], a.gcol[g] + d.off, d.len);
+      if (threadIdx.x == 0) {
+        batch_epilogue<F32>(a, r, g, d.row, tot, vmax);
+        g_mine = g;
+      }
+      break;
+    }
+    case BIN_W64: batch_rows_group<F32, 64>(a, r, lb, BIN_W64, g_mine, vmax); break;
+    case BIN_G32: batch_rows_group<F32, 32>(a, r, lb, BIN_G32, g_mine, vmax); break;
+    case BIN_G16: batch_rows_group<F32, 16>(a, r, lb, BIN_G16, g_mine, vmax); break;
+    case BIN_G8: batch_rows_group<F32, 8>(a, r, lb, BIN_G8, g_mine, vmax); break;
+    case BIN_G4: batch_rows_group<F32, 4>(a, r, lb, BIN_G4, g_mine, vmax); break;
+    case BIN_EMPTY: {
+      // Rows without arcs: x_r = 0 (and c_1 = 0, e = 0 at r = 1).
+      const long long i = lb * kWG + threadIdx.x;
+      if (i < a.bin_count[BIN_EMPTY]) {
+        const int row = a.desc[a.bin_base[BIN_EMPTY] + i].row;
+        const int g = a.gid_of[row];
+        if (graph_live<F32>(a, g)) {
+          reinterpret_cast<T*>(a.xbuf[r & 1])[row] = (T)0;
+          if (r == 1) {
+            a.c[row] = 0.0;
+            if constexpr (F32) a.e[row] = 0.0f;
+          }
+        }
+      }
+      break;
+    }
+    default: break;
+  }
+  batch_store_max<F32>(a, r, g_mine, vmax);
+}
+
+// After the selection of iteration r: FP32 scales of iteration r + 1 for every
+// graph still iterating, then r += 1.  Counts the stopped graphs.
+__global__ void __launch_bounds__(kFinishThreads) batch_advance(int* r_dev, int count, RunScalars* gsc,
+                                                                const unsigned* gxmax32, double* gsigma,
+                                                                double* gsigsum, int* gexp, const double* galpha,
+                                                                const int* gclog2, int stride, int fp32,
+                                                                int* ndone) {
+  const int r = *r_dev;
+  __shared__ int s_done;
+  if (threadIdx.x == 0) s_done = 0;
+  __syncthreads();
+  int done = 0;
+  for (int g = threadIdx.x; g < count; g += kFinishThreads) {
+    const RunScalars& s = gsc[g];
+    if (s.done || s.err) {
+      ++done;
+      continue;
+    }
+    if (fp32 && r + 1 < stride) {
+      const long long at = (long long)g * stride;
+      const float M = __uint_as_float(gxmax32[at + r]);
+      int ex = 0;
+      if (M > 0.0f) {
+        (void)frexpf(M, &ex);
+        ex += gclog2[g];
+      }
+      const double sg = ldexp(galpha[g] * gsigma[at + r], ex);
+      gexp[at + r + 1] = ex;
+      gsigma[at + r + 1] = sg;
+      gsigsum[at + r + 1] = gsigsum[at + r] + sg;
+    }
+  }
+  atomicAdd(&s_done, done);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *r_dev = r + 1;
+    *ndone = s_done;
+  }
+}
+
+__global__ void __launch_bounds__(kWG) fill_ones(void* x, long long n, int fp32) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i >= n) return;
+  if (fp32) reinterpret_cast<float*>(x)[i] = 1.0f;
+  else reinterpret_cast<double*>(x)[i] = 1.0;
+}
+
+// Per graph outputs: caller ids (local), bounds, and the largest upper bound
+// outside the graph's top-k.  Block g handles graph g.
+__global__ void __launch_bounds__(kWG) batch_write(const GraphSel* gsel, int32_t* const* out_ids,
+                                                   double* const* out_lo, double* const* out_up,
+                                                   uint8_t* mark, double* rest) {
+  const GraphSel& gs = gsel[blockIdx.x];
+  const int r = gs.sc->iterations;
+  BoundArgs b = gs.b;
+  b.r = r;
+  b.x = gs.xbuf[r & 1];
+  if (b.fp32) {
+    const double u64 = 0x1p-53;
+    const double kap = (2.0 * r + 32.0) * u64;
+    const double ep = gs.etap[r];
+    b.kappa = kap;
+    b.f_lo_c = 1.0 - kap;
+    b.f_hi_c = 1.0 + kap;
+    b.f_e = 1.0 + kap;
+    b.f_lo_s = b.undirected ? b.alpha * (1.0 - ep) * (1.0 - kap) * (1.0 - 8.0 * u64) : 0.0;
+    b.f_hi_s = b.beta * (1.0 + ep) * (1.0 + kap) * (1.0 + 8.0 * u64);
+  }
+  for (int i = threadIdx.x; i < gs.k; i += kWG) {
+    const int v = gs.top_sorted[i];
+    mark[v] = 1;
+    out_ids[blockIdx.x][i] = v - gs.base;
+    out_lo[blockIdx.x][i] = gs.top_lo[i];
+    out_up[blockIdx.x][i] = gs.top_up[i];
+  }
+  __syncthreads();
+  double best = 0.0;
+  for (int i = threadIdx.x; i < gs.n; i += kWG) {
+    const int v = gs.base + i;
+    if (mark[v]) continue;
+    double lo, up;
+    bound_eval(b, v, lo, up);
+    best = fmax(best, up);
+  }
+  __shared__ double wm[kWG / kWave];
+  for (int o = 32; o >= 1; o >>= 1) best = fmax(best, __shfl_xor(best, o));
+  if (lane_id() == 0) wm[threadIdx.x / kWave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) rest[blockIdx.x] = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_batch_prep(const long long* gbase, const void* const* grp, const int* grp64, const long long* gnnz,
+                             const int32_t* const* gcol, int count, long long total_n, long long max_nnz, int* gid_of,
+                             long long* blk, int nblocks, long long* sums, long long* totals, RowDesc* desc,
+                             SegDesc* segs, HugeRow* huge, RunScalars* sc, int validate, hipStream_t s) {
+  const unsigned nb = (unsigned)std::max<long long>(1, (total_n + kWG - 1) / kWG);
+  hipLaunchKernelGGL(fill_gid, dim3(nb), dim3(kWG), 0, s, gbase, count, total_n, gid_of);
+  hipLaunchKernelGGL(batch_csr_ends, dim3((count + 255) / 256), dim3(256), 0, s, grp, grp64, gbase, gnnz, count, sc);
+  if (validate && max_nnz > 0) {
+    const unsigned gx = (unsigned)std::min<long long>(64, (max_nnz + kWG - 1) / kWG);
+    hipLaunchKernelGGL(batch_col_range, dim3(gx, count), dim3(kWG), 0, s, gcol, gnnz, gbase, sc);
+  }
+  const BatchRows rows{gid_of, gbase, grp, grp64, gnnz};
+  hipLaunchKernelGGL(prep_count<BatchRows>, dim3(nblocks), dim3(kWG), 0, s, rows, total_n, blk, nblocks, sc);
+  hipError_t e = launch_prep_scan(blk, nblocks, sums, totals, sc, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(prep_scatter<BatchRows>, dim3(nblocks), dim3(kWG), 0, s, rows, total_n, (const long long*)blk,
+                     nblocks, desc, segs, huge, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_dmax(const RowDesc* desc, long long count, const int* gid_of, int* gdmax, hipStream_t s) {
+  const unsigned nb = (unsigned)std::max<long long>(1, (count + kWG - 1) / kWG);
+  hipLaunchKernelGGL(batch_dmax, dim3(nb), dim3(kWG), 0, s, desc, count, gid_of, gdmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_ones(void* x, long long n, int fp32, hipStream_t s) {
+  const unsigned nb = (unsigned)std::max<long long>(1, (n + kWG - 1) / kWG);
+  hipLaunchKernelGGL(fill_ones, dim3(nb), dim3(kWG), 0, s, x, n, fp32);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, hipStream_t s) {
+  const unsigned grid = (unsigned)std::max<long long>(1, total_blocks);
+  if (a.fp32) hipLaunchKernelGGL(walk_batch<true>, dim3(grid), dim3(kWG), 0, s, a);
+  else hipLaunchKernelGGL(walk_batch<false>, dim3(grid), dim3(kWG), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(int* r_dev, int count, RunScalars* gsc, const unsigned* gxmax32, double* gsigma,
+                                double* gsigsum, int* gexp, const double* galpha, const int* gclog2, int stride,
+                                int fp32, int* ndone, hipStream_t s) {
+  hipLaunchKernelGGL(batch_advance, dim3(1), dim3(kFinishThreads), 0, s, r_dev, count, gsc, gxmax32, gsigma, gsigsum,
+                     gexp, galpha, gclog2, stride, fp32, ndone);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_write(const GraphSel* gsel, int count, int32_t* const* out_ids, double* const* out_lo,
+                              double* const* out_up, uint8_t* mark, double* rest, hipStream_t s) {
+  hipLaunchKernelGGL(batch_write, dim3(count), dim3(kWG), 0, s, gsel, out_ids, out_lo, out_up, mark, rest);
+  return hipGetLastError();
+}
+
+}  // namespace katz

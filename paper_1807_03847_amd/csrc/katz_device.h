@@ -225,4 +225,100 @@ __device__ inline int block_reserve(int* counter, unsigned mask) {
   return base + ex;
 }
 
+// Binning kernels, shared by every row source (header-only templates; each
+// kernel source instantiates its own copies).
+namespace {
+// ---------------------------------------------------------------------------
+// Prep: per-block bin counts, maximum degree, CSR checks.
+// blk layout: [NUM_BINS + 1][nblocks]; column NUM_BINS counts huge segments.
+// ---------------------------------------------------------------------------
+template <class Rows>
+__global__ void __launch_bounds__(kWG) prep_count(Rows rows, long long count, long long* blk, int nblocks,
+                                                  RunScalars* sc) {
+  __shared__ int cnt[NUM_BINS + 1];
+  if (threadIdx.x <= NUM_BINS) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  int dmax = 0;
+  bool bad = false;
+  if (i < count) {
+    int row;
+    long long off, len;
+    if (!rows.get(i, row, off, len)) {
+      bad = true;
+    } else {
+      const int b = bin_of_len(len);
+      atomicAdd(&cnt[b], 1);
+      if (b == BIN_HUGE) atomicAdd(&cnt[NUM_BINS], (int)((len + kSeg - 1) / kSeg));
+      dmax = (int)len;
+    }
+  }
+  if constexpr (Rows::kCsr) {
+    if (i == 0 && ((long long)rows.rp[0] != 0 || (long long)rows.rp[count] != rows.nnz)) bad = true;
+  }
+  __shared__ int wmax[kWG / kWave];
+  for (int o = 32; o >= 1; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o));
+  if (lane_id() == 0) wmax[threadIdx.x / kWave] = dmax;
+  if (bad) atomicOr(&sc->err, 1);
+  __syncthreads();
+  if (threadIdx.x <= NUM_BINS) blk[(long long)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+  // Column NUM_BINS + 1: the block's longest row (reduced by prep_finalize).
+  if (threadIdx.x == 0)
+    blk[(long long)(NUM_BINS + 1) * nblocks + blockIdx.x] = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+}
+
+template <class Rows>
+__global__ void __launch_bounds__(kWG) prep_scatter(Rows rows, long long count, const long long* blk,
+                                                    int nblocks, RowDesc* desc, SegDesc* segs,
+                                                    HugeRow* huge, RunScalars* sc) {
+  if (sc->err) return;
+  __shared__ int wcnt[NUM_BINS][kWG / kWave];
+  __shared__ int wseg[kWG / kWave];
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  const int lane = lane_id();
+  const int w = threadIdx.x / kWave;
+  long long off = 0, len = 0;
+  int row = 0;
+  int bin = -1;
+  int nseg = 0;
+  if (i < count) {
+    rows.get(i, row, off, len);
+    bin = bin_of_len(len);
+    if (bin == BIN_HUGE) nseg = (int)((len + kSeg - 1) / kSeg);
+  }
+  int rank_in_wave = 0;
+  for (int b = 0; b < NUM_BINS; ++b) {
+    const unsigned long long mask = __ballot(bin == b);
+    if (bin == b) rank_in_wave = __popcll(mask & lanemask_lt());
+    if (lane == 0) wcnt[b][w] = __popcll(mask);
+  }
+  // Segment offsets of huge rows inside the wave (inclusive scan of nseg).
+  int sinc = nseg;
+  for (int o = 1; o < kWave; o <<= 1) {
+    int y = __shfl_up(sinc, o);
+    if (lane >= o) sinc += y;
+  }
+  if (lane == kWave - 1) wseg[w] = sinc;
+  __syncthreads();
+  if (i < count) {
+    int before = 0;
+    for (int ww = 0; ww < w; ++ww) before += wcnt[bin][ww];
+    const long long pos = blk[(long long)bin * nblocks + blockIdx.x] + before + rank_in_wave;
+    desc[pos] = RowDesc{off, (int32_t)row, (int32_t)len};
+    if (bin == BIN_HUGE) {
+      int sbefore = 0;
+      for (int ww = 0; ww < w; ++ww) sbefore += wseg[ww];
+      const long long part0 = blk[(long long)NUM_BINS * nblocks + blockIdx.x] + sbefore + sinc - nseg;
+      const long long hidx = pos - sc->bin_base[BIN_HUGE];
+      huge[hidx] = HugeRow{(int32_t)row, (int32_t)len, nseg, (int32_t)part0};
+      for (int sg = 0; sg < nseg; ++sg) {
+        const int slen = (int)min((long long)kSeg, len - (long long)sg * kSeg);
+        segs[part0 + sg] = SegDesc{off + (long long)sg * kSeg, slen, (int32_t)(part0 + sg), (int32_t)hidx, 0};
+      }
+    }
+  }
+}
+
+}  // namespace
+
 }  // namespace katz

@@ -194,10 +194,39 @@ struct GraphSel {
   int cur;                       // host-driven mode: buffer holding M (act[cur])
 };
 
+// The batched walk step (many graphs, global row ids).
+struct BatchWalk {
+  const RowDesc* desc;
+  const SegDesc* segs;
+  const HugeRow* huge;
+  int* seg_done;
+  long long first_block[NUM_BINS + 1];
+  long long bin_base[NUM_BINS];
+  long long bin_count[NUM_BINS];
+  const int* gid_of;
+  const int32_t* const* gcol;
+  const long long* gbase;
+  const double* galpha;
+  const RunScalars* gsc;        // per graph: done / err
+  const double* gsigma;         // [count][stride] FP32 scale sigma_r
+  const int* gexp;              // [count][stride] exponent e_r
+  unsigned* gxmax32;            // [count][stride]
+  unsigned long long* gxmax64;  // [count][stride]
+  void* xbuf[2];
+  double* c;
+  float* e;
+  void* partial;
+  const double* etap;           // eta'_r
+  const int* r_dev;
+  int stride;
+  int fp32;
+};
+
 // ---- launchers (katz_kernels.hip) ----------------------------------------
 hipError_t launch_prep_count(const void* row_ptr, int row_ptr_64, int64_t n, int64_t nnz,
                              long long* blk, int nblocks, RunScalars* sc, hipStream_t s);
-hipError_t launch_prep_scan(long long* blk, int nblocks, RunScalars* sc, hipStream_t s);
+hipError_t launch_prep_scan(long long* blk, int nblocks, long long* sums, long long* totals, RunScalars* sc,
+                            hipStream_t s);
 hipError_t launch_prep_scatter(const void* row_ptr, int row_ptr_64, int64_t n,
                                const long long* blk, int nblocks, RowDesc* desc,
                                SegDesc* segs, HugeRow* huge, RunScalars* sc, hipStream_t s);
@@ -220,8 +249,8 @@ hipError_t launch_init_run(RunScalars* sc, int64_t n, double* sigma, double* sig
                            unsigned* hist, hipStream_t s);
 
 hipError_t launch_prep_rows(const int32_t* ids, long long count, const long long* off, const int* len,
-                            long long* blk, int nblocks, RowDesc* desc, SegDesc* segs, HugeRow* huge,
-                            RunScalars* sc, hipStream_t s);
+                            long long* blk, int nblocks, long long* sums, long long* totals, RowDesc* desc,
+                            SegDesc* segs, HugeRow* huge, RunScalars* sc, hipStream_t s);
 
 // ---- dynamic update (katz_dynamic.hip) ----------------------------------------
 hipError_t launch_scan_ll(const long long* in, long long count, long long* out, long long* sums,
@@ -269,6 +298,20 @@ hipError_t launch_reactivate_all(const BoundArgs& b, long long n, const unsigned
 hipError_t launch_select_wg(const GraphSel* gsel, int count, const int* r_dev, hipStream_t s);
 hipError_t launch_select_wg_one(const GraphSel& one, hipStream_t s);
 constexpr int kSmallActive = 1 << 16;   // |M| at or below which one workgroup selects
+
+// ---- batched form (katz_batch.hip) --------------------------------------------
+hipError_t launch_batch_prep(const long long* gbase, const void* const* grp, const int* grp64, const long long* gnnz,
+                             const int32_t* const* gcol, int count, long long total_n, long long max_nnz, int* gid_of,
+                             long long* blk, int nblocks, long long* sums, long long* totals, RowDesc* desc,
+                             SegDesc* segs, HugeRow* huge, RunScalars* sc, int validate, hipStream_t s);
+hipError_t launch_batch_dmax(const RowDesc* desc, long long count, const int* gid_of, int* gdmax, hipStream_t s);
+hipError_t launch_fill_ones(void* x, long long n, int fp32, hipStream_t s);
+hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, hipStream_t s);
+hipError_t launch_batch_advance(int* r_dev, int count, RunScalars* gsc, const unsigned* gxmax32, double* gsigma,
+                                double* gsigsum, int* gexp, const double* galpha, const int* gclog2, int stride,
+                                int fp32, int* ndone, hipStream_t s);
+hipError_t launch_batch_write(const GraphSel* gsel, int count, int32_t* const* out_ids, double* const* out_lo,
+                              double* const* out_up, uint8_t* mark, double* rest, hipStream_t s);
 
 int bin_of_host(int64_t len);
 

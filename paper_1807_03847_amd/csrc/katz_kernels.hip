@@ -71,132 +71,28 @@ struct ListRows {
   }
 };
 
-// ---------------------------------------------------------------------------
-// Prep: per-block bin counts, maximum degree, CSR checks.
-// blk layout: [NUM_BINS + 1][nblocks]; column NUM_BINS counts huge segments.
-// ---------------------------------------------------------------------------
-template <class Rows>
-__global__ void __launch_bounds__(kWG) prep_count(Rows rows, long long count, long long* blk, int nblocks,
-                                                  RunScalars* sc) {
-  __shared__ int cnt[NUM_BINS + 1];
-  if (threadIdx.x <= NUM_BINS) cnt[threadIdx.x] = 0;
-  __syncthreads();
-  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
-  int dmax = 0;
-  bool bad = false;
-  if (i < count) {
-    int row;
-    long long off, len;
-    if (!rows.get(i, row, off, len)) {
-      bad = true;
-    } else {
-      const int b = bin_of_len(len);
-      atomicAdd(&cnt[b], 1);
-      if (b == BIN_HUGE) atomicAdd(&cnt[NUM_BINS], (int)((len + kSeg - 1) / kSeg));
-      dmax = (int)len;
-    }
-  }
-  if constexpr (Rows::kCsr) {
-    if (i == 0 && ((long long)rows.rp[0] != 0 || (long long)rows.rp[count] != rows.nnz)) bad = true;
-  }
-  __shared__ int wmax[kWG / kWave];
-  for (int o = 32; o >= 1; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o));
-  if (lane_id() == 0) wmax[threadIdx.x / kWave] = dmax;
-  if (bad) atomicOr(&sc->err, 1);
-  __syncthreads();
-  if (threadIdx.x <= NUM_BINS) blk[(long long)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
-  // Column NUM_BINS + 1: the block's longest row (reduced by prep_scan).
-  if (threadIdx.x == 0)
-    blk[(long long)(NUM_BINS + 1) * nblocks + blockIdx.x] = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
-}
-
-__global__ void __launch_bounds__(kFinishThreads) prep_scan(long long* blk, int nblocks, RunScalars* sc) {
+// After the device-wide scans of the bin counts (bin-major) and of the segment
+// counts: bin bases, bin sizes, segment total and the longest row.
+__global__ void __launch_bounds__(kFinishThreads) prep_finalize(const long long* blk, int nblocks,
+                                                                const long long* totals, RunScalars* sc) {
   if (sc->err) return;
-  // Bins are scanned together (bin-major) so each bin is one contiguous range.
-  __shared__ long long firsts[NUM_BINS];
-  if (threadIdx.x < NUM_BINS) firsts[threadIdx.x] = 0;
-  long long total = 0;
-  // Record per-bin totals before the scan overwrites the counts.
-  for (int b = 0; b < NUM_BINS; ++b) {
-    __syncthreads();
-    long long part = 0;
-    for (long long i = threadIdx.x; i < nblocks; i += kFinishThreads) part += blk[(long long)b * nblocks + i];
-    for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o);
-    if (lane_id() == 0) atomicAdd((unsigned long long*)&firsts[b], (unsigned long long)part);
-  }
-  // Longest row: maximum of the per-block column.
-  {
-    long long dm = 0;
-    for (long long i = threadIdx.x; i < nblocks; i += kFinishThreads)
-      dm = max(dm, blk[(long long)(NUM_BINS + 1) * nblocks + i]);
-    for (int o = 32; o >= 1; o >>= 1) dm = max(dm, __shfl_xor(dm, o));
-    if (lane_id() == 0) atomicMax(&sc->dmax, (int)dm);
-  }
+  long long dm = 0;
+  for (long long i = threadIdx.x; i < nblocks; i += kFinishThreads)
+    dm = max(dm, blk[(long long)(NUM_BINS + 1) * nblocks + i]);
+  for (int o = 32; o >= 1; o >>= 1) dm = max(dm, __shfl_xor(dm, o));
+  __shared__ long long wm[kFinishThreads / kWave];
+  if (lane_id() == 0) wm[threadIdx.x / kWave] = dm;
   __syncthreads();
   if (threadIdx.x == 0) {
-    long long acc = 0;
+    for (int i = 0; i < kFinishThreads / kWave; ++i) dm = max(dm, wm[i]);
+    sc->dmax = (int)dm;
     for (int b = 0; b < NUM_BINS; ++b) {
-      sc->bin_count[b] = firsts[b];
-      sc->bin_base[b] = acc;
-      acc += firsts[b];
+      const long long lo = blk[(long long)b * nblocks];
+      const long long hi = b + 1 < NUM_BINS ? blk[(long long)(b + 1) * nblocks] : totals[0];
+      sc->bin_base[b] = lo;
+      sc->bin_count[b] = hi - lo;
     }
-  }
-  __syncthreads();
-  block_exclusive_scan_ll(blk, (long long)NUM_BINS * nblocks, &total);
-  __syncthreads();
-  block_exclusive_scan_ll(blk + (long long)NUM_BINS * nblocks, nblocks, &total);
-  if (threadIdx.x == 0) sc->seg_total = total;
-}
-
-template <class Rows>
-__global__ void __launch_bounds__(kWG) prep_scatter(Rows rows, long long count, const long long* blk,
-                                                    int nblocks, RowDesc* desc, SegDesc* segs,
-                                                    HugeRow* huge, RunScalars* sc) {
-  if (sc->err) return;
-  __shared__ int wcnt[NUM_BINS][kWG / kWave];
-  __shared__ int wseg[kWG / kWave];
-  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
-  const int lane = lane_id();
-  const int w = threadIdx.x / kWave;
-  long long off = 0, len = 0;
-  int row = 0;
-  int bin = -1;
-  int nseg = 0;
-  if (i < count) {
-    rows.get(i, row, off, len);
-    bin = bin_of_len(len);
-    if (bin == BIN_HUGE) nseg = (int)((len + kSeg - 1) / kSeg);
-  }
-  int rank_in_wave = 0;
-  for (int b = 0; b < NUM_BINS; ++b) {
-    const unsigned long long mask = __ballot(bin == b);
-    if (bin == b) rank_in_wave = __popcll(mask & lanemask_lt());
-    if (lane == 0) wcnt[b][w] = __popcll(mask);
-  }
-  // Segment offsets of huge rows inside the wave (inclusive scan of nseg).
-  int sinc = nseg;
-  for (int o = 1; o < kWave; o <<= 1) {
-    int y = __shfl_up(sinc, o);
-    if (lane >= o) sinc += y;
-  }
-  if (lane == kWave - 1) wseg[w] = sinc;
-  __syncthreads();
-  if (i < count) {
-    int before = 0;
-    for (int ww = 0; ww < w; ++ww) before += wcnt[bin][ww];
-    const long long pos = blk[(long long)bin * nblocks + blockIdx.x] + before + rank_in_wave;
-    desc[pos] = RowDesc{off, (int32_t)row, (int32_t)len};
-    if (bin == BIN_HUGE) {
-      int sbefore = 0;
-      for (int ww = 0; ww < w; ++ww) sbefore += wseg[ww];
-      const long long part0 = blk[(long long)NUM_BINS * nblocks + blockIdx.x] + sbefore + sinc - nseg;
-      const long long hidx = pos - sc->bin_base[BIN_HUGE];
-      huge[hidx] = HugeRow{(int32_t)row, (int32_t)len, nseg, (int32_t)part0};
-      for (int sg = 0; sg < nseg; ++sg) {
-        const int slen = (int)min((long long)kSeg, len - (long long)sg * kSeg);
-        segs[part0 + sg] = SegDesc{off + (long long)sg * kSeg, slen, (int32_t)(part0 + sg), (int32_t)hidx, 0};
-      }
-    }
+    sc->seg_total = totals[1];
   }
 }
 
@@ -295,23 +191,29 @@ __device__ __forceinline__ void epilogue(const IterArgs& a, const Epi<F32>& ep, 
 }
 
 // Strided row sum over G lanes: lane l adds elements l, l+G, l+2G, ... in
-// order (four independent loads in flight), then an xor butterfly.
+// order.  Loads are issued eight at a time (eight column ids, then eight
+// gathers) so a lane keeps eight requests in flight; slots past the row end
+// add an exact zero, which leaves the sum and its rounding unchanged.
+constexpr int kBatch = 8;
+
 template <bool F32, int G>
 __device__ __forceinline__ typename Prec<F32>::T strided_sum(const IterArgs& a, const int32_t* cp, int len,
                                                              int lane) {
   using T = typename Prec<F32>::T;
   T sum = 0;
-  int j = lane;
-  for (; j + 3 * G < len; j += 4 * G) {
-    const int32_t c0 = cp[j], c1 = cp[j + G], c2 = cp[j + 2 * G], c3 = cp[j + 3 * G];
-    const T v0 = ldx<F32>(a.x_in, c0), v1 = ldx<F32>(a.x_in, c1);
-    const T v2 = ldx<F32>(a.x_in, c2), v3 = ldx<F32>(a.x_in, c3);
-    sum += v0;
-    sum += v1;
-    sum += v2;
-    sum += v3;
+  for (int j0 = lane; j0 < len; j0 += kBatch * G) {
+    int32_t c[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int j = j0 + u * G;
+      c[u] = j < len ? cp[j] : -1;
+    }
+    T v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) v[u] = c[u] >= 0 ? ldx<F32>(a.x_in, c[u]) : (T)0;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) sum += v[u];
   }
-  for (; j < len; j += G) sum += ldx<F32>(a.x_in, cp[j]);
   return sum;
 }
 
@@ -461,22 +363,22 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
   store_block_max<F32>(a, vmax);
 }
 
-__global__ void __launch_bounds__(kFinishThreads) reduce_blkmax(const void* blkmax, long long nb, int fp32,
-                                                                unsigned* xmax32, unsigned long long* xmax64,
-                                                                int r, const RunScalars* sc) {
+__global__ void __launch_bounds__(kWG) reduce_blkmax(const void* blkmax, long long nb, int fp32,
+                                                     unsigned* xmax32, unsigned long long* xmax64, int r,
+                                                     const RunScalars* sc) {
   if (sc->err || sc->done) return;
-  __shared__ double wm[kFinishThreads / kWave];
+  __shared__ double wm[kWG / kWave];
   double m = 0.0;
-  for (long long i = threadIdx.x; i < nb; i += kFinishThreads)
+  for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < nb; i += (long long)gridDim.x * kWG)
     m = fmax(m, fp32 ? (double)reinterpret_cast<const float*>(blkmax)[i] : reinterpret_cast<const double*>(blkmax)[i]);
   for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
   if (lane_id() == 0) wm[threadIdx.x / kWave] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int i = 1; i < kFinishThreads / kWave; ++i) m = fmax(m, wm[i]);
-    m = fmax(m, wm[0]);
-    if (fp32) xmax32[r] = __float_as_uint((float)m);
-    else xmax64[r] = (unsigned long long)__double_as_longlong(m);
+    m = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
+    // Non-negative values: the IEEE bit patterns order like the values.
+    if (fp32) atomicMax(&xmax32[r], __float_as_uint((float)m));
+    else atomicMax(&xmax64[r], (unsigned long long)__double_as_longlong(m));
   }
 }
 
@@ -887,7 +789,22 @@ __global__ void __launch_bounds__(kWG) remap_rows(const RowDesc* desc, long long
   if (i >= n) return;
   const RowDesc d = desc[i];
   const long long dst = noff[i];
-  for (long long j = lane_id(); j < d.len; j += kWave) ncol[dst + j] = int_of[col[d.off + j]];
+  for (long long j0 = lane_id(); j0 < d.len; j0 += (long long)kBatch * kWave) {
+    int32_t c[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const long long j = j0 + (long long)u * kWave;
+      c[u] = j < d.len ? col[d.off + j] : -1;
+    }
+    int32_t m[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) m[u] = c[u] >= 0 ? int_of[c[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const long long j = j0 + (long long)u * kWave;
+      if (j < d.len) ncol[dst + j] = m[u];
+    }
+  }
 }
 
 __global__ void reset_flags(RunScalars* sc) {
@@ -936,8 +853,15 @@ hipError_t launch_prep_count(const void* row_ptr, int row_ptr_64, int64_t n, int
   return hipGetLastError();
 }
 
-hipError_t launch_prep_scan(long long* blk, int nblocks, RunScalars* sc, hipStream_t s) {
-  hipLaunchKernelGGL(prep_scan, dim3(1), dim3(kFinishThreads), 0, s, blk, nblocks, sc);
+hipError_t launch_prep_scan(long long* blk, int nblocks, long long* sums, long long* totals, RunScalars* sc,
+                            hipStream_t s) {
+  hipError_t e = launch_scan_ll(blk, (long long)NUM_BINS * nblocks, blk, sums, totals, s);
+  if (e != hipSuccess) return e;
+  e = launch_scan_ll(blk + (long long)NUM_BINS * nblocks, nblocks, blk + (long long)NUM_BINS * nblocks, sums,
+                     totals + 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(prep_finalize, dim3(1), dim3(kFinishThreads), 0, s, (const long long*)blk, nblocks,
+                     (const long long*)totals, sc);
   return hipGetLastError();
 }
 
@@ -956,18 +880,20 @@ hipError_t launch_prep_scatter(const void* row_ptr, int row_ptr_64, int64_t n, c
 }
 
 hipError_t launch_prep_rows(const int32_t* ids, long long count, const long long* off, const int* len,
-                            long long* blk, int nblocks, RowDesc* desc, SegDesc* segs, HugeRow* huge,
-                            RunScalars* sc, hipStream_t s) {
+                            long long* blk, int nblocks, long long* sums, long long* totals, RowDesc* desc,
+                            SegDesc* segs, HugeRow* huge, RunScalars* sc, hipStream_t s) {
   if (ids) {
     const ListRows rows{ids, off, len};
     hipLaunchKernelGGL(prep_count<ListRows>, dim3(nblocks), dim3(kWG), 0, s, rows, count, blk, nblocks, sc);
-    hipLaunchKernelGGL(prep_scan, dim3(1), dim3(kFinishThreads), 0, s, blk, nblocks, sc);
+    const hipError_t e = launch_prep_scan(blk, nblocks, sums, totals, sc, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(prep_scatter<ListRows>, dim3(nblocks), dim3(kWG), 0, s, rows, count, (const long long*)blk,
                        nblocks, desc, segs, huge, sc);
   } else {
     const SlackRows rows{off, len};
     hipLaunchKernelGGL(prep_count<SlackRows>, dim3(nblocks), dim3(kWG), 0, s, rows, count, blk, nblocks, sc);
-    hipLaunchKernelGGL(prep_scan, dim3(1), dim3(kFinishThreads), 0, s, blk, nblocks, sc);
+    const hipError_t e = launch_prep_scan(blk, nblocks, sums, totals, sc, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(prep_scatter<SlackRows>, dim3(nblocks), dim3(kWG), 0, s, rows, count, (const long long*)blk,
                        nblocks, desc, segs, huge, sc);
   }
@@ -1008,7 +934,8 @@ hipError_t launch_check_col_range(const int32_t* col, long long nnz, long long n
 
 hipError_t launch_reduce_blkmax(const void* blkmax, long long nb, int fp32, unsigned* xmax32,
                                 unsigned long long* xmax64, int r, const RunScalars* sc, hipStream_t s) {
-  hipLaunchKernelGGL(reduce_blkmax, dim3(1), dim3(kFinishThreads), 0, s, blkmax, nb, fp32, xmax32, xmax64, r, sc);
+  const unsigned grid = (unsigned)std::min<long long>(64, std::max<long long>(1, (nb + kWG - 1) / kWG));
+  hipLaunchKernelGGL(reduce_blkmax, dim3(grid), dim3(kWG), 0, s, blkmax, nb, fp32, xmax32, xmax64, r, sc);
   return hipGetLastError();
 }
 

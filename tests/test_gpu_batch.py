@@ -1,0 +1,97 @@
+"""GPU parity of the batched form (katz_rank_static with count > 1)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthgraph as sg
+from tests.parity import assert_topk_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def K():
+    import paper_1807_03847_amd.katz as katz
+    return katz
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def batch_workload(count, seed, n_lo=10, n_hi=14):
+    """Barabasi-Albert graphs with n log-uniform in [2^n_lo, 2^n_hi], m in 4..32,
+    each with alpha = f/(1 + d_max), f in (0, 1], k in [10, 500] (capped at n/4)
+    and eps = 1e-6 f."""
+    rng = np.random.default_rng(seed)
+    graphs, params = [], []
+    for gidx in range(count):
+        n = int(round(2 ** rng.uniform(n_lo, n_hi)))
+        m = int(rng.integers(4, 33))
+        m = min(m, n // 4)
+        rp, col = sg.barabasi_albert(n, m, 1000 * seed + gidx + 1)
+        f = float(rng.uniform(0.05, 1.0))
+        alpha = f / (1 + sg.max_degree(rp))
+        k = int(min(rng.integers(10, 501), n // 4))
+        graphs.append((rp, col))
+        params.append(dict(k=k, alpha=alpha, eps=1e-6 * f))
+    return graphs, params
+
+
+def run_batch(graphs, params, precision, host=False):
+    katz = K()
+    dev = (lambda a: torch.from_numpy(a)) if host else (lambda a: torch.from_numpy(a).cuda())
+    gl = [(dev(np.asarray(rp, dtype=np.int64)), dev(np.asarray(col, dtype=np.int32)), True) for rp, col in graphs]
+    pl = [dict(pp, precision=precision) for pp in params]
+    return katz.rank_static_batch(gl, pl)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_matches_single_and_oracle(precision):
+    katz = K()
+    graphs, params = batch_workload(24, 3)
+    say("batch", precision, sum(len(rp) - 1 for rp, _ in graphs), "nodes")
+    res = run_batch(graphs, params, precision)
+    for (rp, col), pp, rb in zip(graphs, params, res):
+        orc = oracle.rank_static(rp, col, pp["alpha"], pp["k"], pp["eps"])
+        assert_topk_parity(rb.topk.cpu().numpy(), rb.lower.cpu().numpy(), rb.upper.cpu().numpy(), orc,
+                           gpu_status=rb.status)
+        single = katz.rank_static(torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda(), pp["k"],
+                                  alpha=pp["alpha"], eps=pp["eps"], precision=precision)
+        assert torch.equal(single.topk, rb.topk)
+        assert single.iterations == rb.iterations and single.status == rb.status
+        if precision == "fp64":
+            assert torch.equal(single.lower, rb.lower) and torch.equal(single.upper, rb.upper)
+            assert single.rest_upper_max == rb.rest_upper_max
+
+
+def test_batch_uneven_convergence_and_host_buffers():
+    """Graphs that stop at very different r (small alpha converges fast), host
+    inputs and outputs, a graph with k = n."""
+    graphs, params = batch_workload(6, 9, 10, 12)
+    rp, col = sg.erdos_renyi(300, 900, 5)
+    graphs.append((rp, col))
+    params.append(dict(k=300, alpha=1.0 / (1 + sg.max_degree(rp)), eps=1e-9))
+    params[0]["alpha"] *= 0.01
+    say("batch uneven")
+    res = run_batch(graphs, params, "fp64", host=True)
+    iters = [r.iterations for r in res]
+    assert max(iters) > min(iters)
+    for (rp, col), pp, rb in zip(graphs, params, res):
+        orc = oracle.rank_static(rp, col, pp["alpha"], pp["k"], pp["eps"])
+        assert rb.iterations == orc.iterations
+        assert_topk_parity(rb.topk.numpy(), rb.lower.numpy(), rb.upper.numpy(), orc, gpu_status=rb.status)
+    assert res[-1].rest_upper_max == -np.inf
+
+
+def test_batch_rejects_mixed_precision():
+    katz = K()
+    graphs, params = batch_workload(2, 1, 10, 10)
+    gl = [(torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda(), True) for rp, col in graphs]
+    pl = [dict(params[0], precision="fp64"), dict(params[1], precision="fp32")]
+    with pytest.raises(katz.KatzError) as e:
+        katz.rank_static_batch(gl, pl)
+    assert e.value.code == katz.E_UNSUPPORTED
