@@ -195,6 +195,35 @@ void katz_state_free(katz_state* st);
 /* A static, human-readable description of a status code. */
 const char* katz_strerror(int code);
 
+/* ---- serving: continuous admission of update batches -------------------------
+ * A server owns dynamic states (katz_rank_update, Algorithm 2 of Section 4)
+ * and a pool of `slots` worker threads, each with its own HIP stream on the
+ * device current at creation.  Requests (edge-update batches) of one graph run
+ * in submission order, one at a time, so the result of a request reflects
+ * exactly that graph's batches up to it; requests of different graphs run
+ * concurrently and overlap on the device.  A waiting request is admitted when
+ * a slot is free and its device-memory estimate fits `memory_budget` bytes
+ * (0 = unlimited).  All buffers passed to these calls are host memory. */
+typedef struct katz_server katz_server;
+
+/* 1 <= slots <= 64.  Errors: E_INVALID_ARG, E_HIP. */
+int katz_server_create(int32_t slots, int64_t memory_budget, katz_server** out);
+/* Ranks g statically (katz_rank_static with a state, FP64, undirected) and
+ * registers it; writes its initial result to out and its id to graph_id. */
+int katz_server_add_graph(katz_server* sv, const katz_csr* g, const katz_params* p, katz_result* out,
+                          int32_t* graph_id);
+/* Queues one batch (arrays are copied before returning) and returns a ticket. */
+int katz_server_submit(katz_server* sv, int32_t graph_id, const int32_t* ins_u, const int32_t* ins_v,
+                       int64_t n_ins, const int32_t* del_u, const int32_t* del_v, int64_t n_del,
+                       int64_t* ticket);
+/* Blocks until the ticket's request has run; writes its result (out's arrays:
+ * host, k entries), its latency from submission and its service time in ms
+ * (either pointer may be NULL).  Returns the request's status code. */
+int katz_server_wait(katz_server* sv, int64_t ticket, katz_result* out, double* latency_ms,
+                     double* service_ms);
+/* Stops the workers (requests still queued are dropped) and frees the states. */
+void katz_server_destroy(katz_server* sv);
+
 /* ---- device timing (instrumentation for benchmarks and profiles) ----------
  * While enabled, every ranking call records hipEvent pairs on its own stream
  * around each of its phases and adds the elapsed device times to process-wide

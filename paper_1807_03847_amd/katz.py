@@ -78,6 +78,18 @@ def _load():
     lib.katz_state_free.argtypes = [vp]
     lib.katz_strerror.restype = ctypes.c_char_p
     lib.katz_strerror.argtypes = [ctypes.c_int]
+    lib.katz_server_create.restype = ctypes.c_int
+    lib.katz_server_create.argtypes = [i32, i64, ctypes.POINTER(vp)]
+    lib.katz_server_add_graph.restype = ctypes.c_int
+    lib.katz_server_add_graph.argtypes = [vp, ctypes.POINTER(KatzCSR), ctypes.POINTER(KatzParams),
+                                          ctypes.POINTER(KatzResult), ctypes.POINTER(i32)]
+    lib.katz_server_submit.restype = ctypes.c_int
+    lib.katz_server_submit.argtypes = [vp, i32, vp, vp, i64, vp, vp, i64, ctypes.POINTER(i64)]
+    lib.katz_server_wait.restype = ctypes.c_int
+    lib.katz_server_wait.argtypes = [vp, i64, ctypes.POINTER(KatzResult), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.katz_server_destroy.restype = None
+    lib.katz_server_destroy.argtypes = [vp]
     lib.katz_timing_enable.restype = None
     lib.katz_timing_enable.argtypes = [ctypes.c_int]
     lib.katz_timing_read.restype = ctypes.c_int
@@ -257,6 +269,78 @@ def create_state(row_ptr, col, k, *, alpha=0.0, eps=0.0, max_iter=0, degree_cap=
     if rc < 0:
         raise KatzError(rc)
     return State(handle.value, k, device), _to_result(res, ids, lo, up)
+
+
+class Server:
+    """katz_server: worker slots with their own streams, per-graph FIFO order,
+    admission by free slots and a device-memory budget."""
+
+    def __init__(self, slots=4, memory_budget=0):
+        h = ctypes.c_void_p(0)
+        rc = lib.katz_server_create(int(slots), int(memory_budget), ctypes.byref(h))
+        if rc < 0:
+            raise KatzError(rc)
+        self._h = h.value
+        self._k = {}
+
+    def add_graph(self, row_ptr, col, k, *, alpha=0.0, eps=0.0, max_iter=0, degree_cap=0,
+                  validate=VALIDATE_BASIC):
+        """Registers a graph (host or device CSR); returns (graph_id, initial RankResult on the host)."""
+        import numpy as np
+        g = make_csr(row_ptr, col, True)
+        p = make_params(k, alpha, eps, "fp64", max_iter, validate, degree_cap)
+        ids = np.empty(k, dtype=np.int32)
+        lo = np.empty(k, dtype=np.float64)
+        up = np.empty(k, dtype=np.float64)
+        res = KatzResult(topk_ids=ids.ctypes.data, lower=lo.ctypes.data, upper=up.ctypes.data)
+        gid = ctypes.c_int32(0)
+        rc = lib.katz_server_add_graph(ctypes.c_void_p(self._h), ctypes.byref(g), ctypes.byref(p),
+                                       ctypes.byref(res), ctypes.byref(gid))
+        if rc < 0:
+            raise KatzError(rc)
+        self._k[gid.value] = k
+        return gid.value, _to_result(res, ids, lo, up)
+
+    def submit(self, graph_id, ins=None, dels=None) -> int:
+        import numpy as np
+        ins = np.asarray(ins if ins is not None else np.zeros((0, 2)), dtype=np.int32).reshape(-1, 2)
+        dels = np.asarray(dels if dels is not None else np.zeros((0, 2)), dtype=np.int32).reshape(-1, 2)
+        iu, iv = np.ascontiguousarray(ins[:, 0]), np.ascontiguousarray(ins[:, 1])
+        du, dv = np.ascontiguousarray(dels[:, 0]), np.ascontiguousarray(dels[:, 1])
+        t = ctypes.c_int64(0)
+        rc = lib.katz_server_submit(ctypes.c_void_p(self._h), int(graph_id), iu.ctypes.data, iv.ctypes.data,
+                                    len(iu), du.ctypes.data, dv.ctypes.data, len(du), ctypes.byref(t))
+        if rc < 0:
+            raise KatzError(rc)
+        self._k[("t", t.value)] = self._k[graph_id]
+        return t.value
+
+    def wait(self, ticket):
+        """Returns (RankResult with host arrays, latency_ms, service_ms); raises on errors."""
+        import numpy as np
+        k = self._k.pop(("t", ticket))
+        ids = np.empty(k, dtype=np.int32)
+        lo = np.empty(k, dtype=np.float64)
+        up = np.empty(k, dtype=np.float64)
+        res = KatzResult(topk_ids=ids.ctypes.data, lower=lo.ctypes.data, upper=up.ctypes.data)
+        lat = ctypes.c_double(0)
+        svc = ctypes.c_double(0)
+        rc = lib.katz_server_wait(ctypes.c_void_p(self._h), int(ticket), ctypes.byref(res), ctypes.byref(lat),
+                                  ctypes.byref(svc))
+        if rc < 0:
+            raise KatzError(rc)
+        return _to_result(res, ids, lo, up), lat.value, svc.value
+
+    def close(self):
+        if self._h:
+            lib.katz_server_destroy(ctypes.c_void_p(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def timing_enable(on: bool = True) -> None:

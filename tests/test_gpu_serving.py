@@ -1,0 +1,111 @@
+"""Serving form: each request's result is the same alone and in the mix."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synthgraph as sg
+
+pytestmark = pytest.mark.gpu
+
+
+def K():
+    import paper_1807_03847_amd.katz as katz
+    return katz
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def request_stream(rp, col, n, count, rng, max_batch=60, hubs=()):
+    """`count` valid batches applied in order: 70% insertions of absent edges,
+    30% deletions of present ones (undirected pairs a < b)."""
+    src = np.repeat(np.arange(n), np.diff(rp))
+    edges = set(zip(src[src < col].tolist(), col[src < col].tolist()))
+    out = []
+    for _ in range(count):
+        size = int(rng.integers(1, max_batch + 1))
+        n_ins = max(1, int(round(0.7 * size)))
+        n_del = size - n_ins
+        dels = [tuple(e) for e in rng.permutation(sorted(edges))[:n_del].tolist()] if n_del else []
+        ins = set()
+        while len(ins) < n_ins:
+            a = int(rng.choice(hubs)) if len(hubs) and rng.random() < 0.3 else int(rng.integers(0, n))
+            b = int(rng.integers(0, n))
+            a, b = min(a, b), max(a, b)
+            if a != b and (a, b) not in edges and (a, b) not in ins:
+                ins.add((a, b))
+        for e in dels:
+            edges.discard(e)
+        edges |= ins
+        out.append((np.array(sorted(ins), dtype=np.int64).reshape(-1, 2),
+                    np.array(dels, dtype=np.int64).reshape(-1, 2)))
+    return out
+
+
+def make_graphs():
+    gs = [sg.erdos_renyi(2000, 8000, 3), sg.rmat(12, seed=4), sg.barabasi_albert(3000, 5, 6)]
+    out = []
+    for rp, col in gs:
+        dmax = sg.max_degree(rp)
+        H = 200
+        out.append((rp, col, 1.0 / (1 + dmax + H), dmax + H))
+    return out
+
+
+@pytest.mark.parametrize("slots,budget", [(3, 0), (2, 1)])
+def test_serving_mix_equals_alone(slots, budget):
+    katz = K()
+    rng = np.random.default_rng(slots)
+    graphs = make_graphs()
+    k, eps = 25, 1e-9
+    streams = []
+    for rp, col, alpha, cap in graphs:
+        hubs = np.argsort(-np.diff(rp))[:5]
+        streams.append(request_stream(rp, col, len(rp) - 1, 8, rng, hubs=hubs))
+    say("serving mix", slots, budget)
+    sv = katz.Server(slots=slots, memory_budget=budget)
+    gids = []
+    for rp, col, alpha, cap in graphs:
+        gid, _ = sv.add_graph(torch.from_numpy(rp), torch.from_numpy(col), k, alpha=alpha, eps=eps, degree_cap=cap)
+        gids.append(gid)
+    tickets = []
+    for j in range(8):                      # interleave the graphs' requests
+        for gi, gid in enumerate(gids):
+            ins, dels = streams[gi][j]
+            tickets.append((gi, j, sv.submit(gid, ins, dels)))
+    mixed = {}
+    for gi, j, t in tickets:
+        res, lat, svc = sv.wait(t)
+        assert lat >= svc > 0
+        mixed[(gi, j)] = res
+    sv.close()
+    say("serving alone")
+    for gi, (rp, col, alpha, cap) in enumerate(graphs):
+        st, _ = katz.create_state(torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda(), k, alpha=alpha,
+                                  eps=eps, degree_cap=cap)
+        for j, (ins, dels) in enumerate(streams[gi]):
+            alone = st.update(ins, dels)
+            m = mixed[(gi, j)]
+            assert np.array_equal(alone.topk.cpu().numpy(), m.topk)
+            assert np.array_equal(alone.lower.cpu().numpy(), m.lower)
+            assert np.array_equal(alone.upper.cpu().numpy(), m.upper)
+            assert (alone.iterations, alone.status) == (m.iterations, m.status)
+        st.free()
+
+
+def test_serving_reports_errors_per_request():
+    katz = K()
+    rp, col = sg.erdos_renyi(500, 2000, 8)
+    sv = katz.Server(slots=2)
+    gid, _ = sv.add_graph(torch.from_numpy(rp), torch.from_numpy(col), 10, alpha=1.0 / (2 + sg.max_degree(rp)),
+                          eps=1e-9, degree_cap=sg.max_degree(rp) + 1)
+    src = np.repeat(np.arange(500), np.diff(rp))
+    t_bad = sv.submit(gid, np.array([[src[0], col[0]]]), None)       # already present
+    with pytest.raises(katz.KatzError) as e:
+        sv.wait(t_bad)
+    assert e.value.code == katz.E_UPDATE
+    sv.close()
