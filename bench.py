@@ -59,6 +59,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
+    ap.add_argument("--workload", default="static", choices=["static", "batched", "serving"],
+                    help="static: R-MAT 22 (the headline line); batched: 256 Barabasi-Albert graphs; "
+                         "serving: update batches against R-MAT 24")
+    ap.add_argument("--requests", type=int, default=200, help="serving: requests per load point")
+    ap.add_argument("--graphs", type=int, default=256, help="batched: number of graphs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -70,6 +75,11 @@ def main():
 
     import synthgraph as sg
     import paper_1807_03847_amd.katz as katz
+
+    if args.workload == "batched":
+        return bench_batched(args, katz, sg, torch, np)
+    if args.workload == "serving":
+        return bench_serving(args, katz, sg, torch, np)
 
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib * (1 << 18), dtype=torch.float32, device="cuda")
@@ -188,6 +198,159 @@ def main():
             "fp32": bool(np.array_equal(idx, orc.topk)),
             "fp64": bool(np.array_equal(f64["res"].topk.cpu().numpy(), orc.topk)),
         }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args, katz, sg, torch, np):
+    """256 Barabasi-Albert graphs, n log-uniform in [2^10, 2^18], m in 4..32 new
+    edges per node, alpha_g = f_g / (1 + d_max,g) with f_g in (0, 1], k_g in
+    [10, 500], eps_g = 1e-6 f_g (seeds 1..256); one katz_rank_static call with
+    count = 256, FP32 walk vector with FP64 bounds."""
+    from concurrent.futures import ThreadPoolExecutor
+    rng = np.random.default_rng(2026)
+    specs = []
+    for gidx in range(args.graphs):
+        n = int(round(2 ** rng.uniform(10, 18)))
+        m = int(rng.integers(4, 33))
+        specs.append((n, m, gidx + 1, float(rng.uniform(1e-3, 1.0)), int(rng.integers(10, 501))))
+    t = time.perf_counter()
+    with ThreadPoolExecutor(16) as ex:
+        csrs = list(ex.map(lambda sp: sg.barabasi_albert(sp[0], sp[1], sp[2]), specs))
+    nnz = sum(int(rp[-1]) for rp, _ in csrs)
+    ntot = sum(len(rp) - 1 for rp, _ in csrs)
+    print(f"[bench] batched graphs generated: {len(csrs)} graphs, n={ntot} nnz={nnz} "
+          f"({time.perf_counter() - t:.1f}s)", flush=True)
+    graphs = [(torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda(), True) for rp, col in csrs]
+    params = []
+    for (rp, col), (n, m, seed, f, k) in zip(csrs, specs):
+        params.append(dict(k=min(k, n), alpha=f / (1 + int(np.max(np.diff(rp)))), eps=1e-6 * f, precision="fp32"))
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        res = katz.rank_static_batch(graphs, params)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = katz.rank_static_batch(graphs, params)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    traversed = sum(r.iterations * int(rp[-1]) for r, (rp, _) in zip(res, csrs))
+    out = {
+        "metric": "batched certified top-k Katz ranking: GTEPS over 256 graphs, one call, 1 GPU",
+        "value": round(traversed / sec / 1e9, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "ba256_batched", "graphs": len(csrs), "n_total": ntot, "nnz_total": nnz,
+                   "iterations_max": max(r.iterations for r in res),
+                   "iterations_min": min(r.iterations for r in res)},
+        "status_counts": {str(st): sum(1 for r in res if r.status == st) for st in sorted({r.status for r in res})},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serving_requests(rp, col, n, count, rng, np):
+    """Update batches of size round(10^U(0,4)): 70% insertions (R-MAT-distributed
+    endpoints, absent edges), 30% deletions of original edges (each at most once)."""
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    keys = src * n + col
+    und = np.nonzero(src < col)[0]
+    order = rng.permutation(und.size)
+    taken = 0
+    inserted = set()
+    out = []
+    for _ in range(count):
+        size = max(1, int(round(10 ** rng.uniform(0, 4))))
+        n_del = int(round(0.3 * size))
+        n_ins = size - n_del
+        di = und[order[taken:taken + n_del]]
+        taken += n_del
+        dels = np.stack([src[di], col[di].astype(np.int64)], 1)
+        ins = []
+        while len(ins) < n_ins:
+            a = rng.integers(0, n, 2 * (n_ins - len(ins)) + 8)
+            b = rng.integers(0, n, a.size)
+            lo, hi = np.minimum(a, b), np.maximum(a, b)
+            cand = lo * n + hi
+            pos = np.searchsorted(keys, cand)
+            present = (pos < keys.size) & (keys[np.minimum(pos, keys.size - 1)] == cand)
+            for x, y, pr in zip(lo.tolist(), hi.tolist(), present.tolist()):
+                if x != y and not pr and (x, y) not in inserted:
+                    inserted.add((x, y))
+                    ins.append((x, y))
+                    if len(ins) == n_ins:
+                        break
+        out.append((np.array(ins, dtype=np.int64).reshape(-1, 2), dels))
+    return out
+
+
+def bench_serving(args, katz, sg, torch, np):
+    """R-MAT scale 24 (seed 2) resident on the device; alpha = 1/(1 + d_max + 1e5),
+    degree cap d_max + 1e5, k = 100, eps = 1e-6; update batches arrive as a
+    Poisson process at a fraction of the measured saturation rate."""
+    import threading
+    t = time.perf_counter()
+    rp, col = sg.rmat(24, 16, 0.57, 0.19, 0.19, seed=2)
+    n = len(rp) - 1
+    dmax = int(np.max(np.diff(rp)))
+    H = 100000
+    print(f"[bench] serving graph: n={n} nnz={int(rp[-1])} dmax={dmax} ({time.perf_counter() - t:.1f}s)", flush=True)
+    rng = np.random.default_rng(24)
+    total = args.requests * 3
+    reqs = serving_requests(rp, col, n, total, rng, np)
+    print(f"[bench] {total} requests generated, {sum(len(a) + len(b) for a, b in reqs)} edge updates", flush=True)
+    sv = katz.Server(slots=4)
+    gid, _ = sv.add_graph(torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda(), 100,
+                          alpha=1.0 / (1 + dmax + H), eps=1e-6, degree_cap=dmax + H)
+    torch.cuda.synchronize()
+    # Saturation: the first block of requests submitted at once.
+    block = reqs[:args.requests]
+    t0 = time.perf_counter()
+    tick = [sv.submit(gid, a, b) for a, b in block]
+    svc = [sv.wait(tk)[2] for tk in tick]
+    sat = len(block) / (time.perf_counter() - t0)
+    print(f"[bench] saturation {sat:.1f} req/s", flush=True)
+    points = []
+    for frac, chunk in ((0.5, reqs[args.requests:2 * args.requests]), (0.8, reqs[2 * args.requests:])):
+        lam = frac * sat
+        gaps = rng.exponential(1.0 / lam, len(chunk))
+        tickets = []
+
+        def submitter():
+            t_next = time.perf_counter()
+            for (a, b), gap in zip(chunk, gaps):
+                t_next += gap
+                delay = t_next - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                tickets.append(sv.submit(gid, a, b))
+
+        t0 = time.perf_counter()
+        th = threading.Thread(target=submitter)
+        th.start()
+        lat = []
+        i = 0
+        while i < len(chunk):
+            if i < len(tickets):
+                lat.append(sv.wait(tickets[i])[1])
+                i += 1
+            else:
+                time.sleep(0.0005)
+        th.join()
+        wall = time.perf_counter() - t0
+        edges = sum(len(a) + len(b) for a, b in chunk)
+        points.append({"load": frac, "arrival_rate": round(lam, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                       "p99_ms": round(float(np.percentile(lat, 99)), 3), "requests_per_s": round(len(chunk) / wall, 2),
+                       "edge_updates_per_s": round(edges / wall, 1)})
+        print(f"[bench] load {frac}: {points[-1]}", flush=True)
+    sv.close()
+    out = {
+        "metric": "serving dynamic updates: p50/p99 latency and throughput, 1 GPU",
+        "value": points[0]["p50_ms"], "unit": "ms p50 latency at 50% load", "n_gpus": 1,
+        "steps": len(reqs), "warmup": 0, "ms_per_step": round(float(np.mean(svc)), 4), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "rmat24_serving", "n": n, "nnz_directed": int(rp[-1]), "k": 100, "eps": 1e-6,
+                   "batch": "round(10^U(0,4)) edges, 70% insertions", "slots": 4},
+        "saturation_requests_per_s": round(sat, 2), "load_points": points,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -426,6 +426,9 @@ struct katz_state {
   unsigned long long* min_bits = nullptr;
   uint8_t* tmark = nullptr;        // touched rows
   katz::RunScalars* sc2 = nullptr;       // prep of one level
+  int32_t* out_ids = nullptr;      // [k] staging for outputs in host memory
+  double* out_lo = nullptr;
+  double* out_up = nullptr;
   katz::UpdateBufs ub;
   int X_dev_synced = 0;            // entries of X already copied to X_dev
   katz::HostSync hs;
@@ -706,6 +709,7 @@ int write_result(Run& run, HostSync& hs, katz_result* out, int32_t* stage_ids, d
   int32_t* ids = direct ? out->topk_ids : stage_ids;
   double* lo = direct ? out->lower : stage_lo;
   double* up = direct ? out->upper : stage_up;
+  if (!ids || !lo || !up) return KATZ_E_INVALID_ARG;
   const int tr = T.start(T_RESULT, s);
   KATZ_HIP(hipMemsetAsync(run.w->mark, 0, (size_t)run.n, s));
   KATZ_HIP(hipMemsetAsync(run.w->rest_bits, 0, sizeof(unsigned long long), s));
@@ -866,7 +870,7 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
   if (pl.reorder) {
     // Renumber by the binned order and rebuild the bins on the renumbered rows
     // (now contiguous per bin).  Column ids were range-checked above.
-    KATZ_HIP(launch_relabel(b.desc, g->n, stg.col, stg.ext_of, stg.int_of, stg.len_ll, stg.len32, stg.noff,
+    KATZ_HIP(launch_relabel(b.desc, g->n, b.bin_base, b.bin_count, stg.col, stg.ext_of, stg.int_of, stg.len_ll, stg.len32, stg.noff,
                             stg.sums, stg.total, stg.ncol, s));
     KATZ_HIP(hipMemsetAsync(b.seg_done, 0, sizeof(int) * b.huge_cap, s));
     KATZ_HIP(launch_prep_rows(nullptr, g->n, stg.noff, stg.len32, b.blk, b.nblocks, b.scan_sums, b.scan_totals,
@@ -1589,10 +1593,13 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
   st->err_dev = dalloc<int>(st, 1);
   st->min_bits = dalloc<unsigned long long>(st, 1);
   st->tmark = dalloc<uint8_t>(st, n);
+  st->out_ids = dalloc<int32_t>(st, st->k);
+  st->out_lo = dalloc<double>(st, st->k);
+  st->out_up = dalloc<double>(st, st->k);
   if (!w.c || !w.act[0] || !w.act[1] || !w.keys || !w.cand_key[0] || !w.cand_key[1] || !w.cand_v[0] ||
       !w.cand_v[1] || !w.hist || !w.xmax32 || !w.xmax64 || !w.sigma || !w.sigma_sum || !w.top_sorted ||
       !w.top_lo || !w.top_up || !w.mark || !w.rest_bits || !st->level_of || !st->clist || !st->counter ||
-      !st->dmax_dev || !st->err_dev || !st->min_bits || !st->tmark)
+      !st->dmax_dev || !st->err_dev || !st->min_bits || !st->tmark || !st->out_ids || !st->out_lo || !st->out_up)
     return KATZ_E_OOM;
   KATZ_HIP(hipMemsetAsync(w.mark, 0, n, s));
   KATZ_HIP(hipMemsetAsync(st->tmark, 0, n, s));
@@ -1607,7 +1614,7 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
   KATZ_TRY(iterate(run, st->hs, 1, false, s, T));
   st->r = st->hs.sc->iterations;
   st->cur = st->hs.sc->cur;
-  const int status = write_result(run, st->hs, out, nullptr, nullptr, nullptr, s, T);
+  const int status = write_result(run, st->hs, out, st->out_ids, st->out_lo, st->out_up, s, T);
   guard.keep = true;
   *stp = st;
   return status;
@@ -1886,7 +1893,7 @@ int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, lon
   KATZ_TRY(iterate(run, st->hs, st->r + 1, true, s, T));
   st->r = st->hs.sc->iterations;
   st->cur = st->hs.sc->cur;
-  return write_result(run, st->hs, out, nullptr, nullptr, nullptr, s, T);
+  return write_result(run, st->hs, out, st->out_ids, st->out_lo, st->out_up, s, T);
 }
 
 }  // namespace

@@ -782,18 +782,23 @@ __global__ void __launch_bounds__(kWG) relabel_ids(const RowDesc* desc, long lon
   len32[i] = d.len;
 }
 
-// One wave per new row: its arcs in their original order, targets renamed.
-__global__ void __launch_bounds__(kWG) remap_rows(const RowDesc* desc, long long n, const int32_t* col,
-                                                  const int32_t* int_of, const long long* noff, int32_t* ncol) {
-  const long long i = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave;
-  if (i >= n) return;
+// G lanes per new row (the row's bin decides G): its arcs in their original
+// order, targets renamed.  Rows of one bin are new ids first .. first+count-1.
+template <int G>
+__global__ void __launch_bounds__(kWG) remap_rows(const RowDesc* desc, long long first, long long count,
+                                                  const int32_t* col, const int32_t* int_of, const long long* noff,
+                                                  int32_t* ncol) {
+  constexpr int RPB = kWG / G;
+  const long long i = first + (long long)blockIdx.x * RPB + threadIdx.x / G;
+  if (i >= first + count) return;
+  const int lane = threadIdx.x & (G - 1);
   const RowDesc d = desc[i];
   const long long dst = noff[i];
-  for (long long j0 = lane_id(); j0 < d.len; j0 += (long long)kBatch * kWave) {
+  for (long long j0 = lane; j0 < d.len; j0 += (long long)kBatch * G) {
     int32_t c[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      const long long j = j0 + (long long)u * kWave;
+      const long long j = j0 + (long long)u * G;
       c[u] = j < d.len ? col[d.off + j] : -1;
     }
     int32_t m[kBatch];
@@ -801,10 +806,19 @@ __global__ void __launch_bounds__(kWG) remap_rows(const RowDesc* desc, long long
     for (int u = 0; u < kBatch; ++u) m[u] = c[u] >= 0 ? int_of[c[u]] : 0;
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      const long long j = j0 + (long long)u * kWave;
+      const long long j = j0 + (long long)u * G;
       if (j < d.len) ncol[dst + j] = m[u];
     }
   }
+}
+
+template <int G>
+void launch_remap_bin(const RowDesc* desc, long long first, long long count, const int32_t* col,
+                      const int32_t* int_of, const long long* noff, int32_t* ncol, hipStream_t s) {
+  if (count <= 0) return;
+  constexpr int RPB = kWG / G;
+  const unsigned nb = (unsigned)((count + RPB - 1) / RPB);
+  hipLaunchKernelGGL(remap_rows<G>, dim3(nb), dim3(kWG), 0, s, desc, first, count, col, int_of, noff, ncol);
 }
 
 __global__ void reset_flags(RunScalars* sc) {
@@ -821,16 +835,21 @@ __global__ void reset_flags(RunScalars* sc) {
 
 }  // namespace
 
-hipError_t launch_relabel(const RowDesc* desc, long long n, const int32_t* col, int32_t* ext_of, int32_t* int_of,
-                          long long* len_ll, int* len32, long long* noff, long long* sums, long long* total,
-                          int32_t* ncol, hipStream_t s) {
+hipError_t launch_relabel(const RowDesc* desc, long long n, const long long* bin_base, const long long* bin_count,
+                          const int32_t* col, int32_t* ext_of, int32_t* int_of, long long* len_ll, int* len32,
+                          long long* noff, long long* sums, long long* total, int32_t* ncol, hipStream_t s) {
   const unsigned nb = (unsigned)std::max<long long>(1, (n + kWG - 1) / kWG);
   hipLaunchKernelGGL(relabel_ids, dim3(nb), dim3(kWG), 0, s, desc, n, ext_of, int_of, len_ll, len32);
   const hipError_t e = launch_scan_ll(len_ll, n, noff, sums, total, s);
   if (e != hipSuccess) return e;
-  const unsigned nw = (unsigned)std::max<long long>(1, (n * kWave + kWG - 1) / kWG);
-  hipLaunchKernelGGL(remap_rows, dim3(nw), dim3(kWG), 0, s, desc, n, col, (const int32_t*)int_of,
-                     (const long long*)noff, ncol);
+  const int32_t* io = int_of;
+  launch_remap_bin<kWG>(desc, bin_base[BIN_HUGE], bin_count[BIN_HUGE], col, io, noff, ncol, s);
+  launch_remap_bin<kWG>(desc, bin_base[BIN_B256], bin_count[BIN_B256], col, io, noff, ncol, s);
+  launch_remap_bin<64>(desc, bin_base[BIN_W64], bin_count[BIN_W64], col, io, noff, ncol, s);
+  launch_remap_bin<32>(desc, bin_base[BIN_G32], bin_count[BIN_G32], col, io, noff, ncol, s);
+  launch_remap_bin<16>(desc, bin_base[BIN_G16], bin_count[BIN_G16], col, io, noff, ncol, s);
+  launch_remap_bin<8>(desc, bin_base[BIN_G8], bin_count[BIN_G8], col, io, noff, ncol, s);
+  launch_remap_bin<4>(desc, bin_base[BIN_G4], bin_count[BIN_G4], col, io, noff, ncol, s);
   return hipGetLastError();
 }
 

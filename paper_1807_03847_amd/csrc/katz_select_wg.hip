@@ -15,7 +15,7 @@ namespace {
 // a device counter (same expressions as the host-side bound arguments).
 __device__ void refresh_bounds(BoundArgs& b, const GraphSel& gs, int r) {
   b.r = r;
-  b.x = gs.xbuf[r & 1];
+  b.x = (r & 1) ? gs.xbuf[1] : gs.xbuf[0];
   if (b.fp32) {
     const double u64 = 0x1p-53;
     const double kap = (2.0 * r + 32.0) * u64;
@@ -37,15 +37,16 @@ struct SortArea {
   int ext[kMaxK];
 };
 
-__global__ void __launch_bounds__(kFinishThreads) select_wg(const GraphSel* gsel, GraphSel one, const int* r_dev) {
-  const GraphSel& gs = gsel ? gsel[blockIdx.x] : one;
+// Two kernels share the body, so that each reads its GraphSel from one address
+// space (global memory or the kernel arguments) and needs no private copy.
+__device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_dev) {
   RunScalars* sc = gs.sc;
   if (sc->done || sc->err) return;
   BoundArgs b = gs.b;
   if (r_dev) refresh_bounds(b, gs, *r_dev);
   const int cur = r_dev ? sc->cur : gs.cur;
-  const int32_t* act_in = gs.act[cur];
-  int32_t* act_out = const_cast<int32_t*>(gs.act[cur ^ 1]);
+  const int32_t* act_in = cur ? gs.act[1] : gs.act[0];
+  int32_t* act_out = const_cast<int32_t*>(cur ? gs.act[0] : gs.act[1]);
   const bool identity = r_dev ? (b.r == 1) : gs.identity_in;
   const int m = identity ? gs.n : sc->m;
   const int k = gs.k;
@@ -139,10 +140,9 @@ __global__ void __launch_bounds__(kFinishThreads) select_wg(const GraphSel* gsel
       s_idneed = need;
     }
     __syncthreads();
-    const int widths[3] = {11, 11, 9};
     int shift = 31;
     for (int L = 0; L < 3; ++L) {
-      const int width = widths[L];
+      const int width = L < 2 ? 11 : 9;
       const int hishift = shift;
       shift -= width;
       for (int d = t; d < kDigits; d += kFinishThreads) sm.h[d] = 0u;
@@ -258,16 +258,21 @@ __global__ void __launch_bounds__(kFinishThreads) select_wg(const GraphSel* gsel
   }
 }
 
+__global__ void __launch_bounds__(kFinishThreads) select_wg(const GraphSel* gsel, const int* r_dev) {
+  select_graph(gsel[blockIdx.x], r_dev);
+}
+
+__global__ void __launch_bounds__(kFinishThreads) select_wg_one(GraphSel one) { select_graph(one, nullptr); }
+
 }  // namespace
 
 hipError_t launch_select_wg(const GraphSel* gsel, int count, const int* r_dev, hipStream_t s) {
-  if (count > 0) hipLaunchKernelGGL(select_wg, dim3(count), dim3(kFinishThreads), 0, s, gsel, GraphSel{}, r_dev);
+  if (count > 0) hipLaunchKernelGGL(select_wg, dim3(count), dim3(kFinishThreads), 0, s, gsel, r_dev);
   return hipGetLastError();
 }
 
 hipError_t launch_select_wg_one(const GraphSel& one, hipStream_t s) {
-  hipLaunchKernelGGL(select_wg, dim3(1), dim3(kFinishThreads), 0, s, (const GraphSel*)nullptr, one,
-                     (const int*)nullptr);
+  hipLaunchKernelGGL(select_wg_one, dim3(1), dim3(kFinishThreads), 0, s, one);
   return hipGetLastError();
 }
 

@@ -164,3 +164,43 @@ def test_empty_batch_is_a_noop():
     assert torch.equal(r0.topk, r1.topk) and torch.equal(r0.lower, r1.lower)
     assert r1.iterations == r0.iterations
     st.free()
+
+
+def test_host_outputs_match_device_outputs():
+    """States created from host buffers write their results into host memory
+    (creation and every update) through device staging; results equal the
+    device-memory path bitwise."""
+    katz = K()
+    rng = np.random.default_rng(11)
+    rp, col = sg.erdos_renyi(1500, 6000, 21)
+    n = len(rp) - 1
+    dmax = sg.max_degree(rp)
+    alpha, cap, k = 1.0 / (dmax + 40), dmax + 39, 20
+    say("host outputs", n)
+    st_h, r_h = katz.create_state(torch.from_numpy(rp), torch.from_numpy(col), k, alpha=alpha, eps=1e-9,
+                                  degree_cap=cap)
+    st_d, r_d = katz.create_state(*dev(rp, col), k, alpha=alpha, eps=1e-9, degree_cap=cap)
+    assert r_h.topk.device.type == "cpu"
+    assert np.array_equal(r_h.topk.numpy(), r_d.topk.cpu().numpy())
+    assert np.array_equal(r_h.lower.numpy(), r_d.lower.cpu().numpy())
+    for _ in range(3):
+        ins, dels = random_batch(rng, rp, col, n, 12, 4)
+        a = st_h.update(ins, dels)
+        b = st_d.update(ins, dels)
+        assert a.topk.device.type == "cpu"
+        assert np.array_equal(a.topk.numpy(), b.topk.cpu().numpy())
+        assert np.array_equal(a.lower.numpy(), b.lower.cpu().numpy())
+        assert np.array_equal(a.upper.numpy(), b.upper.cpu().numpy())
+        assert (a.iterations, a.status) == (b.iterations, b.status)
+        e = np.concatenate([ins, ins[:, ::-1]]) if len(ins) else np.zeros((0, 2), np.int64)
+        d = np.concatenate([dels, dels[:, ::-1]]) if len(dels) else np.zeros((0, 2), np.int64)
+        src = np.repeat(np.arange(n), np.diff(rp))
+        keep = np.ones(len(src), bool)
+        dset = set(map(tuple, d.tolist()))
+        for j, (u, v) in enumerate(zip(src.tolist(), col.tolist())):
+            if (u, v) in dset:
+                keep[j] = False
+        rp, col = sg.from_edges(n, np.concatenate([src[keep], e[:, 0]]), np.concatenate([col[keep], e[:, 1]]),
+                                undirected=False)
+    st_h.free()
+    st_d.free()
