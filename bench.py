@@ -64,6 +64,13 @@ def main():
                          "serving: update batches against R-MAT 24")
     ap.add_argument("--requests", type=int, default=200, help="serving: requests per load point")
     ap.add_argument("--graphs", type=int, default=256, help="batched: number of graphs")
+    ap.add_argument("--serving-scale", type=int, default=24, help="serving: R-MAT scale of the resident graph")
+    ap.add_argument("--batched-max-log2n", type=int, default=18, help="batched: n is log-uniform in [2^10, 2^this]")
+    ap.add_argument("--tuning", default="auto",
+                    help="walk launch shape: 'auto' (katz_autotune per precision before timing), "
+                         "or HUB_BYTES:BLOCKS_PER_CU for both precisions")
+    ap.add_argument("--tuning-sweep", action="store_true",
+                    help="static: also time every autotuner candidate (FP32) and report them")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -99,8 +106,16 @@ def main():
     col_t = torch.from_numpy(col).cuda()
     torch.cuda.synchronize()
 
+    tunings = {}
     forms = {}
     for precision in ("fp32", "fp64"):
+        if args.tuning == "auto":
+            tunings[precision] = katz.autotune(rp_t, col_t, K, eps=EPS, precision=precision)
+        else:
+            hub, bpc = (int(v) for v in args.tuning.split(":"))
+            katz.tuning_set(hub, bpc)
+            tunings[precision] = katz.tuning_get()
+        print(f"[bench] {precision} tuning {tunings[precision]}", flush=True)
         res, sec, tm = time_form(katz, torch, rp_t, col_t, precision, args.steps, args.warmup)
         walk_avg_ms = tm["walk_step_ms"] / max(tm["walk_step_launches"], 1)
         forms[precision] = dict(res=res, sec=sec, tm=tm, walk_avg_ms=walk_avg_ms,
@@ -109,6 +124,7 @@ def main():
               f"walk_step {walk_avg_ms * 1e3:.1f} us", flush=True)
 
     # The same FP32 run without the internal renumbering, for context.
+    katz.tuning_set(**tunings["fp32"])
     res_nr, sec_nr, tm_nr = time_form(katz, torch, rp_t, col_t, "fp32", max(1, args.steps // 2), 1,
                                       flags=katz.FLAG_NO_REORDER)
     print(f"[bench] fp32 caller order: {sec_nr * 1e3:.3f} ms/step", flush=True)
@@ -175,6 +191,21 @@ def main():
     }
     same = bool(torch.equal(f32["res"].topk, f64["res"].topk))
     out["fp32_fp64_same_topk"] = same
+    out["tuning"] = {p: dict(t, arg=f"{t['hub_bytes']}:{t['blocks_per_cu']}") for p, t in tunings.items()}
+    if args.tuning_sweep:
+        sweep = []
+        for hub, bpc in [(0, 0), (0, 2), (0, 4), (0, 8), (0, 16), (16384, 2), (16384, 4), (16384, 8),
+                         (32768, 2), (32768, 4), (65536, 1), (65536, 2)]:
+            katz.tuning_set(hub, bpc)
+            r_s, sec_s, tm_s = time_form(katz, torch, rp_t, col_t, "fp32", max(1, args.steps // 2), 1)
+            walk_us = tm_s["walk_step_ms"] / max(tm_s["walk_step_launches"], 1) * 1e3
+            sweep.append({"hub_bytes": hub, "blocks_per_cu": bpc, "ms_per_step": round(sec_s * 1e3, 4),
+                          "walk_step_avg_us": round(walk_us, 2),
+                          "same_result": bool(torch.equal(r_s.topk, f32["res"].topk)
+                                              and torch.equal(r_s.lower, f32["res"].lower))})
+            print(f"[bench] sweep {hub}:{bpc} {sec_s * 1e3:.3f} ms/step walk_step {walk_us:.1f} us", flush=True)
+        out["tuning_sweep_fp32"] = sweep
+        katz.tuning_set(**tunings["fp32"])
 
     if not args.no_cpu_baseline:
         import oracle
@@ -210,7 +241,7 @@ def bench_batched(args, katz, sg, torch, np):
     rng = np.random.default_rng(2026)
     specs = []
     for gidx in range(args.graphs):
-        n = int(round(2 ** rng.uniform(10, 18)))
+        n = int(round(2 ** rng.uniform(10, args.batched_max_log2n)))
         m = int(rng.integers(4, 33))
         specs.append((n, m, gidx + 1, float(rng.uniform(1e-3, 1.0)), int(rng.integers(10, 501))))
     t = time.perf_counter()
@@ -235,11 +266,11 @@ def bench_batched(args, katz, sg, torch, np):
     sec = (time.perf_counter() - t0) / args.steps
     traversed = sum(r.iterations * int(rp[-1]) for r, (rp, _) in zip(res, csrs))
     out = {
-        "metric": "batched certified top-k Katz ranking: GTEPS over 256 graphs, one call, 1 GPU",
+        "metric": f"batched certified top-k Katz ranking: GTEPS over {len(csrs)} graphs, one call, 1 GPU",
         "value": round(traversed / sec / 1e9, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "ba256_batched", "graphs": len(csrs), "n_total": ntot, "nnz_total": nnz,
+        "config": {"workload": f"ba{len(csrs)}_batched", "graphs": len(csrs), "n_total": ntot, "nnz_total": nnz,
                    "iterations_max": max(r.iterations for r in res),
                    "iterations_min": min(r.iterations for r in res)},
         "status_counts": {str(st): sum(1 for r in res if r.status == st) for st in sorted({r.status for r in res})},
@@ -288,7 +319,7 @@ def bench_serving(args, katz, sg, torch, np):
     Poisson process at a fraction of the measured saturation rate."""
     import threading
     t = time.perf_counter()
-    rp, col = sg.rmat(24, 16, 0.57, 0.19, 0.19, seed=2)
+    rp, col = sg.rmat(args.serving_scale, 16, 0.57, 0.19, 0.19, seed=2)
     n = len(rp) - 1
     dmax = int(np.max(np.diff(rp)))
     H = 100000
@@ -347,7 +378,7 @@ def bench_serving(args, katz, sg, torch, np):
         "value": points[0]["p50_ms"], "unit": "ms p50 latency at 50% load", "n_gpus": 1,
         "steps": len(reqs), "warmup": 0, "ms_per_step": round(float(np.mean(svc)), 4), "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "rmat24_serving", "n": n, "nnz_directed": int(rp[-1]), "k": 100, "eps": 1e-6,
+        "config": {"workload": f"rmat{args.serving_scale}_serving", "n": n, "nnz_directed": int(rp[-1]), "k": 100, "eps": 1e-6,
                    "batch": "round(10^U(0,4)) edges, 70% insertions", "slots": 4},
         "saturation_requests_per_s": round(sat, 2), "load_points": points,
     }

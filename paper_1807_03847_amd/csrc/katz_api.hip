@@ -7,6 +7,8 @@
 // of grow-only arenas; a dynamic state (Algorithm 2) owns its memory: the graph
 // as a CSR with per-row slack, the walk history x_1..x_r, c_r and M.
 #include <algorithm>
+#include <map>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -154,6 +156,42 @@ struct TimingState {
   katz_timing acc{};
 };
 TimingState g_timing;
+
+// Launch tuning of the walk step (katz_tuning_set); read once per call.
+struct TuningState {
+  std::mutex mu;
+  katz_tuning t{};
+};
+TuningState g_tuning;
+
+katz_tuning current_tuning() {
+  std::lock_guard<std::mutex> lk(g_tuning.mu);
+  return g_tuning.t;
+}
+
+int tuning_valid(const katz_tuning& t) {
+  if (t.hub_bytes < 0 || t.hub_bytes > 65536 || (t.hub_bytes & 15)) return KATZ_E_INVALID_ARG;
+  if (t.blocks_per_cu < 0 || t.blocks_per_cu > 32) return KATZ_E_INVALID_ARG;
+  if (t.hub_bytes > 0 && t.blocks_per_cu == 0) return KATZ_E_INVALID_ARG;
+  for (int i = 0; i < 6; ++i)
+    if (t.reserved[i] != 0) return KATZ_E_INVALID_ARG;
+  return KATZ_OK;
+}
+
+int cu_count(int dev) {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) {
+    (void)hipGetLastError();
+    v = 256;
+  }
+  cache[dev] = v;
+  return v;
+}
 
 struct CallTimer {
   bool on = false;
@@ -484,6 +522,8 @@ struct Run {
   int cur = 0;
   bool first_select = true;
   int grid = 1;
+  int hub_n = 0;               // walk entries copied to LDS (renumbered static runs)
+  long long walk_grid = 0;     // persistent walk grid (0: one workgroup per work item)
 };
 
 void* x_at(const Run& run, int r) { return run.st ? (void*)run.st->X[r] : run.w->x[r & 1]; }
@@ -531,6 +571,7 @@ IterArgs iter_args(const Run& run, const Bins& b, int r, bool rewalk, long long&
   ia.count_first = (int)b.count;
   ia.clog2_dmax = clog2(std::max(run.bins->dmax, 1));
   ia.rewalk = rewalk ? 1 : 0;
+  ia.hub_n = rewalk ? 0 : run.hub_n;
   ia.alpha = run.S->alpha;
   ia.etap = run.fp32 ? run.S->etap[r] : 0.0;
   return ia;
@@ -604,9 +645,10 @@ int enqueue_walk(Run& run, int r, hipStream_t s, CallTimer& T) {
   const IterArgs ia = iter_args(run, *run.bins, r, false, tb);
   const int tw = T.start(r == 1 ? T_FIRST : T_STEP, s);
   if (r == 1) KATZ_HIP(launch_walk_first(ia, run.fp32, run.n, run.nnz, run.validate >= KATZ_VALIDATE_BASIC, s));
-  else KATZ_HIP(launch_walk_step(ia, run.fp32, tb, s));
+  long long grid = 1;
+  if (r >= 2) KATZ_HIP(launch_walk_step(ia, run.fp32, tb, run.walk_grid, &grid, s));
   T.stop(tw, s);
-  const long long nb = r == 1 ? std::max<long long>(1, (run.bins->count + kWG - 1) / kWG) : std::max(tb, 1ll);
+  const long long nb = r == 1 ? std::max<long long>(1, (run.bins->count + kWG - 1) / kWG) : grid;
   KATZ_HIP(launch_reduce_blkmax(run.w->blkmax, nb, run.fp32, run.w->xmax32, run.w->xmax64, r, run.w->sc, s));
   return KATZ_OK;
 }
@@ -929,6 +971,11 @@ int rank_one(const katz_csr* g, const katz_params* p, katz_result* out, hipStrea
   run.col = pl.reorder ? stg.ncol : stg.col;
   run.ext_of = pl.reorder ? stg.ext_of : nullptr;
   run.int_of = pl.reorder ? stg.int_of : nullptr;
+  {
+    const katz_tuning tu = current_tuning();
+    run.walk_grid = (long long)tu.blocks_per_cu * cu_count(dev);
+    run.hub_n = pl.reorder ? (int)std::min<long long>(g->n, tu.hub_bytes / (pl.fp32 ? 4 : 8)) : 0;
+  }
   run.bins = &b;
   run.w = &w;
   run.S = &S;
@@ -979,6 +1026,11 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   run.col = pl.reorder ? stg.ncol : stg.col;
   run.ext_of = pl.reorder ? stg.ext_of : nullptr;
   run.int_of = pl.reorder ? stg.int_of : nullptr;
+  {
+    const katz_tuning tu = current_tuning();
+    run.walk_grid = (long long)tu.blocks_per_cu * cu_count(dev);
+    run.hub_n = pl.reorder ? (int)std::min<long long>(g->n, tu.hub_bytes / (pl.fp32 ? 4 : 8)) : 0;
+  }
   run.bins = &b;
   run.w = &w;
   run.S = &S;
@@ -1864,13 +1916,15 @@ int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, lon
       long long tb = 0;
       if (dense) {
         const IterArgs ia2 = iter_args(run, st->bins, i, true, tb);
+        long long g_used = 0;
         if (i == 1) KATZ_HIP(launch_walk_first(ia2, 0, n, st->nnz, 0, s));
-        else KATZ_HIP(launch_walk_step(ia2, 0, tb, s));
+        else KATZ_HIP(launch_walk_step(ia2, 0, tb, 0, &g_used, s));
       } else {
         KATZ_TRY(bin_rows(st, st->lbins, st->sc2, st->clist, csize, s));
         const IterArgs ia2 = iter_args(run, st->lbins, i, true, tb);
+        long long g_used = 0;
         if (i == 1) KATZ_HIP(launch_walk_first(ia2, 0, n, st->nnz, 0, s));
-        else KATZ_HIP(launch_walk_step(ia2, 0, tb, s));
+        else KATZ_HIP(launch_walk_step(ia2, 0, tb, 0, &g_used, s));
       }
     }
     // c_r(w) = sum_i x_i(w) for every recomputed w, in the static order.
@@ -1959,6 +2013,74 @@ KATZ_EXPORT int katz_timing_read(katz_timing* out) {
   std::lock_guard<std::mutex> lk(katz::g_timing.mu);
   *out = katz::g_timing.acc;
   return KATZ_OK;
+}
+
+KATZ_EXPORT int katz_tuning_get(katz_tuning* t) {
+  if (!t) return KATZ_E_INVALID_ARG;
+  *t = katz::current_tuning();
+  return KATZ_OK;
+}
+
+KATZ_EXPORT int katz_tuning_set(const katz_tuning* t) {
+  if (!t) return KATZ_E_INVALID_ARG;
+  KATZ_TRY(katz::tuning_valid(*t));
+  std::lock_guard<std::mutex> lk(katz::g_tuning.mu);
+  katz::g_tuning.t = *t;
+  return KATZ_OK;
+}
+
+// Candidate launch shapes, timed on the caller's graph; the fastest is kept.
+KATZ_EXPORT int katz_autotune(const katz_csr* g, const katz_params* p, katz_tuning* best, void* stream) {
+  if (!g || !p) return KATZ_E_INVALID_ARG;
+  KATZ_TRY(katz::check_graph(g));
+  KATZ_TRY(katz::check_params(p, g->n, true));
+  static const int kCand[][2] = {{0, 0}, {0, 4}, {0, 8}, {16384, 4}, {16384, 8}, {32768, 4}, {65536, 2}};
+  const katz_tuning saved = katz::current_tuning();
+  int32_t* ids = nullptr;
+  double *lo = nullptr, *up = nullptr;
+  if (hipMalloc((void**)&ids, sizeof(int32_t) * p->k) != hipSuccess ||
+      hipMalloc((void**)&lo, sizeof(double) * p->k) != hipSuccess ||
+      hipMalloc((void**)&up, sizeof(double) * p->k) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(ids);
+    (void)hipFree(lo);
+    (void)hipFree(up);
+    return KATZ_E_OOM;
+  }
+  katz_tuning pick = saved;
+  double pick_ms = 1e300;
+  int rc = KATZ_OK;
+  for (const auto& c : kCand) {
+    katz_tuning t{};
+    t.hub_bytes = c[0];
+    t.blocks_per_cu = c[1];
+    {
+      std::lock_guard<std::mutex> lk(katz::g_tuning.mu);
+      katz::g_tuning.t = t;
+    }
+    double ms = 0.0;
+    for (int rep = 0; rep < 2 && rc >= 0; ++rep) {
+      katz_result out{};
+      out.topk_ids = ids;
+      out.lower = lo;
+      out.upper = up;
+      const auto t0 = std::chrono::steady_clock::now();
+      rc = katz_rank_static(1, g, p, &out, nullptr, stream);
+      ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (rc < 0) break;
+    if (ms < pick_ms) {
+      pick_ms = ms;
+      pick = t;
+    }
+  }
+  (void)hipFree(ids);
+  (void)hipFree(lo);
+  (void)hipFree(up);
+  std::lock_guard<std::mutex> lk(katz::g_tuning.mu);
+  katz::g_tuning.t = rc < 0 ? saved : pick;
+  if (best) *best = katz::g_tuning.t;
+  return rc < 0 ? rc : KATZ_OK;
 }
 
 KATZ_EXPORT const char* katz_strerror(int code) {

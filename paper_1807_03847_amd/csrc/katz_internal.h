@@ -140,6 +140,7 @@ struct IterArgs {
   int write_empty;
   int clog2_dmax;
   int rewalk;                    // dynamic re-walk: write x only (no c, no maxima)
+  int hub_n;                     // walk entries 0 .. hub_n - 1 are read from an LDS copy
   double alpha;
   double etap;                   // eta'_r
 };
@@ -234,7 +235,8 @@ hipError_t launch_validate_strict(const RowDesc* desc, long long n, const int32_
                                   long long* row_off, int* row_len, RunScalars* sc, hipStream_t s);
 hipError_t launch_walk_first(const IterArgs& a, int fp32, long long n, long long nnz, int validate,
                              hipStream_t s);
-hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, hipStream_t s);
+hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, long long max_grid,
+                            long long* grid_used, hipStream_t s);
 // Reduces the per-workgroup maxima of walk iteration r into xmax32[r] / xmax64[r].
 hipError_t launch_reduce_blkmax(const void* blkmax, long long nb, int fp32, unsigned* xmax32,
                                 unsigned long long* xmax64, int r, const RunScalars* sc, hipStream_t s);

@@ -193,13 +193,19 @@ __device__ __forceinline__ void epilogue(const IterArgs& a, const Epi<F32>& ep, 
 // Strided row sum over G lanes: lane l adds elements l, l+G, l+2G, ... in
 // order.  Loads are issued eight at a time (eight column ids, then eight
 // gathers) so a lane keeps eight requests in flight; slots past the row end
-// add an exact zero, which leaves the sum and its rounding unchanged.
+// add an exact zero, which leaves the sum and its rounding unchanged.  Walk
+// entries below a.hub_n are read from the workgroup's copy in LDS (after the
+// internal renumbering these are the longest rows, i.e. the most-referenced
+// nodes); the copy is exact, so the sum does not depend on where an entry
+// was read.
 constexpr int kBatch = 8;
 
 template <bool F32, int G>
-__device__ __forceinline__ typename Prec<F32>::T strided_sum(const IterArgs& a, const int32_t* cp, int len,
-                                                             int lane) {
+__device__ __forceinline__ typename Prec<F32>::T strided_sum(const IterArgs& a, const typename Prec<F32>::T* hub,
+                                                             const int32_t* cp, int len, int lane) {
   using T = typename Prec<F32>::T;
+  const T* x = reinterpret_cast<const T*>(a.x_in);
+  const int H = a.hub_n;
   T sum = 0;
   for (int j0 = lane; j0 < len; j0 += kBatch * G) {
     int32_t c[kBatch];
@@ -210,7 +216,7 @@ __device__ __forceinline__ typename Prec<F32>::T strided_sum(const IterArgs& a, 
     }
     T v[kBatch];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) v[u] = c[u] >= 0 ? ldx<F32>(a.x_in, c[u]) : (T)0;
+    for (int u = 0; u < kBatch; ++u) v[u] = c[u] < 0 ? (T)0 : (c[u] < H ? hub[c[u]] : x[c[u]]);
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) sum += v[u];
   }
@@ -218,8 +224,8 @@ __device__ __forceinline__ typename Prec<F32>::T strided_sum(const IterArgs& a, 
 }
 
 template <bool F32, int G>
-__device__ __forceinline__ void rows_group(const IterArgs& a, const Epi<F32>& ep, long long lb, int bin,
-                                           double& vmax) {
+__device__ __forceinline__ void rows_group(const IterArgs& a, const typename Prec<F32>::T* hub, const Epi<F32>& ep,
+                                           long long lb, int bin, double& vmax) {
   using T = typename Prec<F32>::T;
   constexpr int RPB = kWG / G;
   const int lane = threadIdx.x & (G - 1);
@@ -227,7 +233,7 @@ __device__ __forceinline__ void rows_group(const IterArgs& a, const Epi<F32>& ep
   const bool valid = i < a.bin_count[bin];
   RowDesc d{0, 0, 0};
   if (valid) d = a.desc[a.bin_base[bin] + i];
-  T sum = strided_sum<F32, G>(a, a.col + d.off, d.len, lane);
+  T sum = strided_sum<F32, G>(a, hub, a.col + d.off, d.len, lane);
 #pragma unroll
   for (int o = G / 2; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, G);
   if (valid && lane == 0) epilogue<F32>(a, ep, d.row, sum, vmax);
@@ -236,10 +242,11 @@ __device__ __forceinline__ void rows_group(const IterArgs& a, const Epi<F32>& ep
 // Whole-workgroup sum of one row or segment: 256 strided lanes, wave
 // butterflies, then the four wave sums as (w0 + w1) + (w2 + w3).
 template <bool F32>
-__device__ __forceinline__ typename Prec<F32>::T block_sum(const IterArgs& a, const int32_t* cp, int len) {
+__device__ __forceinline__ typename Prec<F32>::T block_sum(const IterArgs& a, const typename Prec<F32>::T* hub,
+                                                           const int32_t* cp, int len) {
   using T = typename Prec<F32>::T;
   __shared__ T part[kWG / kWave];
-  T sum = strided_sum<F32, kWG>(a, cp, len, threadIdx.x);
+  T sum = strided_sum<F32, kWG>(a, hub, cp, len, threadIdx.x);
   for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
   if (lane_id() == 0) part[threadIdx.x / kWave] = sum;
   __syncthreads();
@@ -292,11 +299,21 @@ __global__ void __launch_bounds__(kWG) check_col_range(const int32_t* col, long 
   if (__ballot(bad) && lane_id() == 0) atomicOr(&sc->err, 1);
 }
 
-// Walk step r >= 2: every bin in one launch, heavy bins first.
+// Walk step r >= 2: every bin in one launch, heavy bins first.  The grid may
+// be smaller than the work: workgroup b takes work items b, b + gridDim.x, ...
+// (a persistent grid, which is what makes the LDS copy of the first a.hub_n
+// walk entries worth its fill).
 template <bool F32>
 __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
   if (a.sc->err || a.sc->done) return;
   using T = typename Prec<F32>::T;
+  extern __shared__ __align__(16) unsigned char walk_lds[];
+  T* hub = reinterpret_cast<T*>(walk_lds);
+  {
+    const T* x = reinterpret_cast<const T*>(a.x_in);
+    for (int i = threadIdx.x; i < a.hub_n; i += kWG) hub[i] = x[i];
+    __syncthreads();
+  }
   const Epi<F32> ep = compute_epi<F32>(a);
   if constexpr (F32) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -305,60 +322,63 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
     }
   }
   double vmax = 0.0;
-  const long long b = blockIdx.x;
-  int bin = 0;
-  while (bin < NUM_BINS && b >= a.first_block[bin + 1]) ++bin;
-  const long long lb = b - a.first_block[bin];
-  switch (bin) {
-    case BIN_HUGE: {
-      __shared__ int s_last;
-      const SegDesc sd = a.segs[lb];
-      const T tot = block_sum<F32>(a, a.col + sd.off, sd.len);
-      T* part = reinterpret_cast<T*>(a.partial);
-      if (threadIdx.x == 0) {
-        part[sd.part] = tot;
-        __threadfence();
-        const HugeRow h = a.huge[sd.hrow];
-        s_last = atomicAdd(&a.seg_done[sd.hrow], 1) == h.nseg - 1;
-      }
-      __syncthreads();
-      if (s_last && threadIdx.x < kWave) {
-        // This workgroup finished the row's last segment: combine all partials
-        // in segment order (lane l takes l, l+64, ...; then a butterfly).
-        __threadfence();
-        const HugeRow h = a.huge[sd.hrow];
-        const int lane = threadIdx.x;
-        T sum = 0;
-        for (int s2 = lane; s2 < h.nseg; s2 += kWave) sum += part[h.part0 + s2];
-        for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
-        if (lane == 0) {
-          epilogue<F32>(a, ep, h.row, sum, vmax);
-          a.seg_done[sd.hrow] = 0;
+  const long long total = a.first_block[NUM_BINS];
+  for (long long b = blockIdx.x; b < total; b += gridDim.x) {
+    int bin = 0;
+    while (bin < NUM_BINS && b >= a.first_block[bin + 1]) ++bin;
+    const long long lb = b - a.first_block[bin];
+    switch (bin) {
+      case BIN_HUGE: {
+        __shared__ int s_last;
+        const SegDesc sd = a.segs[lb];
+        const T tot = block_sum<F32>(a, hub, a.col + sd.off, sd.len);
+        T* part = reinterpret_cast<T*>(a.partial);
+        if (threadIdx.x == 0) {
+          part[sd.part] = tot;
+          __threadfence();
+          const HugeRow h = a.huge[sd.hrow];
+          s_last = atomicAdd(&a.seg_done[sd.hrow], 1) == h.nseg - 1;
         }
+        __syncthreads();
+        if (s_last && threadIdx.x < kWave) {
+          // This workgroup finished the row's last segment: combine all partials
+          // in segment order (lane l takes l, l+64, ...; then a butterfly).
+          __threadfence();
+          const HugeRow h = a.huge[sd.hrow];
+          const int lane = threadIdx.x;
+          T sum = 0;
+          for (int s2 = lane; s2 < h.nseg; s2 += kWave) sum += part[h.part0 + s2];
+          for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
+          if (lane == 0) {
+            epilogue<F32>(a, ep, h.row, sum, vmax);
+            a.seg_done[sd.hrow] = 0;
+          }
+        }
+        __syncthreads();
+        break;
       }
-      break;
-    }
-    case BIN_B256: {
-      const RowDesc d = a.desc[a.bin_base[BIN_B256] + lb];
-      const T tot = block_sum<F32>(a, a.col + d.off, d.len);
-      if (threadIdx.x == 0) epilogue<F32>(a, ep, d.row, tot, vmax);
-      break;
-    }
-    case BIN_W64: rows_group<F32, 64>(a, ep, lb, BIN_W64, vmax); break;
-    case BIN_G32: rows_group<F32, 32>(a, ep, lb, BIN_G32, vmax); break;
-    case BIN_G16: rows_group<F32, 16>(a, ep, lb, BIN_G16, vmax); break;
-    case BIN_G8: rows_group<F32, 8>(a, ep, lb, BIN_G8, vmax); break;
-    case BIN_G4: rows_group<F32, 4>(a, ep, lb, BIN_G4, vmax); break;
-    case BIN_EMPTY: {
-      // Only at r = 2: the buffer of x_2 was never written for empty rows.
-      const long long i = lb * kWG + threadIdx.x;
-      if (i < a.bin_count[BIN_EMPTY]) {
-        const int row = a.desc[a.bin_base[BIN_EMPTY] + i].row;
-        reinterpret_cast<T*>(a.x_out)[row] = (T)0;
+      case BIN_B256: {
+        const RowDesc d = a.desc[a.bin_base[BIN_B256] + lb];
+        const T tot = block_sum<F32>(a, hub, a.col + d.off, d.len);
+        if (threadIdx.x == 0) epilogue<F32>(a, ep, d.row, tot, vmax);
+        break;
       }
-      break;
+      case BIN_W64: rows_group<F32, 64>(a, hub, ep, lb, BIN_W64, vmax); break;
+      case BIN_G32: rows_group<F32, 32>(a, hub, ep, lb, BIN_G32, vmax); break;
+      case BIN_G16: rows_group<F32, 16>(a, hub, ep, lb, BIN_G16, vmax); break;
+      case BIN_G8: rows_group<F32, 8>(a, hub, ep, lb, BIN_G8, vmax); break;
+      case BIN_G4: rows_group<F32, 4>(a, hub, ep, lb, BIN_G4, vmax); break;
+      case BIN_EMPTY: {
+        // Only at r = 2: the buffer of x_2 was never written for empty rows.
+        const long long i = lb * kWG + threadIdx.x;
+        if (i < a.bin_count[BIN_EMPTY]) {
+          const int row = a.desc[a.bin_base[BIN_EMPTY] + i].row;
+          reinterpret_cast<T*>(a.x_out)[row] = (T)0;
+        }
+        break;
+      }
+      default: break;
     }
-    default: break;
   }
   store_block_max<F32>(a, vmax);
 }
@@ -958,10 +978,15 @@ hipError_t launch_reduce_blkmax(const void* blkmax, long long nb, int fp32, unsi
   return hipGetLastError();
 }
 
-hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, hipStream_t s) {
-  const unsigned grid = (unsigned)(total_blocks > 0 ? total_blocks : 1);
-  if (fp32) hipLaunchKernelGGL(walk_step<true>, dim3(grid), dim3(kWG), 0, s, a);
-  else hipLaunchKernelGGL(walk_step<false>, dim3(grid), dim3(kWG), 0, s, a);
+hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, long long max_grid,
+                            long long* grid_used, hipStream_t s) {
+  long long g = total_blocks > 0 ? total_blocks : 1;
+  if (max_grid > 0) g = std::min(g, max_grid);
+  const size_t lds = (size_t)a.hub_n * (fp32 ? sizeof(float) : sizeof(double));
+  if (a.hub_n > 0 && max_grid <= 0) return hipErrorInvalidValue;   // the copy pays only on a persistent grid
+  *grid_used = g;
+  if (fp32) hipLaunchKernelGGL(walk_step<true>, dim3((unsigned)g), dim3(kWG), lds, s, a);
+  else hipLaunchKernelGGL(walk_step<false>, dim3((unsigned)g), dim3(kWG), lds, s, a);
   return hipGetLastError();
 }
 

@@ -54,6 +54,11 @@ class KatzResult(ctypes.Structure):
                 ("iterations", ctypes.c_int32), ("status", ctypes.c_int32)]
 
 
+class KatzTuning(ctypes.Structure):
+    _fields_ = [("hub_bytes", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
 class KatzTiming(ctypes.Structure):
     _fields_ = [("walk_step_ms", ctypes.c_double), ("walk_step_launches", ctypes.c_int64),
                 ("walk_first_ms", ctypes.c_double), ("walk_first_launches", ctypes.c_int64),
@@ -94,6 +99,12 @@ def _load():
     lib.katz_timing_enable.argtypes = [ctypes.c_int]
     lib.katz_timing_read.restype = ctypes.c_int
     lib.katz_timing_read.argtypes = [ctypes.POINTER(KatzTiming)]
+    lib.katz_tuning_get.restype = ctypes.c_int
+    lib.katz_tuning_get.argtypes = [ctypes.POINTER(KatzTuning)]
+    lib.katz_tuning_set.restype = ctypes.c_int
+    lib.katz_tuning_set.argtypes = [ctypes.POINTER(KatzTuning)]
+    lib.katz_autotune.restype = ctypes.c_int
+    lib.katz_autotune.argtypes = [ctypes.POINTER(KatzCSR), ctypes.POINTER(KatzParams), ctypes.POINTER(KatzTuning), vp]
     return lib
 
 
@@ -341,6 +352,34 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def tuning_get() -> dict:
+    """katz_tuning_get: the walk kernel's launch shape."""
+    t = KatzTuning()
+    rc = lib.katz_tuning_get(ctypes.byref(t))
+    if rc < 0:
+        raise KatzError(rc)
+    return {"hub_bytes": t.hub_bytes, "blocks_per_cu": t.blocks_per_cu}
+
+
+def tuning_set(hub_bytes=0, blocks_per_cu=0) -> None:
+    """katz_tuning_set (no result depends on it)."""
+    t = KatzTuning(hub_bytes=int(hub_bytes), blocks_per_cu=int(blocks_per_cu))
+    rc = lib.katz_tuning_set(ctypes.byref(t))
+    if rc < 0:
+        raise KatzError(rc)
+
+
+def autotune(row_ptr, col, k, *, alpha=0.0, eps=0.0, precision="fp32", undirected=True, stream=None) -> dict:
+    """katz_autotune: times the candidate launch shapes on this graph and keeps the fastest."""
+    g = make_csr(row_ptr, col, undirected)
+    p = make_params(k, alpha, eps, precision)
+    t = KatzTuning()
+    rc = lib.katz_autotune(ctypes.byref(g), ctypes.byref(p), ctypes.byref(t), _stream_handle(stream, row_ptr.device))
+    if rc < 0:
+        raise KatzError(rc)
+    return {"hub_bytes": t.hub_bytes, "blocks_per_cu": t.blocks_per_cu}
 
 
 def timing_enable(on: bool = True) -> None:

@@ -39,10 +39,12 @@ def test_struct_layout_matches_header():
 #include "katz.h"
 #define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
 int main(void) {
-  printf("katz_csr %zu\nkatz_params %zu\nkatz_result %zu\n", sizeof(katz_csr), sizeof(katz_params), sizeof(katz_result));
+  printf("katz_csr %zu\nkatz_params %zu\nkatz_result %zu\nkatz_tuning %zu\n", sizeof(katz_csr), sizeof(katz_params),
+         sizeof(katz_result), sizeof(katz_tuning));
   F(katz_csr, col) F(katz_csr, row_ptr_64) F(katz_csr, undirected)
   F(katz_params, k) F(katz_params, precision) F(katz_params, validate) F(katz_params, flags) F(katz_params, degree_cap)
   F(katz_result, rest_upper_max) F(katz_result, active_final) F(katz_result, iterations) F(katz_result, status)
+  F(katz_tuning, blocks_per_cu) F(katz_tuning, reserved)
   return 0;
 }
 '''
@@ -57,10 +59,12 @@ int main(void) {
     assert int(got["katz_csr"]) == ctypes.sizeof(katz.KatzCSR)
     assert int(got["katz_params"]) == ctypes.sizeof(katz.KatzParams)
     assert int(got["katz_result"]) == ctypes.sizeof(katz.KatzResult)
+    assert int(got["katz_tuning"]) == ctypes.sizeof(katz.KatzTuning)
     for key, val in got.items():
         if "." in key:
             struct, field = key.split(".")
-            cls = {"katz_csr": katz.KatzCSR, "katz_params": katz.KatzParams, "katz_result": katz.KatzResult}[struct]
+            cls = {"katz_csr": katz.KatzCSR, "katz_params": katz.KatzParams, "katz_result": katz.KatzResult,
+                   "katz_tuning": katz.KatzTuning}[struct]
             assert getattr(cls, field).offset == int(val), key
 
 
@@ -109,3 +113,24 @@ def test_argument_errors_before_device_work():
     assert katz.lib.katz_bounds(ctypes.byref(g), ctypes.byref(katz.make_params(1)), 0, ctypes.addressof(lo),
                                 ctypes.addressof(lo), None) == katz.E_INVALID_ARG
     assert katz.lib.katz_rank_update(None, None, None, 0, None, None, 0, None, None) == katz.E_INVALID_ARG
+
+
+def test_tuning_round_trip_and_limits():
+    katz = K()
+    saved = katz.tuning_get()
+    try:
+        katz.tuning_set(16384, 4)
+        assert katz.tuning_get() == {"hub_bytes": 16384, "blocks_per_cu": 4}
+        for hub, bpc in [(-16, 4), (65552, 4), (100, 4), (16384, 0), (0, 33), (0, -1)]:
+            with pytest.raises(katz.KatzError) as e:
+                katz.tuning_set(hub, bpc)
+            assert e.value.code == katz.E_INVALID_ARG
+            assert katz.tuning_get() == {"hub_bytes": 16384, "blocks_per_cu": 4}    # unchanged
+        t = katz.KatzTuning(hub_bytes=0, blocks_per_cu=0)
+        t.reserved[2] = 1
+        assert katz.lib.katz_tuning_set(ctypes.byref(t)) == katz.E_INVALID_ARG
+        assert katz.lib.katz_tuning_set(None) == katz.E_INVALID_ARG
+        assert katz.lib.katz_tuning_get(None) == katz.E_INVALID_ARG
+        assert katz.lib.katz_autotune(None, None, None, None) == katz.E_INVALID_ARG
+    finally:
+        katz.tuning_set(**saved)
