@@ -225,7 +225,7 @@ int katz_server_wait(katz_server* sv, int64_t ticket, katz_result* out, double* 
 void katz_server_destroy(katz_server* sv);
 
 /* ---- device timing (instrumentation for benchmarks and profiles) ----------
- * While enabled, every ranking call records hipEvent pairs on its own stream
+ * While enabled, every ranking and bounds call records hipEvent pairs on its own stream
  * around each of its phases and adds the elapsed device times to process-wide
  * counters when the call has finished.  walk_step covers the walk
  * sparse matrix-vector product of iterations r >= 2 (one kernel launch per

@@ -303,7 +303,6 @@ struct Bins {
   RowDesc* desc = nullptr;
   SegDesc* segs = nullptr;
   HugeRow* huge = nullptr;
-  int* seg_done = nullptr;
   long long* blk = nullptr;
   long long* scan_sums = nullptr;    // scratch of the device-wide scans
   long long* scan_totals = nullptr;  // [2]
@@ -381,37 +380,36 @@ int resolve_alpha(double alpha_in, int dmax, Scalars& S) {
   return KATZ_OK;
 }
 
-// Deepest rounding chain of any row sum under the bin schedule: serial adds per
-// lane, then the butterfly levels (and the segment combine for huge rows).
-int max_reduction_depth(const Bins& b) {
-  int m = 0;
-  auto upd = [&](int bin, int d) {
-    if (b.bin_count[bin] > 0) m = std::max(m, d);
-  };
-  upd(BIN_G4, 2);
-  upd(BIN_G8, 3);
-  upd(BIN_G16, 4);
-  upd(BIN_G32, 5);
-  upd(BIN_W64, (kPerLane - 1) + 6);
-  upd(BIN_B256, (kPerLane - 1) + 8);
-  if (b.bin_count[BIN_HUGE] > 0) {
-    const long long max_seg = (b.dmax + kSeg - 1) / kSeg;
-    const long long q = (max_seg + kWave - 1) / kWave;
-    m = (int)std::max<long long>(m, (kPerLane - 1) + 8 + (q - 1) + 6);
+// Deepest rounding chain of a row sum under the bin schedule (serial adds per
+// lane, then the butterfly levels, and the segment combine for huge rows).  It
+// grows with the row length, so the longest row of a graph sets its maximum.
+int reduction_depth(long long dmax) {
+  switch (bin_of_host(dmax)) {
+    case BIN_EMPTY: return 0;
+    case BIN_G4: return 2;
+    case BIN_G8: return 3;
+    case BIN_G16: return 4;
+    case BIN_G32: return 5;
+    case BIN_W64: return (kPerLane - 1) + 6;
+    case BIN_B256: return (kPerLane - 1) + 8;
+    default: {
+      const long long max_seg = (dmax + kSeg - 1) / kSeg;
+      const long long q = (max_seg + kWave - 1) / kWave;
+      return (int)((kPerLane - 1) + 8 + (q - 1) + 6);
+    }
   }
-  return m;
 }
 
 // FP32 form: eta_r bounds the relative error of every entry of x~_r; eta_1 = 0
 // because the first walk step sums exact ones; later steps multiply by (1 + rho),
 // rho = gamma_m = m u / (1 - m u) for the deepest reduction chain m.
-void fp32_tables(Scalars& S, const Bins& b, int max_iter) {
-  const int m = max_reduction_depth(b);
+void fp32_tables(Scalars& S, long long dmax, int max_iter) {
+  const int m = reduction_depth(dmax);
   S.rho = (m * kU32) / (1.0 - m * kU32) * (1.0 + 0x1p-40);
   S.eta.assign(max_iter + 1, 0.0);
   S.etap.assign(max_iter + 1, 0.0);
   const double up = 1.0 + 0x1p-50;
-  S.eta[1] = b.dmax < (1 << 24) ? 0.0 : kU32;
+  S.eta[1] = dmax < (1 << 24) ? 0.0 : kU32;
   for (int r = 2; r <= max_iter; ++r) S.eta[r] = ((1.0 + S.eta[r - 1]) * (1.0 + S.rho) - 1.0) * up;
   for (int r = 1; r <= max_iter; ++r) S.etap[r] = S.eta[r] / (1.0 - S.eta[r]) * up;
 }
@@ -549,7 +547,6 @@ IterArgs iter_args(const Run& run, const Bins& b, int r, bool rewalk, long long&
   ia.col = run.col;
   ia.segs = b.segs;
   ia.huge = b.huge;
-  ia.seg_done = b.seg_done;
   for (int i = 0; i < NUM_BINS; ++i) {
     ia.bin_base[i] = b.bin_base[i];
     ia.bin_count[i] = b.bin_count[i];
@@ -820,7 +817,6 @@ void layout(Arena& ar, const Plan& pl, Bins& b, Work& w, Staging& stg) {
   b.desc = ar.take<RowDesc>(n);
   b.segs = ar.take<SegDesc>(b.seg_cap);
   b.huge = ar.take<HugeRow>(b.huge_cap);
-  b.seg_done = ar.take<int>(b.huge_cap);
   if (pl.rp_host) stg.row_ptr = ar.take<char>((size_t)(n + 1) * (pl.g->row_ptr_64 ? 8 : 4));
   if (pl.col_host) stg.col = ar.take<int32_t>(std::max<long long>(nnz, 1));
   if (pl.validate == KATZ_VALIDATE_STRICT && pl.g->undirected) {
@@ -843,7 +839,7 @@ void layout(Arena& ar, const Plan& pl, Bins& b, Work& w, Staging& stg) {
   w.c = ar.take<double>(n);
   if (pl.fp32) w.e = ar.take<float>(n);
   w.partial = ar.take<char>(b.seg_cap * xs);
-  w.blkmax = ar.take<double>(n + b.seg_cap + 1);
+  w.blkmax = ar.take<double>(n + 2 * b.seg_cap + 16);
   w.xmax32 = ar.take<unsigned>(pl.max_iter + 1);
   w.xmax64 = ar.take<unsigned long long>(pl.max_iter + 1);
   w.sigma = ar.take<double>(pl.max_iter + 1);
@@ -894,7 +890,6 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
     stg.col = g->col;
   }
   KATZ_HIP(launch_init_run(w.sc, g->n, w.sigma, w.sigma_sum, w.xmax32, w.xmax64, pl.max_iter, w.hist, s));
-  KATZ_HIP(hipMemsetAsync(b.seg_done, 0, sizeof(int) * b.huge_cap, s));
   KATZ_HIP(launch_prep_count(stg.row_ptr, g->row_ptr_64, g->n, g->nnz, b.blk, b.nblocks, w.sc, s));
   KATZ_HIP(launch_prep_scan(b.blk, b.nblocks, b.scan_sums, b.scan_totals, w.sc, s));
   KATZ_HIP(launch_prep_scatter(stg.row_ptr, g->row_ptr_64, g->n, b.blk, b.nblocks, b.desc, b.segs, b.huge, w.sc, s));
@@ -914,7 +909,6 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
     // (now contiguous per bin).  Column ids were range-checked above.
     KATZ_HIP(launch_relabel(b.desc, g->n, b.bin_base, b.bin_count, stg.col, stg.ext_of, stg.int_of, stg.len_ll, stg.len32, stg.noff,
                             stg.sums, stg.total, stg.ncol, s));
-    KATZ_HIP(hipMemsetAsync(b.seg_done, 0, sizeof(int) * b.huge_cap, s));
     KATZ_HIP(launch_prep_rows(nullptr, g->n, stg.noff, stg.len32, b.blk, b.nblocks, b.scan_sums, b.scan_totals,
                               b.desc, b.segs, b.huge, w.sc, s));
     KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
@@ -960,7 +954,7 @@ int rank_one(const katz_csr* g, const katz_params* p, katz_result* out, hipStrea
 
   Scalars S;
   KATZ_TRY(resolve_alpha(p->alpha, b.dmax, S));
-  if (pl.fp32) fp32_tables(S, b, pl.max_iter);
+  if (pl.fp32) fp32_tables(S, b.dmax, pl.max_iter);
 
   Run run;
   run.n = g->n;
@@ -1016,7 +1010,7 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   KATZ_TRY(prepare(ar.hs, pl, b, w, stg, s));
   Scalars S;
   KATZ_TRY(resolve_alpha(p->alpha, b.dmax, S));
-  if (pl.fp32) fp32_tables(S, b, pl.max_iter);
+  if (pl.fp32) fp32_tables(S, b.dmax, pl.max_iter);
   Run run;
   run.n = g->n;
   run.nnz = g->nnz;
@@ -1035,9 +1029,11 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   run.w = &w;
   run.S = &S;
   CallTimer T;
+  T.call_begin(s);
   for (int r = 1; r <= r_target; ++r) KATZ_TRY(enqueue_walk(run, r, s, T));
   KATZ_HIP(hipMemcpyAsync(ar.hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
   KATZ_HIP(hipStreamSynchronize(s));
+  T.commit(s);
   if (ar.hs.sc->err) return KATZ_E_CSR;
   const BoundArgs bd = bound_args(run, r_target);
   double* lo = pl.out_host ? stg.out_lo : lower;
@@ -1127,7 +1123,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     gexp = ar.take<int>((size_t)count * stride);
     gxmax32 = ar.take<unsigned>((size_t)count * stride);
     gxmax64 = ar.take<unsigned long long>((size_t)count * stride);
-    etap = ar.take<double>(stride);
+    etap = ar.take<double>((size_t)count * stride);
     rest = ar.take<double>(count);
     gid_of = ar.take<int>(total_n);
     gsel = ar.take<GraphSel>(count);
@@ -1142,7 +1138,6 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     b.desc = ar.take<RowDesc>(total_n);
     b.segs = ar.take<SegDesc>(b.seg_cap);
     b.huge = ar.take<HugeRow>(b.huge_cap);
-    b.seg_done = ar.take<int>(b.huge_cap);
     const size_t xs = fp32 ? 4 : 8;
     w.x[0] = ar.take<char>(total_n * xs);
     w.x[1] = ar.take<char>(total_n * xs);
@@ -1200,7 +1195,6 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   KATZ_HIP(hipMemcpyAsync(grp64, h_rp64.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
   KATZ_HIP(hipMemcpyAsync(gcol, h_col.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
   KATZ_HIP(launch_reset_flags(w.sc, s));
-  KATZ_HIP(hipMemsetAsync(b.seg_done, 0, sizeof(int) * b.huge_cap, s));
   KATZ_HIP(hipMemsetAsync(gdmax, 0, sizeof(int) * count, s));
   int validate = 0;
   for (int i = 0; i < count; ++i) validate = std::max(validate, p[i].validate);
@@ -1217,8 +1211,10 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   // ---- per-graph scalars, selection views, initial state ----
   std::vector<Scalars> S(count);
   for (int i = 0; i < count; ++i) KATZ_TRY(resolve_alpha(p[i].alpha, h_dmax[i], S[i]));
-  Scalars G;   // FP32 eta tables for the deepest reduction of the whole batch
-  if (fp32) fp32_tables(G, b, max_iter);
+  // FP32 eta tables per graph, from the graph's own longest row (the same
+  // tables a single-graph call builds, so results match it bitwise).
+  if (fp32)
+    for (int i = 0; i < count; ++i) fp32_tables(S[i], h_dmax[i], max_iter);
   std::vector<double> h_alpha(count), h_sigma((size_t)count * stride, 0.0), h_sigsum((size_t)count * stride, 0.0);
   std::vector<int> h_clog2(count), h_exp((size_t)count * stride, 0);
   std::vector<RunScalars> h_sc(count);
@@ -1256,7 +1252,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     bd.tau_coef = 4.0 * (stride + S[i].beta_hi + 2.0) * (h_dmax[i] + 2.0) * 0x1p-126;
     gs.xbuf[0] = w.x[0];
     gs.xbuf[1] = w.x[1];
-    gs.etap = etap;
+    gs.etap = etap + (size_t)i * stride;
     gs.act[0] = w.act[0] + h_base[i];
     gs.act[1] = w.act[1] + h_base[i];
     gs.keys = w.keys + h_base[i];
@@ -1277,15 +1273,16 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     h_oup[i] = out_host ? st_up + koff : out[i].upper;
     koff += p[i].k;
   }
-  std::vector<double> h_etap(stride, 0.0);
+  std::vector<double> h_etap((size_t)count * stride, 0.0);
   if (fp32)
-    for (int r = 0; r <= max_iter; ++r) h_etap[r] = G.etap[r];
+    for (int i = 0; i < count; ++i)
+      for (int r = 0; r <= max_iter; ++r) h_etap[(size_t)i * stride + r] = S[i].etap[r];
   KATZ_HIP(hipMemcpyAsync(galpha, h_alpha.data(), sizeof(double) * count, hipMemcpyHostToDevice, s));
   KATZ_HIP(hipMemcpyAsync(gclog2, h_clog2.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
   KATZ_HIP(hipMemcpyAsync(gsigma, h_sigma.data(), sizeof(double) * h_sigma.size(), hipMemcpyHostToDevice, s));
   KATZ_HIP(hipMemcpyAsync(gsigsum, h_sigsum.data(), sizeof(double) * h_sigsum.size(), hipMemcpyHostToDevice, s));
   KATZ_HIP(hipMemcpyAsync(gexp, h_exp.data(), sizeof(int) * h_exp.size(), hipMemcpyHostToDevice, s));
-  KATZ_HIP(hipMemcpyAsync(etap, h_etap.data(), sizeof(double) * stride, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(etap, h_etap.data(), sizeof(double) * h_etap.size(), hipMemcpyHostToDevice, s));
   KATZ_HIP(hipMemcpyAsync(gsc, h_sc.data(), sizeof(RunScalars) * count, hipMemcpyHostToDevice, s));
   KATZ_HIP(hipMemcpyAsync(gsel, h_sel.data(), sizeof(GraphSel) * count, hipMemcpyHostToDevice, s));
   KATZ_HIP(hipMemcpyAsync(o_ids, h_oids.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
@@ -1304,7 +1301,6 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   bw.desc = b.desc;
   bw.segs = b.segs;
   bw.huge = b.huge;
-  bw.seg_done = b.seg_done;
   {
     IterArgs tmp{};
     long long tb = 0;
@@ -1350,7 +1346,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   KATZ_HIP(hipStreamSynchronize(s));
   KATZ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   for (int it = 0; it < kItersPerGraph; ++it) {
-    KATZ_HIP(launch_walk_batch(bw, total_blocks, cs));
+    KATZ_HIP(launch_walk_batch(bw, total_blocks, b.bin_count[BIN_HUGE], cs));
     KATZ_HIP(launch_select_wg(gsel, count, r_dev, cs));
     KATZ_HIP(launch_batch_advance(r_dev, count, gsc, gxmax32, gsigma, gsigsum, gexp, galpha, gclog2, stride, fp32,
                                   ndone, cs));
@@ -1404,7 +1400,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     out[i].status = fin[i].done ? fin[i].status : KATZ_W_ITER_LIMIT;
     out[i].active_final = fin[i].m;
     out[i].alpha_used = S[i].alpha;
-    out[i].eta = fp32 ? G.eta[std::max(1, fin[i].iterations)] : 0.0;
+    out[i].eta = fp32 ? S[i].eta[std::max(1, fin[i].iterations)] : 0.0;
     out[i].rest_upper_max = (p[i].k == g[i].n) ? -std::numeric_limits<double>::infinity() : h_rest[i];
     worst = std::max(worst, out[i].status);
   }
@@ -1453,7 +1449,6 @@ int alloc_bins(katz_state* st, Bins& b) {
     dfree(st, b.desc);
     dfree(st, b.segs);
     dfree(st, b.huge);
-    dfree(st, b.seg_done);
     dfree(st, b.blk);
     dfree(st, b.scan_sums);
     dfree(st, b.scan_totals);
@@ -1462,12 +1457,10 @@ int alloc_bins(katz_state* st, Bins& b) {
   b.desc = dalloc<RowDesc>(st, st->n);
   b.segs = dalloc<SegDesc>(st, b.seg_cap);
   b.huge = dalloc<HugeRow>(st, b.huge_cap);
-  b.seg_done = dalloc<int>(st, b.huge_cap);
   b.blk = dalloc<long long>(st, (size_t)(NUM_BINS + 2) * b.nblocks);
   b.scan_sums = dalloc<long long>(st, scan_sums_capacity((long long)NUM_BINS * b.nblocks));
   b.scan_totals = dalloc<long long>(st, 2);
-  if (!b.desc || !b.segs || !b.huge || !b.seg_done || !b.blk || !b.scan_sums || !b.scan_totals) return KATZ_E_OOM;
-  KATZ_HIP(hipMemset(b.seg_done, 0, sizeof(int) * b.huge_cap));
+  if (!b.desc || !b.segs || !b.huge || !b.blk || !b.scan_sums || !b.scan_totals) return KATZ_E_OOM;
   return KATZ_OK;
 }
 
@@ -1475,7 +1468,7 @@ int alloc_partial(katz_state* st) {
   if (st->w.partial) dfree(st, st->w.partial);
   if (st->w.blkmax) dfree(st, st->w.blkmax);
   st->w.partial = dalloc<double>(st, st->bins.seg_cap);
-  st->w.blkmax = dalloc<double>(st, st->n + st->bins.seg_cap + 1);
+  st->w.blkmax = dalloc<double>(st, st->n + 2 * st->bins.seg_cap + 16);
   return st->w.partial && st->w.blkmax ? KATZ_OK : KATZ_E_OOM;
 }
 

@@ -153,7 +153,7 @@ __device__ __forceinline__ void batch_epilogue(const BatchWalk& a, int r, int g,
     const double s = sigma * (double)xs;
     const double e_prev = (r == 1) ? 0.0 : (double)a.e[row];
     a.c[row] = (r == 1) ? s : a.c[row] + s;
-    a.e[row] = __double2float_ru((e_prev + a.etap[r] * s) * (1.0 + 0x1p-50));
+    a.e[row] = __double2float_ru((e_prev + a.etap[(long long)g * a.stride + r] * s) * (1.0 + 0x1p-50));
     vmax = fmax(vmax, (double)xs);
   }
 }
@@ -231,31 +231,14 @@ __global__ void __launch_bounds__(kWG) walk_batch(BatchWalk a) {
   const T* xin = reinterpret_cast<const T*>(a.xbuf[(r + 1) & 1]);
   switch (bin) {
     case BIN_HUGE: {
-      __shared__ int s_last;
+      // One segment of a long row: its partial sum only (batch_huge_combine
+      // adds each row's partials in segment order after this launch).
       const SegDesc sd = a.segs[lb];
       const HugeRow h = a.huge[sd.hrow];
       const int g = a.gid_of[h.row];
       if (!graph_live<F32>(a, g)) break;          // uniform over the workgroup
       const T tot = batch_block_sum<F32>(xin + a.gbase[g], a.gcol[g] + sd.off, sd.len);
-      T* part = reinterpret_cast<T*>(a.partial);
-      if (threadIdx.x == 0) {
-        part[sd.part] = tot;
-        __threadfence();
-        s_last = atomicAdd(&a.seg_done[sd.hrow], 1) == h.nseg - 1;
-      }
-      __syncthreads();
-      if (s_last && threadIdx.x < kWave) {
-        __threadfence();
-        const int lane = threadIdx.x;
-        T sum = 0;
-        for (int s2 = lane; s2 < h.nseg; s2 += kWave) sum += part[h.part0 + s2];
-        for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
-        if (lane == 0) {
-          batch_epilogue<F32>(a, r, g, h.row, sum, vmax);
-          g_mine = g;
-          a.seg_done[sd.hrow] = 0;
-        }
-      }
+      if (threadIdx.x == 0) reinterpret_cast<T*>(a.partial)[sd.part] = tot;
       break;
     }
     case BIN_B256: {
@@ -291,6 +274,34 @@ __global__ void __launch_bounds__(kWG) walk_batch(BatchWalk a) {
       break;
     }
     default: break;
+  }
+  batch_store_max<F32>(a, r, g_mine, vmax);
+}
+
+// Rows longer than one segment: one wave per row of a live graph adds the
+// row's partials in segment order and runs the epilogue.
+template <bool F32>
+__global__ void __launch_bounds__(kWG) batch_huge_combine(BatchWalk a, long long n_huge) {
+  using T = typename Prec<F32>::T;
+  const int r = *a.r_dev;
+  if (r >= a.stride) return;
+  double vmax = 0.0;
+  int g_mine = -1;
+  const long long i = (long long)blockIdx.x * (kWG / kWave) + threadIdx.x / kWave;
+  if (i < n_huge) {
+    const HugeRow h = a.huge[i];
+    const int g = a.gid_of[h.row];
+    if (graph_live<F32>(a, g)) {            // uniform over the wave
+      const int lane = lane_id();
+      const T* part = reinterpret_cast<const T*>(a.partial);
+      T sum = 0;
+      for (int s2 = lane; s2 < h.nseg; s2 += kWave) sum += part[h.part0 + s2];
+      for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
+      if (lane == 0) {
+        batch_epilogue<F32>(a, r, g, h.row, sum, vmax);
+        g_mine = g;
+      }
+    }
   }
   batch_store_max<F32>(a, r, g_mine, vmax);
 }
@@ -423,10 +434,15 @@ hipError_t launch_fill_ones(void* x, long long n, int fp32, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, hipStream_t s) {
+hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, long long n_huge, hipStream_t s) {
   const unsigned grid = (unsigned)std::max<long long>(1, total_blocks);
   if (a.fp32) hipLaunchKernelGGL(walk_batch<true>, dim3(grid), dim3(kWG), 0, s, a);
   else hipLaunchKernelGGL(walk_batch<false>, dim3(grid), dim3(kWG), 0, s, a);
+  if (n_huge > 0) {
+    const unsigned cg = (unsigned)((n_huge + kWG / kWave - 1) / (kWG / kWave));
+    if (a.fp32) hipLaunchKernelGGL(batch_huge_combine<true>, dim3(cg), dim3(kWG), 0, s, a, n_huge);
+    else hipLaunchKernelGGL(batch_huge_combine<false>, dim3(cg), dim3(kWG), 0, s, a, n_huge);
+  }
   return hipGetLastError();
 }
 

@@ -6,8 +6,10 @@
 //     fixed number of lanes per row, so the summation order of every row, and
 //     therefore its floating-point result, depends only on the row's length.
 //   * Rows longer than kBlockRowMax are cut into segments of kSeg arcs; one
-//     workgroup sums a segment; the workgroup that finishes a row's last
-//     segment combines the row's partials in segment order.
+//     workgroup sums a segment, and a second launch (one wave per row) adds a
+//     row's partials in segment order.  The kernel boundary orders the two,
+//     so no device-scope fence is needed between workgroups (on a multi-XCD
+//     part such a fence writes back or invalidates a whole L2).
 //   * The first walk step (x_0 = 1) sums no vector: row v's sum is its length.
 //   * The walk vector is double-buffered; c (FP64) is updated in place; the
 //     FP32 form adds the per-node margin accumulator e (FP32, rounded up).
@@ -128,7 +130,7 @@ struct IterArgs {
   float* e;
   void* partial;
   void* blkmax;                  // per-workgroup maximum of the new walk entries
-  int* seg_done;                 // [n_huge] segments finished this iteration
+  long long blk_base;            // first slot of this launch's workgroup maxima in blkmax
   unsigned* xmax32;              // [max_iter + 1] float bits of max x~_r
   unsigned long long* xmax64;    // [max_iter + 1] double bits of max s_r
   double* sigma;                 // [max_iter + 1]
@@ -200,7 +202,6 @@ struct BatchWalk {
   const RowDesc* desc;
   const SegDesc* segs;
   const HugeRow* huge;
-  int* seg_done;
   long long first_block[NUM_BINS + 1];
   long long bin_base[NUM_BINS];
   long long bin_count[NUM_BINS];
@@ -217,7 +218,7 @@ struct BatchWalk {
   double* c;
   float* e;
   void* partial;
-  const double* etap;           // eta'_r
+  const double* etap;           // eta'_r per graph: [count][stride]
   const int* r_dev;
   int stride;
   int fp32;
@@ -308,7 +309,7 @@ hipError_t launch_batch_prep(const long long* gbase, const void* const* grp, con
                              SegDesc* segs, HugeRow* huge, RunScalars* sc, int validate, hipStream_t s);
 hipError_t launch_batch_dmax(const RowDesc* desc, long long count, const int* gid_of, int* gdmax, hipStream_t s);
 hipError_t launch_fill_ones(void* x, long long n, int fp32, hipStream_t s);
-hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, hipStream_t s);
+hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, long long n_huge, hipStream_t s);
 hipError_t launch_batch_advance(int* r_dev, int count, RunScalars* gsc, const unsigned* gxmax32, double* gsigma,
                                 double* gsigsum, int* gexp, const double* galpha, const int* gclog2, int stride,
                                 int fp32, int* ndone, hipStream_t s);

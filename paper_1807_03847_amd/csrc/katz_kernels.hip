@@ -256,17 +256,17 @@ __device__ __forceinline__ typename Prec<F32>::T block_sum(const IterArgs& a, co
 }
 
 // Per-workgroup maximum of the new walk entries, stored without atomics (a
-// one-block kernel reduces the array afterwards).  All threads must call it.
+// later kernel reduces the array).  All threads must call it.
 template <bool F32>
-__device__ __forceinline__ void store_block_max(const IterArgs& a, double vmax) {
+__device__ __forceinline__ void store_block_max(const IterArgs& a, double vmax, long long slot) {
   __shared__ double wm[kWG / kWave];
   for (int o = 32; o >= 1; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
   if (lane_id() == 0) wm[threadIdx.x / kWave] = vmax;
   __syncthreads();
   if (threadIdx.x == 0) {
     const double m = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
-    if constexpr (F32) reinterpret_cast<float*>(a.blkmax)[blockIdx.x] = (float)m;
-    else reinterpret_cast<double*>(a.blkmax)[blockIdx.x] = m;
+    if constexpr (F32) reinterpret_cast<float*>(a.blkmax)[slot] = (float)m;
+    else reinterpret_cast<double*>(a.blkmax)[slot] = m;
   }
 }
 
@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(kWG) walk_first(IterArgs a) {
     const RowDesc d = a.desc[i];
     epilogue<F32>(a, ep, d.row, (typename Prec<F32>::T)d.len, vmax);
   }
-  store_block_max<F32>(a, vmax);
+  store_block_max<F32>(a, vmax, blockIdx.x);
 }
 
 // 0 <= col < n for every arc (basic validation, before the first gather).
@@ -329,32 +329,11 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
     const long long lb = b - a.first_block[bin];
     switch (bin) {
       case BIN_HUGE: {
-        __shared__ int s_last;
+        // One 4096-arc segment of a long row: its partial sum only; huge_combine
+        // adds the partials of each row in segment order after this launch.
         const SegDesc sd = a.segs[lb];
         const T tot = block_sum<F32>(a, hub, a.col + sd.off, sd.len);
-        T* part = reinterpret_cast<T*>(a.partial);
-        if (threadIdx.x == 0) {
-          part[sd.part] = tot;
-          __threadfence();
-          const HugeRow h = a.huge[sd.hrow];
-          s_last = atomicAdd(&a.seg_done[sd.hrow], 1) == h.nseg - 1;
-        }
-        __syncthreads();
-        if (s_last && threadIdx.x < kWave) {
-          // This workgroup finished the row's last segment: combine all partials
-          // in segment order (lane l takes l, l+64, ...; then a butterfly).
-          __threadfence();
-          const HugeRow h = a.huge[sd.hrow];
-          const int lane = threadIdx.x;
-          T sum = 0;
-          for (int s2 = lane; s2 < h.nseg; s2 += kWave) sum += part[h.part0 + s2];
-          for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
-          if (lane == 0) {
-            epilogue<F32>(a, ep, h.row, sum, vmax);
-            a.seg_done[sd.hrow] = 0;
-          }
-        }
-        __syncthreads();
+        if (threadIdx.x == 0) reinterpret_cast<T*>(a.partial)[sd.part] = tot;
         break;
       }
       case BIN_B256: {
@@ -380,7 +359,30 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
       default: break;
     }
   }
-  store_block_max<F32>(a, vmax);
+  store_block_max<F32>(a, vmax, blockIdx.x);
+}
+
+// Rows longer than one segment: one wave per row adds the row's segment
+// partials in segment order (lane l takes l, l+64, ...; then a butterfly) and
+// runs the epilogue.  Launched after walk_step, so the kernel boundary makes the
+// partials visible to every workgroup without fences.
+template <bool F32>
+__global__ void __launch_bounds__(kWG) huge_combine(IterArgs a) {
+  if (a.sc->err || a.sc->done) return;
+  using T = typename Prec<F32>::T;
+  const Epi<F32> ep = compute_epi<F32>(a);
+  double vmax = 0.0;
+  const long long i = (long long)blockIdx.x * (kWG / kWave) + threadIdx.x / kWave;
+  if (i < a.bin_count[BIN_HUGE]) {
+    const HugeRow h = a.huge[i];
+    const int lane = lane_id();
+    const T* part = reinterpret_cast<const T*>(a.partial);
+    T sum = 0;
+    for (int s2 = lane; s2 < h.nseg; s2 += kWave) sum += part[h.part0 + s2];
+    for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
+    if (lane == 0) epilogue<F32>(a, ep, h.row, sum, vmax);
+  }
+  store_block_max<F32>(a, vmax, a.blk_base + blockIdx.x);
 }
 
 __global__ void __launch_bounds__(kWG) reduce_blkmax(const void* blkmax, long long nb, int fp32,
@@ -978,15 +980,27 @@ hipError_t launch_reduce_blkmax(const void* blkmax, long long nb, int fp32, unsi
   return hipGetLastError();
 }
 
+// walk_step, then huge_combine when there are rows longer than one segment.
+// *blocks_used: workgroup maxima written to a.blkmax (both launches).
 hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, long long max_grid,
-                            long long* grid_used, hipStream_t s) {
+                            long long* blocks_used, hipStream_t s) {
   long long g = total_blocks > 0 ? total_blocks : 1;
   if (max_grid > 0) g = std::min(g, max_grid);
   const size_t lds = (size_t)a.hub_n * (fp32 ? sizeof(float) : sizeof(double));
   if (a.hub_n > 0 && max_grid <= 0) return hipErrorInvalidValue;   // the copy pays only on a persistent grid
-  *grid_used = g;
   if (fp32) hipLaunchKernelGGL(walk_step<true>, dim3((unsigned)g), dim3(kWG), lds, s, a);
   else hipLaunchKernelGGL(walk_step<false>, dim3((unsigned)g), dim3(kWG), lds, s, a);
+  long long used = g;
+  const long long nh = a.bin_count[BIN_HUGE];
+  if (nh > 0) {
+    IterArgs c = a;
+    c.blk_base = g;
+    const long long cg = (nh + kWG / kWave - 1) / (kWG / kWave);
+    if (fp32) hipLaunchKernelGGL(huge_combine<true>, dim3((unsigned)cg), dim3(kWG), 0, s, c);
+    else hipLaunchKernelGGL(huge_combine<false>, dim3((unsigned)cg), dim3(kWG), 0, s, c);
+    used += cg;
+  }
+  *blocks_used = used;
   return hipGetLastError();
 }
 

@@ -95,3 +95,25 @@ def test_batch_rejects_mixed_precision():
     with pytest.raises(katz.KatzError) as e:
         katz.rank_static_batch(gl, pl)
     assert e.value.code == katz.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_long_rows_match_single(precision):
+    """Rows longer than one 4096-arc segment (a star hub, R-MAT hubs) are summed
+    in segments and combined per row; each graph's result equals the
+    single-graph call bitwise."""
+    katz = K()
+    rp1, col1 = sg.star_graph(9000)
+    rp2, col2 = sg.rmat(15, seed=21)
+    rp3, col3 = sg.barabasi_albert(3000, 6, 22)
+    graphs = [(rp1, col1), (rp2, col2), (rp3, col3)]
+    assert sg.max_degree(rp1) > 8192 and sg.max_degree(rp2) > 4096
+    params = [dict(k=min(50, len(rp) - 1), alpha=0.5 / (1 + sg.max_degree(rp)), eps=1e-7) for rp, _ in graphs]
+    say("batch long rows", precision)
+    res = run_batch(graphs, params, precision)
+    for (rp, col), pp, rb in zip(graphs, params, res):
+        single = katz.rank_static(torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda(), pp["k"],
+                                  alpha=pp["alpha"], eps=pp["eps"], precision=precision)
+        assert torch.equal(single.topk, rb.topk)
+        assert torch.equal(single.lower, rb.lower) and torch.equal(single.upper, rb.upper)
+        assert single.iterations == rb.iterations and single.status == rb.status
