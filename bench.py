@@ -35,6 +35,28 @@ def algorithmic_bytes_per_walk_step(n, nnz, precision):
     return 4 * nnz + per_node * n
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "walk_step_rmat22_counters.json")
+
+
+def measured_traffic(tuning_arg):
+    """HBM bytes per walk_step launch from the committed FETCH_SIZE / WRITE_SIZE
+    record (scaled by the copy calibration stored with it), or None when the
+    kernel sources or the launch tuning differ from the ones measured."""
+    import hashlib
+    try:
+        rec = json.load(open(COUNTERS))
+    except (OSError, ValueError):
+        return None, "no counter record"
+    for path, digest in rec["sources_sha256"].items():
+        with open(os.path.join(ROOT, path), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None, f"kernel source changed since the counters were taken ({path})"
+    if rec["tuning"] != tuning_arg:
+        return None, f"counters taken at tuning {rec['tuning']}, timed at {tuning_arg}"
+    return rec["traffic_bytes_per_launch"], ("FETCH_SIZE x%.2f + WRITE_SIZE x%.2f per launch, from %s" % (
+        rec["calibration"]["fetch_scale"], rec["calibration"]["write_scale"], os.path.relpath(COUNTERS, ROOT)))
+
+
 def time_form(katz, torch, rp_t, col_t, precision, steps, warmup, flags=0):
     for _ in range(warmup):
         res = katz.rank_static(rp_t, col_t, K, eps=EPS, precision=precision, flags=flags)
@@ -117,7 +139,10 @@ def main():
             tunings[precision] = katz.tuning_get()
         print(f"[bench] {precision} tuning {tunings[precision]}", flush=True)
         res, sec, tm = time_form(katz, torch, rp_t, col_t, precision, args.steps, args.warmup)
-        walk_avg_ms = tm["walk_step_ms"] / max(tm["walk_step_launches"], 1)
+        # Walk steps that did work: r - 1 per call.  The host enqueues one more
+        # walk launch before it reads the stop flag; that launch returns at once
+        # and is not a walk step.
+        walk_avg_ms = tm["walk_step_ms"] / max(tm["calls"] * (res.iterations - 1), 1)
         forms[precision] = dict(res=res, sec=sec, tm=tm, walk_avg_ms=walk_avg_ms,
                                 gteps=res.iterations * nnz / sec / 1e9)
         print(f"[bench] {precision}: r={res.iterations} status={res.status} {sec * 1e3:.3f} ms/step "
@@ -180,25 +205,27 @@ def main():
             "traffic": None,
             "bytes_per_launch": bytes_step,
             "avg_launch_us": round(f32["walk_avg_ms"] * 1e3, 2),
+            "walk_steps_timed": f32["tm"]["calls"] * (f32["res"].iterations - 1),
             "launches_timed": f32["tm"]["walk_step_launches"],
         },
     }
 
     out["fp32_caller_order"] = {
         "ms_per_step": round(sec_nr * 1e3, 4),
-        "walk_step_avg_us": round(tm_nr["walk_step_ms"] / max(tm_nr["walk_step_launches"], 1) * 1e3, 2),
+        "walk_step_avg_us": round(tm_nr["walk_step_ms"] / max(tm_nr["calls"] * (res_nr.iterations - 1), 1) * 1e3, 2),
         "same_result": bool(torch.equal(res_nr.topk, f32["res"].topk) and torch.equal(res_nr.lower, f32["res"].lower)),
     }
     same = bool(torch.equal(f32["res"].topk, f64["res"].topk))
     out["fp32_fp64_same_topk"] = same
     out["tuning"] = {p: dict(t, arg=f"{t['hub_bytes']}:{t['blocks_per_cu']}") for p, t in tunings.items()}
+    out["roofline"]["traffic"], out["roofline"]["traffic_note"] = measured_traffic(out["tuning"]["fp32"]["arg"])
     if args.tuning_sweep:
         sweep = []
         for hub, bpc in [(0, 0), (0, 2), (0, 4), (0, 8), (0, 16), (16384, 2), (16384, 4), (16384, 8),
                          (32768, 2), (32768, 4), (65536, 1), (65536, 2)]:
             katz.tuning_set(hub, bpc)
             r_s, sec_s, tm_s = time_form(katz, torch, rp_t, col_t, "fp32", max(1, args.steps // 2), 1)
-            walk_us = tm_s["walk_step_ms"] / max(tm_s["walk_step_launches"], 1) * 1e3
+            walk_us = tm_s["walk_step_ms"] / max(tm_s["calls"] * (r_s.iterations - 1), 1) * 1e3
             sweep.append({"hub_bytes": hub, "blocks_per_cu": bpc, "ms_per_step": round(sec_s * 1e3, 4),
                           "walk_step_avg_us": round(walk_us, 2),
                           "same_result": bool(torch.equal(r_s.topk, f32["res"].topk)

@@ -1097,6 +1097,9 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   unsigned long long* gxmax64 = nullptr;
   int* gid_of = nullptr;
   GraphSel* gsel = nullptr;
+  int* blk_g = nullptr;
+  double* blk_m = nullptr;
+  long long blk_cap = 0;
   int* r_dev = nullptr;
   int* ndone = nullptr;
   int32_t** o_ids = nullptr;
@@ -1127,6 +1130,11 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     rest = ar.take<double>(count);
     gid_of = ar.take<int>(total_n);
     gsel = ar.take<GraphSel>(count);
+    // Workgroup slots of one walk step: at most one per 4 rows of up to 1024
+    // arcs, one per longer row or segment, one per long row's combine wave group.
+    blk_cap = total_n / 4 + total_nnz / 1025 + 2 * b.seg_cap + 64;
+    blk_g = ar.take<int>(blk_cap);
+    blk_m = ar.take<double>(blk_cap);
     r_dev = ar.take<int>(1);
     ndone = ar.take<int>(1);
     o_ids = ar.take<int32_t*>(count);
@@ -1328,8 +1336,16 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   bw.etap = etap;
   bw.r_dev = r_dev;
   bw.stride = stride;
+  bw.blk_g = blk_g;
+  bw.blk_m = blk_m;
+  bw.count = count;
+  bw.direct_max = count > kBatchMaxLdsGraphs ? 1 : 0;
   bw.fp32 = fp32;
   const long long total_blocks = bw.first_block[NUM_BINS];
+  {
+    const long long nh = b.bin_count[BIN_HUGE];
+    if (total_blocks + (nh + kWG / kWave - 1) / (kWG / kWave) > blk_cap) return KATZ_E_HIP;   // sizing bound broken
+  }
 
   hipStream_t cs = nullptr;
   KATZ_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));

@@ -158,20 +158,90 @@ __device__ __forceinline__ void batch_epilogue(const BatchWalk& a, int r, int g,
   }
 }
 
-// Per-graph maxima: one atomic per wave when the wave's rows share a graph.
+__device__ __forceinline__ void graph_max_atomic(const BatchWalk& a, int r, int g, double m, bool f32) {
+  if (f32) atomicMax(&a.gxmax32[(long long)g * a.stride + r], __float_as_uint((float)m));
+  else atomicMax(&a.gxmax64[(long long)g * a.stride + r], (unsigned long long)__double_as_longlong(m));
+}
+
+// Per-workgroup maximum of the new walk entries.  A workgroup whose rows belong
+// to one graph stores (graph, maximum) in its slot, and batch_reduce_max folds
+// the slots into the per-graph maxima (no same-address atomics in the walk);
+// rows of several graphs in one workgroup (only where a bin crosses a graph
+// boundary) update the per-graph maxima with atomics.  All threads call it.
 template <bool F32>
-__device__ __forceinline__ void batch_store_max(const BatchWalk& a, int r, int g, double vmax) {
-  const int g0 = __shfl(g, 0);
-  const bool uniform = __all(g == g0 || g < 0);
-  if (uniform) {
-    for (int o = 32; o >= 1; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
-    if (lane_id() == 0 && g0 >= 0 && vmax > 0.0) {
-      if constexpr (F32) atomicMax(&a.gxmax32[(long long)g0 * a.stride + r], __float_as_uint((float)vmax));
-      else atomicMax(&a.gxmax64[(long long)g0 * a.stride + r], (unsigned long long)__double_as_longlong(vmax));
+__device__ __forceinline__ void batch_store_max(const BatchWalk& a, int r, int g, double vmax, long long slot) {
+  __shared__ int s_g[kWG / kWave];
+  __shared__ double s_m[kWG / kWave];
+  const unsigned long long present = __ballot(g >= 0);
+  const int src = present ? __ffsll((long long)present) - 1 : 0;
+  const int g0 = __shfl(g, src);
+  const bool uniform = __all(g < 0 || g == g0);
+  double m = vmax;
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if (a.direct_max) {
+    if (uniform) {
+      if (lane_id() == 0 && present && m > 0.0) graph_max_atomic(a, r, g0, m, F32);
+    } else if (g >= 0 && vmax > 0.0) {
+      graph_max_atomic(a, r, g, vmax, F32);
     }
-  } else if (g >= 0 && vmax > 0.0) {
-    if constexpr (F32) atomicMax(&a.gxmax32[(long long)g * a.stride + r], __float_as_uint((float)vmax));
-    else atomicMax(&a.gxmax64[(long long)g * a.stride + r], (unsigned long long)__double_as_longlong(vmax));
+    return;
+  }
+  if (!uniform && g >= 0 && vmax > 0.0) graph_max_atomic(a, r, g, vmax, F32);
+  if (lane_id() == 0) {
+    s_g[threadIdx.x / kWave] = present == 0 ? -1 : (uniform ? g0 : -2);
+    s_m[threadIdx.x / kWave] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int bg = -1;
+    bool mixed = false;
+    double bm = 0.0;
+    for (int w = 0; w < kWG / kWave; ++w) {
+      if (s_g[w] < 0) {
+        mixed = mixed || s_g[w] == -2;
+        continue;
+      }
+      if (bg < 0) bg = s_g[w];
+      if (s_g[w] != bg) mixed = true;
+      bm = fmax(bm, s_m[w]);
+    }
+    if (mixed) {
+      for (int w = 0; w < kWG / kWave; ++w)
+        if (s_g[w] >= 0 && s_m[w] > 0.0) graph_max_atomic(a, r, s_g[w], s_m[w], F32);
+      bg = -1;
+    }
+    a.blk_g[a.blk_base + slot] = bm > 0.0 ? bg : -1;
+    a.blk_m[a.blk_base + slot] = bm;
+  }
+}
+
+// Folds the workgroup slots of one iteration into the per-graph maxima: each
+// workgroup reduces a contiguous run of slots in LDS (one entry per graph) and
+// issues one atomic per graph it saw.
+template <bool F32>
+__global__ void __launch_bounds__(kWG) batch_reduce_max(BatchWalk a, long long nb) {
+  const int r = *a.r_dev;
+  if (r >= a.stride) return;
+  extern __shared__ unsigned long long gmax_lds[];
+  for (int i = threadIdx.x; i < a.count; i += kWG) gmax_lds[i] = 0ull;
+  __syncthreads();
+  const long long per = (nb + gridDim.x - 1) / gridDim.x;
+  const long long lo = (long long)blockIdx.x * per;
+  const long long hi = min(nb, lo + per);
+  for (long long e = lo + threadIdx.x; e < hi; e += kWG) {
+    const int g = a.blk_g[e];
+    if (g < 0) continue;
+    const double m = a.blk_m[e];
+    const unsigned long long bits =
+        F32 ? (unsigned long long)__float_as_uint((float)m) : (unsigned long long)__double_as_longlong(m);
+    atomicMax(&gmax_lds[g], bits);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.count; i += kWG) {
+    const unsigned long long v = gmax_lds[i];
+    if (!v) continue;
+    if constexpr (F32) atomicMax(&a.gxmax32[(long long)i * a.stride + r], (unsigned)v);
+    else atomicMax(&a.gxmax64[(long long)i * a.stride + r], v);
   }
 }
 
@@ -275,7 +345,7 @@ __global__ void __launch_bounds__(kWG) walk_batch(BatchWalk a) {
     }
     default: break;
   }
-  batch_store_max<F32>(a, r, g_mine, vmax);
+  batch_store_max<F32>(a, r, g_mine, vmax, blockIdx.x);
 }
 
 // Rows longer than one segment: one wave per row of a live graph adds the
@@ -303,7 +373,7 @@ __global__ void __launch_bounds__(kWG) batch_huge_combine(BatchWalk a, long long
       }
     }
   }
-  batch_store_max<F32>(a, r, g_mine, vmax);
+  batch_store_max<F32>(a, r, g_mine, vmax, blockIdx.x);
 }
 
 // After the selection of iteration r: FP32 scales of iteration r + 1 for every
@@ -434,14 +504,28 @@ hipError_t launch_fill_ones(void* x, long long n, int fp32, hipStream_t s) {
   return hipGetLastError();
 }
 
+// One walk step of the batch: walk_batch, batch_huge_combine for rows longer
+// than one segment, and batch_reduce_max for the per-graph maxima.
 hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, long long n_huge, hipStream_t s) {
   const unsigned grid = (unsigned)std::max<long long>(1, total_blocks);
-  if (a.fp32) hipLaunchKernelGGL(walk_batch<true>, dim3(grid), dim3(kWG), 0, s, a);
-  else hipLaunchKernelGGL(walk_batch<false>, dim3(grid), dim3(kWG), 0, s, a);
+  BatchWalk w = a;
+  w.blk_base = 0;
+  if (a.fp32) hipLaunchKernelGGL(walk_batch<true>, dim3(grid), dim3(kWG), 0, s, w);
+  else hipLaunchKernelGGL(walk_batch<false>, dim3(grid), dim3(kWG), 0, s, w);
+  long long nb = grid;
   if (n_huge > 0) {
     const unsigned cg = (unsigned)((n_huge + kWG / kWave - 1) / (kWG / kWave));
-    if (a.fp32) hipLaunchKernelGGL(batch_huge_combine<true>, dim3(cg), dim3(kWG), 0, s, a, n_huge);
-    else hipLaunchKernelGGL(batch_huge_combine<false>, dim3(cg), dim3(kWG), 0, s, a, n_huge);
+    BatchWalk c = a;
+    c.blk_base = grid;
+    if (a.fp32) hipLaunchKernelGGL(batch_huge_combine<true>, dim3(cg), dim3(kWG), 0, s, c, n_huge);
+    else hipLaunchKernelGGL(batch_huge_combine<false>, dim3(cg), dim3(kWG), 0, s, c, n_huge);
+    nb += cg;
+  }
+  if (!a.direct_max) {
+    const unsigned rg = (unsigned)std::min<long long>(64, (nb + 4095) / 4096);
+    const size_t lds = sizeof(unsigned long long) * (size_t)a.count;
+    if (a.fp32) hipLaunchKernelGGL(batch_reduce_max<true>, dim3(rg), dim3(kWG), lds, s, a, nb);
+    else hipLaunchKernelGGL(batch_reduce_max<false>, dim3(rg), dim3(kWG), lds, s, a, nb);
   }
   return hipGetLastError();
 }

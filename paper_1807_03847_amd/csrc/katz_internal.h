@@ -220,6 +220,11 @@ struct BatchWalk {
   void* partial;
   const double* etap;           // eta'_r per graph: [count][stride]
   const int* r_dev;
+  int* blk_g;                   // per workgroup: graph of all its rows, or -1
+  double* blk_m;                // per workgroup: maximum new walk entry of that graph
+  long long blk_base;           // first slot of this launch in blk_g / blk_m
+  int count;                    // graphs in the batch
+  int direct_max;               // 1: workgroups update per-graph maxima with atomics
   int stride;
   int fp32;
 };
@@ -310,6 +315,7 @@ hipError_t launch_batch_prep(const long long* gbase, const void* const* grp, con
 hipError_t launch_batch_dmax(const RowDesc* desc, long long count, const int* gid_of, int* gdmax, hipStream_t s);
 hipError_t launch_fill_ones(void* x, long long n, int fp32, hipStream_t s);
 hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, long long n_huge, hipStream_t s);
+constexpr int kBatchMaxLdsGraphs = 8192;   // per-graph maxima reduced in LDS up to this many graphs
 hipError_t launch_batch_advance(int* r_dev, int count, RunScalars* gsc, const unsigned* gxmax32, double* gsigma,
                                 double* gsigsum, int* gexp, const double* galpha, const int* gclog2, int stride,
                                 int fp32, int* ndone, hipStream_t s);
