@@ -133,27 +133,51 @@ __device__ __forceinline__ typename Prec<F32>::T batch_strided_sum(const typenam
   return sum;
 }
 
+// Per-row inputs of the epilogue, loaded as soon as the row and its graph are
+// known so that the loads overlap the gathers: the previous c (and FP32 margin
+// e) of the row, and the graph's alpha (FP64) or FP32 scale of iteration r.
+struct BatchIn {
+  double c;
+  double scale;
+  double etap;
+  float e;
+  int ex;
+};
+
+template <bool F32>
+__device__ __forceinline__ BatchIn batch_prefetch(const BatchWalk& a, int r, int g, int row) {
+  BatchIn p{0.0, 0.0, 0.0, 0.0f, 0};
+  if (r > 1) p.c = a.c[row];
+  if constexpr (F32) {
+    const long long at = (long long)g * a.stride + r;
+    if (r > 1) p.e = a.e[row];
+    p.ex = a.gexp[at];
+    p.scale = a.gsigma[at];
+    p.etap = a.etap[at];
+  } else {
+    p.scale = a.galpha[g];
+  }
+  return p;
+}
+
 // Row epilogue of the batched walk (same arithmetic as the single-graph one,
 // with the graph's alpha and FP32 scale).
 template <bool F32>
-__device__ __forceinline__ void batch_epilogue(const BatchWalk& a, int r, int g, int row, typename Prec<F32>::T t,
-                                               double& vmax) {
-  const int in = (r + 1) & 1, out = r & 1;
-  (void)in;
+__device__ __forceinline__ void batch_epilogue(const BatchWalk& a, int r, int row, typename Prec<F32>::T t,
+                                               double& vmax, const BatchIn& p) {
+  const int out = r & 1;
   if constexpr (!F32) {
-    const double s = a.galpha[g] * t;
+    const double s = p.scale * t;
     reinterpret_cast<double*>(a.xbuf[out])[row] = s;
-    a.c[row] = (r == 1) ? s : a.c[row] + s;
+    a.c[row] = (r == 1) ? s : p.c + s;
     vmax = fmax(vmax, s);
   } else {
-    const int ex = a.gexp[(long long)g * a.stride + r];
-    const double sigma = a.gsigma[(long long)g * a.stride + r];
-    const float xs = ldexpf(t, -ex);
+    const float xs = ldexpf(t, -p.ex);
     reinterpret_cast<float*>(a.xbuf[out])[row] = xs;
-    const double s = sigma * (double)xs;
-    const double e_prev = (r == 1) ? 0.0 : (double)a.e[row];
-    a.c[row] = (r == 1) ? s : a.c[row] + s;
-    a.e[row] = __double2float_ru((e_prev + a.etap[(long long)g * a.stride + r] * s) * (1.0 + 0x1p-50));
+    const double s = p.scale * (double)xs;
+    const double e_prev = (r == 1) ? 0.0 : (double)p.e;
+    a.c[row] = (r == 1) ? s : p.c + s;
+    a.e[row] = __double2float_ru((e_prev + p.etap * s) * (1.0 + 0x1p-50));
     vmax = fmax(vmax, (double)xs);
   }
 }
@@ -260,6 +284,8 @@ __device__ __forceinline__ void batch_rows_group(const BatchWalk& a, int r, long
     g = a.gid_of[d.row];
     valid = graph_live<F32>(a, g);
   }
+  BatchIn p{0.0, 0.0, 0.0, 0.0f, 0};
+  if (valid && lane == 0) p = batch_prefetch<F32>(a, r, g, d.row);
   T sum = 0;
   if (valid) {
     const T* x = reinterpret_cast<const T*>(a.xbuf[(r + 1) & 1]) + a.gbase[g];
@@ -268,7 +294,7 @@ __device__ __forceinline__ void batch_rows_group(const BatchWalk& a, int r, long
 #pragma unroll
   for (int o = G / 2; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, G);
   if (valid && lane == 0) {
-    batch_epilogue<F32>(a, r, g, d.row, sum, vmax);
+    batch_epilogue<F32>(a, r, d.row, sum, vmax, p);
     g_out = g;
   }
 }
@@ -315,9 +341,11 @@ __global__ void __launch_bounds__(kWG) walk_batch(BatchWalk a) {
       const RowDesc d = a.desc[a.bin_base[BIN_B256] + lb];
       const int g = a.gid_of[d.row];
       if (!graph_live<F32>(a, g)) break;
+      BatchIn p{0.0, 0.0, 0.0, 0.0f, 0};
+      if (threadIdx.x == 0) p = batch_prefetch<F32>(a, r, g, d.row);
       const T tot = batch_block_sum<F32>(xin + a.gbase[g], a.gcol[g] + d.off, d.len);
       if (threadIdx.x == 0) {
-        batch_epilogue<F32>(a, r, g, d.row, tot, vmax);
+        batch_epilogue<F32>(a, r, d.row, tot, vmax, p);
         g_mine = g;
       }
       break;
@@ -363,12 +391,14 @@ __global__ void __launch_bounds__(kWG) batch_huge_combine(BatchWalk a, long long
     const int g = a.gid_of[h.row];
     if (graph_live<F32>(a, g)) {            // uniform over the wave
       const int lane = lane_id();
+      BatchIn p{0.0, 0.0, 0.0, 0.0f, 0};
+      if (lane == 0) p = batch_prefetch<F32>(a, r, g, h.row);
       const T* part = reinterpret_cast<const T*>(a.partial);
       T sum = 0;
       for (int s2 = lane; s2 < h.nseg; s2 += kWave) sum += part[h.part0 + s2];
       for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
       if (lane == 0) {
-        batch_epilogue<F32>(a, r, g, h.row, sum, vmax);
+        batch_epilogue<F32>(a, r, h.row, sum, vmax, p);
         g_mine = g;
       }
     }

@@ -170,21 +170,38 @@ __device__ __forceinline__ Epi<F32> compute_epi(const IterArgs& a) {
   return ep;
 }
 
+// The row's previous c (and FP32 margin e), loaded as soon as the row id is
+// known so the load overlaps the gathers instead of following them.
+struct Prev {
+  double c;
+  float e;
+};
+
+template <bool F32>
+__device__ __forceinline__ Prev load_prev(const IterArgs& a, int row) {
+  Prev p{0.0, 0.0f};
+  if (a.r > 1 && !a.rewalk) {
+    p.c = a.c[row];
+    if constexpr (F32) p.e = a.e[row];
+  }
+  return p;
+}
+
 template <bool F32>
 __device__ __forceinline__ void epilogue(const IterArgs& a, const Epi<F32>& ep, int row,
-                                         typename Prec<F32>::T t, double& vmax) {
+                                         typename Prec<F32>::T t, double& vmax, const Prev& pv) {
   if constexpr (!F32) {
     const double s = a.alpha * t;
     reinterpret_cast<double*>(a.x_out)[row] = s;
     if (a.rewalk) return;
-    a.c[row] = (a.r == 1) ? s : a.c[row] + s;
+    a.c[row] = (a.r == 1) ? s : pv.c + s;
     vmax = fmax(vmax, s);
   } else {
     const float xs = ldexpf(t, -ep.e_r);
     reinterpret_cast<float*>(a.x_out)[row] = xs;
     const double s = ep.sigma_r * (double)xs;
-    const double e_prev = (a.r == 1) ? 0.0 : (double)a.e[row];
-    a.c[row] = (a.r == 1) ? s : a.c[row] + s;
+    const double e_prev = (a.r == 1) ? 0.0 : (double)pv.e;
+    a.c[row] = (a.r == 1) ? s : pv.c + s;
     a.e[row] = __double2float_ru((e_prev + a.etap * s) * (1.0 + 0x1p-50));
     vmax = fmax(vmax, (double)xs);
   }
@@ -225,7 +242,7 @@ __device__ __forceinline__ typename Prec<F32>::T strided_sum(const IterArgs& a, 
 
 template <bool F32, int G>
 __device__ __forceinline__ void rows_group(const IterArgs& a, const typename Prec<F32>::T* hub, const Epi<F32>& ep,
-                                           long long lb, int bin, double& vmax) {
+                                           long long lb, int bin, double& vmax, bool stop) {
   using T = typename Prec<F32>::T;
   constexpr int RPB = kWG / G;
   const int lane = threadIdx.x & (G - 1);
@@ -233,10 +250,13 @@ __device__ __forceinline__ void rows_group(const IterArgs& a, const typename Pre
   const bool valid = i < a.bin_count[bin];
   RowDesc d{0, 0, 0};
   if (valid) d = a.desc[a.bin_base[bin] + i];
+  Prev pv{0.0, 0.0f};
+  if (valid && lane == 0) pv = load_prev<F32>(a, d.row);
+  if (stop) return;
   T sum = strided_sum<F32, G>(a, hub, a.col + d.off, d.len, lane);
 #pragma unroll
   for (int o = G / 2; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, G);
-  if (valid && lane == 0) epilogue<F32>(a, ep, d.row, sum, vmax);
+  if (valid && lane == 0) epilogue<F32>(a, ep, d.row, sum, vmax, pv);
 }
 
 // Whole-workgroup sum of one row or segment: 256 strided lanes, wave
@@ -285,7 +305,7 @@ __global__ void __launch_bounds__(kWG) walk_first(IterArgs a) {
   const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
   if (i < a.count_first) {
     const RowDesc d = a.desc[i];
-    epilogue<F32>(a, ep, d.row, (typename Prec<F32>::T)d.len, vmax);
+    epilogue<F32>(a, ep, d.row, (typename Prec<F32>::T)d.len, vmax, Prev{0.0, 0.0f});
   }
   store_block_max<F32>(a, vmax, blockIdx.x);
 }
@@ -305,18 +325,22 @@ __global__ void __launch_bounds__(kWG) check_col_range(const int32_t* col, long 
 // walk entries worth its fill).
 template <bool F32>
 __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
-  if (a.sc->err || a.sc->done) return;
   using T = typename Prec<F32>::T;
+  // The stop flag (a launch enqueued ahead of the host's flag read skips its
+  // work once the run has stopped) and the FP32 scale are read first and used
+  // late, so their loads overlap the first descriptor loads.
+  const bool stop = a.sc->err || a.sc->done;
+  const Epi<F32> ep = compute_epi<F32>(a);
   extern __shared__ __align__(16) unsigned char walk_lds[];
   T* hub = reinterpret_cast<T*>(walk_lds);
-  {
+  if (a.hub_n > 0) {
     const T* x = reinterpret_cast<const T*>(a.x_in);
-    for (int i = threadIdx.x; i < a.hub_n; i += kWG) hub[i] = x[i];
+    if (!stop)
+      for (int i = threadIdx.x; i < a.hub_n; i += kWG) hub[i] = x[i];
     __syncthreads();
   }
-  const Epi<F32> ep = compute_epi<F32>(a);
   if constexpr (F32) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !stop) {
       a.sigma[a.r] = ep.sigma_r;
       a.sigma_sum[a.r] = a.sigma_sum[a.r - 1] + ep.sigma_r;
     }
@@ -332,25 +356,29 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
         // One 4096-arc segment of a long row: its partial sum only; huge_combine
         // adds the partials of each row in segment order after this launch.
         const SegDesc sd = a.segs[lb];
+        if (stop) break;
         const T tot = block_sum<F32>(a, hub, a.col + sd.off, sd.len);
         if (threadIdx.x == 0) reinterpret_cast<T*>(a.partial)[sd.part] = tot;
         break;
       }
       case BIN_B256: {
         const RowDesc d = a.desc[a.bin_base[BIN_B256] + lb];
+        Prev pv{0.0, 0.0f};
+        if (threadIdx.x == 0) pv = load_prev<F32>(a, d.row);
+        if (stop) break;
         const T tot = block_sum<F32>(a, hub, a.col + d.off, d.len);
-        if (threadIdx.x == 0) epilogue<F32>(a, ep, d.row, tot, vmax);
+        if (threadIdx.x == 0) epilogue<F32>(a, ep, d.row, tot, vmax, pv);
         break;
       }
-      case BIN_W64: rows_group<F32, 64>(a, hub, ep, lb, BIN_W64, vmax); break;
-      case BIN_G32: rows_group<F32, 32>(a, hub, ep, lb, BIN_G32, vmax); break;
-      case BIN_G16: rows_group<F32, 16>(a, hub, ep, lb, BIN_G16, vmax); break;
-      case BIN_G8: rows_group<F32, 8>(a, hub, ep, lb, BIN_G8, vmax); break;
-      case BIN_G4: rows_group<F32, 4>(a, hub, ep, lb, BIN_G4, vmax); break;
+      case BIN_W64: rows_group<F32, 64>(a, hub, ep, lb, BIN_W64, vmax, stop); break;
+      case BIN_G32: rows_group<F32, 32>(a, hub, ep, lb, BIN_G32, vmax, stop); break;
+      case BIN_G16: rows_group<F32, 16>(a, hub, ep, lb, BIN_G16, vmax, stop); break;
+      case BIN_G8: rows_group<F32, 8>(a, hub, ep, lb, BIN_G8, vmax, stop); break;
+      case BIN_G4: rows_group<F32, 4>(a, hub, ep, lb, BIN_G4, vmax, stop); break;
       case BIN_EMPTY: {
         // Only at r = 2: the buffer of x_2 was never written for empty rows.
         const long long i = lb * kWG + threadIdx.x;
-        if (i < a.bin_count[BIN_EMPTY]) {
+        if (!stop && i < a.bin_count[BIN_EMPTY]) {
           const int row = a.desc[a.bin_base[BIN_EMPTY] + i].row;
           reinterpret_cast<T*>(a.x_out)[row] = (T)0;
         }
@@ -376,11 +404,13 @@ __global__ void __launch_bounds__(kWG) huge_combine(IterArgs a) {
   if (i < a.bin_count[BIN_HUGE]) {
     const HugeRow h = a.huge[i];
     const int lane = lane_id();
+    Prev pv{0.0, 0.0f};
+    if (lane == 0) pv = load_prev<F32>(a, h.row);
     const T* part = reinterpret_cast<const T*>(a.partial);
     T sum = 0;
     for (int s2 = lane; s2 < h.nseg; s2 += kWave) sum += part[h.part0 + s2];
     for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
-    if (lane == 0) epilogue<F32>(a, ep, h.row, sum, vmax);
+    if (lane == 0) epilogue<F32>(a, ep, h.row, sum, vmax, pv);
   }
   store_block_max<F32>(a, vmax, a.blk_base + blockIdx.x);
 }
@@ -649,9 +679,16 @@ __global__ void __launch_bounds__(kFinishThreads) sel_check(SelArgs a) {
   __shared__ int sext[kMaxK];
   __shared__ int s_fail;
   const int k = a.k;
+  // The sorted top-k is needed for the pair test (only when no node outside
+  // the top-k survived) and as the output when the run stops here for another
+  // reason; otherwise the iteration goes on and the sort is skipped.
+  const bool walk_zero = a.b.fp32 ? (a.xmax32[a.b.r] == 0u) : (a.xmax64[a.b.r] == 0ull);
+  const bool need_sort = a.sc->kept_count == 0 || walk_zero || (a.b.fp32 && !a.sc->progress) ||
+                         a.b.r >= a.max_iter;
   int P = 1;
   while (P < k) P <<= 1;
-  if (threadIdx.x == 0) s_fail = 0;
+  if (!need_sort) P = 0;
+  if (threadIdx.x == 0) s_fail = need_sort ? 0 : 1;
   for (int i = threadIdx.x; i < P; i += kFinishThreads) {
     if (i < k) {
       const int v = a.act_out[i];
@@ -686,7 +723,7 @@ __global__ void __launch_bounds__(kFinishThreads) sel_check(SelArgs a) {
     }
   }
   const double eps = a.b.eps;
-  for (int i = threadIdx.x; i < k; i += kFinishThreads) {
+  for (int i = threadIdx.x; i < (need_sort ? k : 0); i += kFinishThreads) {
     const int v = int_id(a, sext[i]);
     double lo, up;
     bound_eval(a.b, v, lo, up);
@@ -700,7 +737,6 @@ __global__ void __launch_bounds__(kFinishThreads) sel_check(SelArgs a) {
     RunScalars* sc = a.sc;
     const int kept = sc->kept_count;
     const bool certified = kept == 0 && !s_fail;
-    const bool walk_zero = a.b.fp32 ? (a.xmax32[a.b.r] == 0u) : (a.xmax64[a.b.r] == 0ull);
     int status = -1;
     if (certified) status = KATZ_OK;
     else if (walk_zero) status = KATZ_W_EXACT_TIES;

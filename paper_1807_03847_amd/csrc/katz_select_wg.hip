@@ -194,9 +194,15 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
     if (t == 0) sc->err = 2;
     return;
   }
-  // Sort the top-k by (lower desc, id asc) and test adjacent pairs.
+  // Sort the top-k by (lower desc, id asc) and test adjacent pairs: needed when
+  // no node outside the top-k survived, or as the output when the run stops
+  // here for another reason.
+  const bool walk_zero = b.fp32 ? (gs.xmax32[b.r] == 0u) : (gs.xmax64[b.r] == 0ull);
+  const bool need_sort = s_kept == 0 || walk_zero || (b.fp32 && !s_prog) || b.r >= gs.max_iter;
   int P = 1;
   while (P < k) P <<= 1;
+  if (!need_sort) P = 0;
+  if (t == 0 && !need_sort) s_fail = 1;
   for (int i = t; i < P; i += kFinishThreads) {
     if (i < k) {
       const int v = act_out[i];
@@ -229,7 +235,7 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
       __syncthreads();
     }
   }
-  for (int i = t; i < k; i += kFinishThreads) {
+  for (int i = t; i < (need_sort ? k : 0); i += kFinishThreads) {
     const int v = gs_int(gs, sm.srt.ext[i]);
     double lo, up;
     bound_eval(b, v, lo, up);
@@ -242,7 +248,6 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
   if (t == 0) {
     const int kept = s_kept;
     const bool certified = kept == 0 && !s_fail;
-    const bool walk_zero = b.fp32 ? (gs.xmax32[b.r] == 0u) : (gs.xmax64[b.r] == 0ull);
     int status = -1;
     if (certified) status = KATZ_OK;
     else if (walk_zero) status = KATZ_W_EXACT_TIES;
