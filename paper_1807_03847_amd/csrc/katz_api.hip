@@ -893,7 +893,12 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
   KATZ_HIP(launch_prep_count(stg.row_ptr, g->row_ptr_64, g->n, g->nnz, b.blk, b.nblocks, w.sc, s));
   KATZ_HIP(launch_prep_scan(b.blk, b.nblocks, b.scan_sums, b.scan_totals, w.sc, s));
   KATZ_HIP(launch_prep_scatter(stg.row_ptr, g->row_ptr_64, g->n, b.blk, b.nblocks, b.desc, b.segs, b.huge, w.sc, s));
-  if (pl.validate >= KATZ_VALIDATE_BASIC) KATZ_HIP(launch_check_col_range(stg.col, g->nnz, g->n, w.sc, s));
+  // Column ids are range-checked before any gather uses them: here, or, when
+  // the graph is renumbered with basic validation, inside the renumbering
+  // (which reads every column id anyway and never indexes with a bad one).
+  const bool check_in_remap = pl.reorder && pl.validate == KATZ_VALIDATE_BASIC;
+  if (pl.validate >= KATZ_VALIDATE_BASIC && !check_in_remap)
+    KATZ_HIP(launch_check_col_range(stg.col, g->nnz, g->n, w.sc, s));
   KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
   KATZ_HIP(hipStreamSynchronize(s));
   if (hs.sc->err) return KATZ_E_CSR;
@@ -906,14 +911,14 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
   }
   if (pl.reorder) {
     // Renumber by the binned order and rebuild the bins on the renumbered rows
-    // (now contiguous per bin).  Column ids were range-checked above.
-    KATZ_HIP(launch_relabel(b.desc, g->n, b.bin_base, b.bin_count, stg.col, stg.ext_of, stg.int_of, stg.len_ll, stg.len32, stg.noff,
-                            stg.sums, stg.total, stg.ncol, s));
+    // (now contiguous per bin).
+    KATZ_HIP(launch_relabel(b.desc, g->n, b.bin_base, b.bin_count, b.segs, b.seg_total, stg.col, stg.ext_of,
+                            stg.int_of, stg.len_ll, stg.len32, stg.noff, stg.sums, stg.total, stg.ncol, w.sc, s));
     KATZ_HIP(launch_prep_rows(nullptr, g->n, stg.noff, stg.len32, b.blk, b.nblocks, b.scan_sums, b.scan_totals,
                               b.desc, b.segs, b.huge, w.sc, s));
     KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
     KATZ_HIP(hipStreamSynchronize(s));
-    if (hs.sc->err) return KATZ_E_HIP;
+    if (hs.sc->err) return hs.sc->err == 1 ? KATZ_E_CSR : KATZ_E_HIP;
     b.read_back(*hs.sc, g->n);
   }
   return KATZ_OK;

@@ -294,8 +294,9 @@ hipError_t launch_max_of_vector(const double* x, long long n, unsigned long long
 
 hipError_t launch_reset_flags(RunScalars* sc, hipStream_t s);
 hipError_t launch_relabel(const RowDesc* desc, long long n, const long long* bin_base, const long long* bin_count,
-                          const int32_t* col, int32_t* ext_of, int32_t* int_of, long long* len_ll, int* len32,
-                          long long* noff, long long* sums, long long* total, int32_t* ncol, hipStream_t s);
+                          const SegDesc* segs, long long seg_total, const int32_t* col, int32_t* ext_of,
+                          int32_t* int_of, long long* len_ll, int* len32, long long* noff, long long* sums,
+                          long long* total, int32_t* ncol, RunScalars* sc, hipStream_t s);
 hipError_t launch_gather_int(const int32_t* rows, long long t, const int* src, int* out, hipStream_t s);
 hipError_t launch_gather_ll(const int32_t* rows, long long t, const long long* src, long long* out, hipStream_t s);
 hipError_t launch_min_lower_active(const BoundArgs& b, const int32_t* act, const int* m_ptr,

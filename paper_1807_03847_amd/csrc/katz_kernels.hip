@@ -840,43 +840,75 @@ __global__ void __launch_bounds__(kWG) relabel_ids(const RowDesc* desc, long lon
   len32[i] = d.len;
 }
 
-// G lanes per new row (the row's bin decides G): its arcs in their original
-// order, targets renamed.  Rows of one bin are new ids first .. first+count-1.
+// Column ids of one stretch of a row, renamed: arcs in their original order,
+// 0 <= col < n checked on the way (an id out of range sets sc->err = 1 and is
+// never used as an index).
 template <int G>
-__global__ void __launch_bounds__(kWG) remap_rows(const RowDesc* desc, long long first, long long count,
-                                                  const int32_t* col, const int32_t* int_of, const long long* noff,
-                                                  int32_t* ncol) {
-  constexpr int RPB = kWG / G;
-  const long long i = first + (long long)blockIdx.x * RPB + threadIdx.x / G;
-  if (i >= first + count) return;
-  const int lane = threadIdx.x & (G - 1);
-  const RowDesc d = desc[i];
-  const long long dst = noff[i];
-  for (long long j0 = lane; j0 < d.len; j0 += (long long)kBatch * G) {
+__device__ __forceinline__ bool remap_stretch(const int32_t* cp, int len, int lane, long long n,
+                                              const int32_t* int_of, int32_t* out) {
+  bool bad = false;
+  for (int j0 = lane; j0 < len; j0 += kBatch * G) {
     int32_t c[kBatch];
+    bool in[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      const long long j = j0 + (long long)u * G;
-      c[u] = j < d.len ? col[d.off + j] : -1;
+      const int j = j0 + u * G;
+      in[u] = j < len;
+      c[u] = in[u] ? cp[j] : 0;
+      if (in[u] && (unsigned long long)(unsigned)c[u] >= (unsigned long long)n) {
+        bad = true;
+        in[u] = false;
+      }
     }
     int32_t m[kBatch];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) m[u] = c[u] >= 0 ? int_of[c[u]] : 0;
+    for (int u = 0; u < kBatch; ++u) m[u] = in[u] ? int_of[c[u]] : 0;
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      const long long j = j0 + (long long)u * G;
-      if (j < d.len) ncol[dst + j] = m[u];
+      const int j = j0 + u * G;
+      if (j < len) out[j] = m[u];
     }
   }
+  return bad;
+}
+
+// G lanes per new row (the row's bin decides G).  Rows of one bin are new ids
+// first .. first+count-1.
+template <int G>
+__global__ void __launch_bounds__(kWG) remap_rows(const RowDesc* desc, long long first, long long count,
+                                                  const int32_t* col, const int32_t* int_of, const long long* noff,
+                                                  int32_t* ncol, long long n, RunScalars* sc) {
+  constexpr int RPB = kWG / G;
+  const long long i = first + (long long)blockIdx.x * RPB + threadIdx.x / G;
+  bool bad = false;
+  if (i < first + count) {
+    const RowDesc d = desc[i];
+    bad = remap_stretch<G>(col + d.off, d.len, threadIdx.x & (G - 1), n, int_of, ncol + noff[i]);
+  }
+  if (__ballot(bad) && lane_id() == 0) atomicOr(&sc->err, 1);
+}
+
+// Rows longer than one segment: one workgroup per 4096-arc segment (the
+// segments of the first binning), so the longest rows do not serialise.
+__global__ void __launch_bounds__(kWG) remap_segments(const RowDesc* desc, long long huge_base, const SegDesc* segs,
+                                                      const int32_t* col, const int32_t* int_of,
+                                                      const long long* noff, int32_t* ncol, long long n,
+                                                      RunScalars* sc) {
+  const SegDesc sd = segs[blockIdx.x];
+  const long long i = huge_base + sd.hrow;           // new id of the segment's row
+  const long long dst = noff[i] + (sd.off - desc[i].off);
+  const bool bad = remap_stretch<kWG>(col + sd.off, sd.len, threadIdx.x, n, int_of, ncol + dst);
+  if (__ballot(bad) && lane_id() == 0) atomicOr(&sc->err, 1);
 }
 
 template <int G>
 void launch_remap_bin(const RowDesc* desc, long long first, long long count, const int32_t* col,
-                      const int32_t* int_of, const long long* noff, int32_t* ncol, hipStream_t s) {
+                      const int32_t* int_of, const long long* noff, int32_t* ncol, long long n, RunScalars* sc,
+                      hipStream_t s) {
   if (count <= 0) return;
   constexpr int RPB = kWG / G;
   const unsigned nb = (unsigned)((count + RPB - 1) / RPB);
-  hipLaunchKernelGGL(remap_rows<G>, dim3(nb), dim3(kWG), 0, s, desc, first, count, col, int_of, noff, ncol);
+  hipLaunchKernelGGL(remap_rows<G>, dim3(nb), dim3(kWG), 0, s, desc, first, count, col, int_of, noff, ncol, n, sc);
 }
 
 __global__ void reset_flags(RunScalars* sc) {
@@ -893,21 +925,27 @@ __global__ void reset_flags(RunScalars* sc) {
 
 }  // namespace
 
+// Renumbering: new id i = position of row i in the binned order; renamed
+// columns in ncol (column ids are range-checked here, sc->err = 1 if not).
 hipError_t launch_relabel(const RowDesc* desc, long long n, const long long* bin_base, const long long* bin_count,
-                          const int32_t* col, int32_t* ext_of, int32_t* int_of, long long* len_ll, int* len32,
-                          long long* noff, long long* sums, long long* total, int32_t* ncol, hipStream_t s) {
+                          const SegDesc* segs, long long seg_total, const int32_t* col, int32_t* ext_of,
+                          int32_t* int_of, long long* len_ll, int* len32, long long* noff, long long* sums,
+                          long long* total, int32_t* ncol, RunScalars* sc, hipStream_t s) {
   const unsigned nb = (unsigned)std::max<long long>(1, (n + kWG - 1) / kWG);
   hipLaunchKernelGGL(relabel_ids, dim3(nb), dim3(kWG), 0, s, desc, n, ext_of, int_of, len_ll, len32);
   const hipError_t e = launch_scan_ll(len_ll, n, noff, sums, total, s);
   if (e != hipSuccess) return e;
   const int32_t* io = int_of;
-  launch_remap_bin<kWG>(desc, bin_base[BIN_HUGE], bin_count[BIN_HUGE], col, io, noff, ncol, s);
-  launch_remap_bin<kWG>(desc, bin_base[BIN_B256], bin_count[BIN_B256], col, io, noff, ncol, s);
-  launch_remap_bin<64>(desc, bin_base[BIN_W64], bin_count[BIN_W64], col, io, noff, ncol, s);
-  launch_remap_bin<32>(desc, bin_base[BIN_G32], bin_count[BIN_G32], col, io, noff, ncol, s);
-  launch_remap_bin<16>(desc, bin_base[BIN_G16], bin_count[BIN_G16], col, io, noff, ncol, s);
-  launch_remap_bin<8>(desc, bin_base[BIN_G8], bin_count[BIN_G8], col, io, noff, ncol, s);
-  launch_remap_bin<4>(desc, bin_base[BIN_G4], bin_count[BIN_G4], col, io, noff, ncol, s);
+  const long long* no = noff;
+  if (seg_total > 0)
+    hipLaunchKernelGGL(remap_segments, dim3((unsigned)seg_total), dim3(kWG), 0, s, desc, bin_base[BIN_HUGE], segs, col,
+                       io, no, ncol, n, sc);
+  launch_remap_bin<kWG>(desc, bin_base[BIN_B256], bin_count[BIN_B256], col, io, no, ncol, n, sc, s);
+  launch_remap_bin<64>(desc, bin_base[BIN_W64], bin_count[BIN_W64], col, io, no, ncol, n, sc, s);
+  launch_remap_bin<32>(desc, bin_base[BIN_G32], bin_count[BIN_G32], col, io, no, ncol, n, sc, s);
+  launch_remap_bin<16>(desc, bin_base[BIN_G16], bin_count[BIN_G16], col, io, no, ncol, n, sc, s);
+  launch_remap_bin<8>(desc, bin_base[BIN_G8], bin_count[BIN_G8], col, io, no, ncol, n, sc, s);
+  launch_remap_bin<4>(desc, bin_base[BIN_G4], bin_count[BIN_G4], col, io, no, ncol, n, sc, s);
   return hipGetLastError();
 }
 

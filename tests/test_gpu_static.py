@@ -230,10 +230,18 @@ def test_errors():
     katz = K()
     rp, col = sg.cycle_graph(10)
     say("errors")
-    bad_col = col.copy()
-    bad_col[3] = 10
+    for bad, flags, prec in [(10, 0, "fp64"), (-5, 0, "fp32"), (10, katz.FLAG_NO_REORDER, "fp64"),
+                             (-1, katz.FLAG_NO_REORDER, "fp32")]:
+        bad_col = col.copy()
+        bad_col[3] = bad                            # column id out of range (checked before any gather)
+        with pytest.raises(katz.KatzError) as e:
+            katz.rank_static(*dev(rp, bad_col), 2, flags=flags, precision=prec)
+        assert e.value.code == katz.E_CSR
+    big = sg.star_graph(9000)                       # a row longer than one segment
+    bcol = big[1].copy()
+    bcol[5000] = 9001 + 7
     with pytest.raises(katz.KatzError) as e:
-        katz.rank_static(*dev(rp, bad_col), 2)
+        katz.rank_static(*dev(big[0], bcol), 2)
     assert e.value.code == katz.E_CSR
     bad_rp = rp.copy()
     bad_rp[4], bad_rp[5] = bad_rp[5], bad_rp[4]
