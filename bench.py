@@ -283,6 +283,8 @@ def bench_batched(args, katz, sg, torch, np):
     for (rp, col), (n, m, seed, f, k) in zip(csrs, specs):
         params.append(dict(k=min(k, n), alpha=f / (1 + int(np.max(np.diff(rp)))), eps=1e-6 * f, precision="fp32"))
     torch.cuda.synchronize()
+    tuning = katz.autotune_batch(graphs, params)
+    print(f"[bench] batched tuning {tuning}", flush=True)
     for _ in range(args.warmup):
         res = katz.rank_static_batch(graphs, params)
     torch.cuda.synchronize()
@@ -301,6 +303,7 @@ def bench_batched(args, katz, sg, torch, np):
                    "iterations_max": max(r.iterations for r in res),
                    "iterations_min": min(r.iterations for r in res)},
         "status_counts": {str(st): sum(1 for r in res if r.status == st) for st in sorted({r.status for r in res})},
+        "tuning": tuning,
     }
     print(json.dumps(out), flush=True)
 

@@ -247,38 +247,41 @@ void katz_timing_enable(int on);
 /* Copies the counters; E_INVALID_ARG if out is NULL. */
 int katz_timing_read(katz_timing* out);
 
-/* ---- launch tuning of the walk kernel --------------------------------------
- * Process-wide launch shape of the walk step of single-graph static calls
- * with the internal renumbering (the degree-binned SpMV of Eq.
+/* ---- launch tuning of the walk kernels ------------------------------------
+ * Process-wide launch shape of the walk step (the degree-binned SpMV of Eq.
  * (basic_recurrence), Section 3.2).  No setting changes any result bit: every
  * row is still summed by the same lane schedule, and the LDS copy holds exact
  * walk entries.
- *   hub_bytes      bytes of LDS per workgroup that hold a copy of the first
- *                  walk entries (after the renumbering, the nodes with the
- *                  longest rows, which most arcs point to); 0 = no copy.
- *                  0 .. 65536, a multiple of 16.
- *   blocks_per_cu  persistent walk grid of this many workgroups per compute
- *                  unit, each taking work items with a grid stride; 0 = one
- *                  workgroup per work item.  0 .. 32.  A non-zero hub_bytes
- *                  needs a non-zero blocks_per_cu (the copy is filled once per
- *                  workgroup).
- * Defaults: hub_bytes = 0, blocks_per_cu = 0.  Calls already running keep the
- * setting they started with. */
+ *   hub_bytes            single-graph static calls with the internal
+ *                        renumbering: bytes of LDS per workgroup that hold a
+ *                        copy of the first walk entries (after the renumbering,
+ *                        the nodes with the longest rows, which most arcs point
+ *                        to); 0 = no copy.  0 .. 65536, a multiple of 16.
+ *   blocks_per_cu        single-graph calls: persistent walk grid of this many
+ *                        workgroups per compute unit, each taking work items
+ *                        with a grid stride; 0 = one workgroup per work item.
+ *                        0 .. 32.  A non-zero hub_bytes needs a non-zero
+ *                        blocks_per_cu (the copy is filled once per workgroup).
+ *   batch_blocks_per_cu  the same for the batched form (count > 1); 0 .. 32.
+ * Defaults: all 0.  Calls already running keep the setting they started with. */
 typedef struct katz_tuning {
   int32_t hub_bytes;
   int32_t blocks_per_cu;
-  int32_t reserved[6];       /* must be 0 */
+  int32_t batch_blocks_per_cu;
+  int32_t reserved[5];       /* must be 0 */
 } katz_tuning;
 
 /* Copies the current setting; E_INVALID_ARG if t is NULL. */
 int katz_tuning_get(katz_tuning* t);
 /* Replaces the setting; E_INVALID_ARG (and no change) for values out of range. */
 int katz_tuning_set(const katz_tuning* t);
-/* Autotuner: times katz_rank_static on (g, p) under each candidate setting on
- * `stream` (two calls each, the second timed), installs the fastest and copies
- * it to *best (may be NULL).  Inputs as for katz_rank_static (count = 1);
- * returns the first error of a ranking call, or KATZ_OK. */
-int katz_autotune(const katz_csr* g, const katz_params* p, katz_tuning* best, void* stream);
+/* Autotuner: times katz_rank_static(count, g, p) on `stream` under each
+ * candidate launch shape (two calls each, the second timed), installs the
+ * fastest and copies it to *best (may be NULL).  count = 1 tunes hub_bytes and
+ * blocks_per_cu, count > 1 tunes batch_blocks_per_cu; the other fields keep
+ * their values.  Inputs as for katz_rank_static; returns the first error of a
+ * ranking call (the setting is then left unchanged), or KATZ_OK. */
+int katz_autotune(int32_t count, const katz_csr* g, const katz_params* p, katz_tuning* best, void* stream);
 
 #ifdef __cplusplus
 }

@@ -172,8 +172,9 @@ katz_tuning current_tuning() {
 int tuning_valid(const katz_tuning& t) {
   if (t.hub_bytes < 0 || t.hub_bytes > 65536 || (t.hub_bytes & 15)) return KATZ_E_INVALID_ARG;
   if (t.blocks_per_cu < 0 || t.blocks_per_cu > 32) return KATZ_E_INVALID_ARG;
+  if (t.batch_blocks_per_cu < 0 || t.batch_blocks_per_cu > 32) return KATZ_E_INVALID_ARG;
   if (t.hub_bytes > 0 && t.blocks_per_cu == 0) return KATZ_E_INVALID_ARG;
-  for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < 5; ++i)
     if (t.reserved[i] != 0) return KATZ_E_INVALID_ARG;
   return KATZ_OK;
 }
@@ -1347,6 +1348,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   bw.direct_max = count > kBatchMaxLdsGraphs ? 1 : 0;
   bw.fp32 = fp32;
   const long long total_blocks = bw.first_block[NUM_BINS];
+  const long long walk_grid = (long long)current_tuning().batch_blocks_per_cu * cu_count(dev);
   {
     const long long nh = b.bin_count[BIN_HUGE];
     if (total_blocks + (nh + kWG / kWave - 1) / (kWG / kWave) > blk_cap) return KATZ_E_HIP;   // sizing bound broken
@@ -1367,7 +1369,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   KATZ_HIP(hipStreamSynchronize(s));
   KATZ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   for (int it = 0; it < kItersPerGraph; ++it) {
-    KATZ_HIP(launch_walk_batch(bw, total_blocks, b.bin_count[BIN_HUGE], cs));
+    KATZ_HIP(launch_walk_batch(bw, total_blocks, walk_grid, b.bin_count[BIN_HUGE], cs));
     KATZ_HIP(launch_select_wg(gsel, count, r_dev, cs));
     KATZ_HIP(launch_batch_advance(r_dev, count, gsc, gxmax32, gsigma, gsigsum, gexp, galpha, gclog2, stride, fp32,
                                   ndone, cs));
@@ -2043,43 +2045,66 @@ KATZ_EXPORT int katz_tuning_set(const katz_tuning* t) {
   return KATZ_OK;
 }
 
-// Candidate launch shapes, timed on the caller's graph; the fastest is kept.
-KATZ_EXPORT int katz_autotune(const katz_csr* g, const katz_params* p, katz_tuning* best, void* stream) {
-  if (!g || !p) return KATZ_E_INVALID_ARG;
-  KATZ_TRY(katz::check_graph(g));
-  KATZ_TRY(katz::check_params(p, g->n, true));
-  static const int kCand[][2] = {{0, 0}, {0, 4}, {0, 8}, {16384, 4}, {16384, 8}, {32768, 4}, {65536, 2}};
+// Candidate launch shapes, timed on the caller's graph(s); the fastest is kept.
+KATZ_EXPORT int katz_autotune(int32_t count, const katz_csr* g, const katz_params* p, katz_tuning* best,
+                              void* stream) {
+  if (count < 1 || !g || !p) return KATZ_E_INVALID_ARG;
+  long long sum_k = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    KATZ_TRY(katz::check_graph(&g[i]));
+    KATZ_TRY(katz::check_params(&p[i], g[i].n, true));
+    sum_k += p[i].k;
+  }
+  static const int kSingle[][2] = {{0, 0}, {0, 4}, {0, 8}, {0, 16}, {16384, 4}, {32768, 4}, {65536, 2}};
+  static const int kBatch[] = {0, 2, 4, 8, 16};
   const katz_tuning saved = katz::current_tuning();
   int32_t* ids = nullptr;
   double *lo = nullptr, *up = nullptr;
-  if (hipMalloc((void**)&ids, sizeof(int32_t) * p->k) != hipSuccess ||
-      hipMalloc((void**)&lo, sizeof(double) * p->k) != hipSuccess ||
-      hipMalloc((void**)&up, sizeof(double) * p->k) != hipSuccess) {
+  if (hipMalloc((void**)&ids, sizeof(int32_t) * sum_k) != hipSuccess ||
+      hipMalloc((void**)&lo, sizeof(double) * sum_k) != hipSuccess ||
+      hipMalloc((void**)&up, sizeof(double) * sum_k) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipFree(ids);
     (void)hipFree(lo);
     (void)hipFree(up);
     return KATZ_E_OOM;
   }
+  std::vector<katz_tuning> cand;
+  if (count == 1) {
+    for (const auto& c : kSingle) {
+      katz_tuning t = saved;
+      t.hub_bytes = c[0];
+      t.blocks_per_cu = c[1];
+      cand.push_back(t);
+    }
+  } else {
+    for (int b : kBatch) {
+      katz_tuning t = saved;
+      t.batch_blocks_per_cu = b;
+      cand.push_back(t);
+    }
+  }
+  std::vector<katz_result> out(count);
+  long long koff = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    out[i] = katz_result{};
+    out[i].topk_ids = ids + koff;
+    out[i].lower = lo + koff;
+    out[i].upper = up + koff;
+    koff += p[i].k;
+  }
   katz_tuning pick = saved;
   double pick_ms = 1e300;
   int rc = KATZ_OK;
-  for (const auto& c : kCand) {
-    katz_tuning t{};
-    t.hub_bytes = c[0];
-    t.blocks_per_cu = c[1];
+  for (const katz_tuning& t : cand) {
     {
       std::lock_guard<std::mutex> lk(katz::g_tuning.mu);
       katz::g_tuning.t = t;
     }
     double ms = 0.0;
     for (int rep = 0; rep < 2 && rc >= 0; ++rep) {
-      katz_result out{};
-      out.topk_ids = ids;
-      out.lower = lo;
-      out.upper = up;
       const auto t0 = std::chrono::steady_clock::now();
-      rc = katz_rank_static(1, g, p, &out, nullptr, stream);
+      rc = katz_rank_static(count, g, p, out.data(), nullptr, stream);
       ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     if (rc < 0) break;

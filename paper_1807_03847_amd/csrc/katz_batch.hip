@@ -318,13 +318,16 @@ __global__ void __launch_bounds__(kWG) walk_batch(BatchWalk a) {
   using T = typename Prec<F32>::T;
   const int r = *a.r_dev;
   if (r >= a.stride) return;
+  const T* xin = reinterpret_cast<const T*>(a.xbuf[(r + 1) & 1]);
+  const long long total = a.first_block[NUM_BINS];
+  // Work item b (one bin block) writes workgroup slot b; the grid may be
+  // smaller than the work (persistent workgroups take items with a grid stride).
+  for (long long b = blockIdx.x; b < total; b += gridDim.x) {
   double vmax = 0.0;
   int g_mine = -1;
-  const long long b = blockIdx.x;
   int bin = 0;
   while (bin < NUM_BINS && b >= a.first_block[bin + 1]) ++bin;
   const long long lb = b - a.first_block[bin];
-  const T* xin = reinterpret_cast<const T*>(a.xbuf[(r + 1) & 1]);
   switch (bin) {
     case BIN_HUGE: {
       // One segment of a long row: its partial sum only (batch_huge_combine
@@ -373,7 +376,8 @@ __global__ void __launch_bounds__(kWG) walk_batch(BatchWalk a) {
     }
     default: break;
   }
-  batch_store_max<F32>(a, r, g_mine, vmax, blockIdx.x);
+  batch_store_max<F32>(a, r, g_mine, vmax, b);
+  }
 }
 
 // Rows longer than one segment: one wave per row of a live graph adds the
@@ -534,19 +538,22 @@ hipError_t launch_fill_ones(void* x, long long n, int fp32, hipStream_t s) {
   return hipGetLastError();
 }
 
-// One walk step of the batch: walk_batch, batch_huge_combine for rows longer
-// than one segment, and batch_reduce_max for the per-graph maxima.
-hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, long long n_huge, hipStream_t s) {
-  const unsigned grid = (unsigned)std::max<long long>(1, total_blocks);
+// One walk step of the batch: walk_batch (on at most max_grid workgroups when
+// max_grid > 0), batch_huge_combine for rows longer than one segment, and
+// batch_reduce_max for the per-graph maxima.
+hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, long long max_grid, long long n_huge,
+                             hipStream_t s) {
+  const long long items = std::max<long long>(1, total_blocks);
+  const unsigned grid = (unsigned)(max_grid > 0 ? std::min(items, max_grid) : items);
   BatchWalk w = a;
   w.blk_base = 0;
   if (a.fp32) hipLaunchKernelGGL(walk_batch<true>, dim3(grid), dim3(kWG), 0, s, w);
   else hipLaunchKernelGGL(walk_batch<false>, dim3(grid), dim3(kWG), 0, s, w);
-  long long nb = grid;
+  long long nb = items;
   if (n_huge > 0) {
     const unsigned cg = (unsigned)((n_huge + kWG / kWave - 1) / (kWG / kWave));
     BatchWalk c = a;
-    c.blk_base = grid;
+    c.blk_base = items;
     if (a.fp32) hipLaunchKernelGGL(batch_huge_combine<true>, dim3(cg), dim3(kWG), 0, s, c, n_huge);
     else hipLaunchKernelGGL(batch_huge_combine<false>, dim3(cg), dim3(kWG), 0, s, c, n_huge);
     nb += cg;

@@ -315,7 +315,8 @@ hipError_t launch_batch_prep(const long long* gbase, const void* const* grp, con
                              SegDesc* segs, HugeRow* huge, RunScalars* sc, int validate, hipStream_t s);
 hipError_t launch_batch_dmax(const RowDesc* desc, long long count, const int* gid_of, int* gdmax, hipStream_t s);
 hipError_t launch_fill_ones(void* x, long long n, int fp32, hipStream_t s);
-hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, long long n_huge, hipStream_t s);
+hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, long long max_grid, long long n_huge,
+                             hipStream_t s);
 constexpr int kBatchMaxLdsGraphs = 8192;   // per-graph maxima reduced in LDS up to this many graphs
 hipError_t launch_batch_advance(int* r_dev, int count, RunScalars* gsc, const unsigned* gxmax32, double* gsigma,
                                 double* gsigsum, int* gexp, const double* galpha, const int* gclog2, int stride,

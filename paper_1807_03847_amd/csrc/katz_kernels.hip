@@ -330,6 +330,9 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
   // work once the run has stopped) and the FP32 scale are read first and used
   // late, so their loads overlap the first descriptor loads.
   const bool stop = a.sc->err || a.sc->done;
+  const long long total = a.first_block[NUM_BINS];
+  // A persistent grid visits many work items per workgroup: stop at once.
+  if (stop && (long long)gridDim.x < total) return;
   const Epi<F32> ep = compute_epi<F32>(a);
   extern __shared__ __align__(16) unsigned char walk_lds[];
   T* hub = reinterpret_cast<T*>(walk_lds);
@@ -346,7 +349,6 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
     }
   }
   double vmax = 0.0;
-  const long long total = a.first_block[NUM_BINS];
   for (long long b = blockIdx.x; b < total; b += gridDim.x) {
     int bin = 0;
     while (bin < NUM_BINS && b >= a.first_block[bin + 1]) ++bin;

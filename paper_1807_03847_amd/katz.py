@@ -56,7 +56,7 @@ class KatzResult(ctypes.Structure):
 
 class KatzTuning(ctypes.Structure):
     _fields_ = [("hub_bytes", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("batch_blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class KatzTiming(ctypes.Structure):
@@ -104,7 +104,8 @@ def _load():
     lib.katz_tuning_set.restype = ctypes.c_int
     lib.katz_tuning_set.argtypes = [ctypes.POINTER(KatzTuning)]
     lib.katz_autotune.restype = ctypes.c_int
-    lib.katz_autotune.argtypes = [ctypes.POINTER(KatzCSR), ctypes.POINTER(KatzParams), ctypes.POINTER(KatzTuning), vp]
+    lib.katz_autotune.argtypes = [i32, ctypes.POINTER(KatzCSR), ctypes.POINTER(KatzParams), ctypes.POINTER(KatzTuning),
+                                  vp]
     return lib
 
 
@@ -354,32 +355,50 @@ class Server:
             pass
 
 
+def _tuning_dict(t):
+    return {"hub_bytes": t.hub_bytes, "blocks_per_cu": t.blocks_per_cu, "batch_blocks_per_cu": t.batch_blocks_per_cu}
+
+
 def tuning_get() -> dict:
-    """katz_tuning_get: the walk kernel's launch shape."""
+    """katz_tuning_get: the walk kernels' launch shape."""
     t = KatzTuning()
     rc = lib.katz_tuning_get(ctypes.byref(t))
     if rc < 0:
         raise KatzError(rc)
-    return {"hub_bytes": t.hub_bytes, "blocks_per_cu": t.blocks_per_cu}
+    return _tuning_dict(t)
 
 
-def tuning_set(hub_bytes=0, blocks_per_cu=0) -> None:
+def tuning_set(hub_bytes=0, blocks_per_cu=0, batch_blocks_per_cu=0) -> None:
     """katz_tuning_set (no result depends on it)."""
-    t = KatzTuning(hub_bytes=int(hub_bytes), blocks_per_cu=int(blocks_per_cu))
+    t = KatzTuning(hub_bytes=int(hub_bytes), blocks_per_cu=int(blocks_per_cu),
+                   batch_blocks_per_cu=int(batch_blocks_per_cu))
     rc = lib.katz_tuning_set(ctypes.byref(t))
     if rc < 0:
         raise KatzError(rc)
 
 
 def autotune(row_ptr, col, k, *, alpha=0.0, eps=0.0, precision="fp32", undirected=True, stream=None) -> dict:
-    """katz_autotune: times the candidate launch shapes on this graph and keeps the fastest."""
+    """katz_autotune for one graph: times the candidate launch shapes and keeps the fastest."""
     g = make_csr(row_ptr, col, undirected)
     p = make_params(k, alpha, eps, precision)
     t = KatzTuning()
-    rc = lib.katz_autotune(ctypes.byref(g), ctypes.byref(p), ctypes.byref(t), _stream_handle(stream, row_ptr.device))
+    rc = lib.katz_autotune(1, ctypes.byref(g), ctypes.byref(p), ctypes.byref(t),
+                           _stream_handle(stream, row_ptr.device))
     if rc < 0:
         raise KatzError(rc)
-    return {"hub_bytes": t.hub_bytes, "blocks_per_cu": t.blocks_per_cu}
+    return _tuning_dict(t)
+
+
+def autotune_batch(graphs, params, *, stream=None) -> dict:
+    """katz_autotune for a batch (same arguments as ``rank_static_batch``)."""
+    count = len(graphs)
+    G = (KatzCSR * count)(*[make_csr(rp, c, u) for rp, c, u in graphs])
+    P = (KatzParams * count)(*[make_params(**pp) for pp in params])
+    t = KatzTuning()
+    rc = lib.katz_autotune(count, G, P, ctypes.byref(t), _stream_handle(stream, graphs[0][0].device))
+    if rc < 0:
+        raise KatzError(rc)
+    return _tuning_dict(t)
 
 
 def timing_enable(on: bool = True) -> None:

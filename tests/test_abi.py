@@ -44,7 +44,7 @@ int main(void) {
   F(katz_csr, col) F(katz_csr, row_ptr_64) F(katz_csr, undirected)
   F(katz_params, k) F(katz_params, precision) F(katz_params, validate) F(katz_params, flags) F(katz_params, degree_cap)
   F(katz_result, rest_upper_max) F(katz_result, active_final) F(katz_result, iterations) F(katz_result, status)
-  F(katz_tuning, blocks_per_cu) F(katz_tuning, reserved)
+  F(katz_tuning, blocks_per_cu) F(katz_tuning, batch_blocks_per_cu) F(katz_tuning, reserved)
   return 0;
 }
 '''
@@ -119,18 +119,21 @@ def test_tuning_round_trip_and_limits():
     katz = K()
     saved = katz.tuning_get()
     try:
-        katz.tuning_set(16384, 4)
-        assert katz.tuning_get() == {"hub_bytes": 16384, "blocks_per_cu": 4}
-        for hub, bpc in [(-16, 4), (65552, 4), (100, 4), (16384, 0), (0, 33), (0, -1)]:
+        katz.tuning_set(16384, 4, 8)
+        want = {"hub_bytes": 16384, "blocks_per_cu": 4, "batch_blocks_per_cu": 8}
+        assert katz.tuning_get() == want
+        for hub, bpc, bbpc in [(-16, 4, 0), (65552, 4, 0), (100, 4, 0), (16384, 0, 0), (0, 33, 0), (0, -1, 0),
+                               (0, 0, 33), (0, 0, -2)]:
             with pytest.raises(katz.KatzError) as e:
-                katz.tuning_set(hub, bpc)
+                katz.tuning_set(hub, bpc, bbpc)
             assert e.value.code == katz.E_INVALID_ARG
-            assert katz.tuning_get() == {"hub_bytes": 16384, "blocks_per_cu": 4}    # unchanged
+            assert katz.tuning_get() == want                                  # unchanged
         t = katz.KatzTuning(hub_bytes=0, blocks_per_cu=0)
         t.reserved[2] = 1
         assert katz.lib.katz_tuning_set(ctypes.byref(t)) == katz.E_INVALID_ARG
         assert katz.lib.katz_tuning_set(None) == katz.E_INVALID_ARG
         assert katz.lib.katz_tuning_get(None) == katz.E_INVALID_ARG
-        assert katz.lib.katz_autotune(None, None, None, None) == katz.E_INVALID_ARG
+        assert katz.lib.katz_autotune(1, None, None, None, None) == katz.E_INVALID_ARG
+        assert katz.lib.katz_autotune(0, None, None, None, None) == katz.E_INVALID_ARG
     finally:
         katz.tuning_set(**saved)

@@ -117,3 +117,32 @@ def test_batch_long_rows_match_single(precision):
         assert torch.equal(single.topk, rb.topk)
         assert torch.equal(single.lower, rb.lower) and torch.equal(single.upper, rb.upper)
         assert single.iterations == rb.iterations and single.status == rb.status
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_launch_tuning_is_invisible(precision):
+    """A persistent batched walk grid changes no result bit; the batch
+    autotuner installs one of its candidates."""
+    katz = K()
+    graphs, params = batch_workload(10, 5)
+    rp, col = sg.star_graph(5000)
+    graphs.append((rp, col))
+    params.append(dict(k=20, alpha=0.5 / (1 + sg.max_degree(rp)), eps=1e-7))
+    saved = katz.tuning_get()
+    try:
+        katz.tuning_set(**dict(saved, batch_blocks_per_cu=0))
+        ref = run_batch(graphs, params, precision)
+        for bbpc in (1, 4, 32):
+            say("batch tuning", precision, bbpc)
+            katz.tuning_set(**dict(saved, batch_blocks_per_cu=bbpc))
+            res = run_batch(graphs, params, precision)
+            for a, b in zip(res, ref):
+                assert torch.equal(a.topk, b.topk) and torch.equal(a.lower, b.lower) and torch.equal(a.upper, b.upper)
+                assert (a.iterations, a.status) == (b.iterations, b.status)
+        gl = [(torch.from_numpy(np.asarray(r, dtype=np.int64)).cuda(), torch.from_numpy(c).cuda(), True)
+              for r, c in graphs]
+        best = katz.autotune_batch(gl, [dict(pp, precision=precision) for pp in params])
+        assert best["batch_blocks_per_cu"] in (0, 2, 4, 8, 16)
+        assert katz.tuning_get() == best
+    finally:
+        katz.tuning_set(**saved)
