@@ -1105,6 +1105,9 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   GraphSel* gsel = nullptr;
   int* blk_g = nullptr;
   double* blk_m = nullptr;
+  int* item_g = nullptr;
+  int* items = nullptr;
+  int* n_items = nullptr;
   long long blk_cap = 0;
   int* r_dev = nullptr;
   int* ndone = nullptr;
@@ -1141,6 +1144,9 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     blk_cap = total_n / 4 + total_nnz / 1025 + 2 * b.seg_cap + 64;
     blk_g = ar.take<int>(blk_cap);
     blk_m = ar.take<double>(blk_cap);
+    item_g = ar.take<int>(blk_cap);
+    items = ar.take<int>(blk_cap);
+    n_items = ar.take<int>(1);
     r_dev = ar.take<int>(1);
     ndone = ar.take<int>(1);
     o_ids = ar.take<int32_t*>(count);
@@ -1346,6 +1352,9 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   bw.blk_m = blk_m;
   bw.count = count;
   bw.direct_max = count > kBatchMaxLdsGraphs ? 1 : 0;
+  bw.item_g = item_g;
+  bw.items = items;
+  bw.n_items = n_items;
   bw.fp32 = fp32;
   const long long total_blocks = bw.first_block[NUM_BINS];
   const long long walk_grid = (long long)current_tuning().batch_blocks_per_cu * cu_count(dev);
@@ -1366,13 +1375,16 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
       (void)hipStreamDestroy(s);
     }
   } guard{cs};
+  KATZ_HIP(launch_batch_item_graphs(bw, total_blocks, item_g, s));
+  KATZ_HIP(hipMemsetAsync(n_items, 0, sizeof(int), s));
   KATZ_HIP(hipStreamSynchronize(s));
   KATZ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   for (int it = 0; it < kItersPerGraph; ++it) {
+    KATZ_HIP(launch_batch_live_items(bw, total_blocks, items, n_items, cs));
     KATZ_HIP(launch_walk_batch(bw, total_blocks, walk_grid, b.bin_count[BIN_HUGE], cs));
     KATZ_HIP(launch_select_wg(gsel, count, r_dev, cs));
     KATZ_HIP(launch_batch_advance(r_dev, count, gsc, gxmax32, gsigma, gsigsum, gexp, galpha, gclog2, stride, fp32,
-                                  ndone, cs));
+                                  ndone, n_items, cs));
   }
   KATZ_HIP(hipStreamEndCapture(cs, &guard.gr));
   KATZ_HIP(hipGraphInstantiate(&guard.ex, guard.gr, nullptr, nullptr, 0));

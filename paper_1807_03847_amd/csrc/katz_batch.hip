@@ -269,8 +269,10 @@ __global__ void __launch_bounds__(kWG) batch_reduce_max(BatchWalk a, long long n
   }
 }
 
+// gi: the graph of every row of this work item (its liveness already known),
+// or -1 when the item holds rows of several graphs (looked up per row).
 template <bool F32, int G>
-__device__ __forceinline__ void batch_rows_group(const BatchWalk& a, int r, long long lb, int bin, int& g_out,
+__device__ __forceinline__ void batch_rows_group(const BatchWalk& a, int r, long long lb, int bin, int gi, int& g_out,
                                                  double& vmax) {
   using T = typename Prec<F32>::T;
   constexpr int RPB = kWG / G;
@@ -278,11 +280,13 @@ __device__ __forceinline__ void batch_rows_group(const BatchWalk& a, int r, long
   const long long i = lb * RPB + threadIdx.x / G;
   bool valid = i < a.bin_count[bin];
   RowDesc d{0, 0, 0};
-  int g = -1;
+  int g = gi;
   if (valid) {
     d = a.desc[a.bin_base[bin] + i];
-    g = a.gid_of[d.row];
-    valid = graph_live<F32>(a, g);
+    if (gi < 0) {
+      g = a.gid_of[d.row];
+      valid = graph_live<F32>(a, g);
+    }
   }
   BatchIn p{0.0, 0.0, 0.0, 0.0f, 0};
   if (valid && lane == 0) p = batch_prefetch<F32>(a, r, g, d.row);
@@ -313,71 +317,109 @@ __device__ __forceinline__ typename Prec<F32>::T batch_block_sum(const typename 
   return tot;
 }
 
+// Work items are taken from this iteration's list of live items (built by
+// batch_live_items); work item b writes workgroup slot b.  The grid may be
+// smaller than the list (persistent workgroups take items with a grid stride).
 template <bool F32>
 __global__ void __launch_bounds__(kWG) walk_batch(BatchWalk a) {
   using T = typename Prec<F32>::T;
   const int r = *a.r_dev;
   if (r >= a.stride) return;
+  const long long n_items = *a.n_items;
   const T* xin = reinterpret_cast<const T*>(a.xbuf[(r + 1) & 1]);
-  const long long total = a.first_block[NUM_BINS];
-  // Work item b (one bin block) writes workgroup slot b; the grid may be
-  // smaller than the work (persistent workgroups take items with a grid stride).
-  for (long long b = blockIdx.x; b < total; b += gridDim.x) {
-  double vmax = 0.0;
-  int g_mine = -1;
+  for (long long t = blockIdx.x; t < n_items; t += gridDim.x) {
+    const long long b = a.items[t];
+    const int gi = a.item_g[b];
+    double vmax = 0.0;
+    int g_mine = -1;
+    int bin = 0;
+    while (bin < NUM_BINS && b >= a.first_block[bin + 1]) ++bin;
+    const long long lb = b - a.first_block[bin];
+    switch (bin) {
+      case BIN_HUGE: {
+        // One segment of a long row (item graph gi): its partial sum only;
+        // batch_huge_combine adds each row's partials in segment order.
+        const SegDesc sd = a.segs[lb];
+        const T tot = batch_block_sum<F32>(xin + a.gbase[gi], a.gcol[gi] + sd.off, sd.len);
+        if (threadIdx.x == 0) reinterpret_cast<T*>(a.partial)[sd.part] = tot;
+        break;
+      }
+      case BIN_B256: {
+        const RowDesc d = a.desc[a.bin_base[BIN_B256] + lb];
+        BatchIn p{0.0, 0.0, 0.0, 0.0f, 0};
+        if (threadIdx.x == 0) p = batch_prefetch<F32>(a, r, gi, d.row);
+        const T tot = batch_block_sum<F32>(xin + a.gbase[gi], a.gcol[gi] + d.off, d.len);
+        if (threadIdx.x == 0) {
+          batch_epilogue<F32>(a, r, d.row, tot, vmax, p);
+          g_mine = gi;
+        }
+        break;
+      }
+      case BIN_W64: batch_rows_group<F32, 64>(a, r, lb, BIN_W64, gi, g_mine, vmax); break;
+      case BIN_G32: batch_rows_group<F32, 32>(a, r, lb, BIN_G32, gi, g_mine, vmax); break;
+      case BIN_G16: batch_rows_group<F32, 16>(a, r, lb, BIN_G16, gi, g_mine, vmax); break;
+      case BIN_G8: batch_rows_group<F32, 8>(a, r, lb, BIN_G8, gi, g_mine, vmax); break;
+      case BIN_G4: batch_rows_group<F32, 4>(a, r, lb, BIN_G4, gi, g_mine, vmax); break;
+      case BIN_EMPTY: {
+        // Rows without arcs: x_r = 0 (and c_1 = 0, e = 0 at r = 1).
+        const long long i = lb * kWG + threadIdx.x;
+        if (i < a.bin_count[BIN_EMPTY]) {
+          const int row = a.desc[a.bin_base[BIN_EMPTY] + i].row;
+          const int g = gi >= 0 ? gi : a.gid_of[row];
+          if (gi >= 0 || graph_live<F32>(a, g)) {
+            reinterpret_cast<T*>(a.xbuf[r & 1])[row] = (T)0;
+            if (r == 1) {
+              a.c[row] = 0.0;
+              if constexpr (F32) a.e[row] = 0.0f;
+            }
+          }
+        }
+        break;
+      }
+      default: break;
+    }
+    batch_store_max<F32>(a, r, g_mine, vmax, b);
+  }
+}
+
+// Graph of each work item: the graph of all its rows, or -1 when its rows
+// belong to several graphs (rows of a bin are in global-id order, so the
+// first and last row decide).  Segments and single-row items have one graph.
+__global__ void __launch_bounds__(kWG) batch_item_graphs(BatchWalk a, long long total, int* item_g) {
+  const long long b = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (b >= total) return;
   int bin = 0;
   while (bin < NUM_BINS && b >= a.first_block[bin + 1]) ++bin;
   const long long lb = b - a.first_block[bin];
-  switch (bin) {
-    case BIN_HUGE: {
-      // One segment of a long row: its partial sum only (batch_huge_combine
-      // adds each row's partials in segment order after this launch).
-      const SegDesc sd = a.segs[lb];
-      const HugeRow h = a.huge[sd.hrow];
-      const int g = a.gid_of[h.row];
-      if (!graph_live<F32>(a, g)) break;          // uniform over the workgroup
-      const T tot = batch_block_sum<F32>(xin + a.gbase[g], a.gcol[g] + sd.off, sd.len);
-      if (threadIdx.x == 0) reinterpret_cast<T*>(a.partial)[sd.part] = tot;
-      break;
-    }
-    case BIN_B256: {
-      const RowDesc d = a.desc[a.bin_base[BIN_B256] + lb];
-      const int g = a.gid_of[d.row];
-      if (!graph_live<F32>(a, g)) break;
-      BatchIn p{0.0, 0.0, 0.0, 0.0f, 0};
-      if (threadIdx.x == 0) p = batch_prefetch<F32>(a, r, g, d.row);
-      const T tot = batch_block_sum<F32>(xin + a.gbase[g], a.gcol[g] + d.off, d.len);
-      if (threadIdx.x == 0) {
-        batch_epilogue<F32>(a, r, d.row, tot, vmax, p);
-        g_mine = g;
-      }
-      break;
-    }
-    case BIN_W64: batch_rows_group<F32, 64>(a, r, lb, BIN_W64, g_mine, vmax); break;
-    case BIN_G32: batch_rows_group<F32, 32>(a, r, lb, BIN_G32, g_mine, vmax); break;
-    case BIN_G16: batch_rows_group<F32, 16>(a, r, lb, BIN_G16, g_mine, vmax); break;
-    case BIN_G8: batch_rows_group<F32, 8>(a, r, lb, BIN_G8, g_mine, vmax); break;
-    case BIN_G4: batch_rows_group<F32, 4>(a, r, lb, BIN_G4, g_mine, vmax); break;
-    case BIN_EMPTY: {
-      // Rows without arcs: x_r = 0 (and c_1 = 0, e = 0 at r = 1).
-      const long long i = lb * kWG + threadIdx.x;
-      if (i < a.bin_count[BIN_EMPTY]) {
-        const int row = a.desc[a.bin_base[BIN_EMPTY] + i].row;
-        const int g = a.gid_of[row];
-        if (graph_live<F32>(a, g)) {
-          reinterpret_cast<T*>(a.xbuf[r & 1])[row] = (T)0;
-          if (r == 1) {
-            a.c[row] = 0.0;
-            if constexpr (F32) a.e[row] = 0.0f;
-          }
-        }
-      }
-      break;
-    }
-    default: break;
+  int g = -1;
+  if (bin == BIN_HUGE) {
+    g = a.gid_of[a.huge[a.segs[lb].hrow].row];
+  } else {
+    const long long rpb = bin == BIN_B256 ? 1 : bin == BIN_W64 ? 4 : bin == BIN_G32 ? 8 : bin == BIN_G16 ? 16
+                        : bin == BIN_G8 ? 32 : bin == BIN_G4 ? 64 : kWG;
+    const long long i0 = lb * rpb;
+    const long long i1 = min(i0 + rpb, a.bin_count[bin]) - 1;
+    const int g0 = a.gid_of[a.desc[a.bin_base[bin] + i0].row];
+    const int g1 = a.gid_of[a.desc[a.bin_base[bin] + i1].row];
+    g = g0 == g1 ? g0 : -1;
   }
-  batch_store_max<F32>(a, r, g_mine, vmax, b);
+  item_g[b] = g;
+}
+
+// This iteration's work items: those whose graph is still iterating, and every
+// item with rows of several graphs.  One atomic per workgroup appends the
+// workgroup's items (their order does not matter: each writes its own slot).
+__global__ void __launch_bounds__(kWG) batch_live_items(BatchWalk a, long long total, int* items, int* n_items) {
+  const int r = *a.r_dev;
+  if (r >= a.stride) return;
+  const long long b = (long long)blockIdx.x * kWG + threadIdx.x;
+  bool keep = false;
+  if (b < total) {
+    const int g = a.item_g[b];
+    keep = g < 0 || graph_live<true>(a, g);
   }
+  const int pos = block_reserve(n_items, keep ? 1u : 0u);
+  if (keep) items[pos] = (int)b;
 }
 
 // Rows longer than one segment: one wave per row of a live graph adds the
@@ -416,7 +458,7 @@ __global__ void __launch_bounds__(kFinishThreads) batch_advance(int* r_dev, int 
                                                                 const unsigned* gxmax32, double* gsigma,
                                                                 double* gsigsum, int* gexp, const double* galpha,
                                                                 const int* gclog2, int stride, int fp32,
-                                                                int* ndone) {
+                                                                int* ndone, int* n_items) {
   const int r = *r_dev;
   __shared__ int s_done;
   if (threadIdx.x == 0) s_done = 0;
@@ -447,6 +489,7 @@ __global__ void __launch_bounds__(kFinishThreads) batch_advance(int* r_dev, int 
   if (threadIdx.x == 0) {
     *r_dev = r + 1;
     *ndone = s_done;
+    *n_items = 0;        // the next iteration's list is rebuilt from zero
   }
 }
 
@@ -569,9 +612,23 @@ hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, long lo
 
 hipError_t launch_batch_advance(int* r_dev, int count, RunScalars* gsc, const unsigned* gxmax32, double* gsigma,
                                 double* gsigsum, int* gexp, const double* galpha, const int* gclog2, int stride,
-                                int fp32, int* ndone, hipStream_t s) {
+                                int fp32, int* ndone, int* n_items, hipStream_t s) {
   hipLaunchKernelGGL(batch_advance, dim3(1), dim3(kFinishThreads), 0, s, r_dev, count, gsc, gxmax32, gsigma, gsigsum,
-                     gexp, galpha, gclog2, stride, fp32, ndone);
+                     gexp, galpha, gclog2, stride, fp32, ndone, n_items);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_item_graphs(const BatchWalk& a, long long total_blocks, int* item_g, hipStream_t s) {
+  if (total_blocks <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)((total_blocks + kWG - 1) / kWG);
+  hipLaunchKernelGGL(batch_item_graphs, dim3(nb), dim3(kWG), 0, s, a, total_blocks, item_g);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_live_items(const BatchWalk& a, long long total_blocks, int* items, int* n_items,
+                                   hipStream_t s) {
+  const unsigned nb = (unsigned)std::max<long long>(1, (total_blocks + kWG - 1) / kWG);
+  hipLaunchKernelGGL(batch_live_items, dim3(nb), dim3(kWG), 0, s, a, total_blocks, items, n_items);
   return hipGetLastError();
 }
 

@@ -220,6 +220,9 @@ struct BatchWalk {
   void* partial;
   const double* etap;           // eta'_r per graph: [count][stride]
   const int* r_dev;
+  const int* item_g;            // per work item: the graph of all its rows, or -1 (rows of several graphs)
+  const int* items;             // work items of this iteration (live graphs only), *n_items of them
+  const int* n_items;
   int* blk_g;                   // per workgroup: graph of all its rows, or -1
   double* blk_m;                // per workgroup: maximum new walk entry of that graph
   long long blk_base;           // first slot of this launch in blk_g / blk_m
@@ -317,10 +320,13 @@ hipError_t launch_batch_dmax(const RowDesc* desc, long long count, const int* gi
 hipError_t launch_fill_ones(void* x, long long n, int fp32, hipStream_t s);
 hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, long long max_grid, long long n_huge,
                              hipStream_t s);
+hipError_t launch_batch_item_graphs(const BatchWalk& a, long long total_blocks, int* item_g, hipStream_t s);
+hipError_t launch_batch_live_items(const BatchWalk& a, long long total_blocks, int* items, int* n_items,
+                                   hipStream_t s);
 constexpr int kBatchMaxLdsGraphs = 8192;   // per-graph maxima reduced in LDS up to this many graphs
 hipError_t launch_batch_advance(int* r_dev, int count, RunScalars* gsc, const unsigned* gxmax32, double* gsigma,
                                 double* gsigsum, int* gexp, const double* galpha, const int* gclog2, int stride,
-                                int fp32, int* ndone, hipStream_t s);
+                                int fp32, int* ndone, int* n_items, hipStream_t s);
 hipError_t launch_batch_write(const GraphSel* gsel, int count, int32_t* const* out_ids, double* const* out_lo,
                               double* const* out_up, uint8_t* mark, double* rest, hipStream_t s);
 
