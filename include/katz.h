@@ -263,12 +263,16 @@ int katz_timing_read(katz_timing* out);
  *                        0 .. 32.  A non-zero hub_bytes needs a non-zero
  *                        blocks_per_cu (the copy is filled once per workgroup).
  *   batch_blocks_per_cu  the same for the batched form (count > 1); 0 .. 32.
+ *   batch_tile           batched form: row groups per work item of the short-row
+ *                        bins (each wave sums its rows group after group, each row
+ *                        still by the same lanes); 0 or 1 = one group, up to 16.
  * Defaults: all 0.  Calls already running keep the setting they started with. */
 typedef struct katz_tuning {
   int32_t hub_bytes;
   int32_t blocks_per_cu;
   int32_t batch_blocks_per_cu;
-  int32_t reserved[5];       /* must be 0 */
+  int32_t batch_tile;
+  int32_t reserved[4];       /* must be 0 */
 } katz_tuning;
 
 /* Copies the current setting; E_INVALID_ARG if t is NULL. */
@@ -278,8 +282,8 @@ int katz_tuning_set(const katz_tuning* t);
 /* Autotuner: times katz_rank_static(count, g, p) on `stream` under each
  * candidate launch shape (two calls each, the second timed), installs the
  * fastest and copies it to *best (may be NULL).  count = 1 tunes hub_bytes and
- * blocks_per_cu, count > 1 tunes batch_blocks_per_cu; the other fields keep
- * their values.  Inputs as for katz_rank_static; returns the first error of a
+ * blocks_per_cu, count > 1 tunes batch_blocks_per_cu and batch_tile; the other
+ * fields keep their values.  Inputs as for katz_rank_static; returns the first error of a
  * ranking call (the setting is then left unchanged), or KATZ_OK. */
 int katz_autotune(int32_t count, const katz_csr* g, const katz_params* p, katz_tuning* best, void* stream);
 

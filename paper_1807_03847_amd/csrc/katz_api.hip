@@ -173,8 +173,9 @@ int tuning_valid(const katz_tuning& t) {
   if (t.hub_bytes < 0 || t.hub_bytes > 65536 || (t.hub_bytes & 15)) return KATZ_E_INVALID_ARG;
   if (t.blocks_per_cu < 0 || t.blocks_per_cu > 32) return KATZ_E_INVALID_ARG;
   if (t.batch_blocks_per_cu < 0 || t.batch_blocks_per_cu > 32) return KATZ_E_INVALID_ARG;
+  if (t.batch_tile < 0 || t.batch_tile > 16) return KATZ_E_INVALID_ARG;
   if (t.hub_bytes > 0 && t.blocks_per_cu == 0) return KATZ_E_INVALID_ARG;
-  for (int i = 0; i < 5; ++i)
+  for (int i = 0; i < 4; ++i)
     if (t.reserved[i] != 0) return KATZ_E_INVALID_ARG;
   return KATZ_OK;
 }
@@ -1321,12 +1322,19 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   bw.desc = b.desc;
   bw.segs = b.segs;
   bw.huge = b.huge;
+  const int tile = std::max(1, current_tuning().batch_tile);
   {
-    IterArgs tmp{};
-    long long tb = 0;
-    fill_blocks(tmp, b, true, tb);
-    for (int i = 0; i <= NUM_BINS; ++i) bw.first_block[i] = tmp.first_block[i];
+    // Work items per bin: one per segment / long row, `tile` row groups
+    // otherwise (a row group is one workgroup's worth of rows).
+    const long long per[NUM_BINS] = {1, 1, 4, 8, 16, 32, 64, kWG};
+    long long items[NUM_BINS] = {};
+    items[BIN_HUGE] = b.seg_total;
+    items[BIN_B256] = b.bin_count[BIN_B256];
+    for (int i = BIN_W64; i < NUM_BINS; ++i) items[i] = (b.bin_count[i] + per[i] * tile - 1) / (per[i] * tile);
+    bw.first_block[0] = 0;
+    for (int i = 0; i < NUM_BINS; ++i) bw.first_block[i + 1] = bw.first_block[i] + items[i];
   }
+  bw.tile = tile;
   for (int i = 0; i < NUM_BINS; ++i) {
     bw.bin_base[i] = b.bin_base[i];
     bw.bin_count[i] = b.bin_count[i];
@@ -2068,7 +2076,7 @@ KATZ_EXPORT int katz_autotune(int32_t count, const katz_csr* g, const katz_param
     sum_k += p[i].k;
   }
   static const int kSingle[][2] = {{0, 0}, {0, 4}, {0, 8}, {0, 16}, {16384, 4}, {32768, 4}, {65536, 2}};
-  static const int kBatch[] = {0, 2, 4, 8, 16};
+  static const int kBatch[][2] = {{0, 1}, {4, 1}, {16, 1}, {4, 2}, {16, 2}, {4, 4}, {16, 4}, {16, 8}};
   const katz_tuning saved = katz::current_tuning();
   int32_t* ids = nullptr;
   double *lo = nullptr, *up = nullptr;
@@ -2090,9 +2098,10 @@ KATZ_EXPORT int katz_autotune(int32_t count, const katz_csr* g, const katz_param
       cand.push_back(t);
     }
   } else {
-    for (int b : kBatch) {
+    for (const auto& c : kBatch) {
       katz_tuning t = saved;
-      t.batch_blocks_per_cu = b;
+      t.batch_blocks_per_cu = c[0];
+      t.batch_tile = c[1];
       cand.push_back(t);
     }
   }

@@ -298,8 +298,16 @@ __device__ __forceinline__ void batch_rows_group(const BatchWalk& a, int r, long
 #pragma unroll
   for (int o = G / 2; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, G);
   if (valid && lane == 0) {
-    batch_epilogue<F32>(a, r, d.row, sum, vmax, p);
-    g_out = g;
+    if (gi >= 0) {
+      batch_epilogue<F32>(a, r, d.row, sum, vmax, p);
+      g_out = g;
+    } else {
+      // Rows of several graphs in one item: fold this row's entry into its
+      // graph's maximum at once (such items are rare).
+      double m = 0.0;
+      batch_epilogue<F32>(a, r, d.row, sum, m, p);
+      if (m > 0.0) graph_max_atomic(a, r, g, m, F32);
+    }
   }
 }
 
@@ -355,22 +363,34 @@ __global__ void __launch_bounds__(kWG) walk_batch(BatchWalk a) {
         }
         break;
       }
-      case BIN_W64: batch_rows_group<F32, 64>(a, r, lb, BIN_W64, gi, g_mine, vmax); break;
-      case BIN_G32: batch_rows_group<F32, 32>(a, r, lb, BIN_G32, gi, g_mine, vmax); break;
-      case BIN_G16: batch_rows_group<F32, 16>(a, r, lb, BIN_G16, gi, g_mine, vmax); break;
-      case BIN_G8: batch_rows_group<F32, 8>(a, r, lb, BIN_G8, gi, g_mine, vmax); break;
-      case BIN_G4: batch_rows_group<F32, 4>(a, r, lb, BIN_G4, gi, g_mine, vmax); break;
+      case BIN_W64:
+        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, 64>(a, r, lb * a.tile + k, BIN_W64, gi, g_mine, vmax);
+        break;
+      case BIN_G32:
+        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, 32>(a, r, lb * a.tile + k, BIN_G32, gi, g_mine, vmax);
+        break;
+      case BIN_G16:
+        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, 16>(a, r, lb * a.tile + k, BIN_G16, gi, g_mine, vmax);
+        break;
+      case BIN_G8:
+        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, 8>(a, r, lb * a.tile + k, BIN_G8, gi, g_mine, vmax);
+        break;
+      case BIN_G4:
+        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, 4>(a, r, lb * a.tile + k, BIN_G4, gi, g_mine, vmax);
+        break;
       case BIN_EMPTY: {
         // Rows without arcs: x_r = 0 (and c_1 = 0, e = 0 at r = 1).
-        const long long i = lb * kWG + threadIdx.x;
-        if (i < a.bin_count[BIN_EMPTY]) {
-          const int row = a.desc[a.bin_base[BIN_EMPTY] + i].row;
-          const int g = gi >= 0 ? gi : a.gid_of[row];
-          if (gi >= 0 || graph_live<F32>(a, g)) {
-            reinterpret_cast<T*>(a.xbuf[r & 1])[row] = (T)0;
-            if (r == 1) {
-              a.c[row] = 0.0;
-              if constexpr (F32) a.e[row] = 0.0f;
+        for (int k = 0; k < a.tile; ++k) {
+          const long long i = (lb * a.tile + k) * kWG + threadIdx.x;
+          if (i < a.bin_count[BIN_EMPTY]) {
+            const int row = a.desc[a.bin_base[BIN_EMPTY] + i].row;
+            const int g = gi >= 0 ? gi : a.gid_of[row];
+            if (gi >= 0 || graph_live<F32>(a, g)) {
+              reinterpret_cast<T*>(a.xbuf[r & 1])[row] = (T)0;
+              if (r == 1) {
+                a.c[row] = 0.0;
+                if constexpr (F32) a.e[row] = 0.0f;
+              }
             }
           }
         }
@@ -395,8 +415,9 @@ __global__ void __launch_bounds__(kWG) batch_item_graphs(BatchWalk a, long long 
   if (bin == BIN_HUGE) {
     g = a.gid_of[a.huge[a.segs[lb].hrow].row];
   } else {
-    const long long rpb = bin == BIN_B256 ? 1 : bin == BIN_W64 ? 4 : bin == BIN_G32 ? 8 : bin == BIN_G16 ? 16
-                        : bin == BIN_G8 ? 32 : bin == BIN_G4 ? 64 : kWG;
+    const long long rpb = bin == BIN_B256 ? 1
+                        : (bin == BIN_W64 ? 4 : bin == BIN_G32 ? 8 : bin == BIN_G16 ? 16 : bin == BIN_G8 ? 32
+                           : bin == BIN_G4 ? 64 : kWG) * a.tile;
     const long long i0 = lb * rpb;
     const long long i1 = min(i0 + rpb, a.bin_count[bin]) - 1;
     const int g0 = a.gid_of[a.desc[a.bin_base[bin] + i0].row];

@@ -228,6 +228,7 @@ struct BatchWalk {
   long long blk_base;           // first slot of this launch in blk_g / blk_m
   int count;                    // graphs in the batch
   int direct_max;               // 1: workgroups update per-graph maxima with atomics
+  int tile;                     // row groups per work item in the short-row bins
   int stride;
   int fp32;
 };

@@ -130,11 +130,11 @@ def test_batch_launch_tuning_is_invisible(precision):
     params.append(dict(k=20, alpha=0.5 / (1 + sg.max_degree(rp)), eps=1e-7))
     saved = katz.tuning_get()
     try:
-        katz.tuning_set(**dict(saved, batch_blocks_per_cu=0))
+        katz.tuning_set(**dict(saved, batch_blocks_per_cu=0, batch_tile=0))
         ref = run_batch(graphs, params, precision)
-        for bbpc in (1, 4, 32):
-            say("batch tuning", precision, bbpc)
-            katz.tuning_set(**dict(saved, batch_blocks_per_cu=bbpc))
+        for bbpc, tile in ((1, 1), (4, 3), (32, 2), (0, 16)):
+            say("batch tuning", precision, bbpc, tile)
+            katz.tuning_set(**dict(saved, batch_blocks_per_cu=bbpc, batch_tile=tile))
             res = run_batch(graphs, params, precision)
             for a, b in zip(res, ref):
                 assert torch.equal(a.topk, b.topk) and torch.equal(a.lower, b.lower) and torch.equal(a.upper, b.upper)
@@ -142,7 +142,8 @@ def test_batch_launch_tuning_is_invisible(precision):
         gl = [(torch.from_numpy(np.asarray(r, dtype=np.int64)).cuda(), torch.from_numpy(c).cuda(), True)
               for r, c in graphs]
         best = katz.autotune_batch(gl, [dict(pp, precision=precision) for pp in params])
-        assert best["batch_blocks_per_cu"] in (0, 2, 4, 8, 16)
+        assert (best["batch_blocks_per_cu"], best["batch_tile"]) in ((0, 1), (4, 1), (16, 1), (4, 2), (16, 2), (4, 4),
+                                                                     (16, 4), (16, 8))
         assert katz.tuning_get() == best
     finally:
         katz.tuning_set(**saved)
