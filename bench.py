@@ -139,14 +139,16 @@ def main():
             tunings[precision] = katz.tuning_get()
         print(f"[bench] {precision} tuning {tunings[precision]}", flush=True)
         res, sec, tm = time_form(katz, torch, rp_t, col_t, precision, args.steps, args.warmup)
-        # Walk steps that did work: r - 1 per call.  The host enqueues one more
-        # walk launch before it reads the stop flag; that launch returns at once
-        # and is not a walk step.
-        walk_avg_ms = tm["walk_step_ms"] / max(tm["calls"] * (res.iterations - 1), 1)
-        forms[precision] = dict(res=res, sec=sec, tm=tm, walk_avg_ms=walk_avg_ms,
+        # Plain walk steps that did work: r - 2 per call (steps 3..r; step 2 is
+        # fused with the renumbering and timed on its own).  The host enqueues
+        # one more walk launch before it reads the stop flag; that launch
+        # returns at once and is not a walk step.
+        walk_avg_ms = tm["walk_step_ms"] / max(tm["calls"] * (res.iterations - 2), 1)
+        renum_avg_ms = tm["renumber_step_ms"] / max(tm["renumber_step_launches"], 1)
+        forms[precision] = dict(res=res, sec=sec, tm=tm, walk_avg_ms=walk_avg_ms, renum_avg_ms=renum_avg_ms,
                                 gteps=res.iterations * nnz / sec / 1e9)
         print(f"[bench] {precision}: r={res.iterations} status={res.status} {sec * 1e3:.3f} ms/step "
-              f"walk_step {walk_avg_ms * 1e3:.1f} us", flush=True)
+              f"walk_step {walk_avg_ms * 1e3:.1f} us, renumbering step {renum_avg_ms * 1e3:.1f} us", flush=True)
 
     # The same FP32 run without the internal renumbering, for context.
     katz.tuning_set(**tunings["fp32"])
@@ -187,13 +189,15 @@ def main():
             "iterations": f64["res"].iterations,
             "status": f64["res"].status,
             "walk_step_avg_us": round(f64["walk_avg_ms"] * 1e3, 2),
+            "renumber_step_avg_us": round(f64["renum_avg_ms"] * 1e3, 2),
             "walk_step_hbm_gbs": round(algorithmic_bytes_per_walk_step(n, nnz, "fp64")
                                        / (f64["walk_avg_ms"] * 1e-3) / 1e9, 1),
         },
         "speedup_fp32_vs_fp64": round(f64["sec"] / f32["sec"], 3),
         "phase_ms_per_step_fp32": {
             key: round(f32["tm"][key] / max(f32["tm"]["calls"], 1), 4)
-            for key in ("prep_ms", "walk_first_ms", "walk_step_ms", "select_ms", "result_ms", "call_ms")
+            for key in ("prep_ms", "walk_first_ms", "renumber_step_ms", "walk_step_ms", "select_ms", "result_ms",
+                        "call_ms")
         },
         "roofline": {
             "bound": "hbm",
@@ -205,8 +209,9 @@ def main():
             "traffic": None,
             "bytes_per_launch": bytes_step,
             "avg_launch_us": round(f32["walk_avg_ms"] * 1e3, 2),
-            "walk_steps_timed": f32["tm"]["calls"] * (f32["res"].iterations - 1),
+            "walk_steps_timed": f32["tm"]["calls"] * (f32["res"].iterations - 2),
             "launches_timed": f32["tm"]["walk_step_launches"],
+            "renumber_step_avg_us": round(f32["renum_avg_ms"] * 1e3, 2),
         },
     }
 
@@ -225,7 +230,7 @@ def main():
                          (32768, 2), (32768, 4), (65536, 1), (65536, 2)]:
             katz.tuning_set(hub, bpc)
             r_s, sec_s, tm_s = time_form(katz, torch, rp_t, col_t, "fp32", max(1, args.steps // 2), 1)
-            walk_us = tm_s["walk_step_ms"] / max(tm_s["calls"] * (r_s.iterations - 1), 1) * 1e3
+            walk_us = tm_s["walk_step_ms"] / max(tm_s["calls"] * (r_s.iterations - 2), 1) * 1e3
             sweep.append({"hub_bytes": hub, "blocks_per_cu": bpc, "ms_per_step": round(sec_s * 1e3, 4),
                           "walk_step_avg_us": round(walk_us, 2),
                           "same_result": bool(torch.equal(r_s.topk, f32["res"].topk)

@@ -240,6 +240,9 @@ typedef struct katz_timing {
   double result_ms;          /* output kernels                                 */
   double call_ms;            /* first to last event of each call, summed       */
   int64_t calls;
+  /* Walk step 2 of renumbered static calls, which also renames the column ids
+   * (counted here, not in walk_step_*).                                        */
+  double renumber_step_ms;   int64_t renumber_step_launches;
 } katz_timing;
 
 /* on = 1: reset the counters and start recording; on = 0: stop. */

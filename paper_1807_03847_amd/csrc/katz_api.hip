@@ -148,7 +148,7 @@ bool is_device_ptr(const void* p) {
 // Optional device timing of the phases of every call (hipEvent pairs recorded
 // on the call's stream; summed when the call has synchronised).
 // ---------------------------------------------------------------------------
-enum TimedKind { T_PREP = 0, T_FIRST, T_STEP, T_SELECT, T_RESULT, T_KINDS };
+enum TimedKind { T_PREP = 0, T_FIRST, T_STEP, T_SELECT, T_RESULT, T_RENUM, T_KINDS };
 
 struct TimingState {
   std::mutex mu;
@@ -255,6 +255,8 @@ struct CallTimer {
     t.walk_first_launches += cnt[T_FIRST];
     t.walk_step_ms += sum[T_STEP];
     t.walk_step_launches += cnt[T_STEP];
+    t.renumber_step_ms += sum[T_RENUM];
+    t.renumber_step_launches += cnt[T_RENUM];
     t.select_ms += sum[T_SELECT];
     t.select_iterations += cnt[T_SELECT];
     t.result_ms += sum[T_RESULT];
@@ -392,6 +394,7 @@ int reduction_depth(long long dmax) {
     case BIN_G8: return 3;
     case BIN_G16: return 4;
     case BIN_G32: return 5;
+    case BIN_W16: return (kShortRowMax / 16 - 1) + 4;
     case BIN_W64: return (kPerLane - 1) + 6;
     case BIN_B256: return (kPerLane - 1) + 8;
     default: {
@@ -524,6 +527,13 @@ struct Run {
   int grid = 1;
   int hub_n = 0;               // walk entries copied to LDS (renumbered static runs)
   long long walk_grid = 0;     // persistent walk grid (0: one workgroup per work item)
+  // Renumbered static runs: walk step 2 also renames the caller's column ids
+  // into col (walk_step<F32, true>).
+  bool renumber = false;
+  const int32_t* col_src = nullptr;
+  const long long* coff = nullptr;
+  const IdLen* pmap = nullptr;
+  int32_t* ncol = nullptr;
 };
 
 void* x_at(const Run& run, int r) { return run.st ? (void*)run.st->X[r] : run.w->x[r & 1]; }
@@ -533,6 +543,7 @@ void fill_blocks(IterArgs& ia, const Bins& b, bool write_empty, long long& total
   blocks[BIN_HUGE] = b.seg_total;
   blocks[BIN_B256] = b.bin_count[BIN_B256];
   blocks[BIN_W64] = (b.bin_count[BIN_W64] + 3) / 4;
+  blocks[BIN_W16] = (b.bin_count[BIN_W16] + 15) / 16;
   blocks[BIN_G32] = (b.bin_count[BIN_G32] + 7) / 8;
   blocks[BIN_G16] = (b.bin_count[BIN_G16] + 15) / 16;
   blocks[BIN_G8] = (b.bin_count[BIN_G8] + 31) / 32;
@@ -641,11 +652,19 @@ int ensure_levels(katz_state* st, int r);
 
 int enqueue_walk(Run& run, int r, hipStream_t s, CallTimer& T) {
   long long tb = 0;
-  const IterArgs ia = iter_args(run, *run.bins, r, false, tb);
-  const int tw = T.start(r == 1 ? T_FIRST : T_STEP, s);
+  IterArgs ia = iter_args(run, *run.bins, r, false, tb);
+  const bool renum = run.renumber && r == 2;
+  if (renum) {
+    ia.col_src = run.col_src;
+    ia.coff = run.coff;
+    ia.pmap = run.pmap;
+    ia.ncol = run.ncol;
+    ia.hub_n = 0;
+  }
+  const int tw = T.start(r == 1 ? T_FIRST : renum ? T_RENUM : T_STEP, s);
   if (r == 1) KATZ_HIP(launch_walk_first(ia, run.fp32, run.n, run.nnz, run.validate >= KATZ_VALIDATE_BASIC, s));
   long long grid = 1;
-  if (r >= 2) KATZ_HIP(launch_walk_step(ia, run.fp32, tb, run.walk_grid, &grid, s));
+  if (r >= 2) KATZ_HIP(launch_walk_step(ia, run.fp32, tb, run.walk_grid, &grid, s, renum));
   T.stop(tw, s);
   const long long nb = r == 1 ? std::max<long long>(1, (run.bins->count + kWG - 1) / kWG) : grid;
   KATZ_HIP(launch_reduce_blkmax(run.w->blkmax, nb, run.fp32, run.w->xmax32, run.w->xmax64, r, run.w->sc, s));
@@ -799,6 +818,8 @@ struct Staging {
   int* len32 = nullptr;
   int32_t* ext_of = nullptr;
   int32_t* int_of = nullptr;
+  long long* coff = nullptr;      // internal id -> caller row offset
+  IdLen* pmap = nullptr;          // caller id -> {internal id, length}
   long long* sums = nullptr;
   long long* total = nullptr;
   long long* row_off = nullptr;   // strict symmetry check
@@ -832,6 +853,8 @@ void layout(Arena& ar, const Plan& pl, Bins& b, Work& w, Staging& stg) {
     stg.len32 = ar.take<int>(n);
     stg.ext_of = ar.take<int32_t>(n);
     stg.int_of = ar.take<int32_t>(n);
+    stg.coff = ar.take<long long>(n);
+    stg.pmap = ar.take<IdLen>(n);
     stg.sums = ar.take<long long>(scan_sums_capacity(n));
     stg.total = ar.take<long long>(1);
   }
@@ -877,6 +900,20 @@ int plan_and_allocate(Arena& ar, const Plan& pl, Bins& b, Work& w, Staging& stg)
   return KATZ_OK;
 }
 
+// Renumbered runs that reach walk step 2 rename the column ids there; with
+// basic validation that step also range-checks them.
+bool renumber_in_walk(const Plan& pl) { return pl.reorder && pl.max_iter >= 2; }
+
+// Range check of the caller's column ids for a renumbered run that stopped
+// before walk step 2 read them.
+int check_columns_if_unread(const Plan& pl, const Staging& stg, const Work& w, HostSync& hs, hipStream_t s) {
+  if (!renumber_in_walk(pl) || pl.validate != KATZ_VALIDATE_BASIC || hs.sc->iterations >= 2) return KATZ_OK;
+  KATZ_HIP(launch_check_col_range(stg.col, pl.g->nnz, pl.g->n, w.sc, s));
+  KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+  KATZ_HIP(hipStreamSynchronize(s));
+  return hs.sc->err ? KATZ_E_CSR : KATZ_OK;
+}
+
 // Stages host inputs, bins the rows, reads back d_max and the bin sizes.
 int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStream_t s) {
   const katz_csr* g = pl.g;
@@ -896,10 +933,12 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
   KATZ_HIP(launch_prep_scan(b.blk, b.nblocks, b.scan_sums, b.scan_totals, w.sc, s));
   KATZ_HIP(launch_prep_scatter(stg.row_ptr, g->row_ptr_64, g->n, b.blk, b.nblocks, b.desc, b.segs, b.huge, w.sc, s));
   // Column ids are range-checked before any gather uses them: here, or, when
-  // the graph is renumbered with basic validation, inside the renumbering
-  // (which reads every column id anyway and never indexes with a bad one).
-  const bool check_in_remap = pl.reorder && pl.validate == KATZ_VALIDATE_BASIC;
-  if (pl.validate >= KATZ_VALIDATE_BASIC && !check_in_remap)
+  // the graph is renumbered with basic validation, in walk step 2, which reads
+  // every caller column id to rename it and never indexes with a bad one (no
+  // step before it reads a column id; a run that stops before step 2 is
+  // checked by check_columns_if_unread).
+  const bool check_in_walk = renumber_in_walk(pl);
+  if (pl.validate >= KATZ_VALIDATE_BASIC && !check_in_walk)
     KATZ_HIP(launch_check_col_range(stg.col, g->nnz, g->n, w.sc, s));
   KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
   KATZ_HIP(hipStreamSynchronize(s));
@@ -914,8 +953,8 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
   if (pl.reorder) {
     // Renumber by the binned order and rebuild the bins on the renumbered rows
     // (now contiguous per bin).
-    KATZ_HIP(launch_relabel(b.desc, g->n, b.bin_base, b.bin_count, b.segs, b.seg_total, stg.col, stg.ext_of,
-                            stg.int_of, stg.len_ll, stg.len32, stg.noff, stg.sums, stg.total, stg.ncol, w.sc, s));
+    KATZ_HIP(launch_relabel(b.desc, g->n, stg.ext_of, stg.int_of, stg.coff, stg.pmap, stg.len_ll, stg.len32,
+                            stg.noff, stg.sums, stg.total, s));
     KATZ_HIP(launch_prep_rows(nullptr, g->n, stg.noff, stg.len32, b.blk, b.nblocks, b.scan_sums, b.scan_totals,
                               b.desc, b.segs, b.huge, w.sc, s));
     KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
@@ -968,10 +1007,15 @@ int rank_one(const katz_csr* g, const katz_params* p, katz_result* out, hipStrea
   run.nnz = g->nnz;
   run.undirected = g->undirected;
   run.fp32 = pl.fp32;
-  run.validate = KATZ_VALIDATE_NONE;   // columns were checked in prepare()
+  run.validate = KATZ_VALIDATE_NONE;   // columns are checked in prepare() or in walk step 2
   run.col = pl.reorder ? stg.ncol : stg.col;
   run.ext_of = pl.reorder ? stg.ext_of : nullptr;
   run.int_of = pl.reorder ? stg.int_of : nullptr;
+  run.renumber = renumber_in_walk(pl);
+  run.col_src = stg.col;
+  run.coff = stg.coff;
+  run.pmap = stg.pmap;
+  run.ncol = stg.ncol;
   {
     const katz_tuning tu = current_tuning();
     run.walk_grid = (long long)tu.blocks_per_cu * cu_count(dev);
@@ -985,6 +1029,7 @@ int rank_one(const katz_csr* g, const katz_params* p, katz_result* out, hipStrea
   run.max_iter = pl.max_iter;
   run.grid = (int)std::min<long long>((g->n + kWG - 1) / kWG, 2048);
   KATZ_TRY(iterate(run, ar.hs, 1, false, s, T));
+  KATZ_TRY(check_columns_if_unread(pl, stg, w, ar.hs, s));
   return write_result(run, ar.hs, out, stg.out_ids, stg.out_lo, stg.out_up, s, T);
 }
 
@@ -1023,10 +1068,15 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   run.nnz = g->nnz;
   run.undirected = g->undirected;
   run.fp32 = pl.fp32;
-  run.validate = KATZ_VALIDATE_NONE;   // columns were checked in prepare()
+  run.validate = KATZ_VALIDATE_NONE;   // columns are checked in prepare() or in walk step 2
   run.col = pl.reorder ? stg.ncol : stg.col;
   run.ext_of = pl.reorder ? stg.ext_of : nullptr;
   run.int_of = pl.reorder ? stg.int_of : nullptr;
+  run.renumber = renumber_in_walk(pl);
+  run.col_src = stg.col;
+  run.coff = stg.coff;
+  run.pmap = stg.pmap;
+  run.ncol = stg.ncol;
   {
     const katz_tuning tu = current_tuning();
     run.walk_grid = (long long)tu.blocks_per_cu * cu_count(dev);
@@ -1061,13 +1111,14 @@ constexpr int kItersPerGraph = 4;   // iterations captured in one hipGraph
 
 int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* out, hipStream_t s) {
   const int fp32 = p[0].precision == KATZ_FP32_MARGIN;
-  long long total_n = 0, total_nnz = 0, max_nnz = 0, sum_k = 0;
+  long long total_n = 0, total_nnz = 0, max_nnz = 0, max_n = 0, sum_k = 0;
   int max_iter = 1;
   for (int i = 0; i < count; ++i) {
     if ((p[i].precision == KATZ_FP32_MARGIN) != (fp32 != 0)) return KATZ_E_UNSUPPORTED;
     total_n += g[i].n;
     total_nnz += g[i].nnz;
     max_nnz = std::max<long long>(max_nnz, g[i].nnz);
+    max_n = std::max<long long>(max_n, g[i].n);
     sum_k += p[i].k;
     max_iter = std::max(max_iter, p[i].max_iter ? p[i].max_iter : 1000);
   }
@@ -1098,7 +1149,8 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   double* galpha = nullptr;
   int* gclog2 = nullptr;
   int* gdmax = nullptr;
-  double *gsigma = nullptr, *gsigsum = nullptr, *etap = nullptr, *rest = nullptr;
+  double *gsigma = nullptr, *gsigsum = nullptr, *etap = nullptr;
+  unsigned long long* rest = nullptr;
   int* gexp = nullptr;
   unsigned* gxmax32 = nullptr;
   unsigned long long* gxmax64 = nullptr;
@@ -1137,7 +1189,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     gxmax32 = ar.take<unsigned>((size_t)count * stride);
     gxmax64 = ar.take<unsigned long long>((size_t)count * stride);
     etap = ar.take<double>((size_t)count * stride);
-    rest = ar.take<double>(count);
+    rest = ar.take<unsigned long long>(count);
     gid_of = ar.take<int>(total_n);
     gsel = ar.take<GraphSel>(count);
     // Workgroup slots of one walk step: at most one per 4 rows of up to 1024
@@ -1326,7 +1378,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   {
     // Work items per bin: one per segment / long row, `tile` row groups
     // otherwise (a row group is one workgroup's worth of rows).
-    const long long per[NUM_BINS] = {1, 1, 4, 8, 16, 32, 64, kWG};
+    const long long per[NUM_BINS] = {1, 1, 4, 16, 8, 16, 32, 64, kWG};
     long long items[NUM_BINS] = {};
     items[BIN_HUGE] = b.seg_total;
     items[BIN_B256] = b.bin_count[BIN_B256];
@@ -1422,10 +1474,11 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     if (fin[i].err) return fin[i].err == 2 ? KATZ_E_HIP : KATZ_E_CSR;
   const int tr = T.start(T_RESULT, cs);
   KATZ_HIP(hipMemsetAsync(w.mark, 0, (size_t)total_n, cs));
-  KATZ_HIP(launch_batch_write(gsel, count, o_ids, o_lo, o_up, w.mark, rest, cs));
+  KATZ_HIP(hipMemsetAsync(rest, 0, sizeof(unsigned long long) * count, cs));
+  KATZ_HIP(launch_batch_write(gsel, count, max_n, o_ids, o_lo, o_up, w.mark, rest, cs));
   T.stop(tr, cs);
-  std::vector<double> h_rest(count);
-  KATZ_HIP(hipMemcpyAsync(h_rest.data(), rest, sizeof(double) * count, hipMemcpyDeviceToHost, cs));
+  std::vector<unsigned long long> h_rest(count);
+  KATZ_HIP(hipMemcpyAsync(h_rest.data(), rest, sizeof(unsigned long long) * count, hipMemcpyDeviceToHost, cs));
   if (out_host) {
     koff = 0;
     for (int i = 0; i < count; ++i) {
@@ -1439,12 +1492,14 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   T.commit(cs);
   int worst = KATZ_OK;
   for (int i = 0; i < count; ++i) {
+    double rest_i;
+    std::memcpy(&rest_i, &h_rest[i], sizeof(double));
     out[i].iterations = fin[i].iterations;
     out[i].status = fin[i].done ? fin[i].status : KATZ_W_ITER_LIMIT;
     out[i].active_final = fin[i].m;
     out[i].alpha_used = S[i].alpha;
     out[i].eta = fp32 ? S[i].eta[std::max(1, fin[i].iterations)] : 0.0;
-    out[i].rest_upper_max = (p[i].k == g[i].n) ? -std::numeric_limits<double>::infinity() : h_rest[i];
+    out[i].rest_upper_max = (p[i].k == g[i].n) ? -std::numeric_limits<double>::infinity() : rest_i;
     worst = std::max(worst, out[i].status);
   }
   return worst;

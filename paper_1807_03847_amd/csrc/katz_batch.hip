@@ -84,7 +84,10 @@ __global__ void __launch_bounds__(kWG) batch_col_range(const int32_t* const* gco
   if (__ballot(bad) && lane_id() == 0) atomicOr(&sc->err, 1);
 }
 
-// Longest row of every graph (a wave whose rows share one graph adds one atomic).
+// Longest row of every graph.  A wave whose rows share one graph folds its
+// maximum with one atomic, and only when it exceeds the value it reads first:
+// stored values only grow, so any value read (stale or not) is at most the
+// current one and a skipped atomic never loses a maximum.
 __global__ void __launch_bounds__(kWG) batch_dmax(const RowDesc* desc, long long count, const int* gid_of,
                                                   int* gdmax) {
   const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
@@ -99,7 +102,9 @@ __global__ void __launch_bounds__(kWG) batch_dmax(const RowDesc* desc, long long
   if (uniform) {
     int m = len;
     for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o));
-    if (lane_id() == 0 && g0 >= 0 && m > 0) atomicMax(&gdmax[g0], m);
+    if (lane_id() == 0 && g0 >= 0 && m > 0 &&
+        m > *reinterpret_cast<volatile const int*>(&gdmax[g0]))
+      atomicMax(&gdmax[g0], m);
   } else if (g >= 0 && len > 0) {
     atomicMax(&gdmax[g], len);
   }
@@ -366,6 +371,9 @@ __global__ void __launch_bounds__(kWG) walk_batch(BatchWalk a) {
       case BIN_W64:
         for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, 64>(a, r, lb * a.tile + k, BIN_W64, gi, g_mine, vmax);
         break;
+      case BIN_W16:
+        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, 16>(a, r, lb * a.tile + k, BIN_W16, gi, g_mine, vmax);
+        break;
       case BIN_G32:
         for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, 32>(a, r, lb * a.tile + k, BIN_G32, gi, g_mine, vmax);
         break;
@@ -416,7 +424,7 @@ __global__ void __launch_bounds__(kWG) batch_item_graphs(BatchWalk a, long long 
     g = a.gid_of[a.huge[a.segs[lb].hrow].row];
   } else {
     const long long rpb = bin == BIN_B256 ? 1
-                        : (bin == BIN_W64 ? 4 : bin == BIN_G32 ? 8 : bin == BIN_G16 ? 16 : bin == BIN_G8 ? 32
+                        : (bin == BIN_W64 ? 4 : bin == BIN_W16 ? 16 : bin == BIN_G32 ? 8 : bin == BIN_G16 ? 16 : bin == BIN_G8 ? 32
                            : bin == BIN_G4 ? 64 : kWG) * a.tile;
     const long long i0 = lb * rpb;
     const long long i1 = min(i0 + rpb, a.bin_count[bin]) - 1;
@@ -521,16 +529,12 @@ __global__ void __launch_bounds__(kWG) fill_ones(void* x, long long n, int fp32)
   else reinterpret_cast<double*>(x)[i] = 1.0;
 }
 
-// Per graph outputs: caller ids (local), bounds, and the largest upper bound
-// outside the graph's top-k.  Block g handles graph g.
-__global__ void __launch_bounds__(kWG) batch_write(const GraphSel* gsel, int32_t* const* out_ids,
-                                                   double* const* out_lo, double* const* out_up,
-                                                   uint8_t* mark, double* rest) {
-  const GraphSel& gs = gsel[blockIdx.x];
+// The bound factors of the graph's final iteration.
+__device__ BoundArgs final_bounds(const GraphSel& gs) {
   const int r = gs.sc->iterations;
   BoundArgs b = gs.b;
   b.r = r;
-  b.x = gs.xbuf[r & 1];
+  b.x = (r & 1) ? gs.xbuf[1] : gs.xbuf[0];
   if (b.fp32) {
     const double u64 = 0x1p-53;
     const double kap = (2.0 * r + 32.0) * u64;
@@ -542,6 +546,14 @@ __global__ void __launch_bounds__(kWG) batch_write(const GraphSel* gsel, int32_t
     b.f_lo_s = b.undirected ? b.alpha * (1.0 - ep) * (1.0 - kap) * (1.0 - 8.0 * u64) : 0.0;
     b.f_hi_s = b.beta * (1.0 + ep) * (1.0 + kap) * (1.0 + 8.0 * u64);
   }
+  return b;
+}
+
+// Per graph outputs: caller ids (local) and bounds of the ranked nodes, which
+// are also marked for batch_rest.  Block g handles graph g.
+__global__ void __launch_bounds__(kWG) batch_write(const GraphSel* gsel, int32_t* const* out_ids,
+                                                   double* const* out_lo, double* const* out_up, uint8_t* mark) {
+  const GraphSel& gs = gsel[blockIdx.x];
   for (int i = threadIdx.x; i < gs.k; i += kWG) {
     const int v = gs.top_sorted[i];
     mark[v] = 1;
@@ -549,10 +561,18 @@ __global__ void __launch_bounds__(kWG) batch_write(const GraphSel* gsel, int32_t
     out_lo[blockIdx.x][i] = gs.top_lo[i];
     out_up[blockIdx.x][i] = gs.top_up[i];
   }
-  __syncthreads();
+}
+
+// The largest upper bound outside each graph's top-k: blockIdx.y is the graph,
+// blockIdx.x a slice of its nodes; rest_bits[g] collects the maxima (bit
+// patterns of non-negative doubles order like the values).
+__global__ void __launch_bounds__(kWG) batch_rest(const GraphSel* gsel, const uint8_t* mark,
+                                                  unsigned long long* rest_bits) {
+  const GraphSel& gs = gsel[blockIdx.y];
+  const BoundArgs b = final_bounds(gs);
   double best = 0.0;
-  for (int i = threadIdx.x; i < gs.n; i += kWG) {
-    const int v = gs.base + i;
+  for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < gs.n; i += (long long)gridDim.x * kWG) {
+    const int v = gs.base + (int)i;
     if (mark[v]) continue;
     double lo, up;
     bound_eval(b, v, lo, up);
@@ -562,7 +582,10 @@ __global__ void __launch_bounds__(kWG) batch_write(const GraphSel* gsel, int32_t
   for (int o = 32; o >= 1; o >>= 1) best = fmax(best, __shfl_xor(best, o));
   if (lane_id() == 0) wm[threadIdx.x / kWave] = best;
   __syncthreads();
-  if (threadIdx.x == 0) rest[blockIdx.x] = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
+    if (m > 0.0) atomicMax(&rest_bits[blockIdx.y], (unsigned long long)__double_as_longlong(m));
+  }
 }
 
 }  // namespace
@@ -578,7 +601,7 @@ hipError_t launch_batch_prep(const long long* gbase, const void* const* grp, con
   hipLaunchKernelGGL(fill_gid, dim3(nb), dim3(kWG), 0, s, gbase, count, total_n, gid_of);
   hipLaunchKernelGGL(batch_csr_ends, dim3((count + 255) / 256), dim3(256), 0, s, grp, grp64, gbase, gnnz, count, sc);
   if (validate && max_nnz > 0) {
-    const unsigned gx = (unsigned)std::min<long long>(64, (max_nnz + kWG - 1) / kWG);
+    const unsigned gx = (unsigned)std::min<long long>(256, (max_nnz + kWG * 16 - 1) / (kWG * 16));
     hipLaunchKernelGGL(batch_col_range, dim3(gx, count), dim3(kWG), 0, s, gcol, gnnz, gbase, sc);
   }
   const BatchRows rows{gid_of, gbase, grp, grp64, gnnz};
@@ -653,9 +676,12 @@ hipError_t launch_batch_live_items(const BatchWalk& a, long long total_blocks, i
   return hipGetLastError();
 }
 
-hipError_t launch_batch_write(const GraphSel* gsel, int count, int32_t* const* out_ids, double* const* out_lo,
-                              double* const* out_up, uint8_t* mark, double* rest, hipStream_t s) {
-  hipLaunchKernelGGL(batch_write, dim3(count), dim3(kWG), 0, s, gsel, out_ids, out_lo, out_up, mark, rest);
+hipError_t launch_batch_write(const GraphSel* gsel, int count, long long max_n, int32_t* const* out_ids,
+                              double* const* out_lo, double* const* out_up, uint8_t* mark,
+                              unsigned long long* rest_bits, hipStream_t s) {
+  hipLaunchKernelGGL(batch_write, dim3(count), dim3(kWG), 0, s, gsel, out_ids, out_lo, out_up, mark);
+  const unsigned bx = (unsigned)std::max<long long>(1, std::min<long long>(64, (max_n + 4095) / 4096));
+  hipLaunchKernelGGL(batch_rest, dim3(bx, count), dim3(kWG), 0, s, gsel, (const uint8_t*)mark, rest_bits);
   return hipGetLastError();
 }
 

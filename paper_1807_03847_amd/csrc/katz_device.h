@@ -16,6 +16,7 @@ __host__ __device__ constexpr int bin_of_len(long long len) {
        : len <= 8 ? BIN_G8
        : len <= 16 ? BIN_G16
        : len <= 32 ? BIN_G32
+       : len <= kShortRowMax ? BIN_W16
        : len <= kWaveRowMax ? BIN_W64
        : len <= kBlockRowMax ? BIN_B256
        : BIN_HUGE;

@@ -32,6 +32,7 @@ constexpr int kWave = 64;
 constexpr int kPerLane = 16;             // max row elements summed serially per lane
 constexpr int kSeg = kWG * kPerLane;     // arcs per huge-row segment (4096)
 constexpr int kWaveRowMax = kWave * kPerLane;   // 1024
+constexpr int kShortRowMax = 128;               // 16 lanes x 8 elements
 constexpr int kBlockRowMax = kSeg;              // 4096
 constexpr int kDigitBits = 12;
 constexpr int kDigits = 1 << kDigitBits;        // histogram bins per radix digit
@@ -43,7 +44,8 @@ constexpr int kSmallCand = 16384;               // finish directly below this ma
 enum BinId : int {
   BIN_HUGE = 0,   // len > 4096: segmented, multi-workgroup
   BIN_B256,       // 1025..4096: one workgroup per row
-  BIN_W64,        // 33..1024: one wave per row
+  BIN_W64,        // 129..1024: one wave per row
+  BIN_W16,        // 33..128: 16 lanes per row
   BIN_G32,        // 17..32: 32 lanes per row
   BIN_G16,        // 9..16
   BIN_G8,         // 5..8
@@ -64,6 +66,13 @@ struct SegDesc {
   int32_t part;   // index of this segment's partial sum
   int32_t hrow;   // index of the owning row in the huge-row table
   int32_t pad;
+};
+
+// Renumbering table, indexed by caller id: the node's internal id and its row
+// length (the length gives x_1 of the node, as the first walk step sums ones).
+struct IdLen {
+  int32_t id;
+  int32_t len;
 };
 
 struct HugeRow {
@@ -96,6 +105,12 @@ struct RunScalars {
   long long bin_count[NUM_BINS];
   long long bin_base[NUM_BINS];
   long long seg_total;
+  // Walk step 2 of a renumbered run found a caller column id out of range.
+  // Kept apart from err while that kernel runs: every wave of a walk kernel
+  // reads err once to decide whether to skip its work, and the waves of one
+  // workgroup must decide alike (they meet at barriers).  fold_col_err copies
+  // it into err after the launch.
+  int col_err;
 };
 
 // Bound evaluation parameters of one iteration.
@@ -145,6 +160,14 @@ struct IterArgs {
   int hub_n;                     // walk entries 0 .. hub_n - 1 are read from an LDS copy
   double alpha;
   double etap;                   // eta'_r
+  // Walk step 2 fused with the internal renumbering (walk_step<F32, true>):
+  // each row's caller column ids (col_src + coff[row]) are renamed through
+  // pmap and written to col (at desc.off), and a gathered neighbour's x_1 is
+  // computed from its length in pmap instead of being read from x_in.
+  const int32_t* col_src;
+  const long long* coff;         // internal id -> offset of its row in col_src
+  const IdLen* pmap;             // caller id -> {internal id, row length}
+  int32_t* ncol;                 // renamed column ids (written)
 };
 
 struct SelArgs {
@@ -245,8 +268,10 @@ hipError_t launch_validate_strict(const RowDesc* desc, long long n, const int32_
                                   long long* row_off, int* row_len, RunScalars* sc, hipStream_t s);
 hipError_t launch_walk_first(const IterArgs& a, int fp32, long long n, long long nnz, int validate,
                              hipStream_t s);
+// renumber: walk step 2 fused with the renaming of the column ids (the
+// IterArgs renumbering fields must be set and hub_n must be 0).
 hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, long long max_grid,
-                            long long* grid_used, hipStream_t s);
+                            long long* grid_used, hipStream_t s, bool renumber = false);
 // Reduces the per-workgroup maxima of walk iteration r into xmax32[r] / xmax64[r].
 hipError_t launch_reduce_blkmax(const void* blkmax, long long nb, int fp32, unsigned* xmax32,
                                 unsigned long long* xmax64, int r, const RunScalars* sc, hipStream_t s);
@@ -297,10 +322,9 @@ hipError_t launch_c_from_history(const int32_t* rows, long long count, double* c
 hipError_t launch_max_of_vector(const double* x, long long n, unsigned long long* out, hipStream_t s);
 
 hipError_t launch_reset_flags(RunScalars* sc, hipStream_t s);
-hipError_t launch_relabel(const RowDesc* desc, long long n, const long long* bin_base, const long long* bin_count,
-                          const SegDesc* segs, long long seg_total, const int32_t* col, int32_t* ext_of,
-                          int32_t* int_of, long long* len_ll, int* len32, long long* noff, long long* sums,
-                          long long* total, int32_t* ncol, RunScalars* sc, hipStream_t s);
+hipError_t launch_relabel(const RowDesc* desc, long long n, int32_t* ext_of, int32_t* int_of, long long* coff,
+                          IdLen* pmap, long long* len_ll, int* len32, long long* noff, long long* sums,
+                          long long* total, hipStream_t s);
 hipError_t launch_gather_int(const int32_t* rows, long long t, const int* src, int* out, hipStream_t s);
 hipError_t launch_gather_ll(const int32_t* rows, long long t, const long long* src, long long* out, hipStream_t s);
 hipError_t launch_min_lower_active(const BoundArgs& b, const int32_t* act, const int* m_ptr,
@@ -328,8 +352,9 @@ constexpr int kBatchMaxLdsGraphs = 8192;   // per-graph maxima reduced in LDS up
 hipError_t launch_batch_advance(int* r_dev, int count, RunScalars* gsc, const unsigned* gxmax32, double* gsigma,
                                 double* gsigsum, int* gexp, const double* galpha, const int* gclog2, int stride,
                                 int fp32, int* ndone, int* n_items, hipStream_t s);
-hipError_t launch_batch_write(const GraphSel* gsel, int count, int32_t* const* out_ids, double* const* out_lo,
-                              double* const* out_up, uint8_t* mark, double* rest, hipStream_t s);
+hipError_t launch_batch_write(const GraphSel* gsel, int count, long long max_n, int32_t* const* out_ids,
+                              double* const* out_lo, double* const* out_up, uint8_t* mark,
+                              unsigned long long* rest_bits, hipStream_t s);
 
 int bin_of_host(int64_t len);
 

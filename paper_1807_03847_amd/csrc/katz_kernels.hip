@@ -154,20 +154,35 @@ struct Epi {
 
 // Per-iteration scale of the FP32 form: x~_r = T * 2^-e_r with 2^e_r above
 // deg_max * max(x~_{r-1}), so max x~_r < 1; sigma_r = alpha sigma_{r-1} 2^e_r.
+// At r = 1 the previous vector is all ones (max 1).
 template <bool F32>
-__device__ __forceinline__ Epi<F32> compute_epi(const IterArgs& a) {
+__device__ __forceinline__ Epi<F32> compute_epi_at(const IterArgs& a, int r) {
   Epi<F32> ep{1.0, 0};
   if constexpr (F32) {
-    const float M = (a.r == 1) ? 1.0f : __uint_as_float(a.xmax32[a.r - 1]);
+    const float M = (r == 1) ? 1.0f : __uint_as_float(a.xmax32[r - 1]);
     int ex = 0;
     if (M > 0.0f) {
       (void)frexpf(M, &ex);
       ex += a.clog2_dmax;
     }
     ep.e_r = ex;
-    ep.sigma_r = ldexp(a.alpha * a.sigma[a.r - 1], ex);
+    ep.sigma_r = ldexp(a.alpha * a.sigma[r - 1], ex);
   }
   return ep;
+}
+
+template <bool F32>
+__device__ __forceinline__ Epi<F32> compute_epi(const IterArgs& a) {
+  return compute_epi_at<F32>(a, a.r);
+}
+
+// The stored walk entry of a row whose sum is t: s = alpha t (FP64 form) or
+// x~ = t 2^-e_r (FP32 form).
+template <bool F32>
+__device__ __forceinline__ typename Prec<F32>::T x_entry(const IterArgs& a, const Epi<F32>& ep,
+                                                         typename Prec<F32>::T t) {
+  if constexpr (F32) return ldexpf(t, -ep.e_r);
+  else return a.alpha * t;
 }
 
 // The row's previous c (and FP32 margin e), loaded as soon as the row id is
@@ -191,13 +206,13 @@ template <bool F32>
 __device__ __forceinline__ void epilogue(const IterArgs& a, const Epi<F32>& ep, int row,
                                          typename Prec<F32>::T t, double& vmax, const Prev& pv) {
   if constexpr (!F32) {
-    const double s = a.alpha * t;
+    const double s = x_entry<F32>(a, ep, t);
     reinterpret_cast<double*>(a.x_out)[row] = s;
     if (a.rewalk) return;
     a.c[row] = (a.r == 1) ? s : pv.c + s;
     vmax = fmax(vmax, s);
   } else {
-    const float xs = ldexpf(t, -ep.e_r);
+    const float xs = x_entry<F32>(a, ep, t);
     reinterpret_cast<float*>(a.x_out)[row] = xs;
     const double s = ep.sigma_r * (double)xs;
     const double e_prev = (a.r == 1) ? 0.0 : (double)pv.e;
@@ -207,6 +222,14 @@ __device__ __forceinline__ void epilogue(const IterArgs& a, const Epi<F32>& ep, 
   }
 }
 
+// Where one stretch of a row reads its column ids and, in walk step 2 fused
+// with the renumbering, where it writes the renamed ids.
+struct Stretch {
+  const int32_t* src;
+  int32_t* dst;        // renumbering only
+  int len;
+};
+
 // Strided row sum over G lanes: lane l adds elements l, l+G, l+2G, ... in
 // order.  Loads are issued eight at a time (eight column ids, then eight
 // gathers) so a lane keeps eight requests in flight; slots past the row end
@@ -215,34 +238,73 @@ __device__ __forceinline__ void epilogue(const IterArgs& a, const Epi<F32>& ep, 
 // internal renumbering these are the longest rows, i.e. the most-referenced
 // nodes); the copy is exact, so the sum does not depend on where an entry
 // was read.
+//
+// Renumber (walk step 2 of a renumbered static run): the column ids are the
+// caller's; each is range-checked (an id outside 0..n-1 sets sc->col_err and
+// adds zero, it is never used as an index), renamed through pmap and written
+// out, and the neighbour's x_1 is formed from its length exactly as the first
+// walk step stored it.  The values added, and their order, are those of the
+// unfused step on the renamed columns, so the sum is bitwise the same.
 constexpr int kBatch = 8;
 
-template <bool F32, int G>
+template <bool F32, int G, bool Renumber>
 __device__ __forceinline__ typename Prec<F32>::T strided_sum(const IterArgs& a, const typename Prec<F32>::T* hub,
-                                                             const int32_t* cp, int len, int lane) {
+                                                             const Stretch& st, int lane, const Epi<F32>& ep1) {
   using T = typename Prec<F32>::T;
   const T* x = reinterpret_cast<const T*>(a.x_in);
   const int H = a.hub_n;
+  const int len = st.len;
+  // Loads in flight per lane; the elements a lane adds, and their order, do
+  // not depend on it (the FP64 renumbering step uses four to avoid spills).
+  constexpr int NB = (Renumber && !F32) ? 4 : kBatch;
   T sum = 0;
-  for (int j0 = lane; j0 < len; j0 += kBatch * G) {
-    int32_t c[kBatch];
+  bool bad = false;
+  for (int j0 = lane; j0 < len; j0 += NB * G) {
+    int32_t c[NB];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
+    for (int u = 0; u < NB; ++u) {
       const int j = j0 + u * G;
-      c[u] = j < len ? cp[j] : -1;
+      int32_t cc = j < len ? st.src[j] : -1;
+      if constexpr (Renumber) {
+        if (j < len && (unsigned)cc >= (unsigned)a.n) {
+          bad = true;
+          cc = -1;
+        }
+      }
+      c[u] = cc;
     }
-    T v[kBatch];
+    if constexpr (Renumber) {
+      IdLen m[NB];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) v[u] = c[u] < 0 ? (T)0 : (c[u] < H ? hub[c[u]] : x[c[u]]);
+      for (int u = 0; u < NB; ++u) m[u] = c[u] < 0 ? IdLen{0, 0} : a.pmap[c[u]];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) sum += v[u];
+      for (int u = 0; u < NB; ++u) {
+        const int j = j0 + u * G;
+        if (j < len) st.dst[j] = m[u].id;
+        sum += c[u] < 0 ? (T)0 : x_entry<F32>(a, ep1, (T)m[u].len);
+      }
+    } else {
+      T v[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) v[u] = c[u] < 0 ? (T)0 : (c[u] < H ? hub[c[u]] : x[c[u]]);
+#pragma unroll
+      for (int u = 0; u < NB; ++u) sum += v[u];
+    }
   }
+  if (Renumber && bad) atomicOr(&a.sc->col_err, 1);
   return sum;
 }
 
-template <bool F32, int G>
+// The stretch of a whole row (desc.off indexes the walk's column array).
+template <bool Renumber>
+__device__ __forceinline__ Stretch row_stretch(const IterArgs& a, const RowDesc& d, bool valid) {
+  if constexpr (Renumber) return Stretch{a.col_src + (valid ? a.coff[d.row] : 0), a.ncol + d.off, d.len};
+  else return Stretch{a.col + d.off, nullptr, d.len};
+}
+
+template <bool F32, int G, bool Renumber>
 __device__ __forceinline__ void rows_group(const IterArgs& a, const typename Prec<F32>::T* hub, const Epi<F32>& ep,
-                                           long long lb, int bin, double& vmax, bool stop) {
+                                           const Epi<F32>& ep1, long long lb, int bin, double& vmax, bool stop) {
   using T = typename Prec<F32>::T;
   constexpr int RPB = kWG / G;
   const int lane = threadIdx.x & (G - 1);
@@ -253,7 +315,7 @@ __device__ __forceinline__ void rows_group(const IterArgs& a, const typename Pre
   Prev pv{0.0, 0.0f};
   if (valid && lane == 0) pv = load_prev<F32>(a, d.row);
   if (stop) return;
-  T sum = strided_sum<F32, G>(a, hub, a.col + d.off, d.len, lane);
+  T sum = strided_sum<F32, G, Renumber>(a, hub, row_stretch<Renumber>(a, d, valid), lane, ep1);
 #pragma unroll
   for (int o = G / 2; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, G);
   if (valid && lane == 0) epilogue<F32>(a, ep, d.row, sum, vmax, pv);
@@ -261,12 +323,12 @@ __device__ __forceinline__ void rows_group(const IterArgs& a, const typename Pre
 
 // Whole-workgroup sum of one row or segment: 256 strided lanes, wave
 // butterflies, then the four wave sums as (w0 + w1) + (w2 + w3).
-template <bool F32>
+template <bool F32, bool Renumber>
 __device__ __forceinline__ typename Prec<F32>::T block_sum(const IterArgs& a, const typename Prec<F32>::T* hub,
-                                                           const int32_t* cp, int len) {
+                                                           const Stretch& st, const Epi<F32>& ep1) {
   using T = typename Prec<F32>::T;
   __shared__ T part[kWG / kWave];
-  T sum = strided_sum<F32, kWG>(a, hub, cp, len, threadIdx.x);
+  T sum = strided_sum<F32, kWG, Renumber>(a, hub, st, threadIdx.x, ep1);
   for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
   if (lane_id() == 0) part[threadIdx.x / kWave] = sum;
   __syncthreads();
@@ -322,8 +384,9 @@ __global__ void __launch_bounds__(kWG) check_col_range(const int32_t* col, long 
 // Walk step r >= 2: every bin in one launch, heavy bins first.  The grid may
 // be smaller than the work: workgroup b takes work items b, b + gridDim.x, ...
 // (a persistent grid, which is what makes the LDS copy of the first a.hub_n
-// walk entries worth its fill).
-template <bool F32>
+// walk entries worth its fill).  Renumber: step 2 of a renumbered static run,
+// which also writes the renamed column ids (see strided_sum).
+template <bool F32, bool Renumber>
 __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
   using T = typename Prec<F32>::T;
   // The stop flag (a launch enqueued ahead of the host's flag read skips its
@@ -334,9 +397,10 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
   // A persistent grid visits many work items per workgroup: stop at once.
   if (stop && (long long)gridDim.x < total) return;
   const Epi<F32> ep = compute_epi<F32>(a);
+  const Epi<F32> ep1 = Renumber ? compute_epi_at<F32>(a, 1) : ep;
   extern __shared__ __align__(16) unsigned char walk_lds[];
   T* hub = reinterpret_cast<T*>(walk_lds);
-  if (a.hub_n > 0) {
+  if (!Renumber && a.hub_n > 0) {
     const T* x = reinterpret_cast<const T*>(a.x_in);
     if (!stop)
       for (int i = threadIdx.x; i < a.hub_n; i += kWG) hub[i] = x[i];
@@ -358,8 +422,14 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
         // One 4096-arc segment of a long row: its partial sum only; huge_combine
         // adds the partials of each row in segment order after this launch.
         const SegDesc sd = a.segs[lb];
+        Stretch st{a.col + sd.off, nullptr, sd.len};
+        if constexpr (Renumber) {
+          const HugeRow h = a.huge[sd.hrow];
+          st.src = a.col_src + a.coff[h.row] + (long long)(sd.part - h.part0) * kSeg;
+          st.dst = a.ncol + sd.off;
+        }
         if (stop) break;
-        const T tot = block_sum<F32>(a, hub, a.col + sd.off, sd.len);
+        const T tot = block_sum<F32, Renumber>(a, hub, st, ep1);
         if (threadIdx.x == 0) reinterpret_cast<T*>(a.partial)[sd.part] = tot;
         break;
       }
@@ -367,16 +437,18 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
         const RowDesc d = a.desc[a.bin_base[BIN_B256] + lb];
         Prev pv{0.0, 0.0f};
         if (threadIdx.x == 0) pv = load_prev<F32>(a, d.row);
+        const Stretch st = row_stretch<Renumber>(a, d, true);
         if (stop) break;
-        const T tot = block_sum<F32>(a, hub, a.col + d.off, d.len);
+        const T tot = block_sum<F32, Renumber>(a, hub, st, ep1);
         if (threadIdx.x == 0) epilogue<F32>(a, ep, d.row, tot, vmax, pv);
         break;
       }
-      case BIN_W64: rows_group<F32, 64>(a, hub, ep, lb, BIN_W64, vmax, stop); break;
-      case BIN_G32: rows_group<F32, 32>(a, hub, ep, lb, BIN_G32, vmax, stop); break;
-      case BIN_G16: rows_group<F32, 16>(a, hub, ep, lb, BIN_G16, vmax, stop); break;
-      case BIN_G8: rows_group<F32, 8>(a, hub, ep, lb, BIN_G8, vmax, stop); break;
-      case BIN_G4: rows_group<F32, 4>(a, hub, ep, lb, BIN_G4, vmax, stop); break;
+      case BIN_W64: rows_group<F32, 64, Renumber>(a, hub, ep, ep1, lb, BIN_W64, vmax, stop); break;
+      case BIN_W16: rows_group<F32, 16, Renumber>(a, hub, ep, ep1, lb, BIN_W16, vmax, stop); break;
+      case BIN_G32: rows_group<F32, 32, Renumber>(a, hub, ep, ep1, lb, BIN_G32, vmax, stop); break;
+      case BIN_G16: rows_group<F32, 16, Renumber>(a, hub, ep, ep1, lb, BIN_G16, vmax, stop); break;
+      case BIN_G8: rows_group<F32, 8, Renumber>(a, hub, ep, ep1, lb, BIN_G8, vmax, stop); break;
+      case BIN_G4: rows_group<F32, 4, Renumber>(a, hub, ep, ep1, lb, BIN_G4, vmax, stop); break;
       case BIN_EMPTY: {
         // Only at r = 2: the buffer of x_2 was never written for empty rows.
         const long long i = lb * kWG + threadIdx.x;
@@ -832,85 +904,22 @@ __global__ void init_run(RunScalars* sc, long long n, double* sigma, double* sig
 // Internal renumbering: new id i = position of the row in the binned order
 // (degree classes, longest first).  ext_of[i] is the caller's id of new node i.
 __global__ void __launch_bounds__(kWG) relabel_ids(const RowDesc* desc, long long n, int32_t* ext_of,
-                                                   int32_t* int_of, long long* len_ll, int* len32) {
+                                                   int32_t* int_of, long long* coff, IdLen* pmap, long long* len_ll,
+                                                   int* len32) {
   const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
   if (i >= n) return;
   const RowDesc d = desc[i];
   ext_of[i] = d.row;
   int_of[d.row] = (int32_t)i;
+  coff[i] = d.off;
+  pmap[d.row] = IdLen{(int32_t)i, d.len};
   len_ll[i] = d.len;
   len32[i] = d.len;
 }
 
-// Column ids of one stretch of a row, renamed: arcs in their original order,
-// 0 <= col < n checked on the way (an id out of range sets sc->err = 1 and is
-// never used as an index).
-template <int G>
-__device__ __forceinline__ bool remap_stretch(const int32_t* cp, int len, int lane, long long n,
-                                              const int32_t* int_of, int32_t* out) {
-  bool bad = false;
-  for (int j0 = lane; j0 < len; j0 += kBatch * G) {
-    int32_t c[kBatch];
-    bool in[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int j = j0 + u * G;
-      in[u] = j < len;
-      c[u] = in[u] ? cp[j] : 0;
-      if (in[u] && (unsigned long long)(unsigned)c[u] >= (unsigned long long)n) {
-        bad = true;
-        in[u] = false;
-      }
-    }
-    int32_t m[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) m[u] = in[u] ? int_of[c[u]] : 0;
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int j = j0 + u * G;
-      if (j < len) out[j] = m[u];
-    }
-  }
-  return bad;
-}
-
-// G lanes per new row (the row's bin decides G).  Rows of one bin are new ids
-// first .. first+count-1.
-template <int G>
-__global__ void __launch_bounds__(kWG) remap_rows(const RowDesc* desc, long long first, long long count,
-                                                  const int32_t* col, const int32_t* int_of, const long long* noff,
-                                                  int32_t* ncol, long long n, RunScalars* sc) {
-  constexpr int RPB = kWG / G;
-  const long long i = first + (long long)blockIdx.x * RPB + threadIdx.x / G;
-  bool bad = false;
-  if (i < first + count) {
-    const RowDesc d = desc[i];
-    bad = remap_stretch<G>(col + d.off, d.len, threadIdx.x & (G - 1), n, int_of, ncol + noff[i]);
-  }
-  if (__ballot(bad) && lane_id() == 0) atomicOr(&sc->err, 1);
-}
-
-// Rows longer than one segment: one workgroup per 4096-arc segment (the
-// segments of the first binning), so the longest rows do not serialise.
-__global__ void __launch_bounds__(kWG) remap_segments(const RowDesc* desc, long long huge_base, const SegDesc* segs,
-                                                      const int32_t* col, const int32_t* int_of,
-                                                      const long long* noff, int32_t* ncol, long long n,
-                                                      RunScalars* sc) {
-  const SegDesc sd = segs[blockIdx.x];
-  const long long i = huge_base + sd.hrow;           // new id of the segment's row
-  const long long dst = noff[i] + (sd.off - desc[i].off);
-  const bool bad = remap_stretch<kWG>(col + sd.off, sd.len, threadIdx.x, n, int_of, ncol + dst);
-  if (__ballot(bad) && lane_id() == 0) atomicOr(&sc->err, 1);
-}
-
-template <int G>
-void launch_remap_bin(const RowDesc* desc, long long first, long long count, const int32_t* col,
-                      const int32_t* int_of, const long long* noff, int32_t* ncol, long long n, RunScalars* sc,
-                      hipStream_t s) {
-  if (count <= 0) return;
-  constexpr int RPB = kWG / G;
-  const unsigned nb = (unsigned)((count + RPB - 1) / RPB);
-  hipLaunchKernelGGL(remap_rows<G>, dim3(nb), dim3(kWG), 0, s, desc, first, count, col, int_of, noff, ncol, n, sc);
+// After walk step 2 of a renumbered run: a bad column id fails the run.
+__global__ void fold_col_err(RunScalars* sc) {
+  if (sc->col_err) sc->err = 1;
 }
 
 __global__ void reset_flags(RunScalars* sc) {
@@ -923,32 +932,21 @@ __global__ void reset_flags(RunScalars* sc) {
   sc->cand_count[0] = 0;
   sc->cand_count[1] = 0;
   sc->dmax = 0;
+  sc->col_err = 0;
 }
 
 }  // namespace
 
-// Renumbering: new id i = position of row i in the binned order; renamed
-// columns in ncol (column ids are range-checked here, sc->err = 1 if not).
-hipError_t launch_relabel(const RowDesc* desc, long long n, const long long* bin_base, const long long* bin_count,
-                          const SegDesc* segs, long long seg_total, const int32_t* col, int32_t* ext_of,
-                          int32_t* int_of, long long* len_ll, int* len32, long long* noff, long long* sums,
-                          long long* total, int32_t* ncol, RunScalars* sc, hipStream_t s) {
+// Renumbering: new id i = position of row i in the binned order, the tables
+// of both directions, and the offsets of the renumbered rows (noff, an
+// exclusive scan of the lengths).  The renamed column ids are written by walk
+// step 2 (walk_step<F32, true>), which reads every column id anyway.
+hipError_t launch_relabel(const RowDesc* desc, long long n, int32_t* ext_of, int32_t* int_of, long long* coff,
+                          IdLen* pmap, long long* len_ll, int* len32, long long* noff, long long* sums,
+                          long long* total, hipStream_t s) {
   const unsigned nb = (unsigned)std::max<long long>(1, (n + kWG - 1) / kWG);
-  hipLaunchKernelGGL(relabel_ids, dim3(nb), dim3(kWG), 0, s, desc, n, ext_of, int_of, len_ll, len32);
-  const hipError_t e = launch_scan_ll(len_ll, n, noff, sums, total, s);
-  if (e != hipSuccess) return e;
-  const int32_t* io = int_of;
-  const long long* no = noff;
-  if (seg_total > 0)
-    hipLaunchKernelGGL(remap_segments, dim3((unsigned)seg_total), dim3(kWG), 0, s, desc, bin_base[BIN_HUGE], segs, col,
-                       io, no, ncol, n, sc);
-  launch_remap_bin<kWG>(desc, bin_base[BIN_B256], bin_count[BIN_B256], col, io, no, ncol, n, sc, s);
-  launch_remap_bin<64>(desc, bin_base[BIN_W64], bin_count[BIN_W64], col, io, no, ncol, n, sc, s);
-  launch_remap_bin<32>(desc, bin_base[BIN_G32], bin_count[BIN_G32], col, io, no, ncol, n, sc, s);
-  launch_remap_bin<16>(desc, bin_base[BIN_G16], bin_count[BIN_G16], col, io, no, ncol, n, sc, s);
-  launch_remap_bin<8>(desc, bin_base[BIN_G8], bin_count[BIN_G8], col, io, no, ncol, n, sc, s);
-  launch_remap_bin<4>(desc, bin_base[BIN_G4], bin_count[BIN_G4], col, io, no, ncol, n, sc, s);
-  return hipGetLastError();
+  hipLaunchKernelGGL(relabel_ids, dim3(nb), dim3(kWG), 0, s, desc, n, ext_of, int_of, coff, pmap, len_ll, len32);
+  return launch_scan_ll(len_ll, n, noff, sums, total, s);
 }
 
 hipError_t launch_reset_flags(RunScalars* sc, hipStream_t s) {
@@ -1059,13 +1057,20 @@ hipError_t launch_reduce_blkmax(const void* blkmax, long long nb, int fp32, unsi
 // walk_step, then huge_combine when there are rows longer than one segment.
 // *blocks_used: workgroup maxima written to a.blkmax (both launches).
 hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, long long max_grid,
-                            long long* blocks_used, hipStream_t s) {
+                            long long* blocks_used, hipStream_t s, bool renumber) {
   long long g = total_blocks > 0 ? total_blocks : 1;
   if (max_grid > 0) g = std::min(g, max_grid);
   const size_t lds = (size_t)a.hub_n * (fp32 ? sizeof(float) : sizeof(double));
   if (a.hub_n > 0 && max_grid <= 0) return hipErrorInvalidValue;   // the copy pays only on a persistent grid
-  if (fp32) hipLaunchKernelGGL(walk_step<true>, dim3((unsigned)g), dim3(kWG), lds, s, a);
-  else hipLaunchKernelGGL(walk_step<false>, dim3((unsigned)g), dim3(kWG), lds, s, a);
+  // col_src may be null for a graph without arcs.
+  if (renumber && (a.hub_n > 0 || !a.coff || !a.pmap || !a.ncol || a.r != 2)) return hipErrorInvalidValue;
+  if (renumber) {
+    if (fp32) hipLaunchKernelGGL((walk_step<true, true>), dim3((unsigned)g), dim3(kWG), 0, s, a);
+    else hipLaunchKernelGGL((walk_step<false, true>), dim3((unsigned)g), dim3(kWG), 0, s, a);
+  } else {
+    if (fp32) hipLaunchKernelGGL((walk_step<true, false>), dim3((unsigned)g), dim3(kWG), lds, s, a);
+    else hipLaunchKernelGGL((walk_step<false, false>), dim3((unsigned)g), dim3(kWG), lds, s, a);
+  }
   long long used = g;
   const long long nh = a.bin_count[BIN_HUGE];
   if (nh > 0) {
@@ -1076,6 +1081,7 @@ hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks,
     else hipLaunchKernelGGL(huge_combine<false>, dim3((unsigned)cg), dim3(kWG), 0, s, c);
     used += cg;
   }
+  if (renumber) hipLaunchKernelGGL(fold_col_err, dim3(1), dim3(1), 0, s, a.sc);
   *blocks_used = used;
   return hipGetLastError();
 }

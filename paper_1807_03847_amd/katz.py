@@ -65,7 +65,8 @@ class KatzTiming(ctypes.Structure):
                 ("walk_first_ms", ctypes.c_double), ("walk_first_launches", ctypes.c_int64),
                 ("select_ms", ctypes.c_double), ("select_iterations", ctypes.c_int64),
                 ("prep_ms", ctypes.c_double), ("result_ms", ctypes.c_double),
-                ("call_ms", ctypes.c_double), ("calls", ctypes.c_int64)]
+                ("call_ms", ctypes.c_double), ("calls", ctypes.c_int64),
+                ("renumber_step_ms", ctypes.c_double), ("renumber_step_launches", ctypes.c_int64)]
 
 
 def _load():

@@ -39,13 +39,14 @@ def test_struct_layout_matches_header():
 #include "katz.h"
 #define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
 int main(void) {
-  printf("katz_csr %zu\nkatz_params %zu\nkatz_result %zu\nkatz_tuning %zu\n", sizeof(katz_csr), sizeof(katz_params),
-         sizeof(katz_result), sizeof(katz_tuning));
+  printf("katz_csr %zu\nkatz_params %zu\nkatz_result %zu\nkatz_tuning %zu\nkatz_timing %zu\n", sizeof(katz_csr),
+         sizeof(katz_params), sizeof(katz_result), sizeof(katz_tuning), sizeof(katz_timing));
   F(katz_csr, col) F(katz_csr, row_ptr_64) F(katz_csr, undirected)
   F(katz_params, k) F(katz_params, precision) F(katz_params, validate) F(katz_params, flags) F(katz_params, degree_cap)
   F(katz_result, rest_upper_max) F(katz_result, active_final) F(katz_result, iterations) F(katz_result, status)
   F(katz_tuning, blocks_per_cu) F(katz_tuning, batch_blocks_per_cu) F(katz_tuning, batch_tile)
   F(katz_tuning, reserved)
+  F(katz_timing, prep_ms) F(katz_timing, calls) F(katz_timing, renumber_step_ms) F(katz_timing, renumber_step_launches)
   return 0;
 }
 '''
@@ -61,11 +62,12 @@ int main(void) {
     assert int(got["katz_params"]) == ctypes.sizeof(katz.KatzParams)
     assert int(got["katz_result"]) == ctypes.sizeof(katz.KatzResult)
     assert int(got["katz_tuning"]) == ctypes.sizeof(katz.KatzTuning)
+    assert int(got["katz_timing"]) == ctypes.sizeof(katz.KatzTiming)
     for key, val in got.items():
         if "." in key:
             struct, field = key.split(".")
             cls = {"katz_csr": katz.KatzCSR, "katz_params": katz.KatzParams, "katz_result": katz.KatzResult,
-                   "katz_tuning": katz.KatzTuning}[struct]
+                   "katz_tuning": katz.KatzTuning, "katz_timing": katz.KatzTiming}[struct]
             assert getattr(cls, field).offset == int(val), key
 
 

@@ -237,6 +237,16 @@ def test_errors():
         with pytest.raises(katz.KatzError) as e:
             katz.rank_static(*dev(rp, bad_col), 2, flags=flags, precision=prec)
         assert e.value.code == katz.E_CSR
+    # Runs that stop before walk step 2 (where a renumbered run renames, and
+    # checks, the column ids) are checked all the same.
+    bad_col = col.copy()
+    bad_col[7] = 10
+    for call in (lambda: katz.rank_static(*dev(rp, bad_col), 10),
+                 lambda: katz.bounds(*dev(rp, bad_col), 1),
+                 lambda: katz.rank_static(*dev(rp, bad_col), 2, max_iter=1)):
+        with pytest.raises(katz.KatzError) as e:
+            call()
+        assert e.value.code == katz.E_CSR
     big = sg.star_graph(9000)                       # a row longer than one segment
     bcol = big[1].copy()
     bcol[5000] = 9001 + 7
