@@ -226,8 +226,8 @@ def main():
     out["roofline"]["traffic"], out["roofline"]["traffic_note"] = measured_traffic(out["tuning"]["fp32"]["arg"])
     if args.tuning_sweep:
         sweep = []
-        for hub, bpc in [(0, 0), (0, 2), (0, 4), (0, 8), (0, 16), (16384, 2), (16384, 4), (16384, 8),
-                         (32768, 2), (32768, 4), (65536, 1), (65536, 2)]:
+        for hub, bpc in [(0, 0), (0, 4), (0, 8), (0, 16), (16384, 4), (16384, 8), (20416, 8), (24512, 6),
+                         (32704, 5), (32768, 4), (40896, 4), (54208, 3), (65536, 2)]:
             katz.tuning_set(hub, bpc)
             r_s, sec_s, tm_s = time_form(katz, torch, rp_t, col_t, "fp32", max(1, args.steps // 2), 1)
             walk_us = tm_s["walk_step_ms"] / max(tm_s["calls"] * (r_s.iterations - 2), 1) * 1e3

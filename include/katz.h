@@ -87,7 +87,13 @@ extern "C" {
                                  /* degree class (rows of similar length contiguous,    */
                                  /* high-degree nodes first) so the walk vector's most  */
                                  /* gathered entries share cache lines; results, ids    */
-                                 /* and tie order are the same either way.              */
+                                 /* and tie order are the same either way.  A batch     */
+                                 /* (count > 1) is renumbered graph by graph only when  */
+                                 /* some graph's walk vector is larger than 4 MiB (one  */
+                                 /* XCD's L2; smaller ones stay cached whatever the     */
+                                 /* order) or a graph sets KATZ_FLAG_REORDER; NO_REORDER */
+                                 /* on any graph of a batch turns it off.               */
+#define KATZ_FLAG_REORDER     2  /* renumber a batch even where its graphs are small.   */
 
 /* A graph in compressed sparse row form.  Row v lists the out-neighbours of v:
  * arcs v -> col[j] for row_ptr[v] <= j < row_ptr[v+1].  An undirected graph

@@ -1111,17 +1111,23 @@ constexpr int kItersPerGraph = 4;   // iterations captured in one hipGraph
 
 int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* out, hipStream_t s) {
   const int fp32 = p[0].precision == KATZ_FP32_MARGIN;
-  long long total_n = 0, total_nnz = 0, max_nnz = 0, max_n = 0, sum_k = 0;
+  long long total_n = 0, total_nnz = 0, max_n = 0, sum_k = 0;
   int max_iter = 1;
   for (int i = 0; i < count; ++i) {
     if ((p[i].precision == KATZ_FP32_MARGIN) != (fp32 != 0)) return KATZ_E_UNSUPPORTED;
     total_n += g[i].n;
     total_nnz += g[i].nnz;
-    max_nnz = std::max<long long>(max_nnz, g[i].nnz);
     max_n = std::max<long long>(max_n, g[i].n);
     sum_k += p[i].k;
     max_iter = std::max(max_iter, p[i].max_iter ? p[i].max_iter : 1000);
   }
+  // Renumbering pays where a walk vector outgrows one XCD's L2 (4 MiB).
+  bool reorder = false, no_reorder = false;
+  for (int i = 0; i < count; ++i) {
+    if (p[i].flags & KATZ_FLAG_NO_REORDER) no_reorder = true;
+    if ((p[i].flags & KATZ_FLAG_REORDER) || g[i].n * (fp32 ? 4 : 8) > (4ll << 20)) reorder = true;
+  }
+  if (no_reorder) reorder = false;
   if (total_n > INT32_MAX) return KATZ_E_UNSUPPORTED;
   const int stride = max_iter + 1;
   int dev = 0;
@@ -1142,6 +1148,14 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   Work w;
   RunScalars* gsc = nullptr;
   long long* gbase = nullptr;
+  long long* gabase = nullptr;   // arc bases: graph g's arcs are gabase[g] .. gabase[g+1]-1 of the batch
+  // Internal renumbering of the batch (unless a graph sets KATZ_FLAG_NO_REORDER).
+  long long *run_first = nullptr, *run_last = nullptr, *run_start = nullptr;
+  int32_t *ext_of = nullptr, *int_of = nullptr, *ncol = nullptr;
+  long long *coff = nullptr, *len_ll = nullptr, *noff = nullptr, *rsums = nullptr, *rtot = nullptr;
+  int* len32 = nullptr;
+  IdLen* pmap = nullptr;
+  const int32_t** gcol_walk = nullptr;   // column array of every graph as the walk reads it
   const void** grp = nullptr;
   int* grp64 = nullptr;
   long long* gnnz = nullptr;
@@ -1176,6 +1190,23 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     w.sc = ar.take<RunScalars>(1);
     gsc = ar.take<RunScalars>(count);
     gbase = ar.take<long long>(count + 1);
+    gabase = ar.take<long long>(count + 1);
+    gcol_walk = ar.take<const int32_t*>(count);
+    if (reorder) {
+      run_first = ar.take<long long>((size_t)count * NUM_BINS);
+      run_last = ar.take<long long>((size_t)count * NUM_BINS);
+      run_start = ar.take<long long>((size_t)count * NUM_BINS);
+      ext_of = ar.take<int32_t>(total_n);
+      int_of = ar.take<int32_t>(total_n);
+      coff = ar.take<long long>(total_n);
+      len_ll = ar.take<long long>(total_n);
+      noff = ar.take<long long>(total_n);
+      len32 = ar.take<int>(total_n);
+      pmap = ar.take<IdLen>(total_n);
+      ncol = ar.take<int32_t>(std::max<long long>(total_nnz, 1));
+      rsums = ar.take<long long>(scan_sums_capacity(total_n));
+      rtot = ar.take<long long>(2);
+    }
     grp = ar.take<const void*>(count);
     grp64 = ar.take<int>(count);
     gnnz = ar.take<long long>(count);
@@ -1246,12 +1277,13 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   T.call_begin(s);
   const int tp = T.start(T_PREP, s);
   // ---- per-graph tables ----
-  std::vector<long long> h_base(count + 1, 0), h_nnz(count);
+  std::vector<long long> h_base(count + 1, 0), h_abase(count + 1, 0), h_nnz(count);
   std::vector<const void*> h_rp(count);
   std::vector<const int32_t*> h_col(count);
   std::vector<int> h_rp64(count);
   for (int i = 0; i < count; ++i) {
     h_base[i + 1] = h_base[i] + g[i].n;
+    h_abase[i + 1] = h_abase[i] + g[i].nnz;
     h_nnz[i] = g[i].nnz;
     h_rp64[i] = g[i].row_ptr_64;
     h_rp[i] = rp_host[i] ? stage_rp[i] : g[i].row_ptr;
@@ -1264,6 +1296,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   }
   KATZ_HIP(hipMemcpyAsync(gbase, h_base.data(), sizeof(long long) * (count + 1), hipMemcpyHostToDevice, s));
   KATZ_HIP(hipMemcpyAsync(gnnz, h_nnz.data(), sizeof(long long) * count, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(gabase, h_abase.data(), sizeof(long long) * (count + 1), hipMemcpyHostToDevice, s));
   KATZ_HIP(hipMemcpyAsync(grp, h_rp.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
   KATZ_HIP(hipMemcpyAsync(grp64, h_rp64.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
   KATZ_HIP(hipMemcpyAsync(gcol, h_col.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
@@ -1271,15 +1304,34 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   KATZ_HIP(hipMemsetAsync(gdmax, 0, sizeof(int) * count, s));
   int validate = 0;
   for (int i = 0; i < count; ++i) validate = std::max(validate, p[i].validate);
-  KATZ_HIP(launch_batch_prep(gbase, grp, grp64, gnnz, gcol, count, total_n, max_nnz, gid_of, b.blk, b.nblocks,
-                             b.scan_sums, b.scan_totals, b.desc, b.segs, b.huge, w.sc, validate, s));
-  KATZ_HIP(launch_batch_dmax(b.desc, total_n, gid_of, gdmax, s));
+  KATZ_HIP(launch_batch_prep(gbase, grp, grp64, gnnz, gabase, gcol, count, total_n, total_nnz, gid_of, b.blk,
+                             b.nblocks, b.scan_sums, b.scan_totals, b.desc, b.segs, b.huge, w.sc, validate, s));
+  KATZ_HIP(launch_batch_dmax(grp, grp64, gbase, count, total_n, gdmax, s));
   std::vector<int> h_dmax(count);
   KATZ_HIP(hipMemcpyAsync(h_dmax.data(), gdmax, sizeof(int) * count, hipMemcpyDeviceToHost, s));
   KATZ_HIP(hipMemcpyAsync(ar.hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
   KATZ_HIP(hipStreamSynchronize(s));
   if (ar.hs.sc->err) return KATZ_E_CSR;
   b.read_back(*ar.hs.sc, total_n);
+  if (reorder && total_n > 0) {
+    // Rename every graph's nodes by its binned order, bin the renamed rows
+    // again, then write the renamed column ids (graph-local) into ncol.
+    KATZ_HIP(hipMemsetAsync(run_first, 0xFF, sizeof(long long) * (size_t)count * NUM_BINS, s));
+    KATZ_HIP(hipMemsetAsync(run_last, 0xFF, sizeof(long long) * (size_t)count * NUM_BINS, s));
+    KATZ_HIP(launch_batch_relabel(b.desc, total_n, gbase, count, w.sc, run_first, run_last, run_start, ext_of, int_of,
+                                  coff, pmap, len_ll, len32, noff, rsums, rtot, s));
+    KATZ_HIP(launch_prep_rows(nullptr, total_n, noff, len32, b.blk, b.nblocks, b.scan_sums, b.scan_totals, b.desc,
+                              b.segs, b.huge, w.sc, s));
+    KATZ_HIP(hipMemcpyAsync(ar.hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipStreamSynchronize(s));
+    if (ar.hs.sc->err) return ar.hs.sc->err == 1 ? KATZ_E_CSR : KATZ_E_HIP;
+    b.read_back(*ar.hs.sc, total_n);
+    KATZ_HIP(launch_batch_rename(b.desc, b.bin_base, b.bin_count, b.segs, b.seg_total, b.huge, noff, gid_of, gbase,
+                                 gcol, coff, pmap, ncol, s));
+  }
+  std::vector<const int32_t*> h_cw(count);
+  for (int i = 0; i < count; ++i) h_cw[i] = reorder ? ncol : h_col[i];
+  KATZ_HIP(hipMemcpyAsync(gcol_walk, h_cw.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
 
   // ---- per-graph scalars, selection views, initial state ----
   std::vector<Scalars> S(count);
@@ -1339,6 +1391,8 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     gs.xmax64 = gxmax64 + (size_t)i * stride;
     gs.base = (int)h_base[i];
     gs.n = (int)g[i].n;
+    gs.ext_of = reorder ? ext_of : nullptr;
+    gs.int_of = reorder ? int_of : nullptr;
     gs.k = p[i].k;
     gs.max_iter = p[i].max_iter ? p[i].max_iter : 1000;
     h_oids[i] = out_host ? st_ids + koff : out[i].topk_ids;
@@ -1392,7 +1446,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     bw.bin_count[i] = b.bin_count[i];
   }
   bw.gid_of = gid_of;
-  bw.gcol = gcol;
+  bw.gcol = gcol_walk;
   bw.gbase = gbase;
   bw.galpha = galpha;
   bw.gsc = gsc;
@@ -2130,7 +2184,11 @@ KATZ_EXPORT int katz_autotune(int32_t count, const katz_csr* g, const katz_param
     KATZ_TRY(katz::check_params(&p[i], g[i].n, true));
     sum_k += p[i].k;
   }
-  static const int kSingle[][2] = {{0, 0}, {0, 4}, {0, 8}, {0, 16}, {16384, 4}, {32768, 4}, {65536, 2}};
+  // Hub copies sized so that 3..8 workgroups fill the 160 KiB of LDS of a CU
+  // (with the kernel's own few bytes of static LDS).
+  static const int kSingle[][2] = {{0, 0},        {0, 4},        {0, 8},        {0, 16},      {16384, 4},
+                                   {20416, 8},    {24512, 6},    {32704, 5},    {32768, 4},   {40896, 4},
+                                   {54208, 3},    {65536, 2}};
   static const int kBatch[][2] = {{0, 1}, {4, 1}, {16, 1}, {4, 2}, {16, 2}, {4, 4}, {16, 4}, {16, 8}};
   const katz_tuning saved = katz::current_tuning();
   int32_t* ids = nullptr;

@@ -71,42 +71,73 @@ __global__ void batch_csr_ends(const void* const* grp, const int* grp64, const l
   if (a != 0 || b != gnnz[g]) atomicOr(&sc->err, 1);
 }
 
-// Column range per graph: blockIdx.y is the graph.
-__global__ void __launch_bounds__(kWG) batch_col_range(const int32_t* const* gcol, const long long* gnnz,
-                                                       const long long* gbase, RunScalars* sc) {
-  const int g = blockIdx.y;
-  const long long nnz = gnnz[g];
-  const long long n = gbase[g + 1] - gbase[g];
-  const int32_t* col = gcol[g];
+// The graphs' arcs, and rows, are numbered one after another (graph g's arcs
+// are gabase[g] .. gabase[g+1]-1 of the whole batch), and each workgroup takes
+// one fixed-size chunk of them, so big and small graphs cost alike per arc.
+// Largest g with base[g] <= i: the graph owning index i (empty graphs own none).
+__device__ __forceinline__ int owner_of(const long long* base, int count, long long i) {
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (base[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+constexpr int kColChunk = 16384;   // arcs per workgroup
+constexpr int kRowChunk = 4096;    // rows per workgroup
+
+// 0 <= col < n_g for every arc.
+__global__ void __launch_bounds__(kWG) batch_col_range(const int32_t* const* gcol, const long long* gabase,
+                                                       const long long* gbase, int count, RunScalars* sc) {
+  const long long a0 = (long long)blockIdx.x * kColChunk;
+  const long long a1 = min(a0 + kColChunk, gabase[count]);
   bool bad = false;
-  for (long long j = (long long)blockIdx.x * kWG + threadIdx.x; j < nnz; j += (long long)gridDim.x * kWG)
-    if ((unsigned)col[j] >= (unsigned long long)n) bad = true;
+  for (int g = owner_of(gabase, count, a0); g < count && gabase[g] < a1; ++g) {
+    const unsigned long long n = (unsigned long long)(gbase[g + 1] - gbase[g]);
+    const int32_t* col = gcol[g];
+    const long long s = max(a0, gabase[g]) - gabase[g];
+    const long long e = min(a1, gabase[g + 1]) - gabase[g];
+    for (long long j0 = s + threadIdx.x; j0 < e; j0 += 8 * kWG) {
+      int32_t c[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const long long j = j0 + (long long)u * kWG;
+        c[u] = j < e ? col[j] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if ((unsigned long long)(unsigned)c[u] >= n) bad = true;
+    }
+  }
   if (__ballot(bad) && lane_id() == 0) atomicOr(&sc->err, 1);
 }
 
-// Longest row of every graph.  A wave whose rows share one graph folds its
-// maximum with one atomic, and only when it exceeds the value it reads first:
-// stored values only grow, so any value read (stale or not) is at most the
-// current one and a skipped atomic never loses a maximum.
-__global__ void __launch_bounds__(kWG) batch_dmax(const RowDesc* desc, long long count, const int* gid_of,
-                                                  int* gdmax) {
-  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
-  int g = -1, len = 0;
-  if (i < count) {
-    const RowDesc d = desc[i];
-    g = gid_of[d.row];
-    len = d.len;
-  }
-  const int g0 = __shfl(g, 0);
-  const bool uniform = __all(g == g0 || g < 0);
-  if (uniform) {
-    int m = len;
+// Longest row of every graph: one atomic max per workgroup and graph met.
+__global__ void __launch_bounds__(kWG) batch_dmax(const void* const* grp, const int* grp64, const long long* gbase,
+                                                  int count, int* gdmax) {
+  __shared__ int wm[kWG / kWave];
+  const long long r0 = (long long)blockIdx.x * kRowChunk;
+  const long long r1 = min(r0 + kRowChunk, gbase[count]);
+  for (int g = owner_of(gbase, count, r0); g < count && gbase[g] < r1; ++g) {
+    const long long s = max(r0, gbase[g]) - gbase[g];
+    const long long e = min(r1, gbase[g + 1]) - gbase[g];
+    int m = 0;
+    if (grp64[g]) {
+      const long long* rp = reinterpret_cast<const long long*>(grp[g]);
+      for (long long v = s + threadIdx.x; v < e; v += kWG) m = max(m, (int)min(rp[v + 1] - rp[v], (long long)INT_MAX));
+    } else {
+      const int* rp = reinterpret_cast<const int*>(grp[g]);
+      for (long long v = s + threadIdx.x; v < e; v += kWG) m = max(m, rp[v + 1] - rp[v]);
+    }
     for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o));
-    if (lane_id() == 0 && g0 >= 0 && m > 0 &&
-        m > *reinterpret_cast<volatile const int*>(&gdmax[g0]))
-      atomicMax(&gdmax[g0], m);
-  } else if (g >= 0 && len > 0) {
-    atomicMax(&gdmax[g], len);
+    if (lane_id() == 0) wm[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int bm = max(max(wm[0], wm[1]), max(wm[2], wm[3]));
+      if (bm > 0) atomicMax(&gdmax[g], bm);
+    }
+    __syncthreads();
   }
 }
 
@@ -550,14 +581,14 @@ __device__ BoundArgs final_bounds(const GraphSel& gs) {
 }
 
 // Per graph outputs: caller ids (local) and bounds of the ranked nodes, which
-// are also marked for batch_rest.  Block g handles graph g.
+// are also marked (by internal id) for batch_rest.  Block g handles graph g.
 __global__ void __launch_bounds__(kWG) batch_write(const GraphSel* gsel, int32_t* const* out_ids,
                                                    double* const* out_lo, double* const* out_up, uint8_t* mark) {
   const GraphSel& gs = gsel[blockIdx.x];
   for (int i = threadIdx.x; i < gs.k; i += kWG) {
     const int v = gs.top_sorted[i];
     mark[v] = 1;
-    out_ids[blockIdx.x][i] = v - gs.base;
+    out_ids[blockIdx.x][i] = (gs.ext_of ? gs.ext_of[v] : v) - gs.base;
     out_lo[blockIdx.x][i] = gs.top_lo[i];
     out_up[blockIdx.x][i] = gs.top_up[i];
   }
@@ -588,21 +619,142 @@ __global__ void __launch_bounds__(kWG) batch_rest(const GraphSel* gsel, const ui
   }
 }
 
+// ---------------------------------------------------------------------------
+// Internal renumbering of a batch: each graph's nodes are renamed by their
+// position in the graph's own binned order (longest class first, ties by
+// caller id), inside the graph's id range gbase[g] .. gbase[g+1]-1, as a
+// single-graph call renames them; the walk then reads renamed column ids
+// (graph-local) from one array.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int bin_of_pos(const RunScalars* sc, long long p) {
+  int b = 0;
+  while (b + 1 < NUM_BINS && p >= sc->bin_base[b + 1]) ++b;
+  return b;
+}
+
+// Binned positions are bin-major and, inside a bin, in global row order, so the
+// rows of graph g in bin b are one run of positions: record its first and last.
+__global__ void __launch_bounds__(kWG) batch_runs(const RowDesc* desc, long long total, const long long* gbase,
+                                                  int count, const RunScalars* sc, long long* run_first,
+                                                  long long* run_last) {
+  const long long p = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (p >= total) return;
+  const int b = bin_of_pos(sc, p);
+  const long long lo = sc->bin_base[b], hi = lo + sc->bin_count[b];
+  const int g = owner_of(gbase, count, desc[p].row);
+  if (p == lo || owner_of(gbase, count, desc[p - 1].row) != g) run_first[(long long)g * NUM_BINS + b] = p;
+  if (p == hi - 1 || owner_of(gbase, count, desc[p + 1].row) != g) run_last[(long long)g * NUM_BINS + b] = p;
+}
+
+// Per graph: where each bin's run starts among the graph's new ids.
+__global__ void batch_run_starts(const long long* run_first, const long long* run_last, int count,
+                                 long long* run_start) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= count) return;
+  long long acc = 0;
+  for (int b = 0; b < NUM_BINS; ++b) {
+    const long long i = (long long)g * NUM_BINS + b;
+    run_start[i] = acc;
+    if (run_first[i] >= 0) acc += run_last[i] - run_first[i] + 1;
+  }
+}
+
+// New id of every row, both directions of the renaming, the caller offset and
+// length of each renamed row, and pmap[caller id] = {graph-local new id, length}.
+__global__ void __launch_bounds__(kWG) batch_relabel(const RowDesc* desc, long long total, const long long* gbase,
+                                                     int count, const RunScalars* sc, const long long* run_first,
+                                                     const long long* run_start, int32_t* ext_of, int32_t* int_of,
+                                                     long long* coff, IdLen* pmap, long long* len_ll, int* len32) {
+  const long long p = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (p >= total) return;
+  const int b = bin_of_pos(sc, p);
+  const RowDesc d = desc[p];
+  const int g = owner_of(gbase, count, d.row);
+  const long long ri = (long long)g * NUM_BINS + b;
+  const long long i = gbase[g] + run_start[ri] + (p - run_first[ri]);
+  ext_of[i] = d.row;
+  int_of[d.row] = (int32_t)i;
+  coff[i] = d.off;
+  pmap[d.row] = IdLen{(int32_t)(i - gbase[g]), d.len};
+  len_ll[i] = d.len;
+  len32[i] = d.len;
+}
+
+// Renamed column ids of one stretch of a row (arcs in their original order).
+template <int G>
+__device__ __forceinline__ void batch_rename(const int32_t* src, int32_t* dst, int len, int lane, const IdLen* pm) {
+  for (int j0 = lane; j0 < len; j0 += 8 * G) {
+    int32_t c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u * G;
+      c[u] = j < len ? src[j] : -1;
+    }
+    int32_t m[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) m[u] = c[u] < 0 ? 0 : pm[c[u]].id;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u * G;
+      if (j < len) dst[j] = m[u];
+    }
+  }
+}
+
+// G lanes per renamed row of one bin (rows first .. first+cnt-1 of desc).
+template <int G>
+__global__ void __launch_bounds__(kWG) batch_rename_rows(const RowDesc* desc, long long first, long long cnt,
+                                                         const int* gid_of, const long long* gbase,
+                                                         const int32_t* const* gcol, const long long* coff,
+                                                         const IdLen* pmap, int32_t* ncol) {
+  constexpr int RPB = kWG / G;
+  const long long i = first + (long long)blockIdx.x * RPB + threadIdx.x / G;
+  if (i >= first + cnt) return;
+  const RowDesc d = desc[i];
+  const int g = gid_of[d.row];
+  batch_rename<G>(gcol[g] + coff[d.row], ncol + d.off, d.len, threadIdx.x & (G - 1), pmap + gbase[g]);
+}
+
+// One workgroup per 4096-arc segment of a long renamed row.
+__global__ void __launch_bounds__(kWG) batch_rename_segments(const SegDesc* segs, const HugeRow* huge,
+                                                             const long long* noff, const int* gid_of,
+                                                             const long long* gbase, const int32_t* const* gcol,
+                                                             const long long* coff, const IdLen* pmap,
+                                                             int32_t* ncol) {
+  const SegDesc sd = segs[blockIdx.x];
+  const int row = huge[sd.hrow].row;
+  const int g = gid_of[row];
+  batch_rename<kWG>(gcol[g] + coff[row] + (sd.off - noff[row]), ncol + sd.off, sd.len, threadIdx.x,
+                    pmap + gbase[g]);
+}
+
+template <int G>
+void launch_rename_bin(const RowDesc* desc, long long first, long long cnt, const int* gid_of,
+                       const long long* gbase, const int32_t* const* gcol, const long long* coff,
+                       const IdLen* pmap, int32_t* ncol, hipStream_t s) {
+  if (cnt <= 0) return;
+  constexpr int RPB = kWG / G;
+  const unsigned nb = (unsigned)((cnt + RPB - 1) / RPB);
+  hipLaunchKernelGGL(batch_rename_rows<G>, dim3(nb), dim3(kWG), 0, s, desc, first, cnt, gid_of, gbase, gcol, coff,
+                     pmap, ncol);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
 hipError_t launch_batch_prep(const long long* gbase, const void* const* grp, const int* grp64, const long long* gnnz,
-                             const int32_t* const* gcol, int count, long long total_n, long long max_nnz, int* gid_of,
-                             long long* blk, int nblocks, long long* sums, long long* totals, RowDesc* desc,
-                             SegDesc* segs, HugeRow* huge, RunScalars* sc, int validate, hipStream_t s) {
+                             const long long* gabase, const int32_t* const* gcol, int count, long long total_n,
+                             long long total_nnz, int* gid_of, long long* blk, int nblocks, long long* sums,
+                             long long* totals, RowDesc* desc, SegDesc* segs, HugeRow* huge, RunScalars* sc,
+                             int validate, hipStream_t s) {
   const unsigned nb = (unsigned)std::max<long long>(1, (total_n + kWG - 1) / kWG);
   hipLaunchKernelGGL(fill_gid, dim3(nb), dim3(kWG), 0, s, gbase, count, total_n, gid_of);
   hipLaunchKernelGGL(batch_csr_ends, dim3((count + 255) / 256), dim3(256), 0, s, grp, grp64, gbase, gnnz, count, sc);
-  if (validate && max_nnz > 0) {
-    const unsigned gx = (unsigned)std::min<long long>(256, (max_nnz + kWG * 16 - 1) / (kWG * 16));
-    hipLaunchKernelGGL(batch_col_range, dim3(gx, count), dim3(kWG), 0, s, gcol, gnnz, gbase, sc);
+  if (validate && total_nnz > 0) {
+    const unsigned gx = (unsigned)((total_nnz + kColChunk - 1) / kColChunk);
+    hipLaunchKernelGGL(batch_col_range, dim3(gx), dim3(kWG), 0, s, gcol, gabase, gbase, count, sc);
   }
   const BatchRows rows{gid_of, gbase, grp, grp64, gnnz};
   hipLaunchKernelGGL(prep_count<BatchRows>, dim3(nblocks), dim3(kWG), 0, s, rows, total_n, blk, nblocks, sc);
@@ -613,9 +765,11 @@ hipError_t launch_batch_prep(const long long* gbase, const void* const* grp, con
   return hipGetLastError();
 }
 
-hipError_t launch_batch_dmax(const RowDesc* desc, long long count, const int* gid_of, int* gdmax, hipStream_t s) {
-  const unsigned nb = (unsigned)std::max<long long>(1, (count + kWG - 1) / kWG);
-  hipLaunchKernelGGL(batch_dmax, dim3(nb), dim3(kWG), 0, s, desc, count, gid_of, gdmax);
+hipError_t launch_batch_dmax(const void* const* grp, const int* grp64, const long long* gbase, int count,
+                             long long total_n, int* gdmax, hipStream_t s) {
+  if (total_n <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)((total_n + kRowChunk - 1) / kRowChunk);
+  hipLaunchKernelGGL(batch_dmax, dim3(nb), dim3(kWG), 0, s, grp, grp64, gbase, count, gdmax);
   return hipGetLastError();
 }
 
@@ -682,6 +836,44 @@ hipError_t launch_batch_write(const GraphSel* gsel, int count, long long max_n, 
   hipLaunchKernelGGL(batch_write, dim3(count), dim3(kWG), 0, s, gsel, out_ids, out_lo, out_up, mark);
   const unsigned bx = (unsigned)std::max<long long>(1, std::min<long long>(64, (max_n + 4095) / 4096));
   hipLaunchKernelGGL(batch_rest, dim3(bx, count), dim3(kWG), 0, s, gsel, (const uint8_t*)mark, rest_bits);
+  return hipGetLastError();
+}
+
+
+// Renaming tables of a batch from its first binning (desc, bins in sc); then
+// noff = exclusive scan of the renamed lengths.  run_* hold count * NUM_BINS
+// entries; run_first and run_last must be all -1 on entry.
+hipError_t launch_batch_relabel(const RowDesc* desc, long long total, const long long* gbase, int count,
+                                const RunScalars* sc, long long* run_first, long long* run_last,
+                                long long* run_start, int32_t* ext_of, int32_t* int_of, long long* coff, IdLen* pmap,
+                                long long* len_ll, int* len32, long long* noff, long long* sums, long long* tot,
+                                hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)((total + kWG - 1) / kWG);
+  hipLaunchKernelGGL(batch_runs, dim3(nb), dim3(kWG), 0, s, desc, total, gbase, count, sc, run_first, run_last);
+  hipLaunchKernelGGL(batch_run_starts, dim3((count + 255) / 256), dim3(256), 0, s, (const long long*)run_first,
+                     (const long long*)run_last, count, run_start);
+  hipLaunchKernelGGL(batch_relabel, dim3(nb), dim3(kWG), 0, s, desc, total, gbase, count, sc,
+                     (const long long*)run_first, (const long long*)run_start, ext_of, int_of, coff, pmap, len_ll,
+                     len32);
+  return launch_scan_ll(len_ll, total, noff, sums, tot, s);
+}
+
+// Renamed column ids of every renamed row (bins of the second binning).
+hipError_t launch_batch_rename(const RowDesc* desc, const long long* bin_base, const long long* bin_count,
+                               const SegDesc* segs, long long seg_total, const HugeRow* huge, const long long* noff,
+                               const int* gid_of, const long long* gbase, const int32_t* const* gcol,
+                               const long long* coff, const IdLen* pmap, int32_t* ncol, hipStream_t s) {
+  if (seg_total > 0)
+    hipLaunchKernelGGL(batch_rename_segments, dim3((unsigned)seg_total), dim3(kWG), 0, s, segs, huge, noff, gid_of,
+                       gbase, gcol, coff, pmap, ncol);
+  launch_rename_bin<kWG>(desc, bin_base[BIN_B256], bin_count[BIN_B256], gid_of, gbase, gcol, coff, pmap, ncol, s);
+  launch_rename_bin<64>(desc, bin_base[BIN_W64], bin_count[BIN_W64], gid_of, gbase, gcol, coff, pmap, ncol, s);
+  launch_rename_bin<16>(desc, bin_base[BIN_W16], bin_count[BIN_W16], gid_of, gbase, gcol, coff, pmap, ncol, s);
+  launch_rename_bin<32>(desc, bin_base[BIN_G32], bin_count[BIN_G32], gid_of, gbase, gcol, coff, pmap, ncol, s);
+  launch_rename_bin<16>(desc, bin_base[BIN_G16], bin_count[BIN_G16], gid_of, gbase, gcol, coff, pmap, ncol, s);
+  launch_rename_bin<8>(desc, bin_base[BIN_G8], bin_count[BIN_G8], gid_of, gbase, gcol, coff, pmap, ncol, s);
+  launch_rename_bin<4>(desc, bin_base[BIN_G4], bin_count[BIN_G4], gid_of, gbase, gcol, coff, pmap, ncol, s);
   return hipGetLastError();
 }
 

@@ -338,10 +338,21 @@ constexpr int kSmallActive = 1 << 16;   // |M| at or below which one workgroup s
 
 // ---- batched form (katz_batch.hip) --------------------------------------------
 hipError_t launch_batch_prep(const long long* gbase, const void* const* grp, const int* grp64, const long long* gnnz,
-                             const int32_t* const* gcol, int count, long long total_n, long long max_nnz, int* gid_of,
-                             long long* blk, int nblocks, long long* sums, long long* totals, RowDesc* desc,
-                             SegDesc* segs, HugeRow* huge, RunScalars* sc, int validate, hipStream_t s);
-hipError_t launch_batch_dmax(const RowDesc* desc, long long count, const int* gid_of, int* gdmax, hipStream_t s);
+                             const long long* gabase, const int32_t* const* gcol, int count, long long total_n,
+                             long long total_nnz, int* gid_of, long long* blk, int nblocks, long long* sums,
+                             long long* totals, RowDesc* desc, SegDesc* segs, HugeRow* huge, RunScalars* sc,
+                             int validate, hipStream_t s);
+hipError_t launch_batch_dmax(const void* const* grp, const int* grp64, const long long* gbase, int count,
+                             long long total_n, int* gdmax, hipStream_t s);
+hipError_t launch_batch_relabel(const RowDesc* desc, long long total, const long long* gbase, int count,
+                                const RunScalars* sc, long long* run_first, long long* run_last,
+                                long long* run_start, int32_t* ext_of, int32_t* int_of, long long* coff, IdLen* pmap,
+                                long long* len_ll, int* len32, long long* noff, long long* sums, long long* tot,
+                                hipStream_t s);
+hipError_t launch_batch_rename(const RowDesc* desc, const long long* bin_base, const long long* bin_count,
+                               const SegDesc* segs, long long seg_total, const HugeRow* huge, const long long* noff,
+                               const int* gid_of, const long long* gbase, const int32_t* const* gcol,
+                               const long long* coff, const IdLen* pmap, int32_t* ncol, hipStream_t s);
 hipError_t launch_fill_ones(void* x, long long n, int fp32, hipStream_t s);
 hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, long long max_grid, long long n_huge,
                              hipStream_t s);

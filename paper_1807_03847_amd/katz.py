@@ -159,6 +159,7 @@ def make_csr(row_ptr: torch.Tensor, col: torch.Tensor, undirected: bool = True) 
 
 
 FLAG_NO_REORDER = 1
+FLAG_REORDER = 2
 
 
 def make_params(k=1, alpha=0.0, eps=0.0, precision="fp64", max_iter=0, validate=VALIDATE_BASIC,

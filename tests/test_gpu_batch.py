@@ -147,3 +147,39 @@ def test_batch_launch_tuning_is_invisible(precision):
         assert katz.tuning_get() == best
     finally:
         katz.tuning_set(**saved)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_renumbering_is_invisible(precision):
+    """Renaming each graph's nodes by its binned order changes only the memory
+    layout: every output is bitwise that of the batch in caller order."""
+    katz = K()
+    graphs, params = batch_workload(8, 13)
+    rp, col = sg.star_graph(6000)
+    graphs.insert(3, (rp, col))
+    params.insert(3, dict(k=25, alpha=0.5 / (1 + sg.max_degree(rp)), eps=1e-7))
+    say("batch renumbering", precision)
+    a = run_batch(graphs, [dict(pp, flags=katz.FLAG_REORDER) for pp in params], precision)
+    b = run_batch(graphs, [dict(pp, flags=katz.FLAG_NO_REORDER) for pp in params], precision)
+    for ra, rb in zip(a, b):
+        assert torch.equal(ra.topk, rb.topk) and torch.equal(ra.lower, rb.lower) and torch.equal(ra.upper, rb.upper)
+        assert (ra.iterations, ra.status, ra.rest_upper_max) == (rb.iterations, rb.status, rb.rest_upper_max)
+
+
+def test_batch_column_errors():
+    """A column id out of range in any graph (checked over the arcs of the whole
+    batch in fixed-size chunks) fails the call."""
+    katz = K()
+    graphs, params = batch_workload(5, 17, 10, 12)
+    for gi, pos in ((0, 0), (2, -1), (4, 777)):
+        rp, col = graphs[gi]
+        bad = col.copy()
+        bad[pos] = len(rp) - 1 + 3
+        gl = list(graphs)
+        gl[gi] = (rp, bad)
+        say("batch column error", gi, pos)
+        with pytest.raises(katz.KatzError) as e:
+            run_batch(gl, params, "fp64")
+        assert e.value.code == katz.E_CSR
+    res = run_batch(graphs, params, "fp64")
+    assert len(res) == len(graphs)
