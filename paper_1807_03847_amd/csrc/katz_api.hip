@@ -287,7 +287,7 @@ int check_graph(const katz_csr* g) {
 int check_params(const katz_params* p, long long n, bool need_k) {
   if (!p) return KATZ_E_INVALID_ARG;
   if (p->precision != KATZ_FP64 && p->precision != KATZ_FP32_MARGIN) return KATZ_E_INVALID_ARG;
-  if (p->validate < 0 || p->validate > 2 || (p->flags & ~KATZ_FLAG_NO_REORDER) || p->max_iter < 0)
+  if (p->validate < 0 || p->validate > 2 || (p->flags & ~(KATZ_FLAG_NO_REORDER | KATZ_FLAG_REORDER)) || p->max_iter < 0)
     return KATZ_E_INVALID_ARG;
   if (p->degree_cap < 0) return KATZ_E_INVALID_ARG;
   if (std::isnan(p->alpha) || p->alpha < 0.0 || std::isinf(p->alpha)) return KATZ_E_ALPHA;
@@ -384,18 +384,21 @@ int resolve_alpha(double alpha_in, int dmax, Scalars& S) {
   return KATZ_OK;
 }
 
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
 // Deepest rounding chain of a row sum under the bin schedule (serial adds per
 // lane, then the butterfly levels, and the segment combine for huge rows).  It
 // grows with the row length, so the longest row of a graph sets its maximum.
 int reduction_depth(long long dmax) {
   switch (bin_of_host(dmax)) {
     case BIN_EMPTY: return 0;
-    case BIN_G4: return 2;
-    case BIN_G8: return 3;
-    case BIN_G16: return 4;
-    case BIN_G32: return 5;
-    case BIN_W16: return (kShortRowMax / 16 - 1) + 4;
-    case BIN_W64: return (kPerLane - 1) + 6;
+    // (longest row of the bin / lanes - 1) serial adds, then log2(lanes) levels.
+    case BIN_G4: return 4 / kBinLanes[BIN_G4] - 1 + ilog2(kBinLanes[BIN_G4]);
+    case BIN_G8: return 8 / kBinLanes[BIN_G8] - 1 + ilog2(kBinLanes[BIN_G8]);
+    case BIN_G16: return 16 / kBinLanes[BIN_G16] - 1 + ilog2(kBinLanes[BIN_G16]);
+    case BIN_G32: return 32 / kBinLanes[BIN_G32] - 1 + ilog2(kBinLanes[BIN_G32]);
+    case BIN_W16: return kShortRowMax / kBinLanes[BIN_W16] - 1 + ilog2(kBinLanes[BIN_W16]);
+    case BIN_W64: return kWaveRowMax / kBinLanes[BIN_W64] - 1 + ilog2(kBinLanes[BIN_W64]);
     case BIN_B256: return (kPerLane - 1) + 8;
     default: {
       const long long max_seg = (dmax + kSeg - 1) / kSeg;
@@ -542,12 +545,8 @@ void fill_blocks(IterArgs& ia, const Bins& b, bool write_empty, long long& total
   long long blocks[NUM_BINS] = {};
   blocks[BIN_HUGE] = b.seg_total;
   blocks[BIN_B256] = b.bin_count[BIN_B256];
-  blocks[BIN_W64] = (b.bin_count[BIN_W64] + 3) / 4;
-  blocks[BIN_W16] = (b.bin_count[BIN_W16] + 15) / 16;
-  blocks[BIN_G32] = (b.bin_count[BIN_G32] + 7) / 8;
-  blocks[BIN_G16] = (b.bin_count[BIN_G16] + 15) / 16;
-  blocks[BIN_G8] = (b.bin_count[BIN_G8] + 31) / 32;
-  blocks[BIN_G4] = (b.bin_count[BIN_G4] + 63) / 64;
+  for (int i = BIN_W64; i <= BIN_G4; ++i)
+    blocks[i] = (b.bin_count[i] + bin_rows_per_group(i) - 1) / bin_rows_per_group(i);
   blocks[BIN_EMPTY] = write_empty ? (b.bin_count[BIN_EMPTY] + kWG - 1) / kWG : 0;
   ia.first_block[0] = 0;
   for (int i = 0; i < NUM_BINS; ++i) ia.first_block[i + 1] = ia.first_block[i] + blocks[i];
@@ -1432,7 +1431,8 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   {
     // Work items per bin: one per segment / long row, `tile` row groups
     // otherwise (a row group is one workgroup's worth of rows).
-    const long long per[NUM_BINS] = {1, 1, 4, 16, 8, 16, 32, 64, kWG};
+    long long per[NUM_BINS];
+    for (int i = 0; i < NUM_BINS; ++i) per[i] = bin_rows_per_group(i);
     long long items[NUM_BINS] = {};
     items[BIN_HUGE] = b.seg_total;
     items[BIN_B256] = b.bin_count[BIN_B256];
@@ -1471,7 +1471,8 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   bw.n_items = n_items;
   bw.fp32 = fp32;
   const long long total_blocks = bw.first_block[NUM_BINS];
-  const long long walk_grid = (long long)current_tuning().batch_blocks_per_cu * cu_count(dev);
+  long long walk_grid = (long long)current_tuning().batch_blocks_per_cu * cu_count(dev);
+  if (walk_grid > 0) walk_grid = std::min(walk_grid, batch_walk_resident(fp32));
   {
     const long long nh = b.bin_count[BIN_HUGE];
     if (total_blocks + (nh + kWG / kWave - 1) / (kWG / kWave) > blk_cap) return KATZ_E_HIP;   // sizing bound broken

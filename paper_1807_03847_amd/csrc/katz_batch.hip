@@ -400,22 +400,22 @@ __global__ void __launch_bounds__(kWG) walk_batch(BatchWalk a) {
         break;
       }
       case BIN_W64:
-        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, 64>(a, r, lb * a.tile + k, BIN_W64, gi, g_mine, vmax);
+        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, kBinLanes[BIN_W64]>(a, r, lb * a.tile + k, BIN_W64, gi, g_mine, vmax);
         break;
       case BIN_W16:
-        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, 16>(a, r, lb * a.tile + k, BIN_W16, gi, g_mine, vmax);
+        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, kBinLanes[BIN_W16]>(a, r, lb * a.tile + k, BIN_W16, gi, g_mine, vmax);
         break;
       case BIN_G32:
-        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, 32>(a, r, lb * a.tile + k, BIN_G32, gi, g_mine, vmax);
+        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, kBinLanes[BIN_G32]>(a, r, lb * a.tile + k, BIN_G32, gi, g_mine, vmax);
         break;
       case BIN_G16:
-        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, 16>(a, r, lb * a.tile + k, BIN_G16, gi, g_mine, vmax);
+        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, kBinLanes[BIN_G16]>(a, r, lb * a.tile + k, BIN_G16, gi, g_mine, vmax);
         break;
       case BIN_G8:
-        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, 8>(a, r, lb * a.tile + k, BIN_G8, gi, g_mine, vmax);
+        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, kBinLanes[BIN_G8]>(a, r, lb * a.tile + k, BIN_G8, gi, g_mine, vmax);
         break;
       case BIN_G4:
-        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, 4>(a, r, lb * a.tile + k, BIN_G4, gi, g_mine, vmax);
+        for (int k = 0; k < a.tile; ++k) batch_rows_group<F32, kBinLanes[BIN_G4]>(a, r, lb * a.tile + k, BIN_G4, gi, g_mine, vmax);
         break;
       case BIN_EMPTY: {
         // Rows without arcs: x_r = 0 (and c_1 = 0, e = 0 at r = 1).
@@ -454,9 +454,7 @@ __global__ void __launch_bounds__(kWG) batch_item_graphs(BatchWalk a, long long 
   if (bin == BIN_HUGE) {
     g = a.gid_of[a.huge[a.segs[lb].hrow].row];
   } else {
-    const long long rpb = bin == BIN_B256 ? 1
-                        : (bin == BIN_W64 ? 4 : bin == BIN_W16 ? 16 : bin == BIN_G32 ? 8 : bin == BIN_G16 ? 16 : bin == BIN_G8 ? 32
-                           : bin == BIN_G4 ? 64 : kWG) * a.tile;
+    const long long rpb = bin == BIN_B256 ? 1 : (long long)bin_rows_per_group(bin) * a.tile;
     const long long i0 = lb * rpb;
     const long long i1 = min(i0 + rpb, a.bin_count[bin]) - 1;
     const int g0 = a.gid_of[a.desc[a.bin_base[bin] + i0].row];
@@ -782,10 +780,16 @@ hipError_t launch_fill_ones(void* x, long long n, int fp32, hipStream_t s) {
 // One walk step of the batch: walk_batch (on at most max_grid workgroups when
 // max_grid > 0), batch_huge_combine for rows longer than one segment, and
 // batch_reduce_max for the per-graph maxima.
+// Workgroups of the batched walk kernel the device holds at once (the cap of a
+// persistent grid; queried before the iterations are captured).
+long long batch_walk_resident(int fp32) {
+  return resident_blocks(fp32 ? (const void*)walk_batch<true> : (const void*)walk_batch<false>, 0);
+}
+
 hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, long long max_grid, long long n_huge,
                              hipStream_t s) {
   const long long items = std::max<long long>(1, total_blocks);
-  const unsigned grid = (unsigned)(max_grid > 0 ? std::min(items, max_grid) : items);
+  const unsigned grid = (unsigned)(max_grid > 0 ? std::min(items, max_grid) : items);   // max_grid: see batch_walk_resident
   BatchWalk w = a;
   w.blk_base = 0;
   if (a.fp32) hipLaunchKernelGGL(walk_batch<true>, dim3(grid), dim3(kWG), 0, s, w);

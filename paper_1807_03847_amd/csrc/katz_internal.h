@@ -45,14 +45,23 @@ enum BinId : int {
   BIN_HUGE = 0,   // len > 4096: segmented, multi-workgroup
   BIN_B256,       // 1025..4096: one workgroup per row
   BIN_W64,        // 129..1024: one wave per row
-  BIN_W16,        // 33..128: 16 lanes per row
-  BIN_G32,        // 17..32: 32 lanes per row
+  BIN_W16,        // 33..128
+  BIN_G32,        // 17..32
   BIN_G16,        // 9..16
   BIN_G8,         // 5..8
   BIN_G4,         // 1..4
   BIN_EMPTY,      // 0
   NUM_BINS
 };
+
+// Lanes that sum one row of each bin (lane l adds elements l, l+G, ... in
+// order, then the lanes combine by butterfly).  Short rows take few lanes, at
+// most eight elements each (one batch of loads), so a wave holds many rows;
+// each lane then has eight loads in flight.  The schedule, and so every row
+// sum's rounding, depends only on the row's bin.
+constexpr int kBinLanes[NUM_BINS] = {kWG, kWG, 64, 16, 4, 2, 1, 1, 1};   // empty rows: one thread each
+// Rows per workgroup-sized group of a short-row bin.
+constexpr int bin_rows_per_group(int bin) { return kWG / kBinLanes[bin]; }
 
 struct RowDesc {
   int64_t off;
@@ -270,6 +279,8 @@ hipError_t launch_walk_first(const IterArgs& a, int fp32, long long n, long long
                              hipStream_t s);
 // renumber: walk step 2 fused with the renaming of the column ids (the
 // IterArgs renumbering fields must be set and hub_n must be 0).
+long long resident_blocks(const void* kernel, size_t lds);
+long long batch_walk_resident(int fp32);
 hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, long long max_grid,
                             long long* grid_used, hipStream_t s, bool renumber = false);
 // Reduces the per-workgroup maxima of walk iteration r into xmax32[r] / xmax64[r].

@@ -17,6 +17,9 @@
 #include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "katz_device.h"
 
@@ -443,12 +446,12 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
         if (threadIdx.x == 0) epilogue<F32>(a, ep, d.row, tot, vmax, pv);
         break;
       }
-      case BIN_W64: rows_group<F32, 64, Renumber>(a, hub, ep, ep1, lb, BIN_W64, vmax, stop); break;
-      case BIN_W16: rows_group<F32, 16, Renumber>(a, hub, ep, ep1, lb, BIN_W16, vmax, stop); break;
-      case BIN_G32: rows_group<F32, 32, Renumber>(a, hub, ep, ep1, lb, BIN_G32, vmax, stop); break;
-      case BIN_G16: rows_group<F32, 16, Renumber>(a, hub, ep, ep1, lb, BIN_G16, vmax, stop); break;
-      case BIN_G8: rows_group<F32, 8, Renumber>(a, hub, ep, ep1, lb, BIN_G8, vmax, stop); break;
-      case BIN_G4: rows_group<F32, 4, Renumber>(a, hub, ep, ep1, lb, BIN_G4, vmax, stop); break;
+      case BIN_W64: rows_group<F32, kBinLanes[BIN_W64], Renumber>(a, hub, ep, ep1, lb, BIN_W64, vmax, stop); break;
+      case BIN_W16: rows_group<F32, kBinLanes[BIN_W16], Renumber>(a, hub, ep, ep1, lb, BIN_W16, vmax, stop); break;
+      case BIN_G32: rows_group<F32, kBinLanes[BIN_G32], Renumber>(a, hub, ep, ep1, lb, BIN_G32, vmax, stop); break;
+      case BIN_G16: rows_group<F32, kBinLanes[BIN_G16], Renumber>(a, hub, ep, ep1, lb, BIN_G16, vmax, stop); break;
+      case BIN_G8: rows_group<F32, kBinLanes[BIN_G8], Renumber>(a, hub, ep, ep1, lb, BIN_G8, vmax, stop); break;
+      case BIN_G4: rows_group<F32, kBinLanes[BIN_G4], Renumber>(a, hub, ep, ep1, lb, BIN_G4, vmax, stop); break;
       case BIN_EMPTY: {
         // Only at r = 2: the buffer of x_2 was never written for empty rows.
         const long long i = lb * kWG + threadIdx.x;
@@ -1056,11 +1059,40 @@ hipError_t launch_reduce_blkmax(const void* blkmax, long long nb, int fp32, unsi
 
 // walk_step, then huge_combine when there are rows longer than one segment.
 // *blocks_used: workgroup maxima written to a.blkmax (both launches).
+// Workgroups of a kernel that the device holds at once: a persistent grid
+// larger than this would run its last workgroups after all the others.
+long long resident_blocks(const void* kernel, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, size_t>, long long> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return LLONG_MAX;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  const auto key = std::make_tuple(dev, kernel, lds);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  long long v = LLONG_MAX;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWG, lds) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && per_cu > 0 && cus > 0)
+    v = (long long)per_cu * cus;
+  else
+    (void)hipGetLastError();
+  cache[key] = v;
+  return v;
+}
+
 hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, long long max_grid,
                             long long* blocks_used, hipStream_t s, bool renumber) {
   long long g = total_blocks > 0 ? total_blocks : 1;
-  if (max_grid > 0) g = std::min(g, max_grid);
   const size_t lds = (size_t)a.hub_n * (fp32 ? sizeof(float) : sizeof(double));
+  if (max_grid > 0) {
+    const void* k = renumber ? (fp32 ? (const void*)walk_step<true, true> : (const void*)walk_step<false, true>)
+                             : (fp32 ? (const void*)walk_step<true, false> : (const void*)walk_step<false, false>);
+    g = std::min(g, std::min(max_grid, resident_blocks(k, renumber ? 0 : lds)));
+  }
   if (a.hub_n > 0 && max_grid <= 0) return hipErrorInvalidValue;   // the copy pays only on a persistent grid
   // col_src may be null for a graph without arcs.
   if (renumber && (a.hub_n > 0 || !a.coff || !a.pmap || !a.ncol || a.r != 2)) return hipErrorInvalidValue;

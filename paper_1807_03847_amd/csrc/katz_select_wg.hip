@@ -32,6 +32,8 @@ __device__ void refresh_bounds(BoundArgs& b, const GraphSel& gs, int r) {
 __device__ __forceinline__ int gs_ext(const GraphSel& gs, int v) { return gs.ext_of ? gs.ext_of[v] : v; }
 __device__ __forceinline__ int gs_int(const GraphSel& gs, int e) { return gs.int_of ? gs.int_of[e] : e; }
 
+constexpr int kSelIlp = 4;   // nodes per thread and pass of the key and deactivation passes
+
 struct SortArea {
   unsigned long long key[kMaxK];
   int ext[kMaxK];
@@ -69,13 +71,26 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
     s_prog = 0;
   }
   __syncthreads();
-  for (int i = t; i < m; i += kFinishThreads) {
-    const int v = identity ? gs.base + i : act_in[i];
-    double lo, up;
-    bound_eval(b, v, lo, up);
-    const unsigned long long key = key_of(lo);
-    gs.keys[i] = key;
-    atomicAdd(&sm.h[(key >> 51) & (kDigits - 1)], 1u);
+  // Four nodes per thread and pass, their loads issued together (a slot past
+  // the end evaluates node base, a valid index, and is dropped).
+  for (int i0 = t; i0 < m; i0 += kSelIlp * kFinishThreads) {
+    unsigned long long kk[kSelIlp];
+#pragma unroll
+    for (int u = 0; u < kSelIlp; ++u) {
+      const int i = i0 + u * kFinishThreads;
+      const int v = i < m ? (identity ? gs.base + i : act_in[i]) : gs.base;
+      double lo, up;
+      bound_eval(b, v, lo, up);
+      kk[u] = key_of(lo);
+    }
+#pragma unroll
+    for (int u = 0; u < kSelIlp; ++u) {
+      const int i = i0 + u * kFinishThreads;
+      if (i < m) {
+        gs.keys[i] = kk[u];
+        atomicAdd(&sm.h[(kk[u] >> 51) & (kDigits - 1)], 1u);
+      }
+    }
   }
   __syncthreads();
   Bucket bk = find_bucket(sm.h, kDigits, k, true);
@@ -164,28 +179,32 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
     cut = s_idpre;
   }
   // Deactivation: nodes past position k leave M when u - eps < l(M[k]).
+  // Four nodes per thread and pass as above (the order of M does not matter).
   {
     bool prog = false;
-    for (int base = 0; base < m; base += kFinishThreads) {
-      const int i = base + t;
-      const bool valid = i < m;
-      bool top = false, keep = false;
-      int v = 0;
-      if (valid) {
-        v = identity ? gs.base + i : act_in[i];
-        const unsigned long long key = gs.keys[i];
-        top = key > theta_key || (key == theta_key && gs_ext(gs, v) <= cut);
-        if (!top) {
-          double lo, up;
-          bound_eval(b, v, lo, up);
-          keep = !(up - b.eps < theta);
-        }
-        if ((top || keep) && can_progress(b, v)) prog = true;
+    for (int base = 0; base < m; base += kSelIlp * kFinishThreads) {
+      bool top[kSelIlp], keep[kSelIlp];
+      int vv[kSelIlp];
+#pragma unroll
+      for (int u = 0; u < kSelIlp; ++u) {
+        const int i = base + u * kFinishThreads + t;
+        const bool valid = i < m;
+        const int v = valid ? (identity ? gs.base + i : act_in[i]) : gs.base;
+        const unsigned long long key = valid ? gs.keys[i] : 0ull;
+        double lo, up;
+        bound_eval(b, v, lo, up);
+        top[u] = valid && (key > theta_key || (key == theta_key && gs_ext(gs, v) <= cut));
+        keep[u] = valid && !top[u] && !(up - b.eps < theta);
+        if ((top[u] || keep[u]) && can_progress(b, v)) prog = true;
+        vv[u] = v;
       }
-      const int pt = wave_append(&s_top, top);
-      if (top && pt < k) act_out[pt] = v;
-      const int pk = wave_append(&s_kept, keep);
-      if (keep && k + pk < gs.n) act_out[k + pk] = v;
+#pragma unroll
+      for (int u = 0; u < kSelIlp; ++u) {
+        const int pt = wave_append(&s_top, top[u]);
+        if (top[u] && pt < k) act_out[pt] = vv[u];
+        const int pk = wave_append(&s_kept, keep[u]);
+        if (keep[u] && k + pk < gs.n) act_out[k + pk] = vv[u];
+      }
     }
     if (prog) s_prog = 1;
   }
