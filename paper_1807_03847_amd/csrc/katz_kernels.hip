@@ -526,13 +526,18 @@ __global__ void __launch_bounds__(kWG) sel_hist0(SelArgs a) {
   for (int d = threadIdx.x; d < kDigits; d += kWG) h[d] = 0;
   __syncthreads();
   const int m = a.sc->m;
-  for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < m; i += (long long)gridDim.x * kWG) {
-    const int v = a.identity_in ? (int)i : a.act_in[i];
-    double lo, up;
-    bound_eval(a.b, v, lo, up);
-    const unsigned long long key = key_of(lo);
-    a.keys[i] = key;
-    atomicAdd(&h[(key >> 51) & (kDigits - 1)], 1u);
+  const long long stride = (long long)gridDim.x * kWG;
+  for (long long i0 = (long long)blockIdx.x * kWG; i0 < m; i0 += stride) {   // uniform trip count per wave
+    const long long i = i0 + threadIdx.x;
+    unsigned long long key = 0;
+    if (i < m) {
+      const int v = a.identity_in ? (int)i : a.act_in[i];
+      double lo, up;
+      bound_eval(a.b, v, lo, up);
+      key = key_of(lo);
+      a.keys[i] = key;
+    }
+    wave_hist_add(h, (unsigned)((key >> 51) & (kDigits - 1)), i < m);
   }
   __syncthreads();
   for (int d = threadIdx.x; d < kDigits; d += kWG)
@@ -547,8 +552,11 @@ __global__ void __launch_bounds__(kWG) sel_hist1(SelArgs a) {
   __shared__ unsigned h[kDigits];
   for (int d = threadIdx.x; d < kDigits; d += kWG) h[d] = 0;
   __syncthreads();
-  for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < cnt; i += (long long)gridDim.x * kWG)
-    atomicAdd(&h[(a.cand_key[0][i] >> 39) & (kDigits - 1)], 1u);
+  for (long long i0 = (long long)blockIdx.x * kWG; i0 < cnt; i0 += (long long)gridDim.x * kWG) {
+    const long long i = i0 + threadIdx.x;
+    const unsigned d = i < cnt ? (unsigned)((a.cand_key[0][i] >> 39) & (kDigits - 1)) : 0u;
+    wave_hist_add(h, d, i < cnt);
+  }
   __syncthreads();
   for (int d = threadIdx.x; d < kDigits; d += kWG)
     if (h[d]) atomicAdd(&a.hist[kDigits + d], h[d]);

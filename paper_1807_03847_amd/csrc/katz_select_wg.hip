@@ -73,7 +73,8 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
   __syncthreads();
   // Four nodes per thread and pass, their loads issued together (a slot past
   // the end evaluates node base, a valid index, and is dropped).
-  for (int i0 = t; i0 < m; i0 += kSelIlp * kFinishThreads) {
+  for (int b0 = 0; b0 < m; b0 += kSelIlp * kFinishThreads) {   // same trip count for every thread
+    const int i0 = b0 + t;
     unsigned long long kk[kSelIlp];
 #pragma unroll
     for (int u = 0; u < kSelIlp; ++u) {
@@ -86,10 +87,8 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
 #pragma unroll
     for (int u = 0; u < kSelIlp; ++u) {
       const int i = i0 + u * kFinishThreads;
-      if (i < m) {
-        gs.keys[i] = kk[u];
-        atomicAdd(&sm.h[(kk[u] >> 51) & (kDigits - 1)], 1u);
-      }
+      if (i < m) gs.keys[i] = kk[u];
+      wave_hist_add(sm.h, (unsigned)((kk[u] >> 51) & (kDigits - 1)), i < m);
     }
   }
   __syncthreads();
@@ -100,23 +99,27 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
     s_count = bk.count;
   }
   __syncthreads();
-  // Candidates: the nodes whose top digit is the k-th key's.
+  // Candidates: the nodes whose top digit is the k-th key's (four per thread
+  // and pass, loads first).
   {
     const unsigned long long pre = s_prefix;
-    for (int base = 0; base < m; base += kFinishThreads) {
-      const int i = base + t;
-      const bool valid = i < m;
-      unsigned long long key = 0;
-      int v = 0;
-      if (valid) {
-        key = gs.keys[i];
-        v = identity ? gs.base + i : act_in[i];
+    for (int base = 0; base < m; base += kSelIlp * kFinishThreads) {
+      unsigned long long kk[kSelIlp];
+      int vv[kSelIlp];
+#pragma unroll
+      for (int u = 0; u < kSelIlp; ++u) {
+        const int i = base + u * kFinishThreads + t;
+        kk[u] = i < m ? gs.keys[i] : 0ull;
+        vv[u] = i < m ? (identity ? gs.base + i : act_in[i]) : 0;
       }
-      const bool pred = valid && (key >> 51) == pre;
-      const int pos = wave_append(&s_cnt, pred);
-      if (pred) {
-        gs.cand_key[pos] = key;
-        gs.cand_v[pos] = v;
+#pragma unroll
+      for (int u = 0; u < kSelIlp; ++u) {
+        const bool pred = base + u * kFinishThreads + t < m && (kk[u] >> 51) == pre;
+        const int pos = wave_append(&s_cnt, pred);
+        if (pred) {
+          gs.cand_key[pos] = kk[u];
+          gs.cand_v[pos] = vv[u];
+        }
       }
     }
   }
@@ -130,9 +133,19 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
     for (int d = t; d < kDigits; d += kFinishThreads) sm.h[d] = 0u;
     __syncthreads();
     const unsigned long long pre = s_prefix;
-    for (int i = t; i < cnt; i += kFinishThreads) {
-      const unsigned long long key = gs.cand_key[i];
-      if ((key >> hishift) == pre) atomicAdd(&sm.h[(key >> shift) & ((1u << width) - 1u)], 1u);
+    for (int i0 = 0; i0 < cnt; i0 += kSelIlp * kFinishThreads) {
+      unsigned long long kk[kSelIlp];
+#pragma unroll
+      for (int u = 0; u < kSelIlp; ++u) {
+        const int i = i0 + u * kFinishThreads + t;
+        kk[u] = i < cnt ? gs.cand_key[i] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < kSelIlp; ++u) {
+        const int i = i0 + u * kFinishThreads + t;
+        wave_hist_add(sm.h, (unsigned)((kk[u] >> shift) & ((1u << width) - 1u)),
+                      i < cnt && (kk[u] >> hishift) == pre);
+      }
     }
     __syncthreads();
     bk = find_bucket(sm.h, 1 << width, s_need, true);
