@@ -40,19 +40,19 @@ __device__ __forceinline__ int wave_append(int* counter, bool pred) {
   return base + __popcll(mask & lanemask_lt());
 }
 
-// Histogram increment of a wave: h[d] += 1 for every lane with pred, one LDS
-// atomic per distinct digit in the wave (the keys of a selection share their
-// leading digits, so per-lane atomics would queue on a few addresses).  Every
+// Histogram increment of a wave: h[d] += 1 for every lane with pred.  The
+// lanes that share the first active lane's digit add with one LDS atomic (when
+// keys share their leading digits, per-lane atomics would queue on one
+// address); the others add one by one (spread digits do not collide).  Every
 // lane of the wave must call it.
 __device__ __forceinline__ void wave_hist_add(unsigned* h, unsigned d, bool pred) {
-  unsigned long long pending = __ballot(pred);
-  while (pending) {
-    const int leader = __ffsll((long long)pending) - 1;
-    const unsigned dl = __shfl(d, leader);
-    const unsigned long long same = __ballot(pred && d == dl) & pending;
-    if (lane_id() == leader) atomicAdd(&h[dl], (unsigned)__popcll(same));
-    pending &= ~same;
-  }
+  const unsigned long long active = __ballot(pred);
+  if (!active) return;
+  const int leader = __ffsll((long long)active) - 1;
+  const unsigned dl = __shfl(d, leader);
+  const unsigned long long same = __ballot(pred && d == dl);
+  if (lane_id() == leader) atomicAdd(&h[dl], (unsigned)__popcll(same));
+  else if (pred && d != dl) atomicAdd(&h[d], 1u);
 }
 
 template <bool F32> struct Prec;

@@ -29,8 +29,6 @@ __device__ void refresh_bounds(BoundArgs& b, const GraphSel& gs, int r) {
   }
 }
 
-__device__ __forceinline__ int gs_ext(const GraphSel& gs, int v) { return gs.ext_of ? gs.ext_of[v] : v; }
-__device__ __forceinline__ int gs_int(const GraphSel& gs, int e) { return gs.int_of ? gs.int_of[e] : e; }
 
 constexpr int kSelIlp = 4;   // nodes per thread and pass of the key and deactivation passes
 
@@ -52,109 +50,161 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
   const bool identity = r_dev ? (b.r == 1) : gs.identity_in;
   const int m = identity ? gs.n : sc->m;
   const int k = gs.k;
+  // The graph's arrays and sizes as locals: read from gs once, not again after
+  // every store (gs may sit in global memory, which the stores could alias).
+  const int base_id = gs.base;
+  const int n_g = gs.n;
+  unsigned long long* const keys = gs.keys;
+  unsigned long long* const cand_key = gs.cand_key;
+  int32_t* const cand_v = gs.cand_v;
+  const int32_t* const ext_of = gs.ext_of;
+  const int32_t* const int_of = gs.int_of;
+  int32_t* const top_sorted = gs.top_sorted;
+  double* const top_lo = gs.top_lo;
+  double* const top_up = gs.top_up;
+  auto ext = [ext_of](int v) { return ext_of ? ext_of[v] : v; };
   const int t = threadIdx.x;
 
   __shared__ union {
     unsigned h[kDigits];
     SortArea srt;
   } sm;
-  __shared__ unsigned long long s_prefix;
+  __shared__ unsigned long long s_prefix, s_kmin, s_kmax;
   __shared__ int s_need, s_count, s_cnt, s_top, s_kept, s_fail, s_prog, s_idpre, s_idneed;
 
-  // Keys of M and the histogram of their top digit (bits 62..51).
-  for (int d = t; d < kDigits; d += kFinishThreads) sm.h[d] = 0u;
+  // Keys of M, with their minimum and maximum: the bits above the highest bit
+  // in which two keys differ are common to all keys, so the radix digits start
+  // right below them (the keys of one graph often share their exponent, and a
+  // digit inside it would leave every node a candidate).  Every digit choice
+  // finds the same k-th key.
   if (t == 0) {
     s_cnt = 0;
     s_top = 0;
     s_kept = 0;
     s_fail = 0;
     s_prog = 0;
+    s_kmin = ~0ull;
+    s_kmax = 0ull;
   }
   __syncthreads();
-  // Four nodes per thread and pass, their loads issued together (a slot past
-  // the end evaluates node base, a valid index, and is dropped).
-  for (int b0 = 0; b0 < m; b0 += kSelIlp * kFinishThreads) {   // same trip count for every thread
-    const int i0 = b0 + t;
-    unsigned long long kk[kSelIlp];
-#pragma unroll
-    for (int u = 0; u < kSelIlp; ++u) {
-      const int i = i0 + u * kFinishThreads;
-      const int v = i < m ? (identity ? gs.base + i : act_in[i]) : gs.base;
-      double lo, up;
-      bound_eval(b, v, lo, up);
-      kk[u] = key_of(lo);
-    }
-#pragma unroll
-    for (int u = 0; u < kSelIlp; ++u) {
-      const int i = i0 + u * kFinishThreads;
-      if (i < m) gs.keys[i] = kk[u];
-      wave_hist_add(sm.h, (unsigned)((kk[u] >> 51) & (kDigits - 1)), i < m);
-    }
-  }
-  __syncthreads();
-  Bucket bk = find_bucket(sm.h, kDigits, k, true);
-  if (t == 0) {
-    s_prefix = (unsigned long long)bk.b;
-    s_need = bk.need;
-    s_count = bk.count;
-  }
-  __syncthreads();
-  // Candidates: the nodes whose top digit is the k-th key's (four per thread
-  // and pass, loads first).
   {
-    const unsigned long long pre = s_prefix;
-    for (int base = 0; base < m; base += kSelIlp * kFinishThreads) {
+    unsigned long long kmin = ~0ull, kmax = 0ull;
+    // Four nodes per thread and pass, their loads issued together (a slot past
+    // the end evaluates node base, a valid index, and is dropped).
+    for (int b0 = 0; b0 < m; b0 += kSelIlp * kFinishThreads) {   // same trip count for every thread
+      unsigned long long kk[kSelIlp];
+#pragma unroll
+      for (int u = 0; u < kSelIlp; ++u) {
+        const int i = b0 + u * kFinishThreads + t;
+        const int v = i < m ? (identity ? base_id + i : act_in[i]) : base_id;
+        double lo, up;
+        bound_eval(b, v, lo, up);
+        kk[u] = key_of(lo);
+      }
+#pragma unroll
+      for (int u = 0; u < kSelIlp; ++u) {
+        const int i = b0 + u * kFinishThreads + t;
+        if (i < m) {
+          keys[i] = kk[u];
+          kmin = kk[u] < kmin ? kk[u] : kmin;
+          kmax = kk[u] > kmax ? kk[u] : kmax;
+        }
+      }
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+      const unsigned long long a = __shfl_xor(kmin, o), c = __shfl_xor(kmax, o);
+      kmin = a < kmin ? a : kmin;
+      kmax = c > kmax ? c : kmax;
+    }
+    if (lane_id() == 0) {
+      atomicMin(&s_kmin, kmin);
+      atomicMax(&s_kmax, kmax);
+    }
+  }
+  __syncthreads();
+  const unsigned long long kdiff = s_kmin ^ s_kmax;
+  int rem = kdiff ? 64 - __clzll((long long)kdiff) : 0;   // low bits still to resolve
+  if (rem > 63) rem = 63;                                   // keys of non-negative bounds are below 2^63
+  unsigned long long pre = m > 0 ? (s_kmin >> rem) : 0ull;  // resolved high bits of the k-th key
+  // Level 0 over M: histogram of the first digit below the common bits, then
+  // the candidates, the nodes in the k-th key's bucket.
+  {
+    const int w = min(kDigitBits, rem);
+    const int shift = rem - w;
+    for (int d = t; d < kDigits; d += kFinishThreads) sm.h[d] = 0u;
+    __syncthreads();
+    for (int b0 = 0; b0 < m; b0 += kSelIlp * kFinishThreads) {
+      unsigned long long kk[kSelIlp];
+#pragma unroll
+      for (int u = 0; u < kSelIlp; ++u) {
+        const int i = b0 + u * kFinishThreads + t;
+        kk[u] = i < m ? keys[i] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < kSelIlp; ++u)
+        wave_hist_add(sm.h, (unsigned)((kk[u] >> shift) & ((1u << w) - 1u)), b0 + u * kFinishThreads + t < m);
+    }
+    __syncthreads();
+    const Bucket bk = find_bucket(sm.h, 1 << w, k, true);
+    if (t == 0) {
+      s_prefix = (pre << w) | (unsigned)bk.b;
+      s_need = bk.need;
+      s_count = bk.count;
+    }
+    __syncthreads();
+    pre = s_prefix;
+    rem = shift;
+    for (int b0 = 0; b0 < m; b0 += kSelIlp * kFinishThreads) {
       unsigned long long kk[kSelIlp];
       int vv[kSelIlp];
 #pragma unroll
       for (int u = 0; u < kSelIlp; ++u) {
-        const int i = base + u * kFinishThreads + t;
-        kk[u] = i < m ? gs.keys[i] : 0ull;
-        vv[u] = i < m ? (identity ? gs.base + i : act_in[i]) : 0;
+        const int i = b0 + u * kFinishThreads + t;
+        kk[u] = i < m ? keys[i] : 0ull;
+        vv[u] = i < m ? (identity ? base_id + i : act_in[i]) : 0;
       }
 #pragma unroll
       for (int u = 0; u < kSelIlp; ++u) {
-        const bool pred = base + u * kFinishThreads + t < m && (kk[u] >> 51) == pre;
+        const bool pred = b0 + u * kFinishThreads + t < m && (kk[u] >> rem) == pre;
         const int pos = wave_append(&s_cnt, pred);
         if (pred) {
-          gs.cand_key[pos] = kk[u];
-          gs.cand_v[pos] = vv[u];
+          cand_key[pos] = kk[u];
+          cand_v[pos] = vv[u];
         }
       }
     }
   }
   __syncthreads();
   const int cnt = s_cnt;
-  // Remaining digits: 50..39, 38..27, 26..15, 14..3, 2..0.
-  for (int level = 1; level < kSelectLevels; ++level) {
-    const int shift = level < 5 ? 51 - kDigitBits * level : 0;
-    const int width = level < 5 ? kDigitBits : 3;
-    const int hishift = shift + width;
+  // Remaining digits over the candidates, at most 12 bits each.
+  while (rem > 0) {
+    const int w = min(kDigitBits, rem);
+    const int shift = rem - w;
     for (int d = t; d < kDigits; d += kFinishThreads) sm.h[d] = 0u;
     __syncthreads();
-    const unsigned long long pre = s_prefix;
     for (int i0 = 0; i0 < cnt; i0 += kSelIlp * kFinishThreads) {
       unsigned long long kk[kSelIlp];
 #pragma unroll
       for (int u = 0; u < kSelIlp; ++u) {
         const int i = i0 + u * kFinishThreads + t;
-        kk[u] = i < cnt ? gs.cand_key[i] : 0ull;
+        kk[u] = i < cnt ? cand_key[i] : 0ull;
       }
 #pragma unroll
       for (int u = 0; u < kSelIlp; ++u) {
         const int i = i0 + u * kFinishThreads + t;
-        wave_hist_add(sm.h, (unsigned)((kk[u] >> shift) & ((1u << width) - 1u)),
-                      i < cnt && (kk[u] >> hishift) == pre);
+        wave_hist_add(sm.h, (unsigned)((kk[u] >> shift) & ((1u << w) - 1u)), i < cnt && (kk[u] >> rem) == pre);
       }
     }
     __syncthreads();
-    bk = find_bucket(sm.h, 1 << width, s_need, true);
+    const Bucket bk = find_bucket(sm.h, 1 << w, s_need, true);
     if (t == 0) {
-      s_prefix = (pre << width) | (unsigned)bk.b;
+      s_prefix = (pre << w) | (unsigned)bk.b;
       s_need = bk.need;
       s_count = bk.count;
     }
     __syncthreads();
+    pre = s_prefix;
+    rem = shift;
   }
   const unsigned long long theta_key = s_prefix;
   const double theta = __longlong_as_double((long long)theta_key);
@@ -175,17 +225,17 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
       shift -= width;
       for (int d = t; d < kDigits; d += kFinishThreads) sm.h[d] = 0u;
       __syncthreads();
-      const int pre = s_idpre;
+      const int idpre = s_idpre;
       for (int i = t; i < cnt; i += kFinishThreads) {
-        if (gs.cand_key[i] != theta_key) continue;
-        const int e = gs_ext(gs, gs.cand_v[i]);
-        if ((hishift >= 31 ? 0 : (e >> hishift)) == pre) atomicAdd(&sm.h[(e >> shift) & ((1 << width) - 1)], 1u);
+        if (cand_key[i] != theta_key) continue;
+        const int e = ext(cand_v[i]);
+        if ((hishift >= 31 ? 0 : (e >> hishift)) == idpre) atomicAdd(&sm.h[(e >> shift) & ((1 << width) - 1)], 1u);
       }
       __syncthreads();
-      bk = find_bucket(sm.h, 1 << width, s_idneed, false);
+      const Bucket ib = find_bucket(sm.h, 1 << width, s_idneed, false);
       if (t == 0) {
-        s_idpre = (pre << width) | bk.b;
-        s_idneed = bk.need;
+        s_idpre = (idpre << width) | ib.b;
+        s_idneed = ib.need;
       }
       __syncthreads();
     }
@@ -202,11 +252,11 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
       for (int u = 0; u < kSelIlp; ++u) {
         const int i = base + u * kFinishThreads + t;
         const bool valid = i < m;
-        const int v = valid ? (identity ? gs.base + i : act_in[i]) : gs.base;
-        const unsigned long long key = valid ? gs.keys[i] : 0ull;
+        const int v = valid ? (identity ? base_id + i : act_in[i]) : base_id;
+        const unsigned long long key = valid ? keys[i] : 0ull;
         double lo, up;
         bound_eval(b, v, lo, up);
-        top[u] = valid && (key > theta_key || (key == theta_key && gs_ext(gs, v) <= cut));
+        top[u] = valid && (key > theta_key || (key == theta_key && ext(v) <= cut));
         keep[u] = valid && !top[u] && !(up - b.eps < theta);
         if ((top[u] || keep[u]) && can_progress(b, v)) prog = true;
         vv[u] = v;
@@ -216,7 +266,7 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
         const int pt = wave_append(&s_top, top[u]);
         if (top[u] && pt < k) act_out[pt] = vv[u];
         const int pk = wave_append(&s_kept, keep[u]);
-        if (keep[u] && k + pk < gs.n) act_out[k + pk] = vv[u];
+        if (keep[u] && k + pk < n_g) act_out[k + pk] = vv[u];
       }
     }
     if (prog) s_prog = 1;
@@ -241,7 +291,7 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
       double lo, up;
       bound_eval(b, v, lo, up);
       sm.srt.key[i] = key_of(lo);
-      sm.srt.ext[i] = gs_ext(gs, v);
+      sm.srt.ext[i] = ext(v);
     } else {
       sm.srt.key[i] = 0ull;
       sm.srt.ext[i] = INT_MAX;
@@ -268,12 +318,12 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
     }
   }
   for (int i = t; i < (need_sort ? k : 0); i += kFinishThreads) {
-    const int v = gs_int(gs, sm.srt.ext[i]);
+    const int v = int_of ? int_of[sm.srt.ext[i]] : sm.srt.ext[i];
     double lo, up;
     bound_eval(b, v, lo, up);
-    gs.top_sorted[i] = v;
-    gs.top_lo[i] = lo;
-    gs.top_up[i] = up;
+    top_sorted[i] = v;
+    top_lo[i] = lo;
+    top_up[i] = up;
     if (i > 0 && up - b.eps >= __longlong_as_double((long long)sm.srt.key[i - 1])) s_fail = 1;
   }
   __syncthreads();
