@@ -310,6 +310,24 @@ def bench_batched(args, katz, sg, torch, np):
         "status_counts": {str(st): sum(1 for r in res if r.status == st) for st in sorted({r.status for r in res})},
         "tuning": tuning,
     }
+    if args.tuning_sweep:
+        sweep = []
+        for bbpc, tile, xcd in [(0, 1, 0), (0, 1, 1), (4, 4, 0), (4, 4, 1), (16, 4, 0), (16, 4, 1), (16, 8, 0),
+                                (16, 8, 1), (32, 8, 1)]:
+            katz.tuning_set(**dict(tuning, batch_blocks_per_cu=bbpc, batch_tile=tile, batch_xcd=xcd))
+            katz.rank_static_batch(graphs, params)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(2):
+                r2 = katz.rank_static_batch(graphs, params)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t1) / 2 * 1e3
+            same = all(bool(torch.equal(a.topk, b.topk) and torch.equal(a.lower, b.lower)) for a, b in zip(r2, res))
+            sweep.append({"batch_blocks_per_cu": bbpc, "batch_tile": tile, "batch_xcd": xcd,
+                          "ms_per_step": round(ms, 3), "same_result": same})
+            print(f"[bench] batched sweep {bbpc}:{tile}:{xcd} {ms:.3f} ms same={same}", flush=True)
+        out["tuning_sweep"] = sweep
+        katz.tuning_set(**tuning)
     print(json.dumps(out), flush=True)
 
 

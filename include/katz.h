@@ -275,13 +275,19 @@ int katz_timing_read(katz_timing* out);
  *   batch_tile           batched form: row groups per work item of the short-row
  *                        bins (each wave sums its rows group after group, each row
  *                        still by the same lanes); 0 or 1 = one group, up to 16.
+ *   batch_xcd            batched form: 1 = give every graph to one of the eight
+ *                        XCDs (balanced by arcs) and let the workgroups that the
+ *                        hardware places on an XCD take only its graphs' work
+ *                        items, so each XCD's L2 holds the walk vectors of an
+ *                        eighth of the batch; 0 = any workgroup takes any item.
  * Defaults: all 0.  Calls already running keep the setting they started with. */
 typedef struct katz_tuning {
   int32_t hub_bytes;
   int32_t blocks_per_cu;
   int32_t batch_blocks_per_cu;
   int32_t batch_tile;
-  int32_t reserved[4];       /* must be 0 */
+  int32_t batch_xcd;         /* 0 or 1 */
+  int32_t reserved[3];       /* must be 0 */
 } katz_tuning;
 
 /* Copies the current setting; E_INVALID_ARG if t is NULL. */

@@ -174,8 +174,9 @@ int tuning_valid(const katz_tuning& t) {
   if (t.blocks_per_cu < 0 || t.blocks_per_cu > 32) return KATZ_E_INVALID_ARG;
   if (t.batch_blocks_per_cu < 0 || t.batch_blocks_per_cu > 32) return KATZ_E_INVALID_ARG;
   if (t.batch_tile < 0 || t.batch_tile > 16) return KATZ_E_INVALID_ARG;
+  if (t.batch_xcd != 0 && t.batch_xcd != 1) return KATZ_E_INVALID_ARG;
   if (t.hub_bytes > 0 && t.blocks_per_cu == 0) return KATZ_E_INVALID_ARG;
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 3; ++i)
     if (t.reserved[i] != 0) return KATZ_E_INVALID_ARG;
   return KATZ_OK;
 }
@@ -1109,6 +1110,8 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
 constexpr int kItersPerGraph = 4;   // iterations captured in one hipGraph
 
 int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* out, hipStream_t s) {
+  const katz_tuning tu_b = current_tuning();   // one setting for the whole call
+  const int xcd_groups = tu_b.batch_xcd ? kXcds : 1;
   const int fp32 = p[0].precision == KATZ_FP32_MARGIN;
   long long total_n = 0, total_nnz = 0, max_n = 0, sum_k = 0;
   int max_iter = 1;
@@ -1174,6 +1177,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   int* item_g = nullptr;
   int* items = nullptr;
   int* n_items = nullptr;
+  int* xcd_of = nullptr;
   long long blk_cap = 0;
   int* r_dev = nullptr;
   int* ndone = nullptr;
@@ -1228,8 +1232,9 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     blk_g = ar.take<int>(blk_cap);
     blk_m = ar.take<double>(blk_cap);
     item_g = ar.take<int>(blk_cap);
-    items = ar.take<int>(blk_cap);
-    n_items = ar.take<int>(1);
+    items = ar.take<int>(blk_cap * xcd_groups);
+    n_items = ar.take<int>(kXcds);
+    xcd_of = ar.take<int>(count);
     r_dev = ar.take<int>(1);
     ndone = ar.take<int>(1);
     o_ids = ar.take<int32_t*>(count);
@@ -1427,7 +1432,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   bw.desc = b.desc;
   bw.segs = b.segs;
   bw.huge = b.huge;
-  const int tile = std::max(1, current_tuning().batch_tile);
+  const int tile = std::max(1, tu_b.batch_tile);
   {
     // Work items per bin: one per segment / long row, `tile` row groups
     // otherwise (a row group is one workgroup's worth of rows).
@@ -1469,9 +1474,28 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   bw.item_g = item_g;
   bw.items = items;
   bw.n_items = n_items;
+  bw.xcd_groups = xcd_groups;
+  bw.item_cap = blk_cap;
+  bw.xcd_of = xcd_of;
+  std::vector<int> h_xcd(count, 0);
+  if (xcd_groups > 1) {
+    // Graphs to XCDs, largest first, each to the least loaded (by arcs).
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a2, int b2) { return g[a2].nnz > g[b2].nnz; });
+    long long load[kXcds] = {};
+    for (int i : order) {
+      int best = 0;
+      for (int x = 1; x < kXcds; ++x)
+        if (load[x] < load[best]) best = x;
+      h_xcd[i] = best;
+      load[best] += g[i].nnz + g[i].n;
+    }
+  }
+  KATZ_HIP(hipMemcpyAsync(xcd_of, h_xcd.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
   bw.fp32 = fp32;
   const long long total_blocks = bw.first_block[NUM_BINS];
-  long long walk_grid = (long long)current_tuning().batch_blocks_per_cu * cu_count(dev);
+  long long walk_grid = (long long)tu_b.batch_blocks_per_cu * cu_count(dev);
   if (walk_grid > 0) walk_grid = std::min(walk_grid, batch_walk_resident(fp32));
   {
     const long long nh = b.bin_count[BIN_HUGE];
@@ -1491,7 +1515,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     }
   } guard{cs};
   KATZ_HIP(launch_batch_item_graphs(bw, total_blocks, item_g, s));
-  KATZ_HIP(hipMemsetAsync(n_items, 0, sizeof(int), s));
+  KATZ_HIP(hipMemsetAsync(n_items, 0, sizeof(int) * kXcds, s));
   KATZ_HIP(hipStreamSynchronize(s));
   KATZ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   for (int it = 0; it < kItersPerGraph; ++it) {
@@ -2190,7 +2214,8 @@ KATZ_EXPORT int katz_autotune(int32_t count, const katz_csr* g, const katz_param
   static const int kSingle[][2] = {{0, 0},        {0, 4},        {0, 8},        {0, 16},      {16384, 4},
                                    {20416, 8},    {24512, 6},    {32704, 5},    {32768, 4},   {40896, 4},
                                    {54208, 3},    {65536, 2}};
-  static const int kBatch[][2] = {{0, 1}, {4, 1}, {16, 1}, {4, 2}, {16, 2}, {4, 4}, {16, 4}, {16, 8}};
+  static const int kBatch[][3] = {{0, 1, 0}, {4, 1, 0},  {16, 1, 0}, {4, 2, 0}, {16, 2, 0}, {4, 4, 0}, {16, 4, 0},
+                                  {16, 8, 0}, {0, 1, 1},  {16, 1, 1}, {4, 4, 1}, {16, 4, 1}, {16, 8, 1}};
   const katz_tuning saved = katz::current_tuning();
   int32_t* ids = nullptr;
   double *lo = nullptr, *up = nullptr;
@@ -2216,6 +2241,7 @@ KATZ_EXPORT int katz_autotune(int32_t count, const katz_csr* g, const katz_param
       katz_tuning t = saved;
       t.batch_blocks_per_cu = c[0];
       t.batch_tile = c[1];
+      t.batch_xcd = c[2];
       cand.push_back(t);
     }
   }

@@ -369,10 +369,15 @@ __global__ void __launch_bounds__(kWG) walk_batch(BatchWalk a) {
   using T = typename Prec<F32>::T;
   const int r = *a.r_dev;
   if (r >= a.stride) return;
-  const long long n_items = *a.n_items;
+  // With XCD lists, the workgroups that the hardware places on XCD x (ids
+  // x, x + 8, ...) take the items of list x only.
+  const int x = blockIdx.x % a.xcd_groups;
+  const long long n_items = a.n_items[x];
+  const int* list = a.items + (long long)x * a.item_cap;
+  const long long step = gridDim.x / a.xcd_groups;
   const T* xin = reinterpret_cast<const T*>(a.xbuf[(r + 1) & 1]);
-  for (long long t = blockIdx.x; t < n_items; t += gridDim.x) {
-    const long long b = a.items[t];
+  for (long long t = blockIdx.x / a.xcd_groups; t < n_items; t += step) {
+    const long long b = list[t];
     const int gi = a.item_g[b];
     double vmax = 0.0;
     int g_mine = -1;
@@ -466,18 +471,35 @@ __global__ void __launch_bounds__(kWG) batch_item_graphs(BatchWalk a, long long 
 
 // This iteration's work items: those whose graph is still iterating, and every
 // item with rows of several graphs.  One atomic per workgroup appends the
-// workgroup's items (their order does not matter: each writes its own slot).
+// workgroup's items (their order does not matter: each writes its own slot);
+// with XCD lists, one atomic per wave and list.
 __global__ void __launch_bounds__(kWG) batch_live_items(BatchWalk a, long long total, int* items, int* n_items) {
   const int r = *a.r_dev;
   if (r >= a.stride) return;
   const long long b = (long long)blockIdx.x * kWG + threadIdx.x;
   bool keep = false;
+  int x = 0;
   if (b < total) {
     const int g = a.item_g[b];
     keep = g < 0 || graph_live<true>(a, g);
+    if (a.xcd_groups > 1) x = g >= 0 ? a.xcd_of[g] : (int)(b % a.xcd_groups);
   }
-  const int pos = block_reserve(n_items, keep ? 1u : 0u);
-  if (keep) items[pos] = (int)b;
+  if (a.xcd_groups == 1) {
+    const int pos = block_reserve(n_items, keep ? 1u : 0u);
+    if (keep) items[pos] = (int)b;
+    return;
+  }
+  unsigned long long pending = __ballot(keep);
+  while (pending) {                                    // at most one round per list
+    const int leader = __ffsll((long long)pending) - 1;
+    const int xl = __shfl(x, leader);
+    const unsigned long long same = __ballot(keep && x == xl) & pending;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(&n_items[xl], __popcll(same));
+    base = __shfl(base, leader);
+    if ((same >> lane_id()) & 1ull) items[(long long)xl * a.item_cap + base + __popcll(same & lanemask_lt())] = (int)b;
+    pending &= ~same;
+  }
 }
 
 // Rows longer than one segment: one wave per row of a live graph adds the
@@ -547,7 +569,7 @@ __global__ void __launch_bounds__(kFinishThreads) batch_advance(int* r_dev, int 
   if (threadIdx.x == 0) {
     *r_dev = r + 1;
     *ndone = s_done;
-    *n_items = 0;        // the next iteration's list is rebuilt from zero
+    for (int x = 0; x < kXcds; ++x) n_items[x] = 0;   // the next iteration's lists are rebuilt from zero
   }
 }
 
@@ -789,7 +811,12 @@ long long batch_walk_resident(int fp32) {
 hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, long long max_grid, long long n_huge,
                              hipStream_t s) {
   const long long items = std::max<long long>(1, total_blocks);
-  const unsigned grid = (unsigned)(max_grid > 0 ? std::min(items, max_grid) : items);   // max_grid: see batch_walk_resident
+  long long g = max_grid > 0 ? std::min(items, max_grid) : items;   // max_grid: see batch_walk_resident
+  // Every XCD gets the same number of workgroups (a persistent grid rounds
+  // down, staying within the resident count; one per item rounds up).
+  g = max_grid > 0 ? std::max<long long>(a.xcd_groups, g / a.xcd_groups * a.xcd_groups)
+                   : (g + a.xcd_groups - 1) / a.xcd_groups * a.xcd_groups;
+  const unsigned grid = (unsigned)g;
   BatchWalk w = a;
   w.blk_base = 0;
   if (a.fp32) hipLaunchKernelGGL(walk_batch<true>, dim3(grid), dim3(kWG), 0, s, w);

@@ -28,6 +28,7 @@
 namespace katz {
 
 constexpr int kWG = 256;                 // threads per workgroup (4 waves of 64)
+constexpr int kXcds = 8;                 // XCDs of an MI355X; workgroups go to them round-robin by id
 constexpr int kWave = 64;
 constexpr int kPerLane = 16;             // max row elements summed serially per lane
 constexpr int kSeg = kWG * kPerLane;     // arcs per huge-row segment (4096)
@@ -253,14 +254,17 @@ struct BatchWalk {
   const double* etap;           // eta'_r per graph: [count][stride]
   const int* r_dev;
   const int* item_g;            // per work item: the graph of all its rows, or -1 (rows of several graphs)
-  const int* items;             // work items of this iteration (live graphs only), *n_items of them
-  const int* n_items;
+  const int* items;             // work items of this iteration (live graphs only), n_items[x] in list x
+  const int* n_items;           // [kXcds]
   int* blk_g;                   // per workgroup: graph of all its rows, or -1
   double* blk_m;                // per workgroup: maximum new walk entry of that graph
   long long blk_base;           // first slot of this launch in blk_g / blk_m
   int count;                    // graphs in the batch
   int direct_max;               // 1: workgroups update per-graph maxima with atomics
   int tile;                     // row groups per work item in the short-row bins
+  int xcd_groups;               // 1, or kXcds: work-item lists per XCD (items + x * item_cap)
+  long long item_cap;           // capacity of one work-item list
+  const int* xcd_of;            // per graph: the XCD whose workgroups take its items
   int stride;
   int fp32;
 };

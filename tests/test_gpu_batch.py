@@ -132,9 +132,9 @@ def test_batch_launch_tuning_is_invisible(precision):
     try:
         katz.tuning_set(**dict(saved, batch_blocks_per_cu=0, batch_tile=0))
         ref = run_batch(graphs, params, precision)
-        for bbpc, tile in ((1, 1), (4, 3), (32, 2), (0, 16)):
-            say("batch tuning", precision, bbpc, tile)
-            katz.tuning_set(**dict(saved, batch_blocks_per_cu=bbpc, batch_tile=tile))
+        for bbpc, tile, xcd in ((1, 1, 0), (4, 3, 0), (32, 2, 0), (0, 16, 0), (0, 1, 1), (4, 3, 1), (32, 1, 1)):
+            say("batch tuning", precision, bbpc, tile, xcd)
+            katz.tuning_set(**dict(saved, batch_blocks_per_cu=bbpc, batch_tile=tile, batch_xcd=xcd))
             res = run_batch(graphs, params, precision)
             for a, b in zip(res, ref):
                 assert torch.equal(a.topk, b.topk) and torch.equal(a.lower, b.lower) and torch.equal(a.upper, b.upper)
@@ -142,8 +142,9 @@ def test_batch_launch_tuning_is_invisible(precision):
         gl = [(torch.from_numpy(np.asarray(r, dtype=np.int64)).cuda(), torch.from_numpy(c).cuda(), True)
               for r, c in graphs]
         best = katz.autotune_batch(gl, [dict(pp, precision=precision) for pp in params])
-        assert (best["batch_blocks_per_cu"], best["batch_tile"]) in ((0, 1), (4, 1), (16, 1), (4, 2), (16, 2), (4, 4),
-                                                                     (16, 4), (16, 8))
+        assert (best["batch_blocks_per_cu"], best["batch_tile"], best["batch_xcd"]) in (
+            (0, 1, 0), (4, 1, 0), (16, 1, 0), (4, 2, 0), (16, 2, 0), (4, 4, 0), (16, 4, 0), (16, 8, 0), (0, 1, 1),
+            (16, 1, 1), (4, 4, 1), (16, 4, 1), (16, 8, 1))
         assert katz.tuning_get() == best
     finally:
         katz.tuning_set(**saved)
