@@ -90,7 +90,7 @@ def main():
     ap.add_argument("--batched-max-log2n", type=int, default=18, help="batched: n is log-uniform in [2^10, 2^this]")
     ap.add_argument("--tuning", default="auto",
                     help="walk launch shape: 'auto' (katz_autotune per precision before timing), "
-                         "or HUB_BYTES:BLOCKS_PER_CU for both precisions")
+                         "or HUB_BYTES:BLOCKS_PER_CU[:WALK_GROUPS] for both precisions")
     ap.add_argument("--tuning-sweep", action="store_true",
                     help="static: also time every autotuner candidate (FP32) and report them")
     args = ap.parse_args()
@@ -134,8 +134,8 @@ def main():
         if args.tuning == "auto":
             tunings[precision] = katz.autotune(rp_t, col_t, K, eps=EPS, precision=precision)
         else:
-            hub, bpc = (int(v) for v in args.tuning.split(":"))
-            katz.tuning_set(hub, bpc)
+            parts = [int(v) for v in args.tuning.split(":")]
+            katz.tuning_set(parts[0], parts[1], walk_groups=parts[2] if len(parts) > 2 else 0)
             tunings[precision] = katz.tuning_get()
         print(f"[bench] {precision} tuning {tunings[precision]}", flush=True)
         res, sec, tm = time_form(katz, torch, rp_t, col_t, precision, args.steps, args.warmup)
@@ -201,7 +201,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "walk_step<fp32>",
+            "kernel": "walk_step_grouped<fp32>" if tunings["fp32"].get("walk_groups") == 4 else "walk_step<fp32>",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -222,20 +222,22 @@ def main():
     }
     same = bool(torch.equal(f32["res"].topk, f64["res"].topk))
     out["fp32_fp64_same_topk"] = same
-    out["tuning"] = {p: dict(t, arg=f"{t['hub_bytes']}:{t['blocks_per_cu']}") for p, t in tunings.items()}
+    out["tuning"] = {p: dict(t, arg=f"{t['hub_bytes']}:{t['blocks_per_cu']}:{t['walk_groups']}")
+                     for p, t in tunings.items()}
     out["roofline"]["traffic"], out["roofline"]["traffic_note"] = measured_traffic(out["tuning"]["fp32"]["arg"])
     if args.tuning_sweep:
         sweep = []
-        for hub, bpc in [(0, 0), (0, 4), (0, 8), (0, 16), (16384, 4), (16384, 8), (20416, 8), (24512, 6),
-                         (32704, 5), (32768, 4), (40896, 4), (54208, 3), (65536, 2)]:
-            katz.tuning_set(hub, bpc)
+        for hub, bpc, grp in [(0, 0, 0), (0, 4, 0), (0, 8, 0), (0, 16, 0), (16384, 4, 0), (24512, 6, 0),
+                              (32768, 4, 0), (40896, 4, 0), (65536, 2, 0), (65536, 1, 4), (98304, 1, 4),
+                              (131072, 1, 4), (159744, 1, 4)]:
+            katz.tuning_set(hub, bpc, walk_groups=grp)
             r_s, sec_s, tm_s = time_form(katz, torch, rp_t, col_t, "fp32", max(1, args.steps // 2), 1)
             walk_us = tm_s["walk_step_ms"] / max(tm_s["calls"] * (r_s.iterations - 2), 1) * 1e3
-            sweep.append({"hub_bytes": hub, "blocks_per_cu": bpc, "ms_per_step": round(sec_s * 1e3, 4),
+            sweep.append({"hub_bytes": hub, "blocks_per_cu": bpc, "walk_groups": grp, "ms_per_step": round(sec_s * 1e3, 4),
                           "walk_step_avg_us": round(walk_us, 2),
                           "same_result": bool(torch.equal(r_s.topk, f32["res"].topk)
                                               and torch.equal(r_s.lower, f32["res"].lower))})
-            print(f"[bench] sweep {hub}:{bpc} {sec_s * 1e3:.3f} ms/step walk_step {walk_us:.1f} us", flush=True)
+            print(f"[bench] sweep {hub}:{bpc}:{grp} {sec_s * 1e3:.3f} ms/step walk_step {walk_us:.1f} us", flush=True)
         out["tuning_sweep_fp32"] = sweep
         katz.tuning_set(**tunings["fp32"])
 

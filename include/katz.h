@@ -265,7 +265,8 @@ int katz_timing_read(katz_timing* out);
  *                        renumbering: bytes of LDS per workgroup that hold a
  *                        copy of the first walk entries (after the renumbering,
  *                        the nodes with the longest rows, which most arcs point
- *                        to); 0 = no copy.  0 .. 65536, a multiple of 16.
+ *                        to); 0 = no copy.  0 .. 65536, a multiple of 16
+ *                        (0 .. 162816 with walk_groups = 4).
  *   blocks_per_cu        single-graph calls: persistent walk grid of this many
  *                        workgroups per compute unit, each taking work items
  *                        with a grid stride; 0 = one workgroup per work item.
@@ -275,6 +276,11 @@ int katz_timing_read(katz_timing* out);
  *   batch_tile           batched form: row groups per work item of the short-row
  *                        bins (each wave sums its rows group after group, each row
  *                        still by the same lanes); 0 or 1 = one group, up to 16.
+ *   walk_groups          single-graph calls: 4 = workgroups of four 256-thread
+ *                        groups that share one LDS copy of hub_bytes, each group
+ *                        working as one workgroup does (blocks_per_cu then counts
+ *                        these 1024-thread workgroups); 0 or 1 = 256-thread
+ *                        workgroups.
  *   batch_xcd            batched form: 1 = give every graph to one of the eight
  *                        XCDs (balanced by arcs) and let the workgroups that the
  *                        hardware places on an XCD take only its graphs' work
@@ -287,7 +293,8 @@ typedef struct katz_tuning {
   int32_t batch_blocks_per_cu;
   int32_t batch_tile;
   int32_t batch_xcd;         /* 0 or 1 */
-  int32_t reserved[3];       /* must be 0 */
+  int32_t walk_groups;       /* 0, 1 or 4 */
+  int32_t reserved[2];       /* must be 0 */
 } katz_tuning;
 
 /* Copies the current setting; E_INVALID_ARG if t is NULL. */

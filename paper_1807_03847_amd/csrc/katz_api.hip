@@ -170,13 +170,15 @@ katz_tuning current_tuning() {
 }
 
 int tuning_valid(const katz_tuning& t) {
-  if (t.hub_bytes < 0 || t.hub_bytes > 65536 || (t.hub_bytes & 15)) return KATZ_E_INVALID_ARG;
+  if (t.walk_groups != 0 && t.walk_groups != 1 && t.walk_groups != kWalkGroups) return KATZ_E_INVALID_ARG;
+  const int hub_max = t.walk_groups == kWalkGroups ? 162816 : 65536;
+  if (t.hub_bytes < 0 || t.hub_bytes > hub_max || (t.hub_bytes & 15)) return KATZ_E_INVALID_ARG;
   if (t.blocks_per_cu < 0 || t.blocks_per_cu > 32) return KATZ_E_INVALID_ARG;
   if (t.batch_blocks_per_cu < 0 || t.batch_blocks_per_cu > 32) return KATZ_E_INVALID_ARG;
   if (t.batch_tile < 0 || t.batch_tile > 16) return KATZ_E_INVALID_ARG;
   if (t.batch_xcd != 0 && t.batch_xcd != 1) return KATZ_E_INVALID_ARG;
   if (t.hub_bytes > 0 && t.blocks_per_cu == 0) return KATZ_E_INVALID_ARG;
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 2; ++i)
     if (t.reserved[i] != 0) return KATZ_E_INVALID_ARG;
   return KATZ_OK;
 }
@@ -531,6 +533,7 @@ struct Run {
   int grid = 1;
   int hub_n = 0;               // walk entries copied to LDS (renumbered static runs)
   long long walk_grid = 0;     // persistent walk grid (0: one workgroup per work item)
+  int walk_groups = 1;         // 256-thread groups per walk workgroup (1 or kWalkGroups)
   // Renumbered static runs: walk step 2 also renames the caller's column ids
   // into col (walk_step<F32, true>).
   bool renumber = false;
@@ -664,7 +667,11 @@ int enqueue_walk(Run& run, int r, hipStream_t s, CallTimer& T) {
   const int tw = T.start(r == 1 ? T_FIRST : renum ? T_RENUM : T_STEP, s);
   if (r == 1) KATZ_HIP(launch_walk_first(ia, run.fp32, run.n, run.nnz, run.validate >= KATZ_VALIDATE_BASIC, s));
   long long grid = 1;
-  if (r >= 2) KATZ_HIP(launch_walk_step(ia, run.fp32, tb, run.walk_grid, &grid, s, renum));
+  // The renumbering step runs 256-thread workgroups: as many of them as the
+  // tuned grid has groups.
+  if (r >= 2)
+    KATZ_HIP(launch_walk_step(ia, run.fp32, tb, renum ? run.walk_grid * run.walk_groups : run.walk_grid, &grid, s,
+                              renum, renum ? 1 : run.walk_groups));
   T.stop(tw, s);
   const long long nb = r == 1 ? std::max<long long>(1, (run.bins->count + kWG - 1) / kWG) : grid;
   KATZ_HIP(launch_reduce_blkmax(run.w->blkmax, nb, run.fp32, run.w->xmax32, run.w->xmax64, r, run.w->sc, s));
@@ -1019,6 +1026,7 @@ int rank_one(const katz_csr* g, const katz_params* p, katz_result* out, hipStrea
   {
     const katz_tuning tu = current_tuning();
     run.walk_grid = (long long)tu.blocks_per_cu * cu_count(dev);
+    run.walk_groups = tu.walk_groups == kWalkGroups ? kWalkGroups : 1;
     run.hub_n = pl.reorder ? (int)std::min<long long>(g->n, tu.hub_bytes / (pl.fp32 ? 4 : 8)) : 0;
   }
   run.bins = &b;
@@ -1080,6 +1088,7 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   {
     const katz_tuning tu = current_tuning();
     run.walk_grid = (long long)tu.blocks_per_cu * cu_count(dev);
+    run.walk_groups = tu.walk_groups == kWalkGroups ? kWalkGroups : 1;
     run.hub_n = pl.reorder ? (int)std::min<long long>(g->n, tu.hub_bytes / (pl.fp32 ? 4 : 8)) : 0;
   }
   run.bins = &b;
@@ -2209,11 +2218,13 @@ KATZ_EXPORT int katz_autotune(int32_t count, const katz_csr* g, const katz_param
     KATZ_TRY(katz::check_params(&p[i], g[i].n, true));
     sum_k += p[i].k;
   }
-  // Hub copies sized so that 3..8 workgroups fill the 160 KiB of LDS of a CU
-  // (with the kernel's own few bytes of static LDS).
-  static const int kSingle[][2] = {{0, 0},        {0, 4},        {0, 8},        {0, 16},      {16384, 4},
-                                   {20416, 8},    {24512, 6},    {32704, 5},    {32768, 4},   {40896, 4},
-                                   {54208, 3},    {65536, 2}};
+  // {hub_bytes, blocks_per_cu, walk_groups}: hub copies sized so that 3..8
+  // workgroups fill the 160 KiB of LDS of a CU (with the kernel's own few bytes
+  // of static LDS), and one 1024-thread workgroup with a copy of 64..156 KiB.
+  static const int kSingle[][3] = {{0, 0, 0},      {0, 4, 0},      {0, 8, 0},       {0, 16, 0},      {16384, 4, 0},
+                                   {20416, 8, 0},  {24512, 6, 0},  {32704, 5, 0},   {32768, 4, 0},   {40896, 4, 0},
+                                   {54208, 3, 0},  {65536, 2, 0},  {65536, 1, 4},   {98304, 1, 4},   {131072, 1, 4},
+                                   {159744, 1, 4}};
   static const int kBatch[][3] = {{0, 1, 0}, {4, 1, 0},  {16, 1, 0}, {4, 2, 0}, {16, 2, 0}, {4, 4, 0}, {16, 4, 0},
                                   {16, 8, 0}, {0, 1, 1},  {16, 1, 1}, {4, 4, 1}, {16, 4, 1}, {16, 8, 1}};
   const katz_tuning saved = katz::current_tuning();
@@ -2234,6 +2245,7 @@ KATZ_EXPORT int katz_autotune(int32_t count, const katz_csr* g, const katz_param
       katz_tuning t = saved;
       t.hub_bytes = c[0];
       t.blocks_per_cu = c[1];
+      t.walk_groups = c[2];
       cand.push_back(t);
     }
   } else {

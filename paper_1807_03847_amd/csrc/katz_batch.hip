@@ -805,7 +805,7 @@ hipError_t launch_fill_ones(void* x, long long n, int fp32, hipStream_t s) {
 // Workgroups of the batched walk kernel the device holds at once (the cap of a
 // persistent grid; queried before the iterations are captured).
 long long batch_walk_resident(int fp32) {
-  return resident_blocks(fp32 ? (const void*)walk_batch<true> : (const void*)walk_batch<false>, 0);
+  return resident_blocks(fp32 ? (const void*)walk_batch<true> : (const void*)walk_batch<false>, 0, kWG);
 }
 
 hipError_t launch_walk_batch(const BatchWalk& a, long long total_blocks, long long max_grid, long long n_huge,

@@ -28,7 +28,8 @@
 namespace katz {
 
 constexpr int kWG = 256;                 // threads per workgroup (4 waves of 64)
-constexpr int kXcds = 8;                 // XCDs of an MI355X; workgroups go to them round-robin by id
+constexpr int kXcds = 8;
+constexpr int kWalkGroups = 4;           // 256-thread groups per workgroup of walk_step_grouped                 // XCDs of an MI355X; workgroups go to them round-robin by id
 constexpr int kWave = 64;
 constexpr int kPerLane = 16;             // max row elements summed serially per lane
 constexpr int kSeg = kWG * kPerLane;     // arcs per huge-row segment (4096)
@@ -281,12 +282,15 @@ hipError_t launch_validate_strict(const RowDesc* desc, long long n, const int32_
                                   long long* row_off, int* row_len, RunScalars* sc, hipStream_t s);
 hipError_t launch_walk_first(const IterArgs& a, int fp32, long long n, long long nnz, int validate,
                              hipStream_t s);
-// renumber: walk step 2 fused with the renaming of the column ids (the
-// IterArgs renumbering fields must be set and hub_n must be 0).
-long long resident_blocks(const void* kernel, size_t lds);
+// Workgroups of `block` threads and `lds` dynamic LDS bytes of a kernel that
+// the device holds at once.
+long long resident_blocks(const void* kernel, size_t lds, int block);
 long long batch_walk_resident(int fp32);
+// renumber: walk step 2 fused with the renaming of the column ids (the
+// IterArgs renumbering fields must be set and hub_n must be 0).  groups: 1, or
+// kWalkGroups for walk_step_grouped (not with renumber).
 hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, long long max_grid,
-                            long long* grid_used, hipStream_t s, bool renumber = false);
+                            long long* grid_used, hipStream_t s, bool renumber = false, int groups = 1);
 // Reduces the per-workgroup maxima of walk iteration r into xmax32[r] / xmax64[r].
 hipError_t launch_reduce_blkmax(const void* blkmax, long long nb, int fp32, unsigned* xmax32,
                                 unsigned long long* xmax64, int r, const RunScalars* sc, hipStream_t s);

@@ -305,13 +305,16 @@ __device__ __forceinline__ Stretch row_stretch(const IterArgs& a, const RowDesc&
   else return Stretch{a.col + d.off, nullptr, d.len};
 }
 
+// tid: the thread's index in its 256-thread group (the workgroup, or one of
+// the groups of walk_step_grouped).
 template <bool F32, int G, bool Renumber>
 __device__ __forceinline__ void rows_group(const IterArgs& a, const typename Prec<F32>::T* hub, const Epi<F32>& ep,
-                                           const Epi<F32>& ep1, long long lb, int bin, double& vmax, bool stop) {
+                                           const Epi<F32>& ep1, long long lb, int bin, double& vmax, bool stop,
+                                           int tid) {
   using T = typename Prec<F32>::T;
   constexpr int RPB = kWG / G;
-  const int lane = threadIdx.x & (G - 1);
-  const long long i = lb * RPB + threadIdx.x / G;
+  const int lane = tid & (G - 1);
+  const long long i = lb * RPB + tid / G;
   const bool valid = i < a.bin_count[bin];
   RowDesc d{0, 0, 0};
   if (valid) d = a.desc[a.bin_base[bin] + i];
@@ -324,20 +327,29 @@ __device__ __forceinline__ void rows_group(const IterArgs& a, const typename Pre
   if (valid && lane == 0) epilogue<F32>(a, ep, d.row, sum, vmax, pv);
 }
 
-// Whole-workgroup sum of one row or segment: 256 strided lanes, wave
-// butterflies, then the four wave sums as (w0 + w1) + (w2 + w3).
+// Sum of one row or segment by a 256-thread group: 256 strided lanes, wave
+// butterflies, then the four wave sums as (w0 + w1) + (w2 + w3) through part
+// (the group's four LDS slots).  Contains workgroup barriers: every thread of
+// the workgroup must call it the same number of times.
 template <bool F32, bool Renumber>
-__device__ __forceinline__ typename Prec<F32>::T block_sum(const IterArgs& a, const typename Prec<F32>::T* hub,
-                                                           const Stretch& st, const Epi<F32>& ep1) {
+__device__ __forceinline__ typename Prec<F32>::T group_sum(const IterArgs& a, const typename Prec<F32>::T* hub,
+                                                           const Stretch& st, const Epi<F32>& ep1, int tid,
+                                                           typename Prec<F32>::T* part) {
   using T = typename Prec<F32>::T;
-  __shared__ T part[kWG / kWave];
-  T sum = strided_sum<F32, kWG, Renumber>(a, hub, st, threadIdx.x, ep1);
+  T sum = strided_sum<F32, kWG, Renumber>(a, hub, st, tid, ep1);
   for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
-  if (lane_id() == 0) part[threadIdx.x / kWave] = sum;
+  if (lane_id() == 0) part[tid / kWave] = sum;
   __syncthreads();
   const T tot = (part[0] + part[1]) + (part[2] + part[3]);
   __syncthreads();
   return tot;
+}
+
+template <bool F32, bool Renumber>
+__device__ __forceinline__ typename Prec<F32>::T block_sum(const IterArgs& a, const typename Prec<F32>::T* hub,
+                                                           const Stretch& st, const Epi<F32>& ep1) {
+  __shared__ typename Prec<F32>::T part[kWG / kWave];
+  return group_sum<F32, Renumber>(a, hub, st, ep1, threadIdx.x, part);
 }
 
 // Per-workgroup maximum of the new walk entries, stored without atomics (a
@@ -446,12 +458,12 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
         if (threadIdx.x == 0) epilogue<F32>(a, ep, d.row, tot, vmax, pv);
         break;
       }
-      case BIN_W64: rows_group<F32, kBinLanes[BIN_W64], Renumber>(a, hub, ep, ep1, lb, BIN_W64, vmax, stop); break;
-      case BIN_W16: rows_group<F32, kBinLanes[BIN_W16], Renumber>(a, hub, ep, ep1, lb, BIN_W16, vmax, stop); break;
-      case BIN_G32: rows_group<F32, kBinLanes[BIN_G32], Renumber>(a, hub, ep, ep1, lb, BIN_G32, vmax, stop); break;
-      case BIN_G16: rows_group<F32, kBinLanes[BIN_G16], Renumber>(a, hub, ep, ep1, lb, BIN_G16, vmax, stop); break;
-      case BIN_G8: rows_group<F32, kBinLanes[BIN_G8], Renumber>(a, hub, ep, ep1, lb, BIN_G8, vmax, stop); break;
-      case BIN_G4: rows_group<F32, kBinLanes[BIN_G4], Renumber>(a, hub, ep, ep1, lb, BIN_G4, vmax, stop); break;
+      case BIN_W64: rows_group<F32, kBinLanes[BIN_W64], Renumber>(a, hub, ep, ep1, lb, BIN_W64, vmax, stop, threadIdx.x); break;
+      case BIN_W16: rows_group<F32, kBinLanes[BIN_W16], Renumber>(a, hub, ep, ep1, lb, BIN_W16, vmax, stop, threadIdx.x); break;
+      case BIN_G32: rows_group<F32, kBinLanes[BIN_G32], Renumber>(a, hub, ep, ep1, lb, BIN_G32, vmax, stop, threadIdx.x); break;
+      case BIN_G16: rows_group<F32, kBinLanes[BIN_G16], Renumber>(a, hub, ep, ep1, lb, BIN_G16, vmax, stop, threadIdx.x); break;
+      case BIN_G8: rows_group<F32, kBinLanes[BIN_G8], Renumber>(a, hub, ep, ep1, lb, BIN_G8, vmax, stop, threadIdx.x); break;
+      case BIN_G4: rows_group<F32, kBinLanes[BIN_G4], Renumber>(a, hub, ep, ep1, lb, BIN_G4, vmax, stop, threadIdx.x); break;
       case BIN_EMPTY: {
         // Only at r = 2: the buffer of x_2 was never written for empty rows.
         const long long i = lb * kWG + threadIdx.x;
@@ -465,6 +477,100 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
     }
   }
   store_block_max<F32>(a, vmax, blockIdx.x);
+}
+
+// Walk step r >= 2 by workgroups of kWalkGroups 256-thread groups that share
+// one LDS copy of the hub entries (a larger copy than a 256-thread workgroup
+// can hold at the same number of waves per CU).  Each group works as one
+// workgroup of walk_step does, with the same lane schedule per row, so every
+// sum is bitwise the same.  Group g of workgroup w is virtual workgroup
+// w * kWalkGroups + g.  The workgroup-sum items (long-row segments, rows of
+// 1025..4096 arcs) come first and go in rounds that every group takes part in,
+// an empty share when it has no item, since those sums meet at workgroup-wide
+// barriers; the row-group items after them have no barriers.
+template <bool F32>
+__global__ void __launch_bounds__(kWG * kWalkGroups) walk_step_grouped(IterArgs a) {
+  using T = typename Prec<F32>::T;
+  constexpr int S = kWalkGroups;
+  // The flags cannot change while a walk kernel runs, so every wave of the
+  // workgroup takes the same branch here.
+  if (a.sc->err || a.sc->done) return;
+  const long long total = a.first_block[NUM_BINS];
+  const Epi<F32> ep = compute_epi<F32>(a);
+  extern __shared__ __align__(16) unsigned char walk_lds[];
+  T* hub = reinterpret_cast<T*>(walk_lds);
+  {
+    const T* x = reinterpret_cast<const T*>(a.x_in);
+    for (int i = threadIdx.x; i < a.hub_n; i += kWG * S) hub[i] = x[i];
+    __syncthreads();
+  }
+  if constexpr (F32) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.sigma[a.r] = ep.sigma_r;
+      a.sigma_sum[a.r] = a.sigma_sum[a.r - 1] + ep.sigma_r;
+    }
+  }
+  __shared__ T part[S][kWG / kWave];
+  __shared__ double wm[S][kWG / kWave];
+  const int grp = threadIdx.x / kWG;
+  const int tid = threadIdx.x % kWG;
+  const long long vb = (long long)blockIdx.x * S + grp;
+  const long long nvb = (long long)gridDim.x * S;
+  double vmax = 0.0;
+  const long long n_seg = a.first_block[BIN_B256];
+  const long long n_sum = a.first_block[BIN_W64];
+  const long long rounds = (n_sum + nvb - 1) / nvb;
+  for (long long q = 0; q < rounds; ++q) {
+    const long long b = q * nvb + vb;
+    Stretch st{a.col, nullptr, 0};
+    SegDesc sd{0, 0, 0, 0, 0};
+    RowDesc d{0, 0, 0};
+    Prev pv{0.0, 0.0f};
+    if (b < n_seg) {
+      sd = a.segs[b];
+      st = Stretch{a.col + sd.off, nullptr, sd.len};
+    } else if (b < n_sum) {
+      d = a.desc[a.bin_base[BIN_B256] + (b - n_seg)];
+      st = Stretch{a.col + d.off, nullptr, d.len};
+      if (tid == 0) pv = load_prev<F32>(a, d.row);
+    }
+    const T tot = group_sum<F32, false>(a, hub, st, ep, tid, part[grp]);
+    if (tid == 0) {
+      if (b < n_seg) reinterpret_cast<T*>(a.partial)[sd.part] = tot;
+      else if (b < n_sum) epilogue<F32>(a, ep, d.row, tot, vmax, pv);
+    }
+  }
+  for (long long b = n_sum + vb; b < total; b += nvb) {
+    int bin = BIN_W64;
+    while (bin < NUM_BINS && b >= a.first_block[bin + 1]) ++bin;
+    const long long lb = b - a.first_block[bin];
+    switch (bin) {
+      case BIN_W64: rows_group<F32, kBinLanes[BIN_W64], false>(a, hub, ep, ep, lb, BIN_W64, vmax, false, tid); break;
+      case BIN_W16: rows_group<F32, kBinLanes[BIN_W16], false>(a, hub, ep, ep, lb, BIN_W16, vmax, false, tid); break;
+      case BIN_G32: rows_group<F32, kBinLanes[BIN_G32], false>(a, hub, ep, ep, lb, BIN_G32, vmax, false, tid); break;
+      case BIN_G16: rows_group<F32, kBinLanes[BIN_G16], false>(a, hub, ep, ep, lb, BIN_G16, vmax, false, tid); break;
+      case BIN_G8: rows_group<F32, kBinLanes[BIN_G8], false>(a, hub, ep, ep, lb, BIN_G8, vmax, false, tid); break;
+      case BIN_G4: rows_group<F32, kBinLanes[BIN_G4], false>(a, hub, ep, ep, lb, BIN_G4, vmax, false, tid); break;
+      case BIN_EMPTY: {
+        const long long i = lb * kWG + tid;
+        if (i < a.bin_count[BIN_EMPTY]) {
+          const int row = a.desc[a.bin_base[BIN_EMPTY] + i].row;
+          reinterpret_cast<T*>(a.x_out)[row] = (T)0;
+        }
+        break;
+      }
+      default: break;
+    }
+  }
+  // Per-group maxima, one slot per virtual workgroup.
+  for (int o = 32; o >= 1; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
+  if (lane_id() == 0) wm[grp][tid / kWave] = vmax;
+  __syncthreads();
+  if (tid == 0) {
+    const double m = fmax(fmax(wm[grp][0], wm[grp][1]), fmax(wm[grp][2], wm[grp][3]));
+    if constexpr (F32) reinterpret_cast<float*>(a.blkmax)[vb] = (float)m;
+    else reinterpret_cast<double*>(a.blkmax)[vb] = m;
+  }
 }
 
 // Rows longer than one segment: one wave per row adds the row's segment
@@ -1069,21 +1175,21 @@ hipError_t launch_reduce_blkmax(const void* blkmax, long long nb, int fp32, unsi
 // *blocks_used: workgroup maxima written to a.blkmax (both launches).
 // Workgroups of a kernel that the device holds at once: a persistent grid
 // larger than this would run its last workgroups after all the others.
-long long resident_blocks(const void* kernel, size_t lds) {
+long long resident_blocks(const void* kernel, size_t lds, int block) {
   static std::mutex mu;
-  static std::map<std::tuple<int, const void*, size_t>, long long> cache;
+  static std::map<std::tuple<int, const void*, size_t, int>, long long> cache;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     (void)hipGetLastError();
     return LLONG_MAX;
   }
   std::lock_guard<std::mutex> lk(mu);
-  const auto key = std::make_tuple(dev, kernel, lds);
+  const auto key = std::make_tuple(dev, kernel, lds, block);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
   int per_cu = 0, cus = 0;
   long long v = LLONG_MAX;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWG, lds) == hipSuccess &&
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) == hipSuccess &&
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && per_cu > 0 && cus > 0)
     v = (long long)per_cu * cus;
   else
@@ -1093,29 +1199,42 @@ long long resident_blocks(const void* kernel, size_t lds) {
 }
 
 hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, long long max_grid,
-                            long long* blocks_used, hipStream_t s, bool renumber) {
+                            long long* blocks_used, hipStream_t s, bool renumber, int groups) {
   long long g = total_blocks > 0 ? total_blocks : 1;
   const size_t lds = (size_t)a.hub_n * (fp32 ? sizeof(float) : sizeof(double));
-  if (max_grid > 0) {
-    const void* k = renumber ? (fp32 ? (const void*)walk_step<true, true> : (const void*)walk_step<false, true>)
-                             : (fp32 ? (const void*)walk_step<true, false> : (const void*)walk_step<false, false>);
-    g = std::min(g, std::min(max_grid, resident_blocks(k, renumber ? 0 : lds)));
-  }
   if (a.hub_n > 0 && max_grid <= 0) return hipErrorInvalidValue;   // the copy pays only on a persistent grid
   // col_src may be null for a graph without arcs.
   if (renumber && (a.hub_n > 0 || !a.coff || !a.pmap || !a.ncol || a.r != 2)) return hipErrorInvalidValue;
-  if (renumber) {
-    if (fp32) hipLaunchKernelGGL((walk_step<true, true>), dim3((unsigned)g), dim3(kWG), 0, s, a);
-    else hipLaunchKernelGGL((walk_step<false, true>), dim3((unsigned)g), dim3(kWG), 0, s, a);
+  if (groups != 1 && groups != kWalkGroups) return hipErrorInvalidValue;
+  long long used = 0;
+  if (!renumber && groups == kWalkGroups) {
+    // Workgroups of kWalkGroups groups; slots = virtual workgroups.
+    g = (g + kWalkGroups - 1) / kWalkGroups;
+    const void* k = fp32 ? (const void*)walk_step_grouped<true> : (const void*)walk_step_grouped<false>;
+    if (max_grid > 0) g = std::min(g, max_grid);
+    g = std::max<long long>(1, std::min(g, resident_blocks(k, lds, kWG * kWalkGroups)));
+    if (fp32) hipLaunchKernelGGL(walk_step_grouped<true>, dim3((unsigned)g), dim3(kWG * kWalkGroups), lds, s, a);
+    else hipLaunchKernelGGL(walk_step_grouped<false>, dim3((unsigned)g), dim3(kWG * kWalkGroups), lds, s, a);
+    used = g * kWalkGroups;
   } else {
-    if (fp32) hipLaunchKernelGGL((walk_step<true, false>), dim3((unsigned)g), dim3(kWG), lds, s, a);
-    else hipLaunchKernelGGL((walk_step<false, false>), dim3((unsigned)g), dim3(kWG), lds, s, a);
+    if (max_grid > 0) {
+      const void* k = renumber ? (fp32 ? (const void*)walk_step<true, true> : (const void*)walk_step<false, true>)
+                               : (fp32 ? (const void*)walk_step<true, false> : (const void*)walk_step<false, false>);
+      g = std::min(g, std::min(max_grid, resident_blocks(k, renumber ? 0 : lds, kWG)));
+    }
+    if (renumber) {
+      if (fp32) hipLaunchKernelGGL((walk_step<true, true>), dim3((unsigned)g), dim3(kWG), 0, s, a);
+      else hipLaunchKernelGGL((walk_step<false, true>), dim3((unsigned)g), dim3(kWG), 0, s, a);
+    } else {
+      if (fp32) hipLaunchKernelGGL((walk_step<true, false>), dim3((unsigned)g), dim3(kWG), lds, s, a);
+      else hipLaunchKernelGGL((walk_step<false, false>), dim3((unsigned)g), dim3(kWG), lds, s, a);
+    }
+    used = g;
   }
-  long long used = g;
   const long long nh = a.bin_count[BIN_HUGE];
   if (nh > 0) {
     IterArgs c = a;
-    c.blk_base = g;
+    c.blk_base = used;
     const long long cg = (nh + kWG / kWave - 1) / (kWG / kWave);
     if (fp32) hipLaunchKernelGGL(huge_combine<true>, dim3((unsigned)cg), dim3(kWG), 0, s, c);
     else hipLaunchKernelGGL(huge_combine<false>, dim3((unsigned)cg), dim3(kWG), 0, s, c);

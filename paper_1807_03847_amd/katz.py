@@ -57,7 +57,7 @@ class KatzResult(ctypes.Structure):
 class KatzTuning(ctypes.Structure):
     _fields_ = [("hub_bytes", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("batch_blocks_per_cu", ctypes.c_int32), ("batch_tile", ctypes.c_int32),
-                ("batch_xcd", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("batch_xcd", ctypes.c_int32), ("walk_groups", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class KatzTiming(ctypes.Structure):
@@ -360,7 +360,7 @@ class Server:
 
 def _tuning_dict(t):
     return {"hub_bytes": t.hub_bytes, "blocks_per_cu": t.blocks_per_cu, "batch_blocks_per_cu": t.batch_blocks_per_cu,
-            "batch_tile": t.batch_tile, "batch_xcd": t.batch_xcd}
+            "batch_tile": t.batch_tile, "batch_xcd": t.batch_xcd, "walk_groups": t.walk_groups}
 
 
 def tuning_get() -> dict:
@@ -372,11 +372,12 @@ def tuning_get() -> dict:
     return _tuning_dict(t)
 
 
-def tuning_set(hub_bytes=0, blocks_per_cu=0, batch_blocks_per_cu=0, batch_tile=0, batch_xcd=0) -> None:
+def tuning_set(hub_bytes=0, blocks_per_cu=0, batch_blocks_per_cu=0, batch_tile=0, batch_xcd=0,
+               walk_groups=0) -> None:
     """katz_tuning_set (no result depends on it)."""
     t = KatzTuning(hub_bytes=int(hub_bytes), blocks_per_cu=int(blocks_per_cu),
                    batch_blocks_per_cu=int(batch_blocks_per_cu), batch_tile=int(batch_tile),
-                   batch_xcd=int(batch_xcd))
+                   batch_xcd=int(batch_xcd), walk_groups=int(walk_groups))
     rc = lib.katz_tuning_set(ctypes.byref(t))
     if rc < 0:
         raise KatzError(rc)

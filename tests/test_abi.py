@@ -45,7 +45,7 @@ int main(void) {
   F(katz_params, k) F(katz_params, precision) F(katz_params, validate) F(katz_params, flags) F(katz_params, degree_cap)
   F(katz_result, rest_upper_max) F(katz_result, active_final) F(katz_result, iterations) F(katz_result, status)
   F(katz_tuning, blocks_per_cu) F(katz_tuning, batch_blocks_per_cu) F(katz_tuning, batch_tile)
-  F(katz_tuning, batch_xcd) F(katz_tuning, reserved)
+  F(katz_tuning, batch_xcd) F(katz_tuning, walk_groups) F(katz_tuning, reserved)
   F(katz_timing, prep_ms) F(katz_timing, calls) F(katz_timing, renumber_step_ms) F(katz_timing, renumber_step_launches)
   return 0;
 }
@@ -123,17 +123,22 @@ def test_tuning_round_trip_and_limits():
     saved = katz.tuning_get()
     try:
         katz.tuning_set(16384, 4, 8, 2, 1)
-        want = {"hub_bytes": 16384, "blocks_per_cu": 4, "batch_blocks_per_cu": 8, "batch_tile": 2, "batch_xcd": 1}
+        want = {"hub_bytes": 16384, "blocks_per_cu": 4, "batch_blocks_per_cu": 8, "batch_tile": 2, "batch_xcd": 1,
+                "walk_groups": 0}
         assert katz.tuning_get() == want
         for bad in [(-16, 4, 0, 0), (65552, 4, 0, 0), (100, 4, 0, 0), (16384, 0, 0, 0),
                     (0, 33, 0, 0), (0, -1, 0, 0), (0, 0, 33, 0), (0, 0, -2, 0), (0, 0, 0, 17),
-                    (0, 0, 0, -1), (0, 0, 0, 0, 2), (0, 0, 0, 0, -1)]:
+                    (0, 0, 0, -1), (0, 0, 0, 0, 2), (0, 0, 0, 0, -1), (0, 0, 0, 0, 0, 2), (0, 0, 0, 0, 0, 8),
+                    (131072, 1, 0, 0, 0, 1), (162832, 1, 0, 0, 0, 4)]:
             with pytest.raises(katz.KatzError) as e:
                 katz.tuning_set(*bad)
             assert e.value.code == katz.E_INVALID_ARG
             assert katz.tuning_get() == want                                  # unchanged
+        katz.tuning_set(131072, 1, 0, 0, 0, 4)                              # large copy with 4 groups
+        assert katz.tuning_get()["hub_bytes"] == 131072
+        katz.tuning_set(16384, 4, 8, 2, 1)
         t = katz.KatzTuning(hub_bytes=0, blocks_per_cu=0)
-        t.reserved[2] = 1
+        t.reserved[1] = 1
         assert katz.lib.katz_tuning_set(ctypes.byref(t)) == katz.E_INVALID_ARG
         assert katz.lib.katz_tuning_set(None) == katz.E_INVALID_ARG
         assert katz.lib.katz_tuning_get(None) == katz.E_INVALID_ARG

@@ -327,8 +327,8 @@ def test_internal_renumbering_is_invisible(precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_launch_tuning_is_invisible(precision):
     """The walk kernel's launch shape (persistent grid, LDS copy of the first
-    walk entries) changes no bit of ids, bounds, r or status; the autotuner
-    installs one of its candidates."""
+    walk entries, 1024-thread workgroups of four groups) changes no bit of ids,
+    bounds, r or status; the autotuner installs one of its candidates."""
     katz = K()
     rp, col = sg.rmat(16, seed=12)
     rp_t, col_t = dev(rp, col)
@@ -337,9 +337,10 @@ def test_launch_tuning_is_invisible(precision):
         katz.tuning_set(0, 0)
         ref = katz.rank_static(rp_t, col_t, 500, eps=1e-6, precision=precision)
         lr, ur = katz.bounds(rp_t, col_t, 6, precision=precision)
-        for hub, bpc in [(0, 1), (0, 8), (16384, 2), (65536, 1), (4096, 32)]:
-            say("tuning", precision, hub, bpc)
-            katz.tuning_set(hub, bpc)
+        for hub, bpc, groups in [(0, 1, 0), (0, 8, 0), (16384, 2, 0), (65536, 1, 0), (4096, 32, 0), (0, 1, 4),
+                                 (131072, 1, 4), (40960, 2, 4)]:
+            say("tuning", precision, hub, bpc, groups)
+            katz.tuning_set(hub, bpc, walk_groups=groups)
             a = katz.rank_static(rp_t, col_t, 500, eps=1e-6, precision=precision)
             assert torch.equal(a.topk, ref.topk) and torch.equal(a.lower, ref.lower) and torch.equal(a.upper, ref.upper)
             assert (a.iterations, a.status, a.rest_upper_max) == (ref.iterations, ref.status, ref.rest_upper_max)
