@@ -51,10 +51,16 @@ def measured_traffic(tuning_arg):
         with open(os.path.join(ROOT, path), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return None, f"kernel source changed since the counters were taken ({path})"
-    if rec["tuning"] != tuning_arg:
-        return None, f"counters taken at tuning {rec['tuning']}, timed at {tuning_arg}"
-    return rec["traffic_bytes_per_launch"], ("FETCH_SIZE x%.2f + WRITE_SIZE x%.2f per launch, from %s" % (
-        rec["calibration"]["fetch_scale"], rec["calibration"]["write_scale"], os.path.relpath(COUNTERS, ROOT)))
+    other = rec.get("by_tuning", {})
+    if rec["tuning"] == tuning_arg:
+        traffic = rec["traffic_bytes_per_launch"]
+    elif tuning_arg in other:
+        traffic = other[tuning_arg]
+    else:
+        return None, f"counters taken at tunings {[rec['tuning']] + sorted(other)}, timed at {tuning_arg}"
+    return traffic, ("FETCH_SIZE x%.2f + WRITE_SIZE x%.2f per launch at tuning %s, from %s" % (
+        rec["calibration"]["fetch_scale"], rec["calibration"]["write_scale"], tuning_arg,
+        os.path.relpath(COUNTERS, ROOT)))
 
 
 def time_form(katz, torch, rp_t, col_t, precision, steps, warmup, flags=0):
