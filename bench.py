@@ -101,8 +101,8 @@ def main():
                     help="static: also time every autotuner candidate (FP32) and report them")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(a graph, its bins and its walk vectors live on one device)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -1,10 +1,11 @@
 // Device kernels of the certified top-k Katz ranking (gfx950, wave64).
 //
 // One iteration r of Algorithm 1 (Section 3.2) is
-//   walk_first (r = 1) / walk_step (r >= 2)
+//   walk_first (r = 1) / walk_step or walk_step_grouped (r >= 2)
 //                                 walk step of Eq. (basic_recurrence) for every
 //                                 row, fused with the update of c_r (and of the
-//                                 FP32 margin accumulator),
+//                                 FP32 margin accumulator); in a renumbered run,
+//                                 step 2 also renames the column ids,
 //   sel_hist / sel_scan / sel_compact (levels 0, 1), sel_finish
 //                                 radix select of the k-th largest lower bound
 //                                 over the active set M,
