@@ -314,14 +314,22 @@ def test_internal_renumbering_is_invisible(precision):
     katz = K()
     rp, col = sg.rmat(16, seed=11)
     rp_t, col_t = dev(rp, col)
-    say("renumbering", precision)
-    a = katz.rank_static(rp_t, col_t, 500, eps=1e-6, precision=precision)
-    b = katz.rank_static(rp_t, col_t, 500, eps=1e-6, precision=precision, flags=katz.FLAG_NO_REORDER)
-    assert torch.equal(a.topk, b.topk) and torch.equal(a.lower, b.lower) and torch.equal(a.upper, b.upper)
-    assert (a.iterations, a.status, a.rest_upper_max) == (b.iterations, b.status, b.rest_upper_max)
-    la, ua = katz.bounds(rp_t, col_t, 5, precision=precision)
-    lb, ub = katz.bounds(rp_t, col_t, 5, precision=precision, flags=katz.FLAG_NO_REORDER)
-    assert torch.equal(la, lb) and torch.equal(ua, ub)
+    saved = katz.tuning_get()
+    try:
+        # Default launch shape, then 1024-thread grouped workgroups (which the
+        # caller-order run takes too, without an LDS copy).
+        for hub, bpc, groups in [(0, 0, 0), (65536, 1, 4)]:
+            say("renumbering", precision, hub, bpc, groups)
+            katz.tuning_set(hub, bpc, walk_groups=groups)
+            a = katz.rank_static(rp_t, col_t, 500, eps=1e-6, precision=precision)
+            b = katz.rank_static(rp_t, col_t, 500, eps=1e-6, precision=precision, flags=katz.FLAG_NO_REORDER)
+            assert torch.equal(a.topk, b.topk) and torch.equal(a.lower, b.lower) and torch.equal(a.upper, b.upper)
+            assert (a.iterations, a.status, a.rest_upper_max) == (b.iterations, b.status, b.rest_upper_max)
+            la, ua = katz.bounds(rp_t, col_t, 5, precision=precision)
+            lb, ub = katz.bounds(rp_t, col_t, 5, precision=precision, flags=katz.FLAG_NO_REORDER)
+            assert torch.equal(la, lb) and torch.equal(ua, ub)
+    finally:
+        katz.tuning_set(**saved)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
