@@ -2074,12 +2074,17 @@ int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, lon
     // The walk kernels return at once while the run's stop flag is set; the
     // previous run left it set.
     KATZ_HIP(launch_reset_flags(st->w.sc, s));
+    // Dense re-walk (every row) once C covers a quarter of the nodes, or once
+    // the frontier to expand is large: expanding it would scan about as many
+    // arcs, with an atomic per new node, as re-walking every row does.
     const long long dense_at = std::max<long long>(1, n / 4);
+    const long long dense_frontier = std::max<long long>(4096, n / 64);
     KATZ_HIP(hipMemcpyAsync(st->clist, ub.rows, sizeof(int32_t) * t, hipMemcpyDeviceToDevice, s));
     KATZ_HIP(launch_set_levels(ub.rows, t, st->level_of, 1, s));
     long long csize = t, fbeg = 0;
     bool dense = csize > dense_at;
     for (int i = 1; i <= st->r; ++i) {
+      if (i >= 2 && !dense && csize - fbeg > dense_frontier) dense = true;
       if (i >= 2 && !dense) {
         // C_i = C_{i-1} u in-neighbours(F_{i-1}); F_{i-1} = C[fbeg .. csize).
         KATZ_HIP(hipMemcpyAsync(st->counter, &csize, sizeof(int), hipMemcpyHostToDevice, s));

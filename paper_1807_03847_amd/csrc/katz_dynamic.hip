@@ -216,7 +216,9 @@ __global__ void __launch_bounds__(kWG) frontier_expand(const int32_t* frontier, 
     int u = 0;
     if (j < len) {
       u = pool[off + j];
-      fresh = atomicCAS(&level_of[u], 0, level) == 0;
+      // Most neighbours of a large frontier are in C already: a plain read
+      // skips the atomic for them (a stale 0 only costs the atomic).
+      fresh = level_of[u] == 0 && atomicCAS(&level_of[u], 0, level) == 0;
     }
     const int pos = wave_append(next_count, fresh);
     if (fresh) next[pos] = u;
