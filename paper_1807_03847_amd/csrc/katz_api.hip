@@ -468,6 +468,7 @@ struct katz_state {
   int* level_of = nullptr;
   int32_t* clist = nullptr;
   int* counter = nullptr;
+  unsigned long long* frontier_arcs = nullptr;   // arcs of the last expansion's new frontier
   int* dmax_dev = nullptr;
   int* err_dev = nullptr;
   unsigned long long* min_bits = nullptr;
@@ -1820,6 +1821,7 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
   st->level_of = dalloc<int>(st, n);
   st->clist = dalloc<int32_t>(st, n);
   st->counter = dalloc<int>(st, 1);
+  st->frontier_arcs = dalloc<unsigned long long>(st, 1);
   st->dmax_dev = dalloc<int>(st, 1);
   st->err_dev = dalloc<int>(st, 1);
   st->min_bits = dalloc<unsigned long long>(st, 1);
@@ -1829,7 +1831,7 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
   st->out_up = dalloc<double>(st, st->k);
   if (!w.c || !w.act[0] || !w.act[1] || !w.keys || !w.cand_key[0] || !w.cand_key[1] || !w.cand_v[0] ||
       !w.cand_v[1] || !w.hist || !w.xmax32 || !w.xmax64 || !w.sigma || !w.sigma_sum || !w.top_sorted ||
-      !w.top_lo || !w.top_up || !w.mark || !w.rest_bits || !st->level_of || !st->clist || !st->counter ||
+      !w.top_lo || !w.top_up || !w.mark || !w.rest_bits || !st->level_of || !st->clist || !st->counter || !st->frontier_arcs ||
       !st->dmax_dev || !st->err_dev || !st->min_bits || !st->tmark || !st->out_ids || !st->out_lo || !st->out_up)
     return KATZ_E_OOM;
   KATZ_HIP(hipMemsetAsync(w.mark, 0, n, s));
@@ -2075,23 +2077,27 @@ int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, lon
     // previous run left it set.
     KATZ_HIP(launch_reset_flags(st->w.sc, s));
     // Dense re-walk (every row) once C covers a quarter of the nodes, or once
-    // the frontier to expand is large: expanding it would scan about as many
-    // arcs, with an atomic per new node, as re-walking every row does.
+    // the frontier to expand is large or has many arcs: expanding it would
+    // scan about as many arcs as re-walking every row does.
     const long long dense_at = std::max<long long>(1, n / 4);
     const long long dense_frontier = std::max<long long>(4096, n / 64);
+    const unsigned long long dense_arcs = std::max<unsigned long long>(1ull << 16, (unsigned long long)st->nnz / 16);
+    unsigned long long f_arcs = 0;   // arcs of the frontier about to be expanded (0: not known)
     KATZ_HIP(hipMemcpyAsync(st->clist, ub.rows, sizeof(int32_t) * t, hipMemcpyDeviceToDevice, s));
     KATZ_HIP(launch_set_levels(ub.rows, t, st->level_of, 1, s));
     long long csize = t, fbeg = 0;
     bool dense = csize > dense_at;
     for (int i = 1; i <= st->r; ++i) {
-      if (i >= 2 && !dense && csize - fbeg > dense_frontier) dense = true;
+      if (i >= 2 && !dense && (csize - fbeg > dense_frontier || f_arcs > dense_arcs)) dense = true;
       if (i >= 2 && !dense) {
         // C_i = C_{i-1} u in-neighbours(F_{i-1}); F_{i-1} = C[fbeg .. csize).
         KATZ_HIP(hipMemcpyAsync(st->counter, &csize, sizeof(int), hipMemcpyHostToDevice, s));
+        KATZ_HIP(hipMemsetAsync(st->frontier_arcs, 0, sizeof(unsigned long long), s));
         KATZ_HIP(launch_frontier_expand(st->clist + fbeg, csize - fbeg, st->row_off, st->row_len, st->pool,
-                                        st->level_of, i, st->clist, st->counter, s));
+                                        st->level_of, i, st->clist, st->counter, st->frontier_arcs, s));
         int c2 = 0;
         KATZ_HIP(hipMemcpyAsync(&c2, st->counter, sizeof(int), hipMemcpyDeviceToHost, s));
+        KATZ_HIP(hipMemcpyAsync(&f_arcs, st->frontier_arcs, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
         KATZ_HIP(hipStreamSynchronize(s));
         fbeg = csize;
         csize = c2;

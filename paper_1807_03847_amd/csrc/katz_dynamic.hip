@@ -200,9 +200,12 @@ __global__ void __launch_bounds__(kWG) copy_back_rows(const int32_t* rows, const
 
 // Breadth-first expansion: every neighbour of a frontier row that is not yet in
 // C joins C at `level` and the next frontier.  One wave per frontier row.
+// next_arcs adds up the row lengths of the new frontier (the arcs its own
+// expansion would scan).
 __global__ void __launch_bounds__(kWG) frontier_expand(const int32_t* frontier, long long f, const long long* row_off,
                                                        const int* row_len, const int32_t* pool, int* level_of,
-                                                       int level, int32_t* next, int* next_count) {
+                                                       int level, int32_t* next, int* next_count,
+                                                       unsigned long long* next_arcs) {
   const long long wv = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave;
   const int lane = lane_id();
   const bool valid_row = wv < f;
@@ -222,6 +225,9 @@ __global__ void __launch_bounds__(kWG) frontier_expand(const int32_t* frontier, 
     }
     const int pos = wave_append(next_count, fresh);
     if (fresh) next[pos] = u;
+    unsigned long long arcs = fresh ? (unsigned long long)row_len[u] : 0ull;
+    for (int o = 32; o >= 1; o >>= 1) arcs += __shfl_xor(arcs, o);
+    if (lane == 0 && arcs) atomicAdd(next_arcs, arcs);
   }
 }
 
@@ -412,10 +418,10 @@ hipError_t launch_copy_back_rows(const int32_t* rows, long long t, const long lo
 
 hipError_t launch_frontier_expand(const int32_t* frontier, long long f, const long long* row_off, const int* row_len,
                                   const int32_t* pool, int* level_of, int level, int32_t* next, int* next_count,
-                                  hipStream_t s) {
+                                  unsigned long long* next_arcs, hipStream_t s) {
   if (f > 0)
     hipLaunchKernelGGL(frontier_expand, dim3(blocks_for(f * kWave)), dim3(kWG), 0, s, frontier, f, row_off, row_len,
-                       pool, level_of, level, next, next_count);
+                       pool, level_of, level, next, next_count, next_arcs);
   return hipGetLastError();
 }
 

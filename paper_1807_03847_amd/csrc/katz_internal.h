@@ -333,7 +333,7 @@ hipError_t launch_copy_back_rows(const int32_t* rows, long long t, const long lo
                                  long long* row_off, int* row_len, int* row_cap, int32_t* pool, hipStream_t s);
 hipError_t launch_frontier_expand(const int32_t* frontier, long long f, const long long* row_off, const int* row_len,
                                   const int32_t* pool, int* level_of, int level, int32_t* next, int* next_count,
-                                  hipStream_t s);
+                                  unsigned long long* next_arcs, hipStream_t s);
 hipError_t launch_set_levels(const int32_t* rows, long long t, int* level_of, int level, hipStream_t s);
 hipError_t launch_clear_levels(const int32_t* rows, long long t, int* level_of, hipStream_t s);
 hipError_t launch_c_from_history(const int32_t* rows, long long count, double* const* X, int r, double* c,
