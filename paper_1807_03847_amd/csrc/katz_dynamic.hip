@@ -199,21 +199,27 @@ __global__ void __launch_bounds__(kWG) copy_back_rows(const int32_t* rows, const
 }
 
 // Breadth-first expansion: every neighbour of a frontier row that is not yet in
-// C joins C at `level` and the next frontier.  One wave per frontier row.
+// C joins C at `level` and the next frontier.  kExpandWaves waves per frontier
+// row, wave c taking arcs c*64 .. c*64+63, then the same slots kExpandWaves*64
+// further on, ... (one wave per row left a row of 10^5 arcs to a single wave).
 // next_arcs adds up the row lengths of the new frontier (the arcs its own
 // expansion would scan).
+constexpr int kExpandWaves = 16;
+
 __global__ void __launch_bounds__(kWG) frontier_expand(const int32_t* frontier, long long f, const long long* row_off,
                                                        const int* row_len, const int32_t* pool, int* level_of,
                                                        int level, int32_t* next, int* next_count,
                                                        unsigned long long* next_arcs) {
   const long long wv = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave;
+  const long long ri = wv / kExpandWaves;
+  const int part = (int)(wv % kExpandWaves);
   const int lane = lane_id();
-  const bool valid_row = wv < f;
-  const int w = valid_row ? frontier[wv] : 0;
+  const bool valid_row = ri < f;
+  const int w = valid_row ? frontier[ri] : 0;
   const long long off = valid_row ? row_off[w] : 0;
   const int len = valid_row ? row_len[w] : 0;
   // Every lane of a wave runs the same trip count (wave_append needs them all).
-  for (int base = 0; base < len; base += kWave) {
+  for (int base = part * kWave; base < len; base += kExpandWaves * kWave) {
     const int j = base + lane;
     bool fresh = false;
     int u = 0;
@@ -420,8 +426,8 @@ hipError_t launch_frontier_expand(const int32_t* frontier, long long f, const lo
                                   const int32_t* pool, int* level_of, int level, int32_t* next, int* next_count,
                                   unsigned long long* next_arcs, hipStream_t s) {
   if (f > 0)
-    hipLaunchKernelGGL(frontier_expand, dim3(blocks_for(f * kWave)), dim3(kWG), 0, s, frontier, f, row_off, row_len,
-                       pool, level_of, level, next, next_count, next_arcs);
+    hipLaunchKernelGGL(frontier_expand, dim3(blocks_for(f * kWave * kExpandWaves)), dim3(kWG), 0, s, frontier, f,
+                       row_off, row_len, pool, level_of, level, next, next_count, next_arcs);
   return hipGetLastError();
 }
 
