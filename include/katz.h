@@ -227,7 +227,10 @@ int katz_server_submit(katz_server* sv, int32_t graph_id, const int32_t* ins_u, 
  * (either pointer may be NULL).  Returns the request's status code. */
 int katz_server_wait(katz_server* sv, int64_t ticket, katz_result* out, double* latency_ms,
                      double* service_ms);
-/* Stops the workers (requests still queued are dropped) and frees the states. */
+/* Stops the workers (requests still queued are dropped) and frees the states.
+ * No other call on sv may be in progress, or follow: a wait on a dropped
+ * request would never return.  add_graph, submit and wait may otherwise be
+ * called from any thread while requests run. */
 void katz_server_destroy(katz_server* sv);
 
 /* ---- device timing (instrumentation for benchmarks and profiles) ----------

@@ -57,9 +57,12 @@ struct katz_server {
   std::mutex mu;
   std::condition_variable cv_work;   // workers wait for admissible requests
   std::condition_variable cv_done;   // callers wait for completions
-  std::vector<GraphEntry> graphs;
+  // A deque: add_graph appends while workers hold pointers to other entries,
+  // and push_back on a deque never moves the elements already in it.
+  std::deque<GraphEntry> graphs;
   std::map<int64_t, std::shared_ptr<Request>> tickets;
   std::vector<std::thread> workers;
+  std::vector<hipStream_t> streams;  // one per worker, created with the server
   int64_t next_ticket = 1;
   int64_t budget = 0;                // bytes; 0 = unlimited
   int64_t in_use = 0;
@@ -86,22 +89,21 @@ std::shared_ptr<Request> pick(katz_server* sv) {
   return best;
 }
 
-void worker_main(katz_server* sv) {
+void worker_main(katz_server* sv, hipStream_t s) {
   (void)hipSetDevice(sv->device);
-  hipStream_t s = nullptr;
-  (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
   for (;;) {
     std::shared_ptr<Request> rq;
+    GraphEntry* gep = nullptr;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
       sv->cv_work.wait(lk, [&] { return sv->stopping || (rq = pick(sv)) != nullptr; });
       if (!rq) break;
-      GraphEntry& ge = sv->graphs[rq->graph];
-      ge.queue.pop_front();
-      ge.busy = true;
+      gep = &sv->graphs[rq->graph];
+      gep->queue.pop_front();
+      gep->busy = true;
       sv->in_use += rq->bytes;
     }
-    GraphEntry& ge = sv->graphs[rq->graph];
+    GraphEntry& ge = *gep;  // st and k never change once registered
     rq->ids.resize(ge.k);
     rq->lo.resize(ge.k);
     rq->up.resize(ge.k);
@@ -126,7 +128,6 @@ void worker_main(katz_server* sv) {
     sv->cv_done.notify_all();
     sv->cv_work.notify_all();
   }
-  (void)hipStreamDestroy(s);
 }
 
 }  // namespace
@@ -135,11 +136,18 @@ KATZ_EXPORT int katz_server_create(int32_t slots, int64_t memory_budget, katz_se
   if (!out || slots < 1 || slots > 64 || memory_budget < 0) return KATZ_E_INVALID_ARG;
   katz_server* sv = new katz_server;
   sv->budget = memory_budget;
-  if (hipGetDevice(&sv->device) != hipSuccess) {
+  bool ok = hipGetDevice(&sv->device) == hipSuccess;
+  for (int i = 0; ok && i < slots; ++i) {
+    hipStream_t s = nullptr;
+    ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    if (ok) sv->streams.push_back(s);
+  }
+  if (!ok) {
+    for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
     delete sv;
     return KATZ_E_HIP;
   }
-  for (int i = 0; i < slots; ++i) sv->workers.emplace_back(worker_main, sv);
+  for (hipStream_t s : sv->streams) sv->workers.emplace_back(worker_main, sv, s);
   *out = sv;
   return KATZ_OK;
 }
@@ -221,6 +229,7 @@ KATZ_EXPORT void katz_server_destroy(katz_server* sv) {
   }
   sv->cv_work.notify_all();
   for (std::thread& t : sv->workers) t.join();
+  for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
   for (GraphEntry& ge : sv->graphs) katz_state_free(ge.st);
   delete sv;
 }

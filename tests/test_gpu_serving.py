@@ -56,8 +56,10 @@ def make_graphs():
     return out
 
 
-@pytest.mark.parametrize("slots,budget", [(3, 0), (2, 1)])
-def test_serving_mix_equals_alone(slots, budget):
+@pytest.mark.parametrize("slots,budget,late_add", [(3, 0, False), (2, 1, False), (3, 0, True)])
+def test_serving_mix_equals_alone(slots, budget, late_add):
+    """late_add: graphs after the first are registered while the first graph's
+    requests run, so the server's graph table grows under running workers."""
     katz = K()
     rng = np.random.default_rng(slots)
     graphs = make_graphs()
@@ -66,15 +68,19 @@ def test_serving_mix_equals_alone(slots, budget):
     for rp, col, alpha, cap in graphs:
         hubs = np.argsort(-np.diff(rp))[:5]
         streams.append(request_stream(rp, col, len(rp) - 1, 8, rng, hubs=hubs))
-    say("serving mix", slots, budget)
+    say("serving mix", slots, budget, late_add)
     sv = katz.Server(slots=slots, memory_budget=budget)
     gids = []
-    for rp, col, alpha, cap in graphs:
+    tickets = []
+    for gi, (rp, col, alpha, cap) in enumerate(graphs):
         gid, _ = sv.add_graph(torch.from_numpy(rp), torch.from_numpy(col), k, alpha=alpha, eps=eps, degree_cap=cap)
         gids.append(gid)
-    tickets = []
+        if late_add and gi == 0:
+            tickets += [(0, j, sv.submit(gid, *streams[0][j])) for j in range(8)]
     for j in range(8):                      # interleave the graphs' requests
         for gi, gid in enumerate(gids):
+            if late_add and gi == 0:
+                continue
             ins, dels = streams[gi][j]
             tickets.append((gi, j, sv.submit(gid, ins, dels)))
     mixed = {}
