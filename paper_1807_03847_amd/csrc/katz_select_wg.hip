@@ -226,10 +226,15 @@ __device__ __forceinline__ void select_graph(const GraphSel& gs, const int* r_de
       for (int d = t; d < kDigits; d += kFinishThreads) sm.h[d] = 0u;
       __syncthreads();
       const int idpre = s_idpre;
-      for (int i = t; i < cnt; i += kFinishThreads) {
-        if (cand_key[i] != theta_key) continue;
-        const int e = ext(cand_v[i]);
-        if ((hishift >= 31 ? 0 : (e >> hishift)) == idpre) atomicAdd(&sm.h[(e >> shift) & ((1 << width) - 1)], 1u);
+      // Tied ids share their high digits (all of them at the first level when
+      // the ids are below 2^20), so the counts go through the wave-aggregated
+      // add; the loop has the same trip count for every thread.
+      for (int i0 = 0; i0 < cnt; i0 += kFinishThreads) {
+        const int i = i0 + t;
+        const bool tie = i < cnt && cand_key[i] == theta_key;
+        const int e = tie ? ext(cand_v[i]) : 0;
+        const bool in = tie && (hishift >= 31 ? 0 : (e >> hishift)) == idpre;
+        wave_hist_add(sm.h, (unsigned)((e >> shift) & ((1 << width) - 1)), in);
       }
       __syncthreads();
       const Bucket ib = find_bucket(sm.h, 1 << width, s_idneed, false);
