@@ -68,6 +68,42 @@ def test_batch_matches_single_and_oracle(precision):
             assert single.rest_upper_max == rb.rest_upper_max
 
 
+def circulant(n, offsets):
+    src = np.concatenate([np.arange(n)] * len(offsets))
+    dst = np.concatenate([(np.arange(n) + o) % n for o in offsets])
+    return sg.from_edges(n, src, dst)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_all_nodes_tied(precision):
+    """Vertex-transitive graphs: every node has the same bounds at every r, so
+    the k-th key is shared by all n nodes, the selection breaks the tie by id
+    over every node of the graph, and no ranking is ever certified (eps = 0:
+    the iteration limit ends the run).  A BA graph in the same batch converges
+    normally."""
+    katz = K()
+    graphs = [sg.cycle_graph(5000), sg.cycle_graph(70000), circulant(20000, (1, 5, 17)),
+              sg.barabasi_albert(3000, 6, 77)]
+    params = []
+    for (rp, col), k in zip(graphs, (40, 700, 1000, 50)):
+        params.append(dict(k=k, alpha=0.5 / (1 + sg.max_degree(rp)), eps=0.0, max_iter=9))
+    params[-1]["eps"] = 1e-9
+    say("batch all tied", precision)
+    res = run_batch(graphs, params, precision)
+    for gi, ((rp, col), pp, rb) in enumerate(zip(graphs, params, res)):
+        orc = oracle.rank_static(rp, col, pp["alpha"], pp["k"], pp["eps"], max_iter=pp["max_iter"])
+        if gi < 3:
+            assert orc.status == oracle.W_ITER_LIMIT and rb.iterations == 9
+        assert_topk_parity(rb.topk.cpu().numpy(), rb.lower.cpu().numpy(), rb.upper.cpu().numpy(), orc,
+                           gpu_status=rb.status)
+        single = katz.rank_static(torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda(), pp["k"],
+                                  alpha=pp["alpha"], eps=pp["eps"], precision=precision, max_iter=pp["max_iter"])
+        assert torch.equal(single.topk, rb.topk)
+        assert single.iterations == rb.iterations and single.status == rb.status
+        if gi < 3:   # ties are broken by the smaller id: the k smallest ids, in order
+            assert np.array_equal(rb.topk.cpu().numpy(), np.arange(pp["k"]))
+
+
 def test_batch_uneven_convergence_and_host_buffers():
     """Graphs that stop at very different r (small alpha converges fast), host
     inputs and outputs, a graph with k = n."""
