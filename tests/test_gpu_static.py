@@ -183,6 +183,28 @@ def test_dag_exact_ties():
     check(orc, res)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_large_vertex_transitive_ties(precision):
+    """Every node of a cycle (and of a circulant graph) has the same bounds at
+    every r: the k-th key is shared by all n nodes, the device selection breaks
+    the tie by id over the whole graph, and eps = 0 never certifies (iteration
+    limit).  The top-k is the k smallest ids, in order, with and without the
+    internal renumbering."""
+    n = 200000
+    src = np.concatenate([np.arange(n)] * 3)
+    dst = np.concatenate([(np.arange(n) + o) % n for o in (1, 2, 3)])
+    for name, (rp, col) in (("cycle", sg.cycle_graph(n)), ("circulant", sg.from_edges(n, src, dst))):
+        say("vertex-transitive ties", name, precision)
+        a = 0.5 / (1 + sg.max_degree(rp))
+        orc, res = run_both(rp, col, 1000, 0.0, alpha=a, precision=precision, max_iter=6)
+        assert orc.status == oracle.W_ITER_LIMIT and res.iterations == 6
+        check(orc, res, widened=precision == "fp32")
+        assert np.array_equal(res.topk.cpu().numpy(), np.arange(1000))
+        plain = K().rank_static(*dev(rp, col), 1000, alpha=a, eps=0.0, precision=precision, max_iter=6,
+                                flags=K().FLAG_NO_REORDER)
+        assert torch.equal(plain.topk, res.topk) and plain.status == res.status
+
+
 def test_star_iteration_limit():
     rp, col = sg.star_graph(3)
     say("star iter limit")
