@@ -725,6 +725,8 @@ __global__ void __launch_bounds__(kWG) sel_compact(SelArgs a, int level) {
   }
 }
 
+constexpr int kFinishIlp = 4;   // candidates per thread and pass of sel_finish
+
 // Resolves the remaining digits of the k-th key and the id cut inside its ties.
 __global__ void __launch_bounds__(kFinishThreads) sel_finish(SelArgs a) {
   if (stopped(a.sc)) return;
@@ -748,9 +750,22 @@ __global__ void __launch_bounds__(kFinishThreads) sel_finish(SelArgs a) {
     for (int d = threadIdx.x; d < kDigits; d += kFinishThreads) h[d] = 0u;
     __syncthreads();
     const unsigned long long pre = s_prefix;
-    for (int i = threadIdx.x; i < cnt; i += kFinishThreads) {
-      const unsigned long long key = ck[i];
-      if ((key >> hishift) == pre) atomicAdd(&h[(key >> shift) & ((1u << width) - 1u)], 1u);
+    // Candidates share their leading digits (all of them when many nodes tie
+    // at the k-th key), so the counts go through the wave-aggregated add, with
+    // kFinishIlp loads in flight per thread and the same trip count for every
+    // thread.
+    for (int i0 = 0; i0 < cnt; i0 += kFinishIlp * kFinishThreads) {
+      unsigned long long key[kFinishIlp];
+#pragma unroll
+      for (int u = 0; u < kFinishIlp; ++u) {
+        const int i = i0 + u * kFinishThreads + (int)threadIdx.x;
+        key[u] = i < cnt ? ck[i] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < kFinishIlp; ++u) {
+        const int i = i0 + u * kFinishThreads + (int)threadIdx.x;
+        wave_hist_add(h, (unsigned)((key[u] >> shift) & ((1u << width) - 1u)), i < cnt && (key[u] >> hishift) == pre);
+      }
     }
     __syncthreads();
     const Bucket bk = find_bucket(h, 1 << width, s_need, true);
@@ -783,10 +798,21 @@ __global__ void __launch_bounds__(kFinishThreads) sel_finish(SelArgs a) {
       for (int d = threadIdx.x; d < kDigits; d += kFinishThreads) h[d] = 0u;
       __syncthreads();
       const int pre = s_idpre;
-      for (int i = threadIdx.x; i < cnt; i += kFinishThreads) {
-        if (ck[i] != theta_key) continue;
-        const int e = ext_id(a, cv[i]);
-        if ((hishift >= 31 ? 0 : (e >> hishift)) == pre) atomicAdd(&h[(e >> shift) & ((1 << width) - 1)], 1u);
+      for (int i0 = 0; i0 < cnt; i0 += kFinishIlp * kFinishThreads) {
+        bool tie[kFinishIlp];
+        int v[kFinishIlp];
+#pragma unroll
+        for (int u = 0; u < kFinishIlp; ++u) {
+          const int i = i0 + u * kFinishThreads + (int)threadIdx.x;
+          tie[u] = i < cnt && ck[i] == theta_key;
+          v[u] = i < cnt ? cv[i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kFinishIlp; ++u) {
+          const int e = tie[u] ? ext_id(a, v[u]) : 0;
+          const bool in = tie[u] && (hishift >= 31 ? 0 : (e >> hishift)) == pre;
+          wave_hist_add(h, (unsigned)((e >> shift) & ((1 << width) - 1)), in);
+        }
       }
       __syncthreads();
       const Bucket bk = find_bucket(h, 1 << width, s_idneed, false);
