@@ -731,7 +731,7 @@ constexpr int kFinishIlp = 4;   // candidates per thread and pass of sel_finish
 __global__ void __launch_bounds__(kFinishThreads) sel_finish(SelArgs a) {
   if (stopped(a.sc)) return;
   __shared__ unsigned h[kDigits];
-  __shared__ unsigned long long s_prefix;
+  __shared__ unsigned long long s_prefix, s_kmin, s_kmax;
   __shared__ int s_need, s_count;
   const bool from1 = a.sc->cand_count[0] > kSmallCand;
   const unsigned long long* ck = a.cand_key[from1 ? 1 : 0];
@@ -741,12 +741,26 @@ __global__ void __launch_bounds__(kFinishThreads) sel_finish(SelArgs a) {
     s_prefix = a.sc->prefix;
     s_need = a.sc->need;
     s_count = cnt;
+    s_kmin = ~0ull;
+    s_kmax = 0ull;
   }
   __syncthreads();
-  for (int level = from1 ? 2 : 1; level < kSelectLevels; ++level) {
+  const int first = from1 ? 2 : 1;
+  const bool track = cnt > kSmallCand;   // only a large candidate set repays the min/max
+  for (int level = first; level < kSelectLevels; ++level) {
     const int shift = level < 5 ? 51 - kDigitBits * level : 0;
     const int width = level < 5 ? kDigitBits : 3;
     const int hishift = shift + width;
+    // Every candidate carries the prefix resolved before the first level, and
+    // the first pass finds their smallest and largest key.  A later digit on
+    // which these two agree (with all bits above it) is that digit of every
+    // candidate: its bucket holds all cnt of them and the rank inside it does
+    // not change, so the pass is not needed.
+    if (track && level > first && ((s_kmin ^ s_kmax) >> shift) == 0) {
+      if (threadIdx.x == 0) s_prefix = (s_prefix << width) | ((s_kmin >> shift) & ((1ull << width) - 1ull));
+      __syncthreads();
+      continue;
+    }
     for (int d = threadIdx.x; d < kDigits; d += kFinishThreads) h[d] = 0u;
     __syncthreads();
     const unsigned long long pre = s_prefix;
@@ -754,6 +768,7 @@ __global__ void __launch_bounds__(kFinishThreads) sel_finish(SelArgs a) {
     // at the k-th key), so the counts go through the wave-aggregated add, with
     // kFinishIlp loads in flight per thread and the same trip count for every
     // thread.
+    unsigned long long kmin = ~0ull, kmax = 0ull;
     for (int i0 = 0; i0 < cnt; i0 += kFinishIlp * kFinishThreads) {
       unsigned long long key[kFinishIlp];
 #pragma unroll
@@ -765,6 +780,21 @@ __global__ void __launch_bounds__(kFinishThreads) sel_finish(SelArgs a) {
       for (int u = 0; u < kFinishIlp; ++u) {
         const int i = i0 + u * kFinishThreads + (int)threadIdx.x;
         wave_hist_add(h, (unsigned)((key[u] >> shift) & ((1u << width) - 1u)), i < cnt && (key[u] >> hishift) == pre);
+        if (track && i < cnt) {
+          kmin = key[u] < kmin ? key[u] : kmin;
+          kmax = key[u] > kmax ? key[u] : kmax;
+        }
+      }
+    }
+    if (track && level == first) {
+      for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long x = __shfl_xor(kmin, o), y = __shfl_xor(kmax, o);
+        kmin = x < kmin ? x : kmin;
+        kmax = y > kmax ? y : kmax;
+      }
+      if (lane_id() == 0) {
+        atomicMin(&s_kmin, kmin);
+        atomicMax(&s_kmax, kmax);
       }
     }
     __syncthreads();
