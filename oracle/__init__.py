@@ -12,6 +12,9 @@ Modules:
   ``katz``    plain, slow, sequential FP64 implementation of the static bound
               iteration (Section 3, Algorithm 1) and of the dynamic update
               (Section 4, Algorithm 2) in its delta form.
+  ``cpp``     the static part of ``katz`` in C++ with OpenMP (``katz_ref.cpp``),
+              bit for bit the same results at any thread count, for graphs the
+              numpy form cannot hold (R-MAT scale 27) and for the CPU baseline.
   ``exact``   the same algorithms in exact rational arithmetic for tiny graphs,
               plus the definitions the algorithms are pinned against: the
               closed form of Eq. (la), brute-force walk enumeration, and the
