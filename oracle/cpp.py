@@ -56,6 +56,8 @@ def _load():
                                        ctypes.POINTER(_Res)]
         lib.ko_bounds.restype = ctypes.c_int
         lib.ko_bounds.argtypes = [i64, vp, vp, f64, i32, i32, i32, vp, vp]
+        lib.ko_walk_rows.restype = ctypes.c_int
+        lib.ko_walk_rows.argtypes = [i64, vp, vp, f64, i64, i64, i32, vp, vp]
         lib.ko_max_threads.restype = ctypes.c_int
         lib.ko_max_threads.argtypes = []
         _lib = lib
@@ -115,3 +117,16 @@ def bounds(row_ptr, col, alpha=None, r=1, undirected=True, threads=0):
     if rc != 0:
         raise MemoryError("C++ oracle ran out of host memory")
     return lo, up
+
+
+def walk_rows(row_ptr, col, alpha, lo, hi, x_in, threads=0):
+    """One walk step, x_out = alpha (A x_in) on rows lo..hi-1 (the iteration's
+    own loop), for timing a bounded sample of a large graph."""
+    rp, cl = _csr(row_ptr, col)
+    x = np.ascontiguousarray(x_in, dtype=np.float64)
+    out = np.empty(max(hi - lo, 1), dtype=np.float64)
+    rc = _load().ko_walk_rows(rp.size - 1, rp.ctypes.data, cl.ctypes.data, float(alpha), int(lo), int(hi),
+                              int(threads), x.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("invalid row range")
+    return out[:hi - lo]

@@ -58,17 +58,18 @@ int64_t max_degree(int64_t n, const int64_t* rp) {
   return d;
 }
 
-// x_new = alpha * (A x), c += x_new; returns whether some entry is nonzero.
-bool walk(int64_t n, const int64_t* rp, const int32_t* col, double alpha, const double* x, double* xn,
+// Rows lo..hi-1 of x_new = alpha * (A x) (xn indexed by row), and c += x_new
+// when c is given; returns whether some new entry is nonzero.
+bool walk(int64_t lo, int64_t hi, const int64_t* rp, const int32_t* col, double alpha, const double* x, double* xn,
           double* c) {
   bool any = false;
 #pragma omp parallel for schedule(dynamic, 2048) reduction(|| : any)
-  for (int64_t v = 0; v < n; ++v) {
+  for (int64_t v = lo; v < hi; ++v) {
     double t = 0.0;
     for (int64_t j = rp[v]; j < rp[v + 1]; ++j) t += x[col[j]];
     const double s = alpha * t;
-    xn[v] = s;
-    c[v] = c[v] + s;
+    xn[v - lo] = s;
+    if (c) c[v] = c[v] + s;
     any = any || s != 0.0;
   }
   return any;
@@ -144,7 +145,7 @@ int ko_rank_static(int64_t n, const int64_t* row_ptr, const int32_t* col, double
     int r = 0, status = 0;
     for (;;) {
       ++r;
-      const bool any = walk(n, row_ptr, col, alpha, x.data(), xn.data(), c.data());
+      const bool any = walk(0, n, row_ptr, col, alpha, x.data(), xn.data(), c.data());
       x.swap(xn);
       node_bounds(n, c.data(), x.data(), alpha, beta, undirected, lo.data(), up.data());
       if (converged(M, lo.data(), up.data(), k, eps, buf)) {
@@ -203,13 +204,24 @@ int ko_bounds(int64_t n, const int64_t* row_ptr, const int32_t* col, double alph
   try {
     std::vector<double> x(n, 1.0), xn(n), c(n, 0.0);
     for (int i = 0; i < r; ++i) {
-      walk(n, row_ptr, col, alpha, x.data(), xn.data(), c.data());
+      walk(0, n, row_ptr, col, alpha, x.data(), xn.data(), c.data());
       x.swap(xn);
     }
     node_bounds(n, c.data(), x.data(), alpha, beta, undirected, lower, upper);
   } catch (const std::bad_alloc&) {
     return -2;
   }
+  return 0;
+}
+
+// One walk step over rows lo..hi-1 only (x_out[v - lo] for those rows), the
+// loop the iteration runs; x_in holds all n entries.  Used to time a bounded
+// sample of a graph too large for a full single-thread run.
+int ko_walk_rows(int64_t n, const int64_t* row_ptr, const int32_t* col, double alpha, int64_t lo, int64_t hi,
+                 int32_t threads, const double* x_in, double* x_out) {
+  if (threads > 0) omp_set_num_threads(threads);
+  if (lo < 0 || hi > n || lo > hi) return -1;
+  walk(lo, hi, row_ptr, col, alpha, x_in, x_out, nullptr);
   return 0;
 }
 

@@ -15,21 +15,34 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import weakref
 
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libsynthgraph.so")
+_GPU_LIB_PATH = os.path.join(_HERE, "libsynthgraph_gpu.so")
 _lib = None
+_gpu_lib = None
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
 def build(force: bool = True) -> str:
-    """Compile ``gen.cpp`` into ``libsynthgraph.so`` (g++ with OpenMP)."""
+    """Compile ``gen.cpp`` into ``libsynthgraph.so`` (g++ with OpenMP) and
+    ``gen_gpu.hip`` into ``libsynthgraph_gpu.so`` (hipcc, gfx950)."""
     if force or not os.path.exists(_LIB_PATH):
         cmd = ["g++", "-O3", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
                os.path.join(_HERE, "gen.cpp"), "-o", _LIB_PATH + ".tmp"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    if force or not os.path.exists(_GPU_LIB_PATH):
+        cmd = [HIPCC, "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               os.path.join(_HERE, "gen_gpu.hip"), "-o", _GPU_LIB_PATH + ".tmp"]
+        proc = subprocess.run(cmd, capture_output=True, text=True)
+        if proc.returncode != 0:
+            raise RuntimeError("hipcc failed:\n" + proc.stdout + proc.stderr)
+        os.replace(_GPU_LIB_PATH + ".tmp", _GPU_LIB_PATH)
     return _LIB_PATH
 
 
@@ -53,27 +66,48 @@ def _load():
     lib.sg_nnz.argtypes = [vp]
     lib.sg_export.restype = None
     lib.sg_export.argtypes = [vp, vp, vp]
+    lib.sg_detach.restype = None
+    lib.sg_detach.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    lib.sg_free_array.restype = None
+    lib.sg_free_array.argtypes = [vp]
     lib.sg_free.restype = None
     lib.sg_free.argtypes = [vp]
+    lib.sg_permutation.restype = None
+    lib.sg_permutation.argtypes = [i64, u64, vp]
     lib.sg_draw.restype = None
     lib.sg_draw.argtypes = [u64, u64, u64, i64, vp]
     _lib = lib
     return lib
 
 
+def _own(ptr, count, ctype, dtype):
+    """A numpy array over `count` elements of generator-allocated memory; the
+    memory is freed (sg_free_array) when the last view of it is gone."""
+    lib = _load()
+    if count == 0:
+        lib.sg_free_array(ptr)
+        return np.empty(0, dtype=dtype)
+    buf = (ctype * count).from_address(ptr)
+    arr = np.ctypeslib.as_array(buf)
+    weakref.finalize(buf, lib.sg_free_array, ptr)
+    assert arr.dtype == dtype
+    return arr
+
+
 def _take(handle):
+    """The generated CSR, without copying: large graphs (R-MAT scale 27 holds
+    4.3e9 arcs) are handed over as they are."""
     lib = _load()
     if not handle:
         raise ValueError("graph generator rejected its arguments or ran out of memory")
-    try:
-        n = lib.sg_n(handle)
-        nnz = lib.sg_nnz(handle)
-        row_ptr = np.empty(n + 1, dtype=np.int64)
-        col = np.empty(max(nnz, 1), dtype=np.int32)
-        lib.sg_export(handle, row_ptr.ctypes.data, col.ctypes.data)
-    finally:
-        lib.sg_free(handle)
-    return row_ptr, col[:nnz]
+    n = lib.sg_n(handle)
+    nnz = lib.sg_nnz(handle)
+    rp_p = ctypes.c_void_p()
+    col_p = ctypes.c_void_p()
+    lib.sg_detach(handle, ctypes.byref(rp_p), ctypes.byref(col_p))
+    row_ptr = _own(rp_p.value, n + 1, ctypes.c_int64, np.int64)
+    col = _own(col_p.value, nnz, ctypes.c_int32, np.int32)
+    return row_ptr, col
 
 
 def erdos_renyi(n: int, m_edges: int, seed: int):
@@ -87,6 +121,60 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
     symmetrised, deduplicated, self-loops dropped, vertices relabelled by a
     seeded random permutation.  d = 1 - a - b - c."""
     return _take(_load().sg_rmat(scale, edge_factor, a, b, c, seed, int(relabel)))
+
+
+def _load_gpu():
+    global _gpu_lib
+    if _gpu_lib is None:
+        if not os.path.exists(_GPU_LIB_PATH):
+            raise RuntimeError(f"{_GPU_LIB_PATH} is not built; run synthgraph.build() first")
+        lib = ctypes.CDLL(_GPU_LIB_PATH)
+        vp = ctypes.c_void_p
+        lib.sg_gpu_rmat_begin.restype = ctypes.c_int
+        lib.sg_gpu_rmat_begin.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_uint64, vp, vp, ctypes.POINTER(vp),
+                                          ctypes.POINTER(ctypes.c_int64)]
+        lib.sg_gpu_rmat_finish.restype = ctypes.c_int
+        lib.sg_gpu_rmat_finish.argtypes = [vp, vp, vp]
+        lib.sg_gpu_rmat_abort.restype = None
+        lib.sg_gpu_rmat_abort.argtypes = [vp]
+        _gpu_lib = lib
+    return _gpu_lib
+
+
+def rmat_device(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
+                c: float = 0.19, seed: int = 1, relabel: bool = True):
+    """The graph of ``rmat`` (same arguments, bit for bit the same CSR), built
+    on the current GPU: returns (row_ptr int64, col int32) torch tensors on
+    that device.  For large scales (27: 4.3e9 arcs) this takes seconds where
+    the host build takes minutes; it needs 16 bytes of device memory per arc
+    draw while it runs."""
+    import torch
+    n = 1 << scale
+    perm = None
+    if relabel:
+        perm = np.empty(n, dtype=np.int32)
+        _load().sg_permutation(n, seed, perm.ctypes.data)
+    lib = _load_gpu()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    stream = torch.cuda.current_stream(dev)
+    handle = ctypes.c_void_p()
+    nnz = ctypes.c_int64()
+    torch.cuda.synchronize(dev)
+    rc = lib.sg_gpu_rmat_begin(scale, edge_factor, a, b, c, seed, perm.ctypes.data if perm is not None else None,
+                               ctypes.c_void_p(stream.cuda_stream), ctypes.byref(handle), ctypes.byref(nnz))
+    if rc != 0:
+        raise RuntimeError(f"GPU R-MAT build failed ({rc})")
+    try:
+        row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        col = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)[:nnz.value]
+    except Exception:
+        lib.sg_gpu_rmat_abort(handle)
+        raise
+    rc = lib.sg_gpu_rmat_finish(handle, ctypes.c_void_p(row_ptr.data_ptr()), ctypes.c_void_p(col.data_ptr()))
+    if rc != 0:
+        raise RuntimeError(f"GPU R-MAT build failed ({rc})")
+    return row_ptr, col
 
 
 def barabasi_albert(n: int, m: int, seed: int):

@@ -42,11 +42,22 @@ inline uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-// Counter-based draw: a 64-bit value for (seed, stream, counter).
-inline uint64_t draw(uint64_t seed, uint64_t stream, uint64_t counter) {
-  uint64_t key = mix64(seed * kGolden + mix64(stream + 0x632BE59BD9B4E019ull));
-  return mix64(key + (counter + 1) * kGolden);
+// Counter-based draw: a 64-bit value for (seed, stream, counter).  The key
+// depends only on (seed, stream); Draws caches it for loops over counters.
+inline uint64_t stream_key(uint64_t seed, uint64_t stream) {
+  return mix64(seed * kGolden + mix64(stream + 0x632BE59BD9B4E019ull));
 }
+
+inline uint64_t draw(uint64_t seed, uint64_t stream, uint64_t counter) {
+  return mix64(stream_key(seed, stream) + (counter + 1) * kGolden);
+}
+
+struct Draws {
+  uint64_t key;
+  Draws(uint64_t seed, uint64_t stream) : key(stream_key(seed, stream)) {}
+  uint64_t at(uint64_t counter) const { return mix64(key + (counter + 1) * kGolden); }
+  double unit(uint64_t counter) const { return (double)(at(counter) >> 11) * (1.0 / 9007199254740992.0); }
+};
 
 // Uniform double in [0, 1) with 53 random bits.
 inline double draw_unit(uint64_t seed, uint64_t stream, uint64_t counter) {
@@ -73,9 +84,13 @@ void free_graph(Graph* g) {
   delete g;
 }
 
-// Sort each row, drop duplicates, and compact into a fresh array.
-// `deg` holds the filled length of each row, `start` the row starts of `raw`.
-Graph* finish_csr(int64_t n, const int64_t* start, int64_t* deg, int32_t* raw) {
+// Sort each row of `raw` (row v at start[v], deg[v] entries), drop
+// duplicates, and compact the rows in place into canonical CSR.  Row v moves
+// to row_ptr[v] <= start[v], and row_ptr[v + 1] <= start[v + 1]; rows are moved
+// in increasing order, so a move never overwrites a row not yet moved.  `raw`
+// is shrunk to the final size and becomes the graph's column array; `start` is
+// overwritten by the row offsets (it must hold n + 1 entries).
+Graph* finish_csr(int64_t n, int64_t* start, int64_t* deg, int32_t* raw) {
 #pragma omp parallel for schedule(dynamic, 1024)
   for (int64_t v = 0; v < n; ++v) {
     int32_t* b = raw + start[v];
@@ -83,34 +98,80 @@ Graph* finish_csr(int64_t n, const int64_t* start, int64_t* deg, int32_t* raw) {
     std::sort(b, e);
     deg[v] = std::unique(b, e) - b;
   }
+  int64_t pos = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    const int64_t from = start[v];
+    start[v] = pos;
+    if (deg[v] > 0 && from != pos) std::memmove(raw + pos, raw + from, sizeof(int32_t) * deg[v]);
+    pos += deg[v];
+  }
+  start[n] = pos;
   Graph* g = new Graph;
   g->n = n;
-  g->row_ptr = (int64_t*)std::malloc(sizeof(int64_t) * (n + 1));
-  if (!g->row_ptr) { free_graph(g); return nullptr; }
-  g->row_ptr[0] = 0;
-  for (int64_t v = 0; v < n; ++v) g->row_ptr[v + 1] = g->row_ptr[v] + deg[v];
-  g->nnz = g->row_ptr[n];
-  g->col = (int32_t*)std::malloc(sizeof(int32_t) * (g->nnz > 0 ? g->nnz : 1));
-  if (!g->col) { free_graph(g); return nullptr; }
-#pragma omp parallel for schedule(dynamic, 1024)
-  for (int64_t v = 0; v < n; ++v)
-    std::memcpy(g->col + g->row_ptr[v], raw + start[v], sizeof(int32_t) * deg[v]);
+  g->nnz = pos;
+  g->row_ptr = start;
+  int32_t* shrunk = (int32_t*)std::realloc(raw, sizeof(int32_t) * (pos > 0 ? pos : 1));
+  g->col = shrunk ? shrunk : raw;
   return g;
 }
 
 // Build a symmetric CSR from a generator of undirected pairs.  `pair(i, &u, &v)`
 // returns false for a discarded draw.  Called twice per edge index (count pass
-// and fill pass), so it must be a pure function of i.
+// and fill pass), so it must be a pure function of i.  `perm` (nullable)
+// relabels both endpoints.  Peak memory: the arc array (4 bytes per arc before
+// deduplication) and two n-sized offset arrays.
+//
+// The passes take the draws in blocks: a block's pairs are generated first,
+// then the relabel and counter addresses of the whole block are prefetched
+// before they are used, so the random accesses of a block overlap (one draw
+// costs a few hundred instructions, too many for the core to run ahead to the
+// next draw's memory accesses by itself).  The arc order inside a row depends
+// on the thread schedule, but rows are sorted afterwards.
+constexpr int kBlock = 512;
+
 template <class PairFn>
-Graph* symmetric_csr(int64_t n, int64_t draws, PairFn pair) {
-  int64_t* cnt = (int64_t*)std::calloc(n + 1, sizeof(int64_t));
-  if (!cnt) return nullptr;
-#pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < draws; ++i) {
+int block_pairs(int64_t b0, int64_t draws, PairFn& pair, const int32_t* perm, int64_t* us, int64_t* vs) {
+  int m = 0;
+  const int64_t b1 = std::min<int64_t>(b0 + kBlock, draws);
+  for (int64_t i = b0; i < b1; ++i) {
     int64_t u, v;
     if (!pair(i, &u, &v)) continue;
-    __atomic_fetch_add(&cnt[u], 1, __ATOMIC_RELAXED);
-    __atomic_fetch_add(&cnt[v], 1, __ATOMIC_RELAXED);
+    us[m] = u;
+    vs[m] = v;
+    ++m;
+  }
+  if (perm) {
+    for (int j = 0; j < m; ++j) {
+      __builtin_prefetch(perm + us[j]);
+      __builtin_prefetch(perm + vs[j]);
+    }
+    for (int j = 0; j < m; ++j) {
+      us[j] = perm[us[j]];
+      vs[j] = perm[vs[j]];
+    }
+  }
+  return m;
+}
+
+template <class PairFn>
+Graph* symmetric_csr(int64_t n, int64_t draws, PairFn pair, const int32_t* perm = nullptr) {
+  int64_t* cnt = (int64_t*)std::calloc(n + 1, sizeof(int64_t));
+  if (!cnt) return nullptr;
+#pragma omp parallel
+  {
+    int64_t us[kBlock], vs[kBlock];
+#pragma omp for schedule(static)
+    for (int64_t b0 = 0; b0 < draws; b0 += kBlock) {
+      const int m = block_pairs(b0, draws, pair, perm, us, vs);
+      for (int j = 0; j < m; ++j) {
+        __builtin_prefetch(cnt + us[j], 1);
+        __builtin_prefetch(cnt + vs[j], 1);
+      }
+      for (int j = 0; j < m; ++j) {
+        __atomic_fetch_add(&cnt[us[j]], 1, __ATOMIC_RELAXED);
+        __atomic_fetch_add(&cnt[vs[j]], 1, __ATOMIC_RELAXED);
+      }
+    }
   }
   int64_t* start = (int64_t*)std::malloc(sizeof(int64_t) * (n + 1));
   if (!start) { std::free(cnt); return nullptr; }
@@ -120,31 +181,50 @@ Graph* symmetric_csr(int64_t n, int64_t draws, PairFn pair) {
   int32_t* raw = (int32_t*)std::malloc(sizeof(int32_t) * (total > 0 ? total : 1));
   if (!raw) { std::free(cnt); std::free(start); return nullptr; }
   std::memset(cnt, 0, sizeof(int64_t) * (n + 1));
-#pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < draws; ++i) {
-    int64_t u, v;
-    if (!pair(i, &u, &v)) continue;
-    int64_t pu = __atomic_fetch_add(&cnt[u], 1, __ATOMIC_RELAXED);
-    int64_t pv = __atomic_fetch_add(&cnt[v], 1, __ATOMIC_RELAXED);
-    raw[start[u] + pu] = (int32_t)v;
-    raw[start[v] + pv] = (int32_t)u;
+#pragma omp parallel
+  {
+    int64_t us[kBlock], vs[kBlock], pu[kBlock], pv[kBlock];
+#pragma omp for schedule(static)
+    for (int64_t b0 = 0; b0 < draws; b0 += kBlock) {
+      const int m = block_pairs(b0, draws, pair, perm, us, vs);
+      for (int j = 0; j < m; ++j) {
+        __builtin_prefetch(cnt + us[j], 1);
+        __builtin_prefetch(cnt + vs[j], 1);
+        __builtin_prefetch(start + us[j]);
+        __builtin_prefetch(start + vs[j]);
+      }
+      for (int j = 0; j < m; ++j) {
+        pu[j] = start[us[j]] + __atomic_fetch_add(&cnt[us[j]], 1, __ATOMIC_RELAXED);
+        pv[j] = start[vs[j]] + __atomic_fetch_add(&cnt[vs[j]], 1, __ATOMIC_RELAXED);
+      }
+      for (int j = 0; j < m; ++j) {
+        __builtin_prefetch(raw + pu[j], 1);
+        __builtin_prefetch(raw + pv[j], 1);
+      }
+      for (int j = 0; j < m; ++j) {
+        raw[pu[j]] = (int32_t)vs[j];
+        raw[pv[j]] = (int32_t)us[j];
+      }
+    }
   }
   Graph* g = finish_csr(n, start, cnt, raw);
-  std::free(raw);
-  std::free(start);
   std::free(cnt);
   return g;
 }
 
-// Seeded uniform random permutation (Fisher-Yates, counter-based draws).
+// Seeded uniform random permutation (Fisher-Yates, counter-based draws) into p[n].
+void fill_permutation(int64_t n, uint64_t seed, int32_t* p) {
+  for (int64_t i = 0; i < n; ++i) p[i] = (int32_t)i;
+  const Draws d(seed, 2);
+  for (int64_t i = n - 1; i > 0; --i) {
+    const unsigned __int128 m = (unsigned __int128)d.at((uint64_t)i) * (uint64_t)(i + 1);
+    std::swap(p[i], p[(int64_t)(m >> 64)]);
+  }
+}
+
 int32_t* random_permutation(int64_t n, uint64_t seed) {
   int32_t* p = (int32_t*)std::malloc(sizeof(int32_t) * (n > 0 ? n : 1));
-  if (!p) return nullptr;
-  for (int64_t i = 0; i < n; ++i) p[i] = (int32_t)i;
-  for (int64_t i = n - 1; i > 0; --i) {
-    int64_t j = (int64_t)draw_below(seed, 2, (uint64_t)i, (uint64_t)(i + 1));
-    std::swap(p[i], p[j]);
-  }
+  if (p) fill_permutation(n, seed, p);
   return p;
 }
 
@@ -160,6 +240,15 @@ void sg_export(void* h, int64_t* row_ptr, int32_t* col) {
   std::memcpy(row_ptr, g->row_ptr, sizeof(int64_t) * (g->n + 1));
   if (g->nnz) std::memcpy(col, g->col, sizeof(int32_t) * g->nnz);
 }
+// Hands the graph's two arrays to the caller (who frees each with
+// sg_free_array) and frees the rest of the handle.
+void sg_detach(void* h, int64_t** row_ptr, int32_t** col) {
+  Graph* g = (Graph*)h;
+  *row_ptr = g->row_ptr;
+  *col = g->col;
+  delete g;
+}
+void sg_free_array(void* p) { std::free(p); }
 
 // Erdos-Renyi G(n, M): the first M distinct non-loop pairs of the draw sequence.
 void* sg_er(int64_t n, int64_t m_edges, uint64_t seed) {
@@ -195,27 +284,26 @@ void* sg_rmat(int32_t scale, int32_t edge_factor, double a, double b, double c,
     if (!perm) return nullptr;
   }
   const double ab = a + b, abc = a + b + c;
+  const Draws d(seed, 1);
   auto pair = [&](int64_t i, int64_t* u, int64_t* v) {
     int64_t src = 0, dst = 0;
+    // Quadrant of each level from one uniform p: [0, a) top-left, [a, a+b)
+    // top-right (dst bit), [a+b, a+b+c) bottom-left (src bit), the rest
+    // bottom-right (both bits); most significant bit first.  Written without
+    // branches (the outcome is random, so branches would mispredict).
+    const uint64_t c0 = (uint64_t)i * (uint64_t)scale;
     for (int32_t l = 0; l < scale; ++l) {
-      double p = draw_unit(seed, 1, (uint64_t)i * (uint64_t)scale + (uint64_t)l);
-      int64_t bit = (int64_t)1 << (scale - 1 - l);
-      if (p < a) {
-      } else if (p < ab) {
-        dst |= bit;
-      } else if (p < abc) {
-        src |= bit;
-      } else {
-        src |= bit;
-        dst |= bit;
-      }
+      const double p = d.unit(c0 + (uint64_t)l);
+      const int64_t ge_a = p >= a, ge_ab = p >= ab, ge_abc = p >= abc;
+      src = (src << 1) | ge_ab;
+      dst = (dst << 1) | ((ge_a & (ge_ab ^ 1)) | ge_abc);
     }
     if (src == dst) return false;
-    *u = perm ? perm[src] : src;
-    *v = perm ? perm[dst] : dst;
+    *u = src;
+    *v = dst;
     return true;
   };
-  Graph* g = symmetric_csr(n, draws, pair);
+  Graph* g = symmetric_csr(n, draws, pair, perm);
   std::free(perm);
   return g;
 }
@@ -252,6 +340,10 @@ void* sg_ba(int64_t n, int32_t m, uint64_t seed) {
     return true;
   });
 }
+
+// The relabelling permutation of sg_rmat(scale, ..., seed) for n = 2^scale
+// (used by the GPU build of the same graph).
+void sg_permutation(int64_t n, uint64_t seed, int32_t* out) { fill_permutation(n, seed, out); }
 
 // Raw counter-based draws, exposed so tests can pin the generator itself.
 void sg_draw(uint64_t seed, uint64_t stream, uint64_t first, int64_t count, uint64_t* out) {

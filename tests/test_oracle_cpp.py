@@ -146,3 +146,13 @@ def test_argument_errors():
             cpp.rank_static(rp, col, **kw)
     with pytest.raises(ValueError):
         cpp.bounds(rp, col, None, 0)
+
+
+def test_walk_rows_is_one_iteration_of_the_walk():
+    rp, col = sg.rmat(11, 16, 0.57, 0.19, 0.19, seed=7)
+    n = len(rp) - 1
+    alpha = 1.0 / (1 + sg.max_degree(rp))
+    _, x1 = oracle.walk_state(rp, col, alpha, 1)
+    _, x2 = oracle.walk_state(rp, col, alpha, 2)
+    assert np.array_equal(cpp.walk_rows(rp, col, alpha, 0, n, np.ones(n), threads=1), x1)
+    assert np.array_equal(cpp.walk_rows(rp, col, alpha, 100, 900, x1, threads=4), x2[100:900])
