@@ -257,9 +257,9 @@ class DynamicOracle:
     * alpha is fixed at construction; gamma follows the current deg_max.  A batch
       that would make alpha * deg_max >= 1, or deg_max exceed ``degree_cap``
       (0 = no cap beyond Theorem 1), is rejected.
-    * updateLevel(i) walks a snapshot of S (the nodes whose walk counts may have
-      changed at level i-1); omega'_i defaults to omega_i for untouched nodes; the
-      level-i change of every node in S is added to its running c_r.
+    * The level-by-level update uses S_i, the nodes whose walk counts can change
+      at level i (see ``update``); omega'_i equals omega_i outside S_i, and the
+      level-i change of every node in S_i is added to its running c_r.
     * Reactivation uses the paper's test u(w) >= min_{x in M} l(x) - eps.
     * Afterwards converged() is evaluated and static iterations continue from r
       until it holds (or max_iter / exact ties stop the loop as in rank_static).
@@ -321,51 +321,61 @@ class DynamicOracle:
 
     # -- Algorithm 2 ---------------------------------------------------------
     def update(self, ins_pairs, del_pairs):
+        """Applies one batch (Section 4, Algorithm 2) and re-certifies the top-k.
+
+        The walk vectors of the new graph follow from the old ones level by
+        level.  Split the arcs into K = E minus D (kept), I (inserted) and D
+        (deleted); the new adjacency is A' = A_K + A_I and the old one
+        A = A_K + A_D.  With x_i = alpha A x_{i-1} and x'_i = alpha A' x'_{i-1}
+        (x'_0 = x_0 = 1):
+
+            x'_i - x_i = alpha (A_K (x'_{i-1} - x_{i-1}) + A_I x'_{i-1} - A_D x_{i-1}).
+
+        The difference is zero outside S_i, the nodes whose walk counts can
+        change at level i: the sources of inserted and deleted arcs, and every
+        node with a kept arc into S_{i-1}.  Only those nodes are updated, and
+        c_r moves by the sum of their level differences.
+        """
         ins = np.asarray(ins_pairs if ins_pairs is not None else [], dtype=np.int64).reshape(-1, 2)
         dels = np.asarray(del_pairs if del_pairs is not None else [], dtype=np.int64).reshape(-1, 2)
         arcs_I, arcs_D, keys_E, kdl, new_rp, new_col = self._validate_batch(ins, dels)
         n, alpha = self.n, self.alpha
 
-        # E <- E \ D ; A_ED[w, v] = 1 for w -> v in E \ D.
-        rp_ed, col_ed = _csr_from_keys(keys_E[~np.isin(keys_E, kdl)], n)
-        A_ED = adjacency(rp_ed, col_ed, n)
+        rp_k, col_k = _csr_from_keys(keys_E[~np.isin(keys_E, kdl)], n)
+        A_K = adjacency(rp_k, col_k, n)
+        A_I = sp.csr_matrix((np.ones(len(arcs_I)), (arcs_I[:, 0], arcs_I[:, 1])), shape=(n, n))
+        A_D = sp.csr_matrix((np.ones(len(arcs_D)), (arcs_D[:, 0], arcs_D[:, 1])), shape=(n, n))
 
-        # S <- sources of updated arcs, T <- their targets.
-        inS = np.zeros(n, dtype=bool)
-        inS[arcs_I[:, 0]] = True
-        inS[arcs_D[:, 0]] = True
-
+        seeds = np.zeros(n, dtype=bool)          # sources of updated arcs
+        seeds[arcs_I[:, 0]] = True
+        seeds[arcs_D[:, 0]] = True
+        S = seeds.copy()                          # S_1
         X_new = [self.X[0]]
         for i in range(1, self.r + 1):
-            # updateLevel(i)
-            x_old, x_prev_old, x_prev_new = self.X[i], self.X[i - 1], X_new[i - 1]
-            x_new = x_old.copy()
-            snap = inS.copy()
-            delta = np.where(snap, x_prev_new - x_prev_old, 0.0)
-            # for v in S, for w -> v in E: omega'_i(w) += omega'_{i-1}(v) - omega_{i-1}(v)
-            x_new += alpha * (A_ED @ delta)
-            inS |= (A_ED @ snap.astype(np.float64)) > 0
-            # for w -> v in I: omega'_i(w) += omega'_{i-1}(v)
-            np.add.at(x_new, arcs_I[:, 0], alpha * x_prev_new[arcs_I[:, 1]])
-            # for w -> v in D: omega'_i(w) -= omega_{i-1}(v)
-            np.subtract.at(x_new, arcs_D[:, 0], alpha * x_prev_old[arcs_D[:, 1]])
-            # for w in S: c_i(w) += alpha^i (omega'_i(w) - omega_i(w))
-            self.c[inS] += x_new[inS] - x_old[inS]
+            if i > 1:
+                S = seeds | ((A_K @ S.astype(np.float64)) > 0)
+            diff_prev = X_new[i - 1] - self.X[i - 1]
+            delta = alpha * (A_K @ diff_prev + A_I @ X_new[i - 1] - A_D @ self.X[i - 1])
+            assert not np.any(delta[~S]), "level difference outside the affected set"
+            x_new = self.X[i].copy()
+            x_new[S] = self.X[i][S] + delta[S]
+            self.c[S] += x_new[S] - self.X[i][S]
             X_new.append(x_new)
         self.X = X_new
 
-        # E <- (E \ D) u I ; gamma from the new deg_max.
+        # The graph is now (E minus D) plus I; gamma follows its largest degree.
         self.row_ptr, self.col = new_rp, new_col
         dmax = max_degree(new_rp)
         gamma, beta = gamma_beta(alpha, dmax)
         lower, upper = node_bounds(self.c, self.X[self.r], alpha, beta, self.undirected)
 
-        # Reactivation: u(w) >= min_{x in M} l(x) - eps.
+        # Nodes whose upper bound reaches the smallest lower bound in M, less eps,
+        # join M again (the test as Section 4 states it).
         thr = lower[self.M].min() - self.eps
         react = np.nonzero(upper >= thr)[0]
         M = np.union1d(self.M, react).astype(np.int64)
 
-        # while not converged(): more iterations of the static algorithm.
+        # Static iterations resume from r until the top-k test holds.
         A = adjacency(new_rp, new_col, n)
         status = OK
         while True:
