@@ -157,3 +157,44 @@ def rank_static_exact(row_ptr, col, alpha, k, eps=0, undirected=True, max_iter=2
             return M[:k], r, 3, run
         if r >= max_iter:
             return M[:k], r, 1, run
+
+
+def criterion_holds_exact(lower, upper, eps, criterion, pair=None):
+    """The stopping criteria of Section 3.1 from their pairwise definitions,
+    on exact values, by brute force over all pairs:
+    ranking: every two nodes are eps-separated (the one with the larger lower
+    bound, ties by id, ahead); score: u - l < eps for every node; pair: the two
+    given nodes are eps-separated."""
+    n = len(lower)
+    eps = Fraction(eps)
+
+    def sep(a, b):
+        w, v = (a, b) if (lower[a] > lower[b] or (lower[a] == lower[b] and a < b)) else (b, a)
+        return lower[w] > upper[v] - eps
+
+    if criterion == "ranking":
+        return all(sep(a, b) for a in range(n) for b in range(a + 1, n))
+    if criterion == "score":
+        return all(upper[v] - lower[v] < eps for v in range(n))
+    if criterion == "pair":
+        return sep(*pair)
+    raise ValueError(criterion)
+
+
+def first_stop_exact(row_ptr, col, alpha, eps, criterion, pair=None, undirected=True, max_iter=200):
+    """The first r >= 1 at which the criterion holds on the exact bounds, or None."""
+    run = ExactRun(row_ptr, col, alpha, undirected)
+    for r in range(1, max_iter + 1):
+        run.step()
+        lower, upper = run.bounds()
+        if criterion_holds_exact(lower, upper, eps, criterion, pair):
+            return r, run
+        if not any(run.omega[-1]):
+            return None, run
+    return None, run
+
+
+def separated_pairs_bruteforce(lower, upper):
+    """Unordered pairs {w, v} with l(w) > u(v) or l(v) > u(w), counted one by one."""
+    n = len(lower)
+    return sum(1 for a in range(n) for b in range(a + 1, n) if lower[a] > upper[b] or lower[b] > upper[a])

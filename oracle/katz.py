@@ -46,6 +46,9 @@ W_ITER_LIMIT = 1
 W_PRECISION_LIMIT = 2
 W_EXACT_TIES = 3
 
+# Stopping criteria (Section 3.1).
+TOPK, RANKING, SCORE, PAIR = 0, 1, 2, 3
+
 
 class UpdateRejected(ValueError):
     """An edge-update batch violates the preconditions of Algorithm 2."""
@@ -139,6 +142,34 @@ def converged(M, lower, upper, k, eps):
     return (not bool(not_separated.any())), M_new
 
 
+def converged_score(lower, upper, eps):
+    """Score criterion (Section 3.1): every node's interval is narrower than
+    eps, u - l < eps, so every Katz score is known up to eps."""
+    return bool(np.all(upper - lower < eps))
+
+
+def converged_pair(lower, upper, eps, a, b):
+    """Pair criterion (Section 3.1): the two given nodes are eps-separated.
+    With w the one ahead by (lower desc, id asc) and v the other:
+    l(w) > u(v) - eps.  Returns (separated, (w, v))."""
+    w, v = (a, b) if (lower[a] > lower[b] or (lower[a] == lower[b] and a < b)) else (b, a)
+    return bool(lower[w] > upper[v] - eps), (w, v)
+
+
+def separated_fraction(lower, upper):
+    """Fraction of the n(n-1)/2 unordered node pairs {w, v} that the bounds
+    separate (not only eps-separate): l(w) > u(v) or l(v) > u(w) (the
+    "Separation" column of Table 1).  Both cannot hold for one pair, since
+    l <= u; so the count is the number of ordered pairs with l(w) > u(v),
+    found for each v by a search in the sorted lower bounds."""
+    n = lower.size
+    if n < 2:
+        return 1.0
+    srt = np.sort(lower)
+    above = n - np.searchsorted(srt, upper, side="right")    # #{w : l(w) > u(v)}
+    return float(above.sum()) / (n * (n - 1) / 2)
+
+
 def _result(M, c, s, r, status, alpha, gamma, beta, undirected, k):
     lower, upper = node_bounds(c, s, alpha, beta, undirected)
     top = M[:k]
@@ -161,8 +192,16 @@ def _validate(n, k, eps, max_iter):
 
 
 def rank_static(row_ptr, col, alpha=None, k=10, eps=0.0, undirected=True,
-                max_iter=1000, history=None):
-    """Algorithm 1 (Section 3.2) with the top-k criterion.
+                max_iter=1000, history=None, criterion=TOPK, pair=None):
+    """Algorithm 1 (Section 3.2) with the top-k criterion, or another
+    stopping criterion of Section 3.1:
+
+    * RANKING: every node eps-separated from every other; this is the top-k
+      criterion with k = n (``k`` is ignored).
+    * SCORE: u - l < eps for every node; the result lists every node by
+      (lower desc, id asc) (``k`` is ignored).
+    * PAIR: the two nodes of ``pair`` are eps-separated; the result lists the
+      two by (lower desc, id asc) (``k`` is ignored).
 
     ``alpha=None`` selects 1/(1 + deg_max).  If ``history`` is a list it receives
     x_0, x_1, ..., x_r (used by the dynamic oracle).
@@ -172,6 +211,14 @@ def rank_static(row_ptr, col, alpha=None, k=10, eps=0.0, undirected=True,
     dmax = max_degree(row_ptr)
     alpha = default_alpha(dmax) if alpha is None else float(alpha)
     check_alpha(alpha, dmax)
+    if criterion == PAIR:
+        if pair is None or len(pair) != 2 or not all(0 <= int(q) < n for q in pair) or pair[0] == pair[1]:
+            raise ValueError("the pair criterion needs two distinct node ids")
+        pair = (int(pair[0]), int(pair[1]))
+    elif criterion not in (TOPK, RANKING, SCORE):
+        raise ValueError(f"unknown criterion {criterion!r}")
+    if criterion != TOPK:
+        k = n if criterion in (RANKING, SCORE) else 2
     _validate(n, k, eps, max_iter)
     gamma, beta = gamma_beta(alpha, dmax)
     A = adjacency(row_ptr, col, n)
@@ -189,7 +236,14 @@ def rank_static(row_ptr, col, alpha=None, k=10, eps=0.0, undirected=True,
         if history is not None:
             history.append(x.copy())
         lower, upper = node_bounds(c, x, alpha, beta, undirected)
-        ok, M = converged(M, lower, upper, k, eps)
+        if criterion == SCORE:
+            ok = converged_score(lower, upper, eps)
+            M = order_by_lower(np.arange(n, dtype=np.int64), lower)
+        elif criterion == PAIR:
+            ok, wv = converged_pair(lower, upper, eps, *pair)
+            M = np.array(wv, dtype=np.int64)
+        else:
+            ok, M = converged(M, lower, upper, k, eps)
         if ok:
             status = OK
             break
@@ -398,3 +452,62 @@ class DynamicOracle:
         self.result = _result(M, self.c.copy(), self.X[self.r].copy(), self.r, status,
                               alpha, gamma, beta, self.undirected, self.k)
         return self.result
+
+
+# ---------------------------------------------------------------------------
+# Bounds of a few sampled nodes of a graph too large for the whole-graph run.
+# ---------------------------------------------------------------------------
+
+def local_bounds(fetch_rows, deg, alpha, nodes, r, undirected=True, dmax=None):
+    """l_r(v) and u_r(v) of the nodes v in ``nodes`` alone (Theorem 1 after r
+    iterations of Eq. (basic_recurrence)), each computed from its own r-hop
+    neighbourhood: x_1(w) = alpha deg(w) for any w, and x_i(v) = alpha * (sum
+    of x_{i-1} over the row of v, left to right in CSR order), the same
+    arithmetic in the same order as ``bounds``, so the values are bit for bit
+    those of the whole-graph run.
+
+    ``fetch_rows(ids)`` returns (sub_ptr, sub_col) for a sorted array of node
+    ids: the concatenated rows of those nodes and their offsets.  ``deg`` is
+    the out-degree of every node; ``dmax`` defaults to its maximum (gamma of
+    Theorem 1 depends on the whole graph's maximum degree).
+
+    Returns (nodes sorted, lower, upper, c_r, x_r) as arrays.
+    """
+    deg = np.asarray(deg)
+    dmax = int(deg.max()) if dmax is None else int(dmax)
+    check_alpha(alpha, dmax)
+    if r < 1:
+        raise ValueError("r must be >= 1")
+    _, beta = gamma_beta(alpha, dmax)
+    nodes = np.unique(np.asarray(nodes, dtype=np.int64))
+    # need[i]: the nodes whose x_i is required; rows[v]: the row of v.
+    need = {r: nodes}
+    rows = {}
+    for i in range(r, 1, -1):
+        missing = np.array([v for v in need[i].tolist() if v not in rows], dtype=np.int64)
+        if missing.size:
+            sub_ptr, sub_col = fetch_rows(missing)
+            sub_ptr = np.asarray(sub_ptr, dtype=np.int64)
+            sub_col = np.asarray(sub_col, dtype=np.int64)
+            for j, v in enumerate(missing.tolist()):
+                rows[v] = sub_col[sub_ptr[j]:sub_ptr[j + 1]]
+        nbrs = [rows[v] for v in need[i].tolist()]
+        need[i - 1] = np.union1d(nodes, np.concatenate(nbrs) if nbrs else np.empty(0, dtype=np.int64))
+    # x[i] = (ids, values) over need[i].
+    x = {1: (need[1], alpha * deg[need[1]].astype(np.float64))}
+    for i in range(2, r + 1):
+        ids_prev, val_prev = x[i - 1]
+        vals = np.empty(need[i].size, dtype=np.float64)
+        for j, v in enumerate(need[i].tolist()):
+            row = rows[v]
+            terms = val_prev[np.searchsorted(ids_prev, row)]
+            vals[j] = alpha * (np.cumsum(terms)[-1] if terms.size else 0.0)
+        x[i] = (need[i], vals)
+    c = np.zeros(nodes.size)
+    for i in range(1, r + 1):
+        ids, vals = x[i]
+        c = c + vals[np.searchsorted(ids, nodes)]
+    ids, vals = x[r]
+    s = vals[np.searchsorted(ids, nodes)]
+    lower, upper = node_bounds(c, s, alpha, beta, undirected)
+    return nodes, lower, upper, c, s

@@ -74,6 +74,8 @@ def _load():
     lib.sg_free.argtypes = [vp]
     lib.sg_permutation.restype = None
     lib.sg_permutation.argtypes = [i64, u64, vp]
+    lib.sg_rmat_pairs.restype = None
+    lib.sg_rmat_pairs.argtypes = [i32, f64, f64, f64, u64, i32, u64, u64, i64, vp, vp]
     lib.sg_draw.restype = None
     lib.sg_draw.argtypes = [u64, u64, u64, i64, vp]
     _lib = lib
@@ -121,6 +123,19 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
     symmetrised, deduplicated, self-loops dropped, vertices relabelled by a
     seeded random permutation.  d = 1 - a - b - c."""
     return _take(_load().sg_rmat(scale, edge_factor, a, b, c, seed, int(relabel)))
+
+
+def rmat_pairs(scale: int, count: int, a: float = 0.57, b: float = 0.19, c: float = 0.19, seed: int = 1,
+               relabel: bool = True, stream: int = 7, first: int = 0):
+    """``count`` endpoint pairs drawn from the R-MAT distribution of
+    ``rmat(scale, ..., seed)`` (same quadrant recursion, same relabelling),
+    from counter stream ``stream`` starting at pair ``first``; self-loops
+    included.  Returns an int64 array of shape (count, 2)."""
+    u = np.empty(count, dtype=np.int32)
+    v = np.empty(count, dtype=np.int32)
+    if count:
+        _load().sg_rmat_pairs(scale, a, b, c, seed, int(relabel), stream, first, count, u.ctypes.data, v.ctypes.data)
+    return np.stack([u, v], 1).astype(np.int64)
 
 
 def _load_gpu():

@@ -345,6 +345,32 @@ void* sg_ba(int64_t n, int32_t m, uint64_t seed) {
 // (used by the GPU build of the same graph).
 void sg_permutation(int64_t n, uint64_t seed, int32_t* out) { fill_permutation(n, seed, out); }
 
+// Endpoint pairs drawn from the R-MAT distribution of sg_rmat(scale, ...,
+// seed) -- the same quadrant recursion and the same relabelling -- from the
+// counter stream `stream` (the graph itself uses stream 1), pairs first ..
+// first + count - 1.  Self-loops are kept; callers filter what they need.
+// Used for edge insertions that follow the graph's own degree distribution.
+void sg_rmat_pairs(int32_t scale, double a, double b, double c, uint64_t seed, int32_t relabel,
+                   uint64_t stream, uint64_t first, int64_t count, int32_t* out_u, int32_t* out_v) {
+  const int64_t n = (int64_t)1 << scale;
+  int32_t* perm = relabel ? random_permutation(n, seed) : nullptr;
+  const double ab = a + b, abc = a + b + c;
+  const Draws d(seed, stream);
+  for (int64_t i = 0; i < count; ++i) {
+    int64_t src = 0, dst = 0;
+    const uint64_t c0 = (first + (uint64_t)i) * (uint64_t)scale;
+    for (int32_t l = 0; l < scale; ++l) {
+      const double p = d.unit(c0 + (uint64_t)l);
+      const int64_t ge_a = p >= a, ge_ab = p >= ab, ge_abc = p >= abc;
+      src = (src << 1) | ge_ab;
+      dst = (dst << 1) | ((ge_a & (ge_ab ^ 1)) | ge_abc);
+    }
+    out_u[i] = perm ? perm[src] : (int32_t)src;
+    out_v[i] = perm ? perm[dst] : (int32_t)dst;
+  }
+  std::free(perm);
+}
+
 // Raw counter-based draws, exposed so tests can pin the generator itself.
 void sg_draw(uint64_t seed, uint64_t stream, uint64_t first, int64_t count, uint64_t* out) {
   for (int64_t i = 0; i < count; ++i) out[i] = draw(seed, stream, first + (uint64_t)i);

@@ -77,3 +77,22 @@ def test_small_shapes():
     assert list(np.diff(rp)) == [1, 1, 1, 0]
     rp, col = sg.with_isolated(*sg.cycle_graph(3), 2)
     assert list(np.diff(rp)) == [2, 2, 2, 0, 0]
+
+
+def test_rmat_pairs_follow_the_graph_distribution():
+    """Pairs of counter stream 1 are the graph's own edge draws: every non-loop
+    pair is an arc of rmat(scale, seed); another stream gives other pairs with
+    the same skew (the graph's hubs are hit far more often than average)."""
+    rp, col = sg.rmat(12, seed=4)
+    n = len(rp) - 1
+    keys = set((np.repeat(np.arange(n), np.diff(rp)) * n + col).tolist())
+    own = sg.rmat_pairs(12, 20000, seed=4, stream=1)
+    own = own[own[:, 0] != own[:, 1]]
+    assert all(int(a) * n + int(b) in keys for a, b in own)
+    other = sg.rmat_pairs(12, 20000, seed=4, stream=7)
+    assert not np.array_equal(other[:100], sg.rmat_pairs(12, 100, seed=4, stream=1))
+    hits = np.bincount(other.ravel(), minlength=n)
+    deg = np.diff(rp)
+    hubs = np.argsort(-deg)[:16]
+    assert hits[hubs].mean() > 20 * hits.mean()
+    assert np.array_equal(sg.rmat_pairs(12, 50, seed=4, stream=7, first=10), other[10:60])

@@ -420,3 +420,148 @@ def test_dynamic_reactivation_and_more_iterations():
     st = oracle.rank_static(dyn.row_ptr, dyn.col, alpha, 2, 1e-7)
     assert list(res.topk) == list(st.topk)
     assert 9 in list(res.topk)
+
+
+# --- bounds of sampled nodes (graphs too large for the whole-graph run) -------
+
+def _host_fetch(rp, col):
+    deg = np.diff(rp)
+
+    def fetch(ids):
+        ptr = np.concatenate([[0], np.cumsum(deg[ids])])
+        parts = [col[rp[v]:rp[v + 1]] for v in ids]
+        return ptr, (np.concatenate(parts) if parts else np.empty(0, dtype=np.int32))
+    return fetch
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_local_bounds_walks_match_enumeration(r):
+    """Sampled-node walk vectors against brute-force walk enumeration on small
+    graphs, directed and undirected: x_r(v) = alpha^r omega_r(v)."""
+    for name, (rp, col), und in small_graphs()[:10]:
+        if not _nonempty(rp):
+            continue
+        deg = np.diff(rp)
+        n = len(rp) - 1
+        alpha = 1.0 / (2.0 + deg.max())
+        nodes = np.arange(0, n, 2)
+        ns, lo, up, c, s = K.local_bounds(_host_fetch(rp, col), deg, alpha, nodes, r, und)
+        omega = exact.walks_bruteforce(rp, col, r)
+        want_s = np.array([alpha ** r * omega[v] for v in ns])
+        assert np.allclose(s, want_s, rtol=8 * r * ULP, atol=0), (name, r)
+        want_c = np.array([sum(alpha ** i * exact.walks_bruteforce(rp, col, i)[v] for i in range(1, r + 1)) for v in ns])
+        assert np.allclose(c, want_c, rtol=16 * r * ULP, atol=0), (name, r)
+
+
+def test_local_bounds_equal_whole_graph_run():
+    """On R-MAT 10 (undirected) and a random directed graph, the sampled-node
+    bounds are bit for bit the whole-graph oracle's, hubs and isolated nodes
+    included."""
+    cases = [(sg.rmat(10, seed=1), True), (sg.random_graph(60, 0.1, 5, undirected=False), False)]
+    for (rp, col), und in cases:
+        deg = np.diff(rp)
+        alpha = K.default_alpha(int(deg.max()))
+        nodes = np.unique(np.r_[0, 5, np.argmax(deg), np.argmin(deg), len(rp) - 2])
+        for r in (1, 2, 3):
+            lo, up = K.bounds(rp, col, alpha, r, und)
+            ns, l2, u2, _, _ = K.local_bounds(_host_fetch(rp, col), deg, alpha, nodes, r, und)
+            assert np.array_equal(ns, nodes)
+            assert np.array_equal(l2, lo[ns]) and np.array_equal(u2, up[ns])
+
+
+def test_local_bounds_regular_closed_form():
+    """On a cycle (2-regular) every x_i is (2 alpha)^i and c_r a geometric sum."""
+    rp, col = sg.cycle_graph(11)
+    deg = np.diff(rp)
+    alpha = 0.3
+    ns, lo, up, c, s = K.local_bounds(_host_fetch(rp, col), deg, alpha, [3, 7], 3)
+    q = 2 * alpha
+    assert np.allclose(s, q ** 3, rtol=8 * ULP)
+    assert np.allclose(c, q + q ** 2 + q ** 3, rtol=16 * ULP)
+    assert np.allclose(lo, c + alpha * s, rtol=4 * ULP)
+    gamma = 2 / (1 - 2 * alpha)
+    assert np.allclose(up, c + alpha * gamma * s, rtol=4 * ULP)
+
+
+# --- the other stopping criteria (Section 3.1) ----------------------------------
+
+def _crit_graphs():
+    out = []
+    for seed in range(8):
+        out.append(sg.random_graph(7 + seed % 4, 0.4, 300 + seed))
+    out.append(sg.star_graph(6))
+    out.append(sg.path_graph(7))
+    return out
+
+
+@pytest.mark.parametrize("criterion", ["ranking", "score", "pair"])
+def test_criteria_stop_where_the_exact_definition_first_holds(criterion):
+    """The FP64 oracle stops at the first r at which the criterion holds on the
+    exact bounds (pairwise definitions, brute force), wherever no pair sits
+    within rounding of the eps threshold; its output satisfies the definition
+    on the exact Katz scores."""
+    code = {"ranking": K.RANKING, "score": K.SCORE, "pair": K.PAIR}[criterion]
+    eps = 1e-3
+    checked = 0
+    for rp, col in _crit_graphs():
+        if not _nonempty(rp):
+            continue
+        n = len(rp) - 1
+        alpha = Fraction(1, 2 + sg.max_degree(rp))
+        pair = (0, n - 1) if criterion == "pair" else None
+        r_ex, run = exact.first_stop_exact(rp, col, alpha, Fraction(eps), criterion, pair)
+        res = K.rank_static(rp, col, float(alpha), eps=eps, criterion=code, pair=pair)
+        if r_ex is None:
+            assert res.status != K.OK
+            continue
+        # Skip graphs where some pair's margin is within rounding of eps.
+        lo, up = run.bounds(r_ex)
+        margins = [abs(float(lo[a] - (up[b] - Fraction(eps)))) for a in range(n) for b in range(n) if a != b]
+        margins += [abs(float(up[v] - lo[v] - Fraction(eps))) for v in range(n)]
+        if min(margins) < 1e-12:
+            continue
+        checked += 1
+        assert res.status == K.OK and res.iterations == r_ex
+        c = exact.katz_exact(rp, col, alpha)
+        if criterion == "score":
+            assert all(abs(Fraction(float(res.lower_all[v])) - c[v]) < Fraction(eps) for v in range(n))
+            assert len(res.topk) == n
+        else:
+            order = [int(v) for v in res.topk]
+            assert len(order) == (n if criterion == "ranking" else 2)
+            for i in range(len(order)):
+                for j in range(i + 1, len(order)):
+                    assert c[order[i]] > c[order[j]] - Fraction(eps)
+    assert checked >= 3
+
+
+def test_ranking_criterion_is_topk_with_k_equal_n():
+    """Section 3.1: for k = n the top-k criterion reduces to the ranking criterion."""
+    for seed in range(4):
+        rp, col = sg.rmat(8, seed=seed)
+        n = len(rp) - 1
+        a = K.rank_static(rp, col, None, n, 1e-4)
+        b = K.rank_static(rp, col, None, 5, 1e-4, criterion=K.RANKING)
+        assert np.array_equal(a.topk, b.topk) and a.iterations == b.iterations and a.status == b.status
+
+
+def test_separated_fraction_matches_bruteforce():
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        n = int(rng.integers(2, 40))
+        lo = rng.random(n)
+        up = lo + rng.random(n) * rng.choice([0.0, 0.01, 0.5], n)
+        lo[rng.integers(0, n, 3)] = lo[0]            # some equal values
+        up = np.maximum(up, lo)
+        want = exact.separated_pairs_bruteforce(lo.tolist(), up.tolist()) / (n * (n - 1) / 2)
+        assert K.separated_fraction(lo, up) == pytest.approx(want, abs=1e-15)
+    assert K.separated_fraction(np.array([1.0, 2.0, 3.0]), np.array([1.0, 2.0, 3.0])) == 1.0
+    assert K.separated_fraction(np.array([1.0, 1.0]), np.array([2.0, 2.0])) == 0.0
+
+
+def test_pair_criterion_argument_checks():
+    rp, col = sg.cycle_graph(5)
+    with pytest.raises(ValueError):
+        K.rank_static(rp, col, 0.3, criterion=K.PAIR, pair=(1, 1))
+    with pytest.raises(ValueError):
+        K.rank_static(rp, col, 0.3, criterion=K.PAIR, pair=(0, 9))
