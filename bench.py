@@ -1,9 +1,12 @@
 #!/usr/bin/env python3
 """Benchmark: certified top-k Katz ranking on one MI355X.
 
-Workload: R-MAT scale 22 (2^22 nodes, edge factor 16, a,b,c,d = .57,.19,.19,.05,
-symmetrised, deduplicated, self-loops dropped, seeded relabelling; seed 1),
-CSR with int32 offsets, alpha = 1/(1 + deg_max), top-k = 1000, eps = 1e-6.
+Default workload (the headline line): R-MAT scale 27 (2^27 nodes, edge factor
+16, a,b,c,d = .57,.19,.19,.05, symmetrised, deduplicated, self-loops dropped,
+seeded relabelling; seed 3), CSR with int64 row offsets (about 4.3e9 directed
+entries), alpha = 1/(1 + deg_max), top-k = 100, eps = 1e-6.  The same
+measurement on R-MAT scale 22 (seed 1, int32 offsets, top-1000) is reported
+beside it under "rmat22".  The graphs are generated on the device.
 
 One step is one katz_rank_static call: binning, every iteration (walk step,
 selection, converged()) until the ranking is certified, and the output writes,
@@ -12,6 +15,10 @@ headline value; the plain FP64 form is timed the same way beside it.
 
 value = GTEPS = r * nnz / t_step / 1e9 with nnz the directed CSR entries (each
 undirected edge counted twice, as traversed).
+
+CPU baseline: the C++/OpenMP FP64 oracle's full certified run on every host
+core (it also checks that both forms return the oracle's top-k), plus a
+single-thread walk over a leading row range.
 """
 import argparse
 import json
@@ -23,34 +30,43 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SCALE, EDGE_FACTOR, SEED, K, EPS = 22, 16, 1, 1000, 1e-6
+EDGE_FACTOR, EPS = 16, 1e-6
+WORKLOADS = {
+    27: dict(scale=27, seed=3, k=100, rp64=True, name="rmat27_top100_eps1e-6"),
+    22: dict(scale=22, seed=1, k=1000, rp64=False, name="rmat22_top1000_eps1e-6"),
+}
 
 
-def algorithmic_bytes_per_walk_step(n, nnz, precision):
+def algorithmic_bytes_per_walk_step(n, nnz, precision, rp64):
     """Compulsory HBM bytes of one walk step (iteration r >= 2): every column
-    index once (4 B per arc) and, per node, the int32 row offset (4 B), the
-    previous walk entry (4 B FP32 / 8 B FP64), the new walk entry (4 / 8 B), the
-    read-modify-write of c (16 B), and for FP32 the margin accumulator (8 B)."""
-    per_node = 4 + 4 + 4 + 16 + 8 if precision == "fp32" else 4 + 8 + 8 + 16
+    index once (4 B per arc) and, per node, the row offset (4 B int32 / 8 B
+    int64), the previous walk entry (4 B FP32 / 8 B FP64), the new walk entry
+    (4 / 8 B), the read-modify-write of c (16 B), and for FP32 the margin
+    accumulator (8 B)."""
+    off = 8 if rp64 else 4
+    per_node = off + (4 + 4 + 16 + 8 if precision == "fp32" else 8 + 8 + 16)
     return 4 * nnz + per_node * n
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "walk_step_rmat22_counters.json")
+def counters_path(scale):
+    return os.path.join(ROOT, "profiles", f"walk_step_rmat{scale}_counters.json")
 
 
-def measured_traffic(tuning_arg):
+def measured_traffic(scale, tuning_arg):
     """HBM bytes per walk_step launch from the committed FETCH_SIZE / WRITE_SIZE
-    record (scaled by the copy calibration stored with it), or None when the
-    kernel sources or the launch tuning differ from the ones measured."""
+    record of this workload (scaled by the copy calibration stored with it), or
+    None when the kernel sources or the launch tuning differ from the ones
+    measured."""
     import hashlib
+    path = counters_path(scale)
     try:
-        rec = json.load(open(COUNTERS))
+        rec = json.load(open(path))
     except (OSError, ValueError):
         return None, "no counter record"
-    for path, digest in rec["sources_sha256"].items():
-        with open(os.path.join(ROOT, path), "rb") as f:
+    for src, digest in rec["sources_sha256"].items():
+        with open(os.path.join(ROOT, src), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
-                return None, f"kernel source changed since the counters were taken ({path})"
+                return None, f"kernel source changed since the counters were taken ({src})"
     other = rec.get("by_tuning", {})
     if rec["tuning"] == tuning_arg:
         traffic = rec["traffic_bytes_per_launch"]
@@ -60,23 +76,181 @@ def measured_traffic(tuning_arg):
         return None, f"counters taken at tunings {[rec['tuning']] + sorted(other)}, timed at {tuning_arg}"
     return traffic, ("FETCH_SIZE x%.2f + WRITE_SIZE x%.2f per launch at tuning %s, from %s" % (
         rec["calibration"]["fetch_scale"], rec["calibration"]["write_scale"], tuning_arg,
-        os.path.relpath(COUNTERS, ROOT)))
+        os.path.relpath(path, ROOT)))
 
 
-def time_form(katz, torch, rp_t, col_t, precision, steps, warmup, flags=0):
+def time_form(katz, torch, rp_t, col_t, k, precision, steps, warmup, flags=0):
     for _ in range(warmup):
-        res = katz.rank_static(rp_t, col_t, K, eps=EPS, precision=precision, flags=flags)
+        res = katz.rank_static(rp_t, col_t, k, eps=EPS, precision=precision, flags=flags)
     torch.cuda.synchronize()
     katz.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        res = katz.rank_static(rp_t, col_t, K, eps=EPS, precision=precision, flags=flags)
+        res = katz.rank_static(rp_t, col_t, k, eps=EPS, precision=precision, flags=flags)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     tm = katz.timing_read()
     katz.timing_enable(False)
     return res, (t1 - t0) / steps, tm
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_static(args, katz, sg, torch, np, wl):
+    """Times both forms on one R-MAT workload; returns (line fields, graph tensors)."""
+    scale, k, rp64 = wl["scale"], wl["k"], wl["rp64"]
+    t = time.perf_counter()
+    rp_t, col_t = sg.rmat_device(scale, EDGE_FACTOR, 0.57, 0.19, 0.19, seed=wl["seed"])
+    if not rp64:
+        rp_t = rp_t.to(torch.int32)
+    torch.cuda.synchronize()
+    n, nnz = rp_t.numel() - 1, col_t.numel()
+    dmax = int((rp_t[1:] - rp_t[:-1]).max().item())
+    print(f"[bench] rmat{scale} generated on the device: n={n} nnz={nnz} dmax={dmax} "
+          f"({time.perf_counter() - t:.1f}s)", flush=True)
+
+    tunings, forms = {}, {}
+    for precision in ("fp32", "fp64"):
+        if args.tuning == "auto":
+            tunings[precision] = katz.autotune(rp_t, col_t, k, eps=EPS, precision=precision)
+        else:
+            parts = [int(v) for v in args.tuning.split(":")]
+            katz.tuning_set(parts[0], parts[1], walk_groups=parts[2] if len(parts) > 2 else 0)
+            tunings[precision] = katz.tuning_get()
+        print(f"[bench] rmat{scale} {precision} tuning {tunings[precision]}", flush=True)
+        res, sec, tm = time_form(katz, torch, rp_t, col_t, k, precision, args.steps, args.warmup)
+        # Plain walk steps that did work: r - 2 per call (steps 3..r; step 2 is
+        # fused with the renumbering and timed on its own).  The host enqueues
+        # one more walk launch before it reads the stop flag; that launch
+        # returns at once and is not a walk step.
+        walk_avg_ms = tm["walk_step_ms"] / max(tm["calls"] * (res.iterations - 2), 1)
+        renum_avg_ms = tm["renumber_step_ms"] / max(tm["renumber_step_launches"], 1)
+        forms[precision] = dict(res=res, sec=sec, tm=tm, walk_avg_ms=walk_avg_ms, renum_avg_ms=renum_avg_ms,
+                                gteps=res.iterations * nnz / sec / 1e9)
+        print(f"[bench] rmat{scale} {precision}: r={res.iterations} status={res.status} {sec * 1e3:.3f} ms/step "
+              f"walk_step {walk_avg_ms * 1e3:.1f} us, renumbering step {renum_avg_ms * 1e3:.1f} us", flush=True)
+
+    # The same FP32 run without the internal renumbering, for context.
+    katz.tuning_set(**tunings["fp32"])
+    res_nr, sec_nr, tm_nr = time_form(katz, torch, rp_t, col_t, k, "fp32", max(1, args.steps // 5), 1,
+                                      flags=katz.FLAG_NO_REORDER)
+    print(f"[bench] rmat{scale} fp32 caller order: {sec_nr * 1e3:.3f} ms/step", flush=True)
+
+    f32, f64 = forms["fp32"], forms["fp64"]
+    bytes_step = algorithmic_bytes_per_walk_step(n, nnz, "fp32", rp64)
+    achieved = bytes_step / (f32["walk_avg_ms"] * 1e-3) / 1e9
+    tuning = {p: dict(t, arg=f"{t['hub_bytes']}:{t['blocks_per_cu']}:{t['walk_groups']}")
+              for p, t in tunings.items()}
+    traffic, traffic_note = measured_traffic(scale, tuning["fp32"]["arg"])
+    out = {
+        "value": round(f32["gteps"], 3),
+        "ms_per_step": round(f32["sec"] * 1e3, 4),
+        "config": {
+            "workload": wl["name"],
+            "graph": f"R-MAT scale {scale}, edge factor {EDGE_FACTOR}, (a,b,c,d)=(.57,.19,.19,.05), symmetrised, "
+                     f"deduplicated, no self-loops, seeded relabel, seed {wl['seed']}",
+            "n": n, "nnz_directed": nnz, "deg_max": dmax, "k": k, "eps": EPS,
+            "alpha": "1/(1+deg_max)", "row_ptr": "int64" if rp64 else "int32",
+            "form": "FP32 walk vector and row sums; FP64 c, bounds and rounding margin",
+        },
+        "iterations": f32["res"].iterations,
+        "status": f32["res"].status,
+        "fp64": {
+            "gteps": round(f64["gteps"], 3),
+            "ms_per_step": round(f64["sec"] * 1e3, 4),
+            "iterations": f64["res"].iterations,
+            "status": f64["res"].status,
+            "walk_step_avg_us": round(f64["walk_avg_ms"] * 1e3, 2),
+            "renumber_step_avg_us": round(f64["renum_avg_ms"] * 1e3, 2),
+            "walk_step_hbm_gbs": round(algorithmic_bytes_per_walk_step(n, nnz, "fp64", rp64)
+                                       / (f64["walk_avg_ms"] * 1e-3) / 1e9, 1),
+        },
+        "speedup_fp32_vs_fp64": round(f64["sec"] / f32["sec"], 3),
+        "walk_step_gteps_fp32": round(nnz / (f32["walk_avg_ms"] * 1e-3) / 1e9, 2),
+        "phase_ms_per_step_fp32": {
+            key: round(f32["tm"][key] / max(f32["tm"]["calls"], 1), 4)
+            for key in ("prep_ms", "walk_first_ms", "renumber_step_ms", "walk_step_ms", "select_ms", "result_ms",
+                        "call_ms")
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "walk_step_grouped<fp32>" if tunings["fp32"].get("walk_groups") == 4 else "walk_step<fp32>",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "traffic_note": traffic_note,
+            "bytes_per_launch": bytes_step,
+            "avg_launch_us": round(f32["walk_avg_ms"] * 1e3, 2),
+            "walk_steps_timed": f32["tm"]["calls"] * (f32["res"].iterations - 2),
+            "launches_timed": f32["tm"]["walk_step_launches"],
+            "renumber_step_avg_us": round(f32["renum_avg_ms"] * 1e3, 2),
+        },
+        "fp32_caller_order": {
+            "ms_per_step": round(sec_nr * 1e3, 4),
+            "walk_step_avg_us": round(tm_nr["walk_step_ms"] / max(tm_nr["calls"] * (res_nr.iterations - 1), 1)
+                                      * 1e3, 2),
+            "same_result": bool(torch.equal(res_nr.topk, f32["res"].topk)
+                                and torch.equal(res_nr.lower, f32["res"].lower)),
+        },
+        "fp32_fp64_same_topk": bool(torch.equal(f32["res"].topk, f64["res"].topk)),
+        "tuning": tuning,
+    }
+    return out, (rp_t, col_t, f32["res"], f64["res"], dmax)
+
+
+def oracle_leg(args, np, torch, rp_t, col_t, k, r32, r64, dmax):
+    """CPU baseline: the C++/OpenMP FP64 oracle's full certified run on every
+    host core (about ten seconds at R-MAT 27), which also checks the top-k of
+    both forms, plus a single-thread walk over a leading row range."""
+    from oracle import cpp as ocpp
+    t = time.perf_counter()
+    rp = rp_t.to(torch.int64).cpu().numpy()
+    col = col_t.cpu().numpy()
+    n, nnz = rp.size - 1, int(rp[-1])
+    print(f"[bench] graph copied to the host ({time.perf_counter() - t:.1f}s)", flush=True)
+    cores = ocpp.max_threads()
+    t = time.perf_counter()
+    orc = ocpp.rank_static(rp, col, None, k, EPS, full=False, threads=cores)
+    sec = time.perf_counter() - t
+    # One thread: the walk over a leading row range of about 1/32 of the arcs.
+    hi = int(np.searchsorted(rp, nnz // 32))
+    x = np.ones(n)
+    t = time.perf_counter()
+    ocpp.walk_rows(rp, col, 1.0 / (1 + dmax), 0, hi, x, threads=1)
+    sec_st = time.perf_counter() - t
+    del x
+    out = {"cpu_baseline": {
+        "value": round(orc.iterations * nnz / sec / 1e9, 5),
+        "unit": "GTEPS",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"one full certified run of the C++ FP64 oracle (Algorithm 1, top-{k}, eps={EPS}) on the whole "
+                  f"graph with {cores} OpenMP threads: {sec:.2f} s, r={orc.iterations}",
+        "cpu_model": cpu_model(),
+        "nproc": os.cpu_count(),
+        "single_thread_walk_gteps": round(int(rp[hi]) / sec_st / 1e9, 5),
+        "single_thread_sample": f"walk step of rows 0..{hi - 1} ({int(rp[hi])} arcs), one thread, {sec_st:.2f} s",
+    }}
+    ids32, ids64 = r32.topk.cpu().numpy(), r64.topk.cpu().numpy()
+    same32 = bool(np.array_equal(ids32, orc.topk))
+    out["topk_equal_oracle"] = {"fp32": same32, "fp64": bool(np.array_equal(ids64, orc.topk)),
+                                "oracle_iterations": orc.iterations, "oracle_status": orc.status}
+    if same32:
+        lo32 = r32.lower.cpu().numpy()
+        out["fp32_max_rel_err_vs_oracle"] = float(np.max(np.abs(lo32 - orc.lower) / orc.lower))
+    print(f"[bench] cpu baseline {out['cpu_baseline']} parity {out['topk_equal_oracle']}", flush=True)
+    return out
 
 
 def main():
@@ -87,9 +261,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
-    ap.add_argument("--workload", default="static", choices=["static", "batched", "serving"],
-                    help="static: R-MAT 22 (the headline line); batched: 256 Barabasi-Albert graphs; "
-                         "serving: update batches against R-MAT 24")
+    ap.add_argument("--workload", default="static", choices=["static", "static27", "static22", "batched", "serving"],
+                    help="static: R-MAT 27 (the headline line) with R-MAT 22 beside it; static27 / static22: "
+                         "one of them alone; batched: 256 Barabasi-Albert graphs; serving: update batches "
+                         "against R-MAT 24")
     ap.add_argument("--requests", type=int, default=200, help="serving: requests per load point")
     ap.add_argument("--graphs", type=int, default=256, help="batched: number of graphs")
     ap.add_argument("--serving-scale", type=int, default=24, help="serving: R-MAT scale of the resident graph")
@@ -98,7 +273,7 @@ def main():
                     help="walk launch shape: 'auto' (katz_autotune per precision before timing), "
                          "or HUB_BYTES:BLOCKS_PER_CU[:WALK_GROUPS] for both precisions")
     ap.add_argument("--tuning-sweep", action="store_true",
-                    help="static: also time every autotuner candidate (FP32) and report them")
+                    help="batched: also time every autotuner candidate and report them")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -125,150 +300,30 @@ def main():
         print(f"[bench] calibration copy: {args.copy_mib} MiB read + {args.copy_mib} MiB written", flush=True)
         del src, dst
 
-    t = time.perf_counter()
-    rp, col = sg.rmat(SCALE, EDGE_FACTOR, 0.57, 0.19, 0.19, seed=SEED)
-    n, nnz = len(rp) - 1, int(rp[-1])
-    dmax = int(np.max(np.diff(rp)))
-    print(f"[bench] graph generated: n={n} nnz={nnz} dmax={dmax} ({time.perf_counter() - t:.1f}s)", flush=True)
-    rp_t = torch.from_numpy(rp.astype(np.int32)).cuda()
-    col_t = torch.from_numpy(col).cuda()
-    torch.cuda.synchronize()
-
-    tunings = {}
-    forms = {}
-    for precision in ("fp32", "fp64"):
-        if args.tuning == "auto":
-            tunings[precision] = katz.autotune(rp_t, col_t, K, eps=EPS, precision=precision)
-        else:
-            parts = [int(v) for v in args.tuning.split(":")]
-            katz.tuning_set(parts[0], parts[1], walk_groups=parts[2] if len(parts) > 2 else 0)
-            tunings[precision] = katz.tuning_get()
-        print(f"[bench] {precision} tuning {tunings[precision]}", flush=True)
-        res, sec, tm = time_form(katz, torch, rp_t, col_t, precision, args.steps, args.warmup)
-        # Plain walk steps that did work: r - 2 per call (steps 3..r; step 2 is
-        # fused with the renumbering and timed on its own).  The host enqueues
-        # one more walk launch before it reads the stop flag; that launch
-        # returns at once and is not a walk step.
-        walk_avg_ms = tm["walk_step_ms"] / max(tm["calls"] * (res.iterations - 2), 1)
-        renum_avg_ms = tm["renumber_step_ms"] / max(tm["renumber_step_launches"], 1)
-        forms[precision] = dict(res=res, sec=sec, tm=tm, walk_avg_ms=walk_avg_ms, renum_avg_ms=renum_avg_ms,
-                                gteps=res.iterations * nnz / sec / 1e9)
-        print(f"[bench] {precision}: r={res.iterations} status={res.status} {sec * 1e3:.3f} ms/step "
-              f"walk_step {walk_avg_ms * 1e3:.1f} us, renumbering step {renum_avg_ms * 1e3:.1f} us", flush=True)
-
-    # The same FP32 run without the internal renumbering, for context.
-    katz.tuning_set(**tunings["fp32"])
-    res_nr, sec_nr, tm_nr = time_form(katz, torch, rp_t, col_t, "fp32", max(1, args.steps // 2), 1,
-                                      flags=katz.FLAG_NO_REORDER)
-    print(f"[bench] fp32 caller order: {sec_nr * 1e3:.3f} ms/step", flush=True)
-
-    f32, f64 = forms["fp32"], forms["fp64"]
-    bytes_step = algorithmic_bytes_per_walk_step(n, nnz, "fp32")
-    achieved = bytes_step / (f32["walk_avg_ms"] * 1e-3) / 1e9
-
+    head = WORKLOADS[22 if args.workload == "static22" else 27]
+    fields, (rp_t, col_t, r32, r64, dmax) = run_static(args, katz, sg, torch, np, head)
     out = {
         "metric": "certified top-k Katz ranking: GTEPS and % HBM peak, FP32-SpMV vs FP64, 1 GPU",
-        "value": round(f32["gteps"], 3),
+        "value": fields.pop("value"),
         "unit": "GTEPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(f32["sec"] * 1e3, 4),
+        "ms_per_step": fields.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": "rmat22_top1000_eps1e-6",
-            "graph": "R-MAT scale 22, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), symmetrised, "
-                     "deduplicated, no self-loops, seeded relabel, seed 1",
-            "n": n, "nnz_directed": nnz, "deg_max": dmax, "k": K, "eps": EPS,
-            "alpha": "1/(1+deg_max)", "row_ptr": "int32",
-            "form": "FP32 walk vector and row sums; FP64 c, bounds and rounding margin",
-        },
-        "iterations": f32["res"].iterations,
-        "status": f32["res"].status,
-        "fp64": {
-            "gteps": round(f64["gteps"], 3),
-            "ms_per_step": round(f64["sec"] * 1e3, 4),
-            "iterations": f64["res"].iterations,
-            "status": f64["res"].status,
-            "walk_step_avg_us": round(f64["walk_avg_ms"] * 1e3, 2),
-            "renumber_step_avg_us": round(f64["renum_avg_ms"] * 1e3, 2),
-            "walk_step_hbm_gbs": round(algorithmic_bytes_per_walk_step(n, nnz, "fp64")
-                                       / (f64["walk_avg_ms"] * 1e-3) / 1e9, 1),
-        },
-        "speedup_fp32_vs_fp64": round(f64["sec"] / f32["sec"], 3),
-        "phase_ms_per_step_fp32": {
-            key: round(f32["tm"][key] / max(f32["tm"]["calls"], 1), 4)
-            for key in ("prep_ms", "walk_first_ms", "renumber_step_ms", "walk_step_ms", "select_ms", "result_ms",
-                        "call_ms")
-        },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "walk_step_grouped<fp32>" if tunings["fp32"].get("walk_groups") == 4 else "walk_step<fp32>",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "bytes_per_launch": bytes_step,
-            "avg_launch_us": round(f32["walk_avg_ms"] * 1e3, 2),
-            "walk_steps_timed": f32["tm"]["calls"] * (f32["res"].iterations - 2),
-            "launches_timed": f32["tm"]["walk_step_launches"],
-            "renumber_step_avg_us": round(f32["renum_avg_ms"] * 1e3, 2),
-        },
     }
-
-    out["fp32_caller_order"] = {
-        "ms_per_step": round(sec_nr * 1e3, 4),
-        "walk_step_avg_us": round(tm_nr["walk_step_ms"] / max(tm_nr["calls"] * (res_nr.iterations - 1), 1) * 1e3, 2),
-        "same_result": bool(torch.equal(res_nr.topk, f32["res"].topk) and torch.equal(res_nr.lower, f32["res"].lower)),
-    }
-    same = bool(torch.equal(f32["res"].topk, f64["res"].topk))
-    out["fp32_fp64_same_topk"] = same
-    out["tuning"] = {p: dict(t, arg=f"{t['hub_bytes']}:{t['blocks_per_cu']}:{t['walk_groups']}")
-                     for p, t in tunings.items()}
-    out["roofline"]["traffic"], out["roofline"]["traffic_note"] = measured_traffic(out["tuning"]["fp32"]["arg"])
-    if args.tuning_sweep:
-        sweep = []
-        for hub, bpc, grp in [(0, 0, 0), (0, 4, 0), (0, 8, 0), (0, 16, 0), (16384, 4, 0), (24512, 6, 0),
-                              (32768, 4, 0), (40896, 4, 0), (65536, 2, 0), (65536, 1, 4), (98304, 1, 4),
-                              (131072, 1, 4), (159744, 1, 4)]:
-            katz.tuning_set(hub, bpc, walk_groups=grp)
-            r_s, sec_s, tm_s = time_form(katz, torch, rp_t, col_t, "fp32", max(1, args.steps // 2), 1)
-            walk_us = tm_s["walk_step_ms"] / max(tm_s["calls"] * (r_s.iterations - 2), 1) * 1e3
-            sweep.append({"hub_bytes": hub, "blocks_per_cu": bpc, "walk_groups": grp, "ms_per_step": round(sec_s * 1e3, 4),
-                          "walk_step_avg_us": round(walk_us, 2),
-                          "same_result": bool(torch.equal(r_s.topk, f32["res"].topk)
-                                              and torch.equal(r_s.lower, f32["res"].lower))})
-            print(f"[bench] sweep {hub}:{bpc}:{grp} {sec_s * 1e3:.3f} ms/step walk_step {walk_us:.1f} us", flush=True)
-        out["tuning_sweep_fp32"] = sweep
-        katz.tuning_set(**tunings["fp32"])
-
+    out.update(fields)
     if not args.no_cpu_baseline:
-        import oracle
-        t = time.perf_counter()
-        orc = oracle.rank_static(rp, col, None, K, EPS)
-        sec = time.perf_counter() - t
-        out["cpu_baseline"] = {
-            "value": round(orc.iterations * nnz / sec / 1e9, 5),
-            "unit": "GTEPS",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": "one full certified FP64 run of the same workload (numpy/scipy, single thread), "
-                      f"{sec:.1f} s, r={orc.iterations}",
-        }
-        g32 = f32["res"]
-        lo32 = g32.lower.cpu().numpy()
-        idx = g32.topk.cpu().numpy()
-        rel = np.abs(lo32 - orc.lower_all[idx]) / orc.lower_all[idx]
-        out["fp32_max_rel_err_vs_oracle"] = float(rel.max())
-        out["topk_equal_oracle"] = {
-            "fp32": bool(np.array_equal(idx, orc.topk)),
-            "fp64": bool(np.array_equal(f64["res"].topk.cpu().numpy(), orc.topk)),
-        }
+        out.update(oracle_leg(args, np, torch, rp_t, col_t, head["k"], r32, r64, dmax))
+    del rp_t, col_t, r32, r64
+    torch.cuda.empty_cache()
+    if args.workload == "static":
+        extra, _ = run_static(args, katz, sg, torch, np, WORKLOADS[22])
+        out["rmat22"] = extra
     print(json.dumps(out), flush=True)
 
 
@@ -339,15 +394,20 @@ def bench_batched(args, katz, sg, torch, np):
     print(json.dumps(out), flush=True)
 
 
-def serving_requests(rp, col, n, count, rng, np):
-    """Update batches of size round(10^U(0,4)): 70% insertions (R-MAT-distributed
-    endpoints, absent edges), 30% deletions of original edges (each at most once)."""
+def serving_requests(rp, col, n, count, rng, np, sg, scale, seed):
+    """Update batches of size round(10^U(0,4)): 70% insertions whose endpoints
+    are drawn from the graph's own R-MAT distribution (same quadrant recursion
+    and relabelling as the graph, a separate counter stream), rejecting
+    self-loops, existing edges and repeats; 30% deletions of original edges
+    (each at most once, uniform)."""
     src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
     keys = src * n + col
     und = np.nonzero(src < col)[0]
     order = rng.permutation(und.size)
     taken = 0
     inserted = set()
+    pool = np.empty((0, 2), dtype=np.int64)   # R-MAT endpoint pairs, drawn a million at a time
+    drawn = 0
     out = []
     for _ in range(count):
         size = max(1, int(round(10 ** rng.uniform(0, 4))))
@@ -358,9 +418,12 @@ def serving_requests(rp, col, n, count, rng, np):
         dels = np.stack([src[di], col[di].astype(np.int64)], 1)
         ins = []
         while len(ins) < n_ins:
-            a = rng.integers(0, n, 2 * (n_ins - len(ins)) + 8)
-            b = rng.integers(0, n, a.size)
-            lo, hi = np.minimum(a, b), np.maximum(a, b)
+            want = 2 * (n_ins - len(ins)) + 8
+            if pool.shape[0] < want:
+                pool = np.concatenate([pool, sg.rmat_pairs(scale, 1 << 20, seed=seed, stream=11, first=drawn)])
+                drawn += 1 << 20
+            pairs, pool = pool[:want], pool[want:]
+            lo, hi = np.minimum(pairs[:, 0], pairs[:, 1]), np.maximum(pairs[:, 0], pairs[:, 1])
             cand = lo * n + hi
             pos = np.searchsorted(keys, cand)
             present = (pos < keys.size) & (keys[np.minimum(pos, keys.size - 1)] == cand)
@@ -387,7 +450,7 @@ def bench_serving(args, katz, sg, torch, np):
     print(f"[bench] serving graph: n={n} nnz={int(rp[-1])} dmax={dmax} ({time.perf_counter() - t:.1f}s)", flush=True)
     rng = np.random.default_rng(24)
     total = args.requests * 3
-    reqs = serving_requests(rp, col, n, total, rng, np)
+    reqs = serving_requests(rp, col, n, total, rng, np, sg, args.serving_scale, 2)
     print(f"[bench] {total} requests generated, {sum(len(a) + len(b) for a, b in reqs)} edge updates", flush=True)
     sv = katz.Server(slots=4)
     gid, _ = sv.add_graph(torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda(), 100,

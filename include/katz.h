@@ -72,7 +72,14 @@ extern "C" {
                              /* rounding-error margin that widens both bounds in FP64    */
 
 /* ---- stopping criteria (Section 3.1) -------------------------------------- */
-#define KATZ_TOPK         0  /* the only criterion implemented; others -> E_UNSUPPORTED */
+#define KATZ_TOPK         0  /* the k nodes with the largest lower bounds are eps-     */
+                             /* separated from each other and from every other node  */
+#define KATZ_RANKING      1  /* every node eps-separated from every other: the top-k  */
+                             /* criterion with k = n (katz_params.k is ignored)       */
+#define KATZ_SCORE        2  /* every score known to within eps: u - l < eps for all  */
+                             /* nodes; the output lists all n nodes (k is ignored)    */
+#define KATZ_PAIR         3  /* the two nodes pair_u, pair_v are eps-separated; the   */
+                             /* output lists those two nodes (k is ignored)           */
 
 /* ---- CSR validation levels -------------------------------------------------- */
 #define KATZ_VALIDATE_NONE    0  /* trust the caller                                   */
@@ -114,20 +121,24 @@ typedef struct katz_params {
   double alpha;           /* attenuation, 0 < alpha < 1/deg_max (Theorem 1);        */
                           /* 0.0 selects 1/(1 + deg_max) (Section 3.1)              */
   double epsilon;         /* separation tolerance eps >= 0 (absolute); 0 = strict   */
-  int32_t k;              /* 1 <= k <= min(n, 4096)                                 */
+  int32_t k;              /* top-k: 1 <= k <= n (batches and states: k <= 4096)     */
   int32_t max_iter;       /* iteration cap; 0 selects 1000                          */
   int32_t precision;      /* KATZ_FP64 or KATZ_FP32_MARGIN                          */
-  int32_t criterion;      /* KATZ_TOPK                                              */
+  int32_t criterion;      /* KATZ_TOPK, KATZ_RANKING, KATZ_SCORE or KATZ_PAIR       */
   int32_t validate;       /* KATZ_VALIDATE_*; applies to the input CSR              */
   int32_t flags;          /* KATZ_FLAG_* bits; 0 = defaults                         */
   int64_t degree_cap;     /* states only: the largest deg_max that edge insertions  */
                           /* may create; 0 = the initial deg_max.  alpha must obey  */
                           /* alpha * degree_cap < 1.                                */
+  int32_t pair_u;         /* KATZ_PAIR: the two distinct node ids to separate;      */
+  int32_t pair_v;         /* ignored by the other criteria                          */
 } katz_params;
 
-/* Output of a ranking call.  topk_ids, lower, upper: caller-owned arrays of k
- * elements, host or device, written in ranking order (lower bound descending,
- * ties by ascending id).  The scalar fields are written by the library. */
+/* Output of a ranking call.  topk_ids, lower, upper: caller-owned arrays of
+ * k elements (KATZ_TOPK), n elements (KATZ_RANKING, KATZ_SCORE) or 2 elements
+ * (KATZ_PAIR), host or device, written in ranking order (lower bound
+ * descending, ties by ascending id).  The scalar fields are written by the
+ * library. */
 typedef struct katz_result {
   int32_t* topk_ids;       /* [k] node ids                                          */
   double* lower;           /* [k] l_r of each ranked node (FP32 form: widened)      */
@@ -139,6 +150,10 @@ typedef struct katz_result {
   int64_t active_final;    /* |M| when the run stopped (k once certified)           */
   int32_t iterations;      /* r                                                     */
   int32_t status;          /* same value as the return code                         */
+  double separated_fraction; /* KATZ_RANKING, KATZ_SCORE: fraction of the n(n-1)/2  */
+                           /* unordered node pairs {w, v} that the final bounds     */
+                           /* separate, l(w) > u(v) or l(v) > u(w) (the separation  */
+                           /* measure of Table 1); NaN for the other criteria       */
 } katz_result;
 
 /* Library-owned, device-resident state for dynamic updates: a copy of the graph
@@ -147,7 +162,8 @@ typedef struct katz_result {
 typedef struct katz_state katz_state;
 
 /*
- * katz_rank_static -- Algorithm 1 (Section 3.2) with the top-k criterion.
+ * katz_rank_static -- Algorithm 1 (Section 3.2) with a stopping criterion of
+ * Section 3.1 (katz_params.criterion).
  *
  * Ranks `count` independent graphs: g[i] with parameters p[i] into out[i].
  * count = 1 is the plain call; count > 1 runs all graphs together (one walk
@@ -155,11 +171,19 @@ typedef struct katz_state katz_state;
  * iterating, per-graph selection and separation test), each with its own alpha,
  * k and eps.
  *
+ * Criteria: KATZ_TOPK takes any 1 <= k <= n (past 4096 the top-k is sorted by
+ * a device-wide sort instead of one workgroup's LDS sort); KATZ_RANKING is the
+ * top-k test with k = n; KATZ_SCORE stops once u - l < eps for every node and
+ * then lists all n nodes; KATZ_PAIR stops once pair_u and pair_v are
+ * eps-separated.  Batches (count > 1) and states take KATZ_TOPK with
+ * k <= 4096 only.
+ *
  * states: NULL, or an array of `count` pointers that receives one new
  *         katz_state per graph for later katz_rank_update calls (FP64 only;
  *         free each with katz_state_free).
- * Errors: E_INVALID_ARG, E_ALPHA, E_CSR, E_UNSUPPORTED (criterion other than
- *         top-k, k > 4096, FP32 form with states), E_OOM, E_HIP.  With
+ * Errors: E_INVALID_ARG (also: pair ids out of range or equal), E_ALPHA,
+ *         E_CSR, E_UNSUPPORTED (a batch or a state with a criterion other than
+ *         top-k or k > 4096, FP32 form with states), E_OOM, E_HIP.  With
  *         count > 1 the first failing graph's error is returned and nothing is
  *         written for any graph.
  */

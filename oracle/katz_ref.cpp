@@ -108,6 +108,17 @@ bool converged(std::vector<int32_t>& M, const double* lo, const double* up, int6
   return true;
 }
 
+// The thread count of one call: set for the call, restored on return, so a
+// call with threads > 0 leaves later calls with threads <= 0 on OpenMP's
+// default.
+struct ThreadScope {
+  int saved;
+  explicit ThreadScope(int threads) : saved(omp_get_max_threads()) {
+    if (threads > 0) omp_set_num_threads(threads);
+  }
+  ~ThreadScope() { omp_set_num_threads(saved); }
+};
+
 }  // namespace
 
 extern "C" {
@@ -130,7 +141,7 @@ int ko_rank_static(int64_t n, const int64_t* row_ptr, const int32_t* col, double
                    int32_t undirected, int32_t max_iter, int32_t threads, int32_t* topk, double* lower,
                    double* upper, double* c_out, double* x_out, double* lower_all, double* upper_all,
                    ko_result* res) {
-  if (threads > 0) omp_set_num_threads(threads);
+  const ThreadScope scope(threads);
   if (n < 1 || k < 1 || k > n || !(eps >= 0.0) || max_iter < 1) return -1;
   const int64_t dmax = max_degree(n, row_ptr);
   if (alpha <= 0.0) alpha = 1.0 / (1.0 + (double)dmax);
@@ -194,7 +205,7 @@ int ko_rank_static(int64_t n, const int64_t* row_ptr, const int32_t* col, double
 // l_r and u_r of every node after exactly r iterations (no convergence test).
 int ko_bounds(int64_t n, const int64_t* row_ptr, const int32_t* col, double alpha, int32_t r, int32_t undirected,
               int32_t threads, double* lower, double* upper) {
-  if (threads > 0) omp_set_num_threads(threads);
+  const ThreadScope scope(threads);
   if (n < 1 || r < 1) return -1;
   const int64_t dmax = max_degree(n, row_ptr);
   if (alpha <= 0.0) alpha = 1.0 / (1.0 + (double)dmax);
@@ -219,7 +230,7 @@ int ko_bounds(int64_t n, const int64_t* row_ptr, const int32_t* col, double alph
 // sample of a graph too large for a full single-thread run.
 int ko_walk_rows(int64_t n, const int64_t* row_ptr, const int32_t* col, double alpha, int64_t lo, int64_t hi,
                  int32_t threads, const double* x_in, double* x_out) {
-  if (threads > 0) omp_set_num_threads(threads);
+  const ThreadScope scope(threads);
   if (lo < 0 || hi > n || lo > hi) return -1;
   walk(lo, hi, row_ptr, col, alpha, x_in, x_out, nullptr);
   return 0;

@@ -49,7 +49,7 @@ constexpr double kU32 = 0x1p-24;   // unit roundoff of FP32
 struct HostSync {
   RunScalars* sc = nullptr;        // final read-back
   RunScalars* ring = nullptr;      // 2 slots: per-pass copies of the flags
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};   // null: each pass synchronises the stream
   unsigned long long* bits = nullptr;   // 8 words of scalar read-backs
 
   int init() {
@@ -204,9 +204,9 @@ struct CallTimer {
   std::vector<hipEvent_t> ev;   // start, stop pairs
   hipEvent_t call0 = nullptr, call1 = nullptr;
 
-  CallTimer() {
+  explicit CallTimer(bool allow = true) {
     std::lock_guard<std::mutex> lk(g_timing.mu);
-    on = g_timing.on;
+    on = allow && g_timing.on;
   }
   ~CallTimer() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -295,12 +295,30 @@ int check_params(const katz_params* p, long long n, bool need_k) {
   if (p->degree_cap < 0) return KATZ_E_INVALID_ARG;
   if (std::isnan(p->alpha) || p->alpha < 0.0 || std::isinf(p->alpha)) return KATZ_E_ALPHA;
   if (need_k) {
-    if (p->criterion != KATZ_TOPK) return KATZ_E_UNSUPPORTED;
-    if (p->k < 1 || p->k > n) return KATZ_E_INVALID_ARG;
+    if (p->criterion < KATZ_TOPK || p->criterion > KATZ_PAIR) return KATZ_E_INVALID_ARG;
+    if (p->criterion == KATZ_TOPK && (p->k < 1 || p->k > n)) return KATZ_E_INVALID_ARG;
+    if (p->criterion == KATZ_PAIR &&
+        (p->pair_u < 0 || p->pair_u >= n || p->pair_v < 0 || p->pair_v >= n || p->pair_u == p->pair_v))
+      return KATZ_E_INVALID_ARG;
     if (!(p->epsilon >= 0.0) || std::isinf(p->epsilon)) return KATZ_E_INVALID_ARG;
-    if (p->k > kMaxK) return KATZ_E_UNSUPPORTED;
   }
   return KATZ_OK;
+}
+
+// Length of the ranked output list: k for top-k, every node for the ranking
+// and score criteria, the two nodes for the pair criterion.
+int output_len(const katz_params* p, long long n) {
+  switch (p->criterion) {
+    case KATZ_RANKING:
+    case KATZ_SCORE: return (int)n;
+    case KATZ_PAIR: return 2;
+    default: return p->k;
+  }
+}
+
+// Batched graphs and dynamic states select with one workgroup's LDS sort.
+int check_lds_criterion(const katz_params* p) {
+  return (p->criterion != KATZ_TOPK || p->k > kMaxK) ? KATZ_E_UNSUPPORTED : KATZ_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -360,6 +378,9 @@ struct Work {
   double* top_up = nullptr;
   uint8_t* mark = nullptr;
   unsigned long long* rest_bits = nullptr;
+  unsigned long long* sep_count = nullptr;   // separated pairs (ranking and score criteria)
+  unsigned long long* sort_key = nullptr;    // device-wide sort of the ranked list
+  int32_t* sort_ext = nullptr;
   RunScalars* sc = nullptr;
 };
 
@@ -527,7 +548,9 @@ struct Run {
   const int32_t* int_of = nullptr;
   Scalars* S = nullptr;
   double eps = 0;
-  int k = 1;
+  int criterion = KATZ_TOPK;
+  int pair_u = 0, pair_v = 0;  // caller ids (pair criterion)
+  int k = 1;                   // length of the ranked list
   int max_iter = 1000;
   int cur = 0;
   bool first_select = true;
@@ -683,7 +706,11 @@ int enqueue_walk(Run& run, int r, hipStream_t s, CallTimer& T) {
 // workgroup runs the whole of converged().
 int enqueue_select(Run& run, int r, hipStream_t s, CallTimer& T, bool small_m) {
   const int ts = T.start(T_SELECT, s);
-  if (small_m) {
+  if (run.criterion == KATZ_SCORE) {
+    KATZ_HIP(launch_score_check(sel_args(run, r), s));
+  } else if (run.criterion == KATZ_PAIR) {
+    KATZ_HIP(launch_pair_check(sel_args(run, r), run.pair_u, run.pair_v, s));
+  } else if (small_m && run.k <= kMaxK) {
     GraphSel gs{};
     gs.b = bound_args(run, r);
     gs.act[0] = run.w->act[0];
@@ -708,7 +735,9 @@ int enqueue_select(Run& run, int r, hipStream_t s, CallTimer& T, bool small_m) {
     KATZ_HIP(launch_select_wg_one(gs, s));
   } else {
     const SelArgs sa = sel_args(run, r);
-    KATZ_HIP(launch_select_iteration(sa, run.grid, s));
+    const bool large = run.k > kMaxK;
+    KATZ_HIP(launch_select_iteration(sa, run.grid, s, large ? run.w->sort_key : nullptr,
+                                     large ? run.w->sort_ext : nullptr));
   }
   T.stop(ts, s);
   run.cur ^= 1;
@@ -741,9 +770,10 @@ int iterate(Run& run, HostSync& hs, int r_next, bool check_first, hipStream_t s,
       break;
     }
     KATZ_HIP(hipMemcpyAsync(&hs.ring[pass & 1], run.w->sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
-    KATZ_HIP(hipEventRecord(hs.ev[pass & 1], s));
+    if (hs.ev[0]) KATZ_HIP(hipEventRecord(hs.ev[pass & 1], s));
     if (pass >= 1) {
-      KATZ_HIP(hipEventSynchronize(hs.ev[(pass - 1) & 1]));
+      if (hs.ev[0]) KATZ_HIP(hipEventSynchronize(hs.ev[(pass - 1) & 1]));
+      else KATZ_HIP(hipStreamSynchronize(s));
       const RunScalars& prev = hs.ring[(pass - 1) & 1];
       if (prev.err || prev.done) stopped = true;
       m_known = prev.m;
@@ -779,9 +809,19 @@ int write_result(Run& run, HostSync& hs, katz_result* out, int32_t* stage_ids, d
   double* up = direct ? out->upper : stage_up;
   if (!ids || !lo || !up) return KATZ_E_INVALID_ARG;
   const int tr = T.start(T_RESULT, s);
+  // Score criterion: the output is every node in ranking order.
+  if (run.criterion == KATZ_SCORE) KATZ_HIP(launch_score_output(fa, run.w->sort_key, run.w->sort_ext, s));
   KATZ_HIP(hipMemsetAsync(run.w->mark, 0, (size_t)run.n, s));
   KATZ_HIP(hipMemsetAsync(run.w->rest_bits, 0, sizeof(unsigned long long), s));
   KATZ_HIP(launch_write_result(fa, run.w->mark, ids, lo, up, run.w->rest_bits, run.grid, s));
+  // Ranking and score criteria: the sorted lower bounds of every node give the
+  // separated pairs.
+  const bool all_ranked = run.criterion == KATZ_RANKING || run.criterion == KATZ_SCORE;
+  if (all_ranked) {
+    KATZ_HIP(hipMemsetAsync(run.w->sep_count, 0, sizeof(unsigned long long), s));
+    KATZ_HIP(launch_separated_count(run.w->top_lo, run.w->top_up, run.n, run.w->sep_count, s));
+    KATZ_HIP(hipMemcpyAsync(hs.bits + 1, run.w->sep_count, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  }
   T.stop(tr, s);
   KATZ_HIP(hipMemcpyAsync(hs.bits, run.w->rest_bits, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   if (!direct) {
@@ -794,6 +834,9 @@ int write_result(Run& run, HostSync& hs, katz_result* out, int32_t* stage_ids, d
   double rest;
   std::memcpy(&rest, hs.bits, sizeof(double));
   out->rest_upper_max = (run.k == run.n) ? -std::numeric_limits<double>::infinity() : rest;
+  out->separated_fraction = std::numeric_limits<double>::quiet_NaN();
+  if (all_ranked)
+    out->separated_fraction = run.n < 2 ? 1.0 : (double)hs.bits[1] / ((double)run.n * (double)(run.n - 1) / 2.0);
   out->alpha_used = run.S->alpha;
   out->eta = run.fp32 ? run.S->eta[rf] : 0.0;
   out->active_final = m_final;
@@ -814,6 +857,7 @@ struct Plan {
   bool rp_host, col_host, out_host, select;
   bool reorder;   // renumber nodes by degree class (internal)
   size_t out_n;   // elements per output array (k for ranking, n for bounds)
+  size_t sort_n;  // records of the device-wide sort of the ranked list (0: none)
 };
 
 struct Staging {
@@ -891,6 +935,11 @@ void layout(Arena& ar, const Plan& pl, Bins& b, Work& w, Staging& stg) {
     w.top_up = ar.take<double>(pl.k);
     w.mark = ar.take<uint8_t>(n);
     w.rest_bits = ar.take<unsigned long long>(1);
+    w.sep_count = ar.take<unsigned long long>(1);
+    if (pl.sort_n) {
+      w.sort_key = ar.take<unsigned long long>(pl.sort_n);
+      w.sort_ext = ar.take<int32_t>(pl.sort_n);
+    }
   }
   if (pl.out_host) {
     stg.out_ids = ar.take<int32_t>(pl.out_n);
@@ -973,15 +1022,18 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
   return KATZ_OK;
 }
 
-int rank_one(const katz_csr* g, const katz_params* p, katz_result* out, hipStream_t s) {
+int check_rank_args(const katz_csr* g, const katz_params* p, const katz_result* out) {
   KATZ_TRY(check_graph(g));
   KATZ_TRY(check_params(p, g->n, true));
   if (!out || !out->topk_ids || !out->lower || !out->upper) return KATZ_E_INVALID_ARG;
-  int dev = 0;
-  KATZ_HIP(hipGetDevice(&dev));
-  ArenaLease lease(dev);
-  Arena& ar = *lease.a;
+  return KATZ_OK;
+}
 
+// One static ranking in the workspace of `ar` (grown as needed).
+// timing: whether the call may record the phase timers (events are created).
+int rank_in_arena(Arena& ar, const katz_csr* g, const katz_params* p, katz_result* out, hipStream_t s,
+                  bool timing) {
+  const int dev = ar.device;
   Plan pl{};
   pl.g = g;
   pl.fp32 = p->precision == KATZ_FP32_MARGIN;
@@ -993,13 +1045,16 @@ int rank_one(const katz_csr* g, const katz_params* p, katz_result* out, hipStrea
   pl.out_host = !(is_device_ptr(out->topk_ids) && is_device_ptr(out->lower) && is_device_ptr(out->upper));
   pl.select = true;
   pl.reorder = !(p->flags & KATZ_FLAG_NO_REORDER);
-  pl.out_n = (size_t)p->k;
+  const int klen = output_len(p, g->n);
+  pl.k = klen;
+  pl.out_n = (size_t)klen;
+  pl.sort_n = p->criterion == KATZ_SCORE ? (size_t)g->n : klen > kMaxK ? (size_t)klen : 0;
 
   Bins b;
   Work w;
   Staging stg;
   KATZ_TRY(plan_and_allocate(ar, pl, b, w, stg));
-  CallTimer T;
+  CallTimer T(timing);
   T.call_begin(s);
   const int tp = T.start(T_PREP, s);
   const int prc = prepare(ar.hs, pl, b, w, stg, s);
@@ -1034,12 +1089,23 @@ int rank_one(const katz_csr* g, const katz_params* p, katz_result* out, hipStrea
   run.w = &w;
   run.S = &S;
   run.eps = p->epsilon;
-  run.k = p->k;
+  run.criterion = p->criterion;
+  run.pair_u = p->pair_u;
+  run.pair_v = p->pair_v;
+  run.k = klen;
   run.max_iter = pl.max_iter;
   run.grid = (int)std::min<long long>((g->n + kWG - 1) / kWG, 2048);
   KATZ_TRY(iterate(run, ar.hs, 1, false, s, T));
   KATZ_TRY(check_columns_if_unread(pl, stg, w, ar.hs, s));
   return write_result(run, ar.hs, out, stg.out_ids, stg.out_lo, stg.out_up, s, T);
+}
+
+int rank_one(const katz_csr* g, const katz_params* p, katz_result* out, hipStream_t s) {
+  KATZ_TRY(check_rank_args(g, p, out));
+  int dev = 0;
+  KATZ_HIP(hipGetDevice(&dev));
+  ArenaLease lease(dev);
+  return rank_in_arena(*lease.a, g, p, out, s, true);
 }
 
 int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lower, double* upper,
@@ -2146,6 +2212,7 @@ int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, lon
 // ---------------------------------------------------------------------------
 // C ABI.
 // ---------------------------------------------------------------------------
+
 KATZ_EXPORT int katz_rank_static(int32_t count, const katz_csr* g, const katz_params* p, katz_result* out,
                                  katz_state** states, void* stream) {
   if (count < 1 || !g || !p || !out) return KATZ_E_INVALID_ARG;
@@ -2154,6 +2221,7 @@ KATZ_EXPORT int katz_rank_static(int32_t count, const katz_csr* g, const katz_pa
     if (!rc) rc = katz::check_params(&p[i], g[i].n, true);
     if (!rc && (!out[i].topk_ids || !out[i].lower || !out[i].upper)) rc = KATZ_E_INVALID_ARG;
     if (!rc && states && (p[i].precision != KATZ_FP64 || !g[i].undirected)) rc = KATZ_E_UNSUPPORTED;
+    if (!rc && (states || count > 1)) rc = katz::check_lds_criterion(&p[i]);
     if (rc) return rc;
   }
   if (count > 1 && !states) return katz::rank_batch(count, g, p, out, (hipStream_t)stream);
@@ -2227,7 +2295,7 @@ KATZ_EXPORT int katz_autotune(int32_t count, const katz_csr* g, const katz_param
   for (int32_t i = 0; i < count; ++i) {
     KATZ_TRY(katz::check_graph(&g[i]));
     KATZ_TRY(katz::check_params(&p[i], g[i].n, true));
-    sum_k += p[i].k;
+    sum_k += katz::output_len(&p[i], g[i].n);
   }
   // {hub_bytes, blocks_per_cu, walk_groups}: hub copies sized so that 3..8
   // workgroups fill the 160 KiB of LDS of a CU (with the kernel's own few bytes
@@ -2275,7 +2343,7 @@ KATZ_EXPORT int katz_autotune(int32_t count, const katz_csr* g, const katz_param
     out[i].topk_ids = ids + koff;
     out[i].lower = lo + koff;
     out[i].upper = up + koff;
-    koff += p[i].k;
+    koff += katz::output_len(&p[i], g[i].n);
   }
   katz_tuning pick = saved;
   double pick_ms = 1e300;

@@ -295,7 +295,19 @@ hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks,
 hipError_t launch_reduce_blkmax(const void* blkmax, long long nb, int fp32, unsigned* xmax32,
                                 unsigned long long* xmax64, int r, const RunScalars* sc, hipStream_t s);
 hipError_t launch_check_col_range(const int32_t* col, long long nnz, long long n, RunScalars* sc, hipStream_t s);
-hipError_t launch_select_iteration(const SelArgs& a, int grid, hipStream_t s);
+// sort_key / sort_ext (k elements each): when set, the top-k is sorted and
+// tested device-wide (launch_large_check) instead of in one workgroup's LDS.
+hipError_t launch_select_iteration(const SelArgs& a, int grid, hipStream_t s,
+                                   unsigned long long* sort_key = nullptr, int32_t* sort_ext = nullptr);
+
+// ---- stopping criteria beyond the LDS top-k test (katz_criteria.hip) ------------
+hipError_t launch_large_check(const SelArgs& a, unsigned long long* key, int32_t* ext, hipStream_t s);
+hipError_t launch_score_check(const SelArgs& a, hipStream_t s);
+// Every node (identity list) sorted into top_sorted / top_lo / top_up.
+hipError_t launch_score_output(const SelArgs& a, unsigned long long* key, int32_t* ext, hipStream_t s);
+hipError_t launch_pair_check(const SelArgs& a, int ext_a, int ext_b, hipStream_t s);
+hipError_t launch_separated_count(const double* lo_desc, const double* up, long long n, unsigned long long* count,
+                                  hipStream_t s);
 hipError_t launch_write_result(const SelArgs& a, uint8_t* mark, int32_t* out_ids, double* out_lo,
                                double* out_up, unsigned long long* rest_bits, int grid, hipStream_t s);
 hipError_t launch_all_bounds(const BoundArgs& b, int64_t n, const int32_t* ext_of,

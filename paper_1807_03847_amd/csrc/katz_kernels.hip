@@ -1302,7 +1302,8 @@ hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks,
   return hipGetLastError();
 }
 
-hipError_t launch_select_iteration(const SelArgs& a, int grid, hipStream_t s) {
+hipError_t launch_select_iteration(const SelArgs& a, int grid, hipStream_t s, unsigned long long* sort_key,
+                                   int32_t* sort_ext) {
   hipLaunchKernelGGL(sel_hist0, dim3(grid), dim3(kWG), 0, s, a);
   hipLaunchKernelGGL(sel_scan, dim3(1), dim3(kFinishThreads), 0, s, a, 0);
   hipLaunchKernelGGL(sel_compact, dim3(grid), dim3(kWG), 0, s, a, 0);
@@ -1311,6 +1312,7 @@ hipError_t launch_select_iteration(const SelArgs& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL(sel_compact, dim3(grid), dim3(kWG), 0, s, a, 1);
   hipLaunchKernelGGL(sel_finish, dim3(1), dim3(kFinishThreads), 0, s, a);
   hipLaunchKernelGGL(sel_apply, dim3(grid), dim3(kWG), 0, s, a);
+  if (sort_key) return launch_large_check(a, sort_key, sort_ext, s);
   hipLaunchKernelGGL(sel_check, dim3(1), dim3(kFinishThreads), 0, s, a);
   return hipGetLastError();
 }

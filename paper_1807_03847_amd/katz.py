@@ -31,7 +31,8 @@ E_UNSUPPORTED = -8
 
 FP64 = 0
 FP32_MARGIN = 1
-TOPK = 0
+TOPK, RANKING, SCORE, PAIR = 0, 1, 2, 3
+CRITERIA = {"topk": TOPK, "ranking": RANKING, "score": SCORE, "pair": PAIR}
 VALIDATE_NONE, VALIDATE_BASIC, VALIDATE_STRICT = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32_MARGIN}
 
@@ -44,14 +45,16 @@ class KatzCSR(ctypes.Structure):
 class KatzParams(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("epsilon", ctypes.c_double), ("k", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32), ("criterion", ctypes.c_int32),
-                ("validate", ctypes.c_int32), ("flags", ctypes.c_int32), ("degree_cap", ctypes.c_int64)]
+                ("validate", ctypes.c_int32), ("flags", ctypes.c_int32), ("degree_cap", ctypes.c_int64),
+                ("pair_u", ctypes.c_int32), ("pair_v", ctypes.c_int32)]
 
 
 class KatzResult(ctypes.Structure):
     _fields_ = [("topk_ids", ctypes.c_void_p), ("lower", ctypes.c_void_p), ("upper", ctypes.c_void_p),
                 ("rest_upper_max", ctypes.c_double), ("alpha_used", ctypes.c_double),
                 ("eta", ctypes.c_double), ("active_final", ctypes.c_int64),
-                ("iterations", ctypes.c_int32), ("status", ctypes.c_int32)]
+                ("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("separated_fraction", ctypes.c_double)]
 
 
 class KatzTuning(ctypes.Structure):
@@ -135,6 +138,7 @@ class RankResult:
     alpha: float
     eta: float
     active_final: int
+    separated_fraction: float = math.nan   # ranking and score criteria only
 
 
 def _ptr(t):
@@ -163,10 +167,12 @@ FLAG_REORDER = 2
 
 
 def make_params(k=1, alpha=0.0, eps=0.0, precision="fp64", max_iter=0, validate=VALIDATE_BASIC,
-                degree_cap=0, flags=0) -> KatzParams:
+                degree_cap=0, flags=0, criterion="topk", pair=(0, 0)) -> KatzParams:
     return KatzParams(alpha=float(alpha), epsilon=float(eps), k=int(k), max_iter=int(max_iter),
                       precision=PRECISIONS[precision] if isinstance(precision, str) else int(precision),
-                      criterion=TOPK, validate=int(validate), flags=int(flags), degree_cap=int(degree_cap))
+                      criterion=CRITERIA[criterion] if isinstance(criterion, str) else int(criterion),
+                      validate=int(validate), flags=int(flags), degree_cap=int(degree_cap),
+                      pair_u=int(pair[0]), pair_v=int(pair[1]))
 
 
 def _alloc_outputs(k, device):
@@ -178,18 +184,22 @@ def _alloc_outputs(k, device):
 def _to_result(res: KatzResult, ids, lo, up) -> RankResult:
     return RankResult(topk=ids, lower=lo, upper=up, iterations=res.iterations, status=res.status,
                       rest_upper_max=res.rest_upper_max, alpha=res.alpha_used, eta=res.eta,
-                      active_final=res.active_final)
+                      active_final=res.active_final, separated_fraction=res.separated_fraction)
 
 
 def rank_static(row_ptr, col, k, *, alpha=0.0, eps=0.0, precision="fp64", undirected=True, max_iter=0,
-                validate=VALIDATE_BASIC, flags=0, stream=None, out=None) -> RankResult:
-    """katz_rank_static for one graph (Algorithm 1, top-k criterion).
+                validate=VALIDATE_BASIC, flags=0, stream=None, out=None, criterion="topk",
+                pair=(0, 0)) -> RankResult:
+    """katz_rank_static for one graph (Algorithm 1) with a stopping criterion
+    of Section 3.1: "topk" (k nodes), "ranking" and "score" (every node; k is
+    ignored) or "pair" (the two nodes of ``pair``; k is ignored).
 
-    ``out`` may pass preallocated (ids, lower, upper) tensors of length k."""
+    ``out`` may pass preallocated (ids, lower, upper) tensors of the output length."""
     device = row_ptr.device
     g = make_csr(row_ptr, col, undirected)
-    p = make_params(k, alpha, eps, precision, max_iter, validate, 0, flags)
-    ids, lo, up = out if out is not None else _alloc_outputs(k, device)
+    p = make_params(k, alpha, eps, precision, max_iter, validate, 0, flags, criterion, pair)
+    length = {TOPK: p.k, RANKING: g.n, SCORE: g.n, PAIR: 2}.get(p.criterion, p.k)
+    ids, lo, up = out if out is not None else _alloc_outputs(max(length, 0), device)
     res = KatzResult(topk_ids=ids.data_ptr(), lower=lo.data_ptr(), upper=up.data_ptr())
     rc = lib.katz_rank_static(1, ctypes.byref(g), ctypes.byref(p), ctypes.byref(res), None,
                               _stream_handle(stream, device))
@@ -416,10 +426,6 @@ def timing_read() -> dict:
     t = KatzTiming()
     lib.katz_timing_read(ctypes.byref(t))
     return {name: getattr(t, name) for name, _ in KatzTiming._fields_}
-
-
-def default_alpha(dmax: int) -> float:
-    return 1.0 / (1.0 + dmax)
 
 
 NEG_INF = -math.inf

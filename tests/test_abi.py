@@ -43,7 +43,9 @@ int main(void) {
          sizeof(katz_params), sizeof(katz_result), sizeof(katz_tuning), sizeof(katz_timing));
   F(katz_csr, col) F(katz_csr, row_ptr_64) F(katz_csr, undirected)
   F(katz_params, k) F(katz_params, precision) F(katz_params, validate) F(katz_params, flags) F(katz_params, degree_cap)
+  F(katz_params, criterion) F(katz_params, pair_u) F(katz_params, pair_v)
   F(katz_result, rest_upper_max) F(katz_result, active_final) F(katz_result, iterations) F(katz_result, status)
+  F(katz_result, separated_fraction)
   F(katz_tuning, blocks_per_cu) F(katz_tuning, batch_blocks_per_cu) F(katz_tuning, batch_tile)
   F(katz_tuning, batch_xcd) F(katz_tuning, walk_groups) F(katz_tuning, reserved)
   F(katz_timing, prep_ms) F(katz_timing, calls) F(katz_timing, renumber_step_ms) F(katz_timing, renumber_step_launches)
@@ -103,8 +105,18 @@ def test_argument_errors_before_device_work():
     assert _call(g, katz.make_params(1, eps=-1.0), res) == katz.E_INVALID_ARG
     assert _call(g, katz.make_params(1, precision=7), res) == katz.E_INVALID_ARG
     p = katz.make_params(1)
-    p.criterion = 1
-    assert _call(g, p, res) == katz.E_UNSUPPORTED
+    p.criterion = 9                                                      # unknown criterion
+    assert _call(g, p, res) == katz.E_INVALID_ARG
+    for pair in [(1, 1), (-1, 0), (0, 3), (3, 0)]:                      # equal or out-of-range pair ids
+        assert _call(g, katz.make_params(1, criterion="pair", pair=pair), res) == katz.E_INVALID_ARG
+    # Batches and states take the top-k criterion with k <= 4096 only.
+    g2 = (katz.KatzCSR * 2)(g, g)
+    p2 = (katz.KatzParams * 2)(katz.make_params(1, criterion="ranking"), katz.make_params(1, criterion="ranking"))
+    r2 = (katz.KatzResult * 2)(res, res)
+    assert katz.lib.katz_rank_static(2, g2, p2, r2, None, None) == katz.E_UNSUPPORTED
+    st = (ctypes.c_void_p * 1)()
+    assert katz.lib.katz_rank_static(1, ctypes.byref(g), ctypes.byref(katz.make_params(1, criterion="score")),
+                                     ctypes.byref(res), st, None) == katz.E_UNSUPPORTED
     p = katz.make_params(1)
     p.flags = 1 << 7                                                     # unknown flag bit
     assert _call(g, p, res) == katz.E_INVALID_ARG

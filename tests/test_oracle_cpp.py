@@ -156,3 +156,15 @@ def test_walk_rows_is_one_iteration_of_the_walk():
     _, x2 = oracle.walk_state(rp, col, alpha, 2)
     assert np.array_equal(cpp.walk_rows(rp, col, alpha, 0, n, np.ones(n), threads=1), x1)
     assert np.array_equal(cpp.walk_rows(rp, col, alpha, 100, 900, x1, threads=4), x2[100:900])
+
+
+def test_thread_count_of_one_call_does_not_stick():
+    """A call with threads > 0 uses that many threads for itself only: a later
+    call with threads = 0 runs on OpenMP's default again."""
+    from oracle import cpp as ocpp
+    before = ocpp.max_threads()
+    rp, col = sg.erdos_renyi(2000, 8000, 3)
+    ocpp.walk_rows(rp, col, 0.01, 0, 100, np.ones(2000), threads=1)
+    ocpp.rank_static(rp, col, None, 5, 0.0, threads=1)
+    ocpp.bounds(rp, col, None, 2, threads=1)
+    assert ocpp.max_threads() == before
