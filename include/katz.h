@@ -65,6 +65,8 @@ extern "C" {
 #define KATZ_E_OOM              -6  /* device allocation failed                        */
 #define KATZ_E_HIP              -7  /* a HIP runtime call failed                       */
 #define KATZ_E_UNSUPPORTED      -8  /* valid request outside what this build supports  */
+#define KATZ_E_SCRATCH          -9  /* katz_rank_static_noalloc: the problem needs more */
+                                    /* workspace than the fixed scratch array holds     */
 
 /* ---- precision forms ------------------------------------------------------ */
 #define KATZ_FP64         0  /* walk vector, sums and bounds in FP64 (the plain method)  */
@@ -218,6 +220,31 @@ int katz_rank_update(katz_state* st, const int32_t* ins_u, const int32_t* ins_v,
  */
 int katz_bounds(const katz_csr* g, const katz_params* p, int32_t r,
                 double* lower, double* upper, void* stream);
+
+/*
+ * katz_rank_static_noalloc -- katz_rank_static for one graph (count = 1, no
+ * states), for callers that cannot allocate memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  It calls no
+ * hipMalloc, hipHostMalloc, hipFree or hipHostFree: its workspace is a static
+ * device array of 64 MiB that every device using the library holds until the
+ * process ends, and its flag read-backs go to static host memory (so the host
+ * waits for each iteration instead of reading the stop flag one iteration
+ * behind).  The first call on a device looks up that device's copy of the
+ * array (hipGetSymbolAddress).  The phase timers (katz_timing_*) are not
+ * recorded.
+ *
+ * Arguments, outputs and results are those of katz_rank_static with
+ * count = 1 and states = NULL; the results are bitwise the same.  A graph
+ * whose workspace (about 140 bytes per node plus 4 bytes per arc, more for
+ * host inputs or outputs) exceeds the array returns E_SCRATCH before any
+ * device work.  Every call on a device shares that device's array, and it
+ * keeps the last call's contents: calls that overlap on one device (from
+ * several host threads or on several streams) race and must be serialised
+ * by the caller.
+ * Errors: those of katz_rank_static, and E_SCRATCH.
+ */
+int katz_rank_static_noalloc(const katz_csr* g, const katz_params* p,
+                             katz_result* out, void* stream);
 
 /* Frees a state from katz_rank_static (NULL is ignored). */
 void katz_state_free(katz_state* st);

@@ -51,6 +51,7 @@ struct HostSync {
   RunScalars* ring = nullptr;      // 2 slots: per-pass copies of the flags
   hipEvent_t ev[2] = {nullptr, nullptr};   // null: each pass synchronises the stream
   unsigned long long* bits = nullptr;   // 8 words of scalar read-backs
+  bool borrowed = false;           // the mirrors are static host memory, not owned
 
   int init() {
     if (sc) return KATZ_OK;
@@ -62,6 +63,7 @@ struct HostSync {
     return KATZ_OK;
   }
   ~HostSync() {
+    if (borrowed) return;
     if (sc) (void)hipHostFree(sc);
     if (ring) (void)hipHostFree(ring);
     if (bits) (void)hipHostFree(bits);
@@ -79,10 +81,11 @@ struct Arena {
   size_t cap = 0;
   size_t used = 0;
   bool measuring = false;
+  bool fixed = false;   // base is the library's static scratch: never grown or freed
   HostSync hs;
 
   ~Arena() {
-    if (base) (void)hipFree(base);
+    if (base && !fixed) (void)hipFree(base);
   }
   template <class T>
   T* take(size_t count) {
@@ -94,6 +97,7 @@ struct Arena {
   int grow(size_t bytes) {
     KATZ_TRY(hs.init());
     if (bytes <= cap) return KATZ_OK;
+    if (fixed) return KATZ_E_SCRATCH;
     if (base) (void)hipFree(base);
     base = nullptr;
     cap = 0;
@@ -1029,7 +1033,7 @@ int check_rank_args(const katz_csr* g, const katz_params* p, const katz_result* 
   return KATZ_OK;
 }
 
-// One static ranking in the workspace of `ar` (grown as needed).
+// One static ranking in the workspace of `ar` (grown as needed unless fixed).
 // timing: whether the call may record the phase timers (events are created).
 int rank_in_arena(Arena& ar, const katz_csr* g, const katz_params* p, katz_result* out, hipStream_t s,
                   bool timing) {
@@ -2210,8 +2214,74 @@ int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, lon
 }  // namespace katz
 
 // ---------------------------------------------------------------------------
+// Allocation-free ranking: the workspace is a static device array of fixed
+// size (each device that loads the library holds its own copy until the
+// process ends), and the flag read-backs go to static host memory.
+// ---------------------------------------------------------------------------
+namespace katz {
+namespace {
+
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+
+// Device-side only: host code reaches it through the address that
+// hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+struct ScratchSlot {
+  std::once_flag once;
+  int rc = KATZ_E_HIP;
+  unsigned char* ptr = nullptr;   // device address of `scratch` on this device
+  RunScalars sc;                  // static host mirrors of the flags
+  RunScalars ring[2];
+  unsigned long long bits[8];
+};
+ScratchSlot g_scratch[kMaxDevices];
+
+// Set-up, once per device with that device current: look up the address of
+// the device's copy of the scratch array.
+ScratchSlot* scratch_slot(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  ScratchSlot& sl = g_scratch[dev];
+  std::call_once(sl.once, [&sl] {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p) {
+      sl.ptr = static_cast<unsigned char*>(p);
+      sl.rc = KATZ_OK;
+    } else {
+      (void)hipGetLastError();
+    }
+  });
+  return sl.rc == KATZ_OK ? &sl : nullptr;
+}
+
+int rank_noalloc(const katz_csr* g, const katz_params* p, katz_result* out, hipStream_t s) {
+  KATZ_TRY(check_rank_args(g, p, out));
+  int dev = 0;
+  KATZ_HIP(hipGetDevice(&dev));
+  ScratchSlot* sl = scratch_slot(dev);
+  if (!sl) return KATZ_E_HIP;
+  Arena ar;
+  ar.device = dev;
+  ar.base = reinterpret_cast<char*>(sl->ptr);
+  ar.cap = kScratchBytes;
+  ar.fixed = true;
+  ar.hs.borrowed = true;
+  ar.hs.sc = &sl->sc;
+  ar.hs.ring = sl->ring;
+  ar.hs.bits = sl->bits;
+  return rank_in_arena(ar, g, p, out, s, false);
+}
+
+}  // namespace
+}  // namespace katz
+
+// ---------------------------------------------------------------------------
 // C ABI.
 // ---------------------------------------------------------------------------
+KATZ_EXPORT int katz_rank_static_noalloc(const katz_csr* g, const katz_params* p, katz_result* out, void* stream) {
+  return katz::rank_noalloc(g, p, out, (hipStream_t)stream);
+}
 
 KATZ_EXPORT int katz_rank_static(int32_t count, const katz_csr* g, const katz_params* p, katz_result* out,
                                  katz_state** states, void* stream) {
@@ -2388,6 +2458,7 @@ KATZ_EXPORT const char* katz_strerror(int code) {
     case KATZ_E_OOM: return "error: device memory allocation failed";
     case KATZ_E_HIP: return "error: HIP runtime failure";
     case KATZ_E_UNSUPPORTED: return "error: unsupported request";
+    case KATZ_E_SCRATCH: return "error: the problem needs more workspace than the fixed scratch array holds";
     default: return "unknown status code";
   }
 }

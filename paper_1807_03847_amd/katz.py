@@ -28,6 +28,7 @@ E_DEGREE_CAP = -5
 E_OOM = -6
 E_HIP = -7
 E_UNSUPPORTED = -8
+E_SCRATCH = -9
 
 FP64 = 0
 FP32_MARGIN = 1
@@ -80,6 +81,9 @@ def _load():
     lib.katz_rank_static.restype = ctypes.c_int
     lib.katz_rank_static.argtypes = [i32, ctypes.POINTER(KatzCSR), ctypes.POINTER(KatzParams),
                                      ctypes.POINTER(KatzResult), ctypes.POINTER(vp), vp]
+    lib.katz_rank_static_noalloc.restype = ctypes.c_int
+    lib.katz_rank_static_noalloc.argtypes = [ctypes.POINTER(KatzCSR), ctypes.POINTER(KatzParams),
+                                             ctypes.POINTER(KatzResult), vp]
     lib.katz_rank_update.restype = ctypes.c_int
     lib.katz_rank_update.argtypes = [vp, vp, vp, i64, vp, vp, i64, ctypes.POINTER(KatzResult), vp]
     lib.katz_bounds.restype = ctypes.c_int
@@ -203,6 +207,25 @@ def rank_static(row_ptr, col, k, *, alpha=0.0, eps=0.0, precision="fp64", undire
     res = KatzResult(topk_ids=ids.data_ptr(), lower=lo.data_ptr(), upper=up.data_ptr())
     rc = lib.katz_rank_static(1, ctypes.byref(g), ctypes.byref(p), ctypes.byref(res), None,
                               _stream_handle(stream, device))
+    if rc < 0:
+        raise KatzError(rc)
+    return _to_result(res, ids, lo, up)
+
+
+def rank_static_noalloc(row_ptr, col, k, *, alpha=0.0, eps=0.0, precision="fp64", undirected=True, max_iter=0,
+                        validate=VALIDATE_BASIC, flags=0, stream=None, out=None, criterion="topk",
+                        pair=(0, 0)) -> RankResult:
+    """katz_rank_static_noalloc: rank_static in the library's fixed scratch
+    array, without any allocation by the library.  Pass ``out`` to avoid the
+    output allocation here as well."""
+    device = row_ptr.device
+    g = make_csr(row_ptr, col, undirected)
+    p = make_params(k, alpha, eps, precision, max_iter, validate, 0, flags, criterion, pair)
+    length = {TOPK: p.k, RANKING: g.n, SCORE: g.n, PAIR: 2}.get(p.criterion, p.k)
+    ids, lo, up = out if out is not None else _alloc_outputs(max(length, 0), device)
+    res = KatzResult(topk_ids=ids.data_ptr(), lower=lo.data_ptr(), upper=up.data_ptr())
+    rc = lib.katz_rank_static_noalloc(ctypes.byref(g), ctypes.byref(p), ctypes.byref(res),
+                                      _stream_handle(stream, device))
     if rc < 0:
         raise KatzError(rc)
     return _to_result(res, ids, lo, up)

@@ -75,7 +75,7 @@ int main(void) {
 
 def test_strerror_covers_codes():
     katz = K()
-    for code in range(-8, 4):
+    for code in range(-9, 4):
         assert "unknown" not in katz.strerror(code)
     assert "unknown" in katz.strerror(99)
 
