@@ -11,7 +11,9 @@ Katz arithmetic.
 Modules:
   ``katz``    plain, slow, sequential FP64 implementation of the static bound
               iteration (Section 3, Algorithm 1) and of the dynamic update
-              (Section 4, Algorithm 2) in its delta form.
+              (Section 4, Algorithm 2) in its delta form, and the paper's two
+              comparison methods (Foster's heuristic, conjugate gradients on
+              Eq. (la)).
   ``cpp``     the static part of ``katz`` in C++ with OpenMP (``katz_ref.cpp``),
               bit for bit the same results at any thread count, for graphs the
               numpy form cannot hold (R-MAT scale 27) and for the CPU baseline.
@@ -25,4 +27,4 @@ Every function is pinned by tests under ``tests/`` (``-m "not gpu"``); none is
 """
 from .katz import (OK, W_ITER_LIMIT, W_PRECISION_LIMIT, W_EXACT_TIES,  # noqa: F401
                    OracleResult, rank_static, bounds, walk_state, DynamicOracle,
-                   UpdateRejected)
+                   UpdateRejected, foster, conjugate_gradient, SolveResult)

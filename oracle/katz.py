@@ -287,6 +287,78 @@ def bounds(row_ptr, col, alpha=None, r=1, undirected=True):
 # Dynamic graphs: Algorithm 2 (Section 4) in its delta form.
 # ---------------------------------------------------------------------------
 
+# ---------------------------------------------------------------------------
+# The comparison methods of the paper (Sections 2.2 and 5).
+# ---------------------------------------------------------------------------
+
+@dataclass
+class SolveResult:
+    scores: np.ndarray      # Katz score of every node
+    iterations: int         # matrix-vector products of the iteration
+    converged: bool
+    residual: float         # the last tested quantity
+    alpha: float
+
+
+def foster(row_ptr, col, alpha=None, tol=1e-9, max_iter=1000):
+    """Foster's heuristic (Section 2.2): f_0 = 1, f_{i+1} = alpha A f_i + 1,
+    iterated until the largest change of an entry, max |f_{i+1} - f_i|, is
+    below ``tol`` (the reading of its error tolerance taken here) or max_iter
+    steps; the Katz vector is f - 1."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    n = len(row_ptr) - 1
+    dmax = max_degree(row_ptr)
+    alpha = default_alpha(dmax) if alpha is None else float(alpha)
+    check_alpha(alpha, dmax)
+    A = adjacency(row_ptr, col, n)
+    f = np.ones(n)
+    it, change, conv = 0, float("inf"), False
+    while it < max_iter:
+        f_new = alpha * (A @ f) + 1.0
+        it += 1
+        change = float(np.max(np.abs(f_new - f))) if n else 0.0
+        f = f_new
+        if change < tol:
+            conv = True
+            break
+    return SolveResult(scores=f - 1.0, iterations=it, converged=conv, residual=change, alpha=alpha)
+
+
+def conjugate_gradient(row_ptr, col, alpha=None, tol=1e-15, max_iter=1000):
+    """Conjugate gradients without preconditioning on Eq. (la),
+    (I - alpha A) z = 1, from z = 0 (the textbook iteration of Hestenes and
+    Stiefel), until the relative residual ||1 - (I - alpha A) z||_2 / ||1||_2
+    is below ``tol`` or max_iter steps; the Katz vector is alpha A z
+    (Section 1).  The matrix must be symmetric (undirected graph)."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    n = len(row_ptr) - 1
+    dmax = max_degree(row_ptr)
+    alpha = default_alpha(dmax) if alpha is None else float(alpha)
+    check_alpha(alpha, dmax)
+    A = adjacency(row_ptr, col, n)
+    b = np.ones(n)
+    z = np.zeros(n)
+    r = b.copy()
+    p = r.copy()
+    rr = float(r @ r)
+    bnorm = float(np.sqrt(b @ b))
+    it, res, conv = 0, float(np.sqrt(rr)) / bnorm, False
+    while it < max_iter:
+        q = p - alpha * (A @ p)
+        a = rr / float(p @ q)
+        z = z + a * p
+        r = r - a * q
+        rr_new = float(r @ r)
+        it += 1
+        res = float(np.sqrt(rr_new)) / bnorm
+        if res < tol:
+            conv = True
+            break
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return SolveResult(scores=alpha * (A @ z), iterations=it, converged=conv, residual=res, alpha=alpha)
+
+
 def _arc_keys(row_ptr, col, n):
     src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
     return src * n + np.asarray(col, dtype=np.int64)

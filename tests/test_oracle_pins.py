@@ -565,3 +565,76 @@ def test_pair_criterion_argument_checks():
         K.rank_static(rp, col, 0.3, criterion=K.PAIR, pair=(1, 1))
     with pytest.raises(ValueError):
         K.rank_static(rp, col, 0.3, criterion=K.PAIR, pair=(0, 9))
+
+
+# --- the comparison methods (Foster's heuristic, CG on Eq. (la)) ------------------
+def _dense_katz(rp, col, alpha):
+    n = len(rp) - 1
+    A = np.zeros((n, n))
+    for v in range(n):
+        A[v, col[rp[v]:rp[v + 1]]] = 1.0
+    z = np.linalg.solve(np.eye(n) - alpha * A, np.ones(n))
+    return alpha * (A @ z)
+
+
+def test_foster_iterates_are_the_walk_sums():
+    """Foster's iteration stopped after r steps gives c_r (f_r - 1 = c_r)."""
+    rp, col = sg.erdos_renyi(400, 1600, 3)
+    alpha = 1.0 / (1 + sg.max_degree(rp))
+    for r in (1, 2, 5, 11):
+        res = oracle.foster(rp, col, alpha, tol=0.0, max_iter=r)
+        c, _ = oracle.walk_state(rp, col, alpha, r)
+        assert res.iterations == r and not res.converged
+        np.testing.assert_allclose(res.scores, c, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("name", ["er", "star", "rmat"])
+def test_foster_error_within_its_contraction_bound(name):
+    """The Foster map f -> alpha A f + 1 contracts the max-norm by alpha d_max,
+    so after stopping with change delta the error is at most
+    delta * alpha d_max / (1 - alpha d_max) (plus rounding)."""
+    rp, col = {"er": lambda: sg.erdos_renyi(500, 2500, 4), "star": lambda: sg.star_graph(40),
+               "rmat": lambda: sg.rmat(9, seed=2)}[name]()
+    d = sg.max_degree(rp)
+    alpha = 0.9 / d
+    res = oracle.foster(rp, col, alpha, tol=1e-7)
+    exact_c = _dense_katz(rp, col, alpha)
+    assert res.converged and res.residual < 1e-7
+    bound = res.residual * alpha * d / (1 - alpha * d)
+    assert np.max(np.abs(res.scores - exact_c)) <= bound * (1 + 1e-6) + 1e-12
+
+
+def test_cg_two_distinct_eigenvalues_two_steps():
+    """K_6 has two distinct adjacency eigenvalues (5, -1), so CG on
+    (I - alpha A) z = 1 stops after two steps, at the closed form
+    c = alpha d / (1 - alpha d) = 5 for alpha = 1/6 (Appendix A)."""
+    rp, col = sg.complete_graph(6)
+    res = oracle.conjugate_gradient(rp, col, 1.0 / 6.0, tol=1e-14)
+    assert res.converged and res.iterations <= 2
+    np.testing.assert_allclose(res.scores, 5.0, rtol=1e-14)
+
+
+@pytest.mark.parametrize("name", ["er", "ba", "rmat"])
+def test_cg_matches_direct_solve(name):
+    rp, col = {"er": lambda: sg.erdos_renyi(600, 3000, 9), "ba": lambda: sg.barabasi_albert(500, 4, 3),
+               "rmat": lambda: sg.rmat(9, seed=5)}[name]()
+    alpha = 1.0 / (1 + sg.max_degree(rp))
+    res = oracle.conjugate_gradient(rp, col, alpha, tol=1e-13)
+    assert res.converged
+    np.testing.assert_allclose(res.scores, _dense_katz(rp, col, alpha), rtol=1e-11, atol=1e-14)
+
+
+def test_cg_and_foster_exact_on_star():
+    """Star with L leaves: c(centre) = (1 + alpha) alpha L / (1 - alpha^2 L),
+    c(leaf) = alpha (1 + alpha L) / (1 - alpha^2 L), in exact arithmetic."""
+    L = 12
+    rp, col = sg.star_graph(L)
+    alpha = Fraction(1, 1 + L)
+    c_exact = exact.katz_exact(rp, col, alpha)
+    centre = (1 + alpha) * alpha * L / (1 - alpha * alpha * L)
+    leaf = alpha * (1 + alpha * L) / (1 - alpha * alpha * L)
+    assert c_exact[0] == centre and all(v == leaf for v in c_exact[1:])
+    cg = oracle.conjugate_gradient(rp, col, float(alpha), tol=1e-14)
+    fo = oracle.foster(rp, col, float(alpha), tol=1e-13)
+    for res in (cg, fo):
+        np.testing.assert_allclose(res.scores, [float(v) for v in c_exact], rtol=1e-11)
