@@ -28,9 +28,15 @@
  *     outputs are written by a device-to-host copy that has completed when the
  *     call returns.
  *   - `stream` is a hipStream_t (NULL = the default stream) of the current
- *     device.  Every call is blocking: when it returns, all its device work on
- *     `stream` has finished and every output is written.  Convergence is data
- *     dependent, so the host reads a device flag while iterating.
+ *     device.  Every call orders its device work on `stream` after earlier
+ *     work on that stream.  katz_bounds with both outputs in device memory is
+ *     asynchronous: it returns once its work is enqueued, and the outputs are
+ *     valid when the stream (or an event recorded on it after the call) has
+ *     completed.  Every other call is blocking: when it returns, all its
+ *     device work has finished and every output is written (convergence is
+ *     data dependent, so the host reads a device flag while iterating).  A
+ *     call on another stream that reuses the library's workspace waits for
+ *     the previous call's work first.
  *   - The caller owns every input and output buffer; the library never frees
  *     them and keeps no pointer to them after returning (katz_state copies the
  *     graph).  The library allocates its own workspace on the current device.
@@ -67,6 +73,8 @@ extern "C" {
 #define KATZ_E_UNSUPPORTED      -8  /* valid request outside what this build supports  */
 #define KATZ_E_SCRATCH          -9  /* katz_rank_static_noalloc: the problem needs more */
                                     /* workspace than the fixed scratch array holds     */
+#define KATZ_E_CANCELLED       -10  /* server: the request was still queued when the    */
+                                    /* server was destroyed; it never ran               */
 
 /* ---- precision forms ------------------------------------------------------ */
 #define KATZ_FP64         0  /* walk vector, sums and bounds in FP64 (the plain method)  */
@@ -92,16 +100,18 @@ extern "C" {
 
 /* ---- option flags (katz_params.flags) --------------------------------------- */
 #define KATZ_FLAG_NO_REORDER  1  /* keep the caller's node order on the device.  By     */
-                                 /* default static calls renumber nodes internally by   */
-                                 /* degree class (rows of similar length contiguous,    */
-                                 /* high-degree nodes first) so the walk vector's most  */
-                                 /* gathered entries share cache lines; results, ids    */
-                                 /* and tie order are the same either way.  A batch     */
-                                 /* (count > 1) is renumbered graph by graph only when  */
-                                 /* some graph's walk vector is larger than 4 MiB (one  */
-                                 /* XCD's L2; smaller ones stay cached whatever the     */
-                                 /* order) or a graph sets KATZ_FLAG_REORDER; NO_REORDER */
-                                 /* on any graph of a batch turns it off.               */
+                                 /* default static calls and dynamic states renumber    */
+                                 /* nodes internally by degree class (rows of similar   */
+                                 /* length contiguous, high-degree nodes first) so the  */
+                                 /* walk vector's most gathered entries share cache     */
+                                 /* lines; results, ids and tie order are the same      */
+                                 /* either way (a state keeps each row in the caller-id */
+                                 /* order of its entries).  A batch (count > 1) is      */
+                                 /* renumbered graph by graph only when some graph's    */
+                                 /* walk vector is larger than 4 MiB (one XCD's L2;     */
+                                 /* smaller ones stay cached whatever the order) or a   */
+                                 /* graph sets KATZ_FLAG_REORDER; NO_REORDER on any     */
+                                 /* graph of a batch turns it off.                      */
 #define KATZ_FLAG_REORDER     2  /* renumber a batch even where its graphs are small.   */
 
 /* A graph in compressed sparse row form.  Row v lists the out-neighbours of v:
@@ -215,8 +225,11 @@ int katz_rank_update(katz_state* st, const int32_t* ins_u, const int32_t* ins_v,
  * then l_r and u_r of every node (Section 3.1, Theorem 1).  This is the score
  * surface used for parity checks.  lower, upper: caller-owned arrays of n
  * doubles, host or device, indexed by node id.  p->k, p->epsilon and
- * p->max_iter are ignored.  Errors: E_INVALID_ARG (r < 1), E_ALPHA, E_CSR,
- * E_OOM, E_HIP.
+ * p->max_iter are ignored.  With both arrays in device memory the call is
+ * stream-ordered and asynchronous (every error, E_CSR included, is returned
+ * before it enqueues the iterations); otherwise it blocks until the host
+ * arrays are written.  Errors: E_INVALID_ARG (r < 1), E_ALPHA, E_CSR, E_OOM,
+ * E_HIP.
  */
 int katz_bounds(const katz_csr* g, const katz_params* p, int32_t r,
                 double* lower, double* upper, void* stream);
@@ -246,6 +259,43 @@ int katz_bounds(const katz_csr* g, const katz_params* p, int32_t r,
 int katz_rank_static_noalloc(const katz_csr* g, const katz_params* p,
                              katz_result* out, void* stream);
 
+/* ---- the paper's comparison methods (Sections 2.2 and 5) ----------------------
+ * Score vectors by the methods the paper compares against, on the same device
+ * kernels (the walk step's sparse matrix-vector product y = alpha A v, FP64,
+ * in the caller's node order), for comparison with the bound-based ranking.
+ *   KATZ_SOLVE_FOSTER  Foster's heuristic (Section 2.2): f_0 = 1,
+ *                      f_{i+1} = alpha A f_i + 1, stopped once the largest
+ *                      change of an entry, max_v |f_{i+1}(v) - f_i(v)|, is below
+ *                      tol; scores = f - 1.  No correctness guarantee.
+ *   KATZ_SOLVE_CG      conjugate gradients without preconditioning on Eq.
+ *                      (la), (I - alpha A) z = 1, from z = 0, stopped once the
+ *                      relative residual ||1 - (I - alpha A) z||_2 / sqrt(n) is
+ *                      below tol; scores = alpha A z (Section 1).  Undirected
+ *                      graphs only (the matrix must be symmetric).
+ */
+#define KATZ_SOLVE_FOSTER 0
+#define KATZ_SOLVE_CG     1
+
+typedef struct katz_solve_info {
+  int32_t iterations;      /* sparse matrix-vector products of the iteration        */
+  int32_t converged;       /* 1: the stopping test held; 0: max_iter was reached   */
+  double residual;         /* the last tested quantity (max change / rel. residual) */
+  double alpha_used;
+} katz_solve_info;
+
+/*
+ * katz_solve -- Katz scores of every node by Foster's heuristic or by CG.
+ * p->alpha (0.0 selects 1/(1 + deg_max)), p->max_iter (0 selects 1000) and
+ * p->validate are used; the other fields are ignored.  scores: caller-owned
+ * array of n doubles, host or device, indexed by node id.  info may be NULL.
+ * Blocking.  Returns KATZ_OK when the stopping test held, W_ITER_LIMIT when
+ * max_iter was reached first (scores hold the last iterate).  Errors:
+ * E_INVALID_ARG (method, tol <= 0), E_ALPHA, E_CSR, E_UNSUPPORTED (CG on a
+ * directed graph), E_OOM, E_HIP.
+ */
+int katz_solve(const katz_csr* g, const katz_params* p, int32_t method, double tol,
+               double* scores, katz_solve_info* info, void* stream);
+
 /* Frees a state from katz_rank_static (NULL is ignored). */
 void katz_state_free(katz_state* st);
 
@@ -255,12 +305,18 @@ const char* katz_strerror(int code);
 /* ---- serving: continuous admission of update batches -------------------------
  * A server owns dynamic states (katz_rank_update, Algorithm 2 of Section 4)
  * and a pool of `slots` worker threads, each with its own HIP stream on the
- * device current at creation.  Requests (edge-update batches) of one graph run
- * in submission order, one at a time, so the result of a request reflects
- * exactly that graph's batches up to it; requests of different graphs run
- * concurrently and overlap on the device.  A waiting request is admitted when
- * a slot is free and its device-memory estimate fits `memory_budget` bytes
- * (0 = unlimited).  All buffers passed to these calls are host memory. */
+ * device current at creation.  An update runs in two halves: the host half
+ * (the batch validated on its own and its arcs grouped by row; it reads no
+ * graph state) and the device half (existence checks against the graph, the
+ * merge, the re-walk, the re-certification).  The device halves of one
+ * graph's requests run in submission order, one at a time, so the result of
+ * a request reflects exactly that graph's batches up to it; their host halves
+ * run ahead, on idle slots, while earlier requests of the same graph are on
+ * the device.  Requests of different graphs run concurrently and overlap on
+ * the device.  A prepared request is admitted when a slot is free and its
+ * device-memory estimate (batch buffers, row merges, one more walk-history
+ * level and the slack-pool growth of its insertions) fits `memory_budget`
+ * bytes (0 = unlimited).  All buffers passed to these calls are host memory. */
 typedef struct katz_server katz_server;
 
 /* 1 <= slots <= 64.  Errors: E_INVALID_ARG, E_HIP. */
@@ -278,10 +334,12 @@ int katz_server_submit(katz_server* sv, int32_t graph_id, const int32_t* ins_u, 
  * (either pointer may be NULL).  Returns the request's status code. */
 int katz_server_wait(katz_server* sv, int64_t ticket, katz_result* out, double* latency_ms,
                      double* service_ms);
-/* Stops the workers (requests still queued are dropped) and frees the states.
- * No other call on sv may be in progress, or follow: a wait on a dropped
- * request would never return.  add_graph, submit and wait may otherwise be
- * called from any thread while requests run. */
+/* Stops the server: requests that have not started their device half end
+ * with E_CANCELLED (a thread blocked in katz_server_wait on one returns that
+ * code), requests on the device finish, then the workers stop, the call waits
+ * for every katz_server_wait in progress to return, and the states are freed.
+ * No call on sv may start once destroy has begun.  add_graph, submit and wait
+ * may otherwise be called from any thread while requests run. */
 void katz_server_destroy(katz_server* sv);
 
 /* ---- device timing (instrumentation for benchmarks and profiles) ----------

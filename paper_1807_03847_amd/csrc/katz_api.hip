@@ -83,9 +83,37 @@ struct Arena {
   bool measuring = false;
   bool fixed = false;   // base is the library's static scratch: never grown or freed
   HostSync hs;
+  // The last call's work on this workspace: an event recorded on its stream
+  // when the call returned (a stream-ordered call may still be running).
+  hipEvent_t last = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool recorded = false;
 
   ~Arena() {
+    if (recorded) (void)hipEventSynchronize(last);
+    if (last) (void)hipEventDestroy(last);
     if (base && !fixed) (void)hipFree(base);
+  }
+  // A call on stream s that takes over the workspace orders its work after
+  // the previous call's.
+  int order_after(hipStream_t s) {
+    if (recorded && last_stream != s) KATZ_HIP(hipStreamWaitEvent(s, last, 0));
+    return KATZ_OK;
+  }
+  void mark_used(hipStream_t s) {
+    if (!last && hipEventCreateWithFlags(&last, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      last = nullptr;
+      return;
+    }
+    if (hipEventRecord(last, s) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipStreamSynchronize(s);   // no event: the work is finished instead
+      recorded = false;
+      return;
+    }
+    recorded = true;
+    last_stream = s;
   }
   template <class T>
   T* take(size_t count) {
@@ -98,6 +126,7 @@ struct Arena {
     KATZ_TRY(hs.init());
     if (bytes <= cap) return KATZ_OK;
     if (fixed) return KATZ_E_SCRATCH;
+    if (recorded) KATZ_HIP(hipEventSynchronize(last));   // a stream-ordered call may still use it
     if (base) (void)hipFree(base);
     base = nullptr;
     cap = 0;
@@ -132,10 +161,18 @@ void release_arena(Arena* a) {
   g_pool.push_back(a);
 }
 
+// A static call's hold on a workspace: the call's stream is ordered after the
+// workspace's previous user, and the workspace records the call's work when
+// it goes back to the pool.
 struct ArenaLease {
   Arena* a;
-  explicit ArenaLease(int dev) : a(acquire_arena(dev)) {}
-  ~ArenaLease() { release_arena(a); }
+  hipStream_t s;
+  int rc;
+  ArenaLease(int dev, hipStream_t stream) : a(acquire_arena(dev)), s(stream), rc(a->order_after(stream)) {}
+  ~ArenaLease() {
+    a->mark_used(s);
+    release_arena(a);
+  }
 };
 
 bool is_device_ptr(const void* p) {
@@ -482,7 +519,13 @@ struct katz_state {
   int* row_cap = nullptr;
   int32_t* pool = nullptr;
   long long pool_cap = 0, pool_used = 0;
+  // Internal renumbering (as in static calls): row i of the slack CSR is the
+  // caller's node ext_of[i]; entries are internal ids, each row kept in the
+  // caller-id order of its entries.  Null: the state is in caller order.
+  int32_t* ext_of = nullptr;
+  int32_t* int_of = nullptr;
   katz::Bins bins;    // whole graph
+  bool bins_stale = false;   // rows changed length since the bins were built
   katz::Bins lbins;   // one re-walk level
   katz::Work w;
   katz::Scalars S;
@@ -681,7 +724,12 @@ SelArgs sel_args(const Run& run, int r) {
 
 int ensure_levels(katz_state* st, int r);
 
+int refresh_bins(katz_state* st, hipStream_t s);
+
 int enqueue_walk(Run& run, int r, hipStream_t s, CallTimer& T) {
+  // A dynamic state re-bins its rows lazily, before the first whole-graph walk
+  // after the updates that changed row lengths.
+  if (run.st) KATZ_TRY(refresh_bins(run.st, s));
   long long tb = 0;
   IterArgs ia = iter_args(run, *run.bins, r, false, tb);
   const bool renum = run.renumber && r == 2;
@@ -862,6 +910,8 @@ struct Plan {
   bool reorder;   // renumber nodes by degree class (internal)
   size_t out_n;   // elements per output array (k for ranking, n for bounds)
   size_t sort_n;  // records of the device-wide sort of the ranked list (0: none)
+  bool check_columns_first = false;   // range-check the column ids during preparation
+  int solve_vectors = 0;              // katz_solve: extra n-vectors (FP64) and reduction slots
 };
 
 struct Staging {
@@ -883,6 +933,8 @@ struct Staging {
   int32_t* out_ids = nullptr;
   double* out_lo = nullptr;
   double* out_up = nullptr;
+  double* vec = nullptr;          // katz_solve: solve_vectors n-vectors
+  double* slots = nullptr;        // katz_solve: reduction slots, results and scalars
 };
 
 void layout(Arena& ar, const Plan& pl, Bins& b, Work& w, Staging& stg) {
@@ -945,6 +997,10 @@ void layout(Arena& ar, const Plan& pl, Bins& b, Work& w, Staging& stg) {
       w.sort_ext = ar.take<int32_t>(pl.sort_n);
     }
   }
+  if (pl.solve_vectors) {
+    stg.vec = ar.take<double>((size_t)pl.solve_vectors * n);
+    stg.slots = ar.take<double>(linear_reduce_slots() + 16);
+  }
   if (pl.out_host) {
     stg.out_ids = ar.take<int32_t>(pl.out_n);
     stg.out_lo = ar.take<double>(pl.out_n);
@@ -998,7 +1054,7 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
   // every caller column id to rename it and never indexes with a bad one (no
   // step before it reads a column id; a run that stops before step 2 is
   // checked by check_columns_if_unread).
-  const bool check_in_walk = renumber_in_walk(pl);
+  const bool check_in_walk = renumber_in_walk(pl) && !pl.check_columns_first;
   if (pl.validate >= KATZ_VALIDATE_BASIC && !check_in_walk)
     KATZ_HIP(launch_check_col_range(stg.col, g->nnz, g->n, w.sc, s));
   KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
@@ -1006,7 +1062,8 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
   if (hs.sc->err) return KATZ_E_CSR;
   b.read_back(*hs.sc, g->n);
   if (pl.validate == KATZ_VALIDATE_STRICT) {
-    KATZ_HIP(launch_validate_strict(b.desc, g->n, stg.col, g->undirected, stg.row_off, stg.row_len, w.sc, s));
+    KATZ_HIP(launch_validate_strict(b.desc, g->n, b.segs, b.seg_total, b.huge, stg.col, g->undirected, stg.row_off,
+                                    stg.row_len, w.sc, s));
     KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
     KATZ_HIP(hipStreamSynchronize(s));
     if (hs.sc->err) return KATZ_E_CSR;
@@ -1108,7 +1165,8 @@ int rank_one(const katz_csr* g, const katz_params* p, katz_result* out, hipStrea
   KATZ_TRY(check_rank_args(g, p, out));
   int dev = 0;
   KATZ_HIP(hipGetDevice(&dev));
-  ArenaLease lease(dev);
+  ArenaLease lease(dev, s);
+  KATZ_TRY(lease.rc);
   return rank_in_arena(*lease.a, g, p, out, s, true);
 }
 
@@ -1119,7 +1177,8 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   if (r_target < 1 || !lower || !upper) return KATZ_E_INVALID_ARG;
   int dev = 0;
   KATZ_HIP(hipGetDevice(&dev));
-  ArenaLease lease(dev);
+  ArenaLease lease(dev, s);
+  KATZ_TRY(lease.rc);
   Arena& ar = *lease.a;
   Plan pl{};
   pl.g = g;
@@ -1131,6 +1190,12 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   pl.col_host = g->nnz > 0 && !is_device_ptr(g->col);
   const bool lo_dev = is_device_ptr(lower), up_dev = is_device_ptr(upper);
   pl.out_host = !(lo_dev && up_dev);
+  // Device outputs: the call is stream-ordered and returns once its work is
+  // enqueued.  Every error must then be known before that, so the column ids
+  // are range-checked in the preparation (a renumbered walk step 2 would
+  // otherwise find a bad id only on the device).
+  const bool async = !pl.out_host;
+  pl.check_columns_first = async;
   pl.select = false;
   pl.reorder = !(p->flags & KATZ_FLAG_NO_REORDER);
   pl.out_n = (size_t)g->n;
@@ -1168,10 +1233,11 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   CallTimer T;
   T.call_begin(s);
   for (int r = 1; r <= r_target; ++r) KATZ_TRY(enqueue_walk(run, r, s, T));
-  KATZ_HIP(hipMemcpyAsync(ar.hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
-  KATZ_HIP(hipStreamSynchronize(s));
-  T.commit(s);
-  if (ar.hs.sc->err) return KATZ_E_CSR;
+  if (!async) {
+    KATZ_HIP(hipMemcpyAsync(ar.hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipStreamSynchronize(s));
+    if (ar.hs.sc->err) return KATZ_E_CSR;
+  }
   const BoundArgs bd = bound_args(run, r_target);
   double* lo = pl.out_host ? stg.out_lo : lower;
   double* up = pl.out_host ? stg.out_up : upper;
@@ -1179,9 +1245,150 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   if (pl.out_host) {
     KATZ_HIP(hipMemcpyAsync(lower, lo, sizeof(double) * g->n, hipMemcpyDefault, s));
     KATZ_HIP(hipMemcpyAsync(upper, up, sizeof(double) * g->n, hipMemcpyDefault, s));
+    KATZ_HIP(hipStreamSynchronize(s));
   }
+  T.commit(s);   // with the timers on this waits for the stream
+  return KATZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The paper's comparison methods (katz_solve): Foster's heuristic and
+// conjugate gradients on Eq. (la), on the walk kernels' SpMV.
+// ---------------------------------------------------------------------------
+// y = alpha A v: one walk launch in re-walk mode (row sums times alpha only).
+int spmv(const Run& run, const double* v, double* y, hipStream_t s) {
+  long long tb = 0;
+  IterArgs ia = iter_args(run, *run.bins, 2, true, tb);
+  ia.x_in = v;
+  ia.x_out = y;
+  ia.hub_n = 0;
+  long long grid = 0;
+  KATZ_HIP(launch_walk_step(ia, 0, tb, run.walk_grid, &grid, s, false, run.walk_groups));
+  return KATZ_OK;
+}
+
+int read_scalar(const double* dev, double* host, hipStream_t s) {
+  KATZ_HIP(hipMemcpyAsync(host, dev, sizeof(double), hipMemcpyDeviceToHost, s));
   KATZ_HIP(hipStreamSynchronize(s));
   return KATZ_OK;
+}
+
+int solve_one(const katz_csr* g, const katz_params* p, int method, double tol, double* scores,
+              katz_solve_info* info, hipStream_t s) {
+  KATZ_TRY(check_graph(g));
+  KATZ_TRY(check_params(p, g->n, false));
+  if (!scores || !(tol > 0.0) || std::isinf(tol)) return KATZ_E_INVALID_ARG;
+  if (method != KATZ_SOLVE_FOSTER && method != KATZ_SOLVE_CG) return KATZ_E_INVALID_ARG;
+  // CG needs the symmetric matrix of an undirected graph.
+  if (method == KATZ_SOLVE_CG && !g->undirected) return KATZ_E_UNSUPPORTED;
+  int dev = 0;
+  KATZ_HIP(hipGetDevice(&dev));
+  ArenaLease lease(dev, s);
+  KATZ_TRY(lease.rc);
+  Arena& ar = *lease.a;
+  const long long n = g->n;
+  Plan pl{};
+  pl.g = g;
+  pl.fp32 = 0;
+  pl.k = 1;
+  pl.max_iter = 2;
+  pl.validate = p->validate;
+  pl.rp_host = !is_device_ptr(g->row_ptr);
+  pl.col_host = g->nnz > 0 && !is_device_ptr(g->col);
+  pl.out_host = !is_device_ptr(scores);
+  pl.select = false;
+  pl.reorder = false;   // caller order: the SpMV reads the caller's column ids
+  pl.out_n = (size_t)n;
+  pl.solve_vectors = 3;
+  Bins b;
+  Work w;
+  Staging stg;
+  KATZ_TRY(plan_and_allocate(ar, pl, b, w, stg));
+  KATZ_TRY(prepare(ar.hs, pl, b, w, stg, s));
+  Scalars S;
+  KATZ_TRY(resolve_alpha(p->alpha, b.dmax, S));
+  Run run;
+  run.n = n;
+  run.nnz = g->nnz;
+  run.undirected = g->undirected;
+  run.fp32 = 0;
+  run.col = stg.col;
+  run.bins = &b;
+  run.w = &w;
+  run.S = &S;
+  {
+    const katz_tuning tu = current_tuning();
+    run.walk_grid = (long long)tu.blocks_per_cu * cu_count(dev);
+    run.walk_groups = tu.walk_groups == kWalkGroups ? kWalkGroups : 1;
+  }
+  const int max_iter = p->max_iter ? p->max_iter : 1000;
+  double* x0 = static_cast<double*>(w.x[0]);
+  double* x1 = static_cast<double*>(w.x[1]);
+  double* y = w.c;
+  double* v0 = stg.vec;
+  double* v1 = stg.vec + n;
+  double* slots = stg.slots;
+  double* res_dev = slots + linear_reduce_slots();   // [0] p.q / max change, [1] r.r
+  double* scal = res_dev + 4;                         // [0] r.r, [1] a, [2] b
+  double* out = pl.out_host ? stg.out_lo : scores;
+  int it = 0;
+  bool conv = false;
+  double resid = 0.0;
+  if (method == KATZ_SOLVE_FOSTER) {
+    // f_0 = 1; f_{i+1} = alpha A f_i + 1; the Katz vector is f - 1.
+    double* f = x0;
+    double* fn = x1;
+    KATZ_HIP(launch_fill_value(f, n, 1.0, s));
+    while (it < max_iter) {
+      KATZ_TRY(spmv(run, f, y, s));
+      KATZ_HIP(launch_foster_step(y, f, fn, n, slots, res_dev, s));
+      ++it;
+      std::swap(f, fn);
+      KATZ_TRY(read_scalar(res_dev, &resid, s));
+      if (resid < tol) {
+        conv = true;
+        break;
+      }
+    }
+    KATZ_HIP(launch_write_scores(f, -1.0, n, nullptr, out, s));
+  } else {
+    // (I - alpha A) z = 1 from z = 0: r = p = 1, r.r = n.
+    double* z = x0;
+    double* r = x1;
+    double* pv = v0;
+    double* q = v1;
+    KATZ_HIP(launch_fill_value(z, n, 0.0, s));
+    KATZ_HIP(launch_fill_value(r, n, 1.0, s));
+    KATZ_HIP(launch_fill_value(pv, n, 1.0, s));
+    KATZ_HIP(launch_fill_value(scal, 1, (double)n, s));
+    const double bnorm = std::sqrt((double)n);
+    while (it < max_iter) {
+      KATZ_TRY(spmv(run, pv, y, s));
+      KATZ_HIP(launch_cg_apply(pv, y, q, n, slots, res_dev, scal, s));
+      KATZ_HIP(launch_cg_update(z, r, pv, q, n, slots, res_dev + 1, scal, s));
+      ++it;
+      double rr = 0.0;
+      KATZ_TRY(read_scalar(res_dev + 1, &rr, s));
+      resid = std::sqrt(rr) / bnorm;
+      if (resid < tol) {
+        conv = true;
+        break;
+      }
+      KATZ_HIP(launch_cg_direction(pv, r, scal, n, s));
+    }
+    // The Katz vector alpha A z.
+    KATZ_TRY(spmv(run, z, y, s));
+    KATZ_HIP(launch_write_scores(y, 0.0, n, nullptr, out, s));
+  }
+  if (pl.out_host) KATZ_HIP(hipMemcpyAsync(scores, out, sizeof(double) * n, hipMemcpyDefault, s));
+  KATZ_HIP(hipStreamSynchronize(s));
+  if (info) {
+    info->iterations = it;
+    info->converged = conv ? 1 : 0;
+    info->residual = resid;
+    info->alpha_used = S.alpha;
+  }
+  return conv ? KATZ_OK : KATZ_W_ITER_LIMIT;
 }
 
 // ---------------------------------------------------------------------------
@@ -1214,7 +1421,8 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   const int stride = max_iter + 1;
   int dev = 0;
   KATZ_HIP(hipGetDevice(&dev));
-  ArenaLease lease(dev);
+  ArenaLease lease(dev, s);
+  KATZ_TRY(lease.rc);
   Arena& ar = *lease.a;
 
   // ---- layout ----
@@ -1742,6 +1950,17 @@ int bin_rows(katz_state* st, Bins& b, RunScalars* sc, const int32_t* ids, long l
   return KATZ_OK;
 }
 
+// The whole-graph bins, rebuilt if an update changed row lengths since they
+// were built (the maximum row length is tracked by the updates themselves).
+int refresh_bins(katz_state* st, hipStream_t s) {
+  if (!st->bins_stale) return KATZ_OK;
+  const int dmax = st->bins.dmax;
+  KATZ_TRY(bin_rows(st, st->bins, st->sc2, nullptr, st->n, s));
+  st->bins.dmax = dmax;
+  st->bins_stale = false;
+  return KATZ_OK;
+}
+
 Run state_run(katz_state* st) {
   Run run;
   run.n = st->n;
@@ -1760,6 +1979,16 @@ Run state_run(katz_state* st) {
   run.cur = st->cur;
   run.first_select = false;
   run.grid = (int)std::min<long long>((st->n + kWG - 1) / kWG, 2048);
+  run.ext_of = st->ext_of;
+  run.int_of = st->int_of;
+  if (st->ext_of) {
+    // Renumbered: whole-graph walks take the tuned launch shape with the LDS
+    // copy of the hottest entries, as static calls do.
+    const katz_tuning tu = current_tuning();
+    run.walk_grid = (long long)tu.blocks_per_cu * cu_count(st->device);
+    run.walk_groups = tu.walk_groups == kWalkGroups ? kWalkGroups : 1;
+    run.hub_n = run.walk_grid > 0 ? (int)std::min<long long>(st->n, tu.hub_bytes / 8) : 0;
+  }
   return run;
 }
 
@@ -1854,11 +2083,52 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
   KATZ_TRY(alloc_bins(st, st->lbins));
   KATZ_TRY(bin_rows(st, st->bins, st->w.sc, nullptr, n, s));
   KATZ_HIP(launch_reset_flags(st->w.sc, s));
-  KATZ_HIP(launch_validate_strict(st->bins.desc, n, st->pool, 1, st->row_off, st->row_len, st->w.sc, s));
+  KATZ_HIP(launch_validate_strict(st->bins.desc, n, st->bins.segs, st->bins.seg_total, st->bins.huge, st->pool, 1,
+                                  st->row_off, st->row_len, st->w.sc, s));
   KATZ_HIP(hipMemcpyAsync(st->hs.sc, st->w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
   KATZ_HIP(hipStreamSynchronize(s));
   if (st->hs.sc->err) return KATZ_E_CSR;
   // validate_strict rewrote row_off/row_len from the descriptors: unchanged values.
+
+  if (!(p->flags & KATZ_FLAG_NO_REORDER)) {
+    // Renumber by the binned order (longest rows first), as static calls do, so
+    // the walk's most gathered entries share cache lines and the LDS copy.
+    st->ext_of = dalloc<int32_t>(st, n);
+    st->int_of = dalloc<int32_t>(st, n);
+    long long* cap_ll = dalloc<long long>(st, n);
+    long long* sums = dalloc<long long>(st, scan_sums_capacity(n));
+    long long* total = dalloc<long long>(st, 1);
+    long long* off_new = dalloc<long long>(st, n);
+    int* len_new = dalloc<int>(st, n);
+    int* cap_new = dalloc<int>(st, n);
+    if (!st->ext_of || !st->int_of || !cap_ll || !sums || !total || !off_new || !len_new || !cap_new)
+      return KATZ_E_OOM;
+    KATZ_HIP(launch_state_relabel(st->bins.desc, n, st->row_cap, st->ext_of, st->int_of, cap_ll, s));
+    KATZ_HIP(launch_scan_ll(cap_ll, n, off_new, sums, total, s));
+    long long used = 0;
+    KATZ_HIP(hipMemcpyAsync(&used, total, sizeof(long long), hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipStreamSynchronize(s));
+    const long long cap = used + used / 8 + 4096;
+    int32_t* pool_new = dalloc<int32_t>(st, cap);
+    if (!pool_new) return KATZ_E_OOM;
+    KATZ_HIP(launch_state_rename_rows(st->ext_of, st->int_of, n, st->row_off, st->row_len, st->row_cap, st->pool,
+                                      off_new, len_new, cap_new, pool_new, s));
+    KATZ_HIP(hipStreamSynchronize(s));
+    dfree(st, st->pool);
+    dfree(st, st->row_off);
+    dfree(st, st->row_len);
+    dfree(st, st->row_cap);
+    dfree(st, cap_ll);
+    dfree(st, sums);
+    dfree(st, total);
+    st->pool = pool_new;
+    st->pool_cap = cap;
+    st->pool_used = used;
+    st->row_off = off_new;
+    st->row_len = len_new;
+    st->row_cap = cap_new;
+    KATZ_TRY(bin_rows(st, st->bins, st->w.sc, nullptr, n, s));
+  }
 
   const int dmax = st->bins.dmax;
   KATZ_TRY(resolve_alpha(p->alpha, dmax, st->S));
@@ -1929,9 +2199,15 @@ struct Arc {
 };
 
 // Copies `count` ids from host or device memory into a host vector.
+// Host arrays are copied without a HIP call, so preparing a batch never waits
+// on device work.
 int fetch_ids(const int32_t* p, long long count, std::vector<int32_t>& out) {
   out.resize(count);
   if (count == 0) return KATZ_OK;
+  if (!is_device_ptr(p)) {
+    std::memcpy(out.data(), p, sizeof(int32_t) * count);
+    return KATZ_OK;
+  }
   KATZ_HIP(hipMemcpy(out.data(), p, sizeof(int32_t) * count, hipMemcpyDefault));
   return KATZ_OK;
 }
@@ -1964,14 +2240,20 @@ int grow_pool(katz_state* st, long long need, hipStream_t s) {
   return KATZ_OK;
 }
 
-int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, long long n_ins, const int32_t* del_u,
-                 const int32_t* del_v, long long n_del, katz_result* out, hipStream_t s) {
+}  // namespace
+
+// Host-side half of an update: the batch on its own (ids, loops, repeats,
+// I n D) and its arcs grouped by source row.  It reads no graph state, so a
+// server may prepare a request while an earlier request of the same graph is
+// still running.
+int prepare_batch(long long n, const int32_t* ins_u, const int32_t* ins_v, long long n_ins, const int32_t* del_u,
+                  const int32_t* del_v, long long n_del, PreparedBatch& pb) {
   if (n_ins < 0 || n_del < 0) return KATZ_E_INVALID_ARG;
   if ((n_ins > 0 && (!ins_u || !ins_v)) || (n_del > 0 && (!del_u || !del_v))) return KATZ_E_INVALID_ARG;
-  if (!out || !out->topk_ids || !out->lower || !out->upper) return KATZ_E_INVALID_ARG;
-  const long long n = st->n;
-
-  // ---- validate the batch on its own (ids, loops, repeats, I n D) ----
+  pb = PreparedBatch{};
+  pb.n = n;
+  pb.n_ins = n_ins;
+  pb.n_del = n_del;
   std::vector<int32_t> iu, iv, du, dv;
   KATZ_TRY(fetch_ids(ins_u, n_ins, iu));
   KATZ_TRY(fetch_ids(ins_v, n_ins, iv));
@@ -1997,33 +2279,18 @@ int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, lon
     std::set_intersection(ki.begin(), ki.end(), kd.begin(), kd.end(), std::back_inserter(both));
     if (!both.empty()) return KATZ_E_UPDATE;
   }
-
-  UpdateBufs& ub = st->ub;
-
-  // ---- existence checks against the graph (device) ----
+  // Pairs for the existence check: a-ends then b-ends, insertions first.
   const long long np = n_ins + n_del;
-  if (np > 0) {
-    KATZ_TRY(grow_buf(st, ub.pairs, ub.pairs_cap, 2 * np));
-    std::vector<int32_t> pa(2 * np);
-    for (long long j = 0; j < n_ins; ++j) {
-      pa[j] = iu[j];
-      pa[np + j] = iv[j];
-    }
-    for (long long j = 0; j < n_del; ++j) {
-      pa[n_ins + j] = du[j];
-      pa[np + n_ins + j] = dv[j];
-    }
-    KATZ_HIP(hipMemcpyAsync(ub.pairs, pa.data(), sizeof(int32_t) * 2 * np, hipMemcpyHostToDevice, s));
-    KATZ_HIP(hipMemsetAsync(st->err_dev, 0, sizeof(int), s));
-    KATZ_HIP(launch_batch_exist(ub.pairs, ub.pairs + np, n_ins, np, st->row_off, st->row_len, st->pool, st->err_dev,
-                                s));
-    int err = 0;
-    KATZ_HIP(hipMemcpyAsync(&err, st->err_dev, sizeof(int), hipMemcpyDeviceToHost, s));
-    KATZ_HIP(hipStreamSynchronize(s));
-    if (err) return KATZ_E_UPDATE;
+  pb.pa.resize(2 * np);
+  for (long long j = 0; j < n_ins; ++j) {
+    pb.pa[j] = iu[j];
+    pb.pa[np + j] = iv[j];
   }
-
-  // ---- arcs grouped by source row (both arcs of every pair) ----
+  for (long long j = 0; j < n_del; ++j) {
+    pb.pa[n_ins + j] = du[j];
+    pb.pa[np + n_ins + j] = dv[j];
+  }
+  // Arcs grouped by source row (both arcs of every pair).
   std::vector<Arc> ia, da;
   ia.reserve(2 * n_ins);
   da.reserve(2 * n_del);
@@ -2037,27 +2304,63 @@ int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, lon
   }
   std::sort(ia.begin(), ia.end());
   std::sort(da.begin(), da.end());
-  std::vector<int32_t> trows;
+  std::vector<int32_t>& trows = pb.trows;
   for (const Arc& a : ia) trows.push_back(a.src);
   for (const Arc& a : da) trows.push_back(a.src);
   std::sort(trows.begin(), trows.end());
   trows.erase(std::unique(trows.begin(), trows.end()), trows.end());
   const long long t = (long long)trows.size();
-  std::vector<long long> ins_off(t), del_off(t);
-  std::vector<int> ins_cnt(t, 0), del_cnt(t, 0), delta(t);
-  std::vector<int32_t> ins_dst, del_dst;
-  {
-    size_t pi = 0, pd = 0;
-    for (long long i = 0; i < t; ++i) {
-      ins_off[i] = (long long)ins_dst.size();
-      while (pi < ia.size() && ia[pi].src == trows[i]) ins_dst.push_back(ia[pi++].dst);
-      ins_cnt[i] = (int)(ins_dst.size() - ins_off[i]);
-      del_off[i] = (long long)del_dst.size();
-      while (pd < da.size() && da[pd].src == trows[i]) del_dst.push_back(da[pd++].dst);
-      del_cnt[i] = (int)(del_dst.size() - del_off[i]);
-      delta[i] = ins_cnt[i] - del_cnt[i];
-    }
+  pb.ins_off.assign(t, 0);
+  pb.del_off.assign(t, 0);
+  pb.ins_cnt.assign(t, 0);
+  pb.del_cnt.assign(t, 0);
+  pb.delta.assign(t, 0);
+  size_t pi = 0, pd = 0;
+  for (long long i = 0; i < t; ++i) {
+    pb.ins_off[i] = (long long)pb.ins_dst.size();
+    while (pi < ia.size() && ia[pi].src == trows[i]) pb.ins_dst.push_back(ia[pi++].dst);
+    pb.ins_cnt[i] = (int)(pb.ins_dst.size() - pb.ins_off[i]);
+    pb.del_off[i] = (long long)pb.del_dst.size();
+    while (pd < da.size() && da[pd].src == trows[i]) pb.del_dst.push_back(da[pd++].dst);
+    pb.del_cnt[i] = (int)(pb.del_dst.size() - pb.del_off[i]);
+    pb.delta[i] = pb.ins_cnt[i] - pb.del_cnt[i];
   }
+  return KATZ_OK;
+}
+
+long long state_nodes(const katz_state* st) { return st->n; }
+
+// Device-side half of an update: existence checks against the state's graph,
+// the merge into the slack CSR, the re-walk and the re-certification.
+int apply_batch(katz_state* st, const PreparedBatch& pb, katz_result* out, hipStream_t s) {
+  if (!out || !out->topk_ids || !out->lower || !out->upper) return KATZ_E_INVALID_ARG;
+  if (pb.n != st->n) return KATZ_E_INVALID_ARG;
+  const long long n = st->n;
+  const long long n_ins = pb.n_ins, n_del = pb.n_del;
+  UpdateBufs& ub = st->ub;
+
+  // ---- existence checks against the graph (device) ----
+  const long long np = n_ins + n_del;
+  if (np > 0) {
+    KATZ_TRY(grow_buf(st, ub.pairs, ub.pairs_cap, 2 * np));
+    KATZ_HIP(hipMemcpyAsync(ub.pairs, pb.pa.data(), sizeof(int32_t) * 2 * np, hipMemcpyHostToDevice, s));
+    KATZ_HIP(hipMemsetAsync(st->err_dev, 0, sizeof(int), s));
+    KATZ_HIP(launch_batch_exist(ub.pairs, ub.pairs + np, n_ins, np, st->row_off, st->row_len, st->pool, st->ext_of,
+                                st->int_of, st->err_dev, s));
+    int err = 0;
+    KATZ_HIP(hipMemcpyAsync(&err, st->err_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipStreamSynchronize(s));
+    if (err) return KATZ_E_UPDATE;
+  }
+  const std::vector<int32_t>& trows = pb.trows;
+  const std::vector<long long>& ins_off = pb.ins_off;
+  const std::vector<long long>& del_off = pb.del_off;
+  const std::vector<int>& ins_cnt = pb.ins_cnt;
+  const std::vector<int>& del_cnt = pb.del_cnt;
+  const std::vector<int>& delta = pb.delta;
+  const std::vector<int32_t>& ins_dst = pb.ins_dst;
+  const std::vector<int32_t>& del_dst = pb.del_dst;
+  const long long t = (long long)trows.size();
 
   CallTimer T;
   T.call_begin(s);
@@ -2083,6 +2386,7 @@ int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, lon
     int32_t* d_ins_dst = ub.dst;
     int32_t* d_del_dst = ub.dst + ins_dst.size();
     KATZ_HIP(hipMemcpyAsync(ub.rows, trows.data(), sizeof(int32_t) * t, hipMemcpyHostToDevice, s));
+    if (st->int_of) KATZ_HIP(launch_map_ids(ub.rows, t, st->int_of, s));   // touched rows, internal ids
     KATZ_HIP(hipMemcpyAsync(d_ins_off, ins_off.data(), sizeof(long long) * t, hipMemcpyHostToDevice, s));
     KATZ_HIP(hipMemcpyAsync(d_del_off, del_off.data(), sizeof(long long) * t, hipMemcpyHostToDevice, s));
     KATZ_HIP(hipMemcpyAsync(d_ins_cnt, ins_cnt.data(), sizeof(int) * t, hipMemcpyHostToDevice, s));
@@ -2093,17 +2397,29 @@ int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, lon
     if (!del_dst.empty())
       KATZ_HIP(hipMemcpyAsync(d_del_dst, del_dst.data(), sizeof(int32_t) * del_dst.size(), hipMemcpyHostToDevice, s));
     KATZ_HIP(launch_touched_lengths(ub.rows, t, d_delta, st->row_len, d_new_len, st->tmark, s));
-    KATZ_HIP(hipMemsetAsync(st->dmax_dev, 0, sizeof(int), s));
-    KATZ_HIP(launch_max_len_after(st->row_len, st->tmark, n, d_new_len, t, st->dmax_dev, s));
-    KATZ_HIP(launch_unmark_rows(ub.rows, t, st->tmark, s));
     KATZ_HIP(launch_gather_int(ub.rows, t, st->row_cap, d_caps, s));
     std::vector<int> caps(t);
     std::vector<long long> offs(t);
     KATZ_HIP(launch_gather_ll(ub.rows, t, st->row_off, d_dest_off, s));
-    KATZ_HIP(hipMemcpyAsync(&new_dmax, st->dmax_dev, sizeof(int), hipMemcpyDeviceToHost, s));
     KATZ_HIP(hipMemcpyAsync(new_len.data(), d_new_len, sizeof(long long) * t, hipMemcpyDeviceToHost, s));
     KATZ_HIP(hipMemcpyAsync(caps.data(), d_caps, sizeof(int) * t, hipMemcpyDeviceToHost, s));
     KATZ_HIP(hipMemcpyAsync(offs.data(), d_dest_off, sizeof(long long) * t, hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipStreamSynchronize(s));
+    // The new deg_max: the old one raised by the touched rows, unless a row of
+    // the old maximum length shrank, when every untouched row is scanned too.
+    bool shrank_max = false;
+    new_dmax = st->bins.dmax;
+    for (long long i = 0; i < t; ++i) {
+      const long long old_len = new_len[i] - delta[i];
+      if (old_len == st->bins.dmax && new_len[i] < old_len) shrank_max = true;
+      new_dmax = (int)std::max<long long>(new_dmax, new_len[i]);
+    }
+    if (shrank_max) {
+      KATZ_HIP(hipMemsetAsync(st->dmax_dev, 0, sizeof(int), s));
+      KATZ_HIP(launch_max_len_after(st->row_len, st->tmark, n, d_new_len, t, st->dmax_dev, s));
+      KATZ_HIP(hipMemcpyAsync(&new_dmax, st->dmax_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    }
+    KATZ_HIP(launch_unmark_rows(ub.rows, t, st->tmark, s));
     KATZ_HIP(hipStreamSynchronize(s));
     if (!(st->alpha * (double)new_dmax < 1.0) || new_dmax > st->degree_cap) return KATZ_E_DEGREE_CAP;
 
@@ -2132,14 +2448,14 @@ int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, lon
     KATZ_HIP(hipMemcpyAsync(d_dest_off, dest_off.data(), sizeof(long long) * t, hipMemcpyHostToDevice, s));
     KATZ_HIP(hipMemcpyAsync(d_dest_cap, dest_cap.data(), sizeof(int) * t, hipMemcpyHostToDevice, s));
     KATZ_HIP(launch_merge_rows(ub.rows, t, d_ins_off, d_ins_cnt, d_ins_dst, d_del_off, d_del_cnt, d_del_dst, d_sbase,
-                               st->row_off, st->row_len, st->pool, ub.scratch, s));
+                               st->row_off, st->row_len, st->pool, st->ext_of, st->int_of, ub.scratch, s));
     KATZ_HIP(launch_copy_back_rows(ub.rows, t, d_sbase, d_new_len, d_dest_off, d_dest_cap, ub.scratch, st->row_off,
                                    st->row_len, st->row_cap, st->pool, s));
     st->nnz += 2 * (n_ins - n_del);
 
-    // ---- bins of the new graph ----
+    // ---- bins of the new graph: rebuilt before the next whole-graph walk ----
     run = state_run(st);
-    KATZ_TRY(bin_rows(st, st->bins, st->sc2, nullptr, n, s));
+    st->bins_stale = true;
     st->bins.dmax = new_dmax;
 
     // ---- re-walk levels 1..r over the affected set (Algorithm 2) ----
@@ -2175,10 +2491,14 @@ int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, lon
       }
       long long tb = 0;
       if (dense) {
-        const IterArgs ia2 = iter_args(run, st->bins, i, true, tb);
+        // A whole-graph re-walk level: the tuned launch shape (LDS copy of the
+        // hottest entries of x_{i-1} in a renumbered state).
+        KATZ_TRY(refresh_bins(st, s));
+        IterArgs ia2 = iter_args(run, st->bins, i, true, tb);
+        ia2.hub_n = run.hub_n;
         long long g_used = 0;
         if (i == 1) KATZ_HIP(launch_walk_first(ia2, 0, n, st->nnz, 0, s));
-        else KATZ_HIP(launch_walk_step(ia2, 0, tb, 0, &g_used, s));
+        else KATZ_HIP(launch_walk_step(ia2, 0, tb, run.walk_grid, &g_used, s, false, run.walk_groups));
       } else {
         KATZ_TRY(bin_rows(st, st->lbins, st->sc2, st->clist, csize, s));
         const IterArgs ia2 = iter_args(run, st->lbins, i, true, tb);
@@ -2210,7 +2530,14 @@ int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, lon
   return write_result(run, st->hs, out, st->out_ids, st->out_lo, st->out_up, s, T);
 }
 
-}  // namespace
+int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, long long n_ins, const int32_t* del_u,
+                 const int32_t* del_v, long long n_del, katz_result* out, hipStream_t s) {
+  if (!out || !out->topk_ids || !out->lower || !out->upper) return KATZ_E_INVALID_ARG;
+  PreparedBatch pb;
+  KATZ_TRY(prepare_batch(st->n, ins_u, ins_v, n_ins, del_u, del_v, n_del, pb));
+  return apply_batch(st, pb, out, s);
+}
+
 }  // namespace katz
 
 // ---------------------------------------------------------------------------
@@ -2326,6 +2653,11 @@ KATZ_EXPORT int katz_rank_update(katz_state* st, const int32_t* ins_u, const int
 KATZ_EXPORT int katz_bounds(const katz_csr* g, const katz_params* p, int32_t r, double* lower, double* upper,
                             void* stream) {
   return katz::bounds_one(g, p, r, lower, upper, (hipStream_t)stream);
+}
+
+KATZ_EXPORT int katz_solve(const katz_csr* g, const katz_params* p, int32_t method, double tol, double* scores,
+                           katz_solve_info* info, void* stream) {
+  return katz::solve_one(g, p, method, tol, scores, info, (hipStream_t)stream);
 }
 
 KATZ_EXPORT void katz_state_free(katz_state* st) { delete st; }
@@ -2459,6 +2791,7 @@ KATZ_EXPORT const char* katz_strerror(int code) {
     case KATZ_E_HIP: return "error: HIP runtime failure";
     case KATZ_E_UNSUPPORTED: return "error: unsupported request";
     case KATZ_E_SCRATCH: return "error: the problem needs more workspace than the fixed scratch array holds";
+    case KATZ_E_CANCELLED: return "error: the request was cancelled when the server stopped";
     default: return "unknown status code";
   }
 }

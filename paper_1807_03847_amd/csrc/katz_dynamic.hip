@@ -105,19 +105,75 @@ __device__ __forceinline__ long long lower_bound_i32(const int32_t* a, long long
   return lo;
 }
 
+// A renumbered state stores internal ids, each row sorted by the caller ids
+// of its entries (the static order of that row's sum).  ext_of / int_of map
+// internal <-> caller ids; null maps are the identity (a state in caller order).
+__device__ __forceinline__ int32_t ext_or_id(const int32_t* ext_of, int32_t x) { return ext_of ? ext_of[x] : x; }
+
+// First position in a row whose entry's caller id is not below e.
+__device__ __forceinline__ long long lower_bound_ext(const int32_t* row, long long len, int32_t e,
+                                                     const int32_t* ext_of) {
+  long long lo = 0, hi = len;
+  while (lo < hi) {
+    const long long mid = (lo + hi) >> 1;
+    if (ext_or_id(ext_of, row[mid]) < e) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // Inserted arcs must be absent and deleted arcs present (Section 4: I n E = {},
-// D c E).  Pairs [0, n_ins) are insertions, [n_ins, n_ins + n_del) deletions.
+// D c E).  Pairs [0, n_ins) are insertions, [n_ins, n_ins + n_del) deletions,
+// in caller ids.
 __global__ void __launch_bounds__(kWG) batch_exist(const int32_t* a, const int32_t* b, long long n_ins,
                                                    long long total, const long long* row_off, const int* row_len,
-                                                   const int32_t* pool, int* err) {
+                                                   const int32_t* pool, const int32_t* ext_of, const int32_t* int_of,
+                                                   int* err) {
   const long long j = (long long)blockIdx.x * kWG + threadIdx.x;
   if (j >= total) return;
-  const int32_t u = a[j], v = b[j];
+  const int32_t u = int_of ? int_of[a[j]] : a[j], v = b[j];
   const int32_t* row = pool + row_off[u];
   const long long len = row_len[u];
-  const long long p = lower_bound_i32(row, len, v);
-  const bool found = p < len && row[p] == v;
+  const long long p = lower_bound_ext(row, len, v, ext_of);
+  const bool found = p < len && ext_or_id(ext_of, row[p]) == v;
   if ((j < n_ins) == found) atomicOr(err, 1);
+}
+
+// Caller ids -> internal ids, in place.
+__global__ void __launch_bounds__(kWG) map_ids(int32_t* ids, long long count, const int32_t* int_of) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i < count) ids[i] = int_of[ids[i]];
+}
+
+// Renumbering of a new state: internal id i = position of the caller's row in
+// the binned order (as in a static call); the slack capacities in internal order.
+__global__ void __launch_bounds__(kWG) state_relabel(const RowDesc* desc, long long n, const int* row_cap,
+                                                     int32_t* ext_of, int32_t* int_of, long long* cap_ll) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i >= n) return;
+  const int v = desc[i].row;
+  ext_of[i] = v;
+  int_of[v] = (int32_t)i;
+  cap_ll[i] = row_cap[v];
+}
+
+// One wave per internal row i: the caller's row ext_of[i], entries renamed and
+// kept in their order, copied to the internal pool.
+__global__ void __launch_bounds__(kWG) state_rename_rows(const int32_t* ext_of, const int32_t* int_of, long long n,
+                                                         const long long* off_old, const int* len_old,
+                                                         const int* cap_old, const int32_t* pool_old,
+                                                         const long long* off_new, int* len_new, int* cap_new,
+                                                         int32_t* pool_new) {
+  const long long i = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave;
+  if (i >= n) return;
+  const int v = ext_of[i];
+  const long long src = off_old[v], dst = off_new[i];
+  const int len = len_old[v];
+  for (long long j = lane_id(); j < len; j += kWave) pool_new[dst + j] = int_of[pool_old[src + j]];
+  if (lane_id() == 0) {
+    len_new[i] = len;
+    cap_new[i] = cap_old[v];
+  }
 }
 
 // Candidate lengths of the touched rows; marks them.
@@ -151,13 +207,15 @@ __global__ void __launch_bounds__(kWG) unmark_rows(const int32_t* rows, long lon
   if (i < t) mark[rows[i]] = 0;
 }
 
-// One workgroup per touched row w: new row = (old row \ del) u ins, sorted,
-// written to scratch[sbase[i] ..].  ins and del are sorted per row.
+// One workgroup per touched row w: new row = (old row \ del) u ins, in caller-id
+// order, written to scratch[sbase[i] ..].  ins and del hold caller ids, sorted
+// per row; the row's entries are stored ids (internal in a renumbered state).
 __global__ void __launch_bounds__(kWG) merge_rows(const int32_t* rows, const long long* ins_off, const int* ins_cnt,
                                                   const int32_t* ins_dst, const long long* del_off,
                                                   const int* del_cnt, const int32_t* del_dst,
                                                   const long long* sbase, const long long* row_off,
-                                                  const int* row_len, const int32_t* pool, int32_t* scratch) {
+                                                  const int* row_len, const int32_t* pool, const int32_t* ext_of,
+                                                  const int32_t* int_of, int32_t* scratch) {
   const long long i = blockIdx.x;
   const int w = rows[i];
   const int32_t* old = pool + row_off[w];
@@ -168,16 +226,17 @@ __global__ void __launch_bounds__(kWG) merge_rows(const int32_t* rows, const lon
   int32_t* out = scratch + sbase[i];
   for (long long j = threadIdx.x; j < len; j += kWG) {
     const int32_t x = old[j];
-    const long long pd = lower_bound_i32(del, nd, x);
-    if (pd < nd && del[pd] == x) continue;
-    const long long pi = lower_bound_i32(ins, ni, x);
+    const int32_t e = ext_or_id(ext_of, x);
+    const long long pd = lower_bound_i32(del, nd, e);
+    if (pd < nd && del[pd] == e) continue;
+    const long long pi = lower_bound_i32(ins, ni, e);
     out[j - pd + pi] = x;
   }
   for (int j = threadIdx.x; j < ni; j += kWG) {
-    const int32_t x = ins[j];
-    const long long po = lower_bound_i32(old, len, x);
-    const long long pd = lower_bound_i32(del, nd, x);
-    out[j + po - pd] = x;
+    const int32_t e = ins[j];
+    const long long po = lower_bound_ext(old, len, e, ext_of);
+    const long long pd = lower_bound_i32(del, nd, e);
+    out[j + po - pd] = int_of ? int_of[e] : e;
   }
 }
 
@@ -376,12 +435,33 @@ hipError_t launch_copy_rows_to_pool(const void* rp, int rp64, const int32_t* col
   return hipGetLastError();
 }
 
+hipError_t launch_map_ids(int32_t* ids, long long count, const int32_t* int_of, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(map_ids, dim3(blocks_for(count)), dim3(kWG), 0, s, ids, count, int_of);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_relabel(const RowDesc* desc, long long n, const int* row_cap, int32_t* ext_of,
+                               int32_t* int_of, long long* cap_ll, hipStream_t s) {
+  hipLaunchKernelGGL(state_relabel, dim3(blocks_for(n)), dim3(kWG), 0, s, desc, n, row_cap, ext_of, int_of, cap_ll);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_rename_rows(const int32_t* ext_of, const int32_t* int_of, long long n,
+                                   const long long* off_old, const int* len_old, const int* cap_old,
+                                   const int32_t* pool_old, const long long* off_new, int* len_new, int* cap_new,
+                                   int32_t* pool_new, hipStream_t s) {
+  const long long nb = (n * kWave + kWG - 1) / kWG;
+  hipLaunchKernelGGL(state_rename_rows, dim3((unsigned)nb), dim3(kWG), 0, s, ext_of, int_of, n, off_old, len_old,
+                     cap_old, pool_old, off_new, len_new, cap_new, pool_new);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch_exist(const int32_t* a, const int32_t* b, long long n_ins, long long total,
-                              const long long* row_off, const int* row_len, const int32_t* pool, int* err,
-                              hipStream_t s) {
+                              const long long* row_off, const int* row_len, const int32_t* pool,
+                              const int32_t* ext_of, const int32_t* int_of, int* err, hipStream_t s) {
   if (total > 0)
     hipLaunchKernelGGL(batch_exist, dim3(blocks_for(total)), dim3(kWG), 0, s, a, b, n_ins, total, row_off, row_len,
-                       pool, err);
+                       pool, ext_of, int_of, err);
   return hipGetLastError();
 }
 
@@ -406,10 +486,11 @@ hipError_t launch_unmark_rows(const int32_t* rows, long long t, uint8_t* mark, h
 hipError_t launch_merge_rows(const int32_t* rows, long long t, const long long* ins_off, const int* ins_cnt,
                              const int32_t* ins_dst, const long long* del_off, const int* del_cnt,
                              const int32_t* del_dst, const long long* sbase, const long long* row_off,
-                             const int* row_len, const int32_t* pool, int32_t* scratch, hipStream_t s) {
+                             const int* row_len, const int32_t* pool, const int32_t* ext_of, const int32_t* int_of,
+                             int32_t* scratch, hipStream_t s) {
   if (t > 0)
     hipLaunchKernelGGL(merge_rows, dim3((unsigned)t), dim3(kWG), 0, s, rows, ins_off, ins_cnt, ins_dst, del_off,
-                       del_cnt, del_dst, sbase, row_off, row_len, pool, scratch);
+                       del_cnt, del_dst, sbase, row_off, row_len, pool, ext_of, int_of, scratch);
   return hipGetLastError();
 }
 

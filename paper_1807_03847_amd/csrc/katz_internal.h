@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "katz.h"
 
@@ -278,8 +279,11 @@ hipError_t launch_prep_scan(long long* blk, int nblocks, long long* sums, long l
 hipError_t launch_prep_scatter(const void* row_ptr, int row_ptr_64, int64_t n,
                                const long long* blk, int nblocks, RowDesc* desc,
                                SegDesc* segs, HugeRow* huge, RunScalars* sc, hipStream_t s);
-hipError_t launch_validate_strict(const RowDesc* desc, long long n, const int32_t* col, int undirected,
-                                  long long* row_off, int* row_len, RunScalars* sc, hipStream_t s);
+// segs / nseg / huge: the bins' segments of rows longer than kBlockRowMax
+// (their symmetry is checked segment by segment).
+hipError_t launch_validate_strict(const RowDesc* desc, long long n, const SegDesc* segs, long long nseg,
+                                  const HugeRow* huge, const int32_t* col, int undirected, long long* row_off,
+                                  int* row_len, RunScalars* sc, hipStream_t s);
 hipError_t launch_walk_first(const IterArgs& a, int fp32, long long n, long long nnz, int validate,
                              hipStream_t s);
 // Workgroups of `block` threads and `lds` dynamic LDS bytes of a kernel that
@@ -328,9 +332,18 @@ hipError_t launch_slack_caps(const void* rp, int rp64, long long n, int* row_len
                              long long* cap_ll, hipStream_t s);
 hipError_t launch_copy_rows_to_pool(const void* rp, int rp64, const int32_t* col, long long n,
                                     const long long* row_off, int32_t* pool, hipStream_t s);
+// ext_of / int_of: internal <-> caller id maps of a renumbered state (null:
+// the state is in caller order); batch pairs and per-row lists are caller ids.
 hipError_t launch_batch_exist(const int32_t* a, const int32_t* b, long long n_ins, long long total,
-                              const long long* row_off, const int* row_len, const int32_t* pool, int* err,
-                              hipStream_t s);
+                              const long long* row_off, const int* row_len, const int32_t* pool,
+                              const int32_t* ext_of, const int32_t* int_of, int* err, hipStream_t s);
+hipError_t launch_map_ids(int32_t* ids, long long count, const int32_t* int_of, hipStream_t s);
+hipError_t launch_state_relabel(const RowDesc* desc, long long n, const int* row_cap, int32_t* ext_of,
+                               int32_t* int_of, long long* cap_ll, hipStream_t s);
+hipError_t launch_state_rename_rows(const int32_t* ext_of, const int32_t* int_of, long long n,
+                                   const long long* off_old, const int* len_old, const int* cap_old,
+                                   const int32_t* pool_old, const long long* off_new, int* len_new, int* cap_new,
+                                   int32_t* pool_new, hipStream_t s);
 hipError_t launch_touched_lengths(const int32_t* rows, long long t, const int* delta, const int* row_len,
                                   long long* new_len, uint8_t* mark, hipStream_t s);
 hipError_t launch_max_len_after(const int* row_len, const uint8_t* mark, long long n, const long long* new_len,
@@ -339,7 +352,8 @@ hipError_t launch_unmark_rows(const int32_t* rows, long long t, uint8_t* mark, h
 hipError_t launch_merge_rows(const int32_t* rows, long long t, const long long* ins_off, const int* ins_cnt,
                              const int32_t* ins_dst, const long long* del_off, const int* del_cnt,
                              const int32_t* del_dst, const long long* sbase, const long long* row_off,
-                             const int* row_len, const int32_t* pool, int32_t* scratch, hipStream_t s);
+                             const int* row_len, const int32_t* pool, const int32_t* ext_of, const int32_t* int_of,
+                             int32_t* scratch, hipStream_t s);
 hipError_t launch_copy_back_rows(const int32_t* rows, long long t, const long long* sbase, const long long* new_len,
                                  const long long* dest_off, const int* dest_cap, const int32_t* scratch,
                                  long long* row_off, int* row_len, int* row_cap, int32_t* pool, hipStream_t s);
@@ -399,5 +413,35 @@ hipError_t launch_batch_write(const GraphSel* gsel, int count, long long max_n, 
                               unsigned long long* rest_bits, hipStream_t s);
 
 int bin_of_host(int64_t len);
+
+// ---- vector kernels of katz_solve (katz_linear.hip) -----------------------------
+int linear_reduce_slots();
+hipError_t launch_fill_value(double* x, long long n, double v, hipStream_t s);
+hipError_t launch_foster_step(const double* y, const double* f, double* f_new, long long n, double* slots,
+                              double* out, hipStream_t s);
+hipError_t launch_cg_apply(const double* p, const double* y, double* q, long long n, double* slots, double* out,
+                           double* scal, hipStream_t s);
+hipError_t launch_cg_update(double* z, double* r, const double* p, const double* q, long long n, double* slots,
+                            double* out, double* scal, hipStream_t s);
+hipError_t launch_cg_direction(double* p, const double* r, const double* scal, long long n, hipStream_t s);
+hipError_t launch_write_scores(const double* x, double add, long long n, const int32_t* ext_of, double* out,
+                               hipStream_t s);
+
+// ---- dynamic updates in two halves (katz_api.hip) ------------------------------
+// A validated batch with its arcs grouped by source row; prepared on the host
+// without reading the graph, applied later to a state of the same n.
+struct PreparedBatch {
+  long long n = 0;
+  long long n_ins = 0, n_del = 0;
+  std::vector<int32_t> pa;                 // existence-check pairs: a-ends, then b-ends
+  std::vector<int32_t> trows;              // touched rows, ascending
+  std::vector<long long> ins_off, del_off; // per touched row: first arc in ins_dst / del_dst
+  std::vector<int> ins_cnt, del_cnt, delta;
+  std::vector<int32_t> ins_dst, del_dst;
+};
+int prepare_batch(long long n, const int32_t* ins_u, const int32_t* ins_v, long long n_ins, const int32_t* del_u,
+                  const int32_t* del_v, long long n_del, PreparedBatch& pb);
+int apply_batch(katz_state* st, const PreparedBatch& pb, katz_result* out, hipStream_t s);
+long long state_nodes(const katz_state* st);
 
 }  // namespace katz

@@ -116,26 +116,52 @@ __global__ void __launch_bounds__(kWG) validate_strict(const RowDesc* desc, long
   if (bad) atomicOr(&sc->err, 1);
 }
 
-// Symmetry: arc v->u must have u->v.  Rows are looked up through the row
-// pointer of the descriptor table (desc is in bin order, so use an index).
-__global__ void __launch_bounds__(kWG) validate_symmetry(const long long* row_off, const int* row_len,
-                                                         const int32_t* col, long long n, RunScalars* sc) {
-  const long long v = (long long)blockIdx.x * kWG + threadIdx.x;
-  if (v >= n) return;
-  bool bad = false;
-  const long long o = row_off[v];
-  const int len = row_len[v];
-  for (int j = 0; j < len && !bad; ++j) {
-    const int32_t u = col[o + j];
-    if (u < 0 || u >= n) { bad = true; break; }
-    long long lo = row_off[u], hi = row_off[u] + row_len[u];
-    while (lo < hi) {
-      const long long mid = (lo + hi) >> 1;
-      if (col[mid] < v) lo = mid + 1; else hi = mid;
-    }
-    if (lo >= row_off[u] + row_len[u] || col[lo] != v) bad = true;
+// Symmetry: arc v->u must have u->v (a binary search of v in row u, whose
+// entries are sorted by the strict check).  One wave per row of at most one
+// segment's length, lanes striding over its arcs; longer rows go by segments
+// (one wave per 4096-arc segment), so a hub row is checked by many waves.
+__device__ __forceinline__ bool has_arc(const long long* row_off, const int* row_len, const int32_t* col, int u,
+                                        int v) {
+  long long lo = row_off[u], hi = row_off[u] + row_len[u];
+  const long long end = hi;
+  while (lo < hi) {
+    const long long mid = (lo + hi) >> 1;
+    if (col[mid] < v) lo = mid + 1;
+    else hi = mid;
   }
-  if (bad) atomicOr(&sc->err, 1);
+  return lo < end && col[lo] == v;
+}
+
+__device__ __forceinline__ bool check_arcs(const long long* row_off, const int* row_len, const int32_t* col,
+                                           long long n, int v, long long off, int len) {
+  bool bad = false;
+  for (int j = lane_id(); j < len && !bad; j += kWave) {
+    const int32_t u = col[off + j];
+    bad = u < 0 || u >= n || !has_arc(row_off, row_len, col, u, v);
+  }
+  return bad;
+}
+
+__global__ void __launch_bounds__(kWG) validate_symmetry_rows(const RowDesc* desc, long long count,
+                                                              const long long* row_off, const int* row_len,
+                                                              const int32_t* col, long long n, RunScalars* sc) {
+  const long long i = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave;
+  if (i >= count) return;
+  const RowDesc d = desc[i];
+  if (d.len > kBlockRowMax) return;   // checked by segments
+  const bool bad = check_arcs(row_off, row_len, col, n, d.row, d.off, d.len);
+  if (__ballot(bad) && lane_id() == 0) atomicOr(&sc->err, 1);
+}
+
+__global__ void __launch_bounds__(kWG) validate_symmetry_segs(const SegDesc* segs, long long nseg,
+                                                              const HugeRow* huge, const long long* row_off,
+                                                              const int* row_len, const int32_t* col, long long n,
+                                                              RunScalars* sc) {
+  const long long i = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave;
+  if (i >= nseg) return;
+  const SegDesc sd = segs[i];
+  const bool bad = check_arcs(row_off, row_len, col, n, huge[sd.hrow].row, sd.off, sd.len);
+  if (__ballot(bad) && lane_id() == 0) atomicOr(&sc->err, 1);
 }
 
 __global__ void __launch_bounds__(kWG) desc_to_rows(const RowDesc* desc, long long count,
@@ -1189,14 +1215,21 @@ hipError_t launch_prep_rows(const int32_t* ids, long long count, const long long
   return hipGetLastError();
 }
 
-hipError_t launch_validate_strict(const RowDesc* desc, long long n, const int32_t* col, int undirected,
-                                  long long* row_off, int* row_len, RunScalars* sc, hipStream_t s) {
+hipError_t launch_validate_strict(const RowDesc* desc, long long n, const SegDesc* segs, long long nseg,
+                                  const HugeRow* huge, const int32_t* col, int undirected, long long* row_off,
+                                  int* row_len, RunScalars* sc, hipStream_t s) {
   const long long blocks = (n * kWave + kWG - 1) / kWG;
   hipLaunchKernelGGL(validate_strict, dim3((unsigned)blocks), dim3(kWG), 0, s, desc, n, col, n, sc);
   if (undirected) {
     const long long nb = (n + kWG - 1) / kWG;
     hipLaunchKernelGGL(desc_to_rows, dim3((unsigned)nb), dim3(kWG), 0, s, desc, n, row_off, row_len);
-    hipLaunchKernelGGL(validate_symmetry, dim3((unsigned)nb), dim3(kWG), 0, s, row_off, row_len, col, n, sc);
+    hipLaunchKernelGGL(validate_symmetry_rows, dim3((unsigned)blocks), dim3(kWG), 0, s, desc, n,
+                       (const long long*)row_off, (const int*)row_len, col, n, sc);
+    if (nseg > 0) {
+      const long long sb = (nseg * kWave + kWG - 1) / kWG;
+      hipLaunchKernelGGL(validate_symmetry_segs, dim3((unsigned)sb), dim3(kWG), 0, s, segs, nseg, huge,
+                         (const long long*)row_off, (const int*)row_len, col, n, sc);
+    }
   }
   return hipGetLastError();
 }

@@ -1,13 +1,20 @@
 // Serving loop for dynamic updates (host runtime).
 //
 // Each registered graph is a katz_state (device-resident graph, walk history,
-// bounds and active set).  Requests are edge-update batches; every graph keeps
-// its requests in arrival order and runs at most one at a time, so the result
-// of request j reflects exactly the batches of that graph up to j.  A pool of
-// worker slots, each with its own HIP stream, takes the oldest request of any
-// idle graph whose estimated device memory fits the remaining budget: requests
-// that arrive while others run are admitted as soon as a slot and memory free
-// up, and updates of different graphs overlap on the device.
+// bounds and active set).  Requests are edge-update batches.  An update runs
+// in two halves (prepare_batch / apply_batch): the host half validates the
+// batch on its own and groups its arcs by row, reading no graph state; the
+// device half checks the batch against the graph, merges it, re-walks and
+// re-certifies (Algorithm 2).  The device halves of one graph's requests run
+// in arrival order, one at a time, so request j's result reflects exactly that
+// graph's batches up to j; host halves run ahead on idle slots, so the host
+// work of request j+1 overlaps the device work of request j of the same graph.
+// A pool of worker slots, each with its own HIP stream, takes, in this order:
+// the oldest prepared request at the head of an idle graph's queue whose
+// estimated device memory fits the remaining budget (its device half); the
+// oldest request not yet prepared (its host half, and then its device half at
+// once if it heads an idle graph's queue and fits).  Requests of different
+// graphs overlap on the device.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -28,14 +35,19 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+enum Phase { QUEUED, PREPARING, PREPARED, RUNNING, DONE };
+
 struct Request {
   int64_t ticket = 0;
   int32_t graph = 0;
   std::vector<int32_t> iu, iv, du, dv;
-  int64_t bytes = 0;              // admission estimate
+  int64_t bytes = 0;              // admission estimate of the device half
   Clock::time_point arrival;
+  Phase phase = QUEUED;
+  int prep_rc = KATZ_OK;
+  katz::PreparedBatch pb;
+  double prepare_ms = 0.0;
   // completion
-  bool done = false;
   int status = 0;
   std::vector<int32_t> ids;
   std::vector<double> lo, up;
@@ -47,16 +59,17 @@ struct Request {
 struct GraphEntry {
   katz_state* st = nullptr;
   int32_t k = 0;
-  std::deque<std::shared_ptr<Request>> queue;
-  bool busy = false;
+  int64_t n = 0;
+  std::deque<std::shared_ptr<Request>> queue;   // arrival order, not yet on the device
+  bool busy = false;                             // a device half of this graph runs
 };
 
 }  // namespace
 
 struct katz_server {
   std::mutex mu;
-  std::condition_variable cv_work;   // workers wait for admissible requests
-  std::condition_variable cv_done;   // callers wait for completions
+  std::condition_variable cv_work;   // workers wait for work
+  std::condition_variable cv_done;   // callers wait for completions; destroy waits for callers
   // A deque: add_graph appends while workers hold pointers to other entries,
   // and push_back on a deque never moves the elements already in it.
   std::deque<GraphEntry> graphs;
@@ -66,6 +79,7 @@ struct katz_server {
   int64_t next_ticket = 1;
   int64_t budget = 0;                // bytes; 0 = unlimited
   int64_t in_use = 0;
+  int waiters = 0;                   // threads inside katz_server_wait
   bool stopping = false;
   int device = 0;
   std::atomic<int64_t> completed{0};
@@ -73,60 +87,115 @@ struct katz_server {
 
 namespace {
 
-// Device bytes a request may need beyond the state's resident memory: the
-// batch arrays, the per-row merge scratch and the per-touched-row tables.
-int64_t estimate_bytes(int64_t pairs) { return 4096 + pairs * (2 * 4 + 4 * (8 + 8 + 4 * 5 + 8)); }
+// Device bytes the device half of a request may allocate beyond the state's
+// resident memory: the batch arrays and per-touched-row tables, the row-merge
+// scratch, one more level of the walk history (8 n bytes) should the
+// re-certification need another iteration, and the slack-pool growth its
+// insertions can force (the pool at most doubles: bounded here by the
+// relocated rows' arcs, twice per inserted pair, with the slack factor).
+int64_t estimate_bytes(int64_t pairs, int64_t n) {
+  const int64_t batch = 4096 + pairs * (2 * 4 + 4 * (8 + 8 + 4 * 5 + 8));
+  const int64_t level = 8 * n;
+  const int64_t pool = pairs * 2 * 4 * 9 / 8 * 2;
+  return batch + level + pool;
+}
 
-// Oldest request of an idle graph that fits the memory budget.
-std::shared_ptr<Request> pick(katz_server* sv) {
+bool fits(const katz_server* sv, const Request& rq) {
+  return sv->budget <= 0 || sv->in_use == 0 || sv->in_use + rq.bytes <= sv->budget;
+}
+
+// The oldest prepared request heading the queue of an idle graph that fits.
+std::shared_ptr<Request> pick_run(katz_server* sv) {
   std::shared_ptr<Request> best;
   for (GraphEntry& ge : sv->graphs) {
     if (ge.busy || ge.queue.empty()) continue;
     const auto& head = ge.queue.front();
-    if (sv->budget > 0 && sv->in_use + head->bytes > sv->budget && sv->in_use > 0) continue;
+    if (head->phase != PREPARED || !fits(sv, *head)) continue;
     if (!best || head->ticket < best->ticket) best = head;
   }
   return best;
 }
 
+// The oldest request whose host half has not started.
+std::shared_ptr<Request> pick_prepare(katz_server* sv) {
+  std::shared_ptr<Request> best;
+  for (GraphEntry& ge : sv->graphs)
+    for (const auto& rq : ge.queue)
+      if (rq->phase == QUEUED) {
+        if (!best || rq->ticket < best->ticket) best = rq;
+        break;   // later requests of this graph are younger
+      }
+  return best;
+}
+
+// Completes a request (lock held).
+void finish(katz_server* sv, Request& rq, int status, Clock::time_point t_end) {
+  rq.status = status;
+  rq.latency_ms = std::chrono::duration<double, std::milli>(t_end - rq.arrival).count();
+  rq.phase = DONE;
+  sv->completed++;
+}
+
+// Device half of the request at the head of its idle graph's queue (called
+// with the lock held; returns with it held).
+void run_device_half(katz_server* sv, std::unique_lock<std::mutex>& lk, const std::shared_ptr<Request>& rq,
+                     hipStream_t s) {
+  GraphEntry& ge = sv->graphs[rq->graph];
+  ge.queue.pop_front();
+  ge.busy = true;
+  rq->phase = RUNNING;
+  sv->in_use += rq->bytes;
+  lk.unlock();
+  rq->ids.resize(ge.k);
+  rq->lo.resize(ge.k);
+  rq->up.resize(ge.k);
+  rq->res = katz_result{};
+  rq->res.topk_ids = rq->ids.data();
+  rq->res.lower = rq->lo.data();
+  rq->res.upper = rq->up.data();
+  const auto t0 = Clock::now();
+  int rc = rq->prep_rc;
+  if (rc >= 0) rc = katz::apply_batch(ge.st, rq->pb, &rq->res, s);
+  const auto t1 = Clock::now();
+  rq->pb = katz::PreparedBatch{};
+  lk.lock();
+  rq->service_ms = rq->prepare_ms + std::chrono::duration<double, std::milli>(t1 - t0).count();
+  finish(sv, *rq, rc, t1);
+  ge.busy = false;
+  sv->in_use -= rq->bytes;
+  sv->cv_done.notify_all();
+  sv->cv_work.notify_all();
+}
+
 void worker_main(katz_server* sv, hipStream_t s) {
   (void)hipSetDevice(sv->device);
+  std::unique_lock<std::mutex> lk(sv->mu);
   for (;;) {
-    std::shared_ptr<Request> rq;
-    GraphEntry* gep = nullptr;
-    {
-      std::unique_lock<std::mutex> lk(sv->mu);
-      sv->cv_work.wait(lk, [&] { return sv->stopping || (rq = pick(sv)) != nullptr; });
-      if (!rq) break;
-      gep = &sv->graphs[rq->graph];
-      gep->queue.pop_front();
-      gep->busy = true;
-      sv->in_use += rq->bytes;
+    if (sv->stopping) break;
+    if (auto rq = pick_run(sv)) {
+      run_device_half(sv, lk, rq, s);
+      continue;
     }
-    GraphEntry& ge = *gep;  // st and k never change once registered
-    rq->ids.resize(ge.k);
-    rq->lo.resize(ge.k);
-    rq->up.resize(ge.k);
-    rq->res = katz_result{};
-    rq->res.topk_ids = rq->ids.data();
-    rq->res.lower = rq->lo.data();
-    rq->res.upper = rq->up.data();
-    const auto t0 = Clock::now();
-    const int rc = katz_rank_update(ge.st, rq->iu.data(), rq->iv.data(), (int64_t)rq->iu.size(), rq->du.data(),
-                                    rq->dv.data(), (int64_t)rq->du.size(), &rq->res, s);
-    const auto t1 = Clock::now();
-    {
-      std::lock_guard<std::mutex> lk(sv->mu);
-      rq->status = rc;
-      rq->service_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-      rq->latency_ms = std::chrono::duration<double, std::milli>(t1 - rq->arrival).count();
-      rq->done = true;
-      ge.busy = false;
-      sv->in_use -= rq->bytes;
-      sv->completed++;
+    if (auto rq = pick_prepare(sv)) {
+      rq->phase = PREPARING;
+      const int64_t n = sv->graphs[rq->graph].n;
+      lk.unlock();
+      const auto t0 = Clock::now();
+      const int rc = katz::prepare_batch(n, rq->iu.data(), rq->iv.data(), (int64_t)rq->iu.size(), rq->du.data(),
+                                         rq->dv.data(), (int64_t)rq->du.size(), rq->pb);
+      const auto t1 = Clock::now();
+      lk.lock();
+      // destroy may have cancelled the request meanwhile (phase DONE).
+      if (sv->stopping || rq->phase != PREPARING) break;
+      rq->prepare_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+      rq->prep_rc = rc;
+      rq->phase = PREPARED;
+      sv->cv_work.notify_all();
+      GraphEntry& ge = sv->graphs[rq->graph];
+      if (!ge.busy && !ge.queue.empty() && ge.queue.front() == rq && fits(sv, *rq)) run_device_half(sv, lk, rq, s);
+      continue;
     }
-    sv->cv_done.notify_all();
-    sv->cv_work.notify_all();
+    sv->cv_work.wait(lk);
   }
 }
 
@@ -162,6 +231,7 @@ KATZ_EXPORT int katz_server_add_graph(katz_server* sv, const katz_csr* g, const 
   GraphEntry ge;
   ge.st = st;
   ge.k = p->k;
+  ge.n = katz::state_nodes(st);
   sv->graphs.push_back(std::move(ge));
   *graph_id = (int32_t)sv->graphs.size() - 1;
   return rc;
@@ -178,11 +248,11 @@ KATZ_EXPORT int katz_server_submit(katz_server* sv, int32_t graph_id, const int3
   rq->iv.assign(ins_v, ins_v + n_ins);
   rq->du.assign(del_u, del_u + n_del);
   rq->dv.assign(del_v, del_v + n_del);
-  rq->bytes = estimate_bytes(n_ins + n_del);
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     if (graph_id < 0 || graph_id >= (int32_t)sv->graphs.size() || sv->stopping) return KATZ_E_INVALID_ARG;
     rq->graph = graph_id;
+    rq->bytes = estimate_bytes(n_ins + n_del, sv->graphs[graph_id].n);
     rq->ticket = sv->next_ticket++;
     sv->graphs[graph_id].queue.push_back(rq);
     sv->tickets[rq->ticket] = rq;
@@ -201,8 +271,11 @@ KATZ_EXPORT int katz_server_wait(katz_server* sv, int64_t ticket, katz_result* o
     auto it = sv->tickets.find(ticket);
     if (it == sv->tickets.end()) return KATZ_E_INVALID_ARG;
     rq = it->second;
-    sv->cv_done.wait(lk, [&] { return rq->done; });
-    sv->tickets.erase(it);
+    ++sv->waiters;
+    sv->cv_done.wait(lk, [&] { return rq->phase == DONE; });
+    sv->tickets.erase(ticket);
+    --sv->waiters;
+    sv->cv_done.notify_all();   // destroy may be waiting for the last waiter
   }
   const int k = (int)rq->ids.size();
   if (rq->status >= 0) {
@@ -226,9 +299,22 @@ KATZ_EXPORT void katz_server_destroy(katz_server* sv) {
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->stopping = true;
+    // Requests that have not reached the device end now; a waiter wakes with
+    // E_CANCELLED.  Those on the device finish before the workers stop.
+    const auto now = Clock::now();
+    for (GraphEntry& ge : sv->graphs) {
+      for (auto& rq : ge.queue)
+        if (rq->phase != DONE) finish(sv, *rq, KATZ_E_CANCELLED, now);
+      ge.queue.clear();
+    }
   }
   sv->cv_work.notify_all();
+  sv->cv_done.notify_all();
   for (std::thread& t : sv->workers) t.join();
+  {
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_done.wait(lk, [&] { return sv->waiters == 0; });
+  }
   for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
   for (GraphEntry& ge : sv->graphs) katz_state_free(ge.st);
   delete sv;

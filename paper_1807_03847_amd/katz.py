@@ -29,6 +29,7 @@ E_OOM = -6
 E_HIP = -7
 E_UNSUPPORTED = -8
 E_SCRATCH = -9
+E_CANCELLED = -10
 
 FP64 = 0
 FP32_MARGIN = 1
@@ -58,6 +59,15 @@ class KatzResult(ctypes.Structure):
                 ("separated_fraction", ctypes.c_double)]
 
 
+class KatzSolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("residual", ctypes.c_double),
+                ("alpha_used", ctypes.c_double)]
+
+
+SOLVE_FOSTER, SOLVE_CG = 0, 1
+SOLVE_METHODS = {"foster": SOLVE_FOSTER, "cg": SOLVE_CG}
+
+
 class KatzTuning(ctypes.Structure):
     _fields_ = [("hub_bytes", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("batch_blocks_per_cu", ctypes.c_int32), ("batch_tile", ctypes.c_int32),
@@ -84,6 +94,9 @@ def _load():
     lib.katz_rank_static_noalloc.restype = ctypes.c_int
     lib.katz_rank_static_noalloc.argtypes = [ctypes.POINTER(KatzCSR), ctypes.POINTER(KatzParams),
                                              ctypes.POINTER(KatzResult), vp]
+    lib.katz_solve.restype = ctypes.c_int
+    lib.katz_solve.argtypes = [ctypes.POINTER(KatzCSR), ctypes.POINTER(KatzParams), i32, ctypes.c_double, vp,
+                               ctypes.POINTER(KatzSolveInfo), vp]
     lib.katz_rank_update.restype = ctypes.c_int
     lib.katz_rank_update.argtypes = [vp, vp, vp, i64, vp, vp, i64, ctypes.POINTER(KatzResult), vp]
     lib.katz_bounds.restype = ctypes.c_int
@@ -231,6 +244,24 @@ def rank_static_noalloc(row_ptr, col, k, *, alpha=0.0, eps=0.0, precision="fp64"
     return _to_result(res, ids, lo, up)
 
 
+def solve(row_ptr, col, method="cg", tol=1e-15, *, alpha=0.0, max_iter=0, undirected=True,
+          validate=VALIDATE_BASIC, stream=None, out=None):
+    """katz_solve: Katz scores of every node by Foster's heuristic ("foster")
+    or by conjugate gradients on Eq. (la) ("cg").  Returns (scores, info dict,
+    status)."""
+    device = row_ptr.device
+    g = make_csr(row_ptr, col, undirected)
+    p = make_params(1, alpha, 0.0, "fp64", max_iter, validate)
+    scores = out if out is not None else torch.empty(g.n, dtype=torch.float64, device=device)
+    info = KatzSolveInfo()
+    rc = lib.katz_solve(ctypes.byref(g), ctypes.byref(p), SOLVE_METHODS[method] if isinstance(method, str)
+                        else int(method), float(tol), _ptr(scores), ctypes.byref(info),
+                        _stream_handle(stream, device))
+    if rc < 0:
+        raise KatzError(rc)
+    return scores, {name: getattr(info, name) for name, _ in KatzSolveInfo._fields_}, rc
+
+
 def rank_static_batch(graphs, params, *, stream=None):
     """katz_rank_static with count = len(graphs).
 
@@ -303,12 +334,12 @@ class State:
 
 
 def create_state(row_ptr, col, k, *, alpha=0.0, eps=0.0, max_iter=0, degree_cap=0, validate=VALIDATE_BASIC,
-                 stream=None):
+                 flags=0, stream=None):
     """katz_rank_static with a state: ranks the graph (Algorithm 1, FP64, kept
     walk history) and returns (State, RankResult) for later updates."""
     device = row_ptr.device
     g = make_csr(row_ptr, col, True)
-    p = make_params(k, alpha, eps, "fp64", max_iter, validate, degree_cap)
+    p = make_params(k, alpha, eps, "fp64", max_iter, validate, degree_cap, flags)
     ids, lo, up = _alloc_outputs(k, device)
     res = KatzResult(topk_ids=ids.data_ptr(), lower=lo.data_ptr(), upper=up.data_ptr())
     handle = ctypes.c_void_p(0)

@@ -39,13 +39,15 @@ def test_struct_layout_matches_header():
 #include "katz.h"
 #define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
 int main(void) {
-  printf("katz_csr %zu\nkatz_params %zu\nkatz_result %zu\nkatz_tuning %zu\nkatz_timing %zu\n", sizeof(katz_csr),
-         sizeof(katz_params), sizeof(katz_result), sizeof(katz_tuning), sizeof(katz_timing));
+  printf("katz_csr %zu\nkatz_params %zu\nkatz_result %zu\nkatz_tuning %zu\nkatz_timing %zu\nkatz_solve_info %zu\n",
+         sizeof(katz_csr), sizeof(katz_params), sizeof(katz_result), sizeof(katz_tuning), sizeof(katz_timing),
+         sizeof(katz_solve_info));
   F(katz_csr, col) F(katz_csr, row_ptr_64) F(katz_csr, undirected)
   F(katz_params, k) F(katz_params, precision) F(katz_params, validate) F(katz_params, flags) F(katz_params, degree_cap)
   F(katz_params, criterion) F(katz_params, pair_u) F(katz_params, pair_v)
   F(katz_result, rest_upper_max) F(katz_result, active_final) F(katz_result, iterations) F(katz_result, status)
   F(katz_result, separated_fraction)
+  F(katz_solve_info, converged) F(katz_solve_info, residual) F(katz_solve_info, alpha_used)
   F(katz_tuning, blocks_per_cu) F(katz_tuning, batch_blocks_per_cu) F(katz_tuning, batch_tile)
   F(katz_tuning, batch_xcd) F(katz_tuning, walk_groups) F(katz_tuning, reserved)
   F(katz_timing, prep_ms) F(katz_timing, calls) F(katz_timing, renumber_step_ms) F(katz_timing, renumber_step_launches)
@@ -65,17 +67,19 @@ int main(void) {
     assert int(got["katz_result"]) == ctypes.sizeof(katz.KatzResult)
     assert int(got["katz_tuning"]) == ctypes.sizeof(katz.KatzTuning)
     assert int(got["katz_timing"]) == ctypes.sizeof(katz.KatzTiming)
+    assert int(got["katz_solve_info"]) == ctypes.sizeof(katz.KatzSolveInfo)
     for key, val in got.items():
         if "." in key:
             struct, field = key.split(".")
             cls = {"katz_csr": katz.KatzCSR, "katz_params": katz.KatzParams, "katz_result": katz.KatzResult,
-                   "katz_tuning": katz.KatzTuning, "katz_timing": katz.KatzTiming}[struct]
+                   "katz_tuning": katz.KatzTuning, "katz_timing": katz.KatzTiming,
+                   "katz_solve_info": katz.KatzSolveInfo}[struct]
             assert getattr(cls, field).offset == int(val), key
 
 
 def test_strerror_covers_codes():
     katz = K()
-    for code in range(-9, 4):
+    for code in range(-10, 4):
         assert "unknown" not in katz.strerror(code)
     assert "unknown" in katz.strerror(99)
 
@@ -128,6 +132,17 @@ def test_argument_errors_before_device_work():
     assert katz.lib.katz_bounds(ctypes.byref(g), ctypes.byref(katz.make_params(1)), 0, ctypes.addressof(lo),
                                 ctypes.addressof(lo), None) == katz.E_INVALID_ARG
     assert katz.lib.katz_rank_update(None, None, None, 0, None, None, 0, None, None) == katz.E_INVALID_ARG
+    info = katz.KatzSolveInfo()
+    sc = (ctypes.c_double * 3)()
+    pr = katz.make_params(1)
+    assert katz.lib.katz_solve(ctypes.byref(g), ctypes.byref(pr), 5, 1e-9, ctypes.addressof(sc), ctypes.byref(info),
+                               None) == katz.E_INVALID_ARG                  # unknown method
+    assert katz.lib.katz_solve(ctypes.byref(g), ctypes.byref(pr), 0, 0.0, ctypes.addressof(sc), ctypes.byref(info),
+                               None) == katz.E_INVALID_ARG                  # tol <= 0
+    gd = katz.KatzCSR(n=3, nnz=2, row_ptr=ctypes.addressof(buf), col=ctypes.addressof(col), row_ptr_64=1,
+                      undirected=0)
+    assert katz.lib.katz_solve(ctypes.byref(gd), ctypes.byref(pr), katz.SOLVE_CG, 1e-9, ctypes.addressof(sc),
+                               ctypes.byref(info), None) == katz.E_UNSUPPORTED  # CG needs a symmetric matrix
 
 
 def test_tuning_round_trip_and_limits():

@@ -123,6 +123,150 @@ def test_dynamic_rmat_hubs_and_relocation():
     st.free()
 
 
+def rmat_batch(pool, rng, rp, col, n, size):
+    """One serving-shaped batch: 70% insertions whose endpoints come from the
+    graph's own R-MAT distribution (``pool``, consumed from the front;
+    self-loops, present edges and repeats rejected), 30% deletions of present
+    edges, uniform."""
+    n_del = int(round(0.3 * size))
+    n_ins = size - n_del
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    keys = src * n + col
+    und = np.nonzero(src < col)[0]
+    di = rng.choice(und, size=n_del, replace=False) if n_del else np.zeros(0, np.int64)
+    dels = np.stack([src[di], col[di].astype(np.int64)], 1)
+    ins, seen, used = [], set(), 0
+    while len(ins) < n_ins:
+        a, b = (int(v) for v in pool[used])
+        used += 1
+        a, b = min(a, b), max(a, b)
+        key = a * n + b
+        pos = np.searchsorted(keys, key)
+        if a != b and (a, b) not in seen and not (pos < keys.size and keys[pos] == key):
+            seen.add((a, b))
+            ins.append((a, b))
+    return np.array(ins, dtype=np.int64).reshape(-1, 2), dels, pool[used:]
+
+
+def test_dynamic_rmat18_serving_batches():
+    """R-MAT scale 18 with the serving workload's batches: sizes up to 10^4
+    edges, R-MAT-distributed insertions (hub-heavy), deletions of present
+    edges; each result against the oracle's Algorithm 2 (and its r), and
+    bitwise against katz_bounds on the updated graph.  The large batches take
+    the dense re-walk and relocate hub rows in the slack pool."""
+    katz = K()
+    rng = np.random.default_rng(18)
+    rp, col = sg.rmat(18, seed=5)
+    n = len(rp) - 1
+    dmax = sg.max_degree(rp)
+    H = 20000
+    alpha = 1.0 / (1 + dmax + H)
+    k, eps = 100, 1e-6
+    pool = sg.rmat_pairs(18, 60000, seed=5, stream=11)
+    say("dyn rmat18 create", n, int(rp[-1]))
+    st, res0 = katz.create_state(*dev(rp, col), k, alpha=alpha, eps=eps, degree_cap=dmax + H)
+    dyn = oracle.DynamicOracle(rp, col, alpha, k=k, eps=eps, degree_cap=dmax + H)
+    assert_topk_parity(res0.topk.cpu().numpy(), res0.lower.cpu().numpy(), res0.upper.cpu().numpy(), dyn.result,
+                       gpu_status=res0.status)
+    for b, size in enumerate([1, 3, 40, 700, 10000, 2500]):
+        ins, dels, pool = rmat_batch(pool, rng, dyn.row_ptr, dyn.col, n, size)
+        say("dyn rmat18 batch", b, len(ins), len(dels))
+        res = st.update(ins, dels)
+        orc = dyn.update(ins, dels)
+        assert res.iterations == orc.iterations
+        assert_topk_parity(res.topk.cpu().numpy(), res.lower.cpu().numpy(), res.upper.cpu().numpy(), orc,
+                           gpu_status=res.status)
+        check_against_static(katz, res, dyn.row_ptr, dyn.col, alpha)
+    st.free()
+
+
+def test_node_insertion_and_deletion_through_isolated_padding():
+    """Node insertions and deletions through isolated padding nodes (Section 4:
+    the initial graph carries enough isolated nodes): inserting a node is
+    inserting edges at a padding node, deleting a node is deleting all of its
+    edges.  Each step against the oracle's Algorithm 2, and a deleted node ends
+    with exact zero bounds."""
+    katz = K()
+    rng = np.random.default_rng(4)
+    base_rp, base_col = sg.erdos_renyi(2000, 8000, 12)
+    rp, col = sg.with_isolated(base_rp, base_col, 64)          # nodes 2000..2063: padding
+    n = len(rp) - 1
+    dmax = sg.max_degree(rp)
+    H = 60
+    alpha = 1.0 / (1 + dmax + H)
+    k, eps = 30, 1e-9
+    say("padding create")
+    st, _ = katz.create_state(*dev(rp, col), k, alpha=alpha, eps=eps, degree_cap=dmax + H)
+    dyn = oracle.DynamicOracle(rp, col, alpha, k=k, eps=eps, degree_cap=dmax + H)
+    hub = int(np.argmax(np.diff(rp)))
+    # New nodes 2000 and 2001: 2000 joins ten existing nodes and the hub, 2001
+    # joins 2000 and forty existing nodes (it becomes a high-degree node).
+    nb0 = [int(v) for v in rng.choice(np.setdiff1d(np.arange(2000), [hub]), 10, replace=False)] + [hub]
+    nb1 = [int(v) for v in rng.choice(2000, 40, replace=False)]
+    steps = [(np.array([[min(2000, v), max(2000, v)] for v in nb0]), None),
+             (np.array([[2000, 2001]] + [[v, 2001] for v in nb1]), None)]
+    # Delete node 17: all of its current edges.
+    for ins, dels in steps:
+        say("padding insert", len(ins))
+        res = st.update(ins, dels)
+        orc = dyn.update(ins, dels)
+        assert res.iterations == orc.iterations
+        assert_topk_parity(res.topk.cpu().numpy(), res.lower.cpu().numpy(), res.upper.cpu().numpy(), orc,
+                           gpu_status=res.status)
+    v = 17
+    nbrs = dyn.col[dyn.row_ptr[v]:dyn.row_ptr[v + 1]].astype(np.int64)
+    dels = np.stack([np.minimum(v, nbrs), np.maximum(v, nbrs)], 1)
+    say("padding delete node", v, len(dels))
+    res = st.update(None, dels)
+    orc = dyn.update(None, dels)
+    assert_topk_parity(res.topk.cpu().numpy(), res.lower.cpu().numpy(), res.upper.cpu().numpy(), orc,
+                       gpu_status=res.status)
+    # The isolated node's bounds: zero in a static run on the new graph; the
+    # oracle's delta form keeps only the rounding residue of its updates.
+    assert abs(orc.lower_all[v]) < 1e-15 and abs(orc.upper_all[v]) < 1e-15
+    lo, up = katz.bounds(*dev(dyn.row_ptr, dyn.col), res.iterations, alpha=alpha)
+    assert lo[v].item() == up[v].item() == 0.0
+    st.free()
+
+
+@pytest.mark.parametrize("tuning", [None, (65536, 1, 4), (16384, 4, 0)])
+def test_state_renumbering_is_invisible(tuning):
+    """A state renumbered by degree class (the default) and one in caller order
+    (KATZ_FLAG_NO_REORDER) give bitwise the same results through updates,
+    also under tuned launch shapes whose LDS copy of the hottest entries serves
+    the dense re-walk levels and the resumed iterations."""
+    katz = K()
+    saved = katz.tuning_get()
+    try:
+        if tuning:
+            katz.tuning_set(tuning[0], tuning[1], walk_groups=tuning[2])
+        rng = np.random.default_rng(21)
+        rp, col = sg.rmat(14, seed=8)
+        n = len(rp) - 1
+        dmax = sg.max_degree(rp)
+        H = 3000
+        alpha = 1.0 / (1 + dmax + H)
+        say("state renumbering", tuning)
+        st_a, ra = katz.create_state(*dev(rp, col), 50, alpha=alpha, eps=1e-8, degree_cap=dmax + H)
+        st_b, rb = katz.create_state(*dev(rp, col), 50, alpha=alpha, eps=1e-8, degree_cap=dmax + H,
+                                     flags=katz.FLAG_NO_REORDER)
+        dyn = oracle.DynamicOracle(rp, col, alpha, k=50, eps=1e-8, degree_cap=dmax + H)
+        results = [(ra, rb, dyn.result)]
+        for ni, nd, bias in [(3, 1, 0.5), (200, 50, 0.6), (6000, 2000, 0.3), (1, 0, 0.0)]:
+            ins, dels = random_batch(rng, dyn.row_ptr, dyn.col, n, ni, nd, hub_bias=bias)
+            results.append((st_a.update(ins, dels), st_b.update(ins, dels), dyn.update(ins, dels)))
+        for a, b, orc in results:
+            assert torch.equal(a.topk.cpu(), b.topk.cpu())
+            assert torch.equal(a.lower.cpu(), b.lower.cpu()) and torch.equal(a.upper.cpu(), b.upper.cpu())
+            assert (a.iterations, a.status) == (b.iterations, b.status)
+            assert_topk_parity(a.topk.cpu().numpy(), a.lower.cpu().numpy(), a.upper.cpu().numpy(), orc,
+                               gpu_status=a.status)
+        st_a.free()
+        st_b.free()
+    finally:
+        katz.tuning_set(**saved)
+
+
 def test_dynamic_rejections_leave_state_unchanged():
     katz = K()
     rp, col = sg.erdos_renyi(500, 2000, 9)

@@ -5,7 +5,9 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 import synthgraph as sg
+from tests.parity import assert_topk_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -89,6 +91,16 @@ def test_serving_mix_equals_alone(slots, budget, late_add):
         assert lat >= svc > 0
         mixed[(gi, j)] = res
     sv.close()
+    # Every mixed result against the oracle's Algorithm 2 replaying the same
+    # per-graph request sequence (delta form, FP64 on the host).
+    say("serving oracle")
+    for gi, (rp, col, alpha, cap) in enumerate(graphs):
+        dyn = oracle.DynamicOracle(rp, col, alpha, k=k, eps=eps, degree_cap=cap)
+        for j, (ins, dels) in enumerate(streams[gi]):
+            orc = dyn.update(ins, dels)
+            m = mixed[(gi, j)]
+            assert m.iterations == orc.iterations
+            assert_topk_parity(m.topk, m.lower, m.upper, orc, gpu_status=m.status)
     say("serving alone")
     for gi, (rp, col, alpha, cap) in enumerate(graphs):
         st, _ = katz.create_state(torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda(), k, alpha=alpha,
@@ -115,3 +127,55 @@ def test_serving_reports_errors_per_request():
         sv.wait(t_bad)
     assert e.value.code == katz.E_UPDATE
     sv.close()
+
+
+def test_destroy_cancels_queued_requests():
+    """Destroying a server with requests still queued: threads blocked in
+    wait return (the request ran, or E_CANCELLED), and destroy returns once
+    they have.  A first request of 200000 edges keeps the single slot busy
+    while the others queue."""
+    import threading
+    import time
+    katz = K()
+    rng = np.random.default_rng(5)
+    rp, col = sg.rmat(20, seed=9)
+    dmax = sg.max_degree(rp)
+    n = len(rp) - 1
+    keys = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp)) * n + col
+
+    def fresh_pairs(count):
+        a = rng.integers(0, n, 3 * count)
+        b = rng.integers(0, n, 3 * count)
+        lo, hi = np.minimum(a, b), np.maximum(a, b)
+        k = np.unique(lo * n + hi)
+        pos = np.minimum(np.searchsorted(keys, k), keys.size - 1)
+        k = k[(keys[pos] != k) & (k // n != k % n)]
+        k = rng.permutation(k)[:count]
+        return np.stack([k // n, k % n], 1)
+
+    pairs = fresh_pairs(200000 + 30 * 50)
+    stream = [(pairs[:200000], None)] + [(pairs[200000 + 50 * j:200000 + 50 * (j + 1)], None) for j in range(30)]
+    say("serving destroy")
+    sv = katz.Server(slots=1)
+    gid, _ = sv.add_graph(torch.from_numpy(rp), torch.from_numpy(col), 20, alpha=1.0 / (1 + dmax + 1000),
+                          eps=1e-9, degree_cap=dmax + 1000)
+    tickets = [sv.submit(gid, ins, dels) for ins, dels in stream]
+    codes = {}
+
+    def waiter(t):
+        try:
+            codes[t] = sv.wait(t)[0].status
+        except katz.KatzError as e:
+            codes[t] = e.code
+
+    threads = [threading.Thread(target=waiter, args=(t,)) for t in tickets[-6:]]
+    for th in threads:
+        th.start()
+    time.sleep(0.05)      # the waiters are inside katz_server_wait (no call may start after destroy)
+    sv.close()
+    for th in threads:
+        th.join(timeout=120)
+        assert not th.is_alive()
+    assert set(codes) == set(tickets[-6:])
+    assert all(c in (katz.OK, katz.E_CANCELLED) for c in codes.values())
+    assert katz.E_CANCELLED in codes.values()

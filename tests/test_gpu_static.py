@@ -296,6 +296,23 @@ def test_errors():
     with pytest.raises(katz.KatzError) as e:
         katz.rank_static(*dev(*asym), 1, validate=katz.VALIDATE_STRICT, undirected=True)
     assert e.value.code == katz.E_CSR
+    # Asymmetry inside a row longer than one segment (checked segment by
+    # segment): the hub lists leaf 8500, whose row lacks the hub; and a state
+    # (always strictly checked) refuses the same graph.
+    hub_rp, hub_col = sg.star_graph(9000)
+    keep = np.ones(len(hub_col), bool)
+    keep[int(hub_rp[8500])] = False                 # leaf 8500's only arc, 8500 -> 0
+    arp = hub_rp.copy()
+    arp[8501:] -= 1
+    acol = hub_col[keep]
+    with pytest.raises(katz.KatzError) as e:
+        katz.rank_static(*dev(arp, acol), 1, validate=katz.VALIDATE_STRICT, undirected=True)
+    assert e.value.code == katz.E_CSR
+    with pytest.raises(katz.KatzError) as e:
+        katz.create_state(*dev(arp, acol), 1)
+    assert e.value.code == katz.E_CSR
+    res = katz.rank_static(*dev(hub_rp, hub_col), 1, validate=katz.VALIDATE_STRICT, undirected=True)
+    assert res.status == katz.OK
     # The library still works after errors.
     res = katz.rank_static(*dev(rp, col), 2, eps=1e-9)
     assert res.status == katz.OK
