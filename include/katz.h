@@ -113,6 +113,20 @@ extern "C" {
                                  /* graph sets KATZ_FLAG_REORDER; NO_REORDER on any     */
                                  /* graph of a batch turns it off.                      */
 #define KATZ_FLAG_REORDER     2  /* renumber a batch even where its graphs are small.   */
+#define KATZ_FLAG_INBOUND     4  /* inbound Katz centrality (Section 2.1): count the     */
+                                 /* walks that end at each node.  It equals the         */
+                                 /* outbound centrality of the reverse graph, which the */
+                                 /* library builds on the device (a stable transpose:  */
+                                 /* each reversed row lists its sources in ascending    */
+                                 /* order, so runs stay deterministic) and ranks in     */
+                                 /* place of the graph.  Directed graphs only; on an    */
+                                 /* undirected graph (its own reverse) the flag changes */
+                                 /* nothing.  Offsets and column ids are always checked */
+                                 /* before the transpose.  Taken by single-graph calls, */
+                                 /* katz_bounds, katz_solve and states (update pairs    */
+                                 /* (u, v) still denote the caller's arc u -> v);       */
+                                 /* batches and katz_rank_static_noalloc return         */
+                                 /* E_UNSUPPORTED for it.                               */
 
 /* A graph in compressed sparse row form.  Row v lists the out-neighbours of v:
  * arcs v -> col[j] for row_ptr[v] <= j < row_ptr[v+1].  An undirected graph
@@ -191,8 +205,8 @@ typedef struct katz_state katz_state;
  * k <= 4096 only.
  *
  * states: NULL, or an array of `count` pointers that receives one new
- *         katz_state per graph for later katz_rank_update calls (FP64 only;
- *         free each with katz_state_free).
+ *         katz_state per graph for later katz_rank_update calls (FP64 only,
+ *         undirected or directed; free each with katz_state_free).
  * Errors: E_INVALID_ARG (also: pair ids out of range or equal), E_ALPHA,
  *         E_CSR, E_UNSUPPORTED (a batch or a state with a criterion other than
  *         top-k or k > 4096, FP32 form with states), E_OOM, E_HIP.  With
@@ -203,14 +217,18 @@ int katz_rank_static(int32_t count, const katz_csr* g, const katz_params* p,
                      katz_result* out, katz_state** states, void* stream);
 
 /*
- * katz_rank_update -- Algorithm 2 (Section 4): apply one batch of undirected
- * edge insertions (ins_u[i], ins_v[i]) and deletions (del_u[i], del_v[i]) to the
- * state's graph, recompute the walk counts of every affected node for levels
- * 1..r, patch c_r, recompute the bounds, reactivate nodes whose upper bound
- * reaches min_{x in M} l(x) - eps, and iterate further until converged()
- * holds.  Each pair denotes both arcs.  The batch is atomic: it is validated
- * whole (ids in range, no self-loops, no pair twice, inserted edges absent,
- * deleted edges present, no edge both inserted and deleted, degree cap) and
+ * katz_rank_update -- Algorithm 2 (Section 4): apply one batch of insertions
+ * (ins_u[i], ins_v[i]) and deletions (del_u[i], del_v[i]) to the state's
+ * graph, recompute the walk counts of every affected node for levels 1..r,
+ * patch c_r, recompute the bounds, reactivate nodes whose upper bound reaches
+ * min_{x in M} l(x) - eps, and iterate further until converged() holds.
+ * On an undirected graph each pair is an edge (both arcs); on a directed graph
+ * it is the arc u -> v (the reverse arc is a different arc), and the affected
+ * nodes are found by a search over reverse arcs, which the state keeps as a
+ * second CSR.  An inbound state (KATZ_FLAG_INBOUND) takes the caller's arcs
+ * and stores each as its reverse.  The batch is atomic: it is validated whole
+ * (ids in range, no self-loops, no pair twice, inserted edges or arcs absent,
+ * deleted ones present, none both inserted and deleted, degree cap) and
  * rejected with E_UPDATE / E_DEGREE_CAP before the state changes.
  * The id arrays: host or device; n_ins or n_del may be 0 (arrays then unused).
  * The result has the state's k.  Errors: E_INVALID_ARG, E_UPDATE,
@@ -321,8 +339,8 @@ typedef struct katz_server katz_server;
 
 /* 1 <= slots <= 64.  Errors: E_INVALID_ARG, E_HIP. */
 int katz_server_create(int32_t slots, int64_t memory_budget, katz_server** out);
-/* Ranks g statically (katz_rank_static with a state, FP64, undirected) and
- * registers it; writes its initial result to out and its id to graph_id. */
+/* Ranks g statically (katz_rank_static with a state, FP64; undirected,
+ * directed or inbound) and registers it; writes its initial result to out and its id to graph_id. */
 int katz_server_add_graph(katz_server* sv, const katz_csr* g, const katz_params* p, katz_result* out,
                           int32_t* graph_id);
 /* Queues one batch (arrays are copied before returning) and returns a ticket. */
@@ -370,9 +388,9 @@ int katz_timing_read(katz_timing* out);
 
 /* ---- launch tuning of the walk kernels ------------------------------------
  * Process-wide launch shape of the walk step (the degree-binned SpMV of Eq.
- * (basic_recurrence), Section 3.2).  No setting changes any result bit: every
- * row is still summed by the same lane schedule, and the LDS copy holds exact
- * walk entries.
+ * (basic_recurrence), Section 3.2).  No setting but split_hot_bytes changes
+ * any result bit: every row is still summed by the same lane schedule, and the
+ * LDS copy holds exact walk entries.
  *   hub_bytes            single-graph static calls with the internal
  *                        renumbering: bytes of LDS per workgroup that hold a
  *                        copy of the first walk entries (after the renumbering,
@@ -398,6 +416,19 @@ int katz_timing_read(katz_timing* out);
  *                        hardware places on an XCD take only its graphs' work
  *                        items, so each XCD's L2 holds the walk vectors of an
  *                        eighth of the batch; 0 = any workgroup takes any item.
+ *   split_hot_bytes      single-graph static calls with the internal
+ *                        renumbering, walk steps 3, 4, ...: the walk step runs
+ *                        in two passes, the first summing each row's entries
+ *                        of the hottest nodes (the first split_hot_bytes of
+ *                        the walk vector: a set that stays in an XCD's L2),
+ *                        the second the others and adding the first pass's
+ *                        partial sum (one more rounding level, counted in the
+ *                        FP32 margin).  0 = one pass (default); > 0 = two
+ *                        passes with this hot set (a multiple of 16, at most
+ *                        64 MiB).  The split changes the order of
+ *                        additions, so results differ from one-pass runs in
+ *                        their rounding (both certified); the autotuner leaves
+ *                        it unchanged.
  * Defaults: all 0.  Calls already running keep the setting they started with. */
 typedef struct katz_tuning {
   int32_t hub_bytes;
@@ -406,7 +437,8 @@ typedef struct katz_tuning {
   int32_t batch_tile;
   int32_t batch_xcd;         /* 0 or 1 */
   int32_t walk_groups;       /* 0, 1 or 4 */
-  int32_t reserved[2];       /* must be 0 */
+  int32_t split_hot_bytes;   /* 0, or 16 .. 64 MiB */
+  int32_t reserved;          /* must be 0 */
 } katz_tuning;
 
 /* Copies the current setting; E_INVALID_ARG if t is NULL. */

@@ -27,4 +27,4 @@ Every function is pinned by tests under ``tests/`` (``-m "not gpu"``); none is
 """
 from .katz import (OK, W_ITER_LIMIT, W_PRECISION_LIMIT, W_EXACT_TIES,  # noqa: F401
                    OracleResult, rank_static, bounds, walk_state, DynamicOracle,
-                   UpdateRejected, foster, conjugate_gradient, SolveResult)
+                   UpdateRejected, foster, conjugate_gradient, SolveResult, reverse_graph)

@@ -39,6 +39,24 @@ def walks_bruteforce(row_ptr, col, length):
     return [count(v, length) for v in range(len(rows))]
 
 
+def walks_ending_bruteforce(row_ptr, col, length):
+    """Number of walks with ``length`` arcs that end at each node, by
+    enumerating every walk from every start (inbound walk counts, Section 2.1)."""
+    rows = _rows(row_ptr, col)
+    out = [0] * len(rows)
+
+    def walk(v, remaining):
+        if remaining == 0:
+            out[v] += 1
+            return
+        for x in rows[v]:
+            walk(x, remaining - 1)
+
+    for v in range(len(rows)):
+        walk(v, length)
+    return out
+
+
 def katz_exact(row_ptr, col, alpha):
     """c = alpha A (I - alpha A)^{-1} 1 in rational arithmetic (Eq. (la))."""
     alpha = Fraction(alpha)

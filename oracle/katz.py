@@ -104,6 +104,21 @@ def default_alpha(dmax: int) -> float:
     return 1.0 / (1.0 + dmax)
 
 
+def reverse_graph(row_ptr, col):
+    """The reverse graph (every arc v -> x becomes x -> v) as a CSR whose rows
+    list their sources in ascending order.  Inbound Katz centrality, which
+    counts the walks that end at a node, is the outbound centrality of this
+    graph (Section 2.1)."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    n = len(row_ptr) - 1
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    order = np.lexsort((src, col))           # by target, then by source
+    rt_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rt_ptr, col + 1, 1)
+    return np.cumsum(rt_ptr), src[order].astype(np.int32)
+
+
 def walk_step(A, x_prev, alpha):
     """One application of Eq. (basic_recurrence) in scaled form: alpha * (A x)."""
     return alpha * (A @ x_prev)

@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libkatz.so")
-SOURCES = ["katz_kernels.hip", "katz_select_wg.hip", "katz_criteria.hip", "katz_linear.hip", "katz_dynamic.hip", "katz_batch.hip", "katz_api.hip", "katz_server.hip"]
+SOURCES = ["katz_kernels.hip", "katz_select_wg.hip", "katz_criteria.hip", "katz_linear.hip", "katz_dynamic.hip", "katz_transpose.hip", "katz_batch.hip", "katz_api.hip", "katz_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -88,11 +88,24 @@ struct Arena {
   hipEvent_t last = nullptr;
   hipStream_t last_stream = nullptr;
   bool recorded = false;
+  // Batched calls: the stream their hipGraph replays on, and the instantiated
+  // graph of the last batch with the bytes of every argument it captured (a
+  // call whose arguments are byte-identical replays it without re-capturing).
+  hipStream_t graph_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<unsigned char> graph_key;
 
   ~Arena() {
     if (recorded) (void)hipEventSynchronize(last);
     if (last) (void)hipEventDestroy(last);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph_stream) (void)hipStreamDestroy(graph_stream);
     if (base && !fixed) (void)hipFree(base);
+  }
+  void drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    graph_exec = nullptr;
+    graph_key.clear();
   }
   // A call on stream s that takes over the workspace orders its work after
   // the previous call's.
@@ -127,6 +140,7 @@ struct Arena {
     if (bytes <= cap) return KATZ_OK;
     if (fixed) return KATZ_E_SCRATCH;
     if (recorded) KATZ_HIP(hipEventSynchronize(last));   // a stream-ordered call may still use it
+    drop_graph();                                          // its captured arguments point into the old buffer
     if (base) (void)hipFree(base);
     base = nullptr;
     cap = 0;
@@ -219,8 +233,9 @@ int tuning_valid(const katz_tuning& t) {
   if (t.batch_tile < 0 || t.batch_tile > 16) return KATZ_E_INVALID_ARG;
   if (t.batch_xcd != 0 && t.batch_xcd != 1) return KATZ_E_INVALID_ARG;
   if (t.hub_bytes > 0 && t.blocks_per_cu == 0) return KATZ_E_INVALID_ARG;
-  for (int i = 0; i < 2; ++i)
-    if (t.reserved[i] != 0) return KATZ_E_INVALID_ARG;
+  if (t.split_hot_bytes < 0 || t.split_hot_bytes > (64 << 20) || (t.split_hot_bytes > 0 && (t.split_hot_bytes & 15)))
+    return KATZ_E_INVALID_ARG;
+  if (t.reserved != 0) return KATZ_E_INVALID_ARG;
   return KATZ_OK;
 }
 
@@ -331,7 +346,8 @@ int check_graph(const katz_csr* g) {
 int check_params(const katz_params* p, long long n, bool need_k) {
   if (!p) return KATZ_E_INVALID_ARG;
   if (p->precision != KATZ_FP64 && p->precision != KATZ_FP32_MARGIN) return KATZ_E_INVALID_ARG;
-  if (p->validate < 0 || p->validate > 2 || (p->flags & ~(KATZ_FLAG_NO_REORDER | KATZ_FLAG_REORDER)) || p->max_iter < 0)
+  if (p->validate < 0 || p->validate > 2 ||
+      (p->flags & ~(KATZ_FLAG_NO_REORDER | KATZ_FLAG_REORDER | KATZ_FLAG_INBOUND)) || p->max_iter < 0)
     return KATZ_E_INVALID_ARG;
   if (p->degree_cap < 0) return KATZ_E_INVALID_ARG;
   if (std::isnan(p->alpha) || p->alpha < 0.0 || std::isinf(p->alpha)) return KATZ_E_ALPHA;
@@ -422,6 +438,7 @@ struct Work {
   unsigned long long* sep_count = nullptr;   // separated pairs (ranking and score criteria)
   unsigned long long* sort_key = nullptr;    // device-wide sort of the ranked list
   int32_t* sort_ext = nullptr;
+  void* hot_part = nullptr;                  // two-pass walk step: per-row pass-1 sums
   RunScalars* sc = nullptr;
 };
 
@@ -476,8 +493,10 @@ int reduction_depth(long long dmax) {
 // FP32 form: eta_r bounds the relative error of every entry of x~_r; eta_1 = 0
 // because the first walk step sums exact ones; later steps multiply by (1 + rho),
 // rho = gamma_m = m u / (1 - m u) for the deepest reduction chain m.
-void fp32_tables(Scalars& S, long long dmax, int max_iter) {
-  const int m = reduction_depth(dmax);
+// extra: rounding levels added to every row sum (1 for the two-pass walk step,
+// whose second pass adds the first pass's sum).
+void fp32_tables(Scalars& S, long long dmax, int max_iter, int extra = 0) {
+  const int m = reduction_depth(dmax) + extra;
   S.rho = (m * kU32) / (1.0 - m * kU32) * (1.0 + 0x1p-40);
   S.eta.assign(max_iter + 1, 0.0);
   S.etap.assign(max_iter + 1, 0.0);
@@ -519,6 +538,17 @@ struct katz_state {
   int* row_cap = nullptr;
   int32_t* pool = nullptr;
   long long pool_cap = 0, pool_used = 0;
+  // Directed states: the reverse graph as a second slack CSR (row v lists the
+  // sources of the arcs into v, as stored ids in caller-id order), which
+  // Algorithm 2's breadth-first search follows.  Unused in undirected states,
+  // which are their own reverse.
+  long long* rrow_off = nullptr;
+  int* rrow_len = nullptr;
+  int* rrow_cap = nullptr;
+  int32_t* rpool = nullptr;
+  long long rpool_cap = 0, rpool_used = 0;
+  int directed = 0;   // the graph is directed: lower bound c_r, reverse CSR kept
+  int inbound = 0;    // the state holds (and ranks) the reverse of the caller's graph
   // Internal renumbering (as in static calls): row i of the slack CSR is the
   // caller's node ext_of[i]; entries are internal ids, each row kept in the
   // caller-id order of its entries.  Null: the state is in caller order.
@@ -546,6 +576,7 @@ struct katz_state {
   double* out_lo = nullptr;
   double* out_up = nullptr;
   katz::UpdateBufs ub;
+  katz::UpdateBufs rub;            // the same for the reverse graph of a directed state
   int X_dev_synced = 0;            // entries of X already copied to X_dev
   katz::HostSync hs;
   std::vector<void*> owned;
@@ -605,6 +636,7 @@ struct Run {
   int hub_n = 0;               // walk entries copied to LDS (renumbered static runs)
   long long walk_grid = 0;     // persistent walk grid (0: one workgroup per work item)
   int walk_groups = 1;         // 256-thread groups per walk workgroup (1 or kWalkGroups)
+  int split_n = 0;             // two-pass walk steps: hot entries are ids below split_n (0: one pass)
   // Renumbered static runs: walk step 2 also renames the caller's column ids
   // into col (walk_step<F32, true>).
   bool renumber = false;
@@ -733,6 +765,10 @@ int enqueue_walk(Run& run, int r, hipStream_t s, CallTimer& T) {
   long long tb = 0;
   IterArgs ia = iter_args(run, *run.bins, r, false, tb);
   const bool renum = run.renumber && r == 2;
+  if (run.split_n > 0 && r >= 3) {
+    ia.hot_n = run.split_n;
+    ia.hot_part = run.w->hot_part;
+  }
   if (renum) {
     ia.col_src = run.col_src;
     ia.coff = run.coff;
@@ -912,6 +948,7 @@ struct Plan {
   size_t sort_n;  // records of the device-wide sort of the ranked list (0: none)
   bool check_columns_first = false;   // range-check the column ids during preparation
   int solve_vectors = 0;              // katz_solve: extra n-vectors (FP64) and reduction slots
+  int split_n = 0;                    // two-pass walk steps (hot ids below split_n)
 };
 
 struct Staging {
@@ -971,6 +1008,7 @@ void layout(Arena& ar, const Plan& pl, Bins& b, Work& w, Staging& stg) {
   w.x[1] = ar.take<char>(n * xs);
   w.c = ar.take<double>(n);
   if (pl.fp32) w.e = ar.take<float>(n);
+  if (pl.split_n) w.hot_part = ar.take<char>(n * xs);
   w.partial = ar.take<char>(b.seg_cap * xs);
   w.blkmax = ar.take<double>(n + 2 * b.seg_cap + 16);
   w.xmax32 = ar.take<unsigned>(pl.max_iter + 1);
@@ -1083,6 +1121,16 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
   return KATZ_OK;
 }
 
+// Two-pass walk steps (katz_tuning.split_hot_bytes): hot ids below the
+// returned count; 0 = one pass (the default: on R-MAT 27 the split made the
+// walk step 9-17% slower for hot sets of 1-4 MiB).  Renumbered runs only (the
+// hot nodes are the first ids, the longest rows).
+int split_count(const katz_tuning& tu, const Plan& pl) {
+  if (!pl.reorder || tu.split_hot_bytes <= 0) return 0;
+  const long long xs = pl.fp32 ? 4 : 8;
+  return (int)std::min<long long>(pl.g->n, tu.split_hot_bytes / xs);
+}
+
 int check_rank_args(const katz_csr* g, const katz_params* p, const katz_result* out) {
   KATZ_TRY(check_graph(g));
   KATZ_TRY(check_params(p, g->n, true));
@@ -1110,6 +1158,8 @@ int rank_in_arena(Arena& ar, const katz_csr* g, const katz_params* p, katz_resul
   pl.k = klen;
   pl.out_n = (size_t)klen;
   pl.sort_n = p->criterion == KATZ_SCORE ? (size_t)g->n : klen > kMaxK ? (size_t)klen : 0;
+  const katz_tuning tu = current_tuning();   // one setting for the whole call
+  pl.split_n = split_count(tu, pl);
 
   Bins b;
   Work w;
@@ -1124,7 +1174,7 @@ int rank_in_arena(Arena& ar, const katz_csr* g, const katz_params* p, katz_resul
 
   Scalars S;
   KATZ_TRY(resolve_alpha(p->alpha, b.dmax, S));
-  if (pl.fp32) fp32_tables(S, b.dmax, pl.max_iter);
+  if (pl.fp32) fp32_tables(S, b.dmax, pl.max_iter, pl.split_n > 0 ? 1 : 0);
 
   Run run;
   run.n = g->n;
@@ -1140,12 +1190,10 @@ int rank_in_arena(Arena& ar, const katz_csr* g, const katz_params* p, katz_resul
   run.coff = stg.coff;
   run.pmap = stg.pmap;
   run.ncol = stg.ncol;
-  {
-    const katz_tuning tu = current_tuning();
-    run.walk_grid = (long long)tu.blocks_per_cu * cu_count(dev);
-    run.walk_groups = tu.walk_groups == kWalkGroups ? kWalkGroups : 1;
-    run.hub_n = pl.reorder ? (int)std::min<long long>(g->n, tu.hub_bytes / (pl.fp32 ? 4 : 8)) : 0;
-  }
+  run.walk_grid = (long long)tu.blocks_per_cu * cu_count(dev);
+  run.walk_groups = tu.walk_groups == kWalkGroups ? kWalkGroups : 1;
+  run.hub_n = pl.reorder ? (int)std::min<long long>(g->n, tu.hub_bytes / (pl.fp32 ? 4 : 8)) : 0;
+  run.split_n = pl.split_n;
   run.bins = &b;
   run.w = &w;
   run.S = &S;
@@ -1161,20 +1209,119 @@ int rank_in_arena(Arena& ar, const katz_csr* g, const katz_params* p, katz_resul
   return write_result(run, ar.hs, out, stg.out_ids, stg.out_lo, stg.out_up, s, T);
 }
 
-int rank_one(const katz_csr* g, const katz_params* p, katz_result* out, hipStream_t s) {
-  KATZ_TRY(check_rank_args(g, p, out));
+// ---------------------------------------------------------------------------
+// Inbound form (KATZ_FLAG_INBOUND): inbound Katz centrality of a directed
+// graph is the outbound centrality of its reverse graph (Section 2.1), which
+// the call builds on the device and ranks in place of g.
+// ---------------------------------------------------------------------------
+bool wants_reverse(const katz_csr* g, const katz_params* p) {
+  return (p->flags & KATZ_FLAG_INBOUND) && !g->undirected;
+}
+
+// Checks the offsets and column ids of g (always: the transpose places arcs by
+// them) and writes its reverse graph into `ar`.  gt describes the reverse graph
+// (device memory, int64 offsets); p2 holds the parameters for the run on it
+// (the basic checks are done; strict validation, if asked for, runs on gt,
+// which has the same repeated arcs and self-loops as g).
+int reverse_graph(Arena& ar, const katz_csr* g, const katz_params* p, katz_csr& gt, katz_params& p2, hipStream_t s) {
+  const long long n = g->n, nnz = g->nnz;
+  const bool rp_host = !is_device_ptr(g->row_ptr);
+  const bool col_host = nnz > 0 && !is_device_ptr(g->col);
+  const size_t rp_bytes = (size_t)(n + 1) * (g->row_ptr_64 ? 8 : 4);
+  Bins tmp;
+  bins_caps(tmp, n, nnz);
+  RunScalars* sc = nullptr;
+  long long* blk = nullptr;
+  char* rp_dev = nullptr;
+  int32_t* col_dev = nullptr;
+  long long* rt_ptr = nullptr;
+  int32_t* rt_col = nullptr;
+  char* scratch = nullptr;
+  auto place = [&]() {
+    ar.used = 0;
+    sc = ar.take<RunScalars>(1);
+    blk = ar.take<long long>((size_t)(NUM_BINS + 2) * tmp.nblocks);
+    if (rp_host) rp_dev = ar.take<char>(rp_bytes);
+    if (col_host) col_dev = ar.take<int32_t>(nnz);
+    rt_ptr = ar.take<long long>(n + 1);
+    rt_col = ar.take<int32_t>(std::max<long long>(nnz, 1));
+    scratch = ar.take<char>(transpose_scratch_bytes(n, nnz));
+  };
+  ar.measuring = true;
+  place();
+  ar.measuring = false;
+  KATZ_TRY(ar.grow(ar.used));
+  place();
+  const void* rp = g->row_ptr;
+  const int32_t* col = g->col;
+  if (rp_host) {
+    KATZ_HIP(hipMemcpyAsync(rp_dev, g->row_ptr, rp_bytes, hipMemcpyHostToDevice, s));
+    rp = rp_dev;
+  }
+  if (col_host) {
+    KATZ_HIP(hipMemcpyAsync(col_dev, g->col, (size_t)nnz * 4, hipMemcpyHostToDevice, s));
+    col = col_dev;
+  }
+  KATZ_HIP(launch_reset_flags(sc, s));
+  KATZ_HIP(launch_prep_count(rp, g->row_ptr_64, n, nnz, blk, tmp.nblocks, sc, s));
+  KATZ_HIP(launch_check_col_range(col, nnz, n, sc, s));
+  KATZ_HIP(hipMemcpyAsync(ar.hs.sc, sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+  KATZ_HIP(hipStreamSynchronize(s));
+  if (ar.hs.sc->err) return KATZ_E_CSR;
+  KATZ_HIP(launch_transpose(rp, g->row_ptr_64, col, n, nnz, scratch, rt_ptr, rt_col, s));
+  gt = katz_csr{};
+  gt.n = n;
+  gt.nnz = nnz;
+  gt.row_ptr = rt_ptr;
+  gt.col = rt_col;
+  gt.row_ptr_64 = 1;
+  gt.undirected = 0;
+  p2 = *p;
+  p2.flags &= ~KATZ_FLAG_INBOUND;
+  if (p2.validate == KATZ_VALIDATE_BASIC) p2.validate = KATZ_VALIDATE_NONE;
+  return KATZ_OK;
+}
+
+// body(graph, params) on the reverse graph when the call asks for the inbound
+// form of a directed graph, else on g itself.  The reverse graph's workspace
+// is held until body returns (and ordered after its stream's work).
+template <class F>
+int on_call_graph(const katz_csr* g, const katz_params* p, hipStream_t s, F&& body) {
+  if (!wants_reverse(g, p)) return body(g, p);
   int dev = 0;
   KATZ_HIP(hipGetDevice(&dev));
-  ArenaLease lease(dev, s);
-  KATZ_TRY(lease.rc);
-  return rank_in_arena(*lease.a, g, p, out, s, true);
+  ArenaLease rl(dev, s);
+  KATZ_TRY(rl.rc);
+  katz_csr gt{};
+  katz_params p2{};
+  KATZ_TRY(reverse_graph(*rl.a, g, p, gt, p2, s));
+  return body(&gt, &p2);
 }
+
+int rank_one(const katz_csr* g0, const katz_params* p0, katz_result* out, hipStream_t s) {
+  KATZ_TRY(check_rank_args(g0, p0, out));
+  return on_call_graph(g0, p0, s, [&](const katz_csr* g, const katz_params* p) {
+    int dev = 0;
+    KATZ_HIP(hipGetDevice(&dev));
+    ArenaLease lease(dev, s);
+    KATZ_TRY(lease.rc);
+    return rank_in_arena(*lease.a, g, p, out, s, true);
+  });
+}
+
+int bounds_on(const katz_csr* g, const katz_params* p, int r_target, double* lower, double* upper, hipStream_t s);
 
 int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lower, double* upper,
                hipStream_t s) {
   KATZ_TRY(check_graph(g));
   KATZ_TRY(check_params(p, g->n, false));
   if (r_target < 1 || !lower || !upper) return KATZ_E_INVALID_ARG;
+  return on_call_graph(g, p, s, [&](const katz_csr* g2, const katz_params* p2) {
+    return bounds_on(g2, p2, r_target, lower, upper, s);
+  });
+}
+
+int bounds_on(const katz_csr* g, const katz_params* p, int r_target, double* lower, double* upper, hipStream_t s) {
   int dev = 0;
   KATZ_HIP(hipGetDevice(&dev));
   ArenaLease lease(dev, s);
@@ -1199,6 +1346,8 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   pl.select = false;
   pl.reorder = !(p->flags & KATZ_FLAG_NO_REORDER);
   pl.out_n = (size_t)g->n;
+  const katz_tuning tu = current_tuning();   // one setting for the whole call
+  pl.split_n = split_count(tu, pl);
   Bins b;
   Work w;
   Staging stg;
@@ -1206,7 +1355,7 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   KATZ_TRY(prepare(ar.hs, pl, b, w, stg, s));
   Scalars S;
   KATZ_TRY(resolve_alpha(p->alpha, b.dmax, S));
-  if (pl.fp32) fp32_tables(S, b.dmax, pl.max_iter);
+  if (pl.fp32) fp32_tables(S, b.dmax, pl.max_iter, pl.split_n > 0 ? 1 : 0);
   Run run;
   run.n = g->n;
   run.nnz = g->nnz;
@@ -1221,12 +1370,10 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
   run.coff = stg.coff;
   run.pmap = stg.pmap;
   run.ncol = stg.ncol;
-  {
-    const katz_tuning tu = current_tuning();
-    run.walk_grid = (long long)tu.blocks_per_cu * cu_count(dev);
-    run.walk_groups = tu.walk_groups == kWalkGroups ? kWalkGroups : 1;
-    run.hub_n = pl.reorder ? (int)std::min<long long>(g->n, tu.hub_bytes / (pl.fp32 ? 4 : 8)) : 0;
-  }
+  run.walk_grid = (long long)tu.blocks_per_cu * cu_count(dev);
+  run.walk_groups = tu.walk_groups == kWalkGroups ? kWalkGroups : 1;
+  run.hub_n = pl.reorder ? (int)std::min<long long>(g->n, tu.hub_bytes / (pl.fp32 ? 4 : 8)) : 0;
+  run.split_n = pl.split_n;
   run.bins = &b;
   run.w = &w;
   run.S = &S;
@@ -1273,6 +1420,9 @@ int read_scalar(const double* dev, double* host, hipStream_t s) {
   return KATZ_OK;
 }
 
+int solve_on(const katz_csr* g, const katz_params* p, int method, double tol, double* scores, katz_solve_info* info,
+             hipStream_t s);
+
 int solve_one(const katz_csr* g, const katz_params* p, int method, double tol, double* scores,
               katz_solve_info* info, hipStream_t s) {
   KATZ_TRY(check_graph(g));
@@ -1281,6 +1431,13 @@ int solve_one(const katz_csr* g, const katz_params* p, int method, double tol, d
   if (method != KATZ_SOLVE_FOSTER && method != KATZ_SOLVE_CG) return KATZ_E_INVALID_ARG;
   // CG needs the symmetric matrix of an undirected graph.
   if (method == KATZ_SOLVE_CG && !g->undirected) return KATZ_E_UNSUPPORTED;
+  return on_call_graph(g, p, s, [&](const katz_csr* g2, const katz_params* p2) {
+    return solve_on(g2, p2, method, tol, scores, info, s);
+  });
+}
+
+int solve_on(const katz_csr* g, const katz_params* p, int method, double tol, double* scores, katz_solve_info* info,
+             hipStream_t s) {
   int dev = 0;
   KATZ_HIP(hipGetDevice(&dev));
   ArenaLease lease(dev, s);
@@ -1404,6 +1561,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   int max_iter = 1;
   for (int i = 0; i < count; ++i) {
     if ((p[i].precision == KATZ_FP32_MARGIN) != (fp32 != 0)) return KATZ_E_UNSUPPORTED;
+    if (wants_reverse(&g[i], &p[i])) return KATZ_E_UNSUPPORTED;
     total_n += g[i].n;
     total_nnz += g[i].nnz;
     max_n = std::max<long long>(max_n, g[i].n);
@@ -1716,7 +1874,8 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   T.stop(tp, s);
 
   // ---- the iteration, captured once and replayed ----
-  BatchWalk bw{};
+  BatchWalk bw;
+  std::memset(&bw, 0, sizeof(bw));   // padding too: the bytes key the cached hipGraph
   bw.desc = b.desc;
   bw.segs = b.segs;
   bw.huge = b.huge;
@@ -1790,38 +1949,64 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     if (total_blocks + (nh + kWG / kWave - 1) / (kWG / kWave) > blk_cap) return KATZ_E_HIP;   // sizing bound broken
   }
 
-  hipStream_t cs = nullptr;
-  KATZ_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-  struct StreamGuard {
-    hipStream_t s;
-    hipGraph_t gr = nullptr;
-    hipGraphExec_t ex = nullptr;
-    ~StreamGuard() {
-      if (ex) (void)hipGraphExecDestroy(ex);
-      if (gr) (void)hipGraphDestroy(gr);
-      (void)hipStreamDestroy(s);
-    }
-  } guard{cs};
+  if (!ar.graph_stream) KATZ_HIP(hipStreamCreateWithFlags(&ar.graph_stream, hipStreamNonBlocking));
+  hipStream_t cs = ar.graph_stream;
   KATZ_HIP(launch_batch_item_graphs(bw, total_blocks, item_g, s));
   KATZ_HIP(hipMemsetAsync(n_items, 0, sizeof(int) * kXcds, s));
   KATZ_HIP(hipStreamSynchronize(s));
-  KATZ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  for (int it = 0; it < kItersPerGraph; ++it) {
-    KATZ_HIP(launch_batch_live_items(bw, total_blocks, items, n_items, cs));
-    KATZ_HIP(launch_walk_batch(bw, total_blocks, walk_grid, b.bin_count[BIN_HUGE], cs));
-    KATZ_HIP(launch_select_wg(gsel, count, r_dev, cs));
-    KATZ_HIP(launch_batch_advance(r_dev, count, gsc, gxmax32, gsigma, gsigsum, gexp, galpha, gclog2, stride, fp32,
-                                  ndone, n_items, cs));
+  // The captured launches and every value they take; all pointers lie in this
+  // call's workspace or its per-graph tables, so a batch of the same shape in
+  // the same workspace captures the same bytes.
+  std::vector<unsigned char> key;
+  auto put = [&key](const void* v, size_t bytes) {
+    const unsigned char* c = static_cast<const unsigned char*>(v);
+    key.insert(key.end(), c, c + bytes);
+  };
+  const long long n_huge = b.bin_count[BIN_HUGE];
+  const void* ptrs[] = {gsel, r_dev, gsc, gxmax32, gsigma, gsigsum, gexp, galpha, gclog2, ndone, n_items, items};
+  put(&bw, sizeof(bw));
+  put(ptrs, sizeof(ptrs));
+  put(&count, sizeof(count));
+  put(&stride, sizeof(stride));
+  put(&fp32, sizeof(fp32));
+  put(&total_blocks, sizeof(total_blocks));
+  put(&walk_grid, sizeof(walk_grid));
+  put(&n_huge, sizeof(n_huge));
+  if (!ar.graph_exec || key != ar.graph_key) {
+    ar.drop_graph();
+    hipGraph_t gr = nullptr;
+    KATZ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = hipSuccess;
+    for (int it = 0; it < kItersPerGraph && ce == hipSuccess; ++it) {
+      ce = launch_batch_live_items(bw, total_blocks, items, n_items, cs);
+      if (ce == hipSuccess) ce = launch_walk_batch(bw, total_blocks, walk_grid, n_huge, cs);
+      if (ce == hipSuccess) ce = launch_select_wg(gsel, count, r_dev, cs);
+      if (ce == hipSuccess)
+        ce = launch_batch_advance(r_dev, count, gsc, gxmax32, gsigma, gsigsum, gexp, galpha, gclog2, stride, fp32,
+                                  ndone, n_items, cs);
+    }
+    const hipError_t ee = hipStreamEndCapture(cs, &gr);
+    if (ce != hipSuccess || ee != hipSuccess) {
+      if (gr) (void)hipGraphDestroy(gr);
+      (void)hipGetLastError();
+      return KATZ_E_HIP;
+    }
+    const hipError_t ie = hipGraphInstantiate(&ar.graph_exec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (ie != hipSuccess) {
+      ar.graph_exec = nullptr;
+      (void)hipGetLastError();
+      return KATZ_E_HIP;
+    }
+    ar.graph_key = std::move(key);
   }
-  KATZ_HIP(hipStreamEndCapture(cs, &guard.gr));
-  KATZ_HIP(hipGraphInstantiate(&guard.ex, guard.gr, nullptr, nullptr, 0));
   const int ts = T.start(T_STEP, cs);
   const int max_replays = (max_iter + kItersPerGraph - 1) / kItersPerGraph + 1;
   int replay = 0;
   bool finished = false;
   int* h_done = reinterpret_cast<int*>(ar.hs.bits);
   while (!finished && replay < max_replays) {
-    KATZ_HIP(hipGraphLaunch(guard.ex, cs));
+    KATZ_HIP(hipGraphLaunch(ar.graph_exec, cs));
     KATZ_HIP(hipMemcpyAsync(&h_done[replay & 1], ndone, sizeof(int), hipMemcpyDeviceToHost, cs));
     KATZ_HIP(hipEventRecord(ar.hs.ev[replay & 1], cs));
     if (replay >= 1) {
@@ -1965,7 +2150,7 @@ Run state_run(katz_state* st) {
   Run run;
   run.n = st->n;
   run.nnz = st->nnz;
-  run.undirected = 1;
+  run.undirected = st->directed ? 0 : 1;
   run.fp32 = 0;
   run.validate = 0;
   run.col = st->pool;
@@ -1993,11 +2178,98 @@ Run state_run(katz_state* st) {
 }
 
 // Creates a state from a caller CSR and runs Algorithm 1 on it in history mode.
+// One slack CSR of a state: its graph, or a directed state's reverse graph.
+struct SlackRef {
+  long long*& row_off;
+  int*& row_len;
+  int*& row_cap;
+  int32_t*& pool;
+  long long& pool_cap;
+  long long& pool_used;
+  bool forward;   // the graph the walks read (its pool size sizes the bins)
+};
+
+SlackRef fwd_csr(katz_state* st) {
+  return SlackRef{st->row_off, st->row_len, st->row_cap, st->pool, st->pool_cap, st->pool_used, true};
+}
+
+SlackRef rev_csr(katz_state* st) {
+  return SlackRef{st->rrow_off, st->rrow_len, st->rrow_cap, st->rpool, st->rpool_cap, st->rpool_used, false};
+}
+
+// A slack CSR from a device CSR: per-row capacities with room to grow, their
+// offsets, the rows copied in.
+int build_slack(katz_state* st, SlackRef c, const void* rp, int rp64, const int32_t* col, long long n,
+                hipStream_t s) {
+  c.row_off = dalloc<long long>(st, n);
+  c.row_len = dalloc<int>(st, n);
+  c.row_cap = dalloc<int>(st, n);
+  long long* cap_ll = dalloc<long long>(st, n);
+  long long* sums = dalloc<long long>(st, scan_sums_capacity(n));
+  long long* total = dalloc<long long>(st, 1);
+  if (!c.row_off || !c.row_len || !c.row_cap || !cap_ll || !sums || !total) return KATZ_E_OOM;
+  KATZ_HIP(launch_slack_caps(rp, rp64, n, c.row_len, c.row_cap, cap_ll, s));
+  KATZ_HIP(launch_scan_ll(cap_ll, n, c.row_off, sums, total, s));
+  long long pool_need = 0;
+  KATZ_HIP(hipMemcpyAsync(&pool_need, total, sizeof(long long), hipMemcpyDeviceToHost, s));
+  KATZ_HIP(hipStreamSynchronize(s));
+  dfree(st, cap_ll);
+  dfree(st, sums);
+  dfree(st, total);
+  c.pool_used = pool_need;
+  c.pool_cap = pool_need + pool_need / 8 + 4096;
+  c.pool = dalloc<int32_t>(st, c.pool_cap);
+  if (!c.pool) return KATZ_E_OOM;
+  KATZ_HIP(launch_copy_rows_to_pool(rp, rp64, col, n, c.row_off, c.pool, s));
+  return KATZ_OK;
+}
+
+// Renames a directed state's reverse CSR by the state's renumbering (rows in
+// internal order, entries internal ids kept in caller-id order), as the
+// forward CSR was renamed.
+int rename_slack(katz_state* st, SlackRef c, hipStream_t s) {
+  const long long n = st->n;
+  long long* cap_ll = dalloc<long long>(st, n);
+  long long* sums = dalloc<long long>(st, scan_sums_capacity(n));
+  long long* total = dalloc<long long>(st, 1);
+  long long* off_new = dalloc<long long>(st, n);
+  int* len_new = dalloc<int>(st, n);
+  int* cap_new = dalloc<int>(st, n);
+  if (!cap_ll || !sums || !total || !off_new || !len_new || !cap_new) return KATZ_E_OOM;
+  // The relabelling kernel rewrites ext_of / int_of from the same bins (the
+  // same values) and lists this CSR's capacities in internal order.
+  KATZ_HIP(launch_state_relabel(st->bins.desc, n, c.row_cap, st->ext_of, st->int_of, cap_ll, s));
+  KATZ_HIP(launch_scan_ll(cap_ll, n, off_new, sums, total, s));
+  long long used = 0;
+  KATZ_HIP(hipMemcpyAsync(&used, total, sizeof(long long), hipMemcpyDeviceToHost, s));
+  KATZ_HIP(hipStreamSynchronize(s));
+  const long long cap = used + used / 8 + 4096;
+  int32_t* pool_new = dalloc<int32_t>(st, cap);
+  if (!pool_new) return KATZ_E_OOM;
+  KATZ_HIP(launch_state_rename_rows(st->ext_of, st->int_of, n, c.row_off, c.row_len, c.row_cap, c.pool, off_new,
+                                    len_new, cap_new, pool_new, s));
+  KATZ_HIP(hipStreamSynchronize(s));
+  dfree(st, c.pool);
+  dfree(st, c.row_off);
+  dfree(st, c.row_len);
+  dfree(st, c.row_cap);
+  dfree(st, cap_ll);
+  dfree(st, sums);
+  dfree(st, total);
+  c.pool = pool_new;
+  c.pool_cap = cap;
+  c.pool_used = used;
+  c.row_off = off_new;
+  c.row_len = len_new;
+  c.row_cap = cap_new;
+  return KATZ_OK;
+}
+
 int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz_state** stp, hipStream_t s) {
   KATZ_TRY(check_graph(g));
   KATZ_TRY(check_params(p, g->n, true));
   if (!out || !out->topk_ids || !out->lower || !out->upper) return KATZ_E_INVALID_ARG;
-  if (p->precision != KATZ_FP64 || !g->undirected) return KATZ_E_UNSUPPORTED;
+  if (p->precision != KATZ_FP64) return KATZ_E_UNSUPPORTED;
   int dev = 0;
   KATZ_HIP(hipGetDevice(&dev));
   katz_state* st = new katz_state;
@@ -2011,6 +2283,8 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
   st->device = dev;
   st->n = g->n;
   st->nnz = g->nnz;
+  st->directed = g->undirected ? 0 : 1;
+  st->inbound = wants_reverse(g, p) ? 1 : 0;
   st->eps = p->epsilon;
   st->k = p->k;
   st->max_iter = p->max_iter ? p->max_iter : 1000;
@@ -2054,27 +2328,47 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
     if (st->hs.sc->err) return KATZ_E_CSR;
   }
 
-  // Slack CSR: capacities, offsets, copy.
-  st->row_off = dalloc<long long>(st, n);
-  st->row_len = dalloc<int>(st, n);
-  st->row_cap = dalloc<int>(st, n);
-  long long* cap_ll = dalloc<long long>(st, n);
-  long long* sums = dalloc<long long>(st, scan_sums_capacity(n));
-  long long* total = dalloc<long long>(st, 1);
-  if (!st->row_off || !st->row_len || !st->row_cap || !cap_ll || !sums || !total) return KATZ_E_OOM;
-  KATZ_HIP(launch_slack_caps(rp, g->row_ptr_64, n, st->row_len, st->row_cap, cap_ll, s));
-  KATZ_HIP(launch_scan_ll(cap_ll, n, st->row_off, sums, total, s));
-  long long pool_need = 0;
-  KATZ_HIP(hipMemcpyAsync(&pool_need, total, sizeof(long long), hipMemcpyDeviceToHost, s));
+  // A directed state keeps its graph's reverse for Algorithm 2's search; an
+  // inbound state ranks the reverse of the caller's graph (Section 2.1) and
+  // keeps the caller's graph, rows sorted, as that reverse.  Both come from
+  // the device transpose (reversed rows list their sources in ascending
+  // order): fwd = g or T(g), rev = T(g) or T(T(g)).
+  const void* fwd_rp = rp;
+  int fwd_rp64 = g->row_ptr_64;
+  const int32_t* fwd_col = col;
+  const void* rev_rp = nullptr;
+  const int32_t* rev_col = nullptr;
+  std::vector<void*> temps;
+  if (st->directed) {
+    const long long nnz = g->nnz;
+    char* scratch = dalloc<char>(st, transpose_scratch_bytes(n, nnz));
+    long long* t1_ptr = dalloc<long long>(st, n + 1);
+    int32_t* t1_col = dalloc<int32_t>(st, std::max<long long>(nnz, 1));
+    if (!scratch || !t1_ptr || !t1_col) return KATZ_E_OOM;
+    temps.insert(temps.end(), {scratch, t1_ptr, t1_col});
+    KATZ_HIP(launch_transpose(rp, g->row_ptr_64, col, n, nnz, scratch, t1_ptr, t1_col, s));
+    if (!st->inbound) {
+      rev_rp = t1_ptr;
+      rev_col = t1_col;
+    } else {
+      long long* t2_ptr = dalloc<long long>(st, n + 1);
+      int32_t* t2_col = dalloc<int32_t>(st, std::max<long long>(nnz, 1));
+      if (!t2_ptr || !t2_col) return KATZ_E_OOM;
+      temps.insert(temps.end(), {t2_ptr, t2_col});
+      KATZ_HIP(launch_transpose(t1_ptr, 1, t1_col, n, nnz, scratch, t2_ptr, t2_col, s));
+      fwd_rp = t1_ptr;
+      fwd_rp64 = 1;
+      fwd_col = t1_col;
+      rev_rp = t2_ptr;
+      rev_col = t2_col;
+    }
+  }
+
+  // Slack CSRs: capacities, offsets, copy.
+  KATZ_TRY(build_slack(st, fwd_csr(st), fwd_rp, fwd_rp64, fwd_col, n, s));
+  if (st->directed) KATZ_TRY(build_slack(st, rev_csr(st), rev_rp, 1, rev_col, n, s));
   KATZ_HIP(hipStreamSynchronize(s));
-  dfree(st, cap_ll);
-  dfree(st, sums);
-  dfree(st, total);
-  st->pool_used = pool_need;
-  st->pool_cap = pool_need + pool_need / 8 + 4096;
-  st->pool = dalloc<int32_t>(st, st->pool_cap);
-  if (!st->pool) return KATZ_E_OOM;
-  KATZ_HIP(launch_copy_rows_to_pool(rp, g->row_ptr_64, col, n, st->row_off, st->pool, s));
+  for (void* t : temps) dfree(st, t);
   if (rp_tmp) dfree(st, rp_tmp);
   if (col_tmp) dfree(st, col_tmp);
 
@@ -2083,8 +2377,8 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
   KATZ_TRY(alloc_bins(st, st->lbins));
   KATZ_TRY(bin_rows(st, st->bins, st->w.sc, nullptr, n, s));
   KATZ_HIP(launch_reset_flags(st->w.sc, s));
-  KATZ_HIP(launch_validate_strict(st->bins.desc, n, st->bins.segs, st->bins.seg_total, st->bins.huge, st->pool, 1,
-                                  st->row_off, st->row_len, st->w.sc, s));
+  KATZ_HIP(launch_validate_strict(st->bins.desc, n, st->bins.segs, st->bins.seg_total, st->bins.huge, st->pool,
+                                  st->directed ? 0 : 1, st->row_off, st->row_len, st->w.sc, s));
   KATZ_HIP(hipMemcpyAsync(st->hs.sc, st->w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
   KATZ_HIP(hipStreamSynchronize(s));
   if (st->hs.sc->err) return KATZ_E_CSR;
@@ -2127,6 +2421,7 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
     st->row_off = off_new;
     st->row_len = len_new;
     st->row_cap = cap_new;
+    if (st->directed) KATZ_TRY(rename_slack(st, rev_csr(st), s));
     KATZ_TRY(bin_rows(st, st->bins, st->w.sc, nullptr, n, s));
   }
 
@@ -2224,34 +2519,172 @@ int grow_buf(katz_state* st, T*& p, size_t& cap, size_t count) {
 
 
 // Moves the pool to a larger allocation.
-int grow_pool(katz_state* st, long long need, hipStream_t s) {
-  if (st->pool_used + need <= st->pool_cap) return KATZ_OK;
-  const long long cap = std::max(st->pool_cap * 2, st->pool_used + need + 4096);
+int grow_pool(katz_state* st, SlackRef c, long long need, hipStream_t s) {
+  if (c.pool_used + need <= c.pool_cap) return KATZ_OK;
+  const long long cap = std::max(c.pool_cap * 2, c.pool_used + need + 4096);
   int32_t* np = dalloc<int32_t>(st, cap);
   if (!np) return KATZ_E_OOM;
-  KATZ_HIP(hipMemcpyAsync(np, st->pool, sizeof(int32_t) * st->pool_used, hipMemcpyDeviceToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(np, c.pool, sizeof(int32_t) * c.pool_used, hipMemcpyDeviceToDevice, s));
   KATZ_HIP(hipStreamSynchronize(s));
-  dfree(st, st->pool);
-  st->pool = np;
-  st->pool_cap = cap;
-  KATZ_TRY(alloc_bins(st, st->bins));
-  KATZ_TRY(alloc_bins(st, st->lbins));
-  KATZ_TRY(alloc_partial(st));
+  dfree(st, c.pool);
+  c.pool = np;
+  c.pool_cap = cap;
+  if (c.forward) {
+    KATZ_TRY(alloc_bins(st, st->bins));
+    KATZ_TRY(alloc_bins(st, st->lbins));
+    KATZ_TRY(alloc_partial(st));
+  }
   return KATZ_OK;
+}
+
+// The touched rows of one slack CSR, read before anything changes.
+struct Touched {
+  long long t = 0;
+  std::vector<long long> new_len, offs;
+  std::vector<int> caps;
+};
+
+// Uploads one set of row groups into ub (rows in internal ids) and reads back
+// each touched row's new length, capacity and offset.  The touched rows are
+// left marked in st->tmark.
+int stage_groups(katz_state* st, UpdateBufs& ub, SlackRef c, const RowGroups& g, Touched& tt, hipStream_t s) {
+  const long long t = (long long)g.rows.size();
+  tt.t = t;
+  if (t == 0) return KATZ_OK;
+  KATZ_TRY(grow_buf(st, ub.rows, ub.rows_cap, t));
+  KATZ_TRY(grow_buf(st, ub.ll, ub.ll_cap, 5 * t));
+  KATZ_TRY(grow_buf(st, ub.ints, ub.ints_cap, 5 * t));
+  KATZ_TRY(grow_buf(st, ub.dst, ub.dst_cap, g.ins_dst.size() + g.del_dst.size()));
+  long long* d_ins_off = ub.ll;
+  long long* d_del_off = ub.ll + t;
+  long long* d_new_len = ub.ll + 2 * t;
+  long long* d_offs = ub.ll + 4 * t;
+  int* d_ins_cnt = ub.ints;
+  int* d_del_cnt = ub.ints + t;
+  int* d_delta = ub.ints + 2 * t;
+  int* d_caps = ub.ints + 4 * t;
+  int32_t* d_ins_dst = ub.dst;
+  int32_t* d_del_dst = ub.dst + g.ins_dst.size();
+  KATZ_HIP(hipMemcpyAsync(ub.rows, g.rows.data(), sizeof(int32_t) * t, hipMemcpyHostToDevice, s));
+  if (st->int_of) KATZ_HIP(launch_map_ids(ub.rows, t, st->int_of, s));   // touched rows, internal ids
+  KATZ_HIP(hipMemcpyAsync(d_ins_off, g.ins_off.data(), sizeof(long long) * t, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(d_del_off, g.del_off.data(), sizeof(long long) * t, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(d_ins_cnt, g.ins_cnt.data(), sizeof(int) * t, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(d_del_cnt, g.del_cnt.data(), sizeof(int) * t, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(d_delta, g.delta.data(), sizeof(int) * t, hipMemcpyHostToDevice, s));
+  if (!g.ins_dst.empty())
+    KATZ_HIP(hipMemcpyAsync(d_ins_dst, g.ins_dst.data(), sizeof(int32_t) * g.ins_dst.size(), hipMemcpyHostToDevice,
+                            s));
+  if (!g.del_dst.empty())
+    KATZ_HIP(hipMemcpyAsync(d_del_dst, g.del_dst.data(), sizeof(int32_t) * g.del_dst.size(), hipMemcpyHostToDevice,
+                            s));
+  KATZ_HIP(launch_touched_lengths(ub.rows, t, d_delta, c.row_len, d_new_len, st->tmark, s));
+  KATZ_HIP(launch_gather_int(ub.rows, t, c.row_cap, d_caps, s));
+  KATZ_HIP(launch_gather_ll(ub.rows, t, c.row_off, d_offs, s));
+  tt.new_len.resize(t);
+  tt.caps.resize(t);
+  tt.offs.resize(t);
+  KATZ_HIP(hipMemcpyAsync(tt.new_len.data(), d_new_len, sizeof(long long) * t, hipMemcpyDeviceToHost, s));
+  KATZ_HIP(hipMemcpyAsync(tt.caps.data(), d_caps, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+  KATZ_HIP(hipMemcpyAsync(tt.offs.data(), d_offs, sizeof(long long) * t, hipMemcpyDeviceToHost, s));
+  KATZ_HIP(hipStreamSynchronize(s));
+  return KATZ_OK;
+}
+
+// Pool entries the touched rows that outgrow their capacity will take.
+long long growth_need(const Touched& tt) {
+  long long need = 0;
+  for (long long i = 0; i < tt.t; ++i)
+    if (tt.new_len[i] > tt.caps[i]) need += slack_cap_host(tt.new_len[i]);
+  return need;
+}
+
+// Merges every touched row (old row without the deletions, with the
+// insertions, in caller-id order) into scratch, then places it in place when
+// it fits its capacity, else in a fresh region at the pool's end (the pool
+// has grown already).  ub holds what stage_groups uploaded.
+int merge_groups(katz_state* st, UpdateBufs& ub, SlackRef c, const RowGroups& g, const Touched& tt, hipStream_t s) {
+  const long long t = tt.t;
+  if (t == 0) return KATZ_OK;
+  std::vector<long long> sbase(t), dest_off(t);
+  std::vector<int> dest_cap(t);
+  long long scratch_total = 0;
+  for (long long i = 0; i < t; ++i) {
+    sbase[i] = scratch_total;
+    scratch_total += tt.new_len[i];
+    if (tt.new_len[i] <= tt.caps[i]) {
+      dest_off[i] = tt.offs[i];
+      dest_cap[i] = tt.caps[i];
+    } else {
+      dest_cap[i] = (int)slack_cap_host(tt.new_len[i]);
+      dest_off[i] = c.pool_used;
+      c.pool_used += dest_cap[i];
+    }
+  }
+  KATZ_TRY(grow_buf(st, ub.scratch, ub.scratch_cap, (size_t)scratch_total));
+  long long* d_ins_off = ub.ll;
+  long long* d_del_off = ub.ll + t;
+  long long* d_new_len = ub.ll + 2 * t;
+  long long* d_sbase = ub.ll + 3 * t;
+  long long* d_dest_off = ub.ll + 4 * t;
+  int* d_ins_cnt = ub.ints;
+  int* d_del_cnt = ub.ints + t;
+  int* d_dest_cap = ub.ints + 3 * t;
+  int32_t* d_ins_dst = ub.dst;
+  int32_t* d_del_dst = ub.dst + g.ins_dst.size();
+  KATZ_HIP(hipMemcpyAsync(d_sbase, sbase.data(), sizeof(long long) * t, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(d_dest_off, dest_off.data(), sizeof(long long) * t, hipMemcpyHostToDevice, s));
+  KATZ_HIP(hipMemcpyAsync(d_dest_cap, dest_cap.data(), sizeof(int) * t, hipMemcpyHostToDevice, s));
+  KATZ_HIP(launch_merge_rows(ub.rows, t, d_ins_off, d_ins_cnt, d_ins_dst, d_del_off, d_del_cnt, d_del_dst, d_sbase,
+                             c.row_off, c.row_len, c.pool, st->ext_of, st->int_of, ub.scratch, s));
+  KATZ_HIP(launch_copy_back_rows(ub.rows, t, d_sbase, d_new_len, d_dest_off, d_dest_cap, ub.scratch, c.row_off,
+                                 c.row_len, c.row_cap, c.pool, s));
+  // The host vectors above are read by the copies: wait before they go.
+  KATZ_HIP(hipStreamSynchronize(s));
+  return KATZ_OK;
+}
+
+// Arcs grouped by the row that stores them (sorted by row, then entry).
+void group_arcs(std::vector<Arc>& ia, std::vector<Arc>& da, RowGroups& g) {
+  std::sort(ia.begin(), ia.end());
+  std::sort(da.begin(), da.end());
+  std::vector<int32_t>& rows = g.rows;
+  for (const Arc& a : ia) rows.push_back(a.src);
+  for (const Arc& a : da) rows.push_back(a.src);
+  std::sort(rows.begin(), rows.end());
+  rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+  const long long t = (long long)rows.size();
+  g.ins_off.assign(t, 0);
+  g.del_off.assign(t, 0);
+  g.ins_cnt.assign(t, 0);
+  g.del_cnt.assign(t, 0);
+  g.delta.assign(t, 0);
+  size_t pi = 0, pd = 0;
+  for (long long i = 0; i < t; ++i) {
+    g.ins_off[i] = (long long)g.ins_dst.size();
+    while (pi < ia.size() && ia[pi].src == rows[i]) g.ins_dst.push_back(ia[pi++].dst);
+    g.ins_cnt[i] = (int)(g.ins_dst.size() - g.ins_off[i]);
+    g.del_off[i] = (long long)g.del_dst.size();
+    while (pd < da.size() && da[pd].src == rows[i]) g.del_dst.push_back(da[pd++].dst);
+    g.del_cnt[i] = (int)(g.del_dst.size() - g.del_off[i]);
+    g.delta[i] = g.ins_cnt[i] - g.del_cnt[i];
+  }
 }
 
 }  // namespace
 
 // Host-side half of an update: the batch on its own (ids, loops, repeats,
-// I n D) and its arcs grouped by source row.  It reads no graph state, so a
+// I n D) and its arcs grouped by stored row.  It reads no graph state, so a
 // server may prepare a request while an earlier request of the same graph is
 // still running.
-int prepare_batch(long long n, const int32_t* ins_u, const int32_t* ins_v, long long n_ins, const int32_t* del_u,
-                  const int32_t* del_v, long long n_del, PreparedBatch& pb) {
+int prepare_batch(long long n, int mode, const int32_t* ins_u, const int32_t* ins_v, long long n_ins,
+                  const int32_t* del_u, const int32_t* del_v, long long n_del, PreparedBatch& pb) {
   if (n_ins < 0 || n_del < 0) return KATZ_E_INVALID_ARG;
+  if (mode < PAIRS_UNDIRECTED || mode > PAIRS_REVERSED) return KATZ_E_INVALID_ARG;
   if ((n_ins > 0 && (!ins_u || !ins_v)) || (n_del > 0 && (!del_u || !del_v))) return KATZ_E_INVALID_ARG;
   pb = PreparedBatch{};
   pb.n = n;
+  pb.mode = mode;
   pb.n_ins = n_ins;
   pb.n_del = n_del;
   std::vector<int32_t> iu, iv, du, dv;
@@ -2259,16 +2692,26 @@ int prepare_batch(long long n, const int32_t* ins_u, const int32_t* ins_v, long 
   KATZ_TRY(fetch_ids(ins_v, n_ins, iv));
   KATZ_TRY(fetch_ids(del_u, n_del, du));
   KATZ_TRY(fetch_ids(del_v, n_del, dv));
+  // An inbound state stores the caller's arc u -> v as v -> u.
+  if (mode == PAIRS_REVERSED) {
+    std::swap(iu, iv);
+    std::swap(du, dv);
+  }
+  const bool und = mode == PAIRS_UNDIRECTED;
+  // Keys of the stored arcs (an undirected edge by its ordered ends).
+  auto key = [&](int32_t a, int32_t b) {
+    return und ? (long long)std::min(a, b) * n + std::max(a, b) : (long long)a * n + b;
+  };
   std::vector<long long> ki, kd;
   ki.reserve(n_ins);
   kd.reserve(n_del);
   for (long long j = 0; j < n_ins; ++j) {
     if (iu[j] < 0 || iu[j] >= n || iv[j] < 0 || iv[j] >= n || iu[j] == iv[j]) return KATZ_E_UPDATE;
-    ki.push_back((long long)std::min(iu[j], iv[j]) * n + std::max(iu[j], iv[j]));
+    ki.push_back(key(iu[j], iv[j]));
   }
   for (long long j = 0; j < n_del; ++j) {
     if (du[j] < 0 || du[j] >= n || dv[j] < 0 || dv[j] >= n || du[j] == dv[j]) return KATZ_E_UPDATE;
-    kd.push_back((long long)std::min(du[j], dv[j]) * n + std::max(du[j], dv[j]));
+    kd.push_back(key(du[j], dv[j]));
   }
   std::sort(ki.begin(), ki.end());
   std::sort(kd.begin(), kd.end());
@@ -2279,7 +2722,8 @@ int prepare_batch(long long n, const int32_t* ins_u, const int32_t* ins_v, long 
     std::set_intersection(ki.begin(), ki.end(), kd.begin(), kd.end(), std::back_inserter(both));
     if (!both.empty()) return KATZ_E_UPDATE;
   }
-  // Pairs for the existence check: a-ends then b-ends, insertions first.
+  // Arcs for the existence check: a-ends then b-ends, insertions first (an
+  // undirected edge is checked by one of its arcs).
   const long long np = n_ins + n_del;
   pb.pa.resize(2 * np);
   for (long long j = 0; j < n_ins; ++j) {
@@ -2290,42 +2734,28 @@ int prepare_batch(long long n, const int32_t* ins_u, const int32_t* ins_v, long 
     pb.pa[n_ins + j] = du[j];
     pb.pa[np + n_ins + j] = dv[j];
   }
-  // Arcs grouped by source row (both arcs of every pair).
-  std::vector<Arc> ia, da;
+  // Stored arcs by source row; a directed state also keeps the reverse arcs by
+  // target row (its reverse graph).
+  std::vector<Arc> ia, da, ra, rd;
   ia.reserve(2 * n_ins);
   da.reserve(2 * n_del);
   for (long long j = 0; j < n_ins; ++j) {
     ia.push_back({iu[j], iv[j]});
-    ia.push_back({iv[j], iu[j]});
+    if (und) ia.push_back({iv[j], iu[j]});
+    else ra.push_back({iv[j], iu[j]});
   }
   for (long long j = 0; j < n_del; ++j) {
     da.push_back({du[j], dv[j]});
-    da.push_back({dv[j], du[j]});
+    if (und) da.push_back({dv[j], du[j]});
+    else rd.push_back({dv[j], du[j]});
   }
-  std::sort(ia.begin(), ia.end());
-  std::sort(da.begin(), da.end());
-  std::vector<int32_t>& trows = pb.trows;
-  for (const Arc& a : ia) trows.push_back(a.src);
-  for (const Arc& a : da) trows.push_back(a.src);
-  std::sort(trows.begin(), trows.end());
-  trows.erase(std::unique(trows.begin(), trows.end()), trows.end());
-  const long long t = (long long)trows.size();
-  pb.ins_off.assign(t, 0);
-  pb.del_off.assign(t, 0);
-  pb.ins_cnt.assign(t, 0);
-  pb.del_cnt.assign(t, 0);
-  pb.delta.assign(t, 0);
-  size_t pi = 0, pd = 0;
-  for (long long i = 0; i < t; ++i) {
-    pb.ins_off[i] = (long long)pb.ins_dst.size();
-    while (pi < ia.size() && ia[pi].src == trows[i]) pb.ins_dst.push_back(ia[pi++].dst);
-    pb.ins_cnt[i] = (int)(pb.ins_dst.size() - pb.ins_off[i]);
-    pb.del_off[i] = (long long)pb.del_dst.size();
-    while (pd < da.size() && da[pd].src == trows[i]) pb.del_dst.push_back(da[pd++].dst);
-    pb.del_cnt[i] = (int)(pb.del_dst.size() - pb.del_off[i]);
-    pb.delta[i] = pb.ins_cnt[i] - pb.del_cnt[i];
-  }
+  group_arcs(ia, da, pb.fwd);
+  if (!und) group_arcs(ra, rd, pb.rev);
   return KATZ_OK;
+}
+
+int state_pair_mode(const katz_state* st) {
+  return !st->directed ? PAIRS_UNDIRECTED : (st->inbound ? PAIRS_REVERSED : PAIRS_DIRECTED);
 }
 
 long long state_nodes(const katz_state* st) { return st->n; }
@@ -2334,7 +2764,7 @@ long long state_nodes(const katz_state* st) { return st->n; }
 // the merge into the slack CSR, the re-walk and the re-certification.
 int apply_batch(katz_state* st, const PreparedBatch& pb, katz_result* out, hipStream_t s) {
   if (!out || !out->topk_ids || !out->lower || !out->upper) return KATZ_E_INVALID_ARG;
-  if (pb.n != st->n) return KATZ_E_INVALID_ARG;
+  if (pb.n != st->n || pb.mode != state_pair_mode(st)) return KATZ_E_INVALID_ARG;
   const long long n = st->n;
   const long long n_ins = pb.n_ins, n_del = pb.n_del;
   UpdateBufs& ub = st->ub;
@@ -2352,106 +2782,45 @@ int apply_batch(katz_state* st, const PreparedBatch& pb, katz_result* out, hipSt
     KATZ_HIP(hipStreamSynchronize(s));
     if (err) return KATZ_E_UPDATE;
   }
-  const std::vector<int32_t>& trows = pb.trows;
-  const std::vector<long long>& ins_off = pb.ins_off;
-  const std::vector<long long>& del_off = pb.del_off;
-  const std::vector<int>& ins_cnt = pb.ins_cnt;
-  const std::vector<int>& del_cnt = pb.del_cnt;
-  const std::vector<int>& delta = pb.delta;
-  const std::vector<int32_t>& ins_dst = pb.ins_dst;
-  const std::vector<int32_t>& del_dst = pb.del_dst;
-  const long long t = (long long)trows.size();
+  const long long t = (long long)pb.fwd.rows.size();
 
   CallTimer T;
   T.call_begin(s);
   Run run = state_run(st);
   int new_dmax = st->bins.dmax;
-  std::vector<long long> new_len(t);
   if (t > 0) {
     // ---- candidate degrees and the degree cap (Theorem 1 needs alpha d < 1) ----
-    KATZ_TRY(grow_buf(st, ub.rows, ub.rows_cap, t));
-    KATZ_TRY(grow_buf(st, ub.ll, ub.ll_cap, 5 * t));
-    KATZ_TRY(grow_buf(st, ub.ints, ub.ints_cap, 5 * t));
-    KATZ_TRY(grow_buf(st, ub.dst, ub.dst_cap, ins_dst.size() + del_dst.size()));
-    long long* d_ins_off = ub.ll;
-    long long* d_del_off = ub.ll + t;
-    long long* d_new_len = ub.ll + 2 * t;
-    long long* d_sbase = ub.ll + 3 * t;
-    long long* d_dest_off = ub.ll + 4 * t;
-    int* d_ins_cnt = ub.ints;
-    int* d_del_cnt = ub.ints + t;
-    int* d_delta = ub.ints + 2 * t;
-    int* d_dest_cap = ub.ints + 3 * t;
-    int* d_caps = ub.ints + 4 * t;
-    int32_t* d_ins_dst = ub.dst;
-    int32_t* d_del_dst = ub.dst + ins_dst.size();
-    KATZ_HIP(hipMemcpyAsync(ub.rows, trows.data(), sizeof(int32_t) * t, hipMemcpyHostToDevice, s));
-    if (st->int_of) KATZ_HIP(launch_map_ids(ub.rows, t, st->int_of, s));   // touched rows, internal ids
-    KATZ_HIP(hipMemcpyAsync(d_ins_off, ins_off.data(), sizeof(long long) * t, hipMemcpyHostToDevice, s));
-    KATZ_HIP(hipMemcpyAsync(d_del_off, del_off.data(), sizeof(long long) * t, hipMemcpyHostToDevice, s));
-    KATZ_HIP(hipMemcpyAsync(d_ins_cnt, ins_cnt.data(), sizeof(int) * t, hipMemcpyHostToDevice, s));
-    KATZ_HIP(hipMemcpyAsync(d_del_cnt, del_cnt.data(), sizeof(int) * t, hipMemcpyHostToDevice, s));
-    KATZ_HIP(hipMemcpyAsync(d_delta, delta.data(), sizeof(int) * t, hipMemcpyHostToDevice, s));
-    if (!ins_dst.empty())
-      KATZ_HIP(hipMemcpyAsync(d_ins_dst, ins_dst.data(), sizeof(int32_t) * ins_dst.size(), hipMemcpyHostToDevice, s));
-    if (!del_dst.empty())
-      KATZ_HIP(hipMemcpyAsync(d_del_dst, del_dst.data(), sizeof(int32_t) * del_dst.size(), hipMemcpyHostToDevice, s));
-    KATZ_HIP(launch_touched_lengths(ub.rows, t, d_delta, st->row_len, d_new_len, st->tmark, s));
-    KATZ_HIP(launch_gather_int(ub.rows, t, st->row_cap, d_caps, s));
-    std::vector<int> caps(t);
-    std::vector<long long> offs(t);
-    KATZ_HIP(launch_gather_ll(ub.rows, t, st->row_off, d_dest_off, s));
-    KATZ_HIP(hipMemcpyAsync(new_len.data(), d_new_len, sizeof(long long) * t, hipMemcpyDeviceToHost, s));
-    KATZ_HIP(hipMemcpyAsync(caps.data(), d_caps, sizeof(int) * t, hipMemcpyDeviceToHost, s));
-    KATZ_HIP(hipMemcpyAsync(offs.data(), d_dest_off, sizeof(long long) * t, hipMemcpyDeviceToHost, s));
-    KATZ_HIP(hipStreamSynchronize(s));
+    Touched ft, rt;
+    KATZ_TRY(stage_groups(st, ub, fwd_csr(st), pb.fwd, ft, s));
     // The new deg_max: the old one raised by the touched rows, unless a row of
     // the old maximum length shrank, when every untouched row is scanned too.
     bool shrank_max = false;
     new_dmax = st->bins.dmax;
     for (long long i = 0; i < t; ++i) {
-      const long long old_len = new_len[i] - delta[i];
-      if (old_len == st->bins.dmax && new_len[i] < old_len) shrank_max = true;
-      new_dmax = (int)std::max<long long>(new_dmax, new_len[i]);
+      const long long old_len = ft.new_len[i] - pb.fwd.delta[i];
+      if (old_len == st->bins.dmax && ft.new_len[i] < old_len) shrank_max = true;
+      new_dmax = (int)std::max<long long>(new_dmax, ft.new_len[i]);
     }
     if (shrank_max) {
       KATZ_HIP(hipMemsetAsync(st->dmax_dev, 0, sizeof(int), s));
-      KATZ_HIP(launch_max_len_after(st->row_len, st->tmark, n, d_new_len, t, st->dmax_dev, s));
+      KATZ_HIP(launch_max_len_after(st->row_len, st->tmark, n, ub.ll + 2 * t, t, st->dmax_dev, s));
       KATZ_HIP(hipMemcpyAsync(&new_dmax, st->dmax_dev, sizeof(int), hipMemcpyDeviceToHost, s));
     }
     KATZ_HIP(launch_unmark_rows(ub.rows, t, st->tmark, s));
     KATZ_HIP(hipStreamSynchronize(s));
     if (!(st->alpha * (double)new_dmax < 1.0) || new_dmax > st->degree_cap) return KATZ_E_DEGREE_CAP;
+    if (st->directed) {
+      KATZ_TRY(stage_groups(st, st->rub, rev_csr(st), pb.rev, rt, s));
+      if (rt.t) KATZ_HIP(launch_unmark_rows(st->rub.rows, rt.t, st->tmark, s));
+    }
 
-    // ---- apply: merge every touched row into scratch, then place it ----
-    std::vector<long long> sbase(t), dest_off(t);
-    std::vector<int> dest_cap(t);
-    long long scratch_total = 0, grow_need = 0;
-    for (long long i = 0; i < t; ++i) {
-      sbase[i] = scratch_total;
-      scratch_total += new_len[i];
-      if (new_len[i] > caps[i]) grow_need += slack_cap_host(new_len[i]);
-    }
-    KATZ_TRY(grow_pool(st, grow_need, s));
-    for (long long i = 0; i < t; ++i) {
-      if (new_len[i] <= caps[i]) {
-        dest_off[i] = offs[i];
-        dest_cap[i] = caps[i];
-      } else {
-        dest_cap[i] = (int)slack_cap_host(new_len[i]);
-        dest_off[i] = st->pool_used;
-        st->pool_used += dest_cap[i];
-      }
-    }
-    KATZ_TRY(grow_buf(st, ub.scratch, ub.scratch_cap, (size_t)scratch_total));
-    KATZ_HIP(hipMemcpyAsync(d_sbase, sbase.data(), sizeof(long long) * t, hipMemcpyHostToDevice, s));
-    KATZ_HIP(hipMemcpyAsync(d_dest_off, dest_off.data(), sizeof(long long) * t, hipMemcpyHostToDevice, s));
-    KATZ_HIP(hipMemcpyAsync(d_dest_cap, dest_cap.data(), sizeof(int) * t, hipMemcpyHostToDevice, s));
-    KATZ_HIP(launch_merge_rows(ub.rows, t, d_ins_off, d_ins_cnt, d_ins_dst, d_del_off, d_del_cnt, d_del_dst, d_sbase,
-                               st->row_off, st->row_len, st->pool, st->ext_of, st->int_of, ub.scratch, s));
-    KATZ_HIP(launch_copy_back_rows(ub.rows, t, d_sbase, d_new_len, d_dest_off, d_dest_cap, ub.scratch, st->row_off,
-                                   st->row_len, st->row_cap, st->pool, s));
-    st->nnz += 2 * (n_ins - n_del);
+    // ---- apply: pools grown first (a failed allocation leaves the state as
+    // it was), then every touched row merged into scratch and placed ----
+    KATZ_TRY(grow_pool(st, fwd_csr(st), growth_need(ft), s));
+    if (st->directed) KATZ_TRY(grow_pool(st, rev_csr(st), growth_need(rt), s));
+    KATZ_TRY(merge_groups(st, ub, fwd_csr(st), pb.fwd, ft, s));
+    if (st->directed) KATZ_TRY(merge_groups(st, st->rub, rev_csr(st), pb.rev, rt, s));
+    st->nnz += (st->directed ? 1 : 2) * (n_ins - n_del);
 
     // ---- bins of the new graph: rebuilt before the next whole-graph walk ----
     run = state_run(st);
@@ -2479,7 +2848,9 @@ int apply_batch(katz_state* st, const PreparedBatch& pb, katz_result* out, hipSt
         // C_i = C_{i-1} u in-neighbours(F_{i-1}); F_{i-1} = C[fbeg .. csize).
         KATZ_HIP(hipMemcpyAsync(st->counter, &csize, sizeof(int), hipMemcpyHostToDevice, s));
         KATZ_HIP(hipMemsetAsync(st->frontier_arcs, 0, sizeof(unsigned long long), s));
-        KATZ_HIP(launch_frontier_expand(st->clist + fbeg, csize - fbeg, st->row_off, st->row_len, st->pool,
+        // In-neighbours: the reverse graph's rows (an undirected graph's own).
+        const SlackRef in = st->directed ? rev_csr(st) : fwd_csr(st);
+        KATZ_HIP(launch_frontier_expand(st->clist + fbeg, csize - fbeg, in.row_off, in.row_len, in.pool,
                                         st->level_of, i, st->clist, st->counter, st->frontier_arcs, s));
         int c2 = 0;
         KATZ_HIP(hipMemcpyAsync(&c2, st->counter, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -2534,7 +2905,7 @@ int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, lon
                  const int32_t* del_v, long long n_del, katz_result* out, hipStream_t s) {
   if (!out || !out->topk_ids || !out->lower || !out->upper) return KATZ_E_INVALID_ARG;
   PreparedBatch pb;
-  KATZ_TRY(prepare_batch(st->n, ins_u, ins_v, n_ins, del_u, del_v, n_del, pb));
+  KATZ_TRY(prepare_batch(st->n, state_pair_mode(st), ins_u, ins_v, n_ins, del_u, del_v, n_del, pb));
   return apply_batch(st, pb, out, s);
 }
 
@@ -2584,6 +2955,7 @@ ScratchSlot* scratch_slot(int dev) {
 
 int rank_noalloc(const katz_csr* g, const katz_params* p, katz_result* out, hipStream_t s) {
   KATZ_TRY(check_rank_args(g, p, out));
+  if (wants_reverse(g, p)) return KATZ_E_UNSUPPORTED;   // the reverse graph needs its own workspace
   int dev = 0;
   KATZ_HIP(hipGetDevice(&dev));
   ScratchSlot* sl = scratch_slot(dev);
@@ -2617,7 +2989,7 @@ KATZ_EXPORT int katz_rank_static(int32_t count, const katz_csr* g, const katz_pa
     int rc = katz::check_graph(&g[i]);
     if (!rc) rc = katz::check_params(&p[i], g[i].n, true);
     if (!rc && (!out[i].topk_ids || !out[i].lower || !out[i].upper)) rc = KATZ_E_INVALID_ARG;
-    if (!rc && states && (p[i].precision != KATZ_FP64 || !g[i].undirected)) rc = KATZ_E_UNSUPPORTED;
+    if (!rc && states && p[i].precision != KATZ_FP64) rc = KATZ_E_UNSUPPORTED;
     if (!rc && (states || count > 1)) rc = katz::check_lds_criterion(&p[i]);
     if (rc) return rc;
   }

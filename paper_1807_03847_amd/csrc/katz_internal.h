@@ -180,6 +180,13 @@ struct IterArgs {
   const long long* coff;         // internal id -> offset of its row in col_src
   const IdLen* pmap;             // caller id -> {internal id, row length}
   int32_t* ncol;                 // renamed column ids (written)
+  // Two-pass walk step (hot_n > 0): pass 1 sums each row's entries with column
+  // id below hot_n into hot_part (long-row segments: into their partial);
+  // pass 2 sums the other entries, adds the pass-1 sum, and runs the epilogue.
+  // pass 0: one pass over every entry.
+  int pass;
+  int hot_n;
+  void* hot_part;                // [n] per-row pass-1 sums (FP32 or FP64 as x)
 };
 
 struct SelArgs {
@@ -416,6 +423,15 @@ int bin_of_host(int64_t len);
 
 // ---- vector kernels of katz_solve (katz_linear.hip) -----------------------------
 int linear_reduce_slots();
+
+// ---- reverse graph (katz_transpose.hip) ------------------------------------------
+// Device workspace of launch_transpose for a graph of n nodes and nnz arcs.
+size_t transpose_scratch_bytes(long long n, long long nnz);
+// rt_ptr (n + 1 offsets) and rt_col (nnz ids): the reverse graph of a valid CSR
+// (offsets non-decreasing, 0 <= col < n), each reversed row listing its
+// sources in ascending order.  scratch: transpose_scratch_bytes(n, nnz) bytes.
+hipError_t launch_transpose(const void* rp, int rp64, const int32_t* col, long long n, long long nnz, void* scratch,
+                            long long* rt_ptr, int32_t* rt_col, hipStream_t s);
 hipError_t launch_fill_value(double* x, long long n, double v, hipStream_t s);
 hipError_t launch_foster_step(const double* y, const double* f, double* f_new, long long n, double* slots,
                               double* out, hipStream_t s);
@@ -428,20 +444,33 @@ hipError_t launch_write_scores(const double* x, double add, long long n, const i
                                hipStream_t s);
 
 // ---- dynamic updates in two halves (katz_api.hip) ------------------------------
-// A validated batch with its arcs grouped by source row; prepared on the host
-// without reading the graph, applied later to a state of the same n.
-struct PreparedBatch {
-  long long n = 0;
-  long long n_ins = 0, n_del = 0;
-  std::vector<int32_t> pa;                 // existence-check pairs: a-ends, then b-ends
-  std::vector<int32_t> trows;              // touched rows, ascending
+// How a state reads an update pair (u, v): an undirected edge (arcs u -> v and
+// v -> u), a directed arc u -> v, or, in an inbound state (which holds the
+// reverse of the caller's graph), the caller's arc u -> v stored as v -> u.
+enum PairMode { PAIRS_UNDIRECTED = 0, PAIRS_DIRECTED = 1, PAIRS_REVERSED = 2 };
+
+// The arcs of a batch grouped by the row that stores them.
+struct RowGroups {
+  std::vector<int32_t> rows;               // touched rows, ascending (caller ids)
   std::vector<long long> ins_off, del_off; // per touched row: first arc in ins_dst / del_dst
   std::vector<int> ins_cnt, del_cnt, delta;
   std::vector<int32_t> ins_dst, del_dst;
 };
-int prepare_batch(long long n, const int32_t* ins_u, const int32_t* ins_v, long long n_ins, const int32_t* del_u,
-                  const int32_t* del_v, long long n_del, PreparedBatch& pb);
+
+// A validated batch; prepared on the host without reading the graph, applied
+// later to a state of the same n and pair mode.
+struct PreparedBatch {
+  long long n = 0;
+  int mode = PAIRS_UNDIRECTED;
+  long long n_ins = 0, n_del = 0;
+  std::vector<int32_t> pa;                 // existence-check arcs a -> b: a-ends, then b-ends
+  RowGroups fwd;                           // by source row (the state's graph)
+  RowGroups rev;                           // directed modes: by target row (the reverse graph)
+};
+int prepare_batch(long long n, int mode, const int32_t* ins_u, const int32_t* ins_v, long long n_ins,
+                  const int32_t* del_u, const int32_t* del_v, long long n_del, PreparedBatch& pb);
 int apply_batch(katz_state* st, const PreparedBatch& pb, katz_result* out, hipStream_t s);
+int state_pair_mode(const katz_state* st);
 long long state_nodes(const katz_state* st);
 
 }  // namespace katz

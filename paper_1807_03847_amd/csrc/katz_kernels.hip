@@ -220,17 +220,26 @@ __device__ __forceinline__ typename Prec<F32>::T x_entry(const IterArgs& a, cons
 struct Prev {
   double c;
   float e;
+  double hp;   // pass 2 of a two-pass step: the row's pass-1 sum (exact in FP64)
 };
 
 template <bool F32>
 __device__ __forceinline__ Prev load_prev(const IterArgs& a, int row) {
-  Prev p{0.0, 0.0f};
+  Prev p{0.0, 0.0f, 0.0};
+  if (a.pass == 1) return p;   // pass 1 writes no epilogue
   if (a.r > 1 && !a.rewalk) {
     p.c = a.c[row];
     if constexpr (F32) p.e = a.e[row];
   }
+  if (a.pass == 2) p.hp = (double)reinterpret_cast<const typename Prec<F32>::T*>(a.hot_part)[row];
   return p;
 }
+
+// The end of a row's sum t: pass 1 keeps it for pass 2; otherwise (pass 2 adds
+// the pass-1 sum first) the bound epilogue.
+template <bool F32>
+__device__ __forceinline__ void finish_row(const IterArgs& a, const Epi<F32>& ep, int row,
+                                           typename Prec<F32>::T t, double& vmax, const Prev& pv);
 
 template <bool F32>
 __device__ __forceinline__ void epilogue(const IterArgs& a, const Epi<F32>& ep, int row,
@@ -250,6 +259,18 @@ __device__ __forceinline__ void epilogue(const IterArgs& a, const Epi<F32>& ep, 
     a.e[row] = __double2float_ru((e_prev + a.etap * s) * (1.0 + 0x1p-50));
     vmax = fmax(vmax, (double)xs);
   }
+}
+
+template <bool F32>
+__device__ __forceinline__ void finish_row(const IterArgs& a, const Epi<F32>& ep, int row,
+                                           typename Prec<F32>::T t, double& vmax, const Prev& pv) {
+  using T = typename Prec<F32>::T;
+  if (a.pass == 1) {
+    reinterpret_cast<T*>(a.hot_part)[row] = t;
+    return;
+  }
+  if (a.pass == 2) t = (T)pv.hp + t;
+  epilogue<F32>(a, ep, row, t, vmax, pv);
 }
 
 // Where one stretch of a row reads its column ids and, in walk step 2 fused
@@ -314,9 +335,14 @@ __device__ __forceinline__ typename Prec<F32>::T strided_sum(const IterArgs& a, 
         sum += c[u] < 0 ? (T)0 : x_entry<F32>(a, ep1, (T)m[u].len);
       }
     } else {
+      // A two-pass step takes only its class of entries (hot: column id below
+      // hot_n); the others add an exact zero and issue no gather.
       T v[NB];
 #pragma unroll
-      for (int u = 0; u < NB; ++u) v[u] = c[u] < 0 ? (T)0 : (c[u] < H ? hub[c[u]] : x[c[u]]);
+      for (int u = 0; u < NB; ++u) {
+        const bool take = c[u] >= 0 && (a.pass == 0 || ((c[u] < a.hot_n) == (a.pass == 1)));
+        v[u] = take ? (c[u] < H ? hub[c[u]] : x[c[u]]) : (T)0;
+      }
 #pragma unroll
       for (int u = 0; u < NB; ++u) sum += v[u];
     }
@@ -351,7 +377,7 @@ __device__ __forceinline__ void rows_group(const IterArgs& a, const typename Pre
   T sum = strided_sum<F32, G, Renumber>(a, hub, row_stretch<Renumber>(a, d, valid), lane, ep1);
 #pragma unroll
   for (int o = G / 2; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, G);
-  if (valid && lane == 0) epilogue<F32>(a, ep, d.row, sum, vmax, pv);
+  if (valid && lane == 0) finish_row<F32>(a, ep, d.row, sum, vmax, pv);
 }
 
 // Sum of one row or segment by a 256-thread group: 256 strided lanes, wave
@@ -383,6 +409,7 @@ __device__ __forceinline__ typename Prec<F32>::T block_sum(const IterArgs& a, co
 // later kernel reduces the array).  All threads must call it.
 template <bool F32>
 __device__ __forceinline__ void store_block_max(const IterArgs& a, double vmax, long long slot) {
+  if (a.pass == 1) return;   // uniform: pass 1 computes no walk entry
   __shared__ double wm[kWG / kWave];
   for (int o = 32; o >= 1; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
   if (lane_id() == 0) wm[threadIdx.x / kWave] = vmax;
@@ -472,17 +499,20 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
         }
         if (stop) break;
         const T tot = block_sum<F32, Renumber>(a, hub, st, ep1);
-        if (threadIdx.x == 0) reinterpret_cast<T*>(a.partial)[sd.part] = tot;
+        if (threadIdx.x == 0) {
+          T* part = reinterpret_cast<T*>(a.partial);
+          part[sd.part] = a.pass == 2 ? part[sd.part] + tot : tot;
+        }
         break;
       }
       case BIN_B256: {
         const RowDesc d = a.desc[a.bin_base[BIN_B256] + lb];
-        Prev pv{0.0, 0.0f};
+        Prev pv{0.0, 0.0f, 0.0};
         if (threadIdx.x == 0) pv = load_prev<F32>(a, d.row);
         const Stretch st = row_stretch<Renumber>(a, d, true);
         if (stop) break;
         const T tot = block_sum<F32, Renumber>(a, hub, st, ep1);
-        if (threadIdx.x == 0) epilogue<F32>(a, ep, d.row, tot, vmax, pv);
+        if (threadIdx.x == 0) finish_row<F32>(a, ep, d.row, tot, vmax, pv);
         break;
       }
       case BIN_W64: rows_group<F32, kBinLanes[BIN_W64], Renumber>(a, hub, ep, ep1, lb, BIN_W64, vmax, stop, threadIdx.x); break;
@@ -494,7 +524,7 @@ __global__ void __launch_bounds__(kWG) walk_step(IterArgs a) {
       case BIN_EMPTY: {
         // Only at r = 2: the buffer of x_2 was never written for empty rows.
         const long long i = lb * kWG + threadIdx.x;
-        if (!stop && i < a.bin_count[BIN_EMPTY]) {
+        if (!stop && a.pass != 1 && i < a.bin_count[BIN_EMPTY]) {
           const int row = a.desc[a.bin_base[BIN_EMPTY] + i].row;
           reinterpret_cast<T*>(a.x_out)[row] = (T)0;
         }
@@ -552,7 +582,7 @@ __global__ void __launch_bounds__(kWG * kWalkGroups) walk_step_grouped(IterArgs 
     Stretch st{a.col, nullptr, 0};
     SegDesc sd{0, 0, 0, 0, 0};
     RowDesc d{0, 0, 0};
-    Prev pv{0.0, 0.0f};
+    Prev pv{0.0, 0.0f, 0.0};
     if (b < n_seg) {
       sd = a.segs[b];
       st = Stretch{a.col + sd.off, nullptr, sd.len};
@@ -563,8 +593,12 @@ __global__ void __launch_bounds__(kWG * kWalkGroups) walk_step_grouped(IterArgs 
     }
     const T tot = group_sum<F32, false>(a, hub, st, ep, tid, part[grp]);
     if (tid == 0) {
-      if (b < n_seg) reinterpret_cast<T*>(a.partial)[sd.part] = tot;
-      else if (b < n_sum) epilogue<F32>(a, ep, d.row, tot, vmax, pv);
+      if (b < n_seg) {
+        T* pt = reinterpret_cast<T*>(a.partial);
+        pt[sd.part] = a.pass == 2 ? pt[sd.part] + tot : tot;
+      } else if (b < n_sum) {
+        finish_row<F32>(a, ep, d.row, tot, vmax, pv);
+      }
     }
   }
   for (long long b = n_sum + vb; b < total; b += nvb) {
@@ -580,7 +614,7 @@ __global__ void __launch_bounds__(kWG * kWalkGroups) walk_step_grouped(IterArgs 
       case BIN_G4: rows_group<F32, kBinLanes[BIN_G4], false>(a, hub, ep, ep, lb, BIN_G4, vmax, false, tid); break;
       case BIN_EMPTY: {
         const long long i = lb * kWG + tid;
-        if (i < a.bin_count[BIN_EMPTY]) {
+        if (a.pass != 1 && i < a.bin_count[BIN_EMPTY]) {
           const int row = a.desc[a.bin_base[BIN_EMPTY] + i].row;
           reinterpret_cast<T*>(a.x_out)[row] = (T)0;
         }
@@ -589,7 +623,8 @@ __global__ void __launch_bounds__(kWG * kWalkGroups) walk_step_grouped(IterArgs 
       default: break;
     }
   }
-  // Per-group maxima, one slot per virtual workgroup.
+  // Per-group maxima, one slot per virtual workgroup (pass 1 computes none).
+  if (a.pass == 1) return;
   for (int o = 32; o >= 1; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
   if (lane_id() == 0) wm[grp][tid / kWave] = vmax;
   __syncthreads();
@@ -1288,15 +1323,12 @@ long long resident_blocks(const void* kernel, size_t lds, int block) {
   return v;
 }
 
-hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, long long max_grid,
-                            long long* blocks_used, hipStream_t s, bool renumber, int groups) {
+// One launch of the walk kernel over every work item (the grouped kernel
+// when groups = kWalkGroups); returns the workgroup-maximum slots it writes.
+hipError_t launch_walk_kernel(const IterArgs& a, int fp32, long long total_blocks, long long max_grid,
+                              long long* used_out, hipStream_t s, bool renumber, int groups) {
   long long g = total_blocks > 0 ? total_blocks : 1;
   const size_t lds = (size_t)a.hub_n * (fp32 ? sizeof(float) : sizeof(double));
-  if (a.hub_n > 0 && max_grid <= 0) return hipErrorInvalidValue;   // the copy pays only on a persistent grid
-  // col_src may be null for a graph without arcs.
-  if (renumber && (a.hub_n > 0 || !a.coff || !a.pmap || !a.ncol || a.r != 2)) return hipErrorInvalidValue;
-  if (groups != 1 && groups != kWalkGroups) return hipErrorInvalidValue;
-  long long used = 0;
   if (!renumber && groups == kWalkGroups) {
     // Workgroups of kWalkGroups groups; slots = virtual workgroups.
     g = (g + kWalkGroups - 1) / kWalkGroups;
@@ -1305,7 +1337,7 @@ hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks,
     g = std::max<long long>(1, std::min(g, resident_blocks(k, lds, kWG * kWalkGroups)));
     if (fp32) hipLaunchKernelGGL(walk_step_grouped<true>, dim3((unsigned)g), dim3(kWG * kWalkGroups), lds, s, a);
     else hipLaunchKernelGGL(walk_step_grouped<false>, dim3((unsigned)g), dim3(kWG * kWalkGroups), lds, s, a);
-    used = g * kWalkGroups;
+    *used_out = g * kWalkGroups;
   } else {
     if (max_grid > 0) {
       const void* k = renumber ? (fp32 ? (const void*)walk_step<true, true> : (const void*)walk_step<false, true>)
@@ -1319,11 +1351,43 @@ hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks,
       if (fp32) hipLaunchKernelGGL((walk_step<true, false>), dim3((unsigned)g), dim3(kWG), lds, s, a);
       else hipLaunchKernelGGL((walk_step<false, false>), dim3((unsigned)g), dim3(kWG), lds, s, a);
     }
-    used = g;
+    *used_out = g;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_step(const IterArgs& a, int fp32, long long total_blocks, long long max_grid,
+                            long long* blocks_used, hipStream_t s, bool renumber, int groups) {
+  if (a.hub_n > 0 && max_grid <= 0) return hipErrorInvalidValue;   // the copy pays only on a persistent grid
+  // col_src may be null for a graph without arcs.
+  if (renumber && (a.hub_n > 0 || !a.coff || !a.pmap || !a.ncol || a.r != 2)) return hipErrorInvalidValue;
+  if (groups != 1 && groups != kWalkGroups) return hipErrorInvalidValue;
+  const bool split = a.hot_n > 0 && !renumber && !a.rewalk;
+  if (split && !a.hot_part) return hipErrorInvalidValue;
+  long long used = 0;
+  hipError_t e;
+  if (split) {
+    // Pass 1: the hot entries (with the LDS copy); pass 2: the others, without
+    // a copy (its gathers miss it), then the epilogue.
+    IterArgs p1 = a;
+    p1.pass = 1;
+    long long unused = 0;
+    e = launch_walk_kernel(p1, fp32, total_blocks, max_grid, &unused, s, false, groups);
+    if (e != hipSuccess) return e;
+    IterArgs p2 = a;
+    p2.pass = 2;
+    p2.hub_n = 0;
+    e = launch_walk_kernel(p2, fp32, total_blocks, max_grid, &used, s, false, groups);
+  } else {
+    IterArgs p0 = a;
+    p0.pass = 0;
+    e = launch_walk_kernel(p0, fp32, total_blocks, max_grid, &used, s, renumber, groups);
+  }
+  if (e != hipSuccess) return e;
   const long long nh = a.bin_count[BIN_HUGE];
   if (nh > 0) {
     IterArgs c = a;
+    c.pass = 0;   // the segment partials already hold both passes
     c.blk_base = used;
     const long long cg = (nh + kWG / kWave - 1) / (kWG / kWave);
     if (fp32) hipLaunchKernelGGL(huge_combine<true>, dim3((unsigned)cg), dim3(kWG), 0, s, c);

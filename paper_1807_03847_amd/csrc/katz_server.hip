@@ -60,6 +60,7 @@ struct GraphEntry {
   katz_state* st = nullptr;
   int32_t k = 0;
   int64_t n = 0;
+  int mode = 0;                                  // how update pairs read (katz::PairMode)
   std::deque<std::shared_ptr<Request>> queue;   // arrival order, not yet on the device
   bool busy = false;                             // a device half of this graph runs
 };
@@ -179,9 +180,10 @@ void worker_main(katz_server* sv, hipStream_t s) {
     if (auto rq = pick_prepare(sv)) {
       rq->phase = PREPARING;
       const int64_t n = sv->graphs[rq->graph].n;
+      const int mode = sv->graphs[rq->graph].mode;
       lk.unlock();
       const auto t0 = Clock::now();
-      const int rc = katz::prepare_batch(n, rq->iu.data(), rq->iv.data(), (int64_t)rq->iu.size(), rq->du.data(),
+      const int rc = katz::prepare_batch(n, mode, rq->iu.data(), rq->iv.data(), (int64_t)rq->iu.size(), rq->du.data(),
                                          rq->dv.data(), (int64_t)rq->du.size(), rq->pb);
       const auto t1 = Clock::now();
       lk.lock();
@@ -232,6 +234,7 @@ KATZ_EXPORT int katz_server_add_graph(katz_server* sv, const katz_csr* g, const 
   ge.st = st;
   ge.k = p->k;
   ge.n = katz::state_nodes(st);
+  ge.mode = katz::state_pair_mode(st);
   sv->graphs.push_back(std::move(ge));
   *graph_id = (int32_t)sv->graphs.size() - 1;
   return rc;

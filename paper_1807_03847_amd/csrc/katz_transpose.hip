@@ -1,0 +1,219 @@
+// The reverse graph on the device.  Inbound Katz centrality counts the walks
+// that end at a node, which are the outbound walks of the reverse graph
+// (Section 2.1), and Algorithm 2's breadth-first search runs over reverse arcs
+// (Section 4): both need the transpose of a CSR.
+//
+// The transpose is a stable least-significant-digit radix sort of the arcs by
+// target, with the source as payload.  The arcs enter in source order (CSR
+// order), so every reversed row lists its sources in ascending order
+// (repeated arcs kept, in input order) and the result does not depend on
+// scheduling: a run on the reverse graph sums each row in a fixed order.
+//
+// One pass over digit d of the target ids:
+//   radix_count    tile t of kTile arcs: how many carry each digit value;
+//                  stored digit-major, count[v * tiles + t];
+//   (scan)         an exclusive scan of count gives every (value, tile) its
+//                  first output slot;
+//   radix_scatter  each tile places its arcs in input order: round j takes
+//                  arcs j*kWG .. j*kWG + kWG - 1 of the tile, waves find their
+//                  lanes' ranks among equal digits with ballots, and per-value
+//                  running counts in LDS carry the order across waves and
+//                  rounds.
+// Afterwards row_starts turns the sorted targets into the row offsets.
+#include <algorithm>
+
+#include "katz_device.h"
+
+namespace katz {
+namespace {
+
+constexpr int kRadixMaxBits = 8;
+constexpr int kRadixBins = 1 << kRadixMaxBits;
+constexpr int kTileRounds = 16;
+constexpr long long kTile = (long long)kWG * kTileRounds;   // arcs per tile
+constexpr int kExpandPer = 16;                              // arcs per thread of expand_sources
+
+// src[j] = the row of arc j, for kExpandPer consecutive arcs per thread: one
+// binary search over the offsets for the first, then a walk forward.
+template <class OffT>
+__global__ void __launch_bounds__(kWG) expand_sources(const OffT* rp, long long n, long long nnz, int32_t* src) {
+  const long long j0 = ((long long)blockIdx.x * kWG + threadIdx.x) * kExpandPer;
+  if (j0 >= nnz) return;
+  // The last row v with rp[v] <= j0 (rows before it end at or before j0).
+  long long lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const long long mid = (lo + hi + 1) >> 1;
+    if ((long long)rp[mid] <= j0) lo = mid;
+    else hi = mid - 1;
+  }
+  long long v = lo;
+  long long end = (long long)rp[v + 1];
+  const long long j1 = j0 + kExpandPer < nnz ? j0 + kExpandPer : nnz;
+  for (long long j = j0; j < j1; ++j) {
+    while (j >= end) {   // empty rows are skipped
+      ++v;
+      end = (long long)rp[v + 1];
+    }
+    src[j] = (int32_t)v;
+  }
+}
+
+__device__ __forceinline__ unsigned digit_of(int32_t key, int shift, unsigned mask) {
+  return ((unsigned)key >> shift) & mask;
+}
+
+__global__ void __launch_bounds__(kWG) radix_count(const int32_t* key, long long nnz, int shift, int bits,
+                                                   long long tiles, long long* count) {
+  __shared__ unsigned h[kRadixBins];
+  const unsigned mask = (1u << bits) - 1u;
+  for (int d = threadIdx.x; d < kRadixBins; d += kWG) h[d] = 0;
+  __syncthreads();
+  const long long base = (long long)blockIdx.x * kTile;
+  for (int j = 0; j < kTileRounds; ++j) {
+    const long long i = base + (long long)j * kWG + threadIdx.x;
+    if (i < nnz) atomicAdd(&h[digit_of(key[i], shift, mask)], 1u);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d <= (int)mask; d += kWG) count[(long long)d * tiles + blockIdx.x] = h[d];
+}
+
+// Places the tile's arcs at their sorted positions, stable.  first: the
+// exclusive scan of count (first output slot of each (value, tile)).
+__global__ void __launch_bounds__(kWG) radix_scatter(const int32_t* key_in, const int32_t* val_in, long long nnz,
+                                                     int shift, int bits, long long tiles, const long long* first,
+                                                     int32_t* key_out, int32_t* val_out) {
+  __shared__ long long base[kRadixBins];           // next free slot of each value for this tile
+  __shared__ int wcnt[kWG / kWave][kRadixBins];    // this round's count of each value per wave
+  const unsigned mask = (1u << bits) - 1u;
+  for (int d = threadIdx.x; d <= (int)mask; d += kWG) base[d] = first[(long long)d * tiles + blockIdx.x];
+  const int w = threadIdx.x / kWave;
+  const int lane = lane_id();
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  const long long tile0 = (long long)blockIdx.x * kTile;
+  for (int j = 0; j < kTileRounds; ++j) {
+    const long long i = tile0 + (long long)j * kWG + threadIdx.x;
+    const bool valid = i < nnz;
+    int32_t k = 0, v = 0;
+    if (valid) {
+      k = key_in[i];
+      v = val_in[i];
+    }
+    const unsigned d = digit_of(k, shift, mask);
+    // Lanes of this wave with the same digit: intersect the ballots of every
+    // digit bit.
+    unsigned long long same = __ballot(valid);
+    for (int b = 0; b < bits; ++b) {
+      const unsigned long long on = __ballot((d >> b) & 1u);
+      same &= ((d >> b) & 1u) ? on : ~on;
+    }
+    const int rank = __popcll(same & below);
+    for (int x = threadIdx.x; x < (kWG / kWave) * kRadixBins; x += kWG) (&wcnt[0][0])[x] = 0;
+    __syncthreads();
+    if (valid && rank == 0) wcnt[w][d] = __popcll(same);
+    __syncthreads();
+    long long pos = 0;
+    if (valid) {
+      pos = base[d] + rank;
+      for (int u = 0; u < w; ++u) pos += wcnt[u][d];
+    }
+    __syncthreads();   // every lane has read base[] before it moves on
+    for (int x = threadIdx.x; x <= (int)mask; x += kWG) {
+      int add = 0;
+      for (int u = 0; u < kWG / kWave; ++u) add += wcnt[u][x];
+      base[x] += add;
+    }
+    if (valid) {
+      key_out[pos] = k;
+      val_out[pos] = v;
+    }
+    __syncthreads();   // base[] updated before the next round reads it
+  }
+}
+
+// Row offsets of the reverse graph from its sorted targets: rt_ptr[v] = the
+// first position whose target is at least v.
+__global__ void __launch_bounds__(kWG) row_starts(const int32_t* key, long long nnz, long long n, long long* rt_ptr) {
+  const long long p = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (p > nnz) return;
+  const long long lo = p == 0 ? 0 : (long long)key[p - 1] + 1;   // targets lo .. hi start at p
+  const long long hi = p == nnz ? n : (long long)key[p];
+  for (long long v = lo; v <= hi; ++v) rt_ptr[v] = p;
+}
+
+int bits_for(long long n) {
+  int b = 1;
+  while (b < 31 && (1ll << b) < n) ++b;
+  return b;
+}
+
+}  // namespace
+
+size_t transpose_scratch_bytes(long long n, long long nnz) {
+  const long long tiles = std::max<long long>(1, (nnz + kTile - 1) / kTile);
+  const long long table = (long long)kRadixBins * tiles;
+  auto r = [](size_t b) { return (b + 255) & ~size_t(255); };
+  (void)n;
+  return 3 * r((size_t)std::max<long long>(nnz, 1) * 4) + r((size_t)table * 8) +
+         r((size_t)scan_sums_capacity(table) * 8) + r(8);
+}
+
+hipError_t launch_transpose(const void* rp, int rp64, const int32_t* col, long long n, long long nnz, void* scratch,
+                            long long* rt_ptr, int32_t* rt_col, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (nnz == 0) {
+    return hipMemsetAsync(rt_ptr, 0, sizeof(long long) * (size_t)(n + 1), s);
+  }
+  const long long tiles = (nnz + kTile - 1) / kTile;
+  const long long table = (long long)kRadixBins * tiles;
+  auto r = [](size_t b) { return (b + 255) & ~size_t(255); };
+  char* p = static_cast<char*>(scratch);
+  int32_t* src = reinterpret_cast<int32_t*>(p);
+  p += r((size_t)nnz * 4);
+  int32_t* ka = reinterpret_cast<int32_t*>(p);
+  p += r((size_t)nnz * 4);
+  int32_t* kb = reinterpret_cast<int32_t*>(p);
+  p += r((size_t)nnz * 4);
+  long long* cnt = reinterpret_cast<long long*>(p);
+  p += r((size_t)table * 8);
+  long long* sums = reinterpret_cast<long long*>(p);
+  p += r((size_t)scan_sums_capacity(table) * 8);
+  long long* total = reinterpret_cast<long long*>(p);
+
+  // Digit widths: the fewest passes of at most kRadixMaxBits bits, split evenly.
+  const int total_bits = bits_for(n);
+  const int passes = (total_bits + kRadixMaxBits - 1) / kRadixMaxBits;
+  const int width = (total_bits + passes - 1) / passes;
+  // Ping-pong buffers: pass q reads set (passes - q) & 1 and writes set
+  // (passes - 1 - q) & 1, so the last pass leaves the payload in rt_col.  The
+  // first pass reads its keys from col and its payload from the sources,
+  // which are expanded into the set it reads.
+  int32_t* vbuf[2] = {rt_col, src};
+  int32_t* kbuf[2] = {ka, kb};
+  const unsigned eg = (unsigned)((nnz + (long long)kWG * kExpandPer - 1) / ((long long)kWG * kExpandPer));
+  int32_t* src0 = vbuf[passes & 1];
+  if (rp64)
+    hipLaunchKernelGGL(expand_sources<long long>, dim3(eg), dim3(kWG), 0, s, (const long long*)rp, n, nnz, src0);
+  else hipLaunchKernelGGL(expand_sources<int>, dim3(eg), dim3(kWG), 0, s, (const int*)rp, n, nnz, src0);
+  const int32_t* kin = col;
+  const int32_t* vin = src0;
+  int shift = 0;
+  for (int q = 0; q < passes; ++q) {
+    const int bits = std::min(width, total_bits - shift);
+    const int set = (passes - 1 - q) & 1;
+    int32_t* kout = kbuf[set];
+    int32_t* vout = vbuf[set];
+    hipLaunchKernelGGL(radix_count, dim3((unsigned)tiles), dim3(kWG), 0, s, kin, nnz, shift, bits, tiles, cnt);
+    const hipError_t e = launch_scan_ll(cnt, (long long)(1 << bits) * tiles, cnt, sums, total, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(radix_scatter, dim3((unsigned)tiles), dim3(kWG), 0, s, kin, vin, nnz, shift, bits, tiles,
+                       (const long long*)cnt, kout, vout);
+    kin = kout;
+    vin = vout;
+    shift += bits;
+  }
+  const unsigned rg = (unsigned)((nnz + 1 + kWG - 1) / kWG);
+  hipLaunchKernelGGL(row_starts, dim3(rg), dim3(kWG), 0, s, kin, nnz, n, rt_ptr);
+  return hipGetLastError();
+}
+
+}  // namespace katz

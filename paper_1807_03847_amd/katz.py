@@ -71,7 +71,8 @@ SOLVE_METHODS = {"foster": SOLVE_FOSTER, "cg": SOLVE_CG}
 class KatzTuning(ctypes.Structure):
     _fields_ = [("hub_bytes", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("batch_blocks_per_cu", ctypes.c_int32), ("batch_tile", ctypes.c_int32),
-                ("batch_xcd", ctypes.c_int32), ("walk_groups", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("batch_xcd", ctypes.c_int32), ("walk_groups", ctypes.c_int32), ("split_hot_bytes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class KatzTiming(ctypes.Structure):
@@ -181,6 +182,7 @@ def make_csr(row_ptr: torch.Tensor, col: torch.Tensor, undirected: bool = True) 
 
 FLAG_NO_REORDER = 1
 FLAG_REORDER = 2
+FLAG_INBOUND = 4
 
 
 def make_params(k=1, alpha=0.0, eps=0.0, precision="fp64", max_iter=0, validate=VALIDATE_BASIC,
@@ -245,13 +247,13 @@ def rank_static_noalloc(row_ptr, col, k, *, alpha=0.0, eps=0.0, precision="fp64"
 
 
 def solve(row_ptr, col, method="cg", tol=1e-15, *, alpha=0.0, max_iter=0, undirected=True,
-          validate=VALIDATE_BASIC, stream=None, out=None):
+          validate=VALIDATE_BASIC, flags=0, stream=None, out=None):
     """katz_solve: Katz scores of every node by Foster's heuristic ("foster")
     or by conjugate gradients on Eq. (la) ("cg").  Returns (scores, info dict,
     status)."""
     device = row_ptr.device
     g = make_csr(row_ptr, col, undirected)
-    p = make_params(1, alpha, 0.0, "fp64", max_iter, validate)
+    p = make_params(1, alpha, 0.0, "fp64", max_iter, validate, 0, flags)
     scores = out if out is not None else torch.empty(g.n, dtype=torch.float64, device=device)
     info = KatzSolveInfo()
     rc = lib.katz_solve(ctypes.byref(g), ctypes.byref(p), SOLVE_METHODS[method] if isinstance(method, str)
@@ -298,8 +300,9 @@ def bounds(row_ptr, col, r, *, alpha=0.0, precision="fp64", undirected=True, val
 
 class State:
     """A dynamic ranking state (katz_state): the graph, the walk history, c_r and
-    M on the device.  ``update`` applies one batch of undirected edge insertions
-    and deletions (Algorithm 2) and returns the re-certified top-k."""
+    M on the device.  ``update`` applies one batch of edge (undirected graph) or
+    arc (directed graph) insertions and deletions (Algorithm 2) and returns the
+    re-certified top-k."""
 
     def __init__(self, handle, k, device):
         self._h = handle
@@ -334,11 +337,13 @@ class State:
 
 
 def create_state(row_ptr, col, k, *, alpha=0.0, eps=0.0, max_iter=0, degree_cap=0, validate=VALIDATE_BASIC,
-                 flags=0, stream=None):
+                 flags=0, undirected=True, stream=None):
     """katz_rank_static with a state: ranks the graph (Algorithm 1, FP64, kept
-    walk history) and returns (State, RankResult) for later updates."""
+    walk history) and returns (State, RankResult) for later updates.  A
+    directed graph's update pairs (u, v) are arcs u -> v; with FLAG_INBOUND
+    the state ranks by inbound walks."""
     device = row_ptr.device
-    g = make_csr(row_ptr, col, True)
+    g = make_csr(row_ptr, col, undirected)
     p = make_params(k, alpha, eps, "fp64", max_iter, validate, degree_cap, flags)
     ids, lo, up = _alloc_outputs(k, device)
     res = KatzResult(topk_ids=ids.data_ptr(), lower=lo.data_ptr(), upper=up.data_ptr())
@@ -363,11 +368,11 @@ class Server:
         self._k = {}
 
     def add_graph(self, row_ptr, col, k, *, alpha=0.0, eps=0.0, max_iter=0, degree_cap=0,
-                  validate=VALIDATE_BASIC):
+                  validate=VALIDATE_BASIC, flags=0, undirected=True):
         """Registers a graph (host or device CSR); returns (graph_id, initial RankResult on the host)."""
         import numpy as np
-        g = make_csr(row_ptr, col, True)
-        p = make_params(k, alpha, eps, "fp64", max_iter, validate, degree_cap)
+        g = make_csr(row_ptr, col, undirected)
+        p = make_params(k, alpha, eps, "fp64", max_iter, validate, degree_cap, flags)
         ids = np.empty(k, dtype=np.int32)
         lo = np.empty(k, dtype=np.float64)
         up = np.empty(k, dtype=np.float64)
@@ -424,7 +429,8 @@ class Server:
 
 def _tuning_dict(t):
     return {"hub_bytes": t.hub_bytes, "blocks_per_cu": t.blocks_per_cu, "batch_blocks_per_cu": t.batch_blocks_per_cu,
-            "batch_tile": t.batch_tile, "batch_xcd": t.batch_xcd, "walk_groups": t.walk_groups}
+            "batch_tile": t.batch_tile, "batch_xcd": t.batch_xcd, "walk_groups": t.walk_groups,
+            "split_hot_bytes": t.split_hot_bytes}
 
 
 def tuning_get() -> dict:
@@ -437,11 +443,11 @@ def tuning_get() -> dict:
 
 
 def tuning_set(hub_bytes=0, blocks_per_cu=0, batch_blocks_per_cu=0, batch_tile=0, batch_xcd=0,
-               walk_groups=0) -> None:
-    """katz_tuning_set (no result depends on it)."""
+               walk_groups=0, split_hot_bytes=0) -> None:
+    """katz_tuning_set (no result depends on it, except on split_hot_bytes)."""
     t = KatzTuning(hub_bytes=int(hub_bytes), blocks_per_cu=int(blocks_per_cu),
                    batch_blocks_per_cu=int(batch_blocks_per_cu), batch_tile=int(batch_tile),
-                   batch_xcd=int(batch_xcd), walk_groups=int(walk_groups))
+                   batch_xcd=int(batch_xcd), walk_groups=int(walk_groups), split_hot_bytes=int(split_hot_bytes))
     rc = lib.katz_tuning_set(ctypes.byref(t))
     if rc < 0:
         raise KatzError(rc)

@@ -192,6 +192,16 @@ def rmat_device(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0
     return row_ptr, col
 
 
+def rmat_directed(scale: int, edge_factor: int = 16, seed: int = 1, stream: int = 5):
+    """Directed R-MAT: edge_factor * 2^scale arcs u -> v drawn from the R-MAT
+    distribution of ``rmat(scale, seed=seed)`` (counter stream ``stream``),
+    deduplicated, self-loops dropped; power-law out- and in-degrees that
+    differ from node to node."""
+    n = 1 << scale
+    p = rmat_pairs(scale, edge_factor * n, seed=seed, stream=stream)
+    return from_edges(n, p[:, 0], p[:, 1], undirected=False)
+
+
 def barabasi_albert(n: int, m: int, seed: int):
     """Preferential attachment: (m+1)-clique seed, then m distinct targets per vertex."""
     return _take(_load().sg_ba(n, m, seed))

@@ -399,3 +399,41 @@ def test_launch_tuning_is_invisible(precision):
         assert torch.equal(a.topk, ref.topk) and torch.equal(a.lower, ref.lower)
     finally:
         katz.tuning_set(**saved)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_two_pass_walk_step(precision):
+    """The two-pass walk step (katz_tuning.split_hot_bytes), forced with a
+    64 KiB hot set on R-MAT 16: the certified ranking and the bounds against
+    the oracle (FP64 within 1e-12, FP32 containing it), and every launch shape
+    bitwise the same under the split."""
+    katz = K()
+    rp, col = sg.rmat(16, seed=12)
+    rp_t, col_t = dev(rp, col)
+    a = 1.0 / (1 + sg.max_degree(rp))
+    orc = oracle.rank_static(rp, col, a, 500, 1e-6)
+    saved = katz.tuning_get()
+    try:
+        ref = None
+        for hub, bpc, groups in [(0, 0, 0), (16384, 2, 0), (131072, 1, 4), (0, 1, 4)]:
+            say("two-pass", precision, hub, bpc, groups)
+            katz.tuning_set(hub, bpc, walk_groups=groups, split_hot_bytes=65536)
+            res = katz.rank_static(rp_t, col_t, 500, alpha=a, eps=1e-6, precision=precision)
+            if ref is None:
+                ref = res
+                check(orc, res, widened=precision == "fp32")
+                for r in (3, 5, 8):
+                    lo, up = katz.bounds(rp_t, col_t, r, alpha=a, precision=precision)
+                    lo, up = lo.cpu().numpy(), up.cpu().numpy()
+                    olo, oup = oracle.bounds(rp, col, a, r)
+                    if precision == "fp64":
+                        np.testing.assert_allclose(lo, olo, rtol=1e-12, atol=0)
+                        np.testing.assert_allclose(up, oup, rtol=1e-12, atol=0)
+                    else:
+                        assert np.all(lo <= olo * (1 + TAU) + 1e-300) and np.all(up >= oup * (1 - TAU))
+                        assert np.all(np.abs(lo - olo) <= 1e-6 * olo + 1e-24)
+            else:
+                assert torch.equal(res.topk, ref.topk) and torch.equal(res.lower, ref.lower)
+                assert torch.equal(res.upper, ref.upper) and res.iterations == ref.iterations
+    finally:
+        katz.tuning_set(**saved)

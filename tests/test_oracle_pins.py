@@ -638,3 +638,72 @@ def test_cg_and_foster_exact_on_star():
     fo = oracle.foster(rp, col, float(alpha), tol=1e-13)
     for res in (cg, fo):
         np.testing.assert_allclose(res.scores, [float(v) for v in c_exact], rtol=1e-11)
+
+
+# --- inbound Katz and directed dynamic graphs ---------------------------------------
+
+@pytest.mark.parametrize("name,g,und", [t for t in small_graphs() if not t[2]])
+def test_reverse_graph_counts_walks_ending_at_each_node(name, g, und):
+    """Walk counts of the reverse graph are the inbound walk counts of the
+    graph (Section 2.1), found by enumerating every walk and tallying its end."""
+    rp, col = g
+    rt, rc = oracle.reverse_graph(rp, col)
+    if not _nonempty(rt):
+        pytest.skip("no arcs")
+    alpha = 1.0 / (1 + sg.max_degree(rt))
+    A = K.adjacency(rt, rc)
+    x = np.ones(len(rp) - 1)
+    for i in range(1, 6):
+        x = K.walk_step(A, x, alpha)
+        want = np.array(exact.walks_ending_bruteforce(rp, col, i), dtype=np.float64)
+        np.testing.assert_allclose(x / alpha ** i, want, rtol=8 * i * ULP)
+
+
+def test_reverse_graph_structure():
+    """Reversing twice gives the graph back; an undirected graph is its own
+    reverse; reversed rows are sorted; in-degrees become out-degrees."""
+    for name, (rp, col), und in small_graphs():
+        rt, rc = oracle.reverse_graph(rp, col)
+        rr, rrc = oracle.reverse_graph(rt, rc)
+        np.testing.assert_array_equal(rr, rp)
+        np.testing.assert_array_equal(rrc, col)
+        if und:
+            np.testing.assert_array_equal(rt, rp)
+            np.testing.assert_array_equal(rc, col)
+        for v in range(len(rt) - 1):
+            assert np.all(np.diff(rc[rt[v]:rt[v + 1]]) > 0)
+        np.testing.assert_array_equal(np.diff(rt), np.bincount(col, minlength=len(rp) - 1))
+
+
+def _random_directed_batch(rng, rp, col, n, n_ins, n_del):
+    src = np.repeat(np.arange(n), np.diff(rp))
+    arcs = [(int(a), int(b)) for a, b in zip(src, col)]
+    existing = set(arcs)
+    dels = [arcs[i] for i in rng.choice(len(arcs), size=min(n_del, len(arcs)), replace=False)]
+    ins = set()
+    while len(ins) < n_ins:
+        a, b = (int(v) for v in rng.integers(0, n, 2))
+        if a != b and (a, b) not in existing:
+            ins.add((a, b))
+    return sorted(ins), dels
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_dynamic_directed_equals_static_recompute(seed):
+    """Algorithm 2 on a directed graph (the search follows reverse arcs):
+    after each batch of arc updates the iterates equal a static run on the new
+    graph at the same r, and the certified top-k is the static one."""
+    rng = np.random.default_rng(seed)
+    rp, col = sg.random_graph(300, 0.02, 70 + seed, undirected=False)
+    dmax = sg.max_degree(rp)
+    alpha = 1.0 / (dmax + 1 + 8)
+    dyn = oracle.DynamicOracle(rp, col, alpha, k=15, eps=1e-9, undirected=False, degree_cap=dmax + 8)
+    for batch in range(4):
+        ins, dels = _random_directed_batch(rng, dyn.row_ptr, dyn.col, 300, 1 + 6 * batch, 1 + 3 * batch)
+        res = dyn.update(ins, dels)
+        c_ref, x_ref = oracle.walk_state(dyn.row_ptr, dyn.col, alpha, res.iterations)
+        np.testing.assert_allclose(res.c, c_ref, rtol=1e-12, atol=1e-16)
+        np.testing.assert_allclose(res.x, x_ref, rtol=1e-10, atol=1e-18)
+        st = oracle.rank_static(dyn.row_ptr, dyn.col, alpha, 15, 1e-9, undirected=False)
+        assert res.status == oracle.OK
+        assert list(res.topk) == list(st.topk)
