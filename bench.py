@@ -95,6 +95,15 @@ def time_form(katz, torch, rp_t, col_t, k, precision, steps, warmup, flags=0):
     return res, (t1 - t0) / steps, tm
 
 
+def tuning_arg(t):
+    """HUB_BYTES:BLOCKS_PER_CU:WALK_GROUPS[:B0,...,B5] (the row-length classes
+    only when they are not the defaults)."""
+    arg = f"{t['hub_bytes']}:{t['blocks_per_cu']}:{t['walk_groups']}"
+    if any(t.get("bin_bounds", [0])):
+        arg += ":" + ",".join(str(v) for v in t["bin_bounds"])
+    return arg
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -123,8 +132,9 @@ def run_static(args, katz, sg, torch, np, wl):
         if args.tuning == "auto":
             tunings[precision] = katz.autotune(rp_t, col_t, k, eps=EPS, precision=precision)
         else:
-            parts = [int(v) for v in args.tuning.split(":")]
-            katz.tuning_set(parts[0], parts[1], walk_groups=parts[2] if len(parts) > 2 else 0)
+            parts = args.tuning.split(":")
+            katz.tuning_set(int(parts[0]), int(parts[1]), walk_groups=int(parts[2]) if len(parts) > 2 else 0,
+                            bin_bounds=[int(v) for v in parts[3].split(",")] if len(parts) > 3 else None)
             tunings[precision] = katz.tuning_get()
         print(f"[bench] rmat{scale} {precision} tuning {tunings[precision]}", flush=True)
         res, sec, tm = time_form(katz, torch, rp_t, col_t, k, precision, args.steps, args.warmup)
@@ -148,8 +158,7 @@ def run_static(args, katz, sg, torch, np, wl):
     f32, f64 = forms["fp32"], forms["fp64"]
     bytes_step = algorithmic_bytes_per_walk_step(n, nnz, "fp32", rp64)
     achieved = bytes_step / (f32["walk_avg_ms"] * 1e-3) / 1e9
-    tuning = {p: dict(t, arg=f"{t['hub_bytes']}:{t['blocks_per_cu']}:{t['walk_groups']}")
-              for p, t in tunings.items()}
+    tuning = {p: dict(t, arg=tuning_arg(t)) for p, t in tunings.items()}
     traffic, traffic_note = measured_traffic(scale, tuning["fp32"]["arg"])
     out = {
         "value": round(f32["gteps"], 3),
@@ -271,7 +280,8 @@ def main():
     ap.add_argument("--batched-max-log2n", type=int, default=18, help="batched: n is log-uniform in [2^10, 2^this]")
     ap.add_argument("--tuning", default="auto",
                     help="walk launch shape: 'auto' (katz_autotune per precision before timing), "
-                         "or HUB_BYTES:BLOCKS_PER_CU[:WALK_GROUPS] for both precisions")
+                         "or HUB_BYTES:BLOCKS_PER_CU[:WALK_GROUPS[:B0,B1,B2,B3,B4,B5]] for both precisions "
+                         "(B: the row-length classes of the binning)")
     ap.add_argument("--tuning-sweep", action="store_true",
                     help="batched: also time every autotuner candidate and report them")
     args = ap.parse_args()
@@ -452,10 +462,20 @@ def bench_serving(args, katz, sg, torch, np):
     total = args.requests * 3
     reqs = serving_requests(rp, col, n, total, rng, np, sg, args.serving_scale, 2)
     print(f"[bench] {total} requests generated, {sum(len(a) + len(b) for a, b in reqs)} edge updates", flush=True)
+    rp_t, col_t = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+    # The launch shape of the state's whole-graph walks (creation, dense
+    # re-walk levels, resumed iterations): the autotuner's choice for a
+    # static FP64 ranking of the resident graph.
+    tuning = katz.autotune(rp_t, col_t, 100, eps=1e-6, precision="fp64")
+    print(f"[bench] serving tuning {tuning}", flush=True)
     sv = katz.Server(slots=4)
-    gid, _ = sv.add_graph(torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda(), 100,
-                          alpha=1.0 / (1 + dmax + H), eps=1e-6, degree_cap=dmax + H)
     torch.cuda.synchronize()
+    t_create = time.perf_counter()
+    gid, _ = sv.add_graph(rp_t, col_t, 100, alpha=1.0 / (1 + dmax + H), eps=1e-6, degree_cap=dmax + H)
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - t_create) * 1e3
+    print(f"[bench] state created (checks, slack CSR, renumbering, first certified ranking) in {create_ms:.1f} ms",
+          flush=True)
     # Saturation: the first block of requests submitted at once.
     block = reqs[:args.requests]
     t0 = time.perf_counter()
@@ -504,7 +524,8 @@ def bench_serving(args, katz, sg, torch, np):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"rmat{args.serving_scale}_serving", "n": n, "nnz_directed": int(rp[-1]), "k": 100, "eps": 1e-6,
                    "batch": "round(10^U(0,4)) edges, 70% insertions", "slots": 4},
-        "saturation_requests_per_s": round(sat, 2), "load_points": points,
+        "saturation_requests_per_s": round(sat, 2), "load_points": points, "tuning": tuning,
+        "state_create_ms": round(create_ms, 1),
     }
     print(json.dumps(out), flush=True)
 

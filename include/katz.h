@@ -388,9 +388,9 @@ int katz_timing_read(katz_timing* out);
 
 /* ---- launch tuning of the walk kernels ------------------------------------
  * Process-wide launch shape of the walk step (the degree-binned SpMV of Eq.
- * (basic_recurrence), Section 3.2).  No setting but split_hot_bytes changes
- * any result bit: every row is still summed by the same lane schedule, and the
- * LDS copy holds exact walk entries.
+ * (basic_recurrence), Section 3.2).  No setting but split_hot_bytes and
+ * bin_bounds changes any result bit: every row is still summed by the same
+ * lane schedule, and the LDS copy holds exact walk entries.
  *   hub_bytes            single-graph static calls with the internal
  *                        renumbering: bytes of LDS per workgroup that hold a
  *                        copy of the first walk entries (after the renumbering,
@@ -429,6 +429,16 @@ int katz_timing_read(katz_timing* out);
  *                        additions, so results differ from one-pass runs in
  *                        their rounding (both certified); the autotuner leaves
  *                        it unchanged.
+ *   bin_bounds           the row-length classes of the degree binning: rows of
+ *                        length 1..b0 are summed by one lane, b0+1..b1 by one,
+ *                        b1+1..b2 by 2, b2+1..b3 by 4, b3+1..b4 by 16 lanes,
+ *                        b4+1..b5 by a wave, b5+1..4096 by a workgroup, longer
+ *                        rows by 4096-arc segments.  All 0 = the defaults
+ *                        {4, 8, 16, 32, 128, 1024}.  The classes fix the order
+ *                        of each row's additions, so results differ from
+ *                        other classes in their rounding (both certified);
+ *                        the autotuner searches a few tables.  A state keeps
+ *                        the classes of its creation.
  * Defaults: all 0.  Calls already running keep the setting they started with. */
 typedef struct katz_tuning {
   int32_t hub_bytes;
@@ -438,6 +448,7 @@ typedef struct katz_tuning {
   int32_t batch_xcd;         /* 0 or 1 */
   int32_t walk_groups;       /* 0, 1 or 4 */
   int32_t split_hot_bytes;   /* 0, or 16 .. 64 MiB */
+  int32_t bin_bounds[6];     /* all 0, or 1 <= b0 < b1 < ... < b5 < 4096 */
   int32_t reserved;          /* must be 0 */
 } katz_tuning;
 

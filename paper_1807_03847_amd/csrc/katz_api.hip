@@ -236,7 +236,31 @@ int tuning_valid(const katz_tuning& t) {
   if (t.split_hot_bytes < 0 || t.split_hot_bytes > (64 << 20) || (t.split_hot_bytes > 0 && (t.split_hot_bytes & 15)))
     return KATZ_E_INVALID_ARG;
   if (t.reserved != 0) return KATZ_E_INVALID_ARG;
+  // bin_bounds: all 0 (the default classes), or strictly increasing from 1,
+  // the last below kBlockRowMax (the one-workgroup class keeps its end).
+  bool any = false;
+  for (int v : t.bin_bounds) any = any || v != 0;
+  if (any) {
+    int prev = 0;
+    for (int v : t.bin_bounds) {
+      if (v <= prev) return KATZ_E_INVALID_ARG;
+      prev = v;
+    }
+    if (prev >= kBlockRowMax) return KATZ_E_INVALID_ARG;
+  }
   return KATZ_OK;
+}
+
+BinBounds bounds_of(const katz_tuning& t) {
+  BinBounds bb;
+  if (t.bin_bounds[0] == 0) return bb;
+  bb.g4 = t.bin_bounds[0];
+  bb.g8 = t.bin_bounds[1];
+  bb.g16 = t.bin_bounds[2];
+  bb.g32 = t.bin_bounds[3];
+  bb.w16 = t.bin_bounds[4];
+  bb.w64 = t.bin_bounds[5];
+  return bb;
 }
 
 int cu_count(int dev) {
@@ -395,6 +419,7 @@ struct Bins {
   long long bin_base[NUM_BINS] = {};
   long long seg_total = 0;
   int dmax = 0;
+  BinBounds bb;   // the length classes the rows are binned by
 
   void read_back(const RunScalars& h, long long rows) {
     std::memcpy(bin_count, h.bin_count, sizeof(bin_count));
@@ -468,26 +493,28 @@ int resolve_alpha(double alpha_in, int dmax, Scalars& S) {
 
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
-// Deepest rounding chain of a row sum under the bin schedule (serial adds per
-// lane, then the butterfly levels, and the segment combine for huge rows).  It
-// grows with the row length, so the longest row of a graph sets its maximum.
-int reduction_depth(long long dmax) {
-  switch (bin_of_host(dmax)) {
-    case BIN_EMPTY: return 0;
-    // (longest row of the bin / lanes - 1) serial adds, then log2(lanes) levels.
-    case BIN_G4: return 4 / kBinLanes[BIN_G4] - 1 + ilog2(kBinLanes[BIN_G4]);
-    case BIN_G8: return 8 / kBinLanes[BIN_G8] - 1 + ilog2(kBinLanes[BIN_G8]);
-    case BIN_G16: return 16 / kBinLanes[BIN_G16] - 1 + ilog2(kBinLanes[BIN_G16]);
-    case BIN_G32: return 32 / kBinLanes[BIN_G32] - 1 + ilog2(kBinLanes[BIN_G32]);
-    case BIN_W16: return kShortRowMax / kBinLanes[BIN_W16] - 1 + ilog2(kBinLanes[BIN_W16]);
-    case BIN_W64: return kWaveRowMax / kBinLanes[BIN_W64] - 1 + ilog2(kBinLanes[BIN_W64]);
-    case BIN_B256: return (kPerLane - 1) + 8;
-    default: {
-      const long long max_seg = (dmax + kSeg - 1) / kSeg;
-      const long long q = (max_seg + kWave - 1) / kWave;
-      return (int)((kPerLane - 1) + 8 + (q - 1) + 6);
-    }
+// Deepest rounding chain of a row sum under the bin schedule: a row of
+// length L summed by G lanes takes ceil(L/G) - 1 serial adds per lane, then
+// log2(G) combining levels (butterflies, and for a workgroup the two levels
+// over its four wave sums); a segmented row adds the combine of its segment
+// sums.  Every class up to the longest row's counts at its longest row.
+int reduction_depth(long long dmax, const BinBounds& bb) {
+  if (dmax <= 0) return 0;
+  const long long caps[] = {bb.g4, bb.g8, bb.g16, bb.g32, bb.w16, bb.w64, kBlockRowMax};
+  const int bins[] = {BIN_G4, BIN_G8, BIN_G16, BIN_G32, BIN_W16, BIN_W64, BIN_B256};
+  int depth = 0;
+  for (int i = 0; i < 7; ++i) {
+    const long long first = i == 0 ? 1 : caps[i - 1] + 1;
+    if (dmax < first) break;
+    const int lanes = kBinLanes[bins[i]];
+    depth = std::max(depth, (int)((caps[i] + lanes - 1) / lanes - 1) + ilog2(lanes));
   }
+  if (dmax > kBlockRowMax) {
+    const long long max_seg = (dmax + kSeg - 1) / kSeg;
+    const long long q = (max_seg + kWave - 1) / kWave;
+    depth = std::max(depth, (int)((kPerLane - 1) + 8 + (q - 1) + 6));
+  }
+  return depth;
 }
 
 // FP32 form: eta_r bounds the relative error of every entry of x~_r; eta_1 = 0
@@ -495,8 +522,8 @@ int reduction_depth(long long dmax) {
 // rho = gamma_m = m u / (1 - m u) for the deepest reduction chain m.
 // extra: rounding levels added to every row sum (1 for the two-pass walk step,
 // whose second pass adds the first pass's sum).
-void fp32_tables(Scalars& S, long long dmax, int max_iter, int extra = 0) {
-  const int m = reduction_depth(dmax) + extra;
+void fp32_tables(Scalars& S, long long dmax, int max_iter, const BinBounds& bb, int extra = 0) {
+  const int m = reduction_depth(dmax, bb) + extra;
   S.rho = (m * kU32) / (1.0 - m * kU32) * (1.0 + 0x1p-40);
   S.eta.assign(max_iter + 1, 0.0);
   S.etap.assign(max_iter + 1, 0.0);
@@ -567,6 +594,9 @@ struct katz_state {
   int32_t* clist = nullptr;
   int* counter = nullptr;
   unsigned long long* frontier_arcs = nullptr;   // arcs of the last expansion's new frontier
+  long long* foff = nullptr;       // frontier row offsets of an expansion (n), scan scratch, total
+  long long* fsums = nullptr;
+  long long* ftotal = nullptr;
   int* dmax_dev = nullptr;
   int* err_dev = nullptr;
   unsigned long long* min_bits = nullptr;
@@ -1084,9 +1114,10 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
     stg.col = g->col;
   }
   KATZ_HIP(launch_init_run(w.sc, g->n, w.sigma, w.sigma_sum, w.xmax32, w.xmax64, pl.max_iter, w.hist, s));
-  KATZ_HIP(launch_prep_count(stg.row_ptr, g->row_ptr_64, g->n, g->nnz, b.blk, b.nblocks, w.sc, s));
+  KATZ_HIP(launch_prep_count(stg.row_ptr, g->row_ptr_64, g->n, g->nnz, b.blk, b.nblocks, w.sc, b.bb, s));
   KATZ_HIP(launch_prep_scan(b.blk, b.nblocks, b.scan_sums, b.scan_totals, w.sc, s));
-  KATZ_HIP(launch_prep_scatter(stg.row_ptr, g->row_ptr_64, g->n, b.blk, b.nblocks, b.desc, b.segs, b.huge, w.sc, s));
+  KATZ_HIP(launch_prep_scatter(stg.row_ptr, g->row_ptr_64, g->n, b.blk, b.nblocks, b.desc, b.segs, b.huge, w.sc, b.bb,
+                               s));
   // Column ids are range-checked before any gather uses them: here, or, when
   // the graph is renumbered with basic validation, in walk step 2, which reads
   // every caller column id to rename it and never indexes with a bad one (no
@@ -1112,7 +1143,7 @@ int prepare(HostSync& hs, const Plan& pl, Bins& b, Work& w, Staging& stg, hipStr
     KATZ_HIP(launch_relabel(b.desc, g->n, stg.ext_of, stg.int_of, stg.coff, stg.pmap, stg.len_ll, stg.len32,
                             stg.noff, stg.sums, stg.total, s));
     KATZ_HIP(launch_prep_rows(nullptr, g->n, stg.noff, stg.len32, b.blk, b.nblocks, b.scan_sums, b.scan_totals,
-                              b.desc, b.segs, b.huge, w.sc, s));
+                              b.desc, b.segs, b.huge, w.sc, b.bb, s));
     KATZ_HIP(hipMemcpyAsync(hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
     KATZ_HIP(hipStreamSynchronize(s));
     if (hs.sc->err) return hs.sc->err == 1 ? KATZ_E_CSR : KATZ_E_HIP;
@@ -1162,6 +1193,7 @@ int rank_in_arena(Arena& ar, const katz_csr* g, const katz_params* p, katz_resul
   pl.split_n = split_count(tu, pl);
 
   Bins b;
+  b.bb = bounds_of(tu);
   Work w;
   Staging stg;
   KATZ_TRY(plan_and_allocate(ar, pl, b, w, stg));
@@ -1174,7 +1206,7 @@ int rank_in_arena(Arena& ar, const katz_csr* g, const katz_params* p, katz_resul
 
   Scalars S;
   KATZ_TRY(resolve_alpha(p->alpha, b.dmax, S));
-  if (pl.fp32) fp32_tables(S, b.dmax, pl.max_iter, pl.split_n > 0 ? 1 : 0);
+  if (pl.fp32) fp32_tables(S, b.dmax, pl.max_iter, b.bb, pl.split_n > 0 ? 1 : 0);
 
   Run run;
   run.n = g->n;
@@ -1263,7 +1295,7 @@ int reverse_graph(Arena& ar, const katz_csr* g, const katz_params* p, katz_csr& 
     col = col_dev;
   }
   KATZ_HIP(launch_reset_flags(sc, s));
-  KATZ_HIP(launch_prep_count(rp, g->row_ptr_64, n, nnz, blk, tmp.nblocks, sc, s));
+  KATZ_HIP(launch_prep_count(rp, g->row_ptr_64, n, nnz, blk, tmp.nblocks, sc, BinBounds{}, s));
   KATZ_HIP(launch_check_col_range(col, nnz, n, sc, s));
   KATZ_HIP(hipMemcpyAsync(ar.hs.sc, sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
   KATZ_HIP(hipStreamSynchronize(s));
@@ -1349,13 +1381,14 @@ int bounds_on(const katz_csr* g, const katz_params* p, int r_target, double* low
   const katz_tuning tu = current_tuning();   // one setting for the whole call
   pl.split_n = split_count(tu, pl);
   Bins b;
+  b.bb = bounds_of(tu);
   Work w;
   Staging stg;
   KATZ_TRY(plan_and_allocate(ar, pl, b, w, stg));
   KATZ_TRY(prepare(ar.hs, pl, b, w, stg, s));
   Scalars S;
   KATZ_TRY(resolve_alpha(p->alpha, b.dmax, S));
-  if (pl.fp32) fp32_tables(S, b.dmax, pl.max_iter, pl.split_n > 0 ? 1 : 0);
+  if (pl.fp32) fp32_tables(S, b.dmax, pl.max_iter, b.bb, pl.split_n > 0 ? 1 : 0);
   Run run;
   run.n = g->n;
   run.nnz = g->nnz;
@@ -1458,6 +1491,7 @@ int solve_on(const katz_csr* g, const katz_params* p, int method, double tol, do
   pl.out_n = (size_t)n;
   pl.solve_vectors = 3;
   Bins b;
+  b.bb = bounds_of(current_tuning());
   Work w;
   Staging stg;
   KATZ_TRY(plan_and_allocate(ar, pl, b, w, stg));
@@ -1593,6 +1627,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
                              is_device_ptr(out[i].upper));
   }
   Bins b;
+  b.bb = bounds_of(tu_b);
   Work w;
   RunScalars* gsc = nullptr;
   long long* gbase = nullptr;
@@ -1755,7 +1790,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   int validate = 0;
   for (int i = 0; i < count; ++i) validate = std::max(validate, p[i].validate);
   KATZ_HIP(launch_batch_prep(gbase, grp, grp64, gnnz, gabase, gcol, count, total_n, total_nnz, gid_of, b.blk,
-                             b.nblocks, b.scan_sums, b.scan_totals, b.desc, b.segs, b.huge, w.sc, validate, s));
+                             b.nblocks, b.scan_sums, b.scan_totals, b.desc, b.segs, b.huge, w.sc, validate, b.bb, s));
   KATZ_HIP(launch_batch_dmax(grp, grp64, gbase, count, total_n, gdmax, s));
   std::vector<int> h_dmax(count);
   KATZ_HIP(hipMemcpyAsync(h_dmax.data(), gdmax, sizeof(int) * count, hipMemcpyDeviceToHost, s));
@@ -1771,7 +1806,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
     KATZ_HIP(launch_batch_relabel(b.desc, total_n, gbase, count, w.sc, run_first, run_last, run_start, ext_of, int_of,
                                   coff, pmap, len_ll, len32, noff, rsums, rtot, s));
     KATZ_HIP(launch_prep_rows(nullptr, total_n, noff, len32, b.blk, b.nblocks, b.scan_sums, b.scan_totals, b.desc,
-                              b.segs, b.huge, w.sc, s));
+                              b.segs, b.huge, w.sc, b.bb, s));
     KATZ_HIP(hipMemcpyAsync(ar.hs.sc, w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
     KATZ_HIP(hipStreamSynchronize(s));
     if (ar.hs.sc->err) return ar.hs.sc->err == 1 ? KATZ_E_CSR : KATZ_E_HIP;
@@ -1789,7 +1824,7 @@ int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* 
   // FP32 eta tables per graph, from the graph's own longest row (the same
   // tables a single-graph call builds, so results match it bitwise).
   if (fp32)
-    for (int i = 0; i < count; ++i) fp32_tables(S[i], h_dmax[i], max_iter);
+    for (int i = 0; i < count; ++i) fp32_tables(S[i], h_dmax[i], max_iter, b.bb);
   std::vector<double> h_alpha(count), h_sigma((size_t)count * stride, 0.0), h_sigsum((size_t)count * stride, 0.0);
   std::vector<int> h_clog2(count), h_exp((size_t)count * stride, 0);
   std::vector<RunScalars> h_sc(count);
@@ -2127,7 +2162,7 @@ int bin_rows(katz_state* st, Bins& b, RunScalars* sc, const int32_t* ids, long l
   KATZ_HIP(launch_reset_flags(sc, s));
   b.nblocks = (int)std::max<long long>(1, (count + kWG - 1) / kWG);
   KATZ_HIP(launch_prep_rows(ids, count, st->row_off, st->row_len, b.blk, b.nblocks, b.scan_sums, b.scan_totals,
-                            b.desc, b.segs, b.huge, sc, s));
+                            b.desc, b.segs, b.huge, sc, b.bb, s));
   KATZ_HIP(hipMemcpyAsync(st->hs.sc, sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
   KATZ_HIP(hipStreamSynchronize(s));
   if (st->hs.sc->err) return KATZ_E_HIP;
@@ -2320,7 +2355,7 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
     long long* blk = dalloc<long long>(st, (size_t)(NUM_BINS + 2) * tmp.nblocks);
     if (!blk) return KATZ_E_OOM;
     KATZ_HIP(launch_reset_flags(st->w.sc, s));
-    KATZ_HIP(launch_prep_count(rp, g->row_ptr_64, n, g->nnz, blk, tmp.nblocks, st->w.sc, s));
+    KATZ_HIP(launch_prep_count(rp, g->row_ptr_64, n, g->nnz, blk, tmp.nblocks, st->w.sc, BinBounds{}, s));
     KATZ_HIP(launch_check_col_range(col, g->nnz, n, st->w.sc, s));
     KATZ_HIP(hipMemcpyAsync(st->hs.sc, st->w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
     KATZ_HIP(hipStreamSynchronize(s));
@@ -2328,18 +2363,20 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
     if (st->hs.sc->err) return KATZ_E_CSR;
   }
 
-  // A directed state keeps its graph's reverse for Algorithm 2's search; an
-  // inbound state ranks the reverse of the caller's graph (Section 2.1) and
-  // keeps the caller's graph, rows sorted, as that reverse.  Both come from
-  // the device transpose (reversed rows list their sources in ascending
-  // order): fwd = g or T(g), rev = T(g) or T(T(g)).
+  // Every state transposes its graph once on the device (reversed rows list
+  // their sources in ascending order).  An undirected graph must equal its
+  // transpose: that is the symmetry check (one pass over the arcs instead of a
+  // search per arc).  A directed state keeps the transpose as the reverse
+  // graph for Algorithm 2's search; an inbound state ranks the reverse of the
+  // caller's graph (Section 2.1) and keeps the caller's graph, rows sorted by
+  // a second transpose, as that reverse: fwd = g or T(g), rev = T(g) or T(T(g)).
   const void* fwd_rp = rp;
   int fwd_rp64 = g->row_ptr_64;
   const int32_t* fwd_col = col;
   const void* rev_rp = nullptr;
   const int32_t* rev_col = nullptr;
   std::vector<void*> temps;
-  if (st->directed) {
+  {
     const long long nnz = g->nnz;
     char* scratch = dalloc<char>(st, transpose_scratch_bytes(n, nnz));
     long long* t1_ptr = dalloc<long long>(st, n + 1);
@@ -2347,7 +2384,13 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
     if (!scratch || !t1_ptr || !t1_col) return KATZ_E_OOM;
     temps.insert(temps.end(), {scratch, t1_ptr, t1_col});
     KATZ_HIP(launch_transpose(rp, g->row_ptr_64, col, n, nnz, scratch, t1_ptr, t1_col, s));
-    if (!st->inbound) {
+    if (!st->directed) {
+      KATZ_HIP(launch_reset_flags(st->w.sc, s));
+      KATZ_HIP(launch_csr_equal(rp, g->row_ptr_64, col, t1_ptr, t1_col, n, nnz, st->w.sc, s));
+      KATZ_HIP(hipMemcpyAsync(st->hs.sc, st->w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+      KATZ_HIP(hipStreamSynchronize(s));
+      if (st->hs.sc->err) return KATZ_E_CSR;   // not symmetric (or rows not sorted)
+    } else if (!st->inbound) {
       rev_rp = t1_ptr;
       rev_col = t1_col;
     } else {
@@ -2372,13 +2415,17 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
   if (rp_tmp) dfree(st, rp_tmp);
   if (col_tmp) dfree(st, col_tmp);
 
-  // Bins of the whole graph, strict checks (sorted rows, no loops, symmetry).
+  // Bins of the whole graph, strict checks (sorted rows, no repeats, no loops).
+  // The state keeps the length classes of its creation for every later
+  // binning, so its re-walks sum rows as a static run with that tuning does.
+  st->bins.bb = st->lbins.bb = bounds_of(current_tuning());
   KATZ_TRY(alloc_bins(st, st->bins));
   KATZ_TRY(alloc_bins(st, st->lbins));
   KATZ_TRY(bin_rows(st, st->bins, st->w.sc, nullptr, n, s));
   KATZ_HIP(launch_reset_flags(st->w.sc, s));
-  KATZ_HIP(launch_validate_strict(st->bins.desc, n, st->bins.segs, st->bins.seg_total, st->bins.huge, st->pool,
-                                  st->directed ? 0 : 1, st->row_off, st->row_len, st->w.sc, s));
+  // Symmetry was checked against the transpose above.
+  KATZ_HIP(launch_validate_strict(st->bins.desc, n, st->bins.segs, st->bins.seg_total, st->bins.huge, st->pool, 0,
+                                  st->row_off, st->row_len, st->w.sc, s));
   KATZ_HIP(hipMemcpyAsync(st->hs.sc, st->w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
   KATZ_HIP(hipStreamSynchronize(s));
   if (st->hs.sc->err) return KATZ_E_CSR;
@@ -2457,6 +2504,9 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
   st->clist = dalloc<int32_t>(st, n);
   st->counter = dalloc<int>(st, 1);
   st->frontier_arcs = dalloc<unsigned long long>(st, 1);
+  st->foff = dalloc<long long>(st, n);
+  st->fsums = dalloc<long long>(st, scan_sums_capacity(n));
+  st->ftotal = dalloc<long long>(st, 1);
   st->dmax_dev = dalloc<int>(st, 1);
   st->err_dev = dalloc<int>(st, 1);
   st->min_bits = dalloc<unsigned long long>(st, 1);
@@ -2467,6 +2517,7 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
   if (!w.c || !w.act[0] || !w.act[1] || !w.keys || !w.cand_key[0] || !w.cand_key[1] || !w.cand_v[0] ||
       !w.cand_v[1] || !w.hist || !w.xmax32 || !w.xmax64 || !w.sigma || !w.sigma_sum || !w.top_sorted ||
       !w.top_lo || !w.top_up || !w.mark || !w.rest_bits || !st->level_of || !st->clist || !st->counter || !st->frontier_arcs ||
+      !st->foff || !st->fsums || !st->ftotal ||
       !st->dmax_dev || !st->err_dev || !st->min_bits || !st->tmark || !st->out_ids || !st->out_lo || !st->out_up)
     return KATZ_E_OOM;
   KATZ_HIP(hipMemsetAsync(w.mark, 0, n, s));
@@ -2851,7 +2902,8 @@ int apply_batch(katz_state* st, const PreparedBatch& pb, katz_result* out, hipSt
         // In-neighbours: the reverse graph's rows (an undirected graph's own).
         const SlackRef in = st->directed ? rev_csr(st) : fwd_csr(st);
         KATZ_HIP(launch_frontier_expand(st->clist + fbeg, csize - fbeg, in.row_off, in.row_len, in.pool,
-                                        st->level_of, i, st->clist, st->counter, st->frontier_arcs, s));
+                                        st->level_of, i, st->clist, st->counter, st->frontier_arcs, st->foff,
+                                        st->fsums, st->ftotal, f_arcs, s));
         int c2 = 0;
         KATZ_HIP(hipMemcpyAsync(&c2, st->counter, sizeof(int), hipMemcpyDeviceToHost, s));
         KATZ_HIP(hipMemcpyAsync(&f_arcs, st->frontier_arcs, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
@@ -3122,7 +3174,7 @@ KATZ_EXPORT int katz_autotune(int32_t count, const katz_csr* g, const katz_param
   katz_tuning pick = saved;
   double pick_ms = 1e300;
   int rc = KATZ_OK;
-  for (const katz_tuning& t : cand) {
+  auto trial = [&](const katz_tuning& t) {
     {
       std::lock_guard<std::mutex> lk(katz::g_tuning.mu);
       katz::g_tuning.t = t;
@@ -3133,11 +3185,28 @@ KATZ_EXPORT int katz_autotune(int32_t count, const katz_csr* g, const katz_param
       rc = katz_rank_static(count, g, p, out.data(), nullptr, stream);
       ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
-    if (rc < 0) break;
-    if (ms < pick_ms) {
+    if (rc >= 0 && ms < pick_ms) {
       pick_ms = ms;
       pick = t;
     }
+  };
+  // Stage 1: launch shapes with the caller's row-length classes.
+  for (const katz_tuning& t : cand) {
+    trial(t);
+    if (rc < 0) break;
+  }
+  // Stage 2: row-length classes (bin_bounds) with the chosen shape: the
+  // defaults, fewer lanes per row (longer classes), more lanes per row.
+  static const int kBins[][6] = {{0, 0, 0, 0, 0, 0},
+                                 {4, 8, 16, 64, 256, 2048},
+                                 {2, 4, 8, 16, 64, 512},
+                                 {4, 8, 24, 48, 192, 1536}};
+  const katz_tuning shape = pick;
+  for (int i = 0; i < (int)(sizeof(kBins) / sizeof(kBins[0])) && rc >= 0; ++i) {
+    katz_tuning t = shape;
+    for (int j = 0; j < 6; ++j) t.bin_bounds[j] = kBins[i][j];
+    if (std::equal(t.bin_bounds, t.bin_bounds + 6, shape.bin_bounds)) continue;   // timed in stage 1
+    trial(t);
   }
   (void)hipFree(ids);
   (void)hipFree(lo);

@@ -768,7 +768,7 @@ hipError_t launch_batch_prep(const long long* gbase, const void* const* grp, con
                              const long long* gabase, const int32_t* const* gcol, int count, long long total_n,
                              long long total_nnz, int* gid_of, long long* blk, int nblocks, long long* sums,
                              long long* totals, RowDesc* desc, SegDesc* segs, HugeRow* huge, RunScalars* sc,
-                             int validate, hipStream_t s) {
+                             int validate, const BinBounds& bb, hipStream_t s) {
   const unsigned nb = (unsigned)std::max<long long>(1, (total_n + kWG - 1) / kWG);
   hipLaunchKernelGGL(fill_gid, dim3(nb), dim3(kWG), 0, s, gbase, count, total_n, gid_of);
   hipLaunchKernelGGL(batch_csr_ends, dim3((count + 255) / 256), dim3(256), 0, s, grp, grp64, gbase, gnnz, count, sc);
@@ -777,11 +777,11 @@ hipError_t launch_batch_prep(const long long* gbase, const void* const* grp, con
     hipLaunchKernelGGL(batch_col_range, dim3(gx), dim3(kWG), 0, s, gcol, gabase, gbase, count, sc);
   }
   const BatchRows rows{gid_of, gbase, grp, grp64, gnnz};
-  hipLaunchKernelGGL(prep_count<BatchRows>, dim3(nblocks), dim3(kWG), 0, s, rows, total_n, blk, nblocks, sc);
+  hipLaunchKernelGGL(prep_count<BatchRows>, dim3(nblocks), dim3(kWG), 0, s, rows, total_n, blk, nblocks, sc, bb);
   hipError_t e = launch_prep_scan(blk, nblocks, sums, totals, sc, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(prep_scatter<BatchRows>, dim3(nblocks), dim3(kWG), 0, s, rows, total_n, (const long long*)blk,
-                     nblocks, desc, segs, huge, sc);
+                     nblocks, desc, segs, huge, sc, bb);
   return hipGetLastError();
 }
 

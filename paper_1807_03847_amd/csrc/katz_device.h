@@ -10,14 +10,14 @@
 
 namespace katz {
 
-__host__ __device__ constexpr int bin_of_len(long long len) {
+__host__ __device__ inline int bin_of_len(long long len, const BinBounds& bb) {
   return len <= 0 ? BIN_EMPTY
-       : len <= 4 ? BIN_G4
-       : len <= 8 ? BIN_G8
-       : len <= 16 ? BIN_G16
-       : len <= 32 ? BIN_G32
-       : len <= kShortRowMax ? BIN_W16
-       : len <= kWaveRowMax ? BIN_W64
+       : len <= bb.g4 ? BIN_G4
+       : len <= bb.g8 ? BIN_G8
+       : len <= bb.g16 ? BIN_G16
+       : len <= bb.g32 ? BIN_G32
+       : len <= bb.w16 ? BIN_W16
+       : len <= bb.w64 ? BIN_W64
        : len <= kBlockRowMax ? BIN_B256
        : BIN_HUGE;
 }
@@ -250,7 +250,7 @@ namespace {
 // ---------------------------------------------------------------------------
 template <class Rows>
 __global__ void __launch_bounds__(kWG) prep_count(Rows rows, long long count, long long* blk, int nblocks,
-                                                  RunScalars* sc) {
+                                                  RunScalars* sc, BinBounds bb) {
   __shared__ int cnt[NUM_BINS + 1];
   if (threadIdx.x <= NUM_BINS) cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(kWG) prep_count(Rows rows, long long count, lo
     if (!rows.get(i, row, off, len)) {
       bad = true;
     } else {
-      const int b = bin_of_len(len);
+      const int b = bin_of_len(len, bb);
       atomicAdd(&cnt[b], 1);
       if (b == BIN_HUGE) atomicAdd(&cnt[NUM_BINS], (int)((len + kSeg - 1) / kSeg));
       dmax = (int)len;
@@ -286,7 +286,7 @@ __global__ void __launch_bounds__(kWG) prep_count(Rows rows, long long count, lo
 template <class Rows>
 __global__ void __launch_bounds__(kWG) prep_scatter(Rows rows, long long count, const long long* blk,
                                                     int nblocks, RowDesc* desc, SegDesc* segs,
-                                                    HugeRow* huge, RunScalars* sc) {
+                                                    HugeRow* huge, RunScalars* sc, BinBounds bb) {
   if (sc->err) return;
   __shared__ int wcnt[NUM_BINS][kWG / kWave];
   __shared__ int wseg[kWG / kWave];
@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(kWG) prep_scatter(Rows rows, long long count, 
   int nseg = 0;
   if (i < count) {
     rows.get(i, row, off, len);
-    bin = bin_of_len(len);
+    bin = bin_of_len(len, bb);
     if (bin == BIN_HUGE) nseg = (int)((len + kSeg - 1) / kSeg);
   }
   int rank_in_wave = 0;

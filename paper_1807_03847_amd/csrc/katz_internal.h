@@ -66,6 +66,14 @@ constexpr int kBinLanes[NUM_BINS] = {kWG, kWG, 64, 16, 4, 2, 1, 1, 1};   // empt
 // Rows per workgroup-sized group of a short-row bin.
 constexpr int bin_rows_per_group(int bin) { return kWG / kBinLanes[bin]; }
 
+// Longest row of each length class below BIN_B256 (a row goes to the first
+// class whose bound it does not exceed; BIN_B256 ends at kBlockRowMax, longer
+// rows are segmented).  The bounds decide how many lanes sum a row, so they
+// fix the order of its additions; katz_tuning.bin_bounds sets them.
+struct BinBounds {
+  int g4 = 4, g8 = 8, g16 = 16, g32 = 32, w16 = kShortRowMax, w64 = kWaveRowMax;
+};
+
 struct RowDesc {
   int64_t off;
   int32_t row;
@@ -280,12 +288,13 @@ struct BatchWalk {
 
 // ---- launchers (katz_kernels.hip) ----------------------------------------
 hipError_t launch_prep_count(const void* row_ptr, int row_ptr_64, int64_t n, int64_t nnz,
-                             long long* blk, int nblocks, RunScalars* sc, hipStream_t s);
+                             long long* blk, int nblocks, RunScalars* sc, const BinBounds& bb, hipStream_t s);
 hipError_t launch_prep_scan(long long* blk, int nblocks, long long* sums, long long* totals, RunScalars* sc,
                             hipStream_t s);
 hipError_t launch_prep_scatter(const void* row_ptr, int row_ptr_64, int64_t n,
                                const long long* blk, int nblocks, RowDesc* desc,
-                               SegDesc* segs, HugeRow* huge, RunScalars* sc, hipStream_t s);
+                               SegDesc* segs, HugeRow* huge, RunScalars* sc, const BinBounds& bb,
+                               hipStream_t s);
 // segs / nseg / huge: the bins' segments of rows longer than kBlockRowMax
 // (their symmetry is checked segment by segment).
 hipError_t launch_validate_strict(const RowDesc* desc, long long n, const SegDesc* segs, long long nseg,
@@ -329,7 +338,7 @@ hipError_t launch_init_run(RunScalars* sc, int64_t n, double* sigma, double* sig
 
 hipError_t launch_prep_rows(const int32_t* ids, long long count, const long long* off, const int* len,
                             long long* blk, int nblocks, long long* sums, long long* totals, RowDesc* desc,
-                            SegDesc* segs, HugeRow* huge, RunScalars* sc, hipStream_t s);
+                            SegDesc* segs, HugeRow* huge, RunScalars* sc, const BinBounds& bb, hipStream_t s);
 
 // ---- dynamic update (katz_dynamic.hip) ----------------------------------------
 hipError_t launch_scan_ll(const long long* in, long long count, long long* out, long long* sums,
@@ -364,9 +373,13 @@ hipError_t launch_merge_rows(const int32_t* rows, long long t, const long long* 
 hipError_t launch_copy_back_rows(const int32_t* rows, long long t, const long long* sbase, const long long* new_len,
                                  const long long* dest_off, const int* dest_cap, const int32_t* scratch,
                                  long long* row_off, int* row_len, int* row_cap, int32_t* pool, hipStream_t s);
+// foff: f entries of scratch, sums: scan_sums_capacity(f), total: 1.
+// arcs_hint: the host's estimate of the frontier's arcs (0: unknown), which
+// only sizes the grid.
 hipError_t launch_frontier_expand(const int32_t* frontier, long long f, const long long* row_off, const int* row_len,
                                   const int32_t* pool, int* level_of, int level, int32_t* next, int* next_count,
-                                  unsigned long long* next_arcs, hipStream_t s);
+                                  unsigned long long* next_arcs, long long* foff, long long* sums, long long* total,
+                                  unsigned long long arcs_hint, hipStream_t s);
 hipError_t launch_set_levels(const int32_t* rows, long long t, int* level_of, int level, hipStream_t s);
 hipError_t launch_clear_levels(const int32_t* rows, long long t, int* level_of, hipStream_t s);
 hipError_t launch_c_from_history(const int32_t* rows, long long count, double* const* X, int r, double* c,
@@ -393,7 +406,7 @@ hipError_t launch_batch_prep(const long long* gbase, const void* const* grp, con
                              const long long* gabase, const int32_t* const* gcol, int count, long long total_n,
                              long long total_nnz, int* gid_of, long long* blk, int nblocks, long long* sums,
                              long long* totals, RowDesc* desc, SegDesc* segs, HugeRow* huge, RunScalars* sc,
-                             int validate, hipStream_t s);
+                             int validate, const BinBounds& bb, hipStream_t s);
 hipError_t launch_batch_dmax(const void* const* grp, const int* grp64, const long long* gbase, int count,
                              long long total_n, int* gdmax, hipStream_t s);
 hipError_t launch_batch_relabel(const RowDesc* desc, long long total, const long long* gbase, int count,
@@ -419,7 +432,7 @@ hipError_t launch_batch_write(const GraphSel* gsel, int count, long long max_n, 
                               double* const* out_lo, double* const* out_up, uint8_t* mark,
                               unsigned long long* rest_bits, hipStream_t s);
 
-int bin_of_host(int64_t len);
+int bin_of_host(int64_t len, const BinBounds& bb);
 
 // ---- vector kernels of katz_solve (katz_linear.hip) -----------------------------
 int linear_reduce_slots();
@@ -432,6 +445,10 @@ size_t transpose_scratch_bytes(long long n, long long nnz);
 // sources in ascending order.  scratch: transpose_scratch_bytes(n, nnz) bytes.
 hipError_t launch_transpose(const void* rp, int rp64, const int32_t* col, long long n, long long nnz, void* scratch,
                             long long* rt_ptr, int32_t* rt_col, hipStream_t s);
+// Sets sc->err when the CSR (rp, col) differs from (rt_ptr, rt_col): with rows
+// sorted, a graph equals its transpose exactly when it is symmetric.
+hipError_t launch_csr_equal(const void* rp, int rp64, const int32_t* col, const long long* rt_ptr,
+                            const int32_t* rt_col, long long n, long long nnz, RunScalars* sc, hipStream_t s);
 hipError_t launch_fill_value(double* x, long long n, double v, hipStream_t s);
 hipError_t launch_foster_step(const double* y, const double* f, double* f_new, long long n, double* slots,
                               double* out, hipStream_t s);

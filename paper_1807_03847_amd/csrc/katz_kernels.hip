@@ -26,7 +26,7 @@
 
 namespace katz {
 
-int bin_of_host(int64_t len) { return bin_of_len(len); }
+int bin_of_host(int64_t len, const BinBounds& bb) { return bin_of_len(len, bb); }
 
 namespace {
 
@@ -1193,13 +1193,13 @@ hipError_t launch_reset_flags(RunScalars* sc, hipStream_t s) {
 // Launchers.
 // ---------------------------------------------------------------------------
 hipError_t launch_prep_count(const void* row_ptr, int row_ptr_64, int64_t n, int64_t nnz, long long* blk,
-                             int nblocks, RunScalars* sc, hipStream_t s) {
+                             int nblocks, RunScalars* sc, const BinBounds& bb, hipStream_t s) {
   if (row_ptr_64)
     hipLaunchKernelGGL(prep_count<CsrRows<int64_t>>, dim3(nblocks), dim3(kWG), 0, s,
-                       CsrRows<int64_t>{(const int64_t*)row_ptr, (long long)nnz}, (long long)n, blk, nblocks, sc);
+                       CsrRows<int64_t>{(const int64_t*)row_ptr, (long long)nnz}, (long long)n, blk, nblocks, sc, bb);
   else
     hipLaunchKernelGGL(prep_count<CsrRows<int32_t>>, dim3(nblocks), dim3(kWG), 0, s,
-                       CsrRows<int32_t>{(const int32_t*)row_ptr, (long long)nnz}, (long long)n, blk, nblocks, sc);
+                       CsrRows<int32_t>{(const int32_t*)row_ptr, (long long)nnz}, (long long)n, blk, nblocks, sc, bb);
   return hipGetLastError();
 }
 
@@ -1217,35 +1217,35 @@ hipError_t launch_prep_scan(long long* blk, int nblocks, long long* sums, long l
 
 hipError_t launch_prep_scatter(const void* row_ptr, int row_ptr_64, int64_t n, const long long* blk,
                                int nblocks, RowDesc* desc, SegDesc* segs, HugeRow* huge, RunScalars* sc,
-                               hipStream_t s) {
+                               const BinBounds& bb, hipStream_t s) {
   if (row_ptr_64)
     hipLaunchKernelGGL(prep_scatter<CsrRows<int64_t>>, dim3(nblocks), dim3(kWG), 0, s,
                        CsrRows<int64_t>{(const int64_t*)row_ptr, 0}, (long long)n, blk, nblocks, desc, segs, huge,
-                       sc);
+                       sc, bb);
   else
     hipLaunchKernelGGL(prep_scatter<CsrRows<int32_t>>, dim3(nblocks), dim3(kWG), 0, s,
                        CsrRows<int32_t>{(const int32_t*)row_ptr, 0}, (long long)n, blk, nblocks, desc, segs, huge,
-                       sc);
+                       sc, bb);
   return hipGetLastError();
 }
 
 hipError_t launch_prep_rows(const int32_t* ids, long long count, const long long* off, const int* len,
                             long long* blk, int nblocks, long long* sums, long long* totals, RowDesc* desc,
-                            SegDesc* segs, HugeRow* huge, RunScalars* sc, hipStream_t s) {
+                            SegDesc* segs, HugeRow* huge, RunScalars* sc, const BinBounds& bb, hipStream_t s) {
   if (ids) {
     const ListRows rows{ids, off, len};
-    hipLaunchKernelGGL(prep_count<ListRows>, dim3(nblocks), dim3(kWG), 0, s, rows, count, blk, nblocks, sc);
+    hipLaunchKernelGGL(prep_count<ListRows>, dim3(nblocks), dim3(kWG), 0, s, rows, count, blk, nblocks, sc, bb);
     const hipError_t e = launch_prep_scan(blk, nblocks, sums, totals, sc, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(prep_scatter<ListRows>, dim3(nblocks), dim3(kWG), 0, s, rows, count, (const long long*)blk,
-                       nblocks, desc, segs, huge, sc);
+                       nblocks, desc, segs, huge, sc, bb);
   } else {
     const SlackRows rows{off, len};
-    hipLaunchKernelGGL(prep_count<SlackRows>, dim3(nblocks), dim3(kWG), 0, s, rows, count, blk, nblocks, sc);
+    hipLaunchKernelGGL(prep_count<SlackRows>, dim3(nblocks), dim3(kWG), 0, s, rows, count, blk, nblocks, sc, bb);
     const hipError_t e = launch_prep_scan(blk, nblocks, sums, totals, sc, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(prep_scatter<SlackRows>, dim3(nblocks), dim3(kWG), 0, s, rows, count, (const long long*)blk,
-                       nblocks, desc, segs, huge, sc);
+                       nblocks, desc, segs, huge, sc, bb);
   }
   return hipGetLastError();
 }

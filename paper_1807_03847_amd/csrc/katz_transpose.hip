@@ -140,6 +140,18 @@ __global__ void __launch_bounds__(kWG) row_starts(const int32_t* key, long long 
   for (long long v = lo; v <= hi; ++v) rt_ptr[v] = p;
 }
 
+// Sets sc->err when a CSR differs from another (offsets or column ids).
+template <class OffT>
+__global__ void __launch_bounds__(kWG) csr_equal(const OffT* rp, const int32_t* col, const long long* rt_ptr,
+                                                 const int32_t* rt_col, long long n, long long nnz, RunScalars* sc) {
+  const long long stride = (long long)gridDim.x * kWG;
+  bool bad = false;
+  for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i <= n; i += stride)
+    bad = bad || (long long)rp[i] != rt_ptr[i];
+  for (long long j = (long long)blockIdx.x * kWG + threadIdx.x; j < nnz; j += stride) bad = bad || col[j] != rt_col[j];
+  if (bad) atomicOr(&sc->err, 1);
+}
+
 int bits_for(long long n) {
   int b = 1;
   while (b < 31 && (1ll << b) < n) ++b;
@@ -213,6 +225,18 @@ hipError_t launch_transpose(const void* rp, int rp64, const int32_t* col, long l
   }
   const unsigned rg = (unsigned)((nnz + 1 + kWG - 1) / kWG);
   hipLaunchKernelGGL(row_starts, dim3(rg), dim3(kWG), 0, s, kin, nnz, n, rt_ptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_equal(const void* rp, int rp64, const int32_t* col, const long long* rt_ptr,
+                            const int32_t* rt_col, long long n, long long nnz, RunScalars* sc, hipStream_t s) {
+  const long long work = std::max(n + 1, nnz);
+  const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>(4096, (work + kWG - 1) / kWG));
+  if (rp64)
+    hipLaunchKernelGGL(csr_equal<long long>, dim3(grid), dim3(kWG), 0, s, (const long long*)rp, col, rt_ptr, rt_col, n,
+                       nnz, sc);
+  else
+    hipLaunchKernelGGL(csr_equal<int>, dim3(grid), dim3(kWG), 0, s, (const int*)rp, col, rt_ptr, rt_col, n, nnz, sc);
   return hipGetLastError();
 }
 

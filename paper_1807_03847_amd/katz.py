@@ -72,7 +72,7 @@ class KatzTuning(ctypes.Structure):
     _fields_ = [("hub_bytes", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("batch_blocks_per_cu", ctypes.c_int32), ("batch_tile", ctypes.c_int32),
                 ("batch_xcd", ctypes.c_int32), ("walk_groups", ctypes.c_int32), ("split_hot_bytes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("bin_bounds", ctypes.c_int32 * 6), ("reserved", ctypes.c_int32)]
 
 
 class KatzTiming(ctypes.Structure):
@@ -430,7 +430,7 @@ class Server:
 def _tuning_dict(t):
     return {"hub_bytes": t.hub_bytes, "blocks_per_cu": t.blocks_per_cu, "batch_blocks_per_cu": t.batch_blocks_per_cu,
             "batch_tile": t.batch_tile, "batch_xcd": t.batch_xcd, "walk_groups": t.walk_groups,
-            "split_hot_bytes": t.split_hot_bytes}
+            "split_hot_bytes": t.split_hot_bytes, "bin_bounds": list(t.bin_bounds)}
 
 
 def tuning_get() -> dict:
@@ -443,11 +443,14 @@ def tuning_get() -> dict:
 
 
 def tuning_set(hub_bytes=0, blocks_per_cu=0, batch_blocks_per_cu=0, batch_tile=0, batch_xcd=0,
-               walk_groups=0, split_hot_bytes=0) -> None:
-    """katz_tuning_set (no result depends on it, except on split_hot_bytes)."""
+               walk_groups=0, split_hot_bytes=0, bin_bounds=None) -> None:
+    """katz_tuning_set (no result depends on it, except on split_hot_bytes and
+    bin_bounds, which change the order of additions)."""
+    bb = [int(v) for v in (bin_bounds if bin_bounds is not None else [0] * 6)]
     t = KatzTuning(hub_bytes=int(hub_bytes), blocks_per_cu=int(blocks_per_cu),
                    batch_blocks_per_cu=int(batch_blocks_per_cu), batch_tile=int(batch_tile),
-                   batch_xcd=int(batch_xcd), walk_groups=int(walk_groups), split_hot_bytes=int(split_hot_bytes))
+                   batch_xcd=int(batch_xcd), walk_groups=int(walk_groups), split_hot_bytes=int(split_hot_bytes),
+                   bin_bounds=(ctypes.c_int32 * 6)(*bb))
     rc = lib.katz_tuning_set(ctypes.byref(t))
     if rc < 0:
         raise KatzError(rc)

@@ -49,7 +49,8 @@ int main(void) {
   F(katz_result, separated_fraction)
   F(katz_solve_info, converged) F(katz_solve_info, residual) F(katz_solve_info, alpha_used)
   F(katz_tuning, blocks_per_cu) F(katz_tuning, batch_blocks_per_cu) F(katz_tuning, batch_tile)
-  F(katz_tuning, batch_xcd) F(katz_tuning, walk_groups) F(katz_tuning, split_hot_bytes) F(katz_tuning, reserved)
+  F(katz_tuning, batch_xcd) F(katz_tuning, walk_groups) F(katz_tuning, split_hot_bytes) F(katz_tuning, bin_bounds)
+  F(katz_tuning, reserved)
   F(katz_timing, prep_ms) F(katz_timing, calls) F(katz_timing, renumber_step_ms) F(katz_timing, renumber_step_launches)
   return 0;
 }
@@ -151,7 +152,7 @@ def test_tuning_round_trip_and_limits():
     try:
         katz.tuning_set(16384, 4, 8, 2, 1)
         want = {"hub_bytes": 16384, "blocks_per_cu": 4, "batch_blocks_per_cu": 8, "batch_tile": 2, "batch_xcd": 1,
-                "walk_groups": 0, "split_hot_bytes": 0}
+                "walk_groups": 0, "split_hot_bytes": 0, "bin_bounds": [0] * 6}
         assert katz.tuning_get() == want
         for bad in [(-16, 4, 0, 0), (65552, 4, 0, 0), (100, 4, 0, 0), (16384, 0, 0, 0),
                     (0, 33, 0, 0), (0, -1, 0, 0), (0, 0, 33, 0), (0, 0, -2, 0), (0, 0, 0, 17),
@@ -168,6 +169,15 @@ def test_tuning_round_trip_and_limits():
         assert katz.tuning_get()["split_hot_bytes"] == 1 << 20
         katz.tuning_set(0, 0, 0, 0, 0, 0, 0)
         assert katz.tuning_get()["split_hot_bytes"] == 0
+        # Row-length classes: all 0, or strictly increasing from 1 and below 4096.
+        katz.tuning_set(bin_bounds=[2, 4, 8, 16, 64, 512])
+        assert katz.tuning_get()["bin_bounds"] == [2, 4, 8, 16, 64, 512]
+        for bad in ([0, 8, 16, 32, 128, 1024], [4, 4, 16, 32, 128, 1024], [4, 8, 16, 32, 1024, 128],
+                    [4, 8, 16, 32, 128, 4096], [-1, 8, 16, 32, 128, 1024], [4, 0, 0, 0, 0, 0]):
+            with pytest.raises(katz.KatzError) as e:
+                katz.tuning_set(bin_bounds=bad)
+            assert e.value.code == katz.E_INVALID_ARG
+        assert katz.tuning_get()["bin_bounds"] == [2, 4, 8, 16, 64, 512]
         katz.tuning_set(16384, 4, 8, 2, 1)
         t = katz.KatzTuning(hub_bytes=0, blocks_per_cu=0)
         t.reserved = 1
