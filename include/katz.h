@@ -73,8 +73,13 @@ extern "C" {
 #define KATZ_E_UNSUPPORTED      -8  /* valid request outside what this build supports  */
 #define KATZ_E_SCRATCH          -9  /* katz_rank_static_noalloc: the problem needs more */
                                     /* workspace than the fixed scratch array holds     */
-#define KATZ_E_CANCELLED       -10  /* server: the request was still queued when the    */
-                                    /* server was destroyed; it never ran               */
+#define KATZ_E_CANCELLED       -10  /* server: the request was cancelled (or still      */
+                                    /* queued when the server was destroyed); it never  */
+                                    /* ran                                              */
+#define KATZ_E_TIMEOUT         -11  /* server: the request did not finish within the    */
+                                    /* wait's time limit; its ticket stays valid        */
+#define KATZ_E_BUSY            -12  /* server: the request is on the device or finished */
+                                    /* and can no longer be cancelled                   */
 
 /* ---- precision forms ------------------------------------------------------ */
 #define KATZ_FP64         0  /* walk vector, sums and bounds in FP64 (the plain method)  */
@@ -352,6 +357,16 @@ int katz_server_submit(katz_server* sv, int32_t graph_id, const int32_t* ins_u, 
  * (either pointer may be NULL).  Returns the request's status code. */
 int katz_server_wait(katz_server* sv, int64_t ticket, katz_result* out, double* latency_ms,
                      double* service_ms);
+/* katz_server_wait with a time limit (timeout_ms >= 0): E_TIMEOUT when the
+ * request has not finished by then; the ticket stays valid and may be waited
+ * for again or cancelled.  Other errors as katz_server_wait. */
+int katz_server_wait_for(katz_server* sv, int64_t ticket, int64_t timeout_ms, katz_result* out,
+                         double* latency_ms, double* service_ms);
+/* Cancels a request that has not reached the device: it leaves its graph's
+ * queue, never runs (later requests of the graph do not include its batch),
+ * and its waiter gets E_CANCELLED.  Returns OK, E_BUSY (already on the device
+ * or finished) or E_INVALID_ARG (unknown or already collected ticket). */
+int katz_server_cancel(katz_server* sv, int64_t ticket);
 /* Stops the server: requests that have not started their device half end
  * with E_CANCELLED (a thread blocked in katz_server_wait on one returns that
  * code), requests on the device finish, then the workers stop, the call waits

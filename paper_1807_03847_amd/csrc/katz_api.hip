@@ -13,6 +13,9 @@
 #include <cstdint>
 #include <cstring>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
+#include <dlfcn.h>
 #include <limits>
 #include <mutex>
 #include <numeric>
@@ -277,6 +280,52 @@ int cu_count(int dev) {
   cache[dev] = v;
   return v;
 }
+
+// ---------------------------------------------------------------------------
+// roctx ranges for rocprofv3's marker trace (host side: each call, the enqueue
+// of each iteration, the two halves of an update).  KATZ_ROCTX=1 turns them
+// on: the range functions are then looked up in the ROCm roctx library at run
+// time (no link dependency); without the variable, or without the library,
+// a range costs one test of a null pointer.
+// ---------------------------------------------------------------------------
+struct RoctxApi {
+  int (*push)(const char*) = nullptr;
+  int (*pop)() = nullptr;
+};
+
+const RoctxApi& roctx_api() {
+  static const RoctxApi api = [] {
+    RoctxApi a;
+    const char* e = std::getenv("KATZ_ROCTX");
+    if (!e || std::strcmp(e, "1") != 0) return a;
+    void* h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (!h) h = dlopen("libroctx64.so.4", RTLD_NOW | RTLD_LOCAL);
+    if (!h) return a;
+    a.push = reinterpret_cast<int (*)(const char*)>(dlsym(h, "roctxRangePushA"));
+    a.pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+    if (!a.push || !a.pop) a = RoctxApi{};
+    return a;
+  }();
+  return api;
+}
+
+struct Range {
+  bool on;
+  explicit Range(const char* name) : on(roctx_api().push != nullptr) {
+    if (on) roctx_api().push(name);
+  }
+  Range(const char* name, int v) : on(roctx_api().push != nullptr) {
+    if (!on) return;
+    char buf[96];
+    std::snprintf(buf, sizeof(buf), "%s %d", name, v);
+    roctx_api().push(buf);
+  }
+  ~Range() {
+    if (on) roctx_api().pop();
+  }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 struct CallTimer {
   bool on = false;
@@ -876,6 +925,7 @@ int iterate(Run& run, HostSync& hs, int r_next, bool check_first, hipStream_t s,
   // this loop, so a bound read one pass behind stays valid.
   long long m_known = check_first ? LLONG_MAX : run.n;
   while (!stopped) {
+    const Range range("katz iteration", r);
     const bool small_m = m_known <= kSmallActive;
     if (pass == 0 && check_first) {
       KATZ_TRY(enqueue_select(run, r - 1, s, T, false));
@@ -1173,6 +1223,7 @@ int check_rank_args(const katz_csr* g, const katz_params* p, const katz_result* 
 // timing: whether the call may record the phase timers (events are created).
 int rank_in_arena(Arena& ar, const katz_csr* g, const katz_params* p, katz_result* out, hipStream_t s,
                   bool timing) {
+  const Range range_call("katz_rank_static");
   const int dev = ar.device;
   Plan pl{};
   pl.g = g;
@@ -1354,6 +1405,7 @@ int bounds_one(const katz_csr* g, const katz_params* p, int r_target, double* lo
 }
 
 int bounds_on(const katz_csr* g, const katz_params* p, int r_target, double* lower, double* upper, hipStream_t s) {
+  const Range range_call("katz_bounds");
   int dev = 0;
   KATZ_HIP(hipGetDevice(&dev));
   ArenaLease lease(dev, s);
@@ -1471,6 +1523,7 @@ int solve_one(const katz_csr* g, const katz_params* p, int method, double tol, d
 
 int solve_on(const katz_csr* g, const katz_params* p, int method, double tol, double* scores, katz_solve_info* info,
              hipStream_t s) {
+  const Range range_call("katz_solve");
   int dev = 0;
   KATZ_HIP(hipGetDevice(&dev));
   ArenaLease lease(dev, s);
@@ -1588,6 +1641,7 @@ int solve_on(const katz_csr* g, const katz_params* p, int method, double tol, do
 constexpr int kItersPerGraph = 4;   // iterations captured in one hipGraph
 
 int rank_batch(int count, const katz_csr* g, const katz_params* p, katz_result* out, hipStream_t s) {
+  const Range range_call("katz_rank_static batch");
   const katz_tuning tu_b = current_tuning();   // one setting for the whole call
   const int xcd_groups = tu_b.batch_xcd ? kXcds : 1;
   const int fp32 = p[0].precision == KATZ_FP32_MARGIN;
@@ -2301,6 +2355,7 @@ int rename_slack(katz_state* st, SlackRef c, hipStream_t s) {
 }
 
 int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz_state** stp, hipStream_t s) {
+  const Range range_call("katz_rank_static state");
   KATZ_TRY(check_graph(g));
   KATZ_TRY(check_params(p, g->n, true));
   if (!out || !out->topk_ids || !out->lower || !out->upper) return KATZ_E_INVALID_ARG;
@@ -2730,6 +2785,7 @@ void group_arcs(std::vector<Arc>& ia, std::vector<Arc>& da, RowGroups& g) {
 // still running.
 int prepare_batch(long long n, int mode, const int32_t* ins_u, const int32_t* ins_v, long long n_ins,
                   const int32_t* del_u, const int32_t* del_v, long long n_del, PreparedBatch& pb) {
+  const Range range_call("katz_rank_update host half");
   if (n_ins < 0 || n_del < 0) return KATZ_E_INVALID_ARG;
   if (mode < PAIRS_UNDIRECTED || mode > PAIRS_REVERSED) return KATZ_E_INVALID_ARG;
   if ((n_ins > 0 && (!ins_u || !ins_v)) || (n_del > 0 && (!del_u || !del_v))) return KATZ_E_INVALID_ARG;
@@ -2814,6 +2870,7 @@ long long state_nodes(const katz_state* st) { return st->n; }
 // Device-side half of an update: existence checks against the state's graph,
 // the merge into the slack CSR, the re-walk and the re-certification.
 int apply_batch(katz_state* st, const PreparedBatch& pb, katz_result* out, hipStream_t s) {
+  const Range range_call("katz_rank_update device half");
   if (!out || !out->topk_ids || !out->lower || !out->upper) return KATZ_E_INVALID_ARG;
   if (pb.n != st->n || pb.mode != state_pair_mode(st)) return KATZ_E_INVALID_ARG;
   const long long n = st->n;
@@ -3232,7 +3289,9 @@ KATZ_EXPORT const char* katz_strerror(int code) {
     case KATZ_E_HIP: return "error: HIP runtime failure";
     case KATZ_E_UNSUPPORTED: return "error: unsupported request";
     case KATZ_E_SCRATCH: return "error: the problem needs more workspace than the fixed scratch array holds";
-    case KATZ_E_CANCELLED: return "error: the request was cancelled when the server stopped";
+    case KATZ_E_CANCELLED: return "error: the request was cancelled before it ran";
+    case KATZ_E_TIMEOUT: return "error: the request did not finish within the time limit";
+    case KATZ_E_BUSY: return "error: the request is already on the device or finished";
     default: return "unknown status code";
   }
 }

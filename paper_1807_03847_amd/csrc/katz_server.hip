@@ -187,8 +187,9 @@ void worker_main(katz_server* sv, hipStream_t s) {
                                          rq->dv.data(), (int64_t)rq->du.size(), rq->pb);
       const auto t1 = Clock::now();
       lk.lock();
-      // destroy may have cancelled the request meanwhile (phase DONE).
-      if (sv->stopping || rq->phase != PREPARING) break;
+      if (sv->stopping) break;
+      // katz_server_cancel may have ended the request meanwhile (phase DONE).
+      if (rq->phase != PREPARING) continue;
       rq->prepare_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
       rq->prep_rc = rc;
       rq->phase = PREPARED;
@@ -265,8 +266,12 @@ KATZ_EXPORT int katz_server_submit(katz_server* sv, int32_t graph_id, const int3
   return KATZ_OK;
 }
 
-KATZ_EXPORT int katz_server_wait(katz_server* sv, int64_t ticket, katz_result* out, double* latency_ms,
-                                 double* service_ms) {
+namespace {
+
+// Waits for a request (timeout_ms < 0: without a limit); on completion the
+// ticket is consumed and the result copied out.
+int wait_request(katz_server* sv, int64_t ticket, int64_t timeout_ms, katz_result* out, double* latency_ms,
+                 double* service_ms) {
   if (!sv || !out || !out->topk_ids || !out->lower || !out->upper) return KATZ_E_INVALID_ARG;
   std::shared_ptr<Request> rq;
   {
@@ -275,10 +280,14 @@ KATZ_EXPORT int katz_server_wait(katz_server* sv, int64_t ticket, katz_result* o
     if (it == sv->tickets.end()) return KATZ_E_INVALID_ARG;
     rq = it->second;
     ++sv->waiters;
-    sv->cv_done.wait(lk, [&] { return rq->phase == DONE; });
-    sv->tickets.erase(ticket);
+    const auto done = [&] { return rq->phase == DONE; };
+    bool finished = true;
+    if (timeout_ms < 0) sv->cv_done.wait(lk, done);
+    else finished = sv->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done);
+    if (finished) sv->tickets.erase(ticket);
     --sv->waiters;
     sv->cv_done.notify_all();   // destroy may be waiting for the last waiter
+    if (!finished) return KATZ_E_TIMEOUT;
   }
   const int k = (int)rq->ids.size();
   if (rq->status >= 0) {
@@ -295,6 +304,39 @@ KATZ_EXPORT int katz_server_wait(katz_server* sv, int64_t ticket, katz_result* o
   if (latency_ms) *latency_ms = rq->latency_ms;
   if (service_ms) *service_ms = rq->service_ms;
   return rq->status;
+}
+
+}  // namespace
+
+KATZ_EXPORT int katz_server_wait(katz_server* sv, int64_t ticket, katz_result* out, double* latency_ms,
+                                 double* service_ms) {
+  return wait_request(sv, ticket, -1, out, latency_ms, service_ms);
+}
+
+KATZ_EXPORT int katz_server_wait_for(katz_server* sv, int64_t ticket, int64_t timeout_ms, katz_result* out,
+                                     double* latency_ms, double* service_ms) {
+  if (timeout_ms < 0) return KATZ_E_INVALID_ARG;
+  return wait_request(sv, ticket, timeout_ms, out, latency_ms, service_ms);
+}
+
+KATZ_EXPORT int katz_server_cancel(katz_server* sv, int64_t ticket) {
+  if (!sv) return KATZ_E_INVALID_ARG;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->tickets.find(ticket);
+    if (it == sv->tickets.end()) return KATZ_E_INVALID_ARG;
+    const std::shared_ptr<Request> rq = it->second;
+    if (rq->phase == RUNNING || rq->phase == DONE) return KATZ_E_BUSY;
+    // Not on the device yet: out of its graph's queue, ended for its waiter.
+    // Later requests of the graph run without its batch.  A host half being
+    // prepared meanwhile is dropped by its worker.
+    auto& q = sv->graphs[rq->graph].queue;
+    q.erase(std::remove(q.begin(), q.end(), rq), q.end());
+    finish(sv, *rq, KATZ_E_CANCELLED, Clock::now());
+  }
+  sv->cv_done.notify_all();
+  sv->cv_work.notify_all();
+  return KATZ_OK;
 }
 
 KATZ_EXPORT void katz_server_destroy(katz_server* sv) {

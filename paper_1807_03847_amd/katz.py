@@ -30,6 +30,8 @@ E_HIP = -7
 E_UNSUPPORTED = -8
 E_SCRATCH = -9
 E_CANCELLED = -10
+E_TIMEOUT = -11
+E_BUSY = -12
 
 FP64 = 0
 FP32_MARGIN = 1
@@ -116,6 +118,11 @@ def _load():
     lib.katz_server_wait.restype = ctypes.c_int
     lib.katz_server_wait.argtypes = [vp, i64, ctypes.POINTER(KatzResult), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
+    lib.katz_server_wait_for.restype = ctypes.c_int
+    lib.katz_server_wait_for.argtypes = [vp, i64, i64, ctypes.POINTER(KatzResult), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]
+    lib.katz_server_cancel.restype = ctypes.c_int
+    lib.katz_server_cancel.argtypes = [vp, i64]
     lib.katz_server_destroy.restype = None
     lib.katz_server_destroy.argtypes = [vp]
     lib.katz_timing_enable.restype = None
@@ -399,21 +406,36 @@ class Server:
         self._k[("t", t.value)] = self._k[graph_id]
         return t.value
 
-    def wait(self, ticket):
-        """Returns (RankResult with host arrays, latency_ms, service_ms); raises on errors."""
+    def wait(self, ticket, timeout_ms=None):
+        """Returns (RankResult with host arrays, latency_ms, service_ms); raises on
+        errors.  With timeout_ms, katz_server_wait_for: KatzError(E_TIMEOUT)
+        leaves the ticket valid."""
         import numpy as np
-        k = self._k.pop(("t", ticket))
+        k = self._k[("t", ticket)]
         ids = np.empty(k, dtype=np.int32)
         lo = np.empty(k, dtype=np.float64)
         up = np.empty(k, dtype=np.float64)
         res = KatzResult(topk_ids=ids.ctypes.data, lower=lo.ctypes.data, upper=up.ctypes.data)
         lat = ctypes.c_double(0)
         svc = ctypes.c_double(0)
-        rc = lib.katz_server_wait(ctypes.c_void_p(self._h), int(ticket), ctypes.byref(res), ctypes.byref(lat),
-                                  ctypes.byref(svc))
+        if timeout_ms is None:
+            rc = lib.katz_server_wait(ctypes.c_void_p(self._h), int(ticket), ctypes.byref(res), ctypes.byref(lat),
+                                      ctypes.byref(svc))
+        else:
+            rc = lib.katz_server_wait_for(ctypes.c_void_p(self._h), int(ticket), int(timeout_ms), ctypes.byref(res),
+                                          ctypes.byref(lat), ctypes.byref(svc))
+        if rc != E_TIMEOUT:
+            self._k.pop(("t", ticket), None)
         if rc < 0:
             raise KatzError(rc)
         return _to_result(res, ids, lo, up), lat.value, svc.value
+
+    def cancel(self, ticket) -> int:
+        """katz_server_cancel: OK, or raises KatzError(E_BUSY / E_INVALID_ARG)."""
+        rc = lib.katz_server_cancel(ctypes.c_void_p(self._h), int(ticket))
+        if rc < 0:
+            raise KatzError(rc)
+        return rc
 
     def close(self):
         if self._h:

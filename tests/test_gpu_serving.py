@@ -179,3 +179,59 @@ def test_destroy_cancels_queued_requests():
     assert set(codes) == set(tickets[-6:])
     assert all(c in (katz.OK, katz.E_CANCELLED) for c in codes.values())
     assert katz.E_CANCELLED in codes.values()
+
+
+def test_cancel_and_timed_wait():
+    """katz_server_cancel ends a request that has not reached the device (its
+    waiter gets E_CANCELLED and later requests of the graph run without its
+    batch); a timed wait on unfinished work returns E_TIMEOUT and leaves the
+    ticket valid; a finished or running request cannot be cancelled.  A first
+    request of 200000 edges keeps the single slot busy meanwhile."""
+    katz = K()
+    rng = np.random.default_rng(11)
+    rp, col = sg.rmat(20, seed=9)
+    dmax = sg.max_degree(rp)
+    n = len(rp) - 1
+    keys = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp)) * n + col
+    a = rng.integers(0, n, 700000)
+    b = rng.integers(0, n, 700000)
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    kk = np.unique(lo * n + hi)
+    pos = np.minimum(np.searchsorted(keys, kk), keys.size - 1)
+    kk = rng.permutation(kk[(keys[pos] != kk) & (kk // n != kk % n)])
+    pairs = np.stack([kk // n, kk % n], 1)
+    big, b1, b2, b3 = pairs[:200000], pairs[200000:200040], pairs[200040:200080], pairs[200080:200120]
+    alpha = 1.0 / (1 + dmax + 1000)
+    say("serving cancel")
+    sv = katz.Server(slots=1)
+    gid, _ = sv.add_graph(torch.from_numpy(rp), torch.from_numpy(col), 20, alpha=alpha, eps=1e-9,
+                          degree_cap=dmax + 1000)
+    t0 = sv.submit(gid, big, None)
+    t1 = sv.submit(gid, b1, None)
+    t2 = sv.submit(gid, b2, None)
+    t3 = sv.submit(gid, b3, None)
+    with pytest.raises(katz.KatzError) as e:
+        sv.wait(t0, timeout_ms=0)                      # the big batch is still running
+    assert e.value.code == katz.E_TIMEOUT
+    assert sv.cancel(t2) == katz.OK
+    with pytest.raises(katz.KatzError) as e:
+        sv.cancel(t2)                                  # already ended
+    assert e.value.code == katz.E_BUSY
+    r0, _, _ = sv.wait(t0)
+    r1, _, _ = sv.wait(t1)
+    with pytest.raises(katz.KatzError) as e:
+        sv.wait(t2)
+    assert e.value.code == katz.E_CANCELLED
+    r3, _, _ = sv.wait(t3, timeout_ms=600000)
+    with pytest.raises(katz.KatzError) as e:
+        sv.cancel(t3)                                  # collected: unknown ticket
+    assert e.value.code == katz.E_INVALID_ARG
+    sv.close()
+    # The same sequence without the cancelled batch, on a state of its own.
+    st, _ = katz.create_state(torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda(), 20, alpha=alpha, eps=1e-9,
+                              degree_cap=dmax + 1000)
+    for got, batch in ((r0, big), (r1, b1), (r3, b3)):
+        ref = st.update(batch, None)
+        np.testing.assert_array_equal(np.asarray(got.topk), ref.topk.cpu().numpy())
+        np.testing.assert_array_equal(np.asarray(got.lower), ref.lower.cpu().numpy())
+    st.free()
