@@ -322,6 +322,24 @@ int katz_solve(const katz_csr* g, const katz_params* p, int32_t method, double t
 /* Frees a state from katz_rank_static (NULL is ignored). */
 void katz_state_free(katz_state* st);
 
+/*
+ * katz_state_save / katz_state_load -- checkpoint and resume of a dynamic state
+ * (Section 4: Algorithm 2 continues from Algorithm 1's walk counts, bounds and
+ * active set).  save writes the state's graph (slack CSR, and the reverse CSR
+ * of a directed state), its renumbering, the walk history x_1..x_r, c_r, the
+ * active set M and the run flags to the file at `path` (host file system); it
+ * waits for the state's device work first.  load recreates the state on the
+ * current device: updates applied to it then give bitwise the results they
+ * give on the saved state.  A file written by a library with another state
+ * layout is refused.  Errors: E_INVALID_ARG (null arguments, a file that
+ * cannot be opened, read or written, or is not a state file of this layout),
+ * E_OOM, E_HIP.
+ */
+int katz_state_save(katz_state* st, const char* path);
+int katz_state_load(const char* path, katz_state** out, void* stream);
+/* The node count n and the k of a state (for a caller that restored one). */
+int katz_state_size(const katz_state* st, int64_t* n, int32_t* k);
+
 /* A static, human-readable description of a status code. */
 const char* katz_strerror(int code);
 

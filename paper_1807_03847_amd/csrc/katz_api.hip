@@ -2354,6 +2354,58 @@ int rename_slack(katz_state* st, SlackRef c, hipStream_t s) {
   return KATZ_OK;
 }
 
+// The buffers of a state's runs (bound arguments, active lists, selection,
+// re-walk scratch, output staging), zeroed where a run expects zeros.  The
+// bins must exist (the partial sums are sized by them).
+int alloc_run_buffers(katz_state* st, hipStream_t s) {
+  Work& w = st->w;
+  const long long n = st->n;
+  KATZ_TRY(alloc_partial(st));
+  w.c = dalloc<double>(st, n);
+  w.act[0] = dalloc<int32_t>(st, n);
+  w.act[1] = dalloc<int32_t>(st, n);
+  w.keys = dalloc<unsigned long long>(st, n);
+  w.cand_key[0] = dalloc<unsigned long long>(st, n);
+  w.cand_key[1] = dalloc<unsigned long long>(st, n);
+  w.cand_v[0] = dalloc<int32_t>(st, n);
+  w.cand_v[1] = dalloc<int32_t>(st, n);
+  w.hist = dalloc<unsigned>(st, 2 * kDigits);
+  w.xmax32 = dalloc<unsigned>(st, st->max_iter + 1);
+  w.xmax64 = dalloc<unsigned long long>(st, st->max_iter + 1);
+  w.sigma = dalloc<double>(st, st->max_iter + 1);
+  w.sigma_sum = dalloc<double>(st, st->max_iter + 1);
+  w.top_sorted = dalloc<int32_t>(st, st->k);
+  w.top_lo = dalloc<double>(st, st->k);
+  w.top_up = dalloc<double>(st, st->k);
+  w.mark = dalloc<uint8_t>(st, n);
+  w.rest_bits = dalloc<unsigned long long>(st, 1);
+  st->level_of = dalloc<int>(st, n);
+  st->clist = dalloc<int32_t>(st, n);
+  st->counter = dalloc<int>(st, 1);
+  st->frontier_arcs = dalloc<unsigned long long>(st, 1);
+  st->foff = dalloc<long long>(st, n);
+  st->fsums = dalloc<long long>(st, scan_sums_capacity(n));
+  st->ftotal = dalloc<long long>(st, 1);
+  st->dmax_dev = dalloc<int>(st, 1);
+  st->err_dev = dalloc<int>(st, 1);
+  st->min_bits = dalloc<unsigned long long>(st, 1);
+  st->tmark = dalloc<uint8_t>(st, n);
+  st->out_ids = dalloc<int32_t>(st, st->k);
+  st->out_lo = dalloc<double>(st, st->k);
+  st->out_up = dalloc<double>(st, st->k);
+  if (!w.c || !w.act[0] || !w.act[1] || !w.keys || !w.cand_key[0] || !w.cand_key[1] || !w.cand_v[0] ||
+      !w.cand_v[1] || !w.hist || !w.xmax32 || !w.xmax64 || !w.sigma || !w.sigma_sum || !w.top_sorted ||
+      !w.top_lo || !w.top_up || !w.mark || !w.rest_bits || !st->level_of || !st->clist || !st->counter || !st->frontier_arcs ||
+      !st->foff || !st->fsums || !st->ftotal ||
+      !st->dmax_dev || !st->err_dev || !st->min_bits || !st->tmark || !st->out_ids || !st->out_lo || !st->out_up)
+    return KATZ_E_OOM;
+  KATZ_HIP(hipMemsetAsync(w.mark, 0, n, s));
+  KATZ_HIP(hipMemsetAsync(st->tmark, 0, n, s));
+  KATZ_HIP(hipMemsetAsync(st->level_of, 0, sizeof(int) * n, s));
+  KATZ_HIP(launch_init_run(w.sc, n, w.sigma, w.sigma_sum, w.xmax32, w.xmax64, st->max_iter, w.hist, s));
+  return KATZ_OK;
+}
+
 int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz_state** stp, hipStream_t s) {
   const Range range_call("katz_rank_static state");
   KATZ_TRY(check_graph(g));
@@ -2535,50 +2587,8 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
   if (!(st->alpha * (double)st->degree_cap < 1.0)) return KATZ_E_ALPHA;
 
   // Run buffers.
+  KATZ_TRY(alloc_run_buffers(st, s));
   Work& w = st->w;
-  KATZ_TRY(alloc_partial(st));
-  w.c = dalloc<double>(st, n);
-  w.act[0] = dalloc<int32_t>(st, n);
-  w.act[1] = dalloc<int32_t>(st, n);
-  w.keys = dalloc<unsigned long long>(st, n);
-  w.cand_key[0] = dalloc<unsigned long long>(st, n);
-  w.cand_key[1] = dalloc<unsigned long long>(st, n);
-  w.cand_v[0] = dalloc<int32_t>(st, n);
-  w.cand_v[1] = dalloc<int32_t>(st, n);
-  w.hist = dalloc<unsigned>(st, 2 * kDigits);
-  w.xmax32 = dalloc<unsigned>(st, st->max_iter + 1);
-  w.xmax64 = dalloc<unsigned long long>(st, st->max_iter + 1);
-  w.sigma = dalloc<double>(st, st->max_iter + 1);
-  w.sigma_sum = dalloc<double>(st, st->max_iter + 1);
-  w.top_sorted = dalloc<int32_t>(st, st->k);
-  w.top_lo = dalloc<double>(st, st->k);
-  w.top_up = dalloc<double>(st, st->k);
-  w.mark = dalloc<uint8_t>(st, n);
-  w.rest_bits = dalloc<unsigned long long>(st, 1);
-  st->level_of = dalloc<int>(st, n);
-  st->clist = dalloc<int32_t>(st, n);
-  st->counter = dalloc<int>(st, 1);
-  st->frontier_arcs = dalloc<unsigned long long>(st, 1);
-  st->foff = dalloc<long long>(st, n);
-  st->fsums = dalloc<long long>(st, scan_sums_capacity(n));
-  st->ftotal = dalloc<long long>(st, 1);
-  st->dmax_dev = dalloc<int>(st, 1);
-  st->err_dev = dalloc<int>(st, 1);
-  st->min_bits = dalloc<unsigned long long>(st, 1);
-  st->tmark = dalloc<uint8_t>(st, n);
-  st->out_ids = dalloc<int32_t>(st, st->k);
-  st->out_lo = dalloc<double>(st, st->k);
-  st->out_up = dalloc<double>(st, st->k);
-  if (!w.c || !w.act[0] || !w.act[1] || !w.keys || !w.cand_key[0] || !w.cand_key[1] || !w.cand_v[0] ||
-      !w.cand_v[1] || !w.hist || !w.xmax32 || !w.xmax64 || !w.sigma || !w.sigma_sum || !w.top_sorted ||
-      !w.top_lo || !w.top_up || !w.mark || !w.rest_bits || !st->level_of || !st->clist || !st->counter || !st->frontier_arcs ||
-      !st->foff || !st->fsums || !st->ftotal ||
-      !st->dmax_dev || !st->err_dev || !st->min_bits || !st->tmark || !st->out_ids || !st->out_lo || !st->out_up)
-    return KATZ_E_OOM;
-  KATZ_HIP(hipMemsetAsync(w.mark, 0, n, s));
-  KATZ_HIP(hipMemsetAsync(st->tmark, 0, n, s));
-  KATZ_HIP(hipMemsetAsync(st->level_of, 0, sizeof(int) * n, s));
-  KATZ_HIP(launch_init_run(w.sc, n, w.sigma, w.sigma_sum, w.xmax32, w.xmax64, st->max_iter, w.hist, s));
 
   CallTimer T;
   T.call_begin(s);
@@ -3010,6 +3020,203 @@ int apply_batch(katz_state* st, const PreparedBatch& pb, katz_result* out, hipSt
   return write_result(run, st->hs, out, st->out_ids, st->out_lo, st->out_up, s, T);
 }
 
+// ---------------------------------------------------------------------------
+// Saving and restoring a state (Algorithm 2 resumes from Algorithm 1's walk
+// counts, bounds and active set: a restored state continues exactly where the
+// saved one stood).  The file holds a header of sizes and scalars, then the
+// arrays: the slack CSR (and a directed state's reverse CSR) as offsets,
+// lengths, capacities and the used part of the pool, the renumbering maps,
+// the walk history x_1..x_r, c_r, the active set M, the per-level maxima and
+// the run's device flags.  A file records the library's layout version and
+// the size of the flag block, and is refused by a library that differs.
+// ---------------------------------------------------------------------------
+constexpr char kStateMagic[8] = {'K', 'A', 'T', 'Z', 'S', 'T', 'A', 'T'};
+constexpr int64_t kStateVersion = 1;
+
+struct StateHeader {
+  char magic[8];
+  int64_t version, sc_bytes;
+  int64_t n, nnz, k, max_iter, degree_cap, r, cur, directed, inbound, renumbered, dmax, m;
+  int64_t pool_used, rpool_used;
+  double alpha, eps;
+  int32_t bb[6];
+  int32_t pad;
+};
+
+struct File {
+  FILE* f = nullptr;
+  ~File() {
+    if (f) std::fclose(f);
+  }
+};
+
+// Device array <-> file through a host buffer.
+template <class T>
+int write_dev(FILE* f, const T* dev, size_t count) {
+  if (count == 0) return KATZ_OK;
+  std::vector<T> h(count);
+  KATZ_HIP(hipMemcpy(h.data(), dev, sizeof(T) * count, hipMemcpyDeviceToHost));
+  return std::fwrite(h.data(), sizeof(T), count, f) == count ? KATZ_OK : KATZ_E_INVALID_ARG;
+}
+
+template <class T>
+int read_dev(FILE* f, T* dev, size_t count) {
+  if (count == 0) return KATZ_OK;
+  std::vector<T> h(count);
+  if (std::fread(h.data(), sizeof(T), count, f) != count) return KATZ_E_INVALID_ARG;
+  KATZ_HIP(hipMemcpy(dev, h.data(), sizeof(T) * count, hipMemcpyHostToDevice));
+  return KATZ_OK;
+}
+
+int write_slack(FILE* f, const katz_state* st, bool rev) {
+  const long long n = st->n;
+  KATZ_TRY(write_dev(f, rev ? st->rrow_off : st->row_off, n));
+  KATZ_TRY(write_dev(f, rev ? st->rrow_len : st->row_len, n));
+  KATZ_TRY(write_dev(f, rev ? st->rrow_cap : st->row_cap, n));
+  return write_dev(f, rev ? st->rpool : st->pool, (size_t)(rev ? st->rpool_used : st->pool_used));
+}
+
+int read_slack(FILE* f, katz_state* st, SlackRef c, long long used) {
+  const long long n = st->n;
+  c.row_off = dalloc<long long>(st, n);
+  c.row_len = dalloc<int>(st, n);
+  c.row_cap = dalloc<int>(st, n);
+  c.pool_used = used;
+  c.pool_cap = used + used / 8 + 4096;
+  c.pool = dalloc<int32_t>(st, c.pool_cap);
+  if (!c.row_off || !c.row_len || !c.row_cap || !c.pool) return KATZ_E_OOM;
+  KATZ_TRY(read_dev(f, c.row_off, n));
+  KATZ_TRY(read_dev(f, c.row_len, n));
+  KATZ_TRY(read_dev(f, c.row_cap, n));
+  return read_dev(f, c.pool, (size_t)used);
+}
+
+int save_state(katz_state* st, const char* path) {
+  if (!st || !path) return KATZ_E_INVALID_ARG;
+  KATZ_HIP(hipSetDevice(st->device));
+  KATZ_HIP(hipDeviceSynchronize());
+  RunScalars sc{};
+  KATZ_HIP(hipMemcpy(&sc, st->w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost));
+  StateHeader h{};
+  std::memcpy(h.magic, kStateMagic, sizeof(h.magic));
+  h.version = kStateVersion;
+  h.sc_bytes = sizeof(RunScalars);
+  h.n = st->n;
+  h.nnz = st->nnz;
+  h.k = st->k;
+  h.max_iter = st->max_iter;
+  h.degree_cap = st->degree_cap;
+  h.r = st->r;
+  h.cur = st->cur;
+  h.directed = st->directed;
+  h.inbound = st->inbound;
+  h.renumbered = st->ext_of ? 1 : 0;
+  h.dmax = st->bins.dmax;
+  h.m = sc.m;
+  h.pool_used = st->pool_used;
+  h.rpool_used = st->directed ? st->rpool_used : 0;
+  h.alpha = st->alpha;
+  h.eps = st->eps;
+  const BinBounds& bb = st->bins.bb;
+  const int32_t bbv[6] = {bb.g4, bb.g8, bb.g16, bb.g32, bb.w16, bb.w64};
+  std::memcpy(h.bb, bbv, sizeof(bbv));
+  File file;
+  file.f = std::fopen(path, "wb");
+  if (!file.f) return KATZ_E_INVALID_ARG;
+  if (std::fwrite(&h, sizeof(h), 1, file.f) != 1) return KATZ_E_INVALID_ARG;
+  if (std::fwrite(&sc, sizeof(sc), 1, file.f) != 1) return KATZ_E_INVALID_ARG;
+  KATZ_TRY(write_slack(file.f, st, false));
+  if (st->directed) KATZ_TRY(write_slack(file.f, st, true));
+  if (st->ext_of) {
+    KATZ_TRY(write_dev(file.f, st->ext_of, st->n));
+    KATZ_TRY(write_dev(file.f, st->int_of, st->n));
+  }
+  for (long long i = 1; i <= st->r; ++i) KATZ_TRY(write_dev(file.f, st->X[i], st->n));
+  KATZ_TRY(write_dev(file.f, st->w.c, st->n));
+  KATZ_TRY(write_dev(file.f, st->w.act[st->cur], (size_t)std::max(sc.m, 0)));
+  KATZ_TRY(write_dev(file.f, st->w.xmax64, (size_t)st->max_iter + 1));
+  return std::fflush(file.f) == 0 ? KATZ_OK : KATZ_E_INVALID_ARG;
+}
+
+int load_state(const char* path, katz_state** stp, hipStream_t s) {
+  if (!path || !stp) return KATZ_E_INVALID_ARG;
+  File file;
+  file.f = std::fopen(path, "rb");
+  if (!file.f) return KATZ_E_INVALID_ARG;
+  StateHeader h{};
+  if (std::fread(&h, sizeof(h), 1, file.f) != 1) return KATZ_E_INVALID_ARG;
+  if (std::memcmp(h.magic, kStateMagic, sizeof(h.magic)) != 0 || h.version != kStateVersion ||
+      h.sc_bytes != (int64_t)sizeof(RunScalars))
+    return KATZ_E_INVALID_ARG;
+  if (h.n < 1 || h.n > INT32_MAX || h.k < 1 || h.k > h.n || h.max_iter < 1 || h.r < 1 || h.r > h.max_iter ||
+      h.m < 0 || h.m > h.n || (h.cur != 0 && h.cur != 1) || h.pool_used < 0 || h.rpool_used < 0)
+    return KATZ_E_INVALID_ARG;
+  RunScalars sc{};
+  if (std::fread(&sc, sizeof(sc), 1, file.f) != 1) return KATZ_E_INVALID_ARG;
+  int dev = 0;
+  KATZ_HIP(hipGetDevice(&dev));
+  katz_state* st = new katz_state;
+  struct Guard {
+    katz_state*& p;
+    bool keep = false;
+    ~Guard() {
+      if (!keep) delete p;
+    }
+  } guard{st};
+  st->device = dev;
+  st->n = h.n;
+  st->nnz = h.nnz;
+  st->k = (int)h.k;
+  st->max_iter = (int)h.max_iter;
+  st->degree_cap = h.degree_cap;
+  st->r = (int)h.r;
+  st->cur = (int)h.cur;
+  st->directed = (int)h.directed;
+  st->inbound = (int)h.inbound;
+  st->alpha = h.alpha;
+  st->eps = h.eps;
+  KATZ_TRY(st->hs.init());
+  const long long n = st->n;
+  st->w.sc = dalloc<RunScalars>(st, 1);
+  st->sc2 = dalloc<RunScalars>(st, 1);
+  if (!st->w.sc || !st->sc2) return KATZ_E_OOM;
+  KATZ_TRY(read_slack(file.f, st, fwd_csr(st), h.pool_used));
+  if (st->directed) KATZ_TRY(read_slack(file.f, st, rev_csr(st), h.rpool_used));
+  if (h.renumbered) {
+    st->ext_of = dalloc<int32_t>(st, n);
+    st->int_of = dalloc<int32_t>(st, n);
+    if (!st->ext_of || !st->int_of) return KATZ_E_OOM;
+    KATZ_TRY(read_dev(file.f, st->ext_of, n));
+    KATZ_TRY(read_dev(file.f, st->int_of, n));
+  }
+  BinBounds bb;
+  bb.g4 = h.bb[0];
+  bb.g8 = h.bb[1];
+  bb.g16 = h.bb[2];
+  bb.g32 = h.bb[3];
+  bb.w16 = h.bb[4];
+  bb.w64 = h.bb[5];
+  st->bins.bb = st->lbins.bb = bb;
+  KATZ_TRY(alloc_bins(st, st->bins));
+  KATZ_TRY(alloc_bins(st, st->lbins));
+  st->bins.dmax = (int)h.dmax;
+  st->bins_stale = true;   // binned before the first whole-graph walk
+  st->S.alpha = st->alpha;
+  set_gamma(st->S, (int)h.dmax);
+  KATZ_TRY(alloc_run_buffers(st, s));
+  KATZ_TRY(ensure_levels(st, st->r));
+  for (long long i = 1; i <= st->r; ++i) KATZ_TRY(read_dev(file.f, st->X[i], n));
+  KATZ_TRY(read_dev(file.f, st->w.c, n));
+  KATZ_TRY(read_dev(file.f, st->w.act[st->cur], (size_t)h.m));
+  KATZ_TRY(read_dev(file.f, st->w.xmax64, (size_t)st->max_iter + 1));
+  KATZ_HIP(hipStreamSynchronize(s));   // alloc_run_buffers initialised the flags on s
+  KATZ_HIP(hipMemcpy(st->w.sc, &sc, sizeof(RunScalars), hipMemcpyHostToDevice));
+  *st->hs.sc = sc;
+  guard.keep = true;
+  *stp = st;
+  return KATZ_OK;
+}
+
 int update_state(katz_state* st, const int32_t* ins_u, const int32_t* ins_v, long long n_ins, const int32_t* del_u,
                  const int32_t* del_v, long long n_del, katz_result* out, hipStream_t s) {
   if (!out || !out->topk_ids || !out->lower || !out->upper) return KATZ_E_INVALID_ARG;
@@ -3142,6 +3349,20 @@ KATZ_EXPORT int katz_solve(const katz_csr* g, const katz_params* p, int32_t meth
 }
 
 KATZ_EXPORT void katz_state_free(katz_state* st) { delete st; }
+
+KATZ_EXPORT int katz_state_save(katz_state* st, const char* path) { return katz::save_state(st, path); }
+
+KATZ_EXPORT int katz_state_load(const char* path, katz_state** out, void* stream) {
+  if (out) *out = nullptr;
+  return katz::load_state(path, out, (hipStream_t)stream);
+}
+
+KATZ_EXPORT int katz_state_size(const katz_state* st, int64_t* n, int32_t* k) {
+  if (!st) return KATZ_E_INVALID_ARG;
+  if (n) *n = st->n;
+  if (k) *k = st->k;
+  return KATZ_OK;
+}
 
 KATZ_EXPORT void katz_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(katz::g_timing.mu);

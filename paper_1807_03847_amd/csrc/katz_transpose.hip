@@ -14,11 +14,12 @@
 //                  stored digit-major, count[v * tiles + t];
 //   (scan)         an exclusive scan of count gives every (value, tile) its
 //                  first output slot;
-//   radix_scatter  each tile places its arcs in input order: round j takes
-//                  arcs j*kWG .. j*kWG + kWG - 1 of the tile, waves find their
-//                  lanes' ranks among equal digits with ballots, and per-value
-//                  running counts in LDS carry the order across waves and
-//                  rounds.
+//   radix_scatter  each tile orders its arcs by digit in LDS, input order
+//                  kept: round j takes arcs j*kRadixWG .. of the tile, waves
+//                  find their lanes' ranks among equal digits with ballots,
+//                  and per-value running counts carry the order across waves
+//                  and rounds; the tile then leaves in that order, each
+//                  value's arcs as one contiguous run.
 // Afterwards row_starts turns the sorted targets into the row offsets.
 #include <algorithm>
 
@@ -29,8 +30,10 @@ namespace {
 
 constexpr int kRadixMaxBits = 8;
 constexpr int kRadixBins = 1 << kRadixMaxBits;
+constexpr int kRadixWG = 1024;                               // threads of the radix kernels
+constexpr int kRadixWaves = kRadixWG / kWave;
 constexpr int kTileRounds = 16;
-constexpr long long kTile = (long long)kWG * kTileRounds;   // arcs per tile
+constexpr long long kTile = (long long)kRadixWG * kTileRounds;   // arcs per tile
 constexpr int kExpandPer = 16;                              // arcs per thread of expand_sources
 
 // src[j] = the row of arc j, for kExpandPer consecutive arcs per thread: one
@@ -62,41 +65,71 @@ __device__ __forceinline__ unsigned digit_of(int32_t key, int shift, unsigned ma
   return ((unsigned)key >> shift) & mask;
 }
 
-__global__ void __launch_bounds__(kWG) radix_count(const int32_t* key, long long nnz, int shift, int bits,
-                                                   long long tiles, long long* count) {
+__global__ void __launch_bounds__(kRadixWG) radix_count(const int32_t* key, long long nnz, int shift, int bits,
+                                                        long long tiles, long long* count) {
   __shared__ unsigned h[kRadixBins];
   const unsigned mask = (1u << bits) - 1u;
-  for (int d = threadIdx.x; d < kRadixBins; d += kWG) h[d] = 0;
+  for (int d = threadIdx.x; d < kRadixBins; d += kRadixWG) h[d] = 0;
   __syncthreads();
   const long long base = (long long)blockIdx.x * kTile;
   for (int j = 0; j < kTileRounds; ++j) {
-    const long long i = base + (long long)j * kWG + threadIdx.x;
+    const long long i = base + (long long)j * kRadixWG + threadIdx.x;
     if (i < nnz) atomicAdd(&h[digit_of(key[i], shift, mask)], 1u);
   }
   __syncthreads();
-  for (int d = threadIdx.x; d <= (int)mask; d += kWG) count[(long long)d * tiles + blockIdx.x] = h[d];
+  for (int d = threadIdx.x; d <= (int)mask; d += kRadixWG) count[(long long)d * tiles + blockIdx.x] = h[d];
 }
 
 // Places the tile's arcs at their sorted positions, stable.  first: the
-// exclusive scan of count (first output slot of each (value, tile)).
-__global__ void __launch_bounds__(kWG) radix_scatter(const int32_t* key_in, const int32_t* val_in, long long nnz,
-                                                     int shift, int bits, long long tiles, const long long* first,
-                                                     int32_t* key_out, int32_t* val_out) {
-  __shared__ long long base[kRadixBins];           // next free slot of each value for this tile
-  __shared__ int wcnt[kWG / kWave][kRadixBins];    // this round's count of each value per wave
+// exclusive scan of count (first output slot of each (value, tile)).  The
+// tile is first ordered by digit in LDS (input order kept inside a digit),
+// then written out in that order, so each digit's arcs of the tile leave as
+// one contiguous run instead of lane-by-lane scattered words.
+__global__ void __launch_bounds__(kRadixWG) radix_scatter(const int32_t* key_in, const int32_t* val_in, long long nnz,
+                                                          int shift, int bits, long long tiles,
+                                                          const long long* first, int32_t* key_out,
+                                                          int32_t* val_out) {
+  extern __shared__ __align__(16) int32_t stage[];      // kTile keys, then kTile values
+  int32_t* sk = stage;
+  int32_t* sv = stage + kTile;
+  __shared__ long long gbase[kRadixBins];                // global first slot of each value for this tile
+  __shared__ int lbase[kRadixBins];                      // tile-local first slot of each value
+  __shared__ int run[kRadixBins];                        // arcs of each value placed so far
+  __shared__ int wcnt[kRadixWaves][kRadixBins];          // this round's count of each value per wave
   const unsigned mask = (1u << bits) - 1u;
-  for (int d = threadIdx.x; d <= (int)mask; d += kWG) base[d] = first[(long long)d * tiles + blockIdx.x];
-  const int w = threadIdx.x / kWave;
+  const int nvals = (int)mask + 1;
+  const long long scanned = (long long)nvals * tiles;
+  const int t = threadIdx.x;
+  // This tile's count of value d is the step of the scan to the next entry.
+  if (t < nvals) {
+    const long long idx = (long long)t * tiles + blockIdx.x;
+    const long long nxt = idx + 1 < scanned ? first[idx + 1] : nnz;
+    gbase[t] = first[idx];
+    lbase[t] = (int)(nxt - first[idx]);
+    run[t] = 0;
+  }
+  __syncthreads();
+  if (t == 0) {   // exclusive scan of the tile's counts (at most 256 values)
+    int acc = 0;
+    for (int d = 0; d < nvals; ++d) {
+      const int c = lbase[d];
+      lbase[d] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  const int w = t / kWave;
   const int lane = lane_id();
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   const long long tile0 = (long long)blockIdx.x * kTile;
+  const int tile_len = (int)(nnz - tile0 < kTile ? nnz - tile0 : kTile);
   for (int j = 0; j < kTileRounds; ++j) {
-    const long long i = tile0 + (long long)j * kWG + threadIdx.x;
-    const bool valid = i < nnz;
+    const int li = j * kRadixWG + t;
+    const bool valid = li < tile_len;
     int32_t k = 0, v = 0;
     if (valid) {
-      k = key_in[i];
-      v = val_in[i];
+      k = key_in[tile0 + li];
+      v = val_in[tile0 + li];
     }
     const unsigned d = digit_of(k, shift, mask);
     // Lanes of this wave with the same digit: intersect the ballots of every
@@ -107,26 +140,32 @@ __global__ void __launch_bounds__(kWG) radix_scatter(const int32_t* key_in, cons
       same &= ((d >> b) & 1u) ? on : ~on;
     }
     const int rank = __popcll(same & below);
-    for (int x = threadIdx.x; x < (kWG / kWave) * kRadixBins; x += kWG) (&wcnt[0][0])[x] = 0;
+    for (int x = t; x < kRadixWaves * kRadixBins; x += kRadixWG) (&wcnt[0][0])[x] = 0;
     __syncthreads();
     if (valid && rank == 0) wcnt[w][d] = __popcll(same);
     __syncthreads();
-    long long pos = 0;
     if (valid) {
-      pos = base[d] + rank;
+      int pos = lbase[d] + run[d] + rank;
       for (int u = 0; u < w; ++u) pos += wcnt[u][d];
+      sk[pos] = k;
+      sv[pos] = v;
     }
-    __syncthreads();   // every lane has read base[] before it moves on
-    for (int x = threadIdx.x; x <= (int)mask; x += kWG) {
+    __syncthreads();   // every lane has read run[] before it moves on
+    if (t < nvals) {
       int add = 0;
-      for (int u = 0; u < kWG / kWave; ++u) add += wcnt[u][x];
-      base[x] += add;
+      for (int u = 0; u < kRadixWaves; ++u) add += wcnt[u][t];
+      run[t] += add;
     }
-    if (valid) {
-      key_out[pos] = k;
-      val_out[pos] = v;
-    }
-    __syncthreads();   // base[] updated before the next round reads it
+    __syncthreads();   // run[] updated before the next round reads it
+  }
+  // The tile in digit order: consecutive slots of one value go to
+  // consecutive global positions.
+  for (int li = t; li < tile_len; li += kRadixWG) {
+    const int32_t k = sk[li];
+    const unsigned d = digit_of(k, shift, mask);
+    const long long pos = gbase[d] + (li - lbase[d]);
+    key_out[pos] = k;
+    val_out[pos] = sv[li];
   }
 }
 
@@ -214,11 +253,11 @@ hipError_t launch_transpose(const void* rp, int rp64, const int32_t* col, long l
     const int set = (passes - 1 - q) & 1;
     int32_t* kout = kbuf[set];
     int32_t* vout = vbuf[set];
-    hipLaunchKernelGGL(radix_count, dim3((unsigned)tiles), dim3(kWG), 0, s, kin, nnz, shift, bits, tiles, cnt);
+    hipLaunchKernelGGL(radix_count, dim3((unsigned)tiles), dim3(kRadixWG), 0, s, kin, nnz, shift, bits, tiles, cnt);
     const hipError_t e = launch_scan_ll(cnt, (long long)(1 << bits) * tiles, cnt, sums, total, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(radix_scatter, dim3((unsigned)tiles), dim3(kWG), 0, s, kin, vin, nnz, shift, bits, tiles,
-                       (const long long*)cnt, kout, vout);
+    hipLaunchKernelGGL(radix_scatter, dim3((unsigned)tiles), dim3(kRadixWG), sizeof(int32_t) * 2 * kTile, s, kin,
+                       vin, nnz, shift, bits, tiles, (const long long*)cnt, kout, vout);
     kin = kout;
     vin = vout;
     shift += bits;

@@ -123,6 +123,12 @@ def _load():
                                          ctypes.POINTER(ctypes.c_double)]
     lib.katz_server_cancel.restype = ctypes.c_int
     lib.katz_server_cancel.argtypes = [vp, i64]
+    lib.katz_state_save.restype = ctypes.c_int
+    lib.katz_state_save.argtypes = [vp, ctypes.c_char_p]
+    lib.katz_state_load.restype = ctypes.c_int
+    lib.katz_state_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp), vp]
+    lib.katz_state_size.restype = ctypes.c_int
+    lib.katz_state_size.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]
     lib.katz_server_destroy.restype = None
     lib.katz_server_destroy.argtypes = [vp]
     lib.katz_timing_enable.restype = None
@@ -331,6 +337,12 @@ class State:
             raise KatzError(rc)
         return _to_result(res, ids, lo, up)
 
+    def save(self, path) -> None:
+        """katz_state_save: writes the state to a file (a checkpoint)."""
+        rc = lib.katz_state_save(ctypes.c_void_p(self._h), os.fsencode(path))
+        if rc < 0:
+            raise KatzError(rc)
+
     def free(self):
         if self._h:
             lib.katz_state_free(ctypes.c_void_p(self._h))
@@ -360,6 +372,19 @@ def create_state(row_ptr, col, k, *, alpha=0.0, eps=0.0, max_iter=0, degree_cap=
     if rc < 0:
         raise KatzError(rc)
     return State(handle.value, k, device), _to_result(res, ids, lo, up)
+
+
+def load_state(path, device=None, stream=None) -> State:
+    """katz_state_load: a state restored from a checkpoint file on the current
+    (or given) device."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    h = ctypes.c_void_p(0)
+    rc = lib.katz_state_load(os.fsencode(path), ctypes.byref(h), _stream_handle(stream, dev))
+    if rc < 0:
+        raise KatzError(rc)
+    k = ctypes.c_int32(0)
+    lib.katz_state_size(h, None, ctypes.byref(k))
+    return State(h.value, k.value, dev)
 
 
 class Server:

@@ -348,3 +348,65 @@ def test_host_outputs_match_device_outputs():
                                 undirected=False)
     st_h.free()
     st_d.free()
+
+
+@pytest.mark.parametrize("undirected", [True, False])
+def test_state_save_and_load_resume_bitwise(tmp_path, undirected):
+    """A state saved after two batches and loaded again answers the next batches
+    bitwise as the original state does, and as the oracle's Algorithm 2 does;
+    a truncated or foreign file is refused."""
+    katz = K()
+    rng = np.random.default_rng(4)
+    if undirected:
+        rp, col = sg.rmat(13, seed=5)
+    else:
+        rp, col = sg.rmat_directed(12, 8, seed=6)
+    n = len(rp) - 1
+    dmax = sg.max_degree(rp)
+    alpha = 1.0 / (1 + dmax + 100)
+    say("state save create", undirected)
+    st, _ = katz.create_state(*dev(rp, col), 25, alpha=alpha, eps=1e-9, degree_cap=dmax + 100, undirected=undirected)
+    dyn = oracle.DynamicOracle(rp, col, alpha, k=25, eps=1e-9, undirected=undirected, degree_cap=dmax + 100)
+
+    def batch(size):
+        src = np.repeat(np.arange(n), np.diff(dyn.row_ptr))
+        arcs = np.stack([src, dyn.col], 1)
+        if undirected:
+            arcs = arcs[arcs[:, 0] < arcs[:, 1]]
+        present = set(map(tuple, arcs.tolist()))
+        dels = arcs[rng.choice(len(arcs), size // 3, replace=False)]
+        ins = set()
+        while len(ins) < size:
+            a, b = (int(v) for v in rng.integers(0, n, 2))
+            if undirected:
+                a, b = min(a, b), max(a, b)
+            if a != b and (a, b) not in present:
+                ins.add((a, b))
+        return np.array(sorted(ins)), dels
+
+    for size in (30, 300):
+        ins, dels = batch(size)
+        st.update(ins, dels)
+        dyn.update(ins, dels)
+    path = tmp_path / "state.bin"
+    st.save(path)
+    st2 = katz.load_state(path)
+    for size in (5, 500, 1):
+        ins, dels = batch(size)
+        say("state save batch", undirected, size)
+        a = st.update(ins, dels)
+        b = st2.update(ins, dels)
+        orc = dyn.update(ins, dels)
+        assert torch.equal(a.topk, b.topk) and torch.equal(a.lower, b.lower) and torch.equal(a.upper, b.upper)
+        assert (a.iterations, a.status) == (b.iterations, b.status)
+        assert_topk_parity(b.topk.cpu().numpy(), b.lower.cpu().numpy(), b.upper.cpu().numpy(), orc,
+                           gpu_status=b.status)
+    st.free()
+    st2.free()
+    data = path.read_bytes()
+    (tmp_path / "short.bin").write_bytes(data[:len(data) // 2])
+    (tmp_path / "junk.bin").write_bytes(b"not a state" * 20)
+    for bad in ("short.bin", "junk.bin", "missing.bin"):
+        with pytest.raises(katz.KatzError) as e:
+            katz.load_state(tmp_path / bad)
+        assert e.value.code == katz.E_INVALID_ARG
