@@ -127,11 +127,12 @@ extern "C" {
                                  /* place of the graph.  Directed graphs only; on an    */
                                  /* undirected graph (its own reverse) the flag changes */
                                  /* nothing.  Offsets and column ids are always checked */
-                                 /* before the transpose.  Taken by single-graph calls, */
-                                 /* katz_bounds, katz_solve and states (update pairs    */
-                                 /* (u, v) still denote the caller's arc u -> v);       */
-                                 /* batches and katz_rank_static_noalloc return         */
-                                 /* E_UNSUPPORTED for it.                               */
+                                 /* before the transpose.  Taken by every ranking call, */
+                                 /* batches included, katz_bounds, katz_solve and       */
+                                 /* states (update pairs (u, v) still denote the        */
+                                 /* caller's arc u -> v); katz_rank_static_noalloc      */
+                                 /* returns E_UNSUPPORTED for it (the reverse graph     */
+                                 /* needs a workspace of its own).                      */
 
 /* A graph in compressed sparse row form.  Row v lists the out-neighbours of v:
  * arcs v -> col[j] for row_ptr[v] <= j < row_ptr[v+1].  An undirected graph

@@ -1306,62 +1306,92 @@ bool wants_reverse(const katz_csr* g, const katz_params* p) {
 // (device memory, int64 offsets); p2 holds the parameters for the run on it
 // (the basic checks are done; strict validation, if asked for, runs on gt,
 // which has the same repeated arcs and self-loops as g).
-int reverse_graph(Arena& ar, const katz_csr* g, const katz_params* p, katz_csr& gt, katz_params& p2, hipStream_t s) {
-  const long long n = g->n, nnz = g->nnz;
-  const bool rp_host = !is_device_ptr(g->row_ptr);
-  const bool col_host = nnz > 0 && !is_device_ptr(g->col);
-  const size_t rp_bytes = (size_t)(n + 1) * (g->row_ptr_64 ? 8 : 4);
+int reverse_graphs(Arena& ar, int count, const katz_csr* g, const katz_params* p, std::vector<katz_csr>& gt,
+                   std::vector<katz_params>& p2, hipStream_t s) {
+  gt.assign(g, g + count);
+  p2.assign(p, p + count);
+  // One workspace: per reversed graph its staging and its reverse; the check
+  // flags, bin counts and transpose scratch are shared (used one graph at a time).
+  long long n_max = 1, nnz_max = 0;
+  for (int i = 0; i < count; ++i)
+    if (wants_reverse(&g[i], &p[i])) {
+      n_max = std::max<long long>(n_max, g[i].n);
+      nnz_max = std::max<long long>(nnz_max, g[i].nnz);
+    }
   Bins tmp;
-  bins_caps(tmp, n, nnz);
+  bins_caps(tmp, n_max, nnz_max);
+  struct Place {
+    char* rp_dev = nullptr;
+    int32_t* col_dev = nullptr;
+    long long* rt_ptr = nullptr;
+    int32_t* rt_col = nullptr;
+  };
+  std::vector<Place> pl(count);
   RunScalars* sc = nullptr;
   long long* blk = nullptr;
-  char* rp_dev = nullptr;
-  int32_t* col_dev = nullptr;
-  long long* rt_ptr = nullptr;
-  int32_t* rt_col = nullptr;
   char* scratch = nullptr;
   auto place = [&]() {
     ar.used = 0;
     sc = ar.take<RunScalars>(1);
     blk = ar.take<long long>((size_t)(NUM_BINS + 2) * tmp.nblocks);
-    if (rp_host) rp_dev = ar.take<char>(rp_bytes);
-    if (col_host) col_dev = ar.take<int32_t>(nnz);
-    rt_ptr = ar.take<long long>(n + 1);
-    rt_col = ar.take<int32_t>(std::max<long long>(nnz, 1));
-    scratch = ar.take<char>(transpose_scratch_bytes(n, nnz));
+    scratch = ar.take<char>(transpose_scratch_bytes(n_max, nnz_max));
+    for (int i = 0; i < count; ++i) {
+      if (!wants_reverse(&g[i], &p[i])) continue;
+      const long long n = g[i].n, nnz = g[i].nnz;
+      if (!is_device_ptr(g[i].row_ptr)) pl[i].rp_dev = ar.take<char>((size_t)(n + 1) * (g[i].row_ptr_64 ? 8 : 4));
+      if (nnz > 0 && !is_device_ptr(g[i].col)) pl[i].col_dev = ar.take<int32_t>(nnz);
+      pl[i].rt_ptr = ar.take<long long>(n + 1);
+      pl[i].rt_col = ar.take<int32_t>(std::max<long long>(nnz, 1));
+    }
   };
   ar.measuring = true;
   place();
   ar.measuring = false;
   KATZ_TRY(ar.grow(ar.used));
   place();
-  const void* rp = g->row_ptr;
-  const int32_t* col = g->col;
-  if (rp_host) {
-    KATZ_HIP(hipMemcpyAsync(rp_dev, g->row_ptr, rp_bytes, hipMemcpyHostToDevice, s));
-    rp = rp_dev;
+  for (int i = 0; i < count; ++i) {
+    if (!wants_reverse(&g[i], &p[i])) continue;
+    const long long n = g[i].n, nnz = g[i].nnz;
+    const void* rp = g[i].row_ptr;
+    const int32_t* col = g[i].col;
+    if (pl[i].rp_dev) {
+      KATZ_HIP(hipMemcpyAsync(pl[i].rp_dev, g[i].row_ptr, (size_t)(n + 1) * (g[i].row_ptr_64 ? 8 : 4),
+                              hipMemcpyHostToDevice, s));
+      rp = pl[i].rp_dev;
+    }
+    if (pl[i].col_dev) {
+      KATZ_HIP(hipMemcpyAsync(pl[i].col_dev, g[i].col, (size_t)nnz * 4, hipMemcpyHostToDevice, s));
+      col = pl[i].col_dev;
+    }
+    Bins bi;
+    bins_caps(bi, n, nnz);
+    KATZ_HIP(launch_reset_flags(sc, s));
+    KATZ_HIP(launch_prep_count(rp, g[i].row_ptr_64, n, nnz, blk, bi.nblocks, sc, BinBounds{}, s));
+    KATZ_HIP(launch_check_col_range(col, nnz, n, sc, s));
+    KATZ_HIP(hipMemcpyAsync(ar.hs.sc, sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipStreamSynchronize(s));
+    if (ar.hs.sc->err) return KATZ_E_CSR;
+    KATZ_HIP(launch_transpose(rp, g[i].row_ptr_64, col, n, nnz, scratch, pl[i].rt_ptr, pl[i].rt_col, s));
+    katz_csr& t = gt[i];
+    t = katz_csr{};
+    t.n = n;
+    t.nnz = nnz;
+    t.row_ptr = pl[i].rt_ptr;
+    t.col = pl[i].rt_col;
+    t.row_ptr_64 = 1;
+    t.undirected = 0;
+    p2[i].flags &= ~KATZ_FLAG_INBOUND;
+    if (p2[i].validate == KATZ_VALIDATE_BASIC) p2[i].validate = KATZ_VALIDATE_NONE;
   }
-  if (col_host) {
-    KATZ_HIP(hipMemcpyAsync(col_dev, g->col, (size_t)nnz * 4, hipMemcpyHostToDevice, s));
-    col = col_dev;
-  }
-  KATZ_HIP(launch_reset_flags(sc, s));
-  KATZ_HIP(launch_prep_count(rp, g->row_ptr_64, n, nnz, blk, tmp.nblocks, sc, BinBounds{}, s));
-  KATZ_HIP(launch_check_col_range(col, nnz, n, sc, s));
-  KATZ_HIP(hipMemcpyAsync(ar.hs.sc, sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
-  KATZ_HIP(hipStreamSynchronize(s));
-  if (ar.hs.sc->err) return KATZ_E_CSR;
-  KATZ_HIP(launch_transpose(rp, g->row_ptr_64, col, n, nnz, scratch, rt_ptr, rt_col, s));
-  gt = katz_csr{};
-  gt.n = n;
-  gt.nnz = nnz;
-  gt.row_ptr = rt_ptr;
-  gt.col = rt_col;
-  gt.row_ptr_64 = 1;
-  gt.undirected = 0;
-  p2 = *p;
-  p2.flags &= ~KATZ_FLAG_INBOUND;
-  if (p2.validate == KATZ_VALIDATE_BASIC) p2.validate = KATZ_VALIDATE_NONE;
+  return KATZ_OK;
+}
+
+int reverse_graph(Arena& ar, const katz_csr* g, const katz_params* p, katz_csr& gt, katz_params& p2, hipStream_t s) {
+  std::vector<katz_csr> gv;
+  std::vector<katz_params> pv;
+  KATZ_TRY(reverse_graphs(ar, 1, g, p, gv, pv, s));
+  gt = gv[0];
+  p2 = pv[0];
   return KATZ_OK;
 }
 
@@ -3309,7 +3339,22 @@ KATZ_EXPORT int katz_rank_static(int32_t count, const katz_csr* g, const katz_pa
     if (!rc && (states || count > 1)) rc = katz::check_lds_criterion(&p[i]);
     if (rc) return rc;
   }
-  if (count > 1 && !states) return katz::rank_batch(count, g, p, out, (hipStream_t)stream);
+  if (count > 1 && !states) {
+    bool any_inbound = false;
+    for (int32_t i = 0; i < count; ++i) any_inbound = any_inbound || katz::wants_reverse(&g[i], &p[i]);
+    if (!any_inbound) return katz::rank_batch(count, g, p, out, (hipStream_t)stream);
+    // Inbound graphs of the batch are ranked on their reverse graphs, built in
+    // one workspace held for the call.
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return KATZ_E_HIP;
+    katz::ArenaLease rl(dev, (hipStream_t)stream);
+    if (rl.rc < 0) return rl.rc;
+    std::vector<katz_csr> g2;
+    std::vector<katz_params> p2;
+    const int rc = katz::reverse_graphs(*rl.a, count, g, p, g2, p2, (hipStream_t)stream);
+    if (rc < 0) return rc;
+    return katz::rank_batch(count, g2.data(), p2.data(), out, (hipStream_t)stream);
+  }
   int worst = KATZ_OK;
   for (int32_t i = 0; i < count; ++i) {
     int rc;

@@ -161,13 +161,37 @@ def test_inbound_edge_cases():
         katz.rank_static(rp_t, col_t, 5, undirected=False, flags=katz.FLAG_INBOUND,
                          validate=katz.VALIDATE_NONE)
     assert e.value.code == katz.E_CSR
-    # Batches and the allocation-free entry point do not take it.
+    # The allocation-free entry point does not take it.
     rp, col = sg.rmat_directed(8, 4, seed=1)
     rp_t, col_t = dev(rp, col)
     with pytest.raises(katz.KatzError) as e:
-        katz.rank_static_batch([(rp_t, col_t, False), (rp_t, col_t, False)],
-                               [dict(k=3, flags=katz.FLAG_INBOUND), dict(k=3)])
-    assert e.value.code == katz.E_UNSUPPORTED
-    with pytest.raises(katz.KatzError) as e:
         katz.rank_static_noalloc(rp_t, col_t, 3, undirected=False, flags=katz.FLAG_INBOUND)
     assert e.value.code == katz.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_inbound_in_a_batch_is_bitwise_the_single_call(precision):
+    """A batch mixing inbound, outbound directed and undirected graphs: each
+    result is bitwise the single-graph call with the same flags, and the
+    inbound ones match the oracle on their reverse graphs."""
+    katz = K()
+    specs = [(sg.rmat_directed(11, 8, seed=1), False, katz.FLAG_INBOUND),
+             (sg.rmat_directed(12, 6, seed=2), False, 0),
+             (sg.rmat(11, seed=3), True, 0),
+             (sg.rmat_directed(10, 8, seed=4), False, katz.FLAG_INBOUND)]
+    eps = 1e-7 if precision == "fp64" else 1e-6
+    graphs, params = [], []
+    for (rp, col), und, flags in specs:
+        graphs.append((*dev(rp, col), und))
+        params.append(dict(k=25, eps=eps, precision=precision, flags=flags))
+    say("inbound batch", precision)
+    outs = katz.rank_static_batch(graphs, params)
+    for ((rp, col), und, flags), (rp_t, col_t, _), res in zip(specs, graphs, outs):
+        one = katz.rank_static(rp_t, col_t, 25, eps=eps, precision=precision, undirected=und, flags=flags)
+        assert torch.equal(res.topk, one.topk) and torch.equal(res.lower, one.lower)
+        assert torch.equal(res.upper, one.upper) and res.iterations == one.iterations
+        if flags:
+            rt, rc = oracle.reverse_graph(rp, col)
+            orc = oracle.rank_static(rt, rc, 1.0 / (1 + sg.max_degree(rt)), 25, eps, undirected=False)
+            assert_topk_parity(res.topk.cpu().numpy(), res.lower.cpu().numpy(), res.upper.cpu().numpy(), orc,
+                               TAU, widened=precision == "fp32", gpu_status=res.status)
