@@ -211,11 +211,13 @@ typedef struct katz_state katz_state;
  * k <= 4096 only.
  *
  * states: NULL, or an array of `count` pointers that receives one new
- *         katz_state per graph for later katz_rank_update calls (FP64 only,
- *         undirected or directed; free each with katz_state_free).
+ *         katz_state per graph for later katz_rank_update calls (FP64 or
+ *         FP32 form, undirected or directed; free each with katz_state_free).
+ *         An FP32 state sizes its scales and error tables (Section 3.3) for
+ *         the degree cap, so they hold for every graph its updates may reach.
  * Errors: E_INVALID_ARG (also: pair ids out of range or equal), E_ALPHA,
  *         E_CSR, E_UNSUPPORTED (a batch or a state with a criterion other than
- *         top-k or k > 4096, FP32 form with states), E_OOM, E_HIP.  With
+ *         top-k or k > 4096), E_OOM, E_HIP.  With
  *         count > 1 the first failing graph's error is returned and nothing is
  *         written for any graph.
  */
@@ -228,6 +230,10 @@ int katz_rank_static(int32_t count, const katz_csr* g, const katz_params* p,
  * graph, recompute the walk counts of every affected node for levels 1..r,
  * patch c_r, recompute the bounds, reactivate nodes whose upper bound reaches
  * min_{x in M} l(x) - eps, and iterate further until converged() holds.
+ * An FP32 state re-walks each level with the scale it was first computed
+ * with, so its recomputed entries carry the history's arithmetic; should a
+ * re-walked entry exceed 2^64 (the scales no longer fit the graph), the
+ * update instead re-runs Algorithm 1 from level 1 on the new graph.
  * On an undirected graph each pair is an edge (both arcs); on a directed graph
  * it is the arc u -> v (the reverse arc is a different arc), and the affected
  * nodes are found by a search over reverse arcs, which the state keeps as a
@@ -363,8 +369,8 @@ typedef struct katz_server katz_server;
 
 /* 1 <= slots <= 64.  Errors: E_INVALID_ARG, E_HIP. */
 int katz_server_create(int32_t slots, int64_t memory_budget, katz_server** out);
-/* Ranks g statically (katz_rank_static with a state, FP64; undirected,
- * directed or inbound) and registers it; writes its initial result to out and its id to graph_id. */
+/* Ranks g statically (katz_rank_static with a state, FP64 or FP32 form;
+ * undirected, directed or inbound) and registers it; writes its initial result to out and its id to graph_id. */
 int katz_server_add_graph(katz_server* sv, const katz_csr* g, const katz_params* p, katz_result* out,
                           int32_t* graph_id);
 /* Queues one batch (arrays are copied before returning) and returns a ticket. */

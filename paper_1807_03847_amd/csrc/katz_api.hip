@@ -635,9 +635,15 @@ struct katz_state {
   katz::Bins lbins;   // one re-walk level
   katz::Work w;
   katz::Scalars S;
-  std::vector<double*> X;          // X[1..]: walk history (X[0] unused)
-  double** X_dev = nullptr;        // device copy of the pointer table
+  std::vector<void*> X;            // X[1..]: walk history (X[0] unused); double, or float x~ (FP32)
+  void** X_dev = nullptr;          // device copy of the pointer table
   int X_dev_cap = 0;
+  // FP32 form (Section 3.3): level i keeps the scale it was first computed
+  // with (from the stored maximum of level i - 1 and the degree cap), so a
+  // re-walk reproduces the history's arithmetic; eta'_i on the device for the
+  // recomputed margins.
+  int fp32 = 0;
+  double* etap_dev = nullptr;
   // Re-walk scratch.
   int* level_of = nullptr;
   int32_t* clist = nullptr;
@@ -662,7 +668,7 @@ struct katz_state {
 
   ~katz_state() {
     for (void* p : owned) (void)hipFree(p);
-    for (double* p : X)
+    for (void* p : X)
       if (p) (void)hipFree(p);
   }
 };
@@ -700,7 +706,11 @@ struct Run {
   const int32_t* col = nullptr;
   Bins* bins = nullptr;
   Work* w = nullptr;
-  katz_state* st = nullptr;   // history mode when set (FP64 only)
+  katz_state* st = nullptr;   // history mode when set
+  // FP32 states: the deg_max bound that fixes the scales and the underflow
+  // term (the degree cap, so that they hold for every graph the state may
+  // reach); 0: the bins' deg_max.
+  long long scale_dmax = 0;
   const int32_t* ext_of = nullptr;   // internal -> caller id (nullptr: identity)
   const int32_t* int_of = nullptr;
   Scalars* S = nullptr;
@@ -725,7 +735,9 @@ struct Run {
   int32_t* ncol = nullptr;
 };
 
-void* x_at(const Run& run, int r) { return run.st ? (void*)run.st->X[r] : run.w->x[r & 1]; }
+void* x_at(const Run& run, int r) { return run.st ? run.st->X[r] : run.w->x[r & 1]; }
+
+long long scale_dmax_of(const Run& run) { return run.scale_dmax ? run.scale_dmax : run.bins->dmax; }
 
 void fill_blocks(IterArgs& ia, const Bins& b, bool write_empty, long long& total) {
   long long blocks[NUM_BINS] = {};
@@ -764,7 +776,7 @@ IterArgs iter_args(const Run& run, const Bins& b, int r, bool rewalk, long long&
   ia.n = (int)run.n;
   ia.r = r;
   ia.count_first = (int)b.count;
-  ia.clog2_dmax = clog2(std::max(run.bins->dmax, 1));
+  ia.clog2_dmax = clog2((int)std::max<long long>(scale_dmax_of(run), 1));
   ia.rewalk = rewalk ? 1 : 0;
   ia.hub_n = rewalk ? 0 : run.hub_n;
   ia.alpha = run.S->alpha;
@@ -801,7 +813,7 @@ BoundArgs bound_args(const Run& run, int r) {
     b.f_hi_s = S.beta_hi * (1.0 + ep) * (1.0 + kap) * (1.0 + 8.0 * kU64);
     // Underflow of x~ entries: at most (deg_max + 1) 2^-126 per entry and level
     // in units of sigma_i, carried through c (r levels) and the bounds (beta).
-    b.tau_coef = 4.0 * (r + S.beta_hi + 2.0) * (run.bins->dmax + 2.0) * 0x1p-126;
+    b.tau_coef = 4.0 * (r + S.beta_hi + 2.0) * ((double)scale_dmax_of(run) + 2.0) * 0x1p-126;
   }
   return b;
 }
@@ -2186,17 +2198,18 @@ long long slack_cap_host(long long len) { return len + std::max(2ll, len >> 3); 
 int ensure_levels(katz_state* st, int r) {
   if ((int)st->X.size() <= r) {
     const int want = std::max(r + 1, (int)st->X.size() + 8);
+    const size_t xs = st->fp32 ? sizeof(float) : sizeof(double);
     while ((int)st->X.size() < want) {
-      double* p = nullptr;
+      void* p = nullptr;
       if (st->X.empty()) {
         st->X.push_back(nullptr);   // level 0 is the implicit all-ones vector
         continue;
       }
-      if (hipMalloc((void**)&p, sizeof(double) * st->n) != hipSuccess) {
+      if (hipMalloc(&p, xs * st->n) != hipSuccess) {
         (void)hipGetLastError();
         return KATZ_E_OOM;
       }
-      if (hipMemset(p, 0, sizeof(double) * st->n) != hipSuccess) return KATZ_E_HIP;
+      if (hipMemset(p, 0, xs * st->n) != hipSuccess) return KATZ_E_HIP;
       st->X.push_back(p);
     }
   }
@@ -2204,10 +2217,10 @@ int ensure_levels(katz_state* st, int r) {
   if (st->X_dev_cap < (int)st->X.size()) {
     if (st->X_dev) dfree(st, st->X_dev);
     st->X_dev_cap = (int)st->X.size() + 8;
-    st->X_dev = dalloc<double*>(st, st->X_dev_cap);
+    st->X_dev = dalloc<void*>(st, st->X_dev_cap);
     if (!st->X_dev) return KATZ_E_OOM;
   }
-  KATZ_HIP(hipMemcpy(st->X_dev, st->X.data(), sizeof(double*) * st->X.size(), hipMemcpyHostToDevice));
+  KATZ_HIP(hipMemcpy(st->X_dev, st->X.data(), sizeof(void*) * st->X.size(), hipMemcpyHostToDevice));
   st->X_dev_synced = (int)st->X.size();
   return KATZ_OK;
 }
@@ -2265,12 +2278,20 @@ int refresh_bins(katz_state* st, hipStream_t s) {
   return KATZ_OK;
 }
 
+// The deg_max bound of an FP32 state's scales and error tables: its degree
+// cap, or n - 1 when that is smaller (rows hold no repeated neighbour and no
+// loop, so no row grows past it).
+long long scale_cap(const katz_state* st) {
+  return std::max<long long>(1, std::min<long long>(st->degree_cap, std::max<long long>(st->n - 1, 1)));
+}
+
 Run state_run(katz_state* st) {
   Run run;
   run.n = st->n;
   run.nnz = st->nnz;
   run.undirected = st->directed ? 0 : 1;
-  run.fp32 = 0;
+  run.fp32 = st->fp32;
+  run.scale_dmax = st->fp32 ? scale_cap(st) : 0;
   run.validate = 0;
   run.col = st->pool;
   run.bins = &st->bins;
@@ -2291,9 +2312,33 @@ Run state_run(katz_state* st) {
     const katz_tuning tu = current_tuning();
     run.walk_grid = (long long)tu.blocks_per_cu * cu_count(st->device);
     run.walk_groups = tu.walk_groups == kWalkGroups ? kWalkGroups : 1;
-    run.hub_n = run.walk_grid > 0 ? (int)std::min<long long>(st->n, tu.hub_bytes / 8) : 0;
+    run.hub_n = run.walk_grid > 0 ? (int)std::min<long long>(st->n, tu.hub_bytes / (st->fp32 ? 4 : 8)) : 0;
   }
   return run;
+}
+
+// Algorithm 1 from level 1 on the state's current graph, in history mode.
+int run_from_start(katz_state* st, katz_result* out, hipStream_t s, CallTimer& T) {
+  Run run = state_run(st);
+  run.first_select = true;
+  run.cur = 0;
+  KATZ_TRY(iterate(run, st->hs, 1, false, s, T));
+  st->r = st->hs.sc->iterations;
+  st->cur = st->hs.sc->cur;
+  return write_result(run, st->hs, out, st->out_ids, st->out_lo, st->out_up, s, T);
+}
+
+// An FP32 state whose re-walk left the range of its stored scales: the whole
+// history is recomputed from level 1 with fresh scales (levels cleared, so
+// rows that are empty now read as 0 at every level).
+int rerun_state(katz_state* st, katz_result* out, hipStream_t s, CallTimer& T) {
+  const Range range("katz state re-run");
+  Work& w = st->w;
+  const size_t xs = st->fp32 ? sizeof(float) : sizeof(double);
+  for (size_t i = 1; i < st->X.size(); ++i) KATZ_HIP(hipMemsetAsync(st->X[i], 0, xs * st->n, s));
+  KATZ_HIP(hipMemsetAsync(w.mark, 0, st->n, s));
+  KATZ_HIP(launch_init_run(w.sc, st->n, w.sigma, w.sigma_sum, w.xmax32, w.xmax64, st->max_iter, w.hist, s));
+  return run_from_start(st, out, s, T);
 }
 
 // Creates a state from a caller CSR and runs Algorithm 1 on it in history mode.
@@ -2423,6 +2468,12 @@ int alloc_run_buffers(katz_state* st, hipStream_t s) {
   st->out_ids = dalloc<int32_t>(st, st->k);
   st->out_lo = dalloc<double>(st, st->k);
   st->out_up = dalloc<double>(st, st->k);
+  if (st->fp32) {
+    w.e = dalloc<float>(st, n);
+    st->etap_dev = dalloc<double>(st, st->max_iter + 1);
+    if (!w.e || !st->etap_dev) return KATZ_E_OOM;
+    KATZ_HIP(hipMemcpy(st->etap_dev, st->S.etap.data(), sizeof(double) * (st->max_iter + 1), hipMemcpyHostToDevice));
+  }
   if (!w.c || !w.act[0] || !w.act[1] || !w.keys || !w.cand_key[0] || !w.cand_key[1] || !w.cand_v[0] ||
       !w.cand_v[1] || !w.hist || !w.xmax32 || !w.xmax64 || !w.sigma || !w.sigma_sum || !w.top_sorted ||
       !w.top_lo || !w.top_up || !w.mark || !w.rest_bits || !st->level_of || !st->clist || !st->counter || !st->frontier_arcs ||
@@ -2441,7 +2492,6 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
   KATZ_TRY(check_graph(g));
   KATZ_TRY(check_params(p, g->n, true));
   if (!out || !out->topk_ids || !out->lower || !out->upper) return KATZ_E_INVALID_ARG;
-  if (p->precision != KATZ_FP64) return KATZ_E_UNSUPPORTED;
   int dev = 0;
   KATZ_HIP(hipGetDevice(&dev));
   katz_state* st = new katz_state;
@@ -2457,6 +2507,7 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
   st->nnz = g->nnz;
   st->directed = g->undirected ? 0 : 1;
   st->inbound = wants_reverse(g, p) ? 1 : 0;
+  st->fp32 = p->precision == KATZ_FP32_MARGIN ? 1 : 0;
   st->eps = p->epsilon;
   st->k = p->k;
   st->max_iter = p->max_iter ? p->max_iter : 1000;
@@ -2615,20 +2666,16 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
   st->degree_cap = p->degree_cap ? p->degree_cap : dmax;
   if (st->degree_cap < dmax) return KATZ_E_INVALID_ARG;
   if (!(st->alpha * (double)st->degree_cap < 1.0)) return KATZ_E_ALPHA;
+  // FP32 form: error tables for every graph up to the degree cap.
+  if (st->fp32) fp32_tables(st->S, scale_cap(st), st->max_iter, st->bins.bb);
 
   // Run buffers.
   KATZ_TRY(alloc_run_buffers(st, s));
-  Work& w = st->w;
 
   CallTimer T;
   T.call_begin(s);
-  Run run = state_run(st);
-  run.first_select = true;
-  run.cur = 0;
-  KATZ_TRY(iterate(run, st->hs, 1, false, s, T));
-  st->r = st->hs.sc->iterations;
-  st->cur = st->hs.sc->cur;
-  const int status = write_result(run, st->hs, out, st->out_ids, st->out_lo, st->out_up, s, T);
+  const int status = run_from_start(st, out, s, T);
+  if (status < 0) return status;
   guard.keep = true;
   *stp = st;
   return status;
@@ -3017,25 +3064,50 @@ int apply_batch(katz_state* st, const PreparedBatch& pb, katz_result* out, hipSt
         IterArgs ia2 = iter_args(run, st->bins, i, true, tb);
         ia2.hub_n = run.hub_n;
         long long g_used = 0;
-        if (i == 1) KATZ_HIP(launch_walk_first(ia2, 0, n, st->nnz, 0, s));
-        else KATZ_HIP(launch_walk_step(ia2, 0, tb, run.walk_grid, &g_used, s, false, run.walk_groups));
+        if (i == 1) KATZ_HIP(launch_walk_first(ia2, run.fp32, n, st->nnz, 0, s));
+        else KATZ_HIP(launch_walk_step(ia2, run.fp32, tb, run.walk_grid, &g_used, s, false, run.walk_groups));
       } else {
         KATZ_TRY(bin_rows(st, st->lbins, st->sc2, st->clist, csize, s));
         const IterArgs ia2 = iter_args(run, st->lbins, i, true, tb);
         long long g_used = 0;
-        if (i == 1) KATZ_HIP(launch_walk_first(ia2, 0, n, st->nnz, 0, s));
-        else KATZ_HIP(launch_walk_step(ia2, 0, tb, 0, &g_used, s));
+        if (i == 1) KATZ_HIP(launch_walk_first(ia2, run.fp32, n, st->nnz, 0, s));
+        else KATZ_HIP(launch_walk_step(ia2, run.fp32, tb, 0, &g_used, s));
       }
     }
-    // c_r(w) = sum_i x_i(w) for every recomputed w, in the static order.
-    KATZ_HIP(launch_c_from_history(dense ? nullptr : st->clist, dense ? n : csize, st->X_dev, st->r, st->w.c, s));
+    // c_r(w) = sum_i x_i(w) for every recomputed w, in the static order (FP32
+    // form: sum_i sigma_i x~_i and the margin e_r).
+    const int32_t* rows = dense ? nullptr : st->clist;
+    const long long count = dense ? n : csize;
+    if (!st->fp32) {
+      KATZ_HIP(launch_c_from_history(rows, count, reinterpret_cast<double* const*>(st->X_dev), st->r, st->w.c, s));
+    } else {
+      KATZ_HIP(launch_c_from_history_f32(rows, count, reinterpret_cast<float* const*>(st->X_dev), st->w.sigma,
+                                         st->etap_dev, st->r, st->w.c, st->w.e, s));
+    }
     KATZ_HIP(launch_clear_levels(st->clist, csize, st->level_of, s));
+    if (st->fp32) {
+      int rescale = 0;
+      KATZ_HIP(hipMemcpyAsync(&rescale, &st->w.sc->rescale, sizeof(int), hipMemcpyDeviceToHost, s));
+      KATZ_HIP(hipStreamSynchronize(s));
+      if (rescale) {
+        set_gamma(st->S, new_dmax);
+        return rerun_state(st, out, s, T);
+      }
+    }
   }
 
   // ---- gamma from the new deg_max; bounds, reactivation, resume ----
+  // The top level's maximum is recomputed (FP32 form: it also sets the scale
+  // of the next level); the lower levels keep theirs, which fixed the scales
+  // of the levels above them.
   set_gamma(st->S, new_dmax);
-  KATZ_HIP(hipMemsetAsync(&st->w.xmax64[st->r], 0, sizeof(unsigned long long), s));
-  KATZ_HIP(launch_max_of_vector(st->X[st->r], n, &st->w.xmax64[st->r], s));
+  if (!st->fp32) {
+    KATZ_HIP(hipMemsetAsync(&st->w.xmax64[st->r], 0, sizeof(unsigned long long), s));
+    KATZ_HIP(launch_max_of_vector(static_cast<const double*>(st->X[st->r]), n, &st->w.xmax64[st->r], s));
+  } else {
+    KATZ_HIP(hipMemsetAsync(&st->w.xmax32[st->r], 0, sizeof(unsigned), s));
+    KATZ_HIP(launch_max_of_vector_f32(static_cast<const float*>(st->X[st->r]), n, &st->w.xmax32[st->r], s));
+  }
   KATZ_HIP(launch_reset_flags(st->w.sc, s));
   run = state_run(st);
   const BoundArgs b = bound_args(run, st->r);
@@ -3057,11 +3129,13 @@ int apply_batch(katz_state* st, const PreparedBatch& pb, katz_result* out, hipSt
 // arrays: the slack CSR (and a directed state's reverse CSR) as offsets,
 // lengths, capacities and the used part of the pool, the renumbering maps,
 // the walk history x_1..x_r, c_r, the active set M, the per-level maxima and
-// the run's device flags.  A file records the library's layout version and
+// the run's device flags; an FP32 state adds its margins e_r, the scales
+// sigma_i and their sums, and the FP32 level maxima (last in the file).  A
+// file records the library's layout version and
 // the size of the flag block, and is refused by a library that differs.
 // ---------------------------------------------------------------------------
 constexpr char kStateMagic[8] = {'K', 'A', 'T', 'Z', 'S', 'T', 'A', 'T'};
-constexpr int64_t kStateVersion = 1;
+constexpr int64_t kStateVersion = 2;
 
 struct StateHeader {
   char magic[8];
@@ -3070,7 +3144,7 @@ struct StateHeader {
   int64_t pool_used, rpool_used;
   double alpha, eps;
   int32_t bb[6];
-  int32_t pad;
+  int32_t fp32;
 };
 
 struct File {
@@ -3147,6 +3221,7 @@ int save_state(katz_state* st, const char* path) {
   h.rpool_used = st->directed ? st->rpool_used : 0;
   h.alpha = st->alpha;
   h.eps = st->eps;
+  h.fp32 = st->fp32;
   const BinBounds& bb = st->bins.bb;
   const int32_t bbv[6] = {bb.g4, bb.g8, bb.g16, bb.g32, bb.w16, bb.w64};
   std::memcpy(h.bb, bbv, sizeof(bbv));
@@ -3161,10 +3236,18 @@ int save_state(katz_state* st, const char* path) {
     KATZ_TRY(write_dev(file.f, st->ext_of, st->n));
     KATZ_TRY(write_dev(file.f, st->int_of, st->n));
   }
-  for (long long i = 1; i <= st->r; ++i) KATZ_TRY(write_dev(file.f, st->X[i], st->n));
+  const size_t xs = st->fp32 ? sizeof(float) : sizeof(double);
+  for (long long i = 1; i <= st->r; ++i)
+    KATZ_TRY(write_dev(file.f, static_cast<const char*>(st->X[i]), xs * st->n));
   KATZ_TRY(write_dev(file.f, st->w.c, st->n));
   KATZ_TRY(write_dev(file.f, st->w.act[st->cur], (size_t)std::max(sc.m, 0)));
   KATZ_TRY(write_dev(file.f, st->w.xmax64, (size_t)st->max_iter + 1));
+  if (st->fp32) {
+    KATZ_TRY(write_dev(file.f, st->w.e, st->n));
+    KATZ_TRY(write_dev(file.f, st->w.sigma, (size_t)st->max_iter + 1));
+    KATZ_TRY(write_dev(file.f, st->w.sigma_sum, (size_t)st->max_iter + 1));
+    KATZ_TRY(write_dev(file.f, st->w.xmax32, (size_t)st->max_iter + 1));
+  }
   return std::fflush(file.f) == 0 ? KATZ_OK : KATZ_E_INVALID_ARG;
 }
 
@@ -3179,7 +3262,8 @@ int load_state(const char* path, katz_state** stp, hipStream_t s) {
       h.sc_bytes != (int64_t)sizeof(RunScalars))
     return KATZ_E_INVALID_ARG;
   if (h.n < 1 || h.n > INT32_MAX || h.k < 1 || h.k > h.n || h.max_iter < 1 || h.r < 1 || h.r > h.max_iter ||
-      h.m < 0 || h.m > h.n || (h.cur != 0 && h.cur != 1) || h.pool_used < 0 || h.rpool_used < 0)
+      h.m < 0 || h.m > h.n || (h.cur != 0 && h.cur != 1) || h.pool_used < 0 || h.rpool_used < 0 ||
+      (h.fp32 != 0 && h.fp32 != 1) || h.degree_cap < h.dmax)
     return KATZ_E_INVALID_ARG;
   RunScalars sc{};
   if (std::fread(&sc, sizeof(sc), 1, file.f) != 1) return KATZ_E_INVALID_ARG;
@@ -3203,6 +3287,7 @@ int load_state(const char* path, katz_state** stp, hipStream_t s) {
   st->cur = (int)h.cur;
   st->directed = (int)h.directed;
   st->inbound = (int)h.inbound;
+  st->fp32 = h.fp32;
   st->alpha = h.alpha;
   st->eps = h.eps;
   KATZ_TRY(st->hs.init());
@@ -3233,12 +3318,22 @@ int load_state(const char* path, katz_state** stp, hipStream_t s) {
   st->bins_stale = true;   // binned before the first whole-graph walk
   st->S.alpha = st->alpha;
   set_gamma(st->S, (int)h.dmax);
+  if (st->fp32) fp32_tables(st->S, scale_cap(st), st->max_iter, bb);
   KATZ_TRY(alloc_run_buffers(st, s));
+  // The flag initialisation runs on s; the copies below must follow it.
+  KATZ_HIP(hipStreamSynchronize(s));
   KATZ_TRY(ensure_levels(st, st->r));
-  for (long long i = 1; i <= st->r; ++i) KATZ_TRY(read_dev(file.f, st->X[i], n));
+  const size_t xs = st->fp32 ? sizeof(float) : sizeof(double);
+  for (long long i = 1; i <= st->r; ++i) KATZ_TRY(read_dev(file.f, static_cast<char*>(st->X[i]), xs * n));
   KATZ_TRY(read_dev(file.f, st->w.c, n));
   KATZ_TRY(read_dev(file.f, st->w.act[st->cur], (size_t)h.m));
   KATZ_TRY(read_dev(file.f, st->w.xmax64, (size_t)st->max_iter + 1));
+  if (st->fp32) {
+    KATZ_TRY(read_dev(file.f, st->w.e, n));
+    KATZ_TRY(read_dev(file.f, st->w.sigma, (size_t)st->max_iter + 1));
+    KATZ_TRY(read_dev(file.f, st->w.sigma_sum, (size_t)st->max_iter + 1));
+    KATZ_TRY(read_dev(file.f, st->w.xmax32, (size_t)st->max_iter + 1));
+  }
   KATZ_HIP(hipStreamSynchronize(s));   // alloc_run_buffers initialised the flags on s
   KATZ_HIP(hipMemcpy(st->w.sc, &sc, sizeof(RunScalars), hipMemcpyHostToDevice));
   *st->hs.sc = sc;
@@ -3335,7 +3430,6 @@ KATZ_EXPORT int katz_rank_static(int32_t count, const katz_csr* g, const katz_pa
     int rc = katz::check_graph(&g[i]);
     if (!rc) rc = katz::check_params(&p[i], g[i].n, true);
     if (!rc && (!out[i].topk_ids || !out[i].lower || !out[i].upper)) rc = KATZ_E_INVALID_ARG;
-    if (!rc && states && p[i].precision != KATZ_FP64) rc = KATZ_E_UNSUPPORTED;
     if (!rc && (states || count > 1)) rc = katz::check_lds_criterion(&p[i]);
     if (rc) return rc;
   }

@@ -384,6 +384,39 @@ __global__ void __launch_bounds__(kWG) max_of_vector(const double* x, long long 
     atomicMax(out, (unsigned long long)__double_as_longlong(fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]))));
 }
 
+// FP32 form (Section 3.3): the walk epilogue of level i adds s_i = sigma_i x~_i
+// to c and raises the margin e by eta'_i s_i (rounded upward); recomputed here
+// for the re-walked rows with the same operations in the same order, so a row
+// ends with the bits a walk over the whole history would give it.
+__global__ void __launch_bounds__(kWG) c_from_history_f32(const int32_t* rows, long long count, float* const* X,
+                                                          const double* sigma, const double* etap, int r,
+                                                          double* c, float* e) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i >= count) return;
+  const int w = rows ? rows[i] : (int)i;
+  double acc = 0.0;
+  float m = 0.0f;
+  for (int l = 1; l <= r; ++l) {
+    const double s = sigma[l] * (double)X[l][w];
+    const double e_prev = (l == 1) ? 0.0 : (double)m;
+    acc = (l == 1) ? s : acc + s;
+    m = __double2float_ru((e_prev + etap[l] * s) * (1.0 + 0x1p-50));
+  }
+  c[w] = acc;
+  e[w] = m;
+}
+
+__global__ void __launch_bounds__(kWG) max_of_vector_f32(const float* x, long long n, unsigned* out) {
+  float m = 0.0f;
+  for (long long v = (long long)blockIdx.x * kWG + threadIdx.x; v < n; v += (long long)gridDim.x * kWG)
+    m = fmaxf(m, x[v]);
+  __shared__ float wm[kWG / kWave];
+  for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if (lane_id() == 0) wm[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(out, __float_as_uint(fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]))));
+}
+
 // min over the active list of the lower bound (as non-negative IEEE bits).
 __global__ void __launch_bounds__(kWG) min_lower_active(BoundArgs b, const int32_t* act, const int* m_ptr,
                                                         unsigned long long* out, uint8_t* mark) {
@@ -594,6 +627,20 @@ hipError_t launch_c_from_history(const int32_t* rows, long long count, double* c
 hipError_t launch_max_of_vector(const double* x, long long n, unsigned long long* out, hipStream_t s) {
   const unsigned nb = (unsigned)std::min<long long>(blocks_for(n), 512);
   hipLaunchKernelGGL(max_of_vector, dim3(nb), dim3(kWG), 0, s, x, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_c_from_history_f32(const int32_t* rows, long long count, float* const* X, const double* sigma,
+                                     const double* etap, int r, double* c, float* e, hipStream_t s) {
+  if (count > 0)
+    hipLaunchKernelGGL(c_from_history_f32, dim3(blocks_for(count)), dim3(kWG), 0, s, rows, count, X, sigma, etap, r,
+                       c, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_of_vector_f32(const float* x, long long n, unsigned* out, hipStream_t s) {
+  const unsigned nb = (unsigned)std::min<long long>(blocks_for(n), 512);
+  hipLaunchKernelGGL(max_of_vector_f32, dim3(nb), dim3(kWG), 0, s, x, n, out);
   return hipGetLastError();
 }
 

@@ -131,6 +131,9 @@ struct RunScalars {
   // workgroup must decide alike (they meet at barriers).  fold_col_err copies
   // it into err after the launch.
   int col_err;
+  // An FP32 state's re-walk wrote an entry above its limit (its stored scales
+  // no longer fit the graph): the update re-runs the state from level 1.
+  int rescale;
 };
 
 // Bound evaluation parameters of one iteration.
@@ -385,6 +388,12 @@ hipError_t launch_clear_levels(const int32_t* rows, long long t, int* level_of, 
 hipError_t launch_c_from_history(const int32_t* rows, long long count, double* const* X, int r, double* c,
                                  hipStream_t s);
 hipError_t launch_max_of_vector(const double* x, long long n, unsigned long long* out, hipStream_t s);
+// FP32 form: c_r = sum_i sigma_i x~_i and the margin recurrence e_i over the
+// stored levels, in the order and arithmetic of the walk epilogue.
+hipError_t launch_c_from_history_f32(const int32_t* rows, long long count, float* const* X, const double* sigma,
+                                     const double* etap, int r, double* c, float* e, hipStream_t s);
+// out = max(out, max_v x[v]) as float bits (x >= 0).
+hipError_t launch_max_of_vector_f32(const float* x, long long n, unsigned* out, hipStream_t s);
 
 hipError_t launch_reset_flags(RunScalars* sc, hipStream_t s);
 hipError_t launch_relabel(const RowDesc* desc, long long n, int32_t* ext_of, int32_t* int_of, long long* coff,

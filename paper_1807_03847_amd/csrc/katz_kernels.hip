@@ -176,6 +176,9 @@ __global__ void __launch_bounds__(kWG) desc_to_rows(const RowDesc* desc, long lo
 // ---------------------------------------------------------------------------
 // Walk step (Eq. (basic_recurrence)) with the fused bound epilogue.
 // ---------------------------------------------------------------------------
+// Largest walk entry an FP32 state's re-walk accepts under its stored scales.
+constexpr float kRewalkLimit = 0x1p64f;
+
 template <bool F32>
 struct Epi {
   double sigma_r;
@@ -253,6 +256,13 @@ __device__ __forceinline__ void epilogue(const IterArgs& a, const Epi<F32>& ep, 
   } else {
     const float xs = x_entry<F32>(a, ep, t);
     reinterpret_cast<float*>(a.x_out)[row] = xs;
+    if (a.rewalk) {
+      // A state's re-walk keeps the scales of its history, which were chosen
+      // for max x~ < 1 on the graph of their time; an entry far above that
+      // (or not a number) asks the host to re-run the state from level 1.
+      if (!(xs <= kRewalkLimit)) a.sc->rescale = 1;
+      return;
+    }
     const double s = ep.sigma_r * (double)xs;
     const double e_prev = (a.r == 1) ? 0.0 : (double)pv.e;
     a.c[row] = (a.r == 1) ? s : pv.c + s;
@@ -1168,6 +1178,7 @@ __global__ void reset_flags(RunScalars* sc) {
   sc->cand_count[1] = 0;
   sc->dmax = 0;
   sc->col_err = 0;
+  sc->rescale = 0;
 }
 
 }  // namespace

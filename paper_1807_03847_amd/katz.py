@@ -356,14 +356,14 @@ class State:
 
 
 def create_state(row_ptr, col, k, *, alpha=0.0, eps=0.0, max_iter=0, degree_cap=0, validate=VALIDATE_BASIC,
-                 flags=0, undirected=True, stream=None):
-    """katz_rank_static with a state: ranks the graph (Algorithm 1, FP64, kept
-    walk history) and returns (State, RankResult) for later updates.  A
-    directed graph's update pairs (u, v) are arcs u -> v; with FLAG_INBOUND
-    the state ranks by inbound walks."""
+                 flags=0, undirected=True, precision="fp64", stream=None):
+    """katz_rank_static with a state: ranks the graph (Algorithm 1, FP64 or
+    FP32 form, kept walk history) and returns (State, RankResult) for later
+    updates.  A directed graph's update pairs (u, v) are arcs u -> v; with
+    FLAG_INBOUND the state ranks by inbound walks."""
     device = row_ptr.device
     g = make_csr(row_ptr, col, undirected)
-    p = make_params(k, alpha, eps, "fp64", max_iter, validate, degree_cap, flags)
+    p = make_params(k, alpha, eps, precision, max_iter, validate, degree_cap, flags)
     ids, lo, up = _alloc_outputs(k, device)
     res = KatzResult(topk_ids=ids.data_ptr(), lower=lo.data_ptr(), upper=up.data_ptr())
     handle = ctypes.c_void_p(0)
@@ -400,11 +400,11 @@ class Server:
         self._k = {}
 
     def add_graph(self, row_ptr, col, k, *, alpha=0.0, eps=0.0, max_iter=0, degree_cap=0,
-                  validate=VALIDATE_BASIC, flags=0, undirected=True):
+                  validate=VALIDATE_BASIC, flags=0, undirected=True, precision="fp64"):
         """Registers a graph (host or device CSR); returns (graph_id, initial RankResult on the host)."""
         import numpy as np
         g = make_csr(row_ptr, col, undirected)
-        p = make_params(k, alpha, eps, "fp64", max_iter, validate, degree_cap, flags)
+        p = make_params(k, alpha, eps, precision, max_iter, validate, degree_cap, flags)
         ids = np.empty(k, dtype=np.int32)
         lo = np.empty(k, dtype=np.float64)
         up = np.empty(k, dtype=np.float64)
