@@ -2363,8 +2363,9 @@ SlackRef rev_csr(katz_state* st) {
 
 // A slack CSR from a device CSR: per-row capacities with room to grow, their
 // offsets, the rows copied in.
-int build_slack(katz_state* st, SlackRef c, const void* rp, int rp64, const int32_t* col, long long n,
-                hipStream_t s) {
+// The layout of a slack CSR (lengths, capacities with room to grow, their
+// offsets, the pool size) without its rows.
+int slack_layout(katz_state* st, SlackRef c, const void* rp, int rp64, long long n, hipStream_t s) {
   c.row_off = dalloc<long long>(st, n);
   c.row_len = dalloc<int>(st, n);
   c.row_cap = dalloc<int>(st, n);
@@ -2382,9 +2383,16 @@ int build_slack(katz_state* st, SlackRef c, const void* rp, int rp64, const int3
   dfree(st, total);
   c.pool_used = pool_need;
   c.pool_cap = pool_need + pool_need / 8 + 4096;
+  return KATZ_OK;
+}
+
+// A slack CSR from a device CSR: the layout, then the rows copied in.
+int build_slack(katz_state* st, SlackRef c, const void* rp, int rp64, const int32_t* col, long long n, long long nnz,
+                hipStream_t s) {
+  KATZ_TRY(slack_layout(st, c, rp, rp64, n, s));
   c.pool = dalloc<int32_t>(st, c.pool_cap);
   if (!c.pool) return KATZ_E_OOM;
-  KATZ_HIP(launch_copy_rows_to_pool(rp, rp64, col, n, c.row_off, c.pool, s));
+  KATZ_HIP(launch_copy_rows_to_pool(rp, rp64, col, n, nnz, c.row_off, c.pool, s));
   return KATZ_OK;
 }
 
@@ -2410,8 +2418,8 @@ int rename_slack(katz_state* st, SlackRef c, hipStream_t s) {
   const long long cap = used + used / 8 + 4096;
   int32_t* pool_new = dalloc<int32_t>(st, cap);
   if (!pool_new) return KATZ_E_OOM;
-  KATZ_HIP(launch_state_rename_rows(st->ext_of, st->int_of, n, c.row_off, c.row_len, c.row_cap, c.pool, off_new,
-                                    len_new, cap_new, pool_new, s));
+  KATZ_HIP(launch_state_rename_rows(st->ext_of, st->int_of, n, c.row_off, 1, c.row_len, c.row_cap, c.pool, off_new,
+                                    used, len_new, cap_new, pool_new, s));
   KATZ_HIP(hipStreamSynchronize(s));
   dfree(st, c.pool);
   dfree(st, c.row_off);
@@ -2575,9 +2583,6 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
     if (!st->directed) {
       KATZ_HIP(launch_reset_flags(st->w.sc, s));
       KATZ_HIP(launch_csr_equal(rp, g->row_ptr_64, col, t1_ptr, t1_col, n, nnz, st->w.sc, s));
-      KATZ_HIP(hipMemcpyAsync(st->hs.sc, st->w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
-      KATZ_HIP(hipStreamSynchronize(s));
-      if (st->hs.sc->err) return KATZ_E_CSR;   // not symmetric (or rows not sorted)
     } else if (!st->inbound) {
       rev_rp = t1_ptr;
       rev_col = t1_col;
@@ -2593,33 +2598,31 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
       rev_rp = t2_ptr;
       rev_col = t2_col;
     }
+    // Strict checks of the graph the state ranks: no self-loop, rows strictly
+    // ascending (sorted, no neighbour twice).  With the symmetry check above
+    // (an undirected graph), one read-back.
+    KATZ_HIP(launch_check_rows_strict(fwd_rp, fwd_rp64, fwd_col, n, nnz, st->w.sc, s));
+    KATZ_HIP(hipMemcpyAsync(st->hs.sc, st->w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
+    KATZ_HIP(hipStreamSynchronize(s));
+    if (st->hs.sc->err) return KATZ_E_CSR;
   }
 
-  // Slack CSRs: capacities, offsets, copy.
-  KATZ_TRY(build_slack(st, fwd_csr(st), fwd_rp, fwd_rp64, fwd_col, n, s));
-  if (st->directed) KATZ_TRY(build_slack(st, rev_csr(st), rev_rp, 1, rev_col, n, s));
-  KATZ_HIP(hipStreamSynchronize(s));
-  for (void* t : temps) dfree(st, t);
-  if (rp_tmp) dfree(st, rp_tmp);
-  if (col_tmp) dfree(st, col_tmp);
+  // Slack CSRs: capacities and offsets, then the rows copied in; a renumbered
+  // state's graph takes its rows renamed straight from the CSR below instead.
+  const bool reorder = !(p->flags & KATZ_FLAG_NO_REORDER);
+  if (reorder) KATZ_TRY(slack_layout(st, fwd_csr(st), fwd_rp, fwd_rp64, n, s));
+  else KATZ_TRY(build_slack(st, fwd_csr(st), fwd_rp, fwd_rp64, fwd_col, n, g->nnz, s));
+  if (st->directed) KATZ_TRY(build_slack(st, rev_csr(st), rev_rp, 1, rev_col, n, g->nnz, s));
 
-  // Bins of the whole graph, strict checks (sorted rows, no repeats, no loops).
-  // The state keeps the length classes of its creation for every later
-  // binning, so its re-walks sum rows as a static run with that tuning does.
+  // Bins of the whole graph.  The state keeps the length classes of its
+  // creation for every later binning, so its re-walks sum rows as a static
+  // run with that tuning does.
   st->bins.bb = st->lbins.bb = bounds_of(current_tuning());
   KATZ_TRY(alloc_bins(st, st->bins));
   KATZ_TRY(alloc_bins(st, st->lbins));
   KATZ_TRY(bin_rows(st, st->bins, st->w.sc, nullptr, n, s));
-  KATZ_HIP(launch_reset_flags(st->w.sc, s));
-  // Symmetry was checked against the transpose above.
-  KATZ_HIP(launch_validate_strict(st->bins.desc, n, st->bins.segs, st->bins.seg_total, st->bins.huge, st->pool, 0,
-                                  st->row_off, st->row_len, st->w.sc, s));
-  KATZ_HIP(hipMemcpyAsync(st->hs.sc, st->w.sc, sizeof(RunScalars), hipMemcpyDeviceToHost, s));
-  KATZ_HIP(hipStreamSynchronize(s));
-  if (st->hs.sc->err) return KATZ_E_CSR;
-  // validate_strict rewrote row_off/row_len from the descriptors: unchanged values.
 
-  if (!(p->flags & KATZ_FLAG_NO_REORDER)) {
+  if (reorder) {
     // Renumber by the binned order (longest rows first), as static calls do, so
     // the walk's most gathered entries share cache lines and the LDS copy.
     st->ext_of = dalloc<int32_t>(st, n);
@@ -2640,10 +2643,9 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
     const long long cap = used + used / 8 + 4096;
     int32_t* pool_new = dalloc<int32_t>(st, cap);
     if (!pool_new) return KATZ_E_OOM;
-    KATZ_HIP(launch_state_rename_rows(st->ext_of, st->int_of, n, st->row_off, st->row_len, st->row_cap, st->pool,
-                                      off_new, len_new, cap_new, pool_new, s));
+    KATZ_HIP(launch_state_rename_rows(st->ext_of, st->int_of, n, fwd_rp, fwd_rp64, st->row_len, st->row_cap, fwd_col,
+                                      off_new, used, len_new, cap_new, pool_new, s));
     KATZ_HIP(hipStreamSynchronize(s));
-    dfree(st, st->pool);
     dfree(st, st->row_off);
     dfree(st, st->row_len);
     dfree(st, st->row_cap);
@@ -2659,6 +2661,10 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
     if (st->directed) KATZ_TRY(rename_slack(st, rev_csr(st), s));
     KATZ_TRY(bin_rows(st, st->bins, st->w.sc, nullptr, n, s));
   }
+  KATZ_HIP(hipStreamSynchronize(s));
+  for (void* t : temps) dfree(st, t);
+  if (rp_tmp) dfree(st, rp_tmp);
+  if (col_tmp) dfree(st, col_tmp);
 
   const int dmax = st->bins.dmax;
   KATZ_TRY(resolve_alpha(p->alpha, dmax, st->S));

@@ -85,17 +85,88 @@ __global__ void __launch_bounds__(kWG) scan_chunk_apply(const long long* in, lon
 }
 
 // One wave per row: copy the caller's CSR row into the slack pool.
+// Flattened passes over the positions of a row-partitioned array (the arcs of
+// a CSR, the slots of a slack pool): wave w takes kFlatPer * kWave consecutive
+// positions, lane l the positions c0 + q kWave + l, so every load and store
+// instruction of the wave covers kWave consecutive positions whatever the row
+// lengths (a hub row is spread over many waves, short rows share one).  A
+// lane finds the row of its first position by a binary search over the row
+// offsets and follows the rows forward from there.
+constexpr int kFlatPer = 16;
+
 template <class OffT>
-__global__ void __launch_bounds__(kWG) copy_rows_to_pool(const OffT* rp, const int32_t* col, long long n,
-                                                         const long long* row_off, int32_t* pool) {
-  const long long v = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave;
-  if (v >= n) return;
-  const long long src = (long long)rp[v];
-  const long long len = (long long)rp[v + 1] - src;
-  const long long dst = row_off[v];
-  for (long long j = lane_id(); j < len; j += kWave) pool[dst + j] = col[src + j];
+__device__ __forceinline__ long long row_at(const OffT* off, long long rows, long long p) {
+  long long lo = 0, hi = rows - 1;   // the last row i with off[i] <= p
+  while (lo < hi) {
+    const long long mid = (lo + hi + 1) >> 1;
+    if ((long long)off[mid] <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
+unsigned flat_blocks(long long positions) {
+  const long long waves = (positions + (long long)kWave * kFlatPer - 1) / ((long long)kWave * kFlatPer);
+  return (unsigned)std::max<long long>(1, (waves * kWave + kWG - 1) / kWG);
+}
+
+// Row v of the CSR copied to pool[row_off[v] ..].
+template <class OffT>
+__global__ void __launch_bounds__(kWG) copy_rows_to_pool(const OffT* rp, const int32_t* col, long long n,
+                                                         long long nnz, const long long* row_off, int32_t* pool) {
+  const long long c0 = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave * ((long long)kWave * kFlatPer);
+  if (c0 >= nnz) return;
+  const int lane = lane_id();
+  long long v = -1, start = 0, end = 0;
+  for (int q = 0; q < kFlatPer; ++q) {
+    const long long j = c0 + (long long)q * kWave + lane;
+    if (j >= nnz) break;
+    if (v < 0) {
+      v = row_at(rp, n, j);
+      start = (long long)rp[v];
+      end = (long long)rp[v + 1];
+    }
+    while (j >= end && v + 1 < n) {
+      ++v;
+      start = end;
+      end = (long long)rp[v + 1];
+    }
+    pool[row_off[v] + (j - start)] = col[j];
+  }
+}
+
+// The checks a state needs of its CSR, one pass over the arcs: every column
+// id in range, no self-loop, each row strictly ascending (sorted, no
+// neighbour twice).  Offsets are checked by the binning pass; inconsistent
+// ones cannot make this pass read out of bounds (rows stay in 0..n-1, arcs in
+// 0..nnz-1) and flag the graph.
+template <class OffT>
+__global__ void __launch_bounds__(kWG) check_rows_strict(const OffT* rp, const int32_t* col, long long n,
+                                                         long long nnz, RunScalars* sc) {
+  const long long c0 = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave * ((long long)kWave * kFlatPer);
+  if (c0 >= nnz) return;
+  const int lane = lane_id();
+  long long v = -1, start = 0, end = 0;
+  bool bad = false;
+  for (int q = 0; q < kFlatPer; ++q) {
+    const long long j = c0 + (long long)q * kWave + lane;
+    if (j >= nnz) break;
+    if (v < 0) {
+      v = row_at(rp, n, j);
+      start = (long long)rp[v];
+      end = (long long)rp[v + 1];
+    }
+    while (j >= end && v + 1 < n) {
+      ++v;
+      start = end;
+      end = (long long)rp[v + 1];
+    }
+    const int32_t u = col[j];
+    bad = bad || j < start || j >= end || u < 0 || (long long)u >= n || (long long)u == v ||
+          (j > start && j > 0 && col[j - 1] >= u);
+  }
+  if (__ballot(bad) && lane == 0) atomicOr(&sc->err, 1);
+}
 __device__ __forceinline__ long long lower_bound_i32(const int32_t* a, long long len, int32_t x) {
   long long lo = 0, hi = len;
   while (lo < hi) {
@@ -159,23 +230,53 @@ __global__ void __launch_bounds__(kWG) state_relabel(const RowDesc* desc, long l
 
 // One wave per internal row i: the caller's row ext_of[i], entries renamed and
 // kept in their order, copied to the internal pool.
+// The renumbered slack CSR: slot p of the new pool lies in internal row i
+// (off_new ascending, row i ending where row i + 1 starts, the last at
+// used_new); its first len(ext_of[i]) slots take the old row's entries
+// renamed through int_of, the rest stay free.  Each row's length and capacity
+// move with it.
+template <class OffT>
 __global__ void __launch_bounds__(kWG) state_rename_rows(const int32_t* ext_of, const int32_t* int_of, long long n,
-                                                         const long long* off_old, const int* len_old,
+                                                         const OffT* off_old, const int* len_old,
                                                          const int* cap_old, const int32_t* pool_old,
-                                                         const long long* off_new, int* len_new, int* cap_new,
-                                                         int32_t* pool_new) {
-  const long long i = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave;
-  if (i >= n) return;
-  const int v = ext_of[i];
-  const long long src = off_old[v], dst = off_new[i];
-  const int len = len_old[v];
-  for (long long j = lane_id(); j < len; j += kWave) pool_new[dst + j] = int_of[pool_old[src + j]];
-  if (lane_id() == 0) {
-    len_new[i] = len;
+                                                         const long long* off_new, long long used_new, int* len_new,
+                                                         int* cap_new, int32_t* pool_new) {
+  const long long gid = (long long)blockIdx.x * kWG + threadIdx.x;
+  for (long long i = gid; i < n; i += (long long)gridDim.x * kWG) {
+    const int v = ext_of[i];
+    len_new[i] = len_old[v];
     cap_new[i] = cap_old[v];
   }
+  const long long c0 = gid / kWave * ((long long)kWave * kFlatPer);
+  if (c0 >= used_new) return;
+  const int lane = lane_id();
+  long long i = -1, start = 0, end = 0, src = 0;
+  int len = 0;
+  for (int q = 0; q < kFlatPer; ++q) {
+    const long long p = c0 + (long long)q * kWave + lane;
+    if (p >= used_new) break;
+    bool moved = false;
+    if (i < 0) {
+      i = row_at(off_new, n, p);
+      start = off_new[i];
+      end = i + 1 < n ? off_new[i + 1] : used_new;
+      moved = true;
+    }
+    while (p >= end && i + 1 < n) {
+      ++i;
+      start = end;
+      end = i + 1 < n ? off_new[i + 1] : used_new;
+      moved = true;
+    }
+    if (moved) {
+      const int v = ext_of[i];
+      src = (long long)off_old[v];
+      len = len_old[v];
+    }
+    const long long j = p - start;
+    if (j < len) pool_new[p] = int_of[pool_old[src + j]];
+  }
 }
-
 // Candidate lengths of the touched rows; marks them.
 __global__ void __launch_bounds__(kWG) touched_lengths(const int32_t* rows, long long t, const int* delta,
                                                        const int* row_len, long long* new_len, uint8_t* mark) {
@@ -511,15 +612,27 @@ hipError_t launch_slack_caps(const void* rp, int rp64, long long n, int* row_len
   return hipGetLastError();
 }
 
-hipError_t launch_copy_rows_to_pool(const void* rp, int rp64, const int32_t* col, long long n,
+hipError_t launch_copy_rows_to_pool(const void* rp, int rp64, const int32_t* col, long long n, long long nnz,
                                     const long long* row_off, int32_t* pool, hipStream_t s) {
-  const unsigned nb = blocks_for(n * kWave);
+  if (n <= 0 || nnz <= 0) return hipSuccess;
+  const unsigned nb = flat_blocks(nnz);
   if (rp64)
-    hipLaunchKernelGGL(copy_rows_to_pool<int64_t>, dim3(nb), dim3(kWG), 0, s, (const int64_t*)rp, col, n, row_off,
-                       pool);
+    hipLaunchKernelGGL(copy_rows_to_pool<int64_t>, dim3(nb), dim3(kWG), 0, s, (const int64_t*)rp, col, n, nnz,
+                       row_off, pool);
   else
-    hipLaunchKernelGGL(copy_rows_to_pool<int32_t>, dim3(nb), dim3(kWG), 0, s, (const int32_t*)rp, col, n, row_off,
-                       pool);
+    hipLaunchKernelGGL(copy_rows_to_pool<int32_t>, dim3(nb), dim3(kWG), 0, s, (const int32_t*)rp, col, n, nnz,
+                       row_off, pool);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_rows_strict(const void* rp, int rp64, const int32_t* col, long long n, long long nnz,
+                                    RunScalars* sc, hipStream_t s) {
+  if (n <= 0 || nnz <= 0) return hipSuccess;
+  const unsigned nb = flat_blocks(nnz);
+  if (rp64)
+    hipLaunchKernelGGL(check_rows_strict<int64_t>, dim3(nb), dim3(kWG), 0, s, (const int64_t*)rp, col, n, nnz, sc);
+  else
+    hipLaunchKernelGGL(check_rows_strict<int32_t>, dim3(nb), dim3(kWG), 0, s, (const int32_t*)rp, col, n, nnz, sc);
   return hipGetLastError();
 }
 
@@ -535,12 +648,18 @@ hipError_t launch_state_relabel(const RowDesc* desc, long long n, const int* row
 }
 
 hipError_t launch_state_rename_rows(const int32_t* ext_of, const int32_t* int_of, long long n,
-                                   const long long* off_old, const int* len_old, const int* cap_old,
-                                   const int32_t* pool_old, const long long* off_new, int* len_new, int* cap_new,
-                                   int32_t* pool_new, hipStream_t s) {
-  const long long nb = (n * kWave + kWG - 1) / kWG;
-  hipLaunchKernelGGL(state_rename_rows, dim3((unsigned)nb), dim3(kWG), 0, s, ext_of, int_of, n, off_old, len_old,
-                     cap_old, pool_old, off_new, len_new, cap_new, pool_new);
+                                   const void* off_old, int off64, const int* len_old, const int* cap_old,
+                                   const int32_t* pool_old, const long long* off_new, long long used_new,
+                                   int* len_new, int* cap_new, int32_t* pool_new, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned nb = flat_blocks(std::max<long long>(used_new, 1));
+  if (off64)
+    hipLaunchKernelGGL(state_rename_rows<long long>, dim3(nb), dim3(kWG), 0, s, ext_of, int_of, n,
+                       (const long long*)off_old, len_old, cap_old, pool_old, off_new, used_new, len_new, cap_new,
+                       pool_new);
+  else
+    hipLaunchKernelGGL(state_rename_rows<int>, dim3(nb), dim3(kWG), 0, s, ext_of, int_of, n, (const int*)off_old,
+                       len_old, cap_old, pool_old, off_new, used_new, len_new, cap_new, pool_new);
   return hipGetLastError();
 }
 

@@ -349,8 +349,11 @@ hipError_t launch_scan_ll(const long long* in, long long count, long long* out, 
 long long scan_sums_capacity(long long count);
 hipError_t launch_slack_caps(const void* rp, int rp64, long long n, int* row_len, int* row_cap,
                              long long* cap_ll, hipStream_t s);
-hipError_t launch_copy_rows_to_pool(const void* rp, int rp64, const int32_t* col, long long n,
+hipError_t launch_copy_rows_to_pool(const void* rp, int rp64, const int32_t* col, long long n, long long nnz,
                                     const long long* row_off, int32_t* pool, hipStream_t s);
+// Column ids in range, no self-loop, rows strictly ascending (sc->err |= 1 otherwise).
+hipError_t launch_check_rows_strict(const void* rp, int rp64, const int32_t* col, long long n, long long nnz,
+                                    RunScalars* sc, hipStream_t s);
 // ext_of / int_of: internal <-> caller id maps of a renumbered state (null:
 // the state is in caller order); batch pairs and per-row lists are caller ids.
 hipError_t launch_batch_exist(const int32_t* a, const int32_t* b, long long n_ins, long long total,
@@ -359,10 +362,11 @@ hipError_t launch_batch_exist(const int32_t* a, const int32_t* b, long long n_in
 hipError_t launch_map_ids(int32_t* ids, long long count, const int32_t* int_of, hipStream_t s);
 hipError_t launch_state_relabel(const RowDesc* desc, long long n, const int* row_cap, int32_t* ext_of,
                                int32_t* int_of, long long* cap_ll, hipStream_t s);
+// off_old: row offsets of the old rows by caller id, int64 (off64 = 1) or int32.
 hipError_t launch_state_rename_rows(const int32_t* ext_of, const int32_t* int_of, long long n,
-                                   const long long* off_old, const int* len_old, const int* cap_old,
-                                   const int32_t* pool_old, const long long* off_new, int* len_new, int* cap_new,
-                                   int32_t* pool_new, hipStream_t s);
+                                   const void* off_old, int off64, const int* len_old, const int* cap_old,
+                                   const int32_t* pool_old, const long long* off_new, long long used_new,
+                                   int* len_new, int* cap_new, int32_t* pool_new, hipStream_t s);
 hipError_t launch_touched_lengths(const int32_t* rows, long long t, const int* delta, const int* row_len,
                                   long long* new_len, uint8_t* mark, hipStream_t s);
 hipError_t launch_max_len_after(const int* row_len, const uint8_t* mark, long long n, const long long* new_len,

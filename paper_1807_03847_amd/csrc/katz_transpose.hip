@@ -36,11 +36,16 @@ constexpr int kTileRounds = 16;
 constexpr long long kTile = (long long)kRadixWG * kTileRounds;   // arcs per tile
 constexpr int kExpandPer = 16;                              // arcs per thread of expand_sources
 
-// src[j] = the row of arc j, for kExpandPer consecutive arcs per thread: one
-// binary search over the offsets for the first, then a walk forward.
+// src[j] = the row of arc j.  Wave w takes kExpandPer * kWave consecutive
+// arcs, lane l the arcs c0 + q kWave + l (each store instruction covers kWave
+// consecutive arcs); a lane finds the row of its first arc by a binary search
+// over the offsets, then follows the rows forward.
 template <class OffT>
 __global__ void __launch_bounds__(kWG) expand_sources(const OffT* rp, long long n, long long nnz, int32_t* src) {
-  const long long j0 = ((long long)blockIdx.x * kWG + threadIdx.x) * kExpandPer;
+  const long long c0 = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave * ((long long)kWave * kExpandPer);
+  if (c0 >= nnz) return;
+  const int lane = lane_id();
+  const long long j0 = c0 + lane;
   if (j0 >= nnz) return;
   // The last row v with rp[v] <= j0 (rows before it end at or before j0).
   long long lo = 0, hi = n - 1;
@@ -51,8 +56,9 @@ __global__ void __launch_bounds__(kWG) expand_sources(const OffT* rp, long long 
   }
   long long v = lo;
   long long end = (long long)rp[v + 1];
-  const long long j1 = j0 + kExpandPer < nnz ? j0 + kExpandPer : nnz;
-  for (long long j = j0; j < j1; ++j) {
+  for (int q = 0; q < kExpandPer; ++q) {
+    const long long j = j0 + (long long)q * kWave;
+    if (j >= nnz) break;
     while (j >= end) {   // empty rows are skipped
       ++v;
       end = (long long)rp[v + 1];
@@ -72,10 +78,17 @@ __global__ void __launch_bounds__(kRadixWG) radix_count(const int32_t* key, long
   for (int d = threadIdx.x; d < kRadixBins; d += kRadixWG) h[d] = 0;
   __syncthreads();
   const long long base = (long long)blockIdx.x * kTile;
+  // Every key of the thread is loaded before the first count, so the tile's
+  // loads are in flight together.
+  int32_t kr[kTileRounds];
+#pragma unroll
   for (int j = 0; j < kTileRounds; ++j) {
     const long long i = base + (long long)j * kRadixWG + threadIdx.x;
-    if (i < nnz) atomicAdd(&h[digit_of(key[i], shift, mask)], 1u);
+    kr[j] = i < nnz ? key[i] : -1;
   }
+#pragma unroll
+  for (int j = 0; j < kTileRounds; ++j)
+    if (kr[j] >= 0) atomicAdd(&h[digit_of(kr[j], shift, mask)], 1u);
   __syncthreads();
   for (int d = threadIdx.x; d <= (int)mask; d += kRadixWG) count[(long long)d * tiles + blockIdx.x] = h[d];
 }
@@ -109,28 +122,48 @@ __global__ void __launch_bounds__(kRadixWG) radix_scatter(const int32_t* key_in,
     run[t] = 0;
   }
   __syncthreads();
-  if (t == 0) {   // exclusive scan of the tile's counts (at most 256 values)
-    int acc = 0;
-    for (int d = 0; d < nvals; ++d) {
-      const int c = lbase[d];
-      lbase[d] = acc;
-      acc += c;
+  const int w = t / kWave;
+  const int lane = lane_id();
+  const long long tile0 = (long long)blockIdx.x * kTile;
+  const int tile_len = (int)(nnz - tile0 < kTile ? nnz - tile0 : kTile);
+  // The thread's keys and payloads of every round, loaded at once (their
+  // latency is paid once per tile instead of once per round).
+  int32_t kr[kTileRounds], vr[kTileRounds];
+#pragma unroll
+  for (int j = 0; j < kTileRounds; ++j) {
+    const int li = j * kRadixWG + t;
+    kr[j] = li < tile_len ? key_in[tile0 + li] : 0;
+    vr[j] = li < tile_len ? val_in[tile0 + li] : 0;
+  }
+  if (w == 0) {   // exclusive scan of the tile's counts: four values per lane, then the wave
+    int c[kRadixBins / kWave];
+    int sum = 0;
+#pragma unroll
+    for (int q = 0; q < kRadixBins / kWave; ++q) {
+      const int d = lane * (kRadixBins / kWave) + q;
+      c[q] = d < nvals ? lbase[d] : 0;
+      sum += c[q];
+    }
+    int incl = sum;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    int acc = incl - sum;
+#pragma unroll
+    for (int q = 0; q < kRadixBins / kWave; ++q) {
+      const int d = lane * (kRadixBins / kWave) + q;
+      if (d < nvals) lbase[d] = acc;
+      acc += c[q];
     }
   }
   __syncthreads();
-  const int w = t / kWave;
-  const int lane = lane_id();
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-  const long long tile0 = (long long)blockIdx.x * kTile;
-  const int tile_len = (int)(nnz - tile0 < kTile ? nnz - tile0 : kTile);
+#pragma unroll
   for (int j = 0; j < kTileRounds; ++j) {
     const int li = j * kRadixWG + t;
     const bool valid = li < tile_len;
-    int32_t k = 0, v = 0;
-    if (valid) {
-      k = key_in[tile0 + li];
-      v = val_in[tile0 + li];
-    }
+    const int32_t k = kr[j], v = vr[j];
     const unsigned d = digit_of(k, shift, mask);
     // Lanes of this wave with the same digit: intersect the ballots of every
     // digit bit.
