@@ -503,6 +503,17 @@ int katz_tuning_set(const katz_tuning* t);
  * fields keep their values.  Inputs as for katz_rank_static; returns the first error of a
  * ranking call (the setting is then left unchanged), or KATZ_OK. */
 int katz_autotune(int32_t count, const katz_csr* g, const katz_params* p, katz_tuning* best, void* stream);
+/* Autotuner cache: with a path set, katz_autotune first looks its workload up
+ * in that text file and, on a hit, installs the stored setting without timing
+ * anything; after tuning it appends the result.  A workload is keyed by the
+ * device (architecture, compute units), the graph count, the total nodes and
+ * arcs, and the precision, criterion, flags and direction of the first graph.
+ * One line per entry: the key, a tab, the 13 katz_tuning fields before
+ * `reserved` as decimal integers; the last valid line of a key wins, and lines
+ * that do not parse or hold an invalid setting are ignored.  The file is read
+ * and appended by plain stdio calls (no locking between processes).  path =
+ * NULL or "" turns the cache off (the default).  Returns KATZ_OK. */
+int katz_autotune_cache(const char* path);
 
 #ifdef __cplusplus
 }

@@ -19,6 +19,7 @@
 #include <limits>
 #include <mutex>
 #include <numeric>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -2419,7 +2420,7 @@ int rename_slack(katz_state* st, SlackRef c, hipStream_t s) {
   int32_t* pool_new = dalloc<int32_t>(st, cap);
   if (!pool_new) return KATZ_E_OOM;
   KATZ_HIP(launch_state_rename_rows(st->ext_of, st->int_of, n, c.row_off, 1, c.row_len, c.row_cap, c.pool, off_new,
-                                    used, len_new, cap_new, pool_new, s));
+                                    used, len_new, cap_new, pool_new, cap_ll, s));
   KATZ_HIP(hipStreamSynchronize(s));
   dfree(st, c.pool);
   dfree(st, c.row_off);
@@ -2644,7 +2645,7 @@ int create_state(const katz_csr* g, const katz_params* p, katz_result* out, katz
     int32_t* pool_new = dalloc<int32_t>(st, cap);
     if (!pool_new) return KATZ_E_OOM;
     KATZ_HIP(launch_state_rename_rows(st->ext_of, st->int_of, n, fwd_rp, fwd_rp64, st->row_len, st->row_cap, fwd_col,
-                                      off_new, used, len_new, cap_new, pool_new, s));
+                                      off_new, used, len_new, cap_new, pool_new, cap_ll, s));
     KATZ_HIP(hipStreamSynchronize(s));
     dfree(st, st->row_off);
     dfree(st, st->row_len);
@@ -3536,6 +3537,92 @@ KATZ_EXPORT int katz_tuning_set(const katz_tuning* t) {
   return KATZ_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner cache: one text line per tuned workload, "<key>\t<13 integers>"
+// (the katz_tuning fields in declaration order, reserved left out).  The key
+// names the device (architecture and compute units) and the workload (graph
+// count, total nodes and arcs, precision, criterion, flags).  The last valid
+// line of a key wins; lines that do not parse or hold an invalid setting are
+// skipped.
+// ---------------------------------------------------------------------------
+namespace katz {
+namespace {
+
+struct TuneCache {
+  std::mutex mu;
+  std::string path;
+} g_tune_cache;
+
+std::string tune_key(int32_t count, const katz_csr* g, const katz_params* p) {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return std::string();
+  }
+  long long n = 0, nnz = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    n += g[i].n;
+    nnz += g[i].nnz;
+  }
+  char buf[320];
+  std::snprintf(buf, sizeof(buf), "%s/%d/count=%d/n=%lld/nnz=%lld/prec=%d/crit=%d/flags=%d/und=%d",
+                prop.gcnArchName, prop.multiProcessorCount, (int)count, n, nnz, (int)p[0].precision,
+                (int)p[0].criterion, (int)p[0].flags, (int)g[0].undirected);
+  for (char* c = buf; *c; ++c)
+    if (*c == '\t' || *c == '\n') *c = ' ';
+  return std::string(buf);
+}
+
+bool cache_lookup(const std::string& path, const std::string& key, katz_tuning& out) {
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  bool found = false;
+  char line[1024];
+  while (std::fgets(line, sizeof(line), f)) {
+    char* tab = std::strchr(line, '\t');
+    if (!tab || (size_t)(tab - line) != key.size() || std::strncmp(line, key.c_str(), key.size()) != 0) continue;
+    katz_tuning t{};
+    int32_t* v[13] = {&t.hub_bytes, &t.blocks_per_cu, &t.batch_blocks_per_cu, &t.batch_tile, &t.batch_xcd,
+                      &t.walk_groups, &t.split_hot_bytes, &t.bin_bounds[0], &t.bin_bounds[1], &t.bin_bounds[2],
+                      &t.bin_bounds[3], &t.bin_bounds[4], &t.bin_bounds[5]};
+    char* s = tab + 1;
+    bool ok = true;
+    for (int i = 0; i < 13 && ok; ++i) {
+      char* e = nullptr;
+      const long x = std::strtol(s, &e, 10);
+      ok = e != s && x >= INT32_MIN && x <= INT32_MAX;
+      *v[i] = (int32_t)x;
+      s = e;
+    }
+    while (ok && (*s == ' ' || *s == '\r' || *s == '\n')) ++s;
+    if (ok && *s == '\0' && tuning_valid(t) == KATZ_OK) {
+      out = t;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const std::string& path, const std::string& key, const katz_tuning& t) {
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%s\t%d %d %d %d %d %d %d %d %d %d %d %d %d\n", key.c_str(), t.hub_bytes, t.blocks_per_cu,
+               t.batch_blocks_per_cu, t.batch_tile, t.batch_xcd, t.walk_groups, t.split_hot_bytes, t.bin_bounds[0],
+               t.bin_bounds[1], t.bin_bounds[2], t.bin_bounds[3], t.bin_bounds[4], t.bin_bounds[5]);
+  std::fclose(f);
+}
+
+}  // namespace
+}  // namespace katz
+
+KATZ_EXPORT int katz_autotune_cache(const char* path) {
+  std::lock_guard<std::mutex> lk(katz::g_tune_cache.mu);
+  katz::g_tune_cache.path = path ? path : "";
+  return KATZ_OK;
+}
+
 // Candidate launch shapes, timed on the caller's graph(s); the fastest is kept.
 KATZ_EXPORT int katz_autotune(int32_t count, const katz_csr* g, const katz_params* p, katz_tuning* best,
                               void* stream) {
@@ -3545,6 +3632,21 @@ KATZ_EXPORT int katz_autotune(int32_t count, const katz_csr* g, const katz_param
     KATZ_TRY(katz::check_graph(&g[i]));
     KATZ_TRY(katz::check_params(&p[i], g[i].n, true));
     sum_k += katz::output_len(&p[i], g[i].n);
+  }
+  std::string cache_path, cache_key;
+  {
+    std::lock_guard<std::mutex> lk(katz::g_tune_cache.mu);
+    cache_path = katz::g_tune_cache.path;
+  }
+  if (!cache_path.empty()) {
+    cache_key = katz::tune_key(count, g, p);
+    katz_tuning hit{};
+    if (!cache_key.empty() && katz::cache_lookup(cache_path, cache_key, hit)) {
+      std::lock_guard<std::mutex> lk(katz::g_tuning.mu);
+      katz::g_tuning.t = hit;
+      if (best) *best = hit;
+      return KATZ_OK;
+    }
   }
   // {hub_bytes, blocks_per_cu, walk_groups}: hub copies sized so that 3..8
   // workgroups fill the 160 KiB of LDS of a CU (with the kernel's own few bytes
@@ -3634,6 +3736,7 @@ KATZ_EXPORT int katz_autotune(int32_t count, const katz_csr* g, const katz_param
   (void)hipFree(ids);
   (void)hipFree(lo);
   (void)hipFree(up);
+  if (rc >= 0 && !cache_key.empty()) katz::cache_store(cache_path, cache_key, pick);
   std::lock_guard<std::mutex> lk(katz::g_tuning.mu);
   katz::g_tuning.t = rc < 0 ? saved : pick;
   if (best) *best = katz::g_tuning.t;

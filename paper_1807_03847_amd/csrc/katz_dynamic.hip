@@ -230,24 +230,31 @@ __global__ void __launch_bounds__(kWG) state_relabel(const RowDesc* desc, long l
 
 // One wave per internal row i: the caller's row ext_of[i], entries renamed and
 // kept in their order, copied to the internal pool.
-// The renumbered slack CSR: slot p of the new pool lies in internal row i
-// (off_new ascending, row i ending where row i + 1 starts, the last at
-// used_new); its first len(ext_of[i]) slots take the old row's entries
-// renamed through int_of, the rest stay free.  Each row's length and capacity
-// move with it.
+// The renumbered slack CSR.  Pass 1, one thread per internal row i: its
+// length and capacity, and where its old row starts (old row ext_of[i]).
 template <class OffT>
-__global__ void __launch_bounds__(kWG) state_rename_rows(const int32_t* ext_of, const int32_t* int_of, long long n,
-                                                         const OffT* off_old, const int* len_old,
-                                                         const int* cap_old, const int32_t* pool_old,
-                                                         const long long* off_new, long long used_new, int* len_new,
-                                                         int* cap_new, int32_t* pool_new) {
-  const long long gid = (long long)blockIdx.x * kWG + threadIdx.x;
-  for (long long i = gid; i < n; i += (long long)gridDim.x * kWG) {
-    const int v = ext_of[i];
-    len_new[i] = len_old[v];
-    cap_new[i] = cap_old[v];
-  }
-  const long long c0 = gid / kWave * ((long long)kWave * kFlatPer);
+__global__ void __launch_bounds__(kWG) rename_meta(const int32_t* ext_of, long long n, const OffT* off_old,
+                                                   const int* len_old, const int* cap_old, int* len_new,
+                                                   int* cap_new, long long* src_of) {
+  const long long i = (long long)blockIdx.x * kWG + threadIdx.x;
+  if (i >= n) return;
+  const int v = ext_of[i];
+  len_new[i] = len_old[v];
+  cap_new[i] = cap_old[v];
+  src_of[i] = (long long)off_old[v];
+}
+
+// Pass 2, flattened over the slots of the new pool (wave-interleaved as
+// above).  Slot p lies in internal row i (off_new ascending; row i ends where
+// row i + 1 starts, the last at used_new); the first len_new[i] slots of a row
+// take the old row's entries renamed through int_of, the rest stay free.  The
+// row data a lane needs on entering a row (its end, length and old start) are
+// independent loads.
+__global__ void __launch_bounds__(kWG) rename_slots(const long long* off_new, long long n, long long used_new,
+                                                    const int* len_new, const long long* src_of,
+                                                    const int32_t* pool_old, const int32_t* int_of,
+                                                    int32_t* pool_new) {
+  const long long c0 = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave * ((long long)kWave * kFlatPer);
   if (c0 >= used_new) return;
   const int lane = lane_id();
   long long i = -1, start = 0, end = 0, src = 0;
@@ -255,23 +262,19 @@ __global__ void __launch_bounds__(kWG) state_rename_rows(const int32_t* ext_of, 
   for (int q = 0; q < kFlatPer; ++q) {
     const long long p = c0 + (long long)q * kWave + lane;
     if (p >= used_new) break;
-    bool moved = false;
     if (i < 0) {
       i = row_at(off_new, n, p);
       start = off_new[i];
       end = i + 1 < n ? off_new[i + 1] : used_new;
-      moved = true;
+      len = len_new[i];
+      src = src_of[i];
     }
     while (p >= end && i + 1 < n) {
       ++i;
       start = end;
       end = i + 1 < n ? off_new[i + 1] : used_new;
-      moved = true;
-    }
-    if (moved) {
-      const int v = ext_of[i];
-      src = (long long)off_old[v];
-      len = len_old[v];
+      len = len_new[i];
+      src = src_of[i];
     }
     const long long j = p - start;
     if (j < len) pool_new[p] = int_of[pool_old[src + j]];
@@ -650,16 +653,17 @@ hipError_t launch_state_relabel(const RowDesc* desc, long long n, const int* row
 hipError_t launch_state_rename_rows(const int32_t* ext_of, const int32_t* int_of, long long n,
                                    const void* off_old, int off64, const int* len_old, const int* cap_old,
                                    const int32_t* pool_old, const long long* off_new, long long used_new,
-                                   int* len_new, int* cap_new, int32_t* pool_new, hipStream_t s) {
+                                   int* len_new, int* cap_new, int32_t* pool_new, long long* src_of, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const unsigned nb = flat_blocks(std::max<long long>(used_new, 1));
   if (off64)
-    hipLaunchKernelGGL(state_rename_rows<long long>, dim3(nb), dim3(kWG), 0, s, ext_of, int_of, n,
-                       (const long long*)off_old, len_old, cap_old, pool_old, off_new, used_new, len_new, cap_new,
-                       pool_new);
+    hipLaunchKernelGGL(rename_meta<long long>, dim3(blocks_for(n)), dim3(kWG), 0, s, ext_of, n,
+                       (const long long*)off_old, len_old, cap_old, len_new, cap_new, src_of);
   else
-    hipLaunchKernelGGL(state_rename_rows<int>, dim3(nb), dim3(kWG), 0, s, ext_of, int_of, n, (const int*)off_old,
-                       len_old, cap_old, pool_old, off_new, used_new, len_new, cap_new, pool_new);
+    hipLaunchKernelGGL(rename_meta<int>, dim3(blocks_for(n)), dim3(kWG), 0, s, ext_of, n, (const int*)off_old,
+                       len_old, cap_old, len_new, cap_new, src_of);
+  if (used_new > 0)
+    hipLaunchKernelGGL(rename_slots, dim3(flat_blocks(used_new)), dim3(kWG), 0, s, off_new, n, used_new, len_new,
+                       src_of, pool_old, int_of, pool_new);
   return hipGetLastError();
 }
 

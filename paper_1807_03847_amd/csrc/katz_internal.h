@@ -366,7 +366,7 @@ hipError_t launch_state_relabel(const RowDesc* desc, long long n, const int* row
 hipError_t launch_state_rename_rows(const int32_t* ext_of, const int32_t* int_of, long long n,
                                    const void* off_old, int off64, const int* len_old, const int* cap_old,
                                    const int32_t* pool_old, const long long* off_new, long long used_new,
-                                   int* len_new, int* cap_new, int32_t* pool_new, hipStream_t s);
+                                   int* len_new, int* cap_new, int32_t* pool_new, long long* src_of, hipStream_t s);
 hipError_t launch_touched_lengths(const int32_t* rows, long long t, const int* delta, const int* row_len,
                                   long long* new_len, uint8_t* mark, hipStream_t s);
 hipError_t launch_max_len_after(const int* row_len, const uint8_t* mark, long long n, const long long* new_len,

@@ -32,7 +32,7 @@ constexpr int kRadixMaxBits = 8;
 constexpr int kRadixBins = 1 << kRadixMaxBits;
 constexpr int kRadixWG = 1024;                               // threads of the radix kernels
 constexpr int kRadixWaves = kRadixWG / kWave;
-constexpr int kTileRounds = 16;
+constexpr int kTileRounds = 6;                               // 6144-arc tiles: two workgroups per CU fit the LDS
 constexpr long long kTile = (long long)kRadixWG * kTileRounds;   // arcs per tile
 constexpr int kExpandPer = 16;                              // arcs per thread of expand_sources
 

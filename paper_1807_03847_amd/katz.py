@@ -91,6 +91,8 @@ def _load():
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1807_03847_amd._build`")
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.katz_autotune_cache.restype = ctypes.c_int
+    lib.katz_autotune_cache.argtypes = [ctypes.c_char_p]
     lib.katz_rank_static.restype = ctypes.c_int
     lib.katz_rank_static.argtypes = [i32, ctypes.POINTER(KatzCSR), ctypes.POINTER(KatzParams),
                                      ctypes.POINTER(KatzResult), ctypes.POINTER(vp), vp]
@@ -513,6 +515,11 @@ def autotune(row_ptr, col, k, *, alpha=0.0, eps=0.0, precision="fp32", undirecte
     if rc < 0:
         raise KatzError(rc)
     return _tuning_dict(t)
+
+
+def autotune_cache(path=None) -> None:
+    """katz_autotune_cache: keep autotuner results in a text file (None: off)."""
+    lib.katz_autotune_cache(None if path is None else os.fsencode(str(path)))
 
 
 def autotune_batch(graphs, params, *, stream=None) -> dict:

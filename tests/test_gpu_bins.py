@@ -157,3 +157,32 @@ def test_state_creation_checks_symmetry_loops_and_repeats(katz):
     st, res = katz.create_state(*dev(rp, col), 2, alpha=0.2)
     assert res.status in (katz.OK, katz.W_EXACT_TIES, katz.W_ITER_LIMIT)
     st.free()
+
+
+def test_autotune_cache(katz, tmp_path):
+    """With a cache file set, the first autotune of a workload times the
+    candidates and appends one line; a second call installs the stored setting
+    without timing (the file is unchanged); another workload misses; a line
+    holding an invalid setting is ignored."""
+    path = tmp_path / "tune.txt"
+    katz.autotune_cache(path)
+    try:
+        rp, col = sg.rmat(12, seed=4)
+        say("autotune cache miss")
+        t1 = katz.autotune(*dev(rp, col), 20, eps=1e-6, precision="fp32")
+        lines = path.read_text().splitlines()
+        assert len(lines) == 1 and lines[0].count("\t") == 1
+        katz.tuning_set()
+        say("autotune cache hit")
+        t2 = katz.autotune(*dev(rp, col), 20, eps=1e-6, precision="fp32")
+        assert t2 == t1 and katz.tuning_get() == t1
+        assert path.read_text().splitlines() == lines
+        rp2, col2 = sg.rmat(11, seed=4)
+        katz.autotune(*dev(rp2, col2), 20, eps=1e-6, precision="fp32")
+        assert len(path.read_text().splitlines()) == 2
+        key = lines[0].split("\t")[0]
+        path.write_text(key + "\t1 2 3\n" + key + "\t0 0 0 0 0 7 0 0 0 0 0 0 0\n")
+        katz.autotune(*dev(rp, col), 20, eps=1e-6, precision="fp32")
+        assert len(path.read_text().splitlines()) == 3          # both lines skipped: tuned again
+    finally:
+        katz.autotune_cache(None)
