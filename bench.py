@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="serving: requests per load point")
     ap.add_argument("--graphs", type=int, default=256, help="batched: number of graphs")
     ap.add_argument("--serving-scale", type=int, default=24, help="serving: R-MAT scale of the resident graph")
+    ap.add_argument("--serving-precision", default="fp64", choices=["fp64", "fp32"],
+                    help="serving: form of the resident state (FP32: scaled walk history, Section 3.3 margin)")
     ap.add_argument("--batched-max-log2n", type=int, default=18, help="batched: n is log-uniform in [2^10, 2^this]")
     ap.add_argument("--tuning", default="auto",
                     help="walk launch shape: 'auto' (katz_autotune per precision before timing), "
@@ -466,12 +468,14 @@ def bench_serving(args, katz, sg, torch, np):
     # The launch shape of the state's whole-graph walks (creation, dense
     # re-walk levels, resumed iterations): the autotuner's choice for a
     # static FP64 ranking of the resident graph.
-    tuning = katz.autotune(rp_t, col_t, 100, eps=1e-6, precision="fp64")
+    prec = args.serving_precision
+    tuning = katz.autotune(rp_t, col_t, 100, eps=1e-6, precision=prec)
     print(f"[bench] serving tuning {tuning}", flush=True)
     sv = katz.Server(slots=4)
     torch.cuda.synchronize()
     t_create = time.perf_counter()
-    gid, _ = sv.add_graph(rp_t, col_t, 100, alpha=1.0 / (1 + dmax + H), eps=1e-6, degree_cap=dmax + H)
+    gid, _ = sv.add_graph(rp_t, col_t, 100, alpha=1.0 / (1 + dmax + H), eps=1e-6, degree_cap=dmax + H,
+                          precision=prec)
     torch.cuda.synchronize()
     create_ms = (time.perf_counter() - t_create) * 1e3
     print(f"[bench] state created (checks, slack CSR, renumbering, first certified ranking) in {create_ms:.1f} ms",
@@ -521,8 +525,8 @@ def bench_serving(args, katz, sg, torch, np):
         "metric": "serving dynamic updates: p50/p99 latency and throughput, 1 GPU",
         "value": points[0]["p50_ms"], "unit": "ms p50 latency at 50% load", "n_gpus": 1,
         "steps": len(reqs), "warmup": 0, "ms_per_step": round(float(np.mean(svc)), 4), "higher_is_better": False,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"rmat{args.serving_scale}_serving", "n": n, "nnz_directed": int(rp[-1]), "k": 100, "eps": 1e-6,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": f"rmat{args.serving_scale}_serving", "form": prec, "n": n, "nnz_directed": int(rp[-1]), "k": 100, "eps": 1e-6,
                    "batch": "round(10^U(0,4)) edges, 70% insertions", "slots": 4},
         "saturation_requests_per_s": round(sat, 2), "load_points": points, "tuning": tuning,
         "state_create_ms": round(create_ms, 1),
