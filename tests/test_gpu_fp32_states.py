@@ -267,3 +267,45 @@ def test_fp32_states_in_the_server():
         st.free()
     finally:
         sv.close()
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_fp32_state_random_batch_sequence(seed):
+    """Twenty batches of random size (1 to 3000 updates, insertion-heavy or
+    deletion-heavy) on an undirected R-MAT 12 state with a generous degree
+    cap: every result within the parity contract of the oracle's Algorithm 2,
+    and the last one bitwise a second state that replayed the same batches
+    after a checkpoint in the middle."""
+    katz = K()
+    rng = np.random.default_rng(100 + seed)
+    rp, col = sg.rmat(12, seed=30 + seed)
+    n = len(rp) - 1
+    cap = 2 * sg.max_degree(rp) + 64
+    alpha = 1.0 / (1 + cap)
+    say("fp32 random sequence", seed)
+    st, res = katz.create_state(*dev(rp, col), 24, alpha=alpha, eps=EPS, degree_cap=cap, precision="fp32")
+    dyn = oracle.DynamicOracle(rp, col, alpha, k=24, eps=EPS, degree_cap=cap)
+    check(katz, res, dyn.result)
+    batches = []
+    for b in range(20):
+        size = int(round(10 ** rng.uniform(0, 3.5)))
+        frac_del = rng.choice([0.1, 0.5, 0.8])
+        nd = min(int(size * frac_del), len(dyn.col) // 4)
+        ins, dels = batch(rng, dyn.row_ptr, dyn.col, n, size - nd, nd)
+        batches.append((ins, dels))
+        res = st.update(ins, dels)
+        check(katz, res, dyn.update(ins, dels))
+    st.free()
+    # Replay: the same batches, with a checkpoint and reload after the tenth.
+    st2, _ = katz.create_state(*dev(rp, col), 24, alpha=alpha, eps=EPS, degree_cap=cap, precision="fp32")
+    for b, (ins, dels) in enumerate(batches):
+        r2 = st2.update(ins, dels)
+        if b == 9:
+            import tempfile, os
+            with tempfile.TemporaryDirectory() as d:
+                path = os.path.join(d, "s.bin")
+                st2.save(path)
+                st2.free()
+                st2 = katz.load_state(path)
+    assert torch.equal(r2.topk, res.topk) and torch.equal(r2.lower, res.lower) and torch.equal(r2.upper, res.upper)
+    st2.free()
