@@ -309,3 +309,37 @@ def test_fp32_state_random_batch_sequence(seed):
                 st2 = katz.load_state(path)
     assert torch.equal(r2.topk, res.topk) and torch.equal(r2.lower, res.lower) and torch.equal(r2.upper, res.upper)
     st2.free()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_state_from_int32_offsets_and_host_memory(precision):
+    """States created from int32 row offsets (device, and host memory) rename
+    their rows from the caller's CSR through 32-bit offsets: results bitwise
+    those of the state created from int64 device offsets, through updates."""
+    katz = K()
+    rng = np.random.default_rng(12)
+    rp, col = sg.rmat(12, seed=40)
+    n = len(rp) - 1
+    cap = sg.max_degree(rp) + 80
+    alpha = 1.0 / (1 + cap)
+    eps = EPS if precision == "fp32" else 1e-9
+    say("int32 offsets state", precision)
+    rp32 = np.asarray(rp, dtype=np.int32)
+    col32 = np.asarray(col, dtype=np.int32)
+    kw = dict(alpha=alpha, eps=eps, degree_cap=cap, precision=precision)
+    s64, r64 = katz.create_state(*dev(rp, col), 20, **kw)
+    s32, r32 = katz.create_state(torch.from_numpy(rp32).cuda(), torch.from_numpy(col32).cuda(), 20, **kw)
+    sh, rh = katz.create_state(torch.from_numpy(rp32), torch.from_numpy(col32), 20, **kw)
+    outs = [(r64, r32, rh)]
+    dyn = oracle.DynamicOracle(rp, col, alpha, k=20, eps=eps, degree_cap=cap)
+    for ni, nd in [(15, 5), (400, 100)]:
+        ins, dels = batch(rng, dyn.row_ptr, dyn.col, n, ni, nd)
+        dyn.update(ins, dels)
+        outs.append((s64.update(ins, dels), s32.update(ins, dels), sh.update(ins, dels)))
+    for a, b, c in outs:
+        for o in (b, c):
+            assert torch.equal(a.topk.cpu(), o.topk.cpu())
+            assert torch.equal(a.lower.cpu(), o.lower.cpu()) and torch.equal(a.upper.cpu(), o.upper.cpu())
+            assert (a.iterations, a.status) == (o.iterations, o.status)
+    for s in (s64, s32, sh):
+        s.free()
