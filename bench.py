@@ -262,6 +262,102 @@ def oracle_leg(args, np, torch, rp_t, col_t, k, r32, r64, dmax):
     return out
 
 
+def bench_extras(args, katz, sg, torch, np):
+    """The other stopping criteria of Section 3.1 (ranking with k = n, score,
+    pair), inbound Katz on a directed graph (Section 2.1) and the comparison
+    methods (Foster's heuristic, CG on Eq. (la)), on R-MAT graphs of 2^scale
+    nodes.  Each form: the mean of `steps` device calls after `warmup`, the
+    walk step's rate from the device timers against its algorithmic bytes, and
+    the oracle's time for one call on the same graph beside it."""
+    import oracle
+    from oracle.katz import PAIR, RANKING, SCORE, TOPK
+    scale = args.extras_scale
+    eps = 1e-6
+    rp, col = sg.rmat(scale, EDGE_FACTOR, 0.57, 0.19, 0.19, seed=5)
+    drp, dcol = sg.rmat_directed(scale, EDGE_FACTOR, seed=6)
+    n, nnz = len(rp) - 1, int(rp[-1])
+    dev = lambda a, b: (torch.from_numpy(np.asarray(a, np.int64)).cuda(), torch.from_numpy(np.asarray(b, np.int32)).cuda())
+    g_und, g_dir = dev(rp, col), dev(drp, dcol)
+    alpha = 1.0 / (1 + int(np.max(np.diff(rp))))
+    out = {}
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        katz.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        tm = katz.timing_read()
+        katz.timing_enable(False)
+        return res, ms, tm
+
+    def walk_rate(tm, nn, mm, precision):
+        if tm["walk_step_launches"] == 0:
+            return {}
+        us = tm["walk_step_ms"] * 1e3 / tm["walk_step_launches"]
+        gbs = algorithmic_bytes_per_walk_step(nn, mm, precision, True) / us / 1e3
+        return {"walk_step_avg_us": round(us, 1), "walk_step_gbs": round(gbs, 1), "walk_step_frac": round(gbs / 8000.0, 4)}
+
+    def oracle_time(fn):
+        t0 = time.perf_counter()
+        r = fn()
+        return r, round(time.perf_counter() - t0, 3)
+
+    forms = [("ranking", dict(criterion="ranking")), ("score", dict(criterion="score")),
+             ("topk1000", dict(criterion="topk"))]
+    for name, kw in forms:
+        k = n if name != "topk1000" else 1000
+        res, ms, tm = timed(lambda: katz.rank_static(*g_und, k, alpha=alpha, eps=eps, precision="fp32", **kw))
+        crit = {"ranking": RANKING, "score": SCORE, "topk1000": TOPK}[name]
+        orc, ot = oracle_time(lambda: oracle.rank_static(rp, col, alpha, 1000, eps, criterion=crit))
+        ids = res.topk.cpu().numpy()[:100]
+        out[name] = {"ms": round(ms, 3), "iterations": res.iterations, "status": res.status,
+                     "separated_fraction": None if res.separated_fraction != res.separated_fraction
+                     else round(res.separated_fraction, 6),
+                     "oracle_s": ot, "oracle_iterations": orc.iterations, "oracle_status": orc.status,
+                     "first100_equal_oracle": bool(np.array_equal(ids, np.asarray(orc.topk)[:100]))}
+        out[name].update(walk_rate(tm, n, nnz, "fp32"))
+    top2 = [int(v) for v in katz.rank_static(*g_und, 2, alpha=alpha, eps=eps, precision="fp32").topk.cpu()]
+    res, ms, tm = timed(lambda: katz.rank_static(*g_und, 2, alpha=alpha, eps=eps, precision="fp32", criterion="pair",
+                                                 pair=(top2[0], top2[1])))
+    orc, ot = oracle_time(lambda: oracle.rank_static(rp, col, alpha, 2, eps, criterion=PAIR,
+                                                     pair=(top2[0], top2[1])))
+    out["pair"] = {"ms": round(ms, 3), "pair": top2, "iterations": res.iterations, "status": res.status,
+                   "oracle_s": ot, "oracle_iterations": orc.iterations, "oracle_status": orc.status,
+                   "order_equal_oracle": bool(np.array_equal(res.topk.cpu().numpy(), np.asarray(orc.topk)))}
+    out["pair"].update(walk_rate(tm, n, nnz, "fp32"))
+    trp, tcol = oracle.reverse_graph(drp, dcol)
+    dalpha = 1.0 / (1 + int(np.max(np.diff(trp))))
+    res, ms, tm = timed(lambda: katz.rank_static(*g_dir, 1000, alpha=dalpha, eps=eps, precision="fp32",
+                                                 undirected=False, flags=katz.FLAG_INBOUND))
+    orc, ot = oracle_time(lambda: oracle.rank_static(trp, tcol, dalpha, 1000, eps, undirected=False))
+    out["inbound_topk1000"] = {"ms": round(ms, 3), "nnz": int(drp[-1]), "iterations": res.iterations,
+                               "status": res.status, "oracle_s": ot, "oracle_iterations": orc.iterations,
+                               "topk_equal_oracle": bool(np.array_equal(res.topk.cpu().numpy(), np.asarray(orc.topk)))}
+    out["inbound_topk1000"].update(walk_rate(tm, n, int(drp[-1]), "fp32"))
+    for method, ofn in (("foster", lambda: oracle.foster(rp, col, alpha, tol=1e-9)),
+                        ("cg", lambda: oracle.conjugate_gradient(rp, col, alpha, tol=1e-12))):
+        tol = 1e-9 if method == "foster" else 1e-12
+        (sc, info, st), ms, tm = timed(lambda: katz.solve(*g_und, method, tol, alpha=alpha))
+        o, ot = oracle_time(ofn)
+        oscore = np.asarray(o.scores)
+        rel = float(np.max(np.abs(sc.cpu().numpy() - oscore) / np.maximum(np.abs(oscore), 1e-300)))
+        out[method] = {"ms": round(ms, 3), "tol": tol, "iterations": info.get("iterations"), "status": st,
+                       "oracle_s": ot, "oracle_iterations": o.iterations, "max_rel_diff_oracle": rel}
+    line = {"metric": "other criteria, inbound Katz and comparison methods: ms per call, 1 GPU",
+            "value": out["ranking"]["ms"], "unit": "ms per ranking call (k = n)", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": out["ranking"]["ms"], "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"rmat{scale}_extras", "n": n, "nnz_directed": nnz, "eps": eps,
+                       "alpha": "1/(1+deg_max)", "oracle": "numpy/scipy oracle, one call on the same graph"},
+            "forms": out}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,13 +366,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
-    ap.add_argument("--workload", default="static", choices=["static", "static27", "static22", "batched", "serving"],
+    ap.add_argument("--workload", default="static",
+                    choices=["static", "static27", "static22", "batched", "serving", "extras"],
                     help="static: R-MAT 27 (the headline line) with R-MAT 22 beside it; static27 / static22: "
                          "one of them alone; batched: 256 Barabasi-Albert graphs; serving: update batches "
                          "against R-MAT 24")
     ap.add_argument("--requests", type=int, default=200, help="serving: requests per load point")
     ap.add_argument("--graphs", type=int, default=256, help="batched: number of graphs")
     ap.add_argument("--serving-scale", type=int, default=24, help="serving: R-MAT scale of the resident graph")
+    ap.add_argument("--extras-scale", type=int, default=22, help="extras: R-MAT scale of the graphs")
     ap.add_argument("--serving-precision", default="fp64", choices=["fp64", "fp32"],
                     help="serving: form of the resident state (FP32: scaled walk history, Section 3.3 margin)")
     ap.add_argument("--batched-max-log2n", type=int, default=18, help="batched: n is log-uniform in [2^10, 2^this]")
@@ -302,6 +400,8 @@ def main():
         return bench_batched(args, katz, sg, torch, np)
     if args.workload == "serving":
         return bench_serving(args, katz, sg, torch, np)
+    if args.workload == "extras":
+        return bench_extras(args, katz, sg, torch, np)
 
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib * (1 << 18), dtype=torch.float32, device="cuda")
