@@ -70,7 +70,7 @@ extern "C" {
 #define KATZ_E_DEGREE_CAP       -5  /* insertion would exceed the state's degree cap   */
 #define KATZ_E_OOM              -6  /* device allocation failed                        */
 #define KATZ_E_HIP              -7  /* a HIP runtime call failed                       */
-#define KATZ_E_UNSUPPORTED      -8  /* valid request outside what this build supports  */
+#define KATZ_E_UNSUPPORTED      -8  /* valid request outside what the library supports */
 #define KATZ_E_SCRATCH          -9  /* katz_rank_static_noalloc: the problem needs more */
                                     /* workspace than the fixed scratch array holds     */
 #define KATZ_E_CANCELLED       -10  /* server: the request was cancelled (or still      */
