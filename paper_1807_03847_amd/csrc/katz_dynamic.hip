@@ -244,41 +244,70 @@ __global__ void __launch_bounds__(kWG) rename_meta(const int32_t* ext_of, long l
   src_of[i] = (long long)off_old[v];
 }
 
-// Pass 2, flattened over the slots of the new pool (wave-interleaved as
-// above).  Slot p lies in internal row i (off_new ascending; row i ends where
-// row i + 1 starts, the last at used_new); the first len_new[i] slots of a row
-// take the old row's entries renamed through int_of, the rest stay free.  The
-// row data a lane needs on entering a row (its end, length and old start) are
-// independent loads.
-__global__ void __launch_bounds__(kWG) rename_slots(const long long* off_new, long long n, long long used_new,
-                                                    const int* len_new, const long long* src_of,
-                                                    const int32_t* pool_old, const int32_t* int_of,
-                                                    int32_t* pool_new) {
-  const long long c0 = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave * ((long long)kWave * kFlatPer);
-  if (c0 >= used_new) return;
-  const int lane = lane_id();
-  long long i = -1, start = 0, end = 0, src = 0;
-  int len = 0;
-  for (int q = 0; q < kFlatPer; ++q) {
-    const long long p = c0 + (long long)q * kWave + lane;
-    if (p >= used_new) break;
-    if (i < 0) {
-      i = row_at(off_new, n, p);
-      start = off_new[i];
-      end = i + 1 < n ? off_new[i + 1] : used_new;
-      len = len_new[i];
-      src = src_of[i];
-    }
-    while (p >= end && i + 1 < n) {
-      ++i;
-      start = end;
-      end = i + 1 < n ? off_new[i + 1] : used_new;
-      len = len_new[i];
-      src = src_of[i];
-    }
-    const long long j = p - start;
-    if (j < len) pool_new[p] = int_of[pool_old[src + j]];
+// Pass 2: a 256-thread workgroup takes 4096 consecutive slots of the new
+// pool, thread t the slots c0 + q 256 + t (q = 0 .. 15), so each load and
+// store instruction covers consecutive words.  Slot p lies in internal row i
+// (off_new ascending; every capacity is at least 2, so a chunk touches at most
+// 2050 rows); the first len_new[i] slots of a row take the old row's entries
+// renamed through int_of, the rest stay free.  The chunk's row starts are
+// staged in the LDS, each slot finds its row there by a fixed-step binary
+// search, and the loads of the sixteen slots of a thread are issued phase by
+// phase (row data, old entries, renaming gathers), none waiting on another
+// slot's.
+constexpr int kRenameThreads = 256;
+constexpr int kRenamePer = 16;
+constexpr int kRenameChunk = kRenameThreads * kRenamePer;
+constexpr int kRenameRows = kRenameChunk / 2 + 2;
+
+__global__ void __launch_bounds__(kRenameThreads) rename_slots(const long long* off_new, long long n,
+                                                               long long used_new, const int* len_new,
+                                                               const long long* src_of, const int32_t* pool_old,
+                                                               const int32_t* int_of, int32_t* pool_new) {
+  __shared__ int rel[kRenameRows];   // row starts of the chunk, relative to c0
+  __shared__ long long s_r0;
+  __shared__ int s_rows;
+  const long long c0 = (long long)blockIdx.x * kRenameChunk;
+  if (c0 >= used_new) return;        // uniform over the workgroup
+  const int t = threadIdx.x;
+  const long long c1 = (c0 + kRenameChunk < used_new ? c0 + kRenameChunk : used_new) - 1;
+  if (t == 0) {
+    const long long r0 = row_at(off_new, n, c0);
+    const long long r1 = row_at(off_new, n, c1);
+    s_r0 = r0;
+    s_rows = (int)(r1 - r0 + 1);
   }
+  __syncthreads();
+  const long long r0 = s_r0;
+  const int rows = s_rows < kRenameRows ? s_rows : kRenameRows;
+  for (int k = t; k < rows; k += kRenameThreads) rel[k] = (int)(off_new[r0 + k] - c0);
+  __syncthreads();
+  int kk[kRenamePer], jj[kRenamePer];
+#pragma unroll
+  for (int q = 0; q < kRenamePer; ++q) {
+    const int x = q * kRenameThreads + t;
+    int lo = 0;   // the last row k with rel[k] <= x (rel[0] <= 0 <= x)
+#pragma unroll
+    for (int step = 2048; step > 0; step >>= 1) {
+      const int m = lo + step;
+      if (m < rows && rel[m] <= x) lo = m;
+    }
+    kk[q] = lo;
+    jj[q] = x - rel[lo];
+  }
+  long long addr[kRenamePer];
+#pragma unroll
+  for (int q = 0; q < kRenamePer; ++q) {
+    const bool in = c0 + q * kRenameThreads + t <= c1;
+    const long long i = r0 + kk[q];
+    const int len = in ? len_new[i] : 0;
+    addr[q] = jj[q] < len ? src_of[i] + jj[q] : -1;
+  }
+  int32_t c[kRenamePer];
+#pragma unroll
+  for (int q = 0; q < kRenamePer; ++q) c[q] = addr[q] >= 0 ? pool_old[addr[q]] : -1;
+#pragma unroll
+  for (int q = 0; q < kRenamePer; ++q)
+    if (c[q] >= 0) pool_new[c0 + q * kRenameThreads + t] = int_of[c[q]];
 }
 // Candidate lengths of the touched rows; marks them.
 __global__ void __launch_bounds__(kWG) touched_lengths(const int32_t* rows, long long t, const int* delta,
@@ -662,8 +691,8 @@ hipError_t launch_state_rename_rows(const int32_t* ext_of, const int32_t* int_of
     hipLaunchKernelGGL(rename_meta<int>, dim3(blocks_for(n)), dim3(kWG), 0, s, ext_of, n, (const int*)off_old,
                        len_old, cap_old, len_new, cap_new, src_of);
   if (used_new > 0)
-    hipLaunchKernelGGL(rename_slots, dim3(flat_blocks(used_new)), dim3(kWG), 0, s, off_new, n, used_new, len_new,
-                       src_of, pool_old, int_of, pool_new);
+    hipLaunchKernelGGL(rename_slots, dim3((unsigned)((used_new + kRenameChunk - 1) / kRenameChunk)),
+                       dim3(kRenameThreads), 0, s, off_new, n, used_new, len_new, src_of, pool_old, int_of, pool_new);
   return hipGetLastError();
 }
 
