@@ -137,35 +137,78 @@ __global__ void __launch_bounds__(kWG) copy_rows_to_pool(const OffT* rp, const i
 
 // The checks a state needs of its CSR, one pass over the arcs: every column
 // id in range, no self-loop, each row strictly ascending (sorted, no
-// neighbour twice).  Offsets are checked by the binning pass; inconsistent
-// ones cannot make this pass read out of bounds (rows stay in 0..n-1, arcs in
-// 0..nnz-1) and flag the graph.
+// neighbour twice).  A 256-thread workgroup takes 4096 consecutive arcs,
+// thread t the arcs c0 + q 256 + t; the starts of the rows they fall in are
+// staged in the LDS (up to kStrictRows of them; a chunk that crosses more,
+// through runs of empty rows, follows the rows forward per thread instead),
+// and each arc finds its row there by a fixed-step binary search.  Offsets
+// are checked by the binning pass; inconsistent ones cannot make this pass
+// read out of bounds (rows stay in 0..n-1, arcs in 0..nnz-1) and flag the
+// graph.
+constexpr int kStrictThreads = 256;
+constexpr int kStrictPer = 16;
+constexpr int kStrictChunk = kStrictThreads * kStrictPer;
+constexpr int kStrictRows = 2048;
+
 template <class OffT>
-__global__ void __launch_bounds__(kWG) check_rows_strict(const OffT* rp, const int32_t* col, long long n,
-                                                         long long nnz, RunScalars* sc) {
-  const long long c0 = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave * ((long long)kWave * kFlatPer);
-  if (c0 >= nnz) return;
-  const int lane = lane_id();
-  long long v = -1, start = 0, end = 0;
+__global__ void __launch_bounds__(kStrictThreads) check_rows_strict(const OffT* rp, const int32_t* col, long long n,
+                                                                    long long nnz, RunScalars* sc) {
+  __shared__ long long rel[kStrictRows];   // row starts of the chunk (absolute arc positions)
+  __shared__ long long s_r0;
+  __shared__ int s_rows;
+  const long long c0 = (long long)blockIdx.x * kStrictChunk;
+  if (c0 >= nnz) return;                   // uniform over the workgroup
+  const int t = threadIdx.x;
+  const long long c1 = (c0 + kStrictChunk < nnz ? c0 + kStrictChunk : nnz) - 1;
+  if (t == 0) {
+    const long long r0 = row_at(rp, n, c0);
+    const long long r1 = row_at(rp, n, c1);
+    s_r0 = r0;
+    s_rows = r1 >= r0 ? (int)(r1 - r0 + 1 < kStrictRows + 1 ? r1 - r0 + 1 : kStrictRows + 1) : 1;
+  }
+  __syncthreads();
+  const long long r0 = s_r0;
+  const bool staged = s_rows <= kStrictRows;
+  const int rows = staged ? s_rows : 0;
+  for (int k = t; k < rows; k += kStrictThreads) rel[k] = (long long)rp[r0 + k];
+  __syncthreads();
   bool bad = false;
-  for (int q = 0; q < kFlatPer; ++q) {
-    const long long j = c0 + (long long)q * kWave + lane;
-    if (j >= nnz) break;
-    if (v < 0) {
-      v = row_at(rp, n, j);
-      start = (long long)rp[v];
-      end = (long long)rp[v + 1];
-    }
-    while (j >= end && v + 1 < n) {
-      ++v;
-      start = end;
-      end = (long long)rp[v + 1];
+  long long v = -1, start = 0, end = 0;   // the forward walk of an unstaged chunk
+#pragma unroll 4
+  for (int q = 0; q < kStrictPer; ++q) {
+    const long long j = c0 + (long long)q * kStrictThreads + t;
+    if (j > c1) break;
+    long long row, rs, re;
+    if (staged) {
+      int lo = 0;   // the last staged row k with rel[k] <= j
+#pragma unroll
+      for (int step = kStrictRows / 2; step > 0; step >>= 1) {
+        const int m = lo + step;
+        if (m < rows && rel[m] <= j) lo = m;
+      }
+      row = r0 + lo;
+      rs = rel[lo];
+      re = lo + 1 < rows ? rel[lo + 1] : (long long)rp[row + 1];
+    } else {
+      if (v < 0) {
+        v = row_at(rp, n, j);
+        start = (long long)rp[v];
+        end = (long long)rp[v + 1];
+      }
+      while (j >= end && v + 1 < n) {
+        ++v;
+        start = end;
+        end = (long long)rp[v + 1];
+      }
+      row = v;
+      rs = start;
+      re = end;
     }
     const int32_t u = col[j];
-    bad = bad || j < start || j >= end || u < 0 || (long long)u >= n || (long long)u == v ||
-          (j > start && j > 0 && col[j - 1] >= u);
+    bad = bad || j < rs || j >= re || u < 0 || (long long)u >= n || (long long)u == row ||
+          (j > rs && j > 0 && col[j - 1] >= u);
   }
-  if (__ballot(bad) && lane == 0) atomicOr(&sc->err, 1);
+  if (__ballot(bad) && lane_id() == 0) atomicOr(&sc->err, 1);
 }
 __device__ __forceinline__ long long lower_bound_i32(const int32_t* a, long long len, int32_t x) {
   long long lo = 0, hi = len;
@@ -660,11 +703,13 @@ hipError_t launch_copy_rows_to_pool(const void* rp, int rp64, const int32_t* col
 hipError_t launch_check_rows_strict(const void* rp, int rp64, const int32_t* col, long long n, long long nnz,
                                     RunScalars* sc, hipStream_t s) {
   if (n <= 0 || nnz <= 0) return hipSuccess;
-  const unsigned nb = flat_blocks(nnz);
+  const unsigned nb = (unsigned)((nnz + kStrictChunk - 1) / kStrictChunk);
   if (rp64)
-    hipLaunchKernelGGL(check_rows_strict<int64_t>, dim3(nb), dim3(kWG), 0, s, (const int64_t*)rp, col, n, nnz, sc);
+    hipLaunchKernelGGL(check_rows_strict<int64_t>, dim3(nb), dim3(kStrictThreads), 0, s, (const int64_t*)rp, col, n,
+                       nnz, sc);
   else
-    hipLaunchKernelGGL(check_rows_strict<int32_t>, dim3(nb), dim3(kWG), 0, s, (const int32_t*)rp, col, n, nnz, sc);
+    hipLaunchKernelGGL(check_rows_strict<int32_t>, dim3(nb), dim3(kStrictThreads), 0, s, (const int32_t*)rp, col, n,
+                       nnz, sc);
   return hipGetLastError();
 }
 
