@@ -186,3 +186,40 @@ def test_autotune_cache(katz, tmp_path):
         assert len(path.read_text().splitlines()) == 3          # both lines skipped: tuned again
     finally:
         katz.autotune_cache(None)
+
+
+@pytest.mark.parametrize("undirected", [True, False])
+def test_state_strict_checks_across_runs_of_empty_rows(katz, undirected):
+    """Arcs only on every 40th node, so a 4096-arc chunk of the strict row check
+    crosses more than 2048 rows (runs of empty rows) and follows them forward:
+    the graph is accepted and the state ranks as the oracle does; a self-loop
+    or a repeated neighbour in it is E_CSR (a directed graph has no symmetry
+    check to catch them first)."""
+    n = 40 * 3000
+    act = np.arange(0, n, 40)
+    m = len(act)
+    src, dst = [], []
+    for i in range(m):
+        for d in (1, 2, 3) + ((7,) if i % 5 == 0 else ()):
+            src.append(int(act[i]))
+            dst.append(int(act[(i + d) % m]))
+    rp, col = sg.from_edges(n, src, dst, undirected=undirected)
+    rp, col = np.asarray(rp, np.int64), np.asarray(col, np.int32)
+    assert int(rp[-1]) > 4096
+    alpha = 1.0 / (2 + sg.max_degree(rp))
+    say("strict checks empty-row runs", undirected)
+    st, res = katz.create_state(*dev(rp, col), 16, alpha=alpha, eps=1e-9, undirected=undirected, max_iter=200)
+    orc = oracle.rank_static(rp, col, alpha, 16, 1e-9, undirected=undirected, max_iter=200)
+    assert_topk_parity(res.topk.cpu().numpy(), res.lower.cpu().numpy(), res.upper.cpu().numpy(), orc,
+                       gpu_status=res.status)
+    st.free()
+    row = int(act[m // 2])
+    j = int(rp[row]) + 1
+    loop = col.copy()
+    loop[j] = row
+    dup = col.copy()
+    dup[j] = dup[j - 1]
+    for bad in (loop, dup):
+        with pytest.raises(katz.KatzError) as e:
+            katz.create_state(*dev(rp, bad), 16, alpha=alpha, undirected=undirected)
+        assert e.value.code == katz.E_CSR
