@@ -36,34 +36,78 @@ constexpr int kTileRounds = 6;                               // 6144-arc tiles: 
 constexpr long long kTile = (long long)kRadixWG * kTileRounds;   // arcs per tile
 constexpr int kExpandPer = 16;                              // arcs per thread of expand_sources
 
-// src[j] = the row of arc j.  Wave w takes kExpandPer * kWave consecutive
-// arcs, lane l the arcs c0 + q kWave + l (each store instruction covers kWave
-// consecutive arcs); a lane finds the row of its first arc by a binary search
-// over the offsets, then follows the rows forward.
+// src[j] = the row of arc j.  A 256-thread workgroup takes 4096 consecutive
+// arcs, thread t the arcs c0 + q 256 + t (each store instruction covers
+// consecutive arcs).  The starts of the rows the chunk crosses are staged in
+// the LDS (up to kExpandRows of them) and each arc finds its row there by a
+// fixed-step binary search; a chunk that crosses more rows (runs of empty
+// rows) follows the rows forward per thread from a binary search over the
+// offsets.
+constexpr int kExpandThreads = 256;
+constexpr int kExpandChunk = kExpandThreads * kExpandPer;
+constexpr int kExpandRows = 2048;
+
 template <class OffT>
-__global__ void __launch_bounds__(kWG) expand_sources(const OffT* rp, long long n, long long nnz, int32_t* src) {
-  const long long c0 = ((long long)blockIdx.x * kWG + threadIdx.x) / kWave * ((long long)kWave * kExpandPer);
-  if (c0 >= nnz) return;
-  const int lane = lane_id();
-  const long long j0 = c0 + lane;
-  if (j0 >= nnz) return;
-  // The last row v with rp[v] <= j0 (rows before it end at or before j0).
-  long long lo = 0, hi = n - 1;
+__device__ __forceinline__ long long last_row_at_or_before(const OffT* rp, long long n, long long j) {
+  long long lo = 0, hi = n - 1;   // the last row v with rp[v] <= j
   while (lo < hi) {
     const long long mid = (lo + hi + 1) >> 1;
-    if ((long long)rp[mid] <= j0) lo = mid;
+    if ((long long)rp[mid] <= j) lo = mid;
     else hi = mid - 1;
   }
-  long long v = lo;
-  long long end = (long long)rp[v + 1];
-  for (int q = 0; q < kExpandPer; ++q) {
-    const long long j = j0 + (long long)q * kWave;
-    if (j >= nnz) break;
-    while (j >= end) {   // empty rows are skipped
-      ++v;
-      end = (long long)rp[v + 1];
+  return lo;
+}
+
+template <class OffT>
+__global__ void __launch_bounds__(kExpandThreads) expand_sources(const OffT* rp, long long n, long long nnz,
+                                                                 int32_t* src) {
+  __shared__ long long rel[kExpandRows];
+  __shared__ long long s_r0;
+  __shared__ int s_rows;
+  const long long c0 = (long long)blockIdx.x * kExpandChunk;
+  if (c0 >= nnz) return;   // uniform over the workgroup
+  const int t = threadIdx.x;
+  const long long c1 = (c0 + kExpandChunk < nnz ? c0 + kExpandChunk : nnz) - 1;
+  if (t == 0) {
+    const long long r0 = last_row_at_or_before(rp, n, c0);
+    const long long r1 = last_row_at_or_before(rp, n, c1);
+    s_r0 = r0;
+    s_rows = (int)(r1 - r0 + 1 < kExpandRows + 1 ? r1 - r0 + 1 : kExpandRows + 1);
+  }
+  __syncthreads();
+  const long long r0 = s_r0;
+  const bool staged = s_rows <= kExpandRows;
+  const int rows = staged ? s_rows : 0;
+  for (int k = t; k < rows; k += kExpandThreads) rel[k] = (long long)rp[r0 + k];
+  __syncthreads();
+  if (staged) {
+#pragma unroll 4
+    for (int q = 0; q < kExpandPer; ++q) {
+      const long long j = c0 + (long long)q * kExpandThreads + t;
+      if (j > c1) break;
+      int lo = 0;   // the last staged row k with rel[k] <= j
+#pragma unroll
+      for (int step = kExpandRows / 2; step > 0; step >>= 1) {
+        const int m = lo + step;
+        if (m < rows && rel[m] <= j) lo = m;
+      }
+      src[j] = (int32_t)(r0 + lo);
     }
-    src[j] = (int32_t)v;
+  } else {
+    long long v = -1, end = 0;
+    for (int q = 0; q < kExpandPer; ++q) {
+      const long long j = c0 + (long long)q * kExpandThreads + t;
+      if (j > c1) break;
+      if (v < 0) {
+        v = last_row_at_or_before(rp, n, j);
+        end = (long long)rp[v + 1];
+      }
+      while (j >= end) {   // empty rows are skipped
+        ++v;
+        end = (long long)rp[v + 1];
+      }
+      src[j] = (int32_t)v;
+    }
   }
 }
 
@@ -273,11 +317,12 @@ hipError_t launch_transpose(const void* rp, int rp64, const int32_t* col, long l
   // which are expanded into the set it reads.
   int32_t* vbuf[2] = {rt_col, src};
   int32_t* kbuf[2] = {ka, kb};
-  const unsigned eg = (unsigned)((nnz + (long long)kWG * kExpandPer - 1) / ((long long)kWG * kExpandPer));
+  const unsigned eg = (unsigned)((nnz + kExpandChunk - 1) / kExpandChunk);
   int32_t* src0 = vbuf[passes & 1];
   if (rp64)
-    hipLaunchKernelGGL(expand_sources<long long>, dim3(eg), dim3(kWG), 0, s, (const long long*)rp, n, nnz, src0);
-  else hipLaunchKernelGGL(expand_sources<int>, dim3(eg), dim3(kWG), 0, s, (const int*)rp, n, nnz, src0);
+    hipLaunchKernelGGL(expand_sources<long long>, dim3(eg), dim3(kExpandThreads), 0, s, (const long long*)rp, n, nnz,
+                       src0);
+  else hipLaunchKernelGGL(expand_sources<int>, dim3(eg), dim3(kExpandThreads), 0, s, (const int*)rp, n, nnz, src0);
   const int32_t* kin = col;
   const int32_t* vin = src0;
   int shift = 0;
